@@ -1,0 +1,18 @@
+"""CPU FP64 oracle for the coset probabilities of a detector error model.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library, its
+Python binding, the benchmark's timed path) imports, links or calls this
+package; only the tests, the smoke check and the benchmark's CPU-baseline leg
+do.  It shares no code with the GPU path.
+
+Tiers (each module's header says what pins it):
+  exact.py    O-1 brute force over error patterns / Paulis (the plain
+              definition of p_{m,L}, paper Sec. 2.3-2.4);
+              O-2 exact frontier contraction (variable elimination) of the same
+              sum, in FP64 with a log-scale accumulator.
+  network.py  the layered networks of the configurations, written from the
+              paper's detector picture (Sec. 3.1, 3.3-3.5, 5.1).
+  sweep.py    O-3 the fixed-chi boundary sweep with simple-update truncation
+              (Sec. 4) followed by the boundary-MPS contraction of the final 2D
+              network, with LAPACK QR/SVD.
+"""

@@ -1,0 +1,321 @@
+"""Layered 3D tensor networks whose contraction is p_{m,L}, built per syndrome.
+
+These are the detector-picture networks of the paper (Sec. 3.1, 3.3, 3.5) for
+independent flips on CSS codes, arranged as stacks of identical layers over a
+2D grid (Sec. 4: layered networks; Sec. 5.1: bond tensors on horizontal bonds
+go into two-site gates, those on vertical bonds are contracted exactly between
+layers).  The logical check node is replaced by a parity chain ("snake") over
+the first layer's dangling legs, so each coset is one network with
+non-negative entries (one positive network per coset instead of the
+Walsh-Hadamard combination of Sec. 3.1.2; both give the same probabilities).
+
+A network is described by plain Python objects:
+
+  LayeredNet.Lx, Ly        grid; site (x, y) has index y*Lx + x
+  LayeredNet.init          per site a tensor G[p, w, e, n, s] (float64)
+  LayeredNet.layers        list of Layer
+  LayeredNet.final         per site the vector f_s contracted with the
+                           physical leg after the last layer
+
+  Layer.pre / Layer.post   {site: matrix (d_out x d_in)} one-site ops
+  Layer.gates              list of (kind, x, y, G4) with kind 'H' for the bond
+                           (x,y)-(x+1,y) and 'V' for (x,y)-(x,y+1), and
+                           G4[pA', pB', pA, pB] the two-site operator
+
+Physical legs carry flip parities (of a vertical bond edge, or of the open
+checks assigned to a site), so a flip mechanism between two sites is the gate
+(1-p) I (x) I + p X (x) X and a detector outcome is imposed by a one-site op.
+Exactness of every construction is checked against the frontier contraction
+in the tests (chi large enough that nothing is truncated).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+W_, E_, N_, S_ = 1, 2, 3, 4  # tensor axes of the four virtual legs
+
+
+@dataclass
+class Layer:
+    pre: dict = field(default_factory=dict)
+    gates: list = field(default_factory=list)
+    post: dict = field(default_factory=dict)
+
+
+@dataclass
+class LayeredNet:
+    Lx: int
+    Ly: int
+    init: list
+    layers: list
+    final: list
+
+
+def xx_gate(p, dA, bitA, dB, bitB):
+    """(1-p) I (x) I + p X_bitA (x) X_bitB on physical dims dA, dB."""
+    G = np.zeros((dA, dB, dA, dB))
+    for a in range(dA):
+        for b in range(dB):
+            G[a, b, a, b] += 1.0 - p
+            G[a ^ (1 << bitA), b ^ (1 << bitB), a, b] += p
+    return G
+
+
+def flip_op(p, d, bits):
+    """(1-p) I + p prod_{b in bits} X_b on a physical dim d."""
+    M = (1.0 - p) * np.eye(d)
+    mask = 0
+    for b in bits:
+        mask |= 1 << b
+    for a in range(d):
+        M[a ^ mask, a] += p
+    return M
+
+
+def snake_order(Lx, Ly):
+    order = []
+    for y in range(Ly):
+        xs = range(Lx) if y % 2 == 0 else range(Lx - 1, -1, -1)
+        order.extend((x, y) for x in xs)
+    return order
+
+
+def _leg_towards(a, b):
+    (xa, ya), (xb, yb) = a, b
+    if xb == xa + 1 and yb == ya:
+        return E_
+    if xb == xa - 1 and yb == ya:
+        return W_
+    if yb == ya + 1 and xb == xa:
+        return S_
+    if yb == ya - 1 and xb == xa:
+        return N_
+    raise ValueError("not adjacent")
+
+
+def snake_state(Lx, Ly, weights, coset):
+    """Parity-chain state over per-site bits: value prod_s w_s(b_s) if the
+    parity of all bits equals `coset`, else 0.  weights[s] is a length-2
+    vector for a site carrying a bit, or None for a site without one
+    (physical dim 1).  The chain runs boustrophedon over the grid with bond
+    dimension 2 carrying the running parity."""
+    order = snake_order(Lx, Ly)
+    tens = [None] * (Lx * Ly)
+    n = len(order)
+    for k, (x, y) in enumerate(order):
+        w = weights[y * Lx + x]
+        dp = 1 if w is None else 2
+        shape = [dp, 1, 1, 1, 1]
+        leg_in = _leg_towards((x, y), order[k - 1]) if k > 0 else None
+        leg_out = _leg_towards((x, y), order[k + 1]) if k < n - 1 else None
+        if leg_in is not None:
+            shape[leg_in] = 2
+        if leg_out is not None:
+            shape[leg_out] = 2
+        T = np.zeros(shape)
+        cins = [0] if leg_in is None else [0, 1]
+        for cin in cins:
+            for b in range(dp):
+                val = 1.0 if w is None else w[b]
+                cout = cin ^ b
+                if leg_out is None and cout != coset:
+                    continue
+                idx = [b, 0, 0, 0, 0]
+                if leg_in is not None:
+                    idx[leg_in] = cin
+                if leg_out is not None:
+                    idx[leg_out] = cout
+                T[tuple(idx)] = val
+        tens[y * Lx + x] = T
+    return tens
+
+
+# ---------------------------------------------------------------------------
+# 3D planar code, point sector: sweep along z
+# ---------------------------------------------------------------------------
+
+def point3d_network(L, p, m, coset):
+    """Sweep of the point-sector network of the 3D planar code along z.
+
+    The physical leg of site (x, y) before layer z is the flip of the z-edge
+    entering vertex (x, y, z) from below.  The initial state is the bottom
+    layer of dangling z-edges, weighted by their flip probabilities and
+    constrained to parity `coset` (the logical membrane).  Layer z applies, for
+    every in-plane edge of level z, the gate (1-p) I I + p X X (a flip of that
+    edge toggles the parity seen by both its vertices), then at every vertex
+    X^{m} (the vertex check fixes the up-going edge's flip to the parity of
+    the others xor m) followed by the up-going edge's weight diag(1-p, p).
+    After the last level the top dangling edges are summed over, f = (1, 1).
+
+    p: per-mechanism rates in the canonical numbering of the point-sector DEM.
+    m: the syndrome (detector (x, y, z) -> ((z-1) L + y) L + x).
+    """
+    p = np.asarray(p, dtype=np.float64)
+    nz = L ** 3
+    nx = L * (L - 1) ** 2
+    weights = []
+    for y in range(L):
+        for x in range(L):
+            q = p[y * L + x]
+            weights.append(np.array([1.0 - q, q]))
+    init = snake_state(L, L, weights, coset)
+    X = np.array([[0.0, 1.0], [1.0, 0.0]])
+    layers = []
+    for z in range(1, L):
+        lay = Layer()
+        for y in range(L):
+            for x in range(L - 1):
+                q = p[nz + ((z - 1) * L + y) * (L - 1) + x]
+                lay.gates.append(("H", x, y, xx_gate(q, 2, 0, 2, 0)))
+        for y in range(L - 1):
+            for x in range(L):
+                q = p[nz + nx + ((z - 1) * (L - 1) + y) * L + x]
+                lay.gates.append(("V", x, y, xx_gate(q, 2, 0, 2, 0)))
+        for y in range(L):
+            for x in range(L):
+                mm = int(m[((z - 1) * L + y) * L + x])
+                q = p[z * L * L + y * L + x]
+                Mx = X if mm else np.eye(2)
+                lay.post[y * L + x] = np.diag([1.0 - q, q]) @ Mx
+        layers.append(lay)
+    final = [np.ones(2) for _ in range(L * L)]
+    return LayeredNet(L, L, init, layers, final)
+
+
+# ---------------------------------------------------------------------------
+# Rotated code with phenomenological noise: sweep across data rows
+# ---------------------------------------------------------------------------
+
+def _check_column(x2):
+    return 0 if x2 < 0 else (x2 - 1) // 2
+
+
+def rotated_network(d, T, checks, p, m, coset):
+    """Sweep of the phenomenological rotated-code network across data rows.
+
+    The layer grid is (site column x in [0, d)) x (round y = t-1, t in
+    [1, T+1]).  Z-checks of one gap row are "open" while the data rows on
+    either side are being absorbed; check c with centre x2 sits at column
+    (x2-1)/2 (column 0 for the left-edge checks), so the checks of one gap row
+    occupy distinct columns and two consecutive gap rows share only column 0.
+    The physical leg of a site lists the partial parities of the open checks
+    it holds, one bit per check (older gap row in the low bit).
+
+      initial state   the flips of data row 0, which touch gap row 0 only and
+                      carry the logical: per site the distribution of the
+                      parity of the flips feeding its check, chained to total
+                      parity `coset`.
+      layer j=1..d-1  pre: open a zero bit for every check of gap row j (if
+                      j <= d-2), and apply the flips of data row j whose two
+                      checks share a site; gates: the other flips of row j
+                      ('H', between the two sites of its checks) and the
+                      measurement flips (c, t) of gap row j-1 ('V', between
+                      rounds t and t+1); post: restrict the bits of gap row
+                      j-1 to the syndrome.
+    p: per-mechanism rates in the canonical numbering of the DEM.
+    """
+    p = np.asarray(p, dtype=np.float64)
+    nZ = len(checks)
+    nq = d * d
+    Lx, Ly = d, T + 1
+    by_row = [[] for _ in range(d - 1)]
+    for c, (g, cols, x2) in enumerate(checks):
+        by_row[g].append(c)
+    col_of = {c: _check_column(checks[c][2]) for c in range(nZ)}
+    cover = {}  # (g, data column) -> check
+    for c, (g, cols, x2) in enumerate(checks):
+        for i in cols:
+            cover[(g, i)] = c
+
+    def pdata(i, j, t):
+        return p[(t - 1) * nq + j * d + i]
+
+    def pmeas(c, t):
+        return p[T * nq + (t - 1) * nZ + c]
+
+    # initial state: gap row 0 open at every round
+    weights = [None] * (Lx * Ly)
+    for c in by_row[0]:
+        x = col_of[c]
+        for t in range(1, T + 2):
+            if t <= T:
+                w = np.array([1.0, 0.0])
+                for i in checks[c][1]:
+                    q = pdata(i, 0, t)
+                    w = np.array([w[0] * (1 - q) + w[1] * q, w[0] * q + w[1] * (1 - q)])
+            else:
+                w = np.array([1.0, 0.0])
+            weights[(t - 1) * Lx + x] = w
+    init = snake_state(Lx, Ly, weights, coset)
+
+    layers = []
+    # bits currently held per site, oldest first: list of (gap row)
+    held = [[] for _ in range(Lx * Ly)]
+    for c in by_row[0]:
+        for t in range(1, T + 2):
+            held[(t - 1) * Lx + col_of[c]].append(0)
+    for j in range(1, d):
+        lay = Layer()
+        gclose, gopen = j - 1, (j if j <= d - 2 else None)
+        if gopen is not None:
+            for c in by_row[gopen]:
+                for t in range(1, T + 2):
+                    s = (t - 1) * Lx + col_of[c]
+                    dold = 1 << len(held[s])
+                    Eop = np.zeros((2 * dold, dold))
+                    Eop[np.arange(dold), np.arange(dold)] = 1.0
+                    lay.pre[s] = Eop
+                    held[s].append(gopen)
+        for t in range(1, T + 1):
+            y = t - 1
+            for i in range(d):
+                cc = cover[(gclose, i)]
+                sa = y * Lx + col_of[cc]
+                ba = held[sa].index(gclose)
+                q = pdata(i, j, t)
+                if gopen is None:
+                    M = flip_op(q, 1 << len(held[sa]), [ba])
+                    lay.pre[sa] = M @ lay.pre[sa] if sa in lay.pre else M
+                    continue
+                co = cover[(gopen, i)]
+                sb = y * Lx + col_of[co]
+                bb = held[sb].index(gopen)
+                if sa == sb:
+                    M = flip_op(q, 1 << len(held[sa]), [ba, bb])
+                    lay.pre[sa] = M @ lay.pre[sa] if sa in lay.pre else M
+                    continue
+                xa, xb = col_of[cc], col_of[co]
+                assert abs(xa - xb) == 1
+                if xa < xb:
+                    G = xx_gate(q, 1 << len(held[sa]), ba, 1 << len(held[sb]), bb)
+                    lay.gates.append(("H", xa, y, G))
+                else:
+                    G = xx_gate(q, 1 << len(held[sb]), bb, 1 << len(held[sa]), ba)
+                    lay.gates.append(("H", xb, y, G))
+            for c in by_row[gclose]:
+                x = col_of[c]
+                sa, sb = y * Lx + x, (y + 1) * Lx + x
+                G = xx_gate(pmeas(c, t), 1 << len(held[sa]), held[sa].index(gclose),
+                            1 << len(held[sb]), held[sb].index(gclose))
+                lay.gates.append(("V", x, y, G))
+        for c in by_row[gclose]:
+            for t in range(1, T + 2):
+                s = (t - 1) * Lx + col_of[c]
+                k = held[s].index(gclose)
+                dold = 1 << len(held[s])
+                mm = int(m[(t - 1) * nZ + c])
+                P = np.zeros((dold // 2, dold))
+                for a in range(dold):
+                    if (a >> k) & 1 == mm:
+                        low = a & ((1 << k) - 1)
+                        high = a >> (k + 1)
+                        P[low | (high << k), a] = 1.0
+                lay.post[s] = P
+                held[s].pop(k)
+        layers.append(lay)
+    assert all(len(h) == 0 for h in held)
+    final = [np.ones(1) for _ in range(Lx * Ly)]
+    return LayeredNet(Lx, Ly, init, layers, final)

@@ -1,0 +1,85 @@
+"""Pins for the fixed-chi sweep oracle (O-3) and its network constructions."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.exact import frontier_logprobs
+from oracle.network import point3d_network, rotated_network
+from oracle.sweep import rank_rule, sweep_logprob
+
+
+def _rates(dem, seed, lo=0.02, hi=0.3):
+    return dem.with_p(np.random.default_rng(seed).uniform(lo, hi, dem.n_mech))
+
+
+@pytest.mark.parametrize("L,chi,chi_m", [(2, 4, 4), (3, 8, 64), (3, 64, 64)])
+def test_point_sweep_exact_at_large_chi(L, chi, chi_m):
+    # Two layers with a rank-2 gate per bond never need more than 2*2^2 = 8 on
+    # a 3D bond, so chi = 8 truncates nothing in the sweep on the 3x3 grid; the
+    # boundary MPS of the final 3x3 network needs up to 8*8 = 64.
+    dem = _rates(synth.surface3d_point(L, 0.1), L)
+    m, _ = synth.sample_syndromes(dem, 6, 7)
+    for k in range(6):
+        ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
+        for c in range(2):
+            lp, flags, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), chi, chi_m)
+            assert lp == pytest.approx(ex[c], abs=1e-10)
+
+
+@pytest.mark.parametrize("d,T", [(3, 1), (3, 2), (3, 3), (5, 1)])
+def test_rotated_sweep_exact_at_large_chi(d, T):
+    dem = _rates(synth.rotated_phenom(d, T, 0.05, 0.05), d + T)
+    m, _ = synth.sample_syndromes(dem, 5, 9)
+    for k in range(5):
+        ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
+        for c in range(2):
+            net = rotated_network(d, T, dem.params["checks"], dem.p, m[k], c)
+            lp, flags, _ = sweep_logprob(net, 512)
+            assert lp == pytest.approx(ex[c], abs=1e-10)
+
+
+def test_truncation_is_an_approximation():
+    # At chi = 4 on the L = 3 point sector the sweep truncates; it stays close
+    # to, but differs from, the exact value.
+    dem, m, _, _ = synth.config_workload(1, n=8)
+    diffs = []
+    for k in range(8):
+        ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
+        for c in range(2):
+            lp, _, _ = sweep_logprob(point3d_network(3, dem.p, m[k], c), 4)
+            diffs.append(abs(lp - ex[c]))
+    assert max(diffs) > 1e-6
+    assert max(diffs) < 0.5
+
+
+def test_svd_driver_independence():
+    dem, m, _, _ = synth.config_workload(1, n=6)
+    for k in range(6):
+        for c in range(2):
+            net = point3d_network(3, dem.p, m[k], c)
+            a, fa, na = sweep_logprob(net, 4, svd_driver="gesdd")
+            b, fb, nb = sweep_logprob(net, 4, svd_driver="gesvd")
+            if na == 0 and nb == 0:
+                assert a == pytest.approx(b, abs=1e-11)
+
+
+def test_half_rate_point_sector():
+    # p = 1/2 closed form survives the sweep when nothing is truncated.
+    L = 3
+    dem = synth.surface3d_point(L, 0.5)
+    m, _ = synth.sample_syndromes(dem, 3, 2)
+    rank = dem.n_det + 1
+    for k in range(3):
+        for c in range(2):
+            lp, _, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), 64)
+            assert lp == pytest.approx(-rank * np.log(2), abs=1e-10)
+
+
+def test_rank_rule():
+    S = np.array([1.0, 0.5, 0.5, 0.2, 1e-14])
+    assert rank_rule(S, 10, 1e-12, 1e-9) == (4, False)  # drops the sub-eps value
+    assert rank_rule(S, 2, 1e-12, 1e-9) == (1, False)  # does not split the 0.5 pair
+    assert rank_rule(S, 3, 1e-12, 1e-9) == (3, False)
+    assert rank_rule(np.array([1.0, 1.0, 1.0]), 2, 1e-12, 1e-9) == (2, True)
+    assert rank_rule(np.array([2.0]), 1, 1e-12, 1e-9) == (1, False)
