@@ -21,8 +21,9 @@ literature, Sec. 4):
     x odd, then (x,y)-(x,y+1) with y even, y odd; within a class bonds are
     disjoint; then post-ops; then every site is divided by its max |entry|.
   * rank rule: keep the largest D <= min(chi, #S) with S_D > eps_rel * S_1 and
-    (D = #S or S_D - S_{D+1} > tau_gap * S_1); if none, D = min(chi, #S) and
-    the result is flagged (a degenerate cluster was split).
+    (D = #S or S_{D+1} < (1 - tau_gap) S_D), i.e. never cut inside a cluster of
+    singular values equal to relative precision tau_gap; if none, D =
+    min(chi, #S) and the result is flagged (a degenerate cluster was split).
   * final stage: contract f_s into the physical leg, put sqrt(lambda) on both
     ends of every bond, boundary MPS from row 0 down, zip-up left to right,
     every new MPS site divided by its max |entry|.
@@ -51,7 +52,7 @@ def rank_rule(S, chi, eps_rel, tau_gap):
     for D in range(top, 0, -1):
         if S[D - 1] <= eps_rel * s1:
             continue
-        if D == n or S[D - 1] - S[D] > tau_gap * s1:
+        if D == n or S[D] < (1.0 - tau_gap) * S[D - 1]:
             return D, False
     return top, True
 

@@ -81,5 +81,9 @@ def test_rank_rule():
     assert rank_rule(S, 10, 1e-12, 1e-9) == (4, False)  # drops the sub-eps value
     assert rank_rule(S, 2, 1e-12, 1e-9) == (1, False)  # does not split the 0.5 pair
     assert rank_rule(S, 3, 1e-12, 1e-9) == (3, False)
+    # the gap is relative to the value at the cut, so small values stay separable
+    S = np.array([1.0, 1e-5, 0.5e-5, 0.25e-5])
+    assert rank_rule(S, 2, 1e-12, 1e-4) == (2, False)
+    assert rank_rule(np.array([1.0, 1e-5, 1e-5 * (1 - 1e-6)]), 2, 1e-12, 1e-4) == (1, False)
     assert rank_rule(np.array([1.0, 1.0, 1.0]), 2, 1e-12, 1e-9) == (2, True)
     assert rank_rule(np.array([2.0]), 1, 1e-12, 1e-9) == (1, False)
