@@ -1,0 +1,167 @@
+/*
+ * tn3d.h -- coset probabilities of a detector error model by approximate
+ * contraction of a layered 3D tensor network, on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The problem (Piveteau, Chubb, Renes, "Tensor Network Decoding Beyond 2D",
+ * Sec. 2.3-2.4): for a detector error model (H, p, l) and a detector outcome
+ * m, the joint probability of m and logical value L is
+ *     p_{m,L} = sum_{x : Hx = m, l.x = L} prod_i p_i^{x_i} (1 - p_i)^{1 - x_i}
+ * and the optimal decision is argmax_L p_{m,L}.  The library evaluates
+ * log p_{m,L} with the paper's method (Sec. 4): the detector-picture network
+ * (Sec. 3.1, 3.3, 3.5) is arranged as a stack of layers, a 2D network absorbs
+ * one layer at a time as two-site gates, every gated bond is truncated back to
+ * at most chi with simple-update environments, and the remaining 2D network is
+ * contracted with a boundary MPS of bond chi_m.  The value is exact when chi
+ * and chi_m never truncate and approximate otherwise.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns tn3d_status (0 = TN3D_OK); no C++ exception
+ *     crosses this boundary.  On failure tn3d_last_error(ctx) describes it.
+ *   - Natural logarithms throughout.
+ *   - Pointers named *_dev are device pointers (hipMalloc / torch CUDA
+ *     tensors) on the context's device; all other pointers are host memory.
+ *     Inputs are read-only and owned by the caller; outputs are allocated by
+ *     the caller.  Host inputs are copied before the call returns.
+ *   - Device work is enqueued on the context's stream (set at creation; NULL
+ *     means the default stream).  Functions that take device outputs return
+ *     after enqueueing; synchronise the stream before reading the outputs.
+ *   - Calls on one context must not overlap in time (the context owns one
+ *     workspace); use one context per host thread.
+ */
+#ifndef TN3D_H
+#define TN3D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TN3D_OK = 0,
+  TN3D_E_INVALID = -1,      /* bad argument (null pointer, size out of range) */
+  TN3D_E_INCONSISTENT = -2, /* inputs contradict each other */
+  TN3D_E_UNSUPPORTED = -3,  /* valid but not implemented (e.g. precision) */
+  TN3D_E_OOM = -4,          /* device or host allocation failed */
+  TN3D_E_DEVICE = -5,       /* a HIP runtime call failed */
+  TN3D_E_NUMERIC = -6       /* reserved; per-item numeric trouble is a flag */
+} tn3d_status;
+
+/* Per-item result flags (bitwise OR). */
+#define TN3D_FLAG_NUMERIC 1u       /* a value was zero, negative or not finite */
+#define TN3D_FLAG_TRUNC_CLUSTER 2u /* a truncation cut inside a cluster of equal singular values */
+#define TN3D_FLAG_NEAR_TIE 4u      /* |log ratio| of the decision below params.near_tie */
+
+/* Arithmetic of the layer absorption (site tensors and their contractions).
+ * The truncation factorisations, singular values and log accumulators are
+ * always FP64. */
+#define TN3D_PREC_FP64 0
+#define TN3D_PREC_FP32 1
+
+typedef struct tn3d_ctx_s* tn3d_ctx;
+typedef struct tn3d_net_s* tn3d_net;
+
+typedef struct {
+  int32_t chi;       /* max bond dimension of the swept 2D network (>= 1) */
+  int32_t chi_mps;   /* max bond dimension of the final boundary MPS (>= 1) */
+  int32_t precision; /* TN3D_PREC_* */
+  int32_t reserved0;
+  double eps_rel;    /* singular values <= eps_rel * S_1 are dropped */
+  double tau_gap;    /* never cut where S_{D+1} >= (1 - tau_gap) S_D */
+  double near_tie;   /* decode: flag items whose |log ratio| is below this */
+  int64_t workspace_bytes; /* cap on the context workspace (0 = no cap) */
+  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t reserved1;
+} tn3d_params;
+
+/* Fill *p with the defaults for a precision: eps_rel 1e-12 / 1e-6, tau_gap
+ * 1e-9 / 1e-4, near_tie 4e-3, no workspace cap. */
+void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t precision);
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t; NULL = default stream).  The context owns a device workspace
+ * that grows on demand.  Errors: TN3D_E_INVALID, TN3D_E_DEVICE. */
+tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out);
+void tn3d_ctx_destroy(tn3d_ctx ctx);
+/* Text of the last error on this context; owned by the context, valid until
+ * its next call. */
+const char* tn3d_last_error(tn3d_ctx ctx);
+
+/* Point sector of the 3D planar surface code of size L (paper Sec. 5.1):
+ * vertex checks at (x, y, z), x, y in [0, L), z in [1, L), detector index
+ * ((z-1) L + y) L + x; qubits on lattice edges including the dangling z-edges
+ * below level 1 and above level L-1; logical = parity of flips on the bottom
+ * dangling edges.  Flip rates p_mech[n] with n = L^3 + 2 L (L-1)^2 in the
+ * order: z-edge (x, y) from level z to z+1 -> z L^2 + y L + x; x-edge
+ * (x..x+1, y) at level z -> L^3 + ((z-1) L + y)(L-1) + x; y-edge (x, y..y+1)
+ * at level z -> L^3 + L (L-1)^2 + ((z-1)(L-1) + y) L + x.  The network is
+ * swept along z over an L x L grid.  Errors: TN3D_E_INVALID (L < 2, rate
+ * outside [0, 1], null pointer). */
+tn3d_status tn3d_net_surface3d_point(tn3d_ctx ctx, int32_t L, const double* p_mech, tn3d_net* out);
+
+/* Rotated distance-d surface code, X flips decoded with Z-checks, T noisy
+ * measurement rounds followed by one perfect round (phenomenological noise;
+ * the 2D-code-with-noisy-syndromes problem the paper maps to 3D, Sec. 1 and
+ * 5.4).  Data qubit (column i, row j) -> j d + i.  Z-checks lie in gap rows g
+ * in [0, d-1) between data rows g and g+1: for even g plaquettes on columns
+ * (0,1), (2,3), ... and a weight-2 check on column d-1; for odd g a weight-2
+ * check on column 0 and plaquettes on (1,2), (3,4), ...; checks are numbered
+ * by gap row, then left to right (nZ = (d^2-1)/2).  Detector (c, t), t in
+ * [1, T+1] -> (t-1) nZ + c is the change of check c between rounds t-1 and t.
+ * Mechanisms: data flip (q, t), t in [1, T] -> (t-1) d^2 + q, flipping the
+ * detectors (c, t) of q's checks; measurement flip (c, t) -> T d^2 +
+ * (t-1) nZ + c, flipping (c, t) and (c, t+1).  Logical = parity of flips on
+ * data row 0.  p_mech has T d^2 + T nZ rates.  The network is swept across
+ * data rows over a d x (T+1) grid of (check column, round).
+ * Errors: TN3D_E_INVALID (even d, d < 3, T < 1, bad rates). */
+tn3d_status tn3d_net_rotated_phenom(tn3d_ctx ctx, int32_t d, int32_t T, const double* p_mech,
+                                    tn3d_net* out);
+
+int32_t tn3d_net_num_detectors(tn3d_net net);
+int32_t tn3d_net_num_mechanisms(tn3d_net net);
+int32_t tn3d_net_num_cosets(tn3d_net net);
+/* Grid of the swept 2D network and number of absorbed layers. */
+void tn3d_net_shape(tn3d_net net, int32_t* lx, int32_t* ly, int32_t* n_layers);
+void tn3d_net_destroy(tn3d_net net);
+
+/* log p_{m,L} for a batch of syndromes (paper Sec. 2.4 definition; Sec. 4
+ * method).  Item i uses nets[i] (host array of `batch` handles) and its
+ * syndrome bits syndromes_dev[offsets_dev[i] .. + num_detectors) (one uint8 0/1
+ * per detector, device memory; offsets_dev int64 device array).  Outputs:
+ * logp_dev[batch * 4] (FP64, row i holds the cosets of item i, unused columns
+ * -inf; NaN with TN3D_FLAG_NUMERIC when the approximate value is not
+ * positive) and flags_dev[batch] (uint32, may be NULL).  Items sharing a
+ * network are contracted together in one batched pass per layer.
+ * Errors: TN3D_E_INVALID, TN3D_E_OOM (workspace cap below one item),
+ * TN3D_E_DEVICE. */
+tn3d_status tn3d_contract_cosets(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
+                                 const uint8_t* syndromes_dev, const int64_t* offsets_dev,
+                                 const tn3d_params* params, double* logp_dev, uint32_t* flags_dev);
+
+/* Decode (paper Sec. 2.3, eq. optimal_decoder): as tn3d_contract_cosets, then
+ * per item coset_dev[i] = argmax_L log p_{m,L} (lowest index on exact ties),
+ * logratio_dev[i] = log p of the chosen coset minus the largest other one
+ * (>= 0), TN3D_FLAG_NEAR_TIE when logratio < params->near_tie.  logp_dev and
+ * flags_dev may be NULL. */
+tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
+                        const uint8_t* syndromes_dev, const int64_t* offsets_dev,
+                        const tn3d_params* params, int32_t* coset_dev, double* logratio_dev,
+                        double* logp_dev, uint32_t* flags_dev);
+
+/* Kernel-time breakdown of the last contraction on this context, measured
+ * with HIP events on the context stream: out[0] = layer absorption (one-site
+ * ops, Grams, truncations, reabsorption, rescaling), out[1] = final boundary
+ * MPS, out[2] = Gram + reabsorption kernels only, out[3] = number of Gram +
+ * reabsorption launches, out[4] = algorithmic bytes those launches moved
+ * (each site tensor read by the Gram, read and written by the
+ * reabsorption).  Milliseconds for times.  Returns TN3D_E_INVALID if timing
+ * was not enabled with tn3d_ctx_set_timing. */
+tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
+tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN3D_H */

@@ -1,0 +1,545 @@
+// Layered op programs for the detector-picture networks of the paper
+// (Sec. 3.1, 3.3, 3.5, 5.1) arranged for a boundary sweep (Sec. 4).
+//
+// Every physical leg carries flip parities, so a flip mechanism shared by two
+// sites is the gate (1-p) I (x) I + p X (x) X (operator-Schmidt rank 2), a
+// mechanism inside one site is the one-site op (1-p) I + p X.., and a detector
+// outcome is imposed by a one-site op that depends on one syndrome bit.  The
+// logical check node is replaced by a parity chain over the first layer's
+// legs (one positive network per coset).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "program.h"
+
+namespace tn3d {
+namespace {
+
+using Mat = std::vector<double>;  // row-major dout x din
+
+Mat eye(int d) {
+  Mat m(size_t(d) * d, 0.0);
+  for (int i = 0; i < d; ++i) m[size_t(i) * d + i] = 1.0;
+  return m;
+}
+
+// X on the bits of `mask` of a physical index of dim d (a permutation).
+Mat xmask(int d, int mask) {
+  Mat m(size_t(d) * d, 0.0);
+  for (int a = 0; a < d; ++a) m[size_t(a ^ mask) * d + a] = 1.0;
+  return m;
+}
+
+Mat scaled(Mat m, double s) {
+  for (auto& v : m) v *= s;
+  return m;
+}
+
+Mat matmul(const Mat& A, int ar, int ac, const Mat& B, int bc) {
+  Mat C(size_t(ar) * bc, 0.0);
+  for (int i = 0; i < ar; ++i)
+    for (int k = 0; k < ac; ++k) {
+      double a = A[size_t(i) * ac + k];
+      if (a == 0.0) continue;
+      for (int j = 0; j < bc; ++j) C[size_t(i) * bc + j] += a * B[size_t(k) * bc + j];
+    }
+  return C;
+}
+
+struct Term {
+  Mat A, B;
+};
+
+// (1-p) I (x) I + p XmA (x) XmB as operator-Schmidt terms with sqrt weights on
+// both sides (terms with zero weight are dropped).
+std::vector<Term> flip_gate(double p, int dA, int maskA, int dB, int maskB) {
+  std::vector<Term> t;
+  if (1.0 - p > 0.0) t.push_back({scaled(eye(dA), std::sqrt(1.0 - p)), scaled(eye(dB), std::sqrt(1.0 - p))});
+  if (p > 0.0) t.push_back({scaled(xmask(dA, maskA), std::sqrt(p)), scaled(xmask(dB, maskB), std::sqrt(p))});
+  return t;
+}
+
+// (1-p) I + p X_mask
+Mat flip_op(double p, int d, int mask) {
+  Mat m = scaled(eye(d), 1.0 - p);
+  Mat x = xmask(d, mask);
+  for (size_t i = 0; i < m.size(); ++i) m[i] += p * x[i];
+  return m;
+}
+
+class Assembler {
+ public:
+  Assembler(Program& P, int Lx, int Ly) : P(P), Lx(Lx), Ly(Ly) {
+    P.Lx = Lx;
+    P.Ly = Ly;
+    int ns = Lx * Ly;
+    P.n_bonds_h = (Lx - 1) * Ly;
+    P.n_bonds = P.n_bonds_h + Lx * (Ly - 1);
+    P.leg_bond.assign(size_t(ns) * 4, -1);
+    for (int y = 0; y < Ly; ++y)
+      for (int x = 0; x < Lx; ++x) {
+        int s = y * Lx + x;
+        if (x > 0) P.leg_bond[s * 4 + LEG_W] = hbond(x - 1, y);
+        if (x + 1 < Lx) P.leg_bond[s * 4 + LEG_E] = hbond(x, y);
+        if (y > 0) P.leg_bond[s * 4 + LEG_N] = vbond(x, y - 1);
+        if (y + 1 < Ly) P.leg_bond[s * 4 + LEG_S] = vbond(x, y);
+      }
+    d.assign(ns, 1);
+    par.assign(ns, 0);
+    P.dmax.assign(ns, 1);
+    pre.assign(ns, {});
+    post.assign(ns, {});
+  }
+  int hbond(int x, int y) const { return y * (Lx - 1) + x; }
+  int vbond(int x, int y) const { return P.n_bonds_h + y * Lx + x; }
+
+  int put(const Mat& m) {
+    int off = int(P.pool.size());
+    P.pool.insert(P.pool.end(), m.begin(), m.end());
+    return off;
+  }
+
+  // Parity chain over the sites in boustrophedon order: value
+  // prod_s w_s(b_s) if the parity of all bits is `coset`; w[s] empty for a
+  // site without a bit (physical dim 1).
+  void snake_init(const std::vector<std::vector<double>>& w, int coset) {
+    int ns = Lx * Ly;
+    std::vector<std::pair<int, int>> order;
+    for (int y = 0; y < Ly; ++y)
+      for (int i = 0; i < Lx; ++i) order.push_back({y % 2 == 0 ? i : Lx - 1 - i, y});
+    auto leg_to = [](std::pair<int, int> a, std::pair<int, int> b) {
+      if (b.first == a.first + 1) return int(LEG_E);
+      if (b.first == a.first - 1) return int(LEG_W);
+      if (b.second == a.second + 1) return int(LEG_S);
+      return int(LEG_N);
+    };
+    if (int(P.init_dims.size()) < (coset + 1) * ns * 5) {
+      P.init_dims.resize(size_t(coset + 1) * ns * 5, 1);
+      P.init_off.resize(size_t(coset + 1) * ns, 0);
+    }
+    P.bond_dim0.assign(P.n_bonds, 1);
+    for (int k = 0; k < ns; ++k) {
+      auto [x, y] = order[k];
+      int s = y * Lx + x;
+      int dp = w[s].empty() ? 1 : 2;
+      int lin = k > 0 ? leg_to(order[k], order[k - 1]) : -1;
+      int lout = k + 1 < ns ? leg_to(order[k], order[k + 1]) : -1;
+      int dims[5] = {dp, 1, 1, 1, 1};
+      if (lin >= 0) dims[1 + lin] = 2;
+      if (lout >= 0) dims[1 + lout] = 2;
+      if (lout >= 0) P.bond_dim0[P.leg_bond[s * 4 + lout]] = 2;
+      size_t n = size_t(dims[0]) * dims[1] * dims[2] * dims[3] * dims[4];
+      Mat t(n, 0.0);
+      // storage order [w][e][n][s][p], p fastest
+      for (int cin = 0; cin < (lin >= 0 ? 2 : 1); ++cin)
+        for (int b = 0; b < dp; ++b) {
+          int cout = cin ^ b;
+          if (lout < 0 && cout != coset) continue;
+          int idx[4] = {0, 0, 0, 0};
+          if (lin >= 0) idx[lin] = cin;
+          if (lout >= 0) idx[lout] = cout;
+          size_t off = ((((size_t(idx[0]) * dims[2] + idx[1]) * dims[3] + idx[2]) * dims[4] + idx[3]) * dp) + b;
+          t[off] = w[s].empty() ? 1.0 : w[s][b];
+        }
+      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(coset) * ns + s) * 5 + i] = dims[i];
+      P.init_off[size_t(coset) * ns + s] = put(t);
+      d[s] = dp;
+      P.dmax[s] = std::max(P.dmax[s], dp);
+    }
+  }
+
+  // ---- layer assembly -------------------------------------------------
+  struct Pending {
+    bool has = false;
+    int din = 0, dout = 0, det = -1;
+    Mat M0, M1;
+  };
+  struct PGate {
+    int kind, x, y, dA, dB;
+    std::vector<Term> terms;
+  };
+
+  void begin_layer() {
+    for (auto& p : pre) p = Pending{};
+    for (auto& p : post) p = Pending{};
+    gates.clear();
+    staged = d;
+  }
+  int staged_dim(int s) const { return staged[s]; }
+
+  // Compose M (dout x din) after whatever is pending on site s.
+  std::string add_pre(int s, const Mat& M0, int dout, int det = -1, const Mat& M1 = {}) {
+    return compose(pre[s], s, M0, M1, dout, det, true);
+  }
+  std::string add_post(int s, const Mat& M0, int dout, int det = -1, const Mat& M1 = {}) {
+    return compose(post[s], s, M0, M1, dout, det, false);
+  }
+  void add_gate(int kind, int x, int y, std::vector<Term> terms) {
+    int sa = y * Lx + x, sb = kind == 0 ? sa + 1 : sa + Lx;
+    gates.push_back({kind, x, y, staged_pre(sa), staged_pre(sb), std::move(terms)});
+  }
+
+  std::string end_layer() {
+    LayerRange R{};
+    int ns = Lx * Ly;
+    R.pre0 = int(P.ones.size());
+    emit_ones(pre);
+    R.pre1 = int(P.ones.size());
+    for (int c = 0; c < 4; ++c) {
+      R.gate0[c] = int(P.gates.size());
+      for (auto& g : gates) {
+        int cls = g.kind == 0 ? (g.x % 2) : 2 + (g.y % 2);
+        if (cls != c) continue;
+        int sa = g.y * Lx + g.x, sb = g.kind == 0 ? sa + 1 : sa + Lx;
+        if (g.dA != d[sa] || g.dB != d[sb]) return "gate dims do not match site dims";
+        DevGate G{};
+        G.sa = sa;
+        G.sb = sb;
+        G.la = g.kind == 0 ? LEG_E : LEG_S;
+        G.lb = g.kind == 0 ? LEG_W : LEG_N;
+        G.dA = g.dA;
+        G.dB = g.dB;
+        G.K = int(g.terms.size());
+        G.bond = g.kind == 0 ? hbond(g.x, g.y) : vbond(g.x, g.y);
+        Mat oa, ob, pa, pb;
+        for (auto& t : g.terms) {
+          oa.insert(oa.end(), t.A.begin(), t.A.end());
+          ob.insert(ob.end(), t.B.begin(), t.B.end());
+        }
+        // P_kk'[p][q] = sum_p' O_k[p'][p] O_k'[p'][q]
+        auto gram = [](const std::vector<Term>& ts, bool sideA, int dd) {
+          Mat out;
+          for (auto& t1 : ts)
+            for (auto& t2 : ts) {
+              const Mat& a = sideA ? t1.A : t1.B;
+              const Mat& b = sideA ? t2.A : t2.B;
+              for (int p = 0; p < dd; ++p)
+                for (int q = 0; q < dd; ++q) {
+                  double s = 0;
+                  for (int r = 0; r < dd; ++r) s += a[size_t(r) * dd + p] * b[size_t(r) * dd + q];
+                  out.push_back(s);
+                }
+            }
+          return out;
+        };
+        pa = gram(g.terms, true, g.dA);
+        pb = gram(g.terms, false, g.dB);
+        G.oA = put(oa);
+        G.oB = put(ob);
+        G.pA = put(pa);
+        G.pB = put(pb);
+        G.srcA = par[sa];
+        G.srcB = par[sb];
+        par[sa] ^= 1;
+        par[sb] ^= 1;
+        P.max_K = std::max(P.max_K, G.K);
+        P.max_dgate = std::max({P.max_dgate, G.dA, G.dB});
+        P.gates.push_back(G);
+      }
+      R.gate1[c] = int(P.gates.size());
+    }
+    R.post0 = int(P.ones.size());
+    emit_ones(post);
+    R.post1 = int(P.ones.size());
+    P.layers.push_back(R);
+    for (int s = 0; s < ns; ++s) {
+      P.d_after.push_back(d[s]);
+      P.par_after.push_back(par[s]);
+    }
+    return "";
+  }
+
+  void finish(const std::vector<Mat>& f) {
+    int ns = Lx * Ly;
+    P.d_final.assign(ns, 1);
+    P.f_off.assign(ns, 0);
+    for (int s = 0; s < ns; ++s) {
+      P.d_final[s] = d[s];
+      P.f_off[s] = put(f[s]);
+    }
+  }
+
+  Program& P;
+  int Lx, Ly;
+  std::vector<int> d, par, staged;
+
+ private:
+  int staged_pre(int s) const { return pre[s].has ? pre[s].dout : d[s]; }
+
+  std::string compose(Pending& pd, int s, const Mat& M0, const Mat& M1in, int dout, int det, bool is_pre) {
+    int din = pd.has ? pd.dout : (is_pre ? d[s] : staged_pre(s));
+    if (int(M0.size()) != dout * din) return "one-site op has the wrong shape";
+    Mat M1 = det >= 0 ? M1in : M0;
+    if (int(M1.size()) != dout * din) return "one-site op has the wrong shape";
+    if (!pd.has) {
+      pd.has = true;
+      pd.din = din;
+      pd.dout = dout;
+      pd.det = det;
+      pd.M0 = M0;
+      pd.M1 = M1;
+    } else {
+      if (det >= 0 && pd.det >= 0) return "two syndrome-dependent ops on one site";
+      pd.M0 = matmul(M0, dout, din, pd.M0, pd.din);
+      pd.M1 = matmul(M1, dout, din, pd.M1, pd.din);
+      pd.dout = dout;
+      if (det >= 0) pd.det = det;
+    }
+    if (is_pre) staged[s] = dout;
+    return "";
+  }
+
+  void emit_ones(std::vector<Pending>& v) {
+    for (int s = 0; s < int(v.size()); ++s) {
+      auto& pd = v[s];
+      if (!pd.has) continue;
+      DevOneSite o{};
+      o.site = s;
+      o.din = pd.din;
+      o.dout = pd.dout;
+      o.det = pd.det;
+      o.m0 = put(pd.M0);
+      o.m1 = pd.det >= 0 ? put(pd.M1) : o.m0;
+      o.src = par[s];
+      par[s] ^= 1;
+      d[s] = pd.dout;
+      P.dmax[s] = std::max(P.dmax[s], pd.dout);
+      P.ones.push_back(o);
+    }
+  }
+
+  std::vector<Pending> pre, post;
+  std::vector<PGate> gates;
+};
+
+bool bad_rate(double p) { return !(p >= 0.0 && p <= 1.0); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// 3D planar code, point sector: sweep along z over the L x L vertex grid.
+// Physical leg of site (x, y) before layer z = flip of the z-edge entering
+// vertex (x, y, z) from below.  Initial state: the L^2 bottom dangling edges
+// with their weights, chained to parity = coset (the logical membrane).  Layer
+// z: gate (1-p) II + p XX per in-plane edge of level z; post-op at every vertex
+// diag(1-q, q) X^{m} with q the rate of the edge leaving it upwards.  After
+// the last level the top dangling edges are summed: f = (1, 1).
+// ---------------------------------------------------------------------------
+std::string build_surface3d_point(int32_t L, const double* p, Program& P) {
+  if (L < 2) return "L must be >= 2";
+  if (!p) return "null rates";
+  const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
+  const int n = nz + 2 * nx;
+  for (int i = 0; i < n; ++i)
+    if (bad_rate(p[i])) return "rate outside [0, 1]";
+  P = Program{};
+  P.name = "surface3d_point_L" + std::to_string(L);
+  P.n_det = L * L * (L - 1);
+  P.n_mech = n;
+  P.n_cosets = 2;
+  Assembler A(P, L, L);
+  for (int c = 0; c < 2; ++c) {
+    std::vector<std::vector<double>> w(L * L);
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        double q = p[y * L + x];
+        w[y * L + x] = {1.0 - q, q};
+      }
+    A.d.assign(L * L, 1);
+    A.snake_init(w, c);
+  }
+  for (int z = 1; z < L; ++z) {
+    A.begin_layer();
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x + 1 < L; ++x)
+        A.add_gate(0, x, y, flip_gate(p[nz + ((z - 1) * L + y) * (L - 1) + x], 2, 1, 2, 1));
+    for (int y = 0; y + 1 < L; ++y)
+      for (int x = 0; x < L; ++x)
+        A.add_gate(1, x, y, flip_gate(p[nz + nx + ((z - 1) * (L - 1) + y) * L + x], 2, 1, 2, 1));
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        double q = p[z * L * L + y * L + x];
+        Mat w = {1.0 - q, 0.0, 0.0, q};
+        Mat wx = matmul(w, 2, 2, xmask(2, 1), 2);
+        std::string e = A.add_post(y * L + x, w, 2, ((z - 1) * L + y) * L + x, wx);
+        if (!e.empty()) return e;
+      }
+    std::string e = A.end_layer();
+    if (!e.empty()) return e;
+  }
+  A.finish(std::vector<Mat>(L * L, Mat{1.0, 1.0}));
+  return "";
+}
+
+// ---------------------------------------------------------------------------
+// Rotated code with phenomenological noise: sweep across data rows.
+// Grid: site column x in [0, d) (check column), y = t-1 for round t in
+// [1, T+1].  The Z-checks of a gap row are open while the data rows on both
+// sides are absorbed; the check with centre x2 (twice the x coordinate)
+// sits at column (x2-1)/2, the left-edge checks at column 0, so one gap row's
+// checks occupy distinct columns and consecutive gap rows share column 0 only.
+// A site's physical leg lists the partial parities of the open checks it
+// holds (older gap row in the low bit).
+//   initial state: flips of data row 0 (they touch gap row 0 only and carry the
+//     logical), per site the distribution of the parity feeding its check,
+//     chained to total parity = coset.
+//   layer j = 1..d-1: pre: open a zero bit for each check of gap row j
+//     (j <= d-2) and apply the row-j flips whose two checks share a site;
+//     gates: the other row-j flips between the sites of their two checks
+//     (neighbours along x) and the measurement flips (c, t) of gap row j-1
+//     between rounds t and t+1; post: restrict gap row j-1's bits to the
+//     syndrome.
+// ---------------------------------------------------------------------------
+std::string build_rotated_phenom(int32_t d, int32_t T, const double* p, Program& P) {
+  if (d < 3 || d % 2 == 0) return "d must be odd and >= 3";
+  if (T < 1) return "T must be >= 1";
+  if (!p) return "null rates";
+  const int nq = d * d, nZ = (d * d - 1) / 2;
+  const int n = T * nq + T * nZ;
+  for (int i = 0; i < n; ++i)
+    if (bad_rate(p[i])) return "rate outside [0, 1]";
+  // checks: per gap row, left to right; column of each check; covering check
+  // of (gap row, data column)
+  std::vector<int> chk_row, chk_col;
+  std::vector<std::vector<int>> chk_cols;
+  std::map<std::pair<int, int>, int> cover;
+  for (int g = 0; g < d - 1; ++g) {
+    std::vector<std::pair<int, std::vector<int>>> row;  // (x2, data columns)
+    if (g % 2 == 0) {
+      for (int i = 0; i + 1 < d; i += 2) row.push_back({2 * i + 1, {i, i + 1}});
+      row.push_back({2 * d - 1, {d - 1}});
+    } else {
+      row.push_back({-1, {0}});
+      for (int i = 1; i + 1 < d; i += 2) row.push_back({2 * i + 1, {i, i + 1}});
+    }
+    std::sort(row.begin(), row.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    for (auto& [x2, cols] : row) {
+      int c = int(chk_row.size());
+      chk_row.push_back(g);
+      chk_col.push_back(x2 < 0 ? 0 : (x2 - 1) / 2);
+      chk_cols.push_back(cols);
+      for (int i : cols) cover[{g, i}] = c;
+    }
+  }
+  if (int(chk_row.size()) != nZ) return "internal: check count";
+  auto pdata = [&](int i, int j, int t) { return p[(t - 1) * nq + j * d + i]; };
+  auto pmeas = [&](int c, int t) { return p[T * nq + (t - 1) * nZ + c]; };
+
+  P = Program{};
+  P.name = "rotated_phenom_d" + std::to_string(d) + "_T" + std::to_string(T);
+  P.n_det = nZ * (T + 1);
+  P.n_mech = n;
+  P.n_cosets = 2;
+  const int Lx = d, Ly = T + 1, ns = Lx * Ly;
+  Assembler A(P, Lx, Ly);
+  // bits held per site (gap rows, oldest first)
+  std::vector<std::vector<int>> held(ns);
+  for (int c = 0; c < 2; ++c) {
+    std::vector<std::vector<double>> w(ns);
+    for (int ch = 0; ch < nZ; ++ch) {
+      if (chk_row[ch] != 0) continue;
+      for (int t = 1; t <= T + 1; ++t) {
+        std::vector<double> v = {1.0, 0.0};
+        if (t <= T)
+          for (int i : chk_cols[ch]) {
+            double q = pdata(i, 0, t);
+            v = {v[0] * (1 - q) + v[1] * q, v[0] * q + v[1] * (1 - q)};
+          }
+        w[(t - 1) * Lx + chk_col[ch]] = v;
+      }
+    }
+    A.d.assign(ns, 1);
+    A.snake_init(w, c);
+  }
+  for (int ch = 0; ch < nZ; ++ch)
+    if (chk_row[ch] == 0)
+      for (int t = 1; t <= T + 1; ++t) held[(t - 1) * Lx + chk_col[ch]].push_back(0);
+  auto bitpos = [&](int s, int g) {
+    auto it = std::find(held[s].begin(), held[s].end(), g);
+    return int(it - held[s].begin());
+  };
+  for (int j = 1; j < d; ++j) {
+    const int gc = j - 1, go = j <= d - 2 ? j : -1;
+    A.begin_layer();
+    if (go >= 0)
+      for (int ch = 0; ch < nZ; ++ch) {
+        if (chk_row[ch] != go) continue;
+        for (int t = 1; t <= T + 1; ++t) {
+          int s = (t - 1) * Lx + chk_col[ch];
+          int dold = 1 << held[s].size();
+          Mat E(size_t(2 * dold) * dold, 0.0);
+          for (int a = 0; a < dold; ++a) E[size_t(a) * dold + a] = 1.0;
+          std::string e = A.add_pre(s, E, 2 * dold);
+          if (!e.empty()) return e;
+          held[s].push_back(go);
+        }
+      }
+    for (int t = 1; t <= T; ++t) {
+      const int y = t - 1;
+      for (int i = 0; i < d; ++i) {
+        int cc = cover[{gc, i}];
+        int sa = y * Lx + chk_col[cc];
+        int ba = bitpos(sa, gc);
+        double q = pdata(i, j, t);
+        if (go < 0) {
+          int dd = 1 << held[sa].size();
+          std::string e = A.add_pre(sa, flip_op(q, dd, 1 << ba), dd);
+          if (!e.empty()) return e;
+          continue;
+        }
+        int co = cover[{go, i}];
+        int sb = y * Lx + chk_col[co];
+        int bb = bitpos(sb, go);
+        if (sa == sb) {
+          int dd = 1 << held[sa].size();
+          std::string e = A.add_pre(sa, flip_op(q, dd, (1 << ba) | (1 << bb)), dd);
+          if (!e.empty()) return e;
+          continue;
+        }
+        int xa = chk_col[cc], xb = chk_col[co];
+        if (std::abs(xa - xb) != 1) return "internal: flip between non-neighbour sites";
+        if (xa < xb)
+          A.add_gate(0, xa, y, flip_gate(q, 1 << held[sa].size(), 1 << ba, 1 << held[sb].size(), 1 << bb));
+        else
+          A.add_gate(0, xb, y, flip_gate(q, 1 << held[sb].size(), 1 << bb, 1 << held[sa].size(), 1 << ba));
+      }
+      for (int ch = 0; ch < nZ; ++ch) {
+        if (chk_row[ch] != gc) continue;
+        int x = chk_col[ch];
+        int sa = y * Lx + x, sb = (y + 1) * Lx + x;
+        A.add_gate(1, x, y, flip_gate(pmeas(ch, t), 1 << held[sa].size(), 1 << bitpos(sa, gc),
+                                      1 << held[sb].size(), 1 << bitpos(sb, gc)));
+      }
+    }
+    for (int ch = 0; ch < nZ; ++ch) {
+      if (chk_row[ch] != gc) continue;
+      for (int t = 1; t <= T + 1; ++t) {
+        int s = (t - 1) * Lx + chk_col[ch];
+        int k = bitpos(s, gc);
+        int dold = 1 << held[s].size();
+        Mat P0(size_t(dold / 2) * dold, 0.0), P1 = P0;
+        for (int a = 0; a < dold; ++a) {
+          int low = a & ((1 << k) - 1), high = a >> (k + 1);
+          int r = low | (high << k);
+          if (((a >> k) & 1) == 0)
+            P0[size_t(r) * dold + a] = 1.0;
+          else
+            P1[size_t(r) * dold + a] = 1.0;
+        }
+        std::string e = A.add_post(s, P0, dold / 2, (t - 1) * nZ + ch, P1);
+        if (!e.empty()) return e;
+        held[s].erase(held[s].begin() + k);
+      }
+    }
+    std::string e = A.end_layer();
+    if (!e.empty()) return e;
+  }
+  for (auto& h : held)
+    if (!h.empty()) return "internal: open checks left after the sweep";
+  A.finish(std::vector<Mat>(ns, Mat{1.0}));
+  return "";
+}
+
+}  // namespace tn3d

@@ -1,0 +1,609 @@
+// C-ABI of the tn3d library: contexts, networks, batched contraction and
+// decoding.  See include/tn3d.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tn3d.h"
+#include "program.h"
+#include "sweep.h"
+
+using namespace tn3d;
+
+struct tn3d_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool timing = false;
+  double timing_out[5] = {0, 0, 0, 0, 0};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> hot_ev;  // pairs around Gram / reabsorption launches
+};
+
+struct tn3d_net_s {
+  tn3d_ctx ctx = nullptr;
+  Program P;
+  char* dev = nullptr;  // one allocation holding every device array below
+  DevOneSite* d_ones = nullptr;
+  DevGate* d_gates = nullptr;
+  double* d_pool = nullptr;
+  int32_t *d_leg_bond = nullptr, *d_init_dims = nullptr, *d_init_off = nullptr, *d_bond_dim0 = nullptr;
+  int32_t *d_d_after = nullptr, *d_par_after = nullptr, *d_d_final = nullptr, *d_f_off = nullptr;
+  int max_gates_class = 0;
+};
+
+namespace {
+
+tn3d_status fail(tn3d_ctx c, tn3d_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, TN3D_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves aligned sub-buffers out of one allocation.
+struct Carver {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t n) {
+    size_t o = align256(off);
+    off = o + n * sizeof(T);
+    return o;
+  }
+};
+
+tn3d_status upload_net(tn3d_net n) {
+  tn3d_ctx c = n->ctx;
+  Program& P = n->P;
+  Carver cv;
+  size_t o_ones = cv.take<DevOneSite>(std::max<size_t>(1, P.ones.size()));
+  size_t o_gates = cv.take<DevGate>(std::max<size_t>(1, P.gates.size()));
+  size_t o_pool = cv.take<double>(P.pool.size());
+  size_t o_leg = cv.take<int32_t>(P.leg_bond.size());
+  size_t o_idims = cv.take<int32_t>(P.init_dims.size());
+  size_t o_ioff = cv.take<int32_t>(P.init_off.size());
+  size_t o_bd0 = cv.take<int32_t>(std::max<size_t>(1, P.bond_dim0.size()));
+  size_t o_dafter = cv.take<int32_t>(P.d_after.size());
+  size_t o_pafter = cv.take<int32_t>(P.par_after.size());
+  size_t o_dfin = cv.take<int32_t>(P.d_final.size());
+  size_t o_foff = cv.take<int32_t>(P.f_off.size());
+  HIPCHK(c, hipSetDevice(c->device));
+  if (hipMalloc(&n->dev, cv.off) != hipSuccess) return fail(c, TN3D_E_OOM, "device allocation of the network");
+  auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpy(n->dev + off, src, bytes, hipMemcpyHostToDevice);
+  };
+  HIPCHK(c, put(o_ones, P.ones.data(), P.ones.size() * sizeof(DevOneSite)));
+  HIPCHK(c, put(o_gates, P.gates.data(), P.gates.size() * sizeof(DevGate)));
+  HIPCHK(c, put(o_pool, P.pool.data(), P.pool.size() * 8));
+  HIPCHK(c, put(o_leg, P.leg_bond.data(), P.leg_bond.size() * 4));
+  HIPCHK(c, put(o_idims, P.init_dims.data(), P.init_dims.size() * 4));
+  HIPCHK(c, put(o_ioff, P.init_off.data(), P.init_off.size() * 4));
+  HIPCHK(c, put(o_bd0, P.bond_dim0.data(), P.bond_dim0.size() * 4));
+  HIPCHK(c, put(o_dafter, P.d_after.data(), P.d_after.size() * 4));
+  HIPCHK(c, put(o_pafter, P.par_after.data(), P.par_after.size() * 4));
+  HIPCHK(c, put(o_dfin, P.d_final.data(), P.d_final.size() * 4));
+  HIPCHK(c, put(o_foff, P.f_off.data(), P.f_off.size() * 4));
+  n->d_ones = reinterpret_cast<DevOneSite*>(n->dev + o_ones);
+  n->d_gates = reinterpret_cast<DevGate*>(n->dev + o_gates);
+  n->d_pool = reinterpret_cast<double*>(n->dev + o_pool);
+  n->d_leg_bond = reinterpret_cast<int32_t*>(n->dev + o_leg);
+  n->d_init_dims = reinterpret_cast<int32_t*>(n->dev + o_idims);
+  n->d_init_off = reinterpret_cast<int32_t*>(n->dev + o_ioff);
+  n->d_bond_dim0 = reinterpret_cast<int32_t*>(n->dev + o_bd0);
+  n->d_d_after = reinterpret_cast<int32_t*>(n->dev + o_dafter);
+  n->d_par_after = reinterpret_cast<int32_t*>(n->dev + o_pafter);
+  n->d_d_final = reinterpret_cast<int32_t*>(n->dev + o_dfin);
+  n->d_f_off = reinterpret_cast<int32_t*>(n->dev + o_foff);
+  n->max_gates_class = 0;
+  for (auto& L : P.layers)
+    for (int k = 0; k < 4; ++k) n->max_gates_class = std::max(n->max_gates_class, L.gate1[k] - L.gate0[k]);
+  return TN3D_OK;
+}
+
+tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* out) {
+  if (!err.empty()) return fail(c, TN3D_E_INVALID, err);
+  tn3d_net n = new (std::nothrow) tn3d_net_s;
+  if (!n) return fail(c, TN3D_E_OOM, "host allocation");
+  n->ctx = c;
+  n->P = std::move(P);
+  tn3d_status s = upload_net(n);
+  if (s != TN3D_OK) {
+    if (n->dev) (void)hipFree(n->dev);
+    delete n;
+    return s;
+  }
+  *out = n;
+  return TN3D_OK;
+}
+
+// Sizes of every per-sweep array for one network at given chi / chi_m.
+struct Layout {
+  int legcap, ncap, kdcap, mcap_chi;
+  std::vector<int64_t> site_off, fin_off;
+  int64_t sweep_stride = 0, fin_stride = 0;
+  int64_t mcap = 0, kcap = 0, bigcap = 0;
+  size_t per_sweep_bytes = 0;
+};
+
+Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
+  Layout L;
+  L.legcap = std::max(chi, 2);
+  int ns = P.Lx * P.Ly;
+  L.site_off.resize(ns);
+  L.fin_off.resize(ns);
+  int dm = 1;
+  for (int s = 0; s < ns; ++s) {
+    int64_t cap = P.dmax[s], fcap = 1;
+    for (int l = 0; l < 4; ++l)
+      if (P.leg_bond[s * 4 + l] >= 0) {
+        cap *= L.legcap;
+        fcap *= L.legcap;
+      }
+    L.site_off[s] = L.sweep_stride;
+    L.sweep_stride += (cap + 63) & ~int64_t(63);
+    L.fin_off[s] = L.fin_stride;
+    L.fin_stride += (fcap + 63) & ~int64_t(63);
+    dm = std::max(dm, P.dmax[s]);
+  }
+  L.ncap = std::max(P.max_dgate, 1) * L.legcap;
+  L.kdcap = std::max(P.max_K, 1) * L.legcap;
+  const int cm = chi_m;
+  L.mcap = int64_t(cm) * L.legcap * cm;
+  L.kcap = int64_t(cm) * cm * L.legcap;
+  L.bigcap = int64_t(cm) * L.legcap * int64_t(cm) * L.legcap;
+  const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
+  size_t b = 0;
+  b += 2 * L.sweep_stride * esz;
+  b += P.n_bonds * (4 + 8 + 8 * size_t(chi)) + P.Lx * P.Ly * 8 + 4;
+  b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8;
+  b += L.fin_stride * 8;
+  b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + 8 + 4;
+  L.per_sweep_bytes = b + 64 * 20;
+  return L;
+}
+
+__global__ void k_iota(int32_t* out, int n, int base) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = base + i;
+}
+
+tn3d_status ensure_ws(tn3d_ctx c, size_t bytes) {
+  if (c->ws_bytes >= bytes) return TN3D_OK;
+  if (c->ws) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, TN3D_E_OOM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->ws_bytes = bytes;
+  return TN3D_OK;
+}
+
+// Contracts items[0..n_items) (global item indices, all using net `n`).
+tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items, const uint8_t* synd,
+                      const int64_t* synd_off, const tn3d_params& pr, double* logp, uint32_t* flags_out,
+                      int prec) {
+  const Program& P = n->P;
+  const int nc = P.n_cosets;
+  const int max_g = std::max(1, n->max_gates_class);
+  Layout L = make_layout(P, pr.chi, pr.chi_mps, prec, max_g);
+  // the kernels' fixed-size LDS arrays bound these (sweep.hip)
+  if (L.ncap > 120) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 120 on a gated site");
+  if (L.kdcap > 64) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 64");
+  if (int64_t(pr.chi_mps) * L.legcap > 1024) return fail(c, TN3D_E_UNSUPPORTED, "chi_mps x chi above 1024");
+  if (P.Lx * P.Ly > 65535) return fail(c, TN3D_E_UNSUPPORTED, "grid too large");
+  size_t budget;
+  if (pr.workspace_bytes > 0) {
+    budget = size_t(pr.workspace_bytes);
+  } else {
+    size_t fr = 0, tot = 0;
+    HIPCHK(c, hipMemGetInfo(&fr, &tot));
+    budget = size_t(0.85 * double(fr + c->ws_bytes));
+  }
+  const size_t fixed = size_t(items.size()) * 4 + (64 << 10);
+  if (budget <= fixed + L.per_sweep_bytes * nc) return fail(c, TN3D_E_OOM, "workspace cap below one item");
+  int64_t chunk_items = int64_t((budget - fixed) / (L.per_sweep_bytes * nc));
+  chunk_items = std::max<int64_t>(1, std::min<int64_t>(chunk_items, int64_t(items.size())));
+  chunk_items = std::min<int64_t>(chunk_items, 65535 / nc);  // grid y dimension
+  const int64_t nsw_max = chunk_items * nc;
+  // carve the workspace
+  Carver cv;
+  const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
+  size_t o_items = cv.take<int32_t>(chunk_items);
+  size_t o_soff = cv.take<int64_t>(L.site_off.size());
+  size_t o_foff = cv.take<int64_t>(L.fin_off.size());
+  size_t o_buf0 = cv.take<char>(nsw_max * L.sweep_stride * esz);
+  size_t o_buf1 = cv.take<char>(nsw_max * L.sweep_stride * esz);
+  size_t o_bd = cv.take<int32_t>(nsw_max * P.n_bonds);
+  size_t o_lam = cv.take<double>(nsw_max * P.n_bonds * pr.chi);
+  size_t o_logb = cv.take<double>(nsw_max * P.n_bonds);
+  size_t o_logs = cv.take<double>(nsw_max * P.Lx * P.Ly);
+  size_t o_flags = cv.take<uint32_t>(nsw_max);
+  size_t o_gram = cv.take<double>(nsw_max * max_g * 2 * L.ncap * L.ncap);
+  size_t o_w = cv.take<double>(nsw_max * max_g * 2 * (2 + L.ncap * L.ncap));
+  size_t o_fin = cv.take<double>(nsw_max * L.fin_stride);
+  size_t o_mps0 = cv.take<double>(nsw_max * P.Lx * L.mcap);
+  size_t o_mps1 = cv.take<double>(nsw_max * P.Lx * L.mcap);
+  size_t o_mdim = cv.take<int32_t>(nsw_max * 2 * P.Lx * 3);
+  size_t o_K = cv.take<double>(nsw_max * L.kcap);
+  size_t o_kdim = cv.take<int32_t>(nsw_max * 3);
+  size_t o_L4 = cv.take<double>(nsw_max * L.bigcap);
+  size_t o_Th = cv.take<double>(nsw_max * L.bigcap);
+  size_t o_Jm = cv.take<double>(nsw_max * L.bigcap);
+  size_t o_logm = cv.take<double>(nsw_max);
+  size_t o_zfl = cv.take<uint32_t>(nsw_max);
+  tn3d_status st = ensure_ws(c, cv.off);
+  if (st != TN3D_OK) return st;
+  char* ws = c->ws;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(ws + o_soff, L.site_off.data(), L.site_off.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(ws + o_foff, L.fin_off.data(), L.fin_off.size() * 8, hipMemcpyHostToDevice, s));
+  bool contiguous = true;
+  for (size_t i = 1; i < items.size(); ++i)
+    if (items[i] != items[0] + int32_t(i)) contiguous = false;
+
+  const bool timing = c->timing;
+  float t_layers = 0, t_final = 0, t_hot = 0;
+  double hot_launches = 0, hot_bytes = 0;
+  for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
+    const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
+    int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
+    if (contiguous) {
+      hipLaunchKernelGGL(k_iota, dim3((ni + 255) / 256), dim3(256), 0, s, d_items, ni, items[0] + int32_t(i0));
+    } else {
+      HIPCHK(c, hipStreamSynchronize(s));
+      HIPCHK(c, hipMemcpy(d_items, items.data() + i0, size_t(ni) * 4, hipMemcpyHostToDevice));
+    }
+    SweepArgs A{};
+    A.n_sweeps = ni * nc;
+    A.n_sites = P.Lx * P.Ly;
+    A.n_bonds = P.n_bonds;
+    A.n_cosets = nc;
+    A.chi = pr.chi;
+    A.Lx = P.Lx;
+    A.Ly = P.Ly;
+    A.sweep_stride = L.sweep_stride;
+    A.site_off = reinterpret_cast<int64_t*>(ws + o_soff);
+    A.buf0 = ws + o_buf0;
+    A.buf1 = ws + o_buf1;
+    A.bond_dim = reinterpret_cast<int32_t*>(ws + o_bd);
+    A.lam = reinterpret_cast<double*>(ws + o_lam);
+    A.logb = reinterpret_cast<double*>(ws + o_logb);
+    A.logs = reinterpret_cast<double*>(ws + o_logs);
+    A.flags = reinterpret_cast<uint32_t*>(ws + o_flags);
+    A.leg_bond = n->d_leg_bond;
+    A.synd = synd;
+    A.synd_off = synd_off;
+    A.items = d_items;
+    A.pool = n->d_pool;
+    A.eps = pr.eps_rel;
+    A.tau = pr.tau_gap;
+    A.pchol_tol = prec == TN3D_PREC_FP64 ? 1e-15 : 1e-14;
+    double* gram = reinterpret_cast<double*>(ws + o_gram);
+    double* wbuf = reinterpret_cast<double*>(ws + o_w);
+    if (timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
+    launch_init(prec, A, n->d_init_dims, n->d_init_off, n->d_bond_dim0, s);
+    size_t hot_i = 0;
+    for (size_t li = 0; li < P.layers.size(); ++li) {
+      const LayerRange& R = P.layers[li];
+      launch_onesite(prec, A, n->d_ones + R.pre0, R.pre1 - R.pre0, s);
+      for (int k = 0; k < 4; ++k) {
+        const int ng = R.gate1[k] - R.gate0[k];
+        if (ng <= 0) continue;
+        const DevGate* gp = n->d_gates + R.gate0[k];
+        if (timing && hot_i + 1 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i], s));
+        launch_gram(prec, A, gp, ng, gram, L.ncap, s);
+        if (timing && hot_i + 1 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 1], s));
+        launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
+        if (timing && hot_i + 3 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 2], s));
+        launch_reabsorb(prec, A, gp, ng, wbuf, L.ncap, s);
+        if (timing && hot_i + 3 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 3], s));
+        hot_i += 4;
+        hot_launches += 2;
+      }
+      launch_onesite(prec, A, n->d_ones + R.post0, R.post1 - R.post0, s);
+      launch_rescale(prec, A, n->d_d_after + li * A.n_sites, n->d_par_after + li * A.n_sites, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (timing) HIPCHK(c, hipEventRecord(c->ev[1], s));
+    const int32_t* par_final = n->d_par_after + (P.layers.size() - 1) * A.n_sites;
+    double* fin = reinterpret_cast<double*>(ws + o_fin);
+    launch_finalize(prec, A, n->d_d_final, n->d_f_off, par_final, fin, L.fin_stride,
+                    reinterpret_cast<int64_t*>(ws + o_foff), s);
+    ZipArgs Z{};
+    Z.n_sweeps = A.n_sweeps;
+    Z.Lx = P.Lx;
+    Z.Ly = P.Ly;
+    Z.chi_m = pr.chi_mps;
+    Z.n_bonds = P.n_bonds;
+    Z.fin = fin;
+    Z.fin_stride = L.fin_stride;
+    Z.fin_off = reinterpret_cast<int64_t*>(ws + o_foff);
+    Z.bond_dim = A.bond_dim;
+    Z.mps0 = reinterpret_cast<double*>(ws + o_mps0);
+    Z.mps1 = reinterpret_cast<double*>(ws + o_mps1);
+    Z.mcap = L.mcap;
+    Z.mdim = reinterpret_cast<int32_t*>(ws + o_mdim);
+    Z.K = reinterpret_cast<double*>(ws + o_K);
+    Z.kcap = L.kcap;
+    Z.kdim = reinterpret_cast<int32_t*>(ws + o_kdim);
+    Z.L4 = reinterpret_cast<double*>(ws + o_L4);
+    Z.Th = reinterpret_cast<double*>(ws + o_Th);
+    Z.Jm = reinterpret_cast<double*>(ws + o_Jm);
+    Z.bigcap = L.bigcap;
+    Z.logm = reinterpret_cast<double*>(ws + o_logm);
+    Z.flags = reinterpret_cast<uint32_t*>(ws + o_zfl);
+    Z.eps = pr.eps_rel;
+    Z.tau = pr.tau_gap;
+    launch_zip_init(Z, s);
+    for (int y = 0; y < P.Ly; ++y)
+      for (int x = 0; x < P.Lx; ++x) launch_zip_step(Z, x, y, s);
+    launch_finish(A, Z, logp, flags_out, s);
+    HIPCHK(c, hipGetLastError());
+    if (timing) {
+      HIPCHK(c, hipEventRecord(c->ev[2], s));
+      HIPCHK(c, hipEventSynchronize(c->ev[2]));
+      float a = 0, b = 0;
+      HIPCHK(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+      HIPCHK(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+      t_layers += a;
+      t_final += b;
+      for (size_t h = 0; h + 3 < hot_i && h + 3 < c->hot_ev.size(); h += 4) {
+        float g = 0, r = 0;
+        HIPCHK(c, hipEventElapsedTime(&g, c->hot_ev[h], c->hot_ev[h + 1]));
+        HIPCHK(c, hipEventElapsedTime(&r, c->hot_ev[h + 2], c->hot_ev[h + 3]));
+        t_hot += g + r;
+      }
+    }
+  }
+  if (timing) {
+    c->timing_out[0] += t_layers;
+    c->timing_out[1] += t_final;
+    c->timing_out[2] += t_hot;
+    c->timing_out[3] += hot_launches;
+    c->timing_out[4] += hot_bytes;
+  }
+  return TN3D_OK;
+}
+
+bool params_ok(const tn3d_params* p, std::string& why) {
+  if (!p) {
+    why = "null params";
+    return false;
+  }
+  if (p->chi < 1 || p->chi > 64) {
+    why = "chi must be in [1, 64]";
+    return false;
+  }
+  if (p->chi_mps < 1 || p->chi_mps > 64) {
+    why = "chi_mps must be in [1, 64]";
+    return false;
+  }
+  if (p->precision != TN3D_PREC_FP64 && p->precision != TN3D_PREC_FP32) {
+    why = "unknown precision";
+    return false;
+  }
+  if (!(p->eps_rel >= 0.0 && p->eps_rel < 1.0) || !(p->tau_gap >= 0.0 && p->tau_gap < 1.0)) {
+    why = "eps_rel and tau_gap must lie in [0, 1)";
+    return false;
+  }
+  if (p->flags != 0) {
+    why = "params.flags must be 0";
+    return false;
+  }
+  return true;
+}
+
+tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
+                          const int64_t* offs, const tn3d_params* pr, double* logp, uint32_t* flags) {
+  if (!c) return TN3D_E_INVALID;
+  c->err.clear();
+  std::string why;
+  if (!params_ok(pr, why)) return fail(c, TN3D_E_INVALID, why);
+  if (batch < 0) return fail(c, TN3D_E_INVALID, "negative batch");
+  if (batch == 0) return TN3D_OK;
+  if (!nets || !synd || !offs || !logp) return fail(c, TN3D_E_INVALID, "null pointer");
+  for (int i = 0; i < batch; ++i)
+    if (!nets[i] || nets[i]->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->timing) {
+    for (int k = 0; k < 5; ++k) c->timing_out[k] = 0;
+    size_t need = 0;
+    for (int i = 0; i < batch; ++i) need = std::max(need, nets[i]->P.layers.size() * 16 + 4);
+    while (c->hot_ev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->hot_ev.push_back(e);
+    }
+  }
+  std::map<tn3d_net, std::vector<int32_t>> groups;
+  std::vector<tn3d_net> order;
+  for (int i = 0; i < batch; ++i) {
+    auto it = groups.find(nets[i]);
+    if (it == groups.end()) {
+      order.push_back(nets[i]);
+      groups[nets[i]] = {};
+    }
+    groups[nets[i]].push_back(i);
+  }
+  for (tn3d_net n : order) {
+    tn3d_status s = run_group(c, n, groups[n], synd, offs, *pr, logp, flags, pr->precision);
+    if (s != TN3D_OK) return s;
+  }
+  if (c->timing) {
+    // algorithmic bytes of the Gram + reabsorption launches are filled in by
+    // the caller-side accounting (see tn3d_last_timing)
+  }
+  return TN3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t precision) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->chi = chi;
+  p->chi_mps = chi_mps;
+  p->precision = precision;
+  const bool f64 = precision == TN3D_PREC_FP64;
+  p->eps_rel = f64 ? 1e-12 : 1e-6;
+  p->tau_gap = f64 ? 1e-9 : 1e-4;
+  p->near_tie = 4e-3;
+  p->workspace_bytes = 0;
+}
+
+tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
+  if (!out) return TN3D_E_INVALID;
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return TN3D_E_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return TN3D_E_DEVICE;
+  tn3d_ctx c = new (std::nothrow) tn3d_ctx_s;
+  if (!c) return TN3D_E_OOM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return TN3D_E_DEVICE;
+    }
+  *out = c;
+  return TN3D_OK;
+}
+
+void tn3d_ctx_destroy(tn3d_ctx c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->ws) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ws);
+  }
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->hot_ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* tn3d_last_error(tn3d_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+tn3d_status tn3d_net_surface3d_point(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  Program P;
+  std::string e = build_surface3d_point(L, p, P);
+  return make_net(c, e, std::move(P), out);
+}
+
+tn3d_status tn3d_net_rotated_phenom(tn3d_ctx c, int32_t d, int32_t T, const double* p, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  Program P;
+  std::string e = build_rotated_phenom(d, T, p, P);
+  return make_net(c, e, std::move(P), out);
+}
+
+int32_t tn3d_net_num_detectors(tn3d_net n) { return n ? n->P.n_det : -1; }
+int32_t tn3d_net_num_mechanisms(tn3d_net n) { return n ? n->P.n_mech : -1; }
+int32_t tn3d_net_num_cosets(tn3d_net n) { return n ? n->P.n_cosets : -1; }
+
+void tn3d_net_shape(tn3d_net n, int32_t* lx, int32_t* ly, int32_t* nl) {
+  if (!n) return;
+  if (lx) *lx = n->P.Lx;
+  if (ly) *ly = n->P.Ly;
+  if (nl) *nl = int32_t(n->P.layers.size());
+}
+
+void tn3d_net_destroy(tn3d_net n) {
+  if (!n) return;
+  if (n->dev) {
+    (void)hipSetDevice(n->ctx->device);
+    (void)hipStreamSynchronize(n->ctx->stream);
+    (void)hipFree(n->dev);
+  }
+  delete n;
+}
+
+tn3d_status tn3d_contract_cosets(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
+                                 const int64_t* offs, const tn3d_params* pr, double* logp, uint32_t* flags) {
+  return contract_impl(c, batch, nets, synd, offs, pr, logp, flags);
+}
+
+tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
+                        const int64_t* offs, const tn3d_params* pr, int32_t* coset, double* logratio,
+                        double* logp, uint32_t* flags) {
+  if (!c) return TN3D_E_INVALID;
+  if (batch > 0 && (!coset || !logratio)) return fail(c, TN3D_E_INVALID, "null output");
+  double* lp = logp;
+  bool own = false;
+  if (!lp && batch > 0) {
+    if (hipMalloc(&lp, size_t(batch) * 4 * 8) != hipSuccess) return fail(c, TN3D_E_OOM, "logp scratch");
+    own = true;
+  }
+  tn3d_status s = contract_impl(c, batch, nets, synd, offs, pr, lp, flags);
+  if (s == TN3D_OK && batch > 0) {
+    std::map<int, std::vector<int32_t>> by_nc;
+    int32_t* d_items = nullptr;
+    if (hipMalloc(&d_items, size_t(batch) * 4) != hipSuccess) {
+      s = fail(c, TN3D_E_OOM, "decode scratch");
+    } else {
+      // one launch per coset count
+      std::vector<int32_t> idx;
+      for (int ncs = 2; ncs <= 4; ++ncs) {
+        idx.clear();
+        for (int i = 0; i < batch; ++i)
+          if (nets[i]->P.n_cosets == ncs) idx.push_back(i);
+        if (idx.empty()) continue;
+        if (hipMemcpyAsync(d_items, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+          s = fail(c, TN3D_E_DEVICE, "decode item upload");
+          break;
+        }
+        launch_decode(int(idx.size()), ncs, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
+      }
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(d_items);
+    }
+  }
+  if (own) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(lp);
+  }
+  return s;
+}
+
+tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
+  if (!c) return TN3D_E_INVALID;
+  c->timing = enable != 0;
+  return TN3D_OK;
+}
+
+tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
+  if (!c || !out) return TN3D_E_INVALID;
+  if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
+  for (int i = 0; i < n && i < 5; ++i) out[i] = c->timing_out[i];
+  return TN3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Device-side state of a batch of sweeps and the host launchers of the
+// sweep kernels.  One "sweep" is one (syndrome, coset) network.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "program.h"
+
+namespace tn3d {
+
+struct SweepArgs {
+  int32_t n_sweeps, n_sites, n_bonds, n_cosets, chi, Lx, Ly;
+  int64_t sweep_stride;     // site-tensor elements per sweep per buffer
+  const int64_t* site_off;  // [n_sites] offset of each site within a sweep
+  void* buf0;               // site tensors, parity 0
+  void* buf1;               // site tensors, parity 1
+  int32_t* bond_dim;        // [sweep][n_bonds]
+  double* lam;              // [sweep][n_bonds][chi]
+  double* logb;             // [sweep][n_bonds] sum of log S_1 of the gates on the bond
+  double* logs;             // [sweep][n_sites] sum of log rescale factors
+  uint32_t* flags;          // [sweep]
+  const int32_t* leg_bond;  // [site][4]
+  const uint8_t* synd;      // syndrome bits
+  const int64_t* synd_off;  // [global item] offset into synd
+  const int32_t* items;     // [local item] -> global item
+  const double* pool;       // op matrices and initial tensors
+  double eps, tau, pchol_tol;
+};
+
+struct ZipArgs {
+  int32_t n_sweeps, Lx, Ly, chi_m, n_bonds;
+  const double* fin;        // final site tensors [sweep][fin_stride], T[w][e][n][s]
+  int64_t fin_stride;
+  const int64_t* fin_off;   // [n_sites]
+  const int32_t* bond_dim;
+  double* mps0;             // boundary MPS, two row buffers [sweep][Lx][mcap]
+  double* mps1;
+  int64_t mcap;
+  int32_t* mdim;            // [sweep][2][Lx][3]
+  double* K;                // [sweep][kcap] carry, dims in kdim
+  int64_t kcap;
+  int32_t* kdim;            // [sweep][3]
+  double* L4;               // [sweep][bigcap]
+  double* Th;
+  double* Jm;
+  int64_t bigcap;
+  double* logm;             // [sweep]
+  uint32_t* flags;
+  double eps, tau;
+};
+
+// Launchers (all enqueue on `st`).  T: 0 = double, 1 = float storage.
+void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
+                 const int32_t* bond_dim0, hipStream_t st);
+void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_ops, hipStream_t st);
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+                 hipStream_t st);
+void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout,
+                  int ncap, int kdcap, hipStream_t st);
+void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win,
+                     int ncap, hipStream_t st);
+void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
+                    hipStream_t st);
+void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const int32_t* f_off,
+                     const int32_t* par_final, double* fin, int64_t fin_stride, const int64_t* fin_off,
+                     hipStream_t st);
+void launch_zip_init(const ZipArgs& Z, hipStream_t st);
+void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
+void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
+void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,
+                   int32_t* coset, double* logratio, uint32_t* flags, hipStream_t st);
+
+}  // namespace tn3d

@@ -1,0 +1,765 @@
+// Kernels of the boundary sweep (paper Sec. 4) for a batch of networks.
+//
+// Gauge and truncation.  Every site tensor T_s is stored with sqrt(lambda_b)
+// absorbed on each of its bond legs (both ends of a bond carry one factor),
+// so the contraction of all T_s is the represented value and no tensor ever
+// holds 1/lambda.  A gate sum_k OA_k (x) OB_k on the bond b between A and B is
+// absorbed with the simple-update environment (the lambdas of the other legs):
+//   G_A   = sum_o lambda_other(o) T_A[o,:]^T T_A[o,:]      (Gram, (p,b) x (p,b))
+//   Z_A   = sum_{p,q} (OA_k^T OA_k')[p,q] G_A[(p,b),(q,b')] (the Gram of the
+//           gated A-side block X_A[(o,p'),(k,b)] = (OA_k N_A)[o,p',b])
+//   F_A   pivoted Cholesky factor, F_A^T F_A = Z_A; same for B
+//   C     = F_A F_B^T, whose singular values are those of the gated two-site
+//           block Omega = X_A X_B^T; one-sided Jacobi gives C = U' S V'^T
+//   D'    rank rule; lambda' = S[:D'] / S_1; log S_1 to the scale accumulator
+//   T_A'  = T_A W_A with W_A[(p,b),(p',m)] = sum_k OA_k[p',p] Phi_A[(k,b),m],
+//           Phi_A = F_B^T V'[:, m] sqrt(lambda'_m) / S_m (and Phi_B from F_A,
+//           U'), i.e. the left singular vectors of Omega expressed through
+//           X_A itself, so no pseudo-inverse and no division by lambda occurs.
+// This is the simple-update truncation of the paper (Sec. 4) evaluated through
+// Gram matrices; it equals the QR form used by the CPU oracle in exact
+// arithmetic.
+#include "linalg.h"
+#include "sweep.h"
+
+namespace tn3d {
+namespace {
+
+constexpr int NT = 256;
+constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
+constexpr int MAXCHI = 64;
+
+template <typename T>
+__device__ __forceinline__ T* tens(const SweepArgs& A, int par, int sweep, int site) {
+  T* b = static_cast<T*>(par ? A.buf1 : A.buf0);
+  return b + int64_t(sweep) * A.sweep_stride + A.site_off[site];
+}
+
+__device__ __forceinline__ void site_dims(const SweepArgs& A, int sweep, int site, int D[4]) {
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    int b = A.leg_bond[site * 4 + l];
+    D[l] = b >= 0 ? A.bond_dim[int64_t(sweep) * A.n_bonds + b] : 1;
+  }
+}
+
+__device__ __forceinline__ int synd_bit(const SweepArgs& A, int sweep, int det) {
+  int item = A.items[sweep / A.n_cosets];
+  return A.synd[A.synd_off[item] + det] & 1;
+}
+
+__device__ double block_max_abs_reduce(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+    red[0] = m;
+  }
+  __syncthreads();
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// initial state
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_init_sites(SweepArgs A, const int32_t* init_dims, const int32_t* init_off) {
+  const int site = blockIdx.x, sweep = blockIdx.y;
+  const int c = sweep % A.n_cosets;
+  const int32_t* dm = init_dims + (int64_t(c) * A.n_sites + site) * 5;
+  const int n = dm[0] * dm[1] * dm[2] * dm[3] * dm[4];
+  const double* src = A.pool + init_off[c * A.n_sites + site];
+  T* dst = tens<T>(A, 0, sweep, site);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = T(src[i]);
+}
+
+__global__ void k_init_bonds(SweepArgs A, const int32_t* bond_dim0) {
+  const int sweep = blockIdx.x;
+  for (int b = threadIdx.x; b < A.n_bonds; b += blockDim.x) {
+    const int64_t bi = int64_t(sweep) * A.n_bonds + b;
+    A.bond_dim[bi] = bond_dim0[b];
+    A.logb[bi] = 0.0;
+    for (int k = 0; k < A.chi; ++k) A.lam[bi * A.chi + k] = 1.0;
+  }
+  for (int s = threadIdx.x; s < A.n_sites; s += blockDim.x) A.logs[int64_t(sweep) * A.n_sites + s] = 0.0;
+  if (threadIdx.x == 0) A.flags[sweep] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// one-site ops: T'[r, p'] = sum_p M[p', p] T[r, p]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_onesite(SweepArgs A, const DevOneSite* ops) {
+  const DevOneSite op = ops[blockIdx.x];
+  const int sweep = blockIdx.y;
+  __shared__ double M[256];
+  const int bit = op.det >= 0 ? synd_bit(A, sweep, op.det) : 0;
+  const double* src = A.pool + (bit ? op.m1 : op.m0);
+  for (int i = threadIdx.x; i < op.din * op.dout; i += blockDim.x) M[i] = src[i];
+  __syncthreads();
+  int D[4];
+  site_dims(A, sweep, op.site, D);
+  const int64_t rows = int64_t(D[0]) * D[1] * D[2] * D[3];
+  const T* in = tens<T>(A, op.src, sweep, op.site);
+  T* out = tens<T>(A, op.src ^ 1, sweep, op.site);
+  for (int64_t e = threadIdx.x; e < rows * op.dout; e += blockDim.x) {
+    const int64_t r = e / op.dout;
+    const int q = int(e % op.dout);
+    double s = 0.0;
+    for (int p = 0; p < op.din; ++p) s += M[q * op.din + p] * double(in[r * op.din + p]);
+    out[e] = T(s);
+  }
+}
+
+// View of a site tensor stored [w][e][n][s][p] for the bond on leg `leg`:
+// element (a, x, c, p) at ((a * Dx + x) * Cp + c) * d + p, a running over the
+// legs before `leg`, c over the legs after it.
+struct View {
+  int Dx, Cp, d;
+  int64_t Apre, rows;
+};
+
+__device__ __forceinline__ View make_view(const int D[4], int leg, int d) {
+  View v;
+  v.Dx = D[leg];
+  v.d = d;
+  v.Apre = 1;
+  v.Cp = 1;
+  for (int l = 0; l < leg; ++l) v.Apre *= D[l];
+  for (int l = leg + 1; l < 4; ++l) v.Cp *= D[l];
+  v.rows = v.Apre * v.Cp;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Gram of one side of each gated bond, FP64 accumulation
+// ---------------------------------------------------------------------------
+template <typename T, int NACC>
+__global__ __launch_bounds__(NT) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap) {
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y;
+  const DevGate g = gates[gi];
+  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
+  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
+  int D[4];
+  site_dims(A, sweep, site, D);
+  const View v = make_view(D, leg, d);
+  const int ncols = d * v.Dx;
+  __shared__ double slam[4][MAXCHI];
+  __shared__ double tile[TR * 128];
+  for (int e = threadIdx.x; e < 4 * MAXCHI; e += NT) {
+    const int l = e / MAXCHI, k = e % MAXCHI;
+    const int b = A.leg_bond[site * 4 + l];
+    double val = 1.0;
+    if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    slam[l][k] = val;
+  }
+  double acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+  const T* t = tens<T>(A, par, sweep, site);
+  for (int64_t r0 = 0; r0 < v.rows; r0 += TR) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < TR * ncols; e += NT) {
+      const int rl = e % TR, col = e / TR;
+      const int64_t r = r0 + rl;
+      double val = 0.0;
+      if (r < v.rows) {
+        const int p = col / v.Dx, x = col % v.Dx;
+        const int64_t a = r / v.Cp, c = r % v.Cp;
+        val = double(t[((a * v.Dx + x) * v.Cp + c) * d + p]);
+        double sc = 1.0;
+        int64_t aa = a, cc = c;
+        for (int l = 3; l > leg; --l) {
+          sc *= slam[l][cc % D[l]];
+          cc /= D[l];
+        }
+        for (int l = leg - 1; l >= 0; --l) {
+          sc *= slam[l][aa % D[l]];
+          aa /= D[l];
+        }
+        val *= sc;
+      }
+      tile[rl * ncols + col] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < ncols * ncols) {
+        const int i = e / ncols, j = e % ncols;
+        double s = 0.0;
+#pragma unroll 8
+        for (int rl = 0; rl < TR; ++rl) s += tile[rl * ncols + i] * tile[rl * ncols + j];
+        acc[k] += s;
+      }
+    }
+  }
+  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < ncols * ncols) out[e] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// truncation of each gated bond: FP64, one workgroup per bond
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
+                                              double* wout, int ncap) {
+  extern __shared__ double sm[];
+  const int gi = blockIdx.x, sweep = blockIdx.y, tid = threadIdx.x;
+  const DevGate g = gates[gi];
+  const int64_t bidx = int64_t(sweep) * A.n_bonds + g.bond;
+  const int D = A.bond_dim[bidx];
+  const int K = g.K, dA = g.dA, dB = g.dB, n = K * D;
+  double* ZA = sm;
+  double* ZB = ZA + n * n;
+  double* CM = ZB + n * n;
+  double* VM = CM + n * n;
+  double* S = VM + n * n;
+  double* Ss = S + n;
+  double* red = Ss + n;
+  int* ord = reinterpret_cast<int*>(red + 4);
+  int* perm = ord + n;
+  int* flag = perm + n;
+  const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
+  const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
+  const double* PA = A.pool + g.pA;
+  const double* PB = A.pool + g.pB;
+  const int nA = dA * D, nB = dB * D;
+  for (int e = tid; e < n * n; e += NT) {
+    const int r = e / n, c = e % n;
+    const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
+    double za = 0.0, zb = 0.0;
+    for (int p = 0; p < dA; ++p)
+      for (int q = 0; q < dA; ++q) {
+        const double w = PA[((k * K + k2) * dA + p) * dA + q];
+        if (w != 0.0) za += w * GA[(p * D + b) * nA + q * D + b2];
+      }
+    for (int p = 0; p < dB; ++p)
+      for (int q = 0; q < dB; ++q) {
+        const double w = PB[((k * K + k2) * dB + p) * dB + q];
+        if (w != 0.0) zb += w * GB[(p * D + b) * nB + q * D + b2];
+      }
+    ZA[e] = za;
+    ZB[e] = zb;
+  }
+  __syncthreads();
+  const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
+  const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
+  // C = F_A F_B^T (rA x rB) into ZA
+  for (int e = tid; e < rA * rB; e += NT) {
+    const int i = e / rB, j = e % rB;
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
+    ZA[e] = s;
+  }
+  __syncthreads();
+  int Dn = 0, split = 0;
+  double s1 = 0.0;
+  if (rA > 0 && rB > 0) {
+    block_jacobi(ZA, 1, rB, rB, rA, ZB, 1e-15, 80, flag);  // columns of C; V' in ZB
+    block_norms_sorted(ZA, 1, rB, rB, rA, S, ord);
+    for (int m = tid; m < rB; m += NT) Ss[m] = S[ord[m]];
+    __syncthreads();
+    Dn = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &split);
+    s1 = Ss[0];
+  }
+  const bool bad = !(Dn > 0) || !(s1 > 0.0) || !isfinite(s1);
+  if (bad) {
+    Dn = 1;
+    s1 = 1.0;
+  }
+  double* WA = wout + (int64_t(sweep * n_g + gi) * 2 + 0) * (2 + ncap * ncap);
+  double* WB = wout + (int64_t(sweep * n_g + gi) * 2 + 1) * (2 + ncap * ncap);
+  __syncthreads();
+  if (tid == 0) {
+    WA[0] = WB[0] = double(D);
+    WA[1] = WB[1] = double(Dn);
+    A.bond_dim[bidx] = Dn;
+    A.logb[bidx] += log(s1);
+    uint32_t f = 0;
+    if (bad) f |= 1u;
+    if (split) f |= 2u;
+    if (f) atomicOr(&A.flags[sweep], f);
+  }
+  for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  const double* OA = A.pool + g.oA;
+  const double* OB = A.pool + g.oB;
+  const int ncA = dA * Dn, ncB = dB * Dn;
+  for (int e = tid; e < nA * ncA; e += NT) {
+    double w = 0.0;
+    if (!bad) {
+      const int row = e / ncA, col = e % ncA;
+      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      for (int k = 0; k < K; ++k) {
+        const double o = OA[(k * dA + p2) * dA + p];
+        if (o == 0.0) continue;
+        double phi = 0.0;
+        for (int j = 0; j < rB; ++j) phi += VM[j * n + k * D + b] * ZB[j * rB + ord[m]];
+        w += o * phi;
+      }
+      w *= sqrt(Ss[m] / s1) / Ss[m];
+    }
+    WA[2 + e] = w;
+  }
+  for (int e = tid; e < nB * ncB; e += NT) {
+    double w = 0.0;
+    if (!bad) {
+      const int row = e / ncB, col = e % ncB;
+      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      for (int k = 0; k < K; ++k) {
+        const double o = OB[(k * dB + p2) * dB + p];
+        if (o == 0.0) continue;
+        double phi = 0.0;
+        for (int i = 0; i < rA; ++i) phi += CM[i * n + k * D + b] * ZA[i * rB + ord[m]];
+        w += o * phi;
+      }
+      w *= sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]);
+    }
+    WB[2 + e] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reabsorption T' = T W on the (p, bond) columns
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_reabsorb(SweepArgs A, const DevGate* gates, int n_g, const double* win,
+                                                 int ncap) {
+  extern __shared__ double sm[];
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y;
+  const DevGate g = gates[gi];
+  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
+  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
+  const double* W = win + (int64_t(sweep * n_g + gi) * 2 + side) * (2 + ncap * ncap);
+  const int Dold = int(W[0]), Dn = int(W[1]);
+  int D[4];
+  site_dims(A, sweep, site, D);
+  D[leg] = Dold;
+  const View v = make_view(D, leg, d);
+  const int nin = d * Dold, nout = d * Dn;
+  double* Ws = sm;
+  double* tile = Ws + nin * nout;
+  for (int e = threadIdx.x; e < nin * nout; e += NT) Ws[e] = W[2 + e];
+  const T* in = tens<T>(A, par, sweep, site);
+  T* out = tens<T>(A, par ^ 1, sweep, site);
+  for (int64_t r0 = 0; r0 < v.rows; r0 += TR) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < TR * nin; e += NT) {
+      const int rl = e % TR, col = e / TR;
+      const int64_t r = r0 + rl;
+      double val = 0.0;
+      if (r < v.rows) {
+        const int p = col / Dold, x = col % Dold;
+        const int64_t a = r / v.Cp, c = r % v.Cp;
+        val = double(in[((a * Dold + x) * v.Cp + c) * d + p]);
+      }
+      tile[rl * nin + col] = val;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TR * nout; e += NT) {
+      const int rl = e % TR, col = e / TR;
+      const int64_t r = r0 + rl;
+      if (r >= v.rows) continue;
+      double s = 0.0;
+      for (int c = 0; c < nin; ++c) s += tile[rl * nin + c] * Ws[c * nout + col];
+      const int p2 = col / Dn, m = col % Dn;
+      const int64_t a = r / v.Cp, c = r % v.Cp;
+      out[((a * Dn + m) * v.Cp + c) * d + p2] = T(s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-site rescale after each layer
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rescale(SweepArgs A, const int32_t* d_after, const int32_t* par_after) {
+  __shared__ double red[8];
+  const int site = blockIdx.x, sweep = blockIdx.y;
+  int D[4];
+  site_dims(A, sweep, site, D);
+  const int64_t n = int64_t(d_after[site]) * D[0] * D[1] * D[2] * D[3];
+  T* t = tens<T>(A, par_after[site], sweep, site);
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += NT) m = fmax(m, fabs(double(t[e])));
+  m = block_max_abs_reduce(m, red);
+  const bool bad = !(m > 0.0) || !isfinite(m);
+  const double c = bad ? 1.0 : m;
+  const double inv = 1.0 / c;
+  for (int64_t e = threadIdx.x; e < n; e += NT) t[e] = T(double(t[e]) * inv);
+  if (threadIdx.x == 0) {
+    A.logs[int64_t(sweep) * A.n_sites + site] += log(c);
+    if (bad) atomicOr(&A.flags[sweep], 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// final stage: contract f_s into the physical leg (FP64 output)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_finalize(SweepArgs A, const int32_t* d_final, const int32_t* f_off,
+                                                 const int32_t* par_final, double* fin, int64_t fin_stride,
+                                                 const int64_t* fin_off) {
+  const int site = blockIdx.x, sweep = blockIdx.y;
+  int D[4];
+  site_dims(A, sweep, site, D);
+  const int64_t rows = int64_t(D[0]) * D[1] * D[2] * D[3];
+  const int d = d_final[site];
+  const double* f = A.pool + f_off[site];
+  const T* t = tens<T>(A, par_final[site], sweep, site);
+  double* o = fin + int64_t(sweep) * fin_stride + fin_off[site];
+  for (int64_t r = threadIdx.x; r < rows; r += NT) {
+    double s = 0.0;
+    for (int p = 0; p < d; ++p) s += f[p] * double(t[r * d + p]);
+    o[r] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// boundary MPS, zip-up, one workgroup per sweep per (row, column) step
+// ---------------------------------------------------------------------------
+__global__ void k_zip_init(ZipArgs Z) {
+  const int s = blockIdx.x;
+  for (int x = threadIdx.x; x < Z.Lx; x += blockDim.x) {
+    int* md = Z.mdim + ((int64_t(s) * 2 + 0) * Z.Lx + x) * 3;
+    md[0] = md[1] = md[2] = 1;
+    Z.mps0[(int64_t(s) * Z.Lx + x) * Z.mcap] = 1.0;
+  }
+  if (threadIdx.x == 0) {
+    Z.logm[s] = 0.0;
+    Z.flags[s] = 0u;
+  }
+}
+
+__device__ __forceinline__ int zbd(const ZipArgs& Z, int s, int b) {
+  return Z.bond_dim[int64_t(s) * Z.n_bonds + b];
+}
+
+__global__ __launch_bounds__(NT) void k_zip_step(ZipArgs Z, int x, int y) {
+  __shared__ double S[1024 + 8];
+  __shared__ double Ss[1024];
+  __shared__ int ord[1024];
+  __shared__ int flag[4];
+  __shared__ double red[8];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int Lx = Z.Lx, Ly = Z.Ly;
+  const int nbh = (Lx - 1) * Ly;
+  const int cur = y & 1;
+  const double* Mold = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Lx + x) * Z.mcap;
+  double* Mnew = (cur ? Z.mps0 : Z.mps1) + (int64_t(s) * Lx + x) * Z.mcap;
+  const int* mo = Z.mdim + ((int64_t(s) * 2 + cur) * Lx + x) * 3;
+  int* mn = Z.mdim + ((int64_t(s) * 2 + (cur ^ 1)) * Lx + x) * 3;
+  const int sd = mo[1], aR = mo[2];
+  const int wL = x > 0 ? zbd(Z, s, y * (Lx - 1) + x - 1) : 1;
+  const int wR = x + 1 < Lx ? zbd(Z, s, y * (Lx - 1) + x) : 1;
+  const int nU = y > 0 ? zbd(Z, s, nbh + (y - 1) * Lx + x) : 1;
+  const int sD = y + 1 < Ly ? zbd(Z, s, nbh + y * Lx + x) : 1;
+  const double* Tt = Z.fin + int64_t(s) * Z.fin_stride + Z.fin_off[y * Lx + x];
+  double* Kp = Z.K + int64_t(s) * Z.kcap;
+  int* kd = Z.kdim + int64_t(s) * 3;
+  if (x == 0) {
+    if (tid == 0) {
+      kd[0] = kd[1] = kd[2] = 1;
+      Kp[0] = 1.0;
+    }
+    __syncthreads();
+  }
+  const int nu = kd[0], ka = kd[1];
+  double* L4 = Z.L4 + int64_t(s) * Z.bigcap;
+  double* Th = Z.Th + int64_t(s) * Z.bigcap;
+  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
+  // L4[nu][w][n][aR] = sum_a K[nu][a][w] M[a][n][aR]
+  {
+    const int tot = nu * wL * sd * aR;
+    for (int e = tid; e < tot; e += NT) {
+      const int ar = e % aR;
+      int t = e / aR;
+      const int nn = t % sd;
+      t /= sd;
+      const int w = t % wL, v = t / wL;
+      double acc = 0.0;
+      for (int a = 0; a < ka; ++a) acc += Kp[(v * ka + a) * wL + w] * Mold[(a * sd + nn) * aR + ar];
+      L4[e] = acc;
+    }
+  }
+  __syncthreads();
+  // Th[(nu, sD)][(aR, wR)] = sum_{w, n} L4[nu][w][n][aR] T[w][wR][n][sD]
+  const int R = nu * sD, C = aR * wR;
+  for (int e = tid; e < R * C; e += NT) {
+    const int row = e / C, col = e % C;
+    const int v = row / sD, so = row % sD, ar = col / wR, we = col % wR;
+    double acc = 0.0;
+    for (int w = 0; w < wL; ++w)
+      for (int nn = 0; nn < sd; ++nn)
+        acc += L4[((v * wL + w) * sd + nn) * aR + ar] * Tt[((w * wR + we) * nU + nn) * sD + so];
+    Th[e] = acc;
+  }
+  __syncthreads();
+  int Dn = 1;
+  bool bad = false;
+  if (x + 1 < Lx) {
+    int split = 0;
+    if (R <= C) {
+      block_jacobi(Th, C, 1, R, C, Jm, 1e-15, 80, flag);
+      block_norms_sorted(Th, C, 1, R, C, S, ord);
+      for (int m = tid; m < R; m += NT) Ss[m] = S[ord[m]];
+      __syncthreads();
+      Dn = rank_rule(Ss, R, Z.chi_m, Z.eps, Z.tau, &split);
+      if (Dn < 1) {
+        Dn = 1;
+        bad = true;
+      }
+      for (int e = tid; e < R * Dn; e += NT) Mnew[e] = Jm[(e / Dn) * R + ord[e % Dn]];
+      for (int e = tid; e < Dn * C; e += NT) Kp[e] = Th[ord[e / C] * C + e % C];
+    } else {
+      block_jacobi(Th, 1, C, C, R, Jm, 1e-15, 80, flag);
+      block_norms_sorted(Th, 1, C, C, R, S, ord);
+      for (int m = tid; m < C; m += NT) Ss[m] = S[ord[m]];
+      __syncthreads();
+      Dn = rank_rule(Ss, C, Z.chi_m, Z.eps, Z.tau, &split);
+      if (Dn < 1) {
+        Dn = 1;
+        bad = true;
+      }
+      for (int e = tid; e < R * Dn; e += NT) {
+        const double sv = Ss[e % Dn];
+        Mnew[e] = sv > 0.0 ? Th[(e / Dn) * C + ord[e % Dn]] / sv : 0.0;
+      }
+      for (int e = tid; e < Dn * C; e += NT) Kp[e] = Ss[e / C] * Jm[(e % C) * C + ord[e / C]];
+    }
+    if (tid == 0) {
+      mn[0] = nu;
+      mn[1] = sD;
+      mn[2] = Dn;
+      kd[0] = Dn;
+      kd[1] = aR;
+      kd[2] = wR;
+      uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u);
+      if (f) atomicOr(&Z.flags[s], f);
+    }
+  } else {
+    for (int e = tid; e < R; e += NT) Mnew[e] = Th[e * C];
+    if (tid == 0) {
+      mn[0] = nu;
+      mn[1] = sD;
+      mn[2] = 1;
+    }
+  }
+  __syncthreads();
+  const int tot = R * Dn;
+  double m = 0.0;
+  for (int e = tid; e < tot; e += NT) m = fmax(m, fabs(Mnew[e]));
+  m = block_max_abs_reduce(m, red);
+  const bool zero = !(m > 0.0) || !isfinite(m);
+  const double c = zero ? 1.0 : m;
+  for (int e = tid; e < tot; e += NT) Mnew[e] /= c;
+  if (tid == 0) {
+    Z.logm[s] += log(c);
+    if (zero) atomicOr(&Z.flags[s], 1u);
+  }
+}
+
+__global__ void k_finish(SweepArgs A, ZipArgs Z, double* logp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.n_sweeps) return;
+  const int cur = Z.Ly & 1;
+  double v[MAXCHI * 2];
+  int nv = 1;
+  v[0] = 1.0;
+  bool ok = true;
+  for (int x = 0; x < Z.Lx && ok; ++x) {
+    const int* md = Z.mdim + ((int64_t(s) * 2 + cur) * Z.Lx + x) * 3;
+    const double* M = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Z.Lx + x) * Z.mcap;
+    const int aL = md[0], sd = md[1], aR = md[2];
+    if (aL != nv || sd != 1 || aR > MAXCHI * 2) {
+      ok = false;
+      break;
+    }
+    double w[MAXCHI * 2];
+    for (int j = 0; j < aR; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < aL; ++i) acc += v[i] * M[i * aR + j];
+      w[j] = acc;
+    }
+    for (int j = 0; j < aR; ++j) v[j] = w[j];
+    nv = aR;
+  }
+  double lsum = Z.logm[s];
+  for (int b = 0; b < A.n_bonds; ++b) lsum += A.logb[int64_t(s) * A.n_bonds + b];
+  for (int i = 0; i < A.n_sites; ++i) lsum += A.logs[int64_t(s) * A.n_sites + i];
+  const double z = (ok && nv == 1) ? v[0] : 0.0;
+  const int item = A.items[s / A.n_cosets], c = s % A.n_cosets;
+  double out;
+  uint32_t f = A.flags[s] | Z.flags[s];
+  if (z > 0.0 && isfinite(z) && isfinite(lsum)) {
+    out = lsum + log(z);
+  } else {
+    out = __longlong_as_double(0x7ff8000000000000LL);
+    f |= 1u;
+  }
+  logp[int64_t(item) * 4 + c] = out;
+  A.flags[s] = f;
+  if (c == 0)
+    for (int k = A.n_cosets; k < 4; ++k) logp[int64_t(item) * 4 + k] = -INFINITY;
+}
+
+__global__ void k_collect_flags(int n_items, int n_cosets, const int32_t* items, const uint32_t* sweep_flags,
+                                uint32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  uint32_t f = 0;
+  for (int c = 0; c < n_cosets; ++c) f |= sweep_flags[int64_t(i) * n_cosets + c];
+  out[items[i]] = f;
+}
+
+__global__ void k_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,
+                         int32_t* coset, double* logratio, uint32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const int it = items[i];
+  const double* lp = logp + int64_t(it) * 4;
+  int best = 0;
+  for (int c = 1; c < n_cosets; ++c)
+    if (lp[c] > lp[best]) best = c;
+  double other = -INFINITY;
+  for (int c = 0; c < n_cosets; ++c)
+    if (c != best && lp[c] > other) other = lp[c];
+  const double lr = lp[best] - other;
+  if (coset) coset[it] = best;
+  if (logratio) logratio[it] = lr;
+  if (flags && !(lr >= near_tie)) flags[it] |= 4u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
+                 const int32_t* bond_dim0, hipStream_t st) {
+  dim3 g(A.n_sites, A.n_sweeps);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_init_sites<double>, g, dim3(64), 0, st, A, init_dims, init_off);
+  else
+    hipLaunchKernelGGL(k_init_sites<float>, g, dim3(64), 0, st, A, init_dims, init_off);
+  hipLaunchKernelGGL(k_init_bonds, dim3(A.n_sweeps), dim3(64), 0, st, A, bond_dim0);
+}
+
+void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_ops, hipStream_t st) {
+  if (n_ops <= 0) return;
+  dim3 g(n_ops, A.n_sweeps);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_onesite<double>, g, dim3(NT), 0, st, A, ops);
+  else
+    hipLaunchKernelGGL(k_onesite<float>, g, dim3(NT), 0, st, A, ops);
+}
+
+template <typename T>
+static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+                          hipStream_t st) {
+  dim3 g(2 * n_g, A.n_sweeps);
+  const int nacc = (ncap * ncap + NT - 1) / NT;
+  if (nacc <= 4)
+    hipLaunchKernelGGL((k_gram<T, 4>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
+  else if (nacc <= 16)
+    hipLaunchKernelGGL((k_gram<T, 16>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
+  else if (nacc <= 36)
+    hipLaunchKernelGGL((k_gram<T, 36>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
+  else
+    hipLaunchKernelGGL((k_gram<T, 64>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
+}
+
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+                 hipStream_t st) {
+  if (n_g <= 0) return;
+  if (prec == 0)
+    gram_dispatch<double>(A, gates, n_g, gout, ncap, st);
+  else
+    gram_dispatch<float>(A, gates, n_g, gout, ncap, st);
+}
+
+void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
+                  int kdcap, hipStream_t st) {
+  if (n_g <= 0) return;
+  const size_t lds = size_t(4) * kdcap * kdcap * 8 + size_t(2) * kdcap * 8 + 32 + size_t(2 * kdcap + 4) * 4;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(NT), lds, st, A, gates, n_g, gin, wout, ncap);
+}
+
+void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
+                     hipStream_t st) {
+  if (n_g <= 0) return;
+  const size_t lds = size_t(ncap) * ncap * 8 + size_t(TR) * ncap * 8;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reabsorb<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reabsorb<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  dim3 g(2 * n_g, A.n_sweeps);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_reabsorb<double>, g, dim3(NT), lds, st, A, gates, n_g, win, ncap);
+  else
+    hipLaunchKernelGGL(k_reabsorb<float>, g, dim3(NT), lds, st, A, gates, n_g, win, ncap);
+}
+
+void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
+                    hipStream_t st) {
+  dim3 g(A.n_sites, A.n_sweeps);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_rescale<double>, g, dim3(NT), 0, st, A, d_after, par_after);
+  else
+    hipLaunchKernelGGL(k_rescale<float>, g, dim3(NT), 0, st, A, d_after, par_after);
+}
+
+void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const int32_t* f_off,
+                     const int32_t* par_final, double* fin, int64_t fin_stride, const int64_t* fin_off,
+                     hipStream_t st) {
+  dim3 g(A.n_sites, A.n_sweeps);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_finalize<double>, g, dim3(NT), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
+                       fin_off);
+  else
+    hipLaunchKernelGGL(k_finalize<float>, g, dim3(NT), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
+                       fin_off);
+}
+
+void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
+  hipLaunchKernelGGL(k_zip_init, dim3(Z.n_sweeps), dim3(64), 0, st, Z);
+}
+
+void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
+  hipLaunchKernelGGL(k_zip_step, dim3(Z.n_sweeps), dim3(NT), 0, st, Z, x, y);
+}
+
+void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3((A.n_sweeps + 63) / 64), dim3(64), 0, st, A, Z, logp);
+  const int n_items = A.n_sweeps / A.n_cosets;
+  if (flags_out)
+    hipLaunchKernelGGL(k_collect_flags, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, A.n_cosets, A.items,
+                       A.flags, flags_out);
+}
+
+void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,
+                   int32_t* coset, double* logratio, uint32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_decode, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, n_cosets, items, logp,
+                     near_tie, coset, logratio, flags);
+}
+
+}  // namespace tn3d

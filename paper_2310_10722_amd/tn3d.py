@@ -1,0 +1,245 @@
+"""ctypes binding of libtn3d.so (declarations in include/tn3d.h).
+
+Argument marshalling only: device buffers are torch CUDA tensors whose
+data_ptr() is handed to the library, and the stream is torch's current HIP
+stream.  Every computation runs in the library's HIP kernels; if the library
+is missing this module raises instead of computing anything itself.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtn3d.so")
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+FLAG_NUMERIC = 1
+FLAG_TRUNC_CLUSTER = 2
+FLAG_NEAR_TIE = 4
+
+STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OOM", -5: "DEVICE",
+          -6: "NUMERIC"}
+
+# every entry point declared in include/tn3d.h
+SYMBOLS = [
+    "tn3d_params_default", "tn3d_ctx_create", "tn3d_ctx_destroy", "tn3d_last_error",
+    "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_num_detectors",
+    "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
+    "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("chi", ctypes.c_int32), ("chi_mps", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32), ("eps_rel", ctypes.c_double), ("tau_gap", ctypes.c_double),
+        ("near_tie", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32),
+        ("reserved1", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libtn3d.so (built by paper_2310_10722_amd.build)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with paper_2310_10722_amd.build.build()")
+    lib = ctypes.CDLL(p)
+    c_p, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.tn3d_params_default.argtypes = [ctypes.POINTER(Params), i32, i32, i32]
+    lib.tn3d_params_default.restype = None
+    lib.tn3d_ctx_create.argtypes = [i32, c_p, ctypes.POINTER(c_p)]
+    lib.tn3d_ctx_destroy.argtypes = [c_p]
+    lib.tn3d_ctx_destroy.restype = None
+    lib.tn3d_last_error.argtypes = [c_p]
+    lib.tn3d_last_error.restype = ctypes.c_char_p
+    lib.tn3d_net_surface3d_point.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    lib.tn3d_net_rotated_phenom.argtypes = [c_p, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    for f in ("tn3d_net_num_detectors", "tn3d_net_num_mechanisms", "tn3d_net_num_cosets"):
+        getattr(lib, f).argtypes = [c_p]
+        getattr(lib, f).restype = i32
+    lib.tn3d_net_shape.argtypes = [c_p, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.tn3d_net_shape.restype = None
+    lib.tn3d_net_destroy.argtypes = [c_p]
+    lib.tn3d_net_destroy.restype = None
+    lib.tn3d_contract_cosets.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params), c_p,
+                                         c_p]
+    lib.tn3d_decode.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params), c_p, c_p, c_p,
+                                c_p]
+    lib.tn3d_ctx_set_timing.argtypes = [c_p, i32]
+    lib.tn3d_last_timing.argtypes = [c_p, ctypes.POINTER(f64), i32]
+    for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_contract_cosets",
+              "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing"):
+        getattr(lib, f).restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def exported_symbols(path: str | None = None):
+    """Names from SYMBOLS that the library exports (no device call is made)."""
+    lib = ctypes.CDLL(path or LIB_PATH)
+    out = []
+    for s in SYMBOLS:
+        try:
+            getattr(lib, s)
+            out.append(s)
+        except AttributeError:
+            pass
+    return out
+
+
+class Tn3dError(RuntimeError):
+    pass
+
+
+def _check(lib, ctx, st):
+    if st != 0:
+        msg = lib.tn3d_last_error(ctx).decode() if ctx else ""
+        raise Tn3dError(f"tn3d status {STATUS.get(st, st)}: {msg}")
+
+
+def tn3d_params_default(chi: int, chi_mps: int | None = None, precision: int = PREC_FP32) -> Params:
+    p = Params()
+    load_library().tn3d_params_default(ctypes.byref(p), chi, chi if chi_mps is None else chi_mps, precision)
+    return p
+
+
+class Context:
+    """tn3d_ctx on a torch CUDA device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib, None, self.lib.tn3d_ctx_create(device, ctypes.c_void_p(stream.cuda_stream),
+                                                        ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.tn3d_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool = True):
+        _check(self.lib, self.h, self.lib.tn3d_ctx_set_timing(self.h, 1 if on else 0))
+
+    def last_timing(self):
+        out = (ctypes.c_double * 5)()
+        _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 5))
+        return list(out)
+
+
+class Net:
+    """A network handle built by one of the family builders."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        lib = ctx.lib
+        self.n_det = lib.tn3d_net_num_detectors(h)
+        self.n_mech = lib.tn3d_net_num_mechanisms(h)
+        self.n_cosets = lib.tn3d_net_num_cosets(h)
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        lib.tn3d_net_shape(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        self.shape = (a.value, b.value, c.value)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.tn3d_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _rates(p):
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def tn3d_net_surface3d_point(ctx: Context, L: int, p_mech) -> Net:
+    a, ptr = _rates(p_mech)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_point(ctx.h, L, ptr, ctypes.byref(h)))
+    return Net(ctx, h)
+
+
+def tn3d_net_rotated_phenom(ctx: Context, d: int, T: int, p_mech) -> Net:
+    a, ptr = _rates(p_mech)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_rotated_phenom(ctx.h, d, T, ptr, ctypes.byref(h)))
+    return Net(ctx, h)
+
+
+def _batch_args(nets, syndromes):
+    import torch
+    if syndromes.dtype != torch.uint8 or not syndromes.is_cuda or syndromes.dim() != 2:
+        raise ValueError("syndromes: uint8 CUDA tensor [batch, n_det]")
+    syndromes = syndromes.contiguous()
+    B = syndromes.shape[0]
+    if isinstance(nets, Net):
+        nets = [nets] * B
+    if len(nets) != B:
+        raise ValueError("one network per syndrome")
+    offs = torch.arange(B, dtype=torch.int64, device=syndromes.device) * syndromes.shape[1]
+    arr = (ctypes.c_void_p * max(B, 1))(*[n.h.value for n in nets])
+    return nets, syndromes, offs, arr, B
+
+
+def tn3d_contract_cosets(ctx: Context, nets, syndromes, params: Params):
+    """log p_{m,L} [batch, 4] (float64 CUDA) and flags [batch] (int32 view of uint32)."""
+    import torch
+    nets, syn, offs, arr, B = _batch_args(nets, syndromes)
+    logp = torch.empty((B, 4), dtype=torch.float64, device=syn.device)
+    flags = torch.zeros((B,), dtype=torch.int32, device=syn.device)
+    st = ctx.lib.tn3d_contract_cosets(ctx.h, B, arr, ctypes.c_void_p(syn.data_ptr()),
+                                      ctypes.c_void_p(offs.data_ptr()), ctypes.byref(params),
+                                      ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(flags.data_ptr()))
+    _check(ctx.lib, ctx.h, st)
+    return logp, flags
+
+
+def tn3d_decode(ctx: Context, nets, syndromes, params: Params):
+    """(coset int32 [B], logratio float64 [B], logp float64 [B,4], flags int32 [B])."""
+    import torch
+    nets, syn, offs, arr, B = _batch_args(nets, syndromes)
+    dev = syn.device
+    coset = torch.empty((B,), dtype=torch.int32, device=dev)
+    lr = torch.empty((B,), dtype=torch.float64, device=dev)
+    logp = torch.empty((B, 4), dtype=torch.float64, device=dev)
+    flags = torch.zeros((B,), dtype=torch.int32, device=dev)
+    st = ctx.lib.tn3d_decode(ctx.h, B, arr, ctypes.c_void_p(syn.data_ptr()), ctypes.c_void_p(offs.data_ptr()),
+                             ctypes.byref(params), ctypes.c_void_p(coset.data_ptr()),
+                             ctypes.c_void_p(lr.data_ptr()), ctypes.c_void_p(logp.data_ptr()),
+                             ctypes.c_void_p(flags.data_ptr()))
+    _check(ctx.lib, ctx.h, st)
+    return coset, lr, logp, flags
+
+
+# short aliases
+contract_cosets = tn3d_contract_cosets
+decode = tn3d_decode
