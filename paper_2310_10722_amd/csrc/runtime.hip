@@ -26,6 +26,8 @@ struct tn3d_ctx_s {
   double timing_out[5] = {0, 0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> hot_ev;  // pairs around Gram / reabsorption launches
+  char* aux = nullptr;             // decode scratch
+  size_t aux_bytes = 0;
 };
 
 struct tn3d_net_s {
@@ -252,6 +254,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_Jm = cv.take<double>(nsw_max * L.bigcap);
   size_t o_logm = cv.take<double>(nsw_max);
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
+  size_t o_ctr = cv.take<unsigned long long>(1);
   tn3d_status st = ensure_ws(c, cv.off);
   if (st != TN3D_OK) return st;
   char* ws = c->ws;
@@ -299,6 +302,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.eps = pr.eps_rel;
     A.tau = pr.tau_gap;
     A.pchol_tol = prec == TN3D_PREC_FP64 ? 1e-15 : 1e-14;
+    A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
+    if (timing) HIPCHK(c, hipMemsetAsync(A.bytes_ctr, 0, 8, s));
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     if (timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
@@ -368,6 +373,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       HIPCHK(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
       t_layers += a;
       t_final += b;
+      unsigned long long nb = 0;
+      HIPCHK(c, hipMemcpy(&nb, A.bytes_ctr, 8, hipMemcpyDeviceToHost));
+      hot_bytes += double(nb);
       for (size_t h = 0; h + 3 < hot_i && h + 3 < c->hot_ev.size(); h += 4) {
         float g = 0, r = 0;
         HIPCHK(c, hipEventElapsedTime(&g, c->hot_ev[h], c->hot_ev[h + 1]));
@@ -503,6 +511,7 @@ void tn3d_ctx_destroy(tn3d_ctx c) {
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->hot_ev) (void)hipEventDestroy(e);
+  if (c->aux) (void)hipFree(c->aux);
   delete c;
 }
 
@@ -555,42 +564,45 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
                         double* logp, uint32_t* flags) {
   if (!c) return TN3D_E_INVALID;
   if (batch > 0 && (!coset || !logratio)) return fail(c, TN3D_E_INVALID, "null output");
-  double* lp = logp;
-  bool own = false;
-  if (!lp && batch > 0) {
-    if (hipMalloc(&lp, size_t(batch) * 4 * 8) != hipSuccess) return fail(c, TN3D_E_OOM, "logp scratch");
-    own = true;
+  if (batch <= 0) return contract_impl(c, batch, nets, synd, offs, pr, logp, flags);
+  HIPCHK(c, hipSetDevice(c->device));
+  // context-owned scratch: log p (when the caller passes none) and item lists
+  const size_t need = size_t(batch) * 4 * 8 + size_t(batch) * 4 + 512;
+  if (c->aux_bytes < need) {
+    if (c->aux) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->aux);
+      c->aux = nullptr;
+      c->aux_bytes = 0;
+    }
+    if (hipMalloc(&c->aux, need) != hipSuccess) return fail(c, TN3D_E_OOM, "decode scratch");
+    c->aux_bytes = need;
   }
+  double* lp = logp ? logp : reinterpret_cast<double*>(c->aux);
+  int32_t* d_items = reinterpret_cast<int32_t*>(c->aux + align256(size_t(batch) * 4 * 8));
   tn3d_status s = contract_impl(c, batch, nets, synd, offs, pr, lp, flags);
-  if (s == TN3D_OK && batch > 0) {
-    std::map<int, std::vector<int32_t>> by_nc;
-    int32_t* d_items = nullptr;
-    if (hipMalloc(&d_items, size_t(batch) * 4) != hipSuccess) {
-      s = fail(c, TN3D_E_OOM, "decode scratch");
-    } else {
-      // one launch per coset count
-      std::vector<int32_t> idx;
-      for (int ncs = 2; ncs <= 4; ++ncs) {
-        idx.clear();
-        for (int i = 0; i < batch; ++i)
-          if (nets[i]->P.n_cosets == ncs) idx.push_back(i);
-        if (idx.empty()) continue;
-        if (hipMemcpyAsync(d_items, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess) {
-          s = fail(c, TN3D_E_DEVICE, "decode item upload");
-          break;
-        }
-        launch_decode(int(idx.size()), ncs, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
-      }
-      (void)hipStreamSynchronize(c->stream);
-      (void)hipFree(d_items);
+  if (s != TN3D_OK) return s;
+  int ncs0 = nets[0]->P.n_cosets;
+  bool uniform = true;
+  for (int i = 1; i < batch; ++i)
+    if (nets[i]->P.n_cosets != ncs0) uniform = false;
+  if (uniform) {
+    hipLaunchKernelGGL(k_iota, dim3((batch + 255) / 256), dim3(256), 0, c->stream, d_items, batch, 0);
+    launch_decode(batch, ncs0, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
+  } else {
+    std::vector<int32_t> idx;
+    for (int ncs = 2; ncs <= 4; ++ncs) {
+      idx.clear();
+      for (int i = 0; i < batch; ++i)
+        if (nets[i]->P.n_cosets == ncs) idx.push_back(i);
+      if (idx.empty()) continue;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      HIPCHK(c, hipMemcpy(d_items, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+      launch_decode(int(idx.size()), ncs, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
     }
   }
-  if (own) {
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(lp);
-  }
-  return s;
+  HIPCHK(c, hipGetLastError());
+  return TN3D_OK;
 }
 
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {

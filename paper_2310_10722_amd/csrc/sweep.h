@@ -27,6 +27,7 @@ struct SweepArgs {
   const int32_t* items;     // [local item] -> global item
   const double* pool;       // op matrices and initial tensors
   double eps, tau, pchol_tol;
+  unsigned long long* bytes_ctr;  // if not null: site-tensor bytes moved by Gram + reabsorption
 };
 
 struct ZipArgs {

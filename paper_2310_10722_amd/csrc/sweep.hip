@@ -200,6 +200,8 @@ __global__ __launch_bounds__(NT) void k_gram(SweepArgs A, const DevGate* gates, 
       }
     }
   }
+  if (A.bytes_ctr && threadIdx.x == 0)
+    atomicAdd(A.bytes_ctr, (unsigned long long)(v.rows * ncols * int64_t(sizeof(T))));
   double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
 #pragma unroll
   for (int k = 0; k < NACC; ++k) {
@@ -351,6 +353,8 @@ __global__ __launch_bounds__(NT) void k_reabsorb(SweepArgs A, const DevGate* gat
   for (int e = threadIdx.x; e < nin * nout; e += NT) Ws[e] = W[2 + e];
   const T* in = tens<T>(A, par, sweep, site);
   T* out = tens<T>(A, par ^ 1, sweep, site);
+  if (A.bytes_ctr && threadIdx.x == 0)
+    atomicAdd(A.bytes_ctr, (unsigned long long)(v.rows * (nin + nout) * int64_t(sizeof(T))));
   for (int64_t r0 = 0; r0 < v.rows; r0 += TR) {
     __syncthreads();
     for (int e = threadIdx.x; e < TR * nin; e += NT) {
