@@ -115,9 +115,11 @@ def main():
     results = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    stats = None
     for _ in range(a.steps):
         results = tn3d.tn3d_decode(ctx, net, syn, prm)
         tl = ctx.last_timing()
+        stats = ctx.last_stats()
         lay_ms += tl[0]
         fin_ms += tl[1]
         hot_ms += tl[2]
@@ -152,8 +154,11 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "algorithmic_bytes_per_launch": hot_bytes / max(hot_launch, 1),
                      "avg_launch_ms": hot_ms / max(hot_launch, 1), "traffic": None},
+        "bonds_after_sweep": {"mean_dim": stats[0], "max_dim": stats[1],
+                              "mean_smallest_lambda": stats[3], "max_jacobi_sweeps": stats[4],
+                              "max_jacobi_sweeps_boundary": stats[5]},
         "flags": {"numeric": int(np.sum(flags & 1 != 0)), "trunc_cluster": int(np.sum(flags & 2 != 0)),
-                  "near_tie": int(np.sum(flags & 4 != 0))},
+                  "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0))},
     }
     if not a.no_cpu:
         n = min(a.cpu_sample, B)

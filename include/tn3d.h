@@ -52,6 +52,7 @@ typedef enum {
 #define TN3D_FLAG_NUMERIC 1u       /* a value was zero, negative or not finite */
 #define TN3D_FLAG_TRUNC_CLUSTER 2u /* a truncation cut inside a cluster of equal singular values */
 #define TN3D_FLAG_NEAR_TIE 4u      /* |log ratio| of the decision below params.near_tie */
+#define TN3D_FLAG_NO_CONVERGE 8u   /* a Jacobi SVD stopped at its sweep limit */
 
 /* Arithmetic of the layer absorption (site tensors and their contractions).
  * The truncation factorisations, singular values and log accumulators are
@@ -159,6 +160,15 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * was not enabled with tn3d_ctx_set_timing. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);
+
+/* Bond statistics of the last contraction with timing enabled, over all its
+ * sweeps, taken after the last layer: out[0] = mean bond dimension of the
+ * swept 2D network, out[1] = largest, out[2] = number of sweeps, out[3] = mean
+ * over sweeps of the smallest kept lambda (relative to its bond's largest),
+ * out[4] = most Jacobi sweeps any truncation needed, out[5] = same for the
+ * boundary MPS.
+ * Returns TN3D_E_INVALID if timing was not enabled. */
+tn3d_status tn3d_last_stats(tn3d_ctx ctx, double* out, int32_t n);
 
 #ifdef __cplusplus
 }

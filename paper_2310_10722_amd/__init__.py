@@ -9,6 +9,7 @@ from .tn3d import (  # noqa: F401
     PREC_FP32,
     PREC_FP64,
     FLAG_NEAR_TIE,
+    FLAG_NO_CONVERGE,
     FLAG_NUMERIC,
     FLAG_TRUNC_CLUSTER,
     Context,

@@ -91,10 +91,14 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
 // One-sided Jacobi: orthogonalises the `nv` vectors of length `len` stored at
 // A[v * vs + e * es] by plane rotations, applying the same rotations to the
 // rows of the nv x nv matrix J (row-major, leading dimension nv, initialised to
-// the identity here), so that A_out = A_in J.  Afterwards the vectors are
-// mutually orthogonal to relative precision tol.  Returns the number of sweeps.
+// the identity here), so that A_out = A_in J.  A pair is rotated while
+// |a_i . a_j| > tol |a_i| |a_j|; pairs in which a vector's norm is below
+// floor_rel * (largest initial norm) are left alone: such vectors hold only
+// rounding noise of the large ones, cannot be orthogonalised to relative
+// precision tol, and lie below the truncation threshold.  Returns the number
+// of sweeps; max_sweeps means no convergence.  red: 2 doubles scratch.
 __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double* J, double tol,
-                            int max_sweeps, int* flag) {
+                            double floor_rel, int max_sweeps, int* flag, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < nv * nv; e += nt) J[e] = (e / nv == e % nv) ? 1.0 : 0.0;
   const int ne = nv + (nv & 1);
@@ -102,6 +106,20 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
   int team = 64;
   while (team > 1 && team * npairs > nt) team >>= 1;
   const int pair = tid / team, lane = tid % team;
+  if (tid == 0) red[0] = 0.0;
+  __syncthreads();
+  // largest squared norm
+  for (int v = tid / 64; v < nv; v += nt / 64) {
+    double s = 0.0;
+    for (int e = tid % 64; e < len; e += 64) {
+      double x = A[v * vs + e * es];
+      s += x * x;
+    }
+    s = team_sum(s, 64);
+    if (tid % 64 == 0) atomicMax(reinterpret_cast<unsigned long long*>(red), __double_as_longlong(s));
+  }
+  __syncthreads();
+  const double floor2 = floor_rel * floor_rel * red[0];
   __syncthreads();
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
@@ -133,7 +151,7 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
         a = team_sum(a, team);
         b = team_sum(b, team);
         g = team_sum(g, team);
-        if (fabs(g) > tol * sqrt(a * b) && g != 0.0) {
+        if (a > floor2 && b > floor2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           double zeta = (b - a) / (2.0 * g);
           double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -199,6 +217,306 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
   }
   *split = 1;
   return top;
+}
+
+// C[m][n] = sum_k A(m, k) B(k, n) for a 512-thread workgroup, FP64, through
+// 64 x 64 output tiles and 32-deep K slices staged in LDS (lds: 4096 doubles).
+// Each thread owns a 4 x 2 block of the tile.  a_at / b_at return operands
+// (any layout); c_put(m, n, v) stores.
+template <class FA, class FB, class FC>
+__device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, double* lds) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 5, tx = tid & 31;
+  double* As = lds;         // [32][64]  (k, m)
+  double* Bs = lds + 2048;  // [32][64]  (k, n)
+  for (int m0 = 0; m0 < M; m0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) {
+      double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        __syncthreads();
+        for (int e = tid; e < 2048; e += 512) {
+          const int kk = e >> 6, mm = e & 63;
+          const int m = m0 + mm, k = k0 + kk;
+          As[e] = (m < M && k < K) ? a_at(m, k) : 0.0;
+          const int n = n0 + mm;
+          Bs[e] = (n < N && k < K) ? b_at(k, n) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+          double a[4], b[2];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = As[kk * 64 + ty * 4 + i];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) b[j] = Bs[kk * 64 + tx * 2 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] += a[i] * b[j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int m = m0 + ty * 4 + i, n = n0 + tx * 2 + j;
+          if (m < M && n < N) c_put(m, n, acc[i][j]);
+        }
+    }
+  __syncthreads();
+}
+
+// Left-looking pivoted Cholesky of the n x n symmetric PSD matrix G (any
+// memory, row-major, read only): rows of F (r x n, leading dimension n, in
+// fast memory) with F^T F = G up to a remainder whose largest diagonal is
+// <= tol * max(diag G).  Stops at rmax rows; *complete is 0 if the remainder
+// was still above the threshold then.  diag: n doubles, used: n ints scratch.
+__device__ int block_pchol_ll(const double* G, int n, double* F, int rmax, double tol, double* diag,
+                              int* used, double* red, int* complete) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < n; i += nt) {
+    diag[i] = G[i * n + i];
+    used[i] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, diag[i]);
+    red[0] = m;
+  }
+  __syncthreads();
+  const double thr = tol * red[0];
+  __syncthreads();
+  int r = 0;
+  int done = 0;
+  for (int k = 0; k < rmax; ++k) {
+    if (tid == 0) {
+      int p = -1;
+      double best = -1.0;
+      for (int i = 0; i < n; ++i)
+        if (!used[i] && diag[i] > best) {
+          best = diag[i];
+          p = i;
+        }
+      red[1] = double(p);
+      red[0] = best;
+      if (p >= 0) used[p] = 1;
+    }
+    __syncthreads();
+    const int p = int(red[1]);
+    const double piv = red[0];
+    if (p < 0 || !(piv > thr)) {
+      done = 1;
+      break;
+    }
+    const double rp = sqrt(piv);
+    for (int i = tid; i < n; i += nt) {
+      double v = G[p * n + i];
+      for (int j = 0; j < k; ++j) v -= F[j * n + p] * F[j * n + i];
+      v = used[i] ? 0.0 : v / rp;
+      if (i == p) v = rp;
+      F[k * n + i] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) diag[i] = used[i] ? 0.0 : diag[i] - F[k * n + i] * F[k * n + i];
+    __syncthreads();
+    r = k + 1;
+  }
+  if (!done && r == rmax) {
+    // check the remainder once more
+    if (tid == 0) {
+      double m = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (!used[i]) m = fmax(m, diag[i]);
+      red[0] = m;
+    }
+    __syncthreads();
+    done = red[0] <= thr;
+    __syncthreads();
+  }
+  *complete = done;
+  return r;
+}
+
+// Orthonormalises the b columns of X (n x b, row-major, leading dimension b)
+// in place by classical Gram-Schmidt applied twice per column.  A column whose
+// norm falls below 1e-13 of its norm before projection is set to zero.
+// dots: b doubles scratch.
+__device__ void block_cgs2(double* X, int n, int b, double* dots, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  for (int j = 0; j < b; ++j) {
+    // norm before projection
+    if (tid == 0) red[2] = 0.0;
+    __syncthreads();
+    if (wv == 0) {
+      double q = 0.0;
+      for (int e = lane; e < n; e += 64) q += X[e * b + j] * X[e * b + j];
+      q = team_sum(q, 64);
+      if (lane == 0) red[2] = q;
+    }
+    __syncthreads();
+    const double n0 = sqrt(red[2]);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = wv; i < j; i += nw) {
+        double d = 0.0;
+        for (int e = lane; e < n; e += 64) d += X[e * b + i] * X[e * b + j];
+        d = team_sum(d, 64);
+        if (lane == 0) dots[i] = d;
+      }
+      __syncthreads();
+      for (int e = tid; e < n; e += nt) {
+        double v = X[e * b + j];
+        for (int i = 0; i < j; ++i) v -= dots[i] * X[e * b + i];
+        X[e * b + j] = v;
+      }
+      __syncthreads();
+    }
+    if (wv == 0) {
+      double q = 0.0;
+      for (int e = lane; e < n; e += 64) q += X[e * b + j] * X[e * b + j];
+      q = team_sum(q, 64);
+      if (lane == 0) red[2] = q;
+    }
+    __syncthreads();
+    const double nj = sqrt(red[2]);
+    const double inv = (nj > 1e-13 * n0 && nj > 0.0) ? 1.0 / nj : 0.0;
+    for (int e = tid; e < n; e += nt) X[e * b + j] *= inv;
+    __syncthreads();
+  }
+}
+
+// Eigen-decomposition of the symmetric n x n matrix A (row-major, leading
+// dimension n, destroyed) by Householder reduction to tridiagonal form and
+// the implicit QL algorithm with Wilkinson-type shifts (the published
+// tridiagonal QL method of Bowdler, Martin, Reinsch and Wilkinson, 1968).  On return Z (n x n, row-major)
+// holds the eigenvectors in its columns and d the eigenvalues (unsorted).
+// Written for a workgroup of exactly one wavefront: the scalar recurrences of
+// the QL sweeps run redundantly in every lane, each lane owning rows of Z.
+// e, beta: n doubles scratch each.  Returns 0, or 1 if an eigenvalue took more
+// than 60 QL iterations.
+__device__ int wave_sym_eig(double* A, int n, double* Z, double* d, double* e, double* beta, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // --- tridiagonalisation: A = Q T Q^T, Q = H_0 ... H_{n-3}
+  for (int k = 0; k + 2 < n; ++k) {
+    double q = 0.0;
+    for (int i = k + 1 + tid; i < n; i += nt) q += A[i * n + k] * A[i * n + k];
+    q = team_sum(q, 64);
+    if (tid == 0) red[0] = q;
+    __syncthreads();
+    const double sigma = red[0];
+    const double x0 = A[(k + 1) * n + k];
+    __syncthreads();
+    if (!(sigma > 0.0) || sigma - x0 * x0 <= 1e-300) {
+      if (tid == 0) {
+        e[k] = x0;
+        beta[k] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x0 >= 0.0 ? -sqrt(sigma) : sqrt(sigma);
+    const double bk = 1.0 / (sigma - x0 * alpha);  // 2 / (v.v) with v0 = x0 - alpha
+    // v in column k below the diagonal
+    if (tid == 0) {
+      A[(k + 1) * n + k] = x0 - alpha;
+      e[k] = alpha;
+      beta[k] = bk;
+    }
+    __syncthreads();
+    // p = beta A' v  (p kept in Z's row k as scratch), then K = beta/2 p.v
+    double pv = 0.0;
+    for (int i = k + 1 + tid; i < n; i += nt) {
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += A[i * n + j] * A[j * n + k];
+      acc *= bk;
+      Z[k * n + i] = acc;
+      pv += acc * A[i * n + k];
+    }
+    pv = team_sum(pv, 64);
+    if (tid == 0) red[1] = 0.5 * bk * pv;
+    __syncthreads();
+    const double K = red[1];
+    for (int i = k + 1 + tid; i < n; i += nt) Z[k * n + i] -= K * A[i * n + k];  // w
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) {
+      const double vi = A[i * n + k], wi = Z[k * n + i];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= vi * Z[k * n + j] + wi * A[j * n + k];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) d[i] = A[i * n + i];
+  if (tid == 0) {
+    if (n >= 2) e[n - 2] = A[(n - 1) * n + n - 2];
+    e[n - 1] = 0.0;
+    if (n >= 2) beta[n - 2] = 0.0;
+    beta[n - 1] = 0.0;
+  }
+  __syncthreads();
+  // --- accumulate Q: Z = I, then Z <- H_k Z for k = n-3 .. 0
+  for (int x = tid; x < n * n; x += nt) Z[x] = (x / n == x % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double bk = beta[k];
+    if (bk == 0.0) continue;
+    for (int j = k + 1 + tid; j < n; j += nt) {
+      double u = 0.0;
+      for (int i = k + 1; i < n; ++i) u += A[i * n + k] * Z[i * n + j];
+      u *= bk;
+      for (int i = k + 1; i < n; ++i) Z[i * n + j] -= u * A[i * n + k];
+    }
+    __syncthreads();
+  }
+  // --- implicit QL with shifts on (d, e), rotations accumulated into Z
+  int fail = 0;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double dd = fabs(d[m]) + fabs(d[m + 1]);
+        if (fabs(e[m]) <= 1e-16 * dd || e[m] == 0.0) break;
+      }
+      if (m == l) break;
+      if (iter >= 60) {
+        fail = 1;
+        break;
+      }
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      bool early = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = sn * e[i], b = cs * e[i];
+        r = hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          early = true;
+          break;
+        }
+        sn = f / r;
+        cs = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * sn + 2.0 * cs * b;
+        p = sn * r;
+        d[i + 1] = g + p;
+        g = cs * r - b;
+        for (int kr = tid; kr < n; kr += nt) {
+          const double zt = Z[kr * n + i + 1], zi = Z[kr * n + i];
+          Z[kr * n + i + 1] = sn * zi + cs * zt;
+          Z[kr * n + i] = cs * zi - sn * zt;
+        }
+      }
+      if (early) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  __syncthreads();
+  return fail;
 }
 
 }  // namespace tn3d

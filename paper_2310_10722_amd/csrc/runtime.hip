@@ -24,6 +24,8 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   bool timing = false;
   double timing_out[5] = {0, 0, 0, 0, 0};
+  double stats_out[6] = {0, 0, 0, 0, 0, 0};
+  int nb_last = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> hot_ev;  // pairs around Gram / reabsorption launches
   char* aux = nullptr;             // decode scratch
@@ -175,7 +177,7 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   b += P.n_bonds * (4 + 8 + 8 * size_t(chi)) + P.Lx * P.Ly * 8 + 4;
   b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8;
   b += L.fin_stride * 8;
-  b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + 8 + 4;
+  b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 4 * L.bigcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
   L.per_sweep_bytes = b + 64 * 20;
   return L;
 }
@@ -252,9 +254,12 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_L4 = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Th = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Jm = cv.take<double>(nsw_max * L.bigcap);
+  size_t o_Gm = cv.take<double>(prec == TN3D_PREC_FP64 ? 1 : nsw_max * L.bigcap);
+  size_t o_zdim = cv.take<int32_t>(nsw_max * 12);
+  size_t o_zS = cv.take<double>(nsw_max * 1024);
   size_t o_logm = cv.take<double>(nsw_max);
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
-  size_t o_ctr = cv.take<unsigned long long>(1);
+  size_t o_ctr = cv.take<unsigned long long>(2);
   tn3d_status st = ensure_ws(c, cv.off);
   if (st != TN3D_OK) return st;
   char* ws = c->ws;
@@ -302,8 +307,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.eps = pr.eps_rel;
     A.tau = pr.tau_gap;
     A.pchol_tol = prec == TN3D_PREC_FP64 ? 1e-15 : 1e-14;
+    A.jtol = prec == TN3D_PREC_FP64 ? 1e-14 : 1e-10;
+    A.jfloor = prec == TN3D_PREC_FP64 ? std::min(1e-13, 0.1 * pr.eps_rel) : std::min(1e-8, 0.1 * pr.eps_rel);
     A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
-    if (timing) HIPCHK(c, hipMemsetAsync(A.bytes_ctr, 0, 8, s));
+    A.sweeps_max = reinterpret_cast<int32_t*>(ws + o_ctr + 8);
+    HIPCHK(c, hipMemsetAsync(ws + o_ctr, 0, 16, s));
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     if (timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
@@ -360,6 +368,13 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.flags = reinterpret_cast<uint32_t*>(ws + o_zfl);
     Z.eps = pr.eps_rel;
     Z.tau = pr.tau_gap;
+    Z.jtol = A.jtol;
+    Z.jfloor = A.jfloor;
+    Z.gram_path = prec == TN3D_PREC_FP64 ? 0 : 1;
+    Z.sweeps_max = A.sweeps_max;
+    Z.zdim = reinterpret_cast<int32_t*>(ws + o_zdim);
+    Z.zS = reinterpret_cast<double*>(ws + o_zS);
+    Z.Gm = reinterpret_cast<double*>(ws + o_Gm);
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
       for (int x = 0; x < P.Lx; ++x) launch_zip_step(Z, x, y, s);
@@ -376,6 +391,26 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       unsigned long long nb = 0;
       HIPCHK(c, hipMemcpy(&nb, A.bytes_ctr, 8, hipMemcpyDeviceToHost));
       hot_bytes += double(nb);
+      std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
+      std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
+      HIPCHK(c, hipMemcpy(bd.data(), A.bond_dim, bd.size() * 4, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(lm.data(), A.lam, lm.size() * 8, hipMemcpyDeviceToHost));
+      for (int sw = 0; sw < A.n_sweeps; ++sw) {
+        double mn = 1.0;
+        for (int b = 0; b < P.n_bonds; ++b) {
+          const int D = bd[size_t(sw) * P.n_bonds + b];
+          c->stats_out[0] += D;
+          c->stats_out[1] = std::max(c->stats_out[1], double(D));
+          mn = std::min(mn, lm[(size_t(sw) * P.n_bonds + b) * pr.chi + D - 1]);
+        }
+        c->stats_out[3] += mn;
+      }
+      c->stats_out[2] += A.n_sweeps;
+      int32_t smax[2] = {0, 0};
+      HIPCHK(c, hipMemcpy(smax, A.sweeps_max, 8, hipMemcpyDeviceToHost));
+      c->stats_out[4] = std::max(c->stats_out[4], double(smax[0]));
+      c->stats_out[5] = std::max(c->stats_out[5], double(smax[1]));
+      c->nb_last = P.n_bonds;
       for (size_t h = 0; h + 3 < hot_i && h + 3 < c->hot_ev.size(); h += 4) {
         float g = 0, r = 0;
         HIPCHK(c, hipEventElapsedTime(&g, c->hot_ev[h], c->hot_ev[h + 1]));
@@ -436,6 +471,7 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
   HIPCHK(c, hipSetDevice(c->device));
   if (c->timing) {
     for (int k = 0; k < 5; ++k) c->timing_out[k] = 0;
+    for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
     size_t need = 0;
     for (int i = 0; i < batch; ++i) need = std::max(need, nets[i]->P.layers.size() * 16 + 4);
     while (c->hot_ev.size() < need) {
@@ -608,6 +644,17 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   if (!c) return TN3D_E_INVALID;
   c->timing = enable != 0;
+  return TN3D_OK;
+}
+
+tn3d_status tn3d_last_stats(tn3d_ctx c, double* out, int32_t n) {
+  if (!c || !out) return TN3D_E_INVALID;
+  if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
+  const double ns = c->stats_out[2] > 0 ? c->stats_out[2] : 1.0;
+  double v[6] = {0, c->stats_out[1], c->stats_out[2], c->stats_out[3] / ns, c->stats_out[4], c->stats_out[5]};
+  // mean over all bonds of all sweeps
+  v[0] = c->stats_out[0] / (ns * (c->nb_last > 0 ? c->nb_last : 1));
+  for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
   return TN3D_OK;
 }
 

@@ -27,7 +27,9 @@ struct SweepArgs {
   const int32_t* items;     // [local item] -> global item
   const double* pool;       // op matrices and initial tensors
   double eps, tau, pchol_tol;
-  unsigned long long* bytes_ctr;  // if not null: site-tensor bytes moved by Gram + reabsorption
+  double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
+  unsigned long long* bytes_ctr;
+  int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
 };
 
 struct ZipArgs {
@@ -50,6 +52,12 @@ struct ZipArgs {
   double* logm;             // [sweep]
   uint32_t* flags;
   double eps, tau;
+  double jtol, jfloor;
+  int32_t gram_path;        // 1: FP32 mode, step SVDs through the Gram of the smaller family
+  int32_t* sweeps_max;
+  double* Gm;               // [sweep][bigcap] that Gram
+  int32_t* zdim;            // [sweep][12] shapes passed between the step kernels
+  double* zS;               // [sweep][1024] singular values of the step
 };
 
 // Launchers (all enqueue on `st`).  T: 0 = double, 1 = float storage.

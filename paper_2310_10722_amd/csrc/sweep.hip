@@ -26,6 +26,7 @@ namespace tn3d {
 namespace {
 
 constexpr int NT = 256;
+constexpr int SNT = 64;    // one wavefront per bond truncation: barriers stay cheap
 constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
 constexpr int MAXCHI = 64;
 
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(NT) void k_gram(SweepArgs A, const DevGate* gates, 
 // ---------------------------------------------------------------------------
 // truncation of each gated bond: FP64, one workgroup per bond
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
+__global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
                                               double* wout, int ncap) {
   extern __shared__ double sm[];
   const int gi = blockIdx.x, sweep = blockIdx.y, tid = threadIdx.x;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   const double* PA = A.pool + g.pA;
   const double* PB = A.pool + g.pB;
   const int nA = dA * D, nB = dB * D;
-  for (int e = tid; e < n * n; e += NT) {
+  for (int e = tid; e < n * n; e += SNT) {
     const int r = e / n, c = e % n;
     const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
     double za = 0.0, zb = 0.0;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
   const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
   // C = F_A F_B^T (rA x rB) into ZA
-  for (int e = tid; e < rA * rB; e += NT) {
+  for (int e = tid; e < rA * rB; e += SNT) {
     const int i = e / rB, j = e % rB;
     double s = 0.0;
     for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
@@ -267,9 +268,13 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   int Dn = 0, split = 0;
   double s1 = 0.0;
   if (rA > 0 && rB > 0) {
-    block_jacobi(ZA, 1, rB, rB, rA, ZB, 1e-15, 80, flag);  // columns of C; V' in ZB
+    const int nsw = block_jacobi(ZA, 1, rB, rB, rA, ZB, A.jtol, A.jfloor, 40, flag, red);  // columns of C; V' in ZB
+    if (tid == 0) {
+      atomicMax(&A.sweeps_max[0], nsw);
+      if (nsw >= 40) atomicOr(&A.flags[sweep], 8u);
+    }
     block_norms_sorted(ZA, 1, rB, rB, rA, S, ord);
-    for (int m = tid; m < rB; m += NT) Ss[m] = S[ord[m]];
+    for (int m = tid; m < rB; m += SNT) Ss[m] = S[ord[m]];
     __syncthreads();
     Dn = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &split);
     s1 = Ss[0];
@@ -292,11 +297,11 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (split) f |= 2u;
     if (f) atomicOr(&A.flags[sweep], f);
   }
-  for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  for (int m = tid; m < Dn; m += SNT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
   const double* OA = A.pool + g.oA;
   const double* OB = A.pool + g.oB;
   const int ncA = dA * Dn, ncB = dB * Dn;
-  for (int e = tid; e < nA * ncA; e += NT) {
+  for (int e = tid; e < nA * ncA; e += SNT) {
     double w = 0.0;
     if (!bad) {
       const int row = e / ncA, col = e % ncA;
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     }
     WA[2 + e] = w;
   }
-  for (int e = tid; e < nB * ncB; e += NT) {
+  for (int e = tid; e < nB * ncB; e += SNT) {
     double w = 0.0;
     if (!bad) {
       const int row = e / ncB, col = e % ncB;
@@ -448,26 +453,44 @@ __device__ __forceinline__ int zbd(const ZipArgs& Z, int s, int b) {
   return Z.bond_dim[int64_t(s) * Z.n_bonds + b];
 }
 
-__global__ __launch_bounds__(NT) void k_zip_step(ZipArgs Z, int x, int y) {
-  __shared__ double S[1024 + 8];
-  __shared__ double Ss[1024];
-  __shared__ int ord[1024];
-  __shared__ int flag[4];
-  __shared__ double red[8];
-  const int s = blockIdx.x, tid = threadIdx.x;
-  const int Lx = Z.Lx, Ly = Z.Ly;
-  const int nbh = (Lx - 1) * Ly;
-  const int cur = y & 1;
-  const double* Mold = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Lx + x) * Z.mcap;
-  double* Mnew = (cur ? Z.mps0 : Z.mps1) + (int64_t(s) * Lx + x) * Z.mcap;
+constexpr int ZNT = 512;  // threads of the contraction / output kernels of a boundary-MPS step
+constexpr int ZBT = 64;   // threads of the decomposition kernel (one wavefront)
+
+// One zip-up step of the boundary MPS (row y, column x) for one sweep, in
+// three kernels:
+//   a: L4[nu,w,n,a'] = sum_a K[nu,a,w] M[a,n,a'];
+//      Th[(nu,s'),(a',w')] = sum_{w,n} L4[nu,w,n,a'] T[w,w',n,s'];
+//      in FP32 mode also the Gram G of the smaller family of Th (its rows if
+//      R <= C, else its columns)
+//   b: orthonormal singular vectors Fv of that family and singular values S:
+//      one-sided Jacobi on the columns of G (FP32 mode; G is PSD, so the
+//      rotated column norms are its eigenvalues S^2), or on the family of Th
+//      itself (FP64 mode); rank rule with chi_m
+//   c: rows family: new MPS site U = Fv, carry K = Fv^T Th;
+//      columns family: U = Th Fv / S, carry K = S Fv^T;
+//      the last column keeps Th whole; the new site is divided by its max.
+// zdim per sweep: R, C, nu, sD, aR, wR, rows, nv, Dn.
+
+__device__ __forceinline__ void zip_dims(const ZipArgs& Z, int s, int x, int y, int& sd, int& aR, int& wL,
+                                         int& wR, int& nU, int& sD) {
+  const int Lx = Z.Lx, Ly = Z.Ly, nbh = (Lx - 1) * Ly, cur = y & 1;
   const int* mo = Z.mdim + ((int64_t(s) * 2 + cur) * Lx + x) * 3;
-  int* mn = Z.mdim + ((int64_t(s) * 2 + (cur ^ 1)) * Lx + x) * 3;
-  const int sd = mo[1], aR = mo[2];
-  const int wL = x > 0 ? zbd(Z, s, y * (Lx - 1) + x - 1) : 1;
-  const int wR = x + 1 < Lx ? zbd(Z, s, y * (Lx - 1) + x) : 1;
-  const int nU = y > 0 ? zbd(Z, s, nbh + (y - 1) * Lx + x) : 1;
-  const int sD = y + 1 < Ly ? zbd(Z, s, nbh + y * Lx + x) : 1;
-  const double* Tt = Z.fin + int64_t(s) * Z.fin_stride + Z.fin_off[y * Lx + x];
+  sd = mo[1];
+  aR = mo[2];
+  wL = x > 0 ? zbd(Z, s, y * (Lx - 1) + x - 1) : 1;
+  wR = x + 1 < Lx ? zbd(Z, s, y * (Lx - 1) + x) : 1;
+  nU = y > 0 ? zbd(Z, s, nbh + (y - 1) * Lx + x) : 1;
+  sD = y + 1 < Ly ? zbd(Z, s, nbh + y * Lx + x) : 1;
+}
+
+__global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y) {
+  __shared__ double gst[4096];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int cur = y & 1;
+  const double* Mold = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Z.Lx + x) * Z.mcap;
+  int sd, aR, wL, wR, nU, sD;
+  zip_dims(Z, s, x, y, sd, aR, wL, wR, nU, sD);
+  const double* Tt = Z.fin + int64_t(s) * Z.fin_stride + Z.fin_off[y * Z.Lx + x];
   double* Kp = Z.K + int64_t(s) * Z.kcap;
   int* kd = Z.kdim + int64_t(s) * 3;
   if (x == 0) {
@@ -480,92 +503,182 @@ __global__ __launch_bounds__(NT) void k_zip_step(ZipArgs Z, int x, int y) {
   const int nu = kd[0], ka = kd[1];
   double* L4 = Z.L4 + int64_t(s) * Z.bigcap;
   double* Th = Z.Th + int64_t(s) * Z.bigcap;
-  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
-  // L4[nu][w][n][aR] = sum_a K[nu][a][w] M[a][n][aR]
-  {
-    const int tot = nu * wL * sd * aR;
-    for (int e = tid; e < tot; e += NT) {
-      const int ar = e % aR;
-      int t = e / aR;
-      const int nn = t % sd;
-      t /= sd;
-      const int w = t % wL, v = t / wL;
-      double acc = 0.0;
-      for (int a = 0; a < ka; ++a) acc += Kp[(v * ka + a) * wL + w] * Mold[(a * sd + nn) * aR + ar];
-      L4[e] = acc;
-    }
-  }
-  __syncthreads();
-  // Th[(nu, sD)][(aR, wR)] = sum_{w, n} L4[nu][w][n][aR] T[w][wR][n][sD]
+  const int sa = sd * aR;
+  block_gemm512(
+      nu * wL, sa, ka, [&](int m, int k) { return Kp[((m / wL) * ka + k) * wL + m % wL]; },
+      [&](int k, int n) { return Mold[k * sa + n]; }, [&](int m, int n, double v) { L4[m * sa + n] = v; }, gst);
   const int R = nu * sD, C = aR * wR;
-  for (int e = tid; e < R * C; e += NT) {
-    const int row = e / C, col = e % C;
-    const int v = row / sD, so = row % sD, ar = col / wR, we = col % wR;
-    double acc = 0.0;
-    for (int w = 0; w < wL; ++w)
-      for (int nn = 0; nn < sd; ++nn)
-        acc += L4[((v * wL + w) * sd + nn) * aR + ar] * Tt[((w * wR + we) * nU + nn) * sD + so];
-    Th[e] = acc;
+  block_gemm512(
+      nu * aR, wR * sD, wL * sd,
+      [&](int m, int k) { return L4[(((m / aR) * wL + k / sd) * sd + k % sd) * aR + m % aR]; },
+      [&](int k, int n) { return Tt[(((k / sd) * wR + n / sD) * nU + k % sd) * sD + n % sD]; },
+      [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; }, gst);
+  const bool rows = R <= C;
+  const int nv = rows ? R : C;
+  if (x + 1 < Z.Lx && Z.gram_path) {
+    double* G = Z.Gm + int64_t(s) * Z.bigcap;
+    if (rows)
+      block_gemm512(
+          R, R, C, [&](int m, int k) { return Th[m * C + k]; }, [&](int k, int n) { return Th[n * C + k]; },
+          [&](int m, int n, double v) { G[m * R + n] = v; }, gst);
+    else
+      block_gemm512(
+          C, C, R, [&](int m, int k) { return Th[k * C + m]; }, [&](int k, int n) { return Th[k * C + n]; },
+          [&](int m, int n, double v) { G[m * C + n] = v; }, gst);
+  }
+  if (tid == 0) {
+    int* zd = Z.zdim + int64_t(s) * 12;
+    zd[0] = R;
+    zd[1] = C;
+    zd[2] = nu;
+    zd[3] = sD;
+    zd[4] = aR;
+    zd[5] = wR;
+    zd[6] = rows ? 1 : 0;
+    zd[7] = nv;
+    zd[8] = 1;
+  }
+}
+
+__global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_doubles) {
+  extern __shared__ double zsm[];
+  __shared__ double S[1024];
+  __shared__ int ord[1024];
+  __shared__ int flag[4];
+  __shared__ double red[8];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* zd = Z.zdim + int64_t(s) * 12;
+  const int R = zd[0], C = zd[1];
+  const bool rows = zd[6] != 0;
+  const int nv = zd[7], len = rows ? C : R;
+  double* Th = Z.Th + int64_t(s) * Z.bigcap;
+  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
+  double* Sout = Z.zS + int64_t(s) * 1024;
+  int nsw = 0;
+  const double* Zv = nullptr;  // eigen / singular vectors of the family, columns
+  if (Z.gram_path) {
+    // symmetric eigenproblem of the PSD Gram: eigenvalues S^2, eigenvectors Fv
+    double* G = Z.Gm + int64_t(s) * Z.bigcap;
+    const bool fits = 2 * int64_t(nv) * nv + 3 * nv <= lds_doubles;
+    double* A = fits ? zsm : G;
+    double* Zm = fits ? zsm + nv * nv : Jm;
+    double* dv = fits ? zsm + 2 * nv * nv : zsm;
+    if (fits)
+      for (int e = tid; e < nv * nv; e += ZBT) A[e] = G[e];
+    __syncthreads();
+    const int fail = wave_sym_eig(A, nv, Zm, dv, dv + nv, dv + 2 * nv, red);
+    for (int v = tid; v < nv; v += ZBT) {
+      const double lv = dv[v];
+      int rk = 0;
+      for (int u = 0; u < nv; ++u)
+        if (dv[u] > lv || (dv[u] == lv && u < v)) ++rk;
+      ord[rk] = v;
+    }
+    __syncthreads();
+    for (int m = tid; m < nv; m += ZBT) Sout[m] = sqrt(fmax(dv[ord[m]], 0.0));
+    nsw = fail ? 40 : 1;
+    Zv = Zm;
+  } else {
+    double* A;
+    double* J;
+    long vs, es;
+    const bool fits = int64_t(nv) * len + int64_t(nv) * nv <= lds_doubles;
+    if (fits) {
+      A = zsm;
+      J = zsm + nv * len;
+      for (int e = tid; e < nv * len; e += ZBT) {
+        const int v = e / len, k = e % len;
+        A[e] = rows ? Th[v * C + k] : Th[k * C + v];
+      }
+      vs = len;
+      es = 1;
+    } else {
+      A = Th;
+      J = Jm;
+      vs = rows ? C : 1;
+      es = rows ? 1 : C;
+    }
+    __syncthreads();
+    nsw = block_jacobi(A, vs, es, nv, len, J, Z.jtol, Z.jfloor, 40, flag, red);
+    block_norms_sorted(A, vs, es, nv, len, S, ord);
+    for (int m = tid; m < nv; m += ZBT) Sout[m] = S[ord[m]];
+    Zv = J;
   }
   __syncthreads();
-  int Dn = 1;
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
   bool bad = false;
+  if (Dn < 1) {
+    Dn = 1;
+    bad = true;
+  }
+  for (int e = tid; e < nv * Dn; e += ZBT) Fv[e] = Zv[(e / Dn) * nv + ord[e % Dn]];
+  if (tid == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], nsw);
+    uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (nsw >= 40 ? 8u : 0u);
+    if (f) atomicOr(&Z.flags[s], f);
+  }
+}
+
+__global__ __launch_bounds__(ZNT) void k_zip_c(ZipArgs Z, int x, int y) {
+  __shared__ double gst[4096];
+  __shared__ double red[8];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int Lx = Z.Lx, cur = y & 1;
+  double* Mnew = (cur ? Z.mps0 : Z.mps1) + (int64_t(s) * Lx + x) * Z.mcap;
+  int* mn = Z.mdim + ((int64_t(s) * 2 + (cur ^ 1)) * Lx + x) * 3;
+  const int* zd = Z.zdim + int64_t(s) * 12;
+  const int R = zd[0], C = zd[1], nu = zd[2], sD = zd[3], aR = zd[4], wR = zd[5];
+  const bool rows = zd[6] != 0;
+  const int nv = zd[7];
+  const double* Th = Z.Th + int64_t(s) * Z.bigcap;
+  double* Kp = Z.K + int64_t(s) * Z.kcap;
+  int* kd = Z.kdim + int64_t(s) * 3;
+  int Dn = 1;
   if (x + 1 < Lx) {
-    int split = 0;
-    if (R <= C) {
-      block_jacobi(Th, C, 1, R, C, Jm, 1e-15, 80, flag);
-      block_norms_sorted(Th, C, 1, R, C, S, ord);
-      for (int m = tid; m < R; m += NT) Ss[m] = S[ord[m]];
-      __syncthreads();
-      Dn = rank_rule(Ss, R, Z.chi_m, Z.eps, Z.tau, &split);
-      if (Dn < 1) {
-        Dn = 1;
-        bad = true;
-      }
-      for (int e = tid; e < R * Dn; e += NT) Mnew[e] = Jm[(e / Dn) * R + ord[e % Dn]];
-      for (int e = tid; e < Dn * C; e += NT) Kp[e] = Th[ord[e / C] * C + e % C];
+    Dn = zd[8];
+    const int D = Dn;
+    const double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
+    const double* Sv = Z.zS + int64_t(s) * 1024;
+    if (rows) {
+      for (int e = tid; e < R * D; e += ZNT) Mnew[e] = Fv[e];
+      block_gemm512(
+          D, C, R, [&](int m, int k) { return Fv[k * D + m]; }, [&](int k, int n) { return Th[k * C + n]; },
+          [&](int m, int n, double v) { Kp[m * C + n] = v; }, gst);
     } else {
-      block_jacobi(Th, 1, C, C, R, Jm, 1e-15, 80, flag);
-      block_norms_sorted(Th, 1, C, C, R, S, ord);
-      for (int m = tid; m < C; m += NT) Ss[m] = S[ord[m]];
-      __syncthreads();
-      Dn = rank_rule(Ss, C, Z.chi_m, Z.eps, Z.tau, &split);
-      if (Dn < 1) {
-        Dn = 1;
-        bad = true;
-      }
-      for (int e = tid; e < R * Dn; e += NT) {
-        const double sv = Ss[e % Dn];
-        Mnew[e] = sv > 0.0 ? Th[(e / Dn) * C + ord[e % Dn]] / sv : 0.0;
-      }
-      for (int e = tid; e < Dn * C; e += NT) Kp[e] = Ss[e / C] * Jm[(e % C) * C + ord[e / C]];
+      block_gemm512(
+          R, D, C, [&](int m, int k) { return Th[m * C + k]; }, [&](int k, int n) { return Fv[k * D + n]; },
+          [&](int m, int n, double v) {
+            const double sv = Sv[n];
+            Mnew[m * D + n] = sv > 0.0 ? v / sv : 0.0;
+          },
+          gst);
+      for (int e = tid; e < D * C; e += ZNT) Kp[e] = Sv[e / C] * Fv[(e % C) * D + e / C];
     }
+    (void)nv;
     if (tid == 0) {
-      mn[0] = nu;
-      mn[1] = sD;
-      mn[2] = Dn;
       kd[0] = Dn;
       kd[1] = aR;
       kd[2] = wR;
-      uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u);
-      if (f) atomicOr(&Z.flags[s], f);
     }
   } else {
-    for (int e = tid; e < R; e += NT) Mnew[e] = Th[e * C];
-    if (tid == 0) {
-      mn[0] = nu;
-      mn[1] = sD;
-      mn[2] = 1;
-    }
+    for (int e = tid; e < R; e += ZNT) Mnew[e] = Th[e * C];
+  }
+  if (tid == 0) {
+    mn[0] = nu;
+    mn[1] = sD;
+    mn[2] = Dn;
   }
   __syncthreads();
   const int tot = R * Dn;
   double m = 0.0;
-  for (int e = tid; e < tot; e += NT) m = fmax(m, fabs(Mnew[e]));
+  for (int e = tid; e < tot; e += ZNT) m = fmax(m, fabs(Mnew[e]));
   m = block_max_abs_reduce(m, red);
   const bool zero = !(m > 0.0) || !isfinite(m);
   const double c = zero ? 1.0 : m;
-  for (int e = tid; e < tot; e += NT) Mnew[e] /= c;
+  for (int e = tid; e < tot; e += ZNT) Mnew[e] /= c;
   if (tid == 0) {
     Z.logm[s] += log(c);
     if (zero) atomicOr(&Z.flags[s], 1u);
@@ -701,7 +814,7 @@ void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const doubl
                               160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(NT), lds, st, A, gates, n_g, gin, wout, ncap);
+  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), lds, st, A, gates, n_g, gin, wout, ncap);
 }
 
 void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
@@ -749,7 +862,16 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
-  hipLaunchKernelGGL(k_zip_step, dim3(Z.n_sweeps), dim3(NT), 0, st, Z, x, y);
+  const int lds = Z.gram_path ? 8384 : 18432;  // doubles; FP32 mode keeps two workgroups per CU
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              18432 * 8);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
+  if (x + 1 < Z.Lx) hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(lds) * 8, st, Z, x, y, lds);
+  hipLaunchKernelGGL(k_zip_c, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
 }
 
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st) {

@@ -21,6 +21,7 @@ PREC_FP32 = 1
 FLAG_NUMERIC = 1
 FLAG_TRUNC_CLUSTER = 2
 FLAG_NEAR_TIE = 4
+FLAG_NO_CONVERGE = 8
 
 STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OOM", -5: "DEVICE",
           -6: "NUMERIC"}
@@ -30,7 +31,7 @@ SYMBOLS = [
     "tn3d_params_default", "tn3d_ctx_create", "tn3d_ctx_destroy", "tn3d_last_error",
     "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
-    "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing",
+    "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_last_stats",
 ]
 
 
@@ -78,6 +79,8 @@ def load_library(path: str | None = None):
                                 c_p]
     lib.tn3d_ctx_set_timing.argtypes = [c_p, i32]
     lib.tn3d_last_timing.argtypes = [c_p, ctypes.POINTER(f64), i32]
+    lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
+    lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_contract_cosets",
               "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing"):
         getattr(lib, f).restype = i32
@@ -147,6 +150,11 @@ class Context:
     def last_timing(self):
         out = (ctypes.c_double * 5)()
         _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 5))
+        return list(out)
+
+    def last_stats(self):
+        out = (ctypes.c_double * 6)()
+        _check(self.lib, self.h, self.lib.tn3d_last_stats(self.h, out, 6))
         return list(out)
 
 
