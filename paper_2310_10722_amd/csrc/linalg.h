@@ -391,6 +391,7 @@ __device__ void block_cgs2(double* X, int n, int b, double* dots, double* red) {
 // the implicit QL algorithm with Wilkinson-type shifts (the published
 // tridiagonal QL method of Bowdler, Martin, Reinsch and Wilkinson, 1968).  On return Z (n x n, row-major)
 // holds the eigenvectors in its columns and d the eigenvalues (unsorted).
+// A should be scaled to O(1) entries (plane rotations use sqrt(f^2 + g^2)).
 // Written for a workgroup of exactly one wavefront: the scalar recurrences of
 // the QL sweeps run redundantly in every lane, each lane owning rows of Z.
 // e, beta: n doubles scratch each.  Returns 0, or 1 if an eigenvalue took more
@@ -482,13 +483,13 @@ __device__ int wave_sym_eig(double* A, int n, double* Z, double* d, double* e, d
         break;
       }
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = hypot(g, 1.0);
+      double r = sqrt(g * g + 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
       double sn = 1.0, cs = 1.0, p = 0.0;
       bool early = false;
       for (int i = m - 1; i >= l; --i) {
         const double f = sn * e[i], b = cs * e[i];
-        r = hypot(f, g);
+        r = sqrt(f * f + g * g);  // |f|, |g| stay O(1) for a normalised matrix
         e[i + 1] = r;
         if (r == 0.0) {
           d[i + 1] -= p;
@@ -496,8 +497,9 @@ __device__ int wave_sym_eig(double* A, int n, double* Z, double* d, double* e, d
           early = true;
           break;
         }
-        sn = f / r;
-        cs = g / r;
+        const double ir = 1.0 / r;
+        sn = f * ir;
+        cs = g * ir;
         g = d[i + 1] - p;
         r = (d[i] - g) * sn + 2.0 * cs * b;
         p = sn * r;
@@ -515,6 +517,175 @@ __device__ int wave_sym_eig(double* A, int n, double* Z, double* d, double* e, d
       e[m] = 0.0;
     }
   }
+  __syncthreads();
+  return fail;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = team_sum(v, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Multi-wavefront version of wave_sym_eig for larger n: the reduction to
+// tridiagonal form and the accumulation of Q use the whole workgroup; in the
+// QL phase each wavefront repeats the scalar recurrence on its own copy of
+// (d, e) (dw: 2 n doubles per wavefront) and rotates only the rows of Z its
+// lanes own (row k belongs to thread k mod blockDim, at most 4 rows each),
+// carrying the moving column in registers.  red: 16 doubles.
+__device__ int block_sym_eig(double* A, int n, double* Z, double* d, double* e, double* beta, double* dw,
+                             double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k + 2 < n; ++k) {
+    double q = 0.0;
+    for (int i = k + 1 + tid; i < n; i += nt) q += A[i * n + k] * A[i * n + k];
+    const double sigma = block_sum(q, red);
+    const double x0 = A[(k + 1) * n + k];
+    __syncthreads();
+    if (!(sigma > 0.0) || sigma - x0 * x0 <= 1e-300) {
+      if (tid == 0) {
+        e[k] = x0;
+        beta[k] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x0 >= 0.0 ? -sqrt(sigma) : sqrt(sigma);
+    const double bk = 1.0 / (sigma - x0 * alpha);
+    if (tid == 0) {
+      A[(k + 1) * n + k] = x0 - alpha;
+      e[k] = alpha;
+      beta[k] = bk;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = k + 1 + tid; i < n; i += nt) {
+      double acc = 0.0;
+      for (int j = k + 1; j < n; ++j) acc += A[i * n + j] * A[j * n + k];
+      acc *= bk;
+      Z[k * n + i] = acc;
+      pv += acc * A[i * n + k];
+    }
+    const double K = 0.5 * bk * block_sum(pv, red);
+    for (int i = k + 1 + tid; i < n; i += nt) Z[k * n + i] -= K * A[i * n + k];
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) {
+      const double vi = A[i * n + k], wi = Z[k * n + i];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= vi * Z[k * n + j] + wi * A[j * n + k];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) d[i] = A[i * n + i];
+  if (tid == 0) {
+    if (n >= 2) e[n - 2] = A[(n - 1) * n + n - 2];
+    e[n - 1] = 0.0;
+    if (n >= 2) beta[n - 2] = 0.0;
+    beta[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int x = tid; x < n * n; x += nt) Z[x] = (x / n == x % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double bk = beta[k];
+    if (bk == 0.0) continue;
+    for (int j = k + 1 + tid; j < n; j += nt) {
+      double u = 0.0;
+      for (int i = k + 1; i < n; ++i) u += A[i * n + k] * Z[i * n + j];
+      u *= bk;
+      for (int i = k + 1; i < n; ++i) Z[i * n + j] -= u * A[i * n + k];
+    }
+    __syncthreads();
+  }
+  // QL: per-wavefront copies of (d, e)
+  const int w = tid >> 6;
+  double* dd = dw + size_t(w) * 2 * n;
+  double* ee = dd + n;
+  const int ws = nt < 64 ? nt : 64;
+  for (int i = tid % ws; i < n; i += ws) {
+    dd[i] = d[i];
+    ee[i] = e[i];
+  }
+  __syncthreads();
+#ifndef TN3D_EIG_RPT
+#define TN3D_EIG_RPT 4
+#endif
+  constexpr int RPT = TN3D_EIG_RPT;
+  int fail = 0;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double sm = fabs(dd[m]) + fabs(dd[m + 1]);
+        if (fabs(ee[m]) <= 1e-16 * sm || ee[m] == 0.0) break;
+      }
+      if (m == l) break;
+      if (iter >= 60) {
+        fail = 1;
+        break;
+      }
+      double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+      double r = hypot(g, 1.0);
+      g = dd[m] - dd[l] + ee[l] / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      double zc[RPT];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int kr = tid + j * nt;
+        zc[j] = kr < n ? Z[kr * n + m] : 0.0;
+      }
+      bool early = false;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double zi[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int kr = tid + j * nt;
+          zi[j] = kr < n ? Z[kr * n + i] : 0.0;
+        }
+        const double f = sn * ee[i], b = cs * ee[i];
+        r = hypot(f, g);
+        ee[i + 1] = r;
+        if (r == 0.0) {
+          dd[i + 1] -= p;
+          ee[m] = 0.0;
+          early = true;
+          break;
+        }
+        sn = f / r;
+        cs = g / r;
+        g = dd[i + 1] - p;
+        r = (dd[i] - g) * sn + 2.0 * cs * b;
+        p = sn * r;
+        dd[i + 1] = g + p;
+        g = cs * r - b;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int kr = tid + j * nt;
+          if (kr < n) Z[kr * n + i + 1] = sn * zi[j] + cs * zc[j];
+          zc[j] = cs * zi[j] - sn * zc[j];
+        }
+      }
+      // write back the carried column (i + 1 after an early exit, l otherwise)
+      const int col = early ? i + 1 : l;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int kr = tid + j * nt;
+        if (kr < n) Z[kr * n + col] = zc[j];
+      }
+      if (early) continue;
+      dd[l] -= p;
+      ee[l] = g;
+      ee[m] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) d[i] = dw[i];
   __syncthreads();
   return fail;
 }

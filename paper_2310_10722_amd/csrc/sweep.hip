@@ -455,6 +455,7 @@ __device__ __forceinline__ int zbd(const ZipArgs& Z, int s, int b) {
 
 constexpr int ZNT = 512;  // threads of the contraction / output kernels of a boundary-MPS step
 constexpr int ZBT = 64;   // threads of the decomposition kernel (one wavefront)
+constexpr int ZBIG = 64;  // FP32 mode: larger Gram blocks go to the 512-thread kernel
 
 // One zip-up step of the boundary MPS (row y, column x) for one sweep, in
 // three kernels:
@@ -557,6 +558,7 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   double* Sout = Z.zS + int64_t(s) * 1024;
   int nsw = 0;
   const double* Zv = nullptr;  // eigen / singular vectors of the family, columns
+  if (Z.gram_path && nv > ZBIG) return;  // k_zip_bbig takes it
   if (Z.gram_path) {
     // symmetric eigenproblem of the PSD Gram: eigenvalues S^2, eigenvectors Fv
     double* G = Z.Gm + int64_t(s) * Z.bigcap;
@@ -564,10 +566,18 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
     double* A = fits ? zsm : G;
     double* Zm = fits ? zsm + nv * nv : Jm;
     double* dv = fits ? zsm + 2 * nv * nv : zsm;
-    if (fits)
-      for (int e = tid; e < nv * nv; e += ZBT) A[e] = G[e];
+    // normalise to the largest diagonal entry (eigenvalues rescaled below)
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int i = 0; i < nv; ++i) mx = fmax(mx, G[i * nv + i]);
+      red[4] = mx > 0.0 ? mx : 1.0;
+    }
+    __syncthreads();
+    const double gsc = red[4], igs = 1.0 / gsc;
+    for (int e = tid; e < nv * nv; e += ZBT) A[e] = G[e] * igs;
     __syncthreads();
     const int fail = wave_sym_eig(A, nv, Zm, dv, dv + nv, dv + 2 * nv, red);
+    for (int v = tid; v < nv; v += ZBT) dv[v] *= gsc;
     for (int v = tid; v < nv; v += ZBT) {
       const double lv = dv[v];
       int rk = 0;
@@ -618,6 +628,57 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
     zd[8] = Dn;
     atomicMax(&Z.sweeps_max[1], nsw);
     uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (nsw >= 40 ? 8u : 0u);
+    if (f) atomicOr(&Z.flags[s], f);
+  }
+}
+
+// Decomposition of the Gram blocks larger than ZBIG (FP32 mode) with the
+// whole 512-thread workgroup; matrix and eigenvectors in LDS when they fit.
+__global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int lds_doubles) {
+  extern __shared__ double zsm[];
+  __shared__ int ord[1024];
+  __shared__ double red[16];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* zd = Z.zdim + int64_t(s) * 12;
+  const int nv = zd[7];
+  if (nv <= ZBIG) return;
+  double* G = Z.Gm + int64_t(s) * Z.bigcap;
+  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
+  double* Sout = Z.zS + int64_t(s) * 1024;
+  const int nw = ZNT / 64;
+  const int small = 3 * nv + 2 * nw * nv;  // d, e, beta, per-wavefront (d, e)
+  const bool fits = 2 * int64_t(nv) * nv + small <= lds_doubles;
+  double* dv = zsm;
+  double* dw = zsm + 3 * nv;
+  double* A = fits ? zsm + small : G;
+  double* Zm = fits ? zsm + small + nv * nv : Jm;
+  if (fits)
+    for (int e = tid; e < nv * nv; e += ZNT) A[e] = G[e];
+  __syncthreads();
+  const int fail = block_sym_eig(A, nv, Zm, dv, dv + nv, dv + 2 * nv, dw, red);
+  for (int v = tid; v < nv; v += ZNT) {
+    const double lv = dv[v];
+    int rk = 0;
+    for (int u = 0; u < nv; ++u)
+      if (dv[u] > lv || (dv[u] == lv && u < v)) ++rk;
+    ord[rk] = v;
+  }
+  __syncthreads();
+  for (int m = tid; m < nv; m += ZNT) Sout[m] = sqrt(fmax(dv[ord[m]], 0.0));
+  __syncthreads();
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
+  bool bad = false;
+  if (Dn < 1) {
+    Dn = 1;
+    bad = true;
+  }
+  for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = Zm[(e / Dn) * nv + ord[e % Dn]];
+  if (tid == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], fail ? 40 : 1);
+    uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (fail ? 8u : 0u);
     if (f) atomicOr(&Z.flags[s], f);
   }
 }
@@ -862,7 +923,7 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
-  const int lds = Z.gram_path ? 8384 : 18432;  // doubles; FP32 mode keeps two workgroups per CU
+  const int lds = Z.gram_path ? 256 : 18432;  // doubles; FP32 mode: Gram and vectors stay in L2, many workgroups per CU
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -870,7 +931,18 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
     attr = true;
   }
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
-  if (x + 1 < Z.Lx) hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(lds) * 8, st, Z, x, y, lds);
+  if (x + 1 < Z.Lx) {
+    hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(lds) * 8, st, Z, x, y, lds);
+    if (Z.gram_path) {
+      static bool attr2 = false;
+      if (!attr2) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 19200 * 8);
+        attr2 = true;
+      }
+      hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
+    }
+  }
   hipLaunchKernelGGL(k_zip_c, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
 }
 
