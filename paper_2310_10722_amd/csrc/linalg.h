@@ -386,138 +386,157 @@ __device__ void block_cgs2(double* X, int n, int b, double* dots, double* red) {
   }
 }
 
-// Eigen-decomposition of the symmetric n x n matrix A (row-major, leading
-// dimension n, destroyed) by Householder reduction to tridiagonal form and
-// the implicit QL algorithm with Wilkinson-type shifts (the published
-// tridiagonal QL method of Bowdler, Martin, Reinsch and Wilkinson, 1968).  On return Z (n x n, row-major)
-// holds the eigenvectors in its columns and d the eigenvalues (unsorted).
-// A should be scaled to O(1) entries (plane rotations use sqrt(f^2 + g^2)).
-// Written for a workgroup of exactly one wavefront: the scalar recurrences of
-// the QL sweeps run redundantly in every lane, each lane owning rows of Z.
-// e, beta: n doubles scratch each.  Returns 0, or 1 if an eigenvalue took more
-// than 60 QL iterations.
-__device__ int wave_sym_eig(double* A, int n, double* Z, double* d, double* e, double* beta, double* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  // --- tridiagonalisation: A = Q T Q^T, Q = H_0 ... H_{n-3}
+// Value of v in lane src (uniform) of the wavefront, in every lane.
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lowest lane whose pred is true (64 if none).
+__device__ __forceinline__ int wave_first(bool pred) {
+  const unsigned long long m = __ballot(pred);
+  return m ? __builtin_ctzll(m) : 64;
+}
+
+// Eigen-decomposition of a symmetric n x n matrix, n <= 64, by Householder
+// reduction to tridiagonal form and the implicit QL algorithm with
+// Wilkinson-type shifts (the tridiagonal QL method of Bowdler, Martin, Reinsch
+// and Wilkinson, 1968), for a workgroup of exactly one wavefront.
+//   A  n x n row-major, symmetric, scaled to O(1) entries (destroyed; row k
+//      ends up holding the k-th Householder vector).
+//   Zt n x n: eigenvector j is stored contiguously at Zt[j n .. j n + n).
+//   d  n eigenvalues, unsorted.
+// Lane i owns index i: it only reads and writes column i of A and component i
+// of every vector in Zt, so every access of the wavefront is one contiguous
+// row and no barrier is needed.  The tridiagonal matrix (d_i, e_i) and the
+// Householder scalars live in lane i's registers; the scalar QL recurrence
+// runs redundantly in all lanes on values broadcast with readlane.  Returns 0,
+// or 1 if an eigenvalue took more than 60 QL iterations.
+__device__ int wave_sym_eig(double* A, int n, double* Zt, double* d) {
+  const int i = threadIdx.x;
+  const bool own = i < n;
+  const int ic = own ? i : n - 1;  // clamped column for loads of lanes >= n
+  double dr = 0.0, er = 0.0, br = 0.0;
+  // --- Householder tridiagonalisation, A = Q T Q^T with Q = H_0 ... H_{n-3}
   for (int k = 0; k + 2 < n; ++k) {
-    double q = 0.0;
-    for (int i = k + 1 + tid; i < n; i += nt) q += A[i * n + k] * A[i * n + k];
-    q = team_sum(q, 64);
-    if (tid == 0) red[0] = q;
-    __syncthreads();
-    const double sigma = red[0];
-    const double x0 = A[(k + 1) * n + k];
-    __syncthreads();
+    const bool act = own && i > k;
+    double v = act ? A[k * n + i] : 0.0;  // row k = column k (symmetry)
+    const double sigma = team_sum(v * v, 64);
+    const double x0 = wave_bcast(v, k + 1);
     if (!(sigma > 0.0) || sigma - x0 * x0 <= 1e-300) {
-      if (tid == 0) {
-        e[k] = x0;
-        beta[k] = 0.0;
+      if (i == k) {
+        er = x0;
+        br = 0.0;
       }
-      __syncthreads();
       continue;
     }
     const double alpha = x0 >= 0.0 ? -sqrt(sigma) : sqrt(sigma);
-    const double bk = 1.0 / (sigma - x0 * alpha);  // 2 / (v.v) with v0 = x0 - alpha
-    // v in column k below the diagonal
-    if (tid == 0) {
-      A[(k + 1) * n + k] = x0 - alpha;
-      e[k] = alpha;
-      beta[k] = bk;
+    const double bk = 1.0 / (sigma - x0 * alpha);  // 2 / (v.v) with v_{k+1} = x0 - alpha
+    if (i == k + 1) v = x0 - alpha;
+    if (i == k) {
+      er = alpha;
+      br = bk;
     }
-    __syncthreads();
-    // p = beta A' v  (p kept in Z's row k as scratch), then K = beta/2 p.v
-    double pv = 0.0;
-    for (int i = k + 1 + tid; i < n; i += nt) {
-      double acc = 0.0;
-      for (int j = k + 1; j < n; ++j) acc += A[i * n + j] * A[j * n + k];
-      acc *= bk;
-      Z[k * n + i] = acc;
-      pv += acc * A[i * n + k];
+    if (act) A[k * n + i] = v;
+    // p = bk A' v, K = bk/2 p.v, w = p - K v; A' <- A' - v w^T - w v^T
+    double pi = 0.0;
+    for (int j = k + 1; j < n; ++j) pi += A[j * n + ic] * wave_bcast(v, j);
+    pi *= bk;
+    const double K = 0.5 * bk * team_sum(pi * v, 64);
+    const double w = pi - K * v;
+    for (int j = k + 1; j < n; ++j) {
+      const double vj = wave_bcast(v, j), wj = wave_bcast(w, j);
+      if (act) A[j * n + i] -= v * wj + w * vj;
     }
-    pv = team_sum(pv, 64);
-    if (tid == 0) red[1] = 0.5 * bk * pv;
-    __syncthreads();
-    const double K = red[1];
-    for (int i = k + 1 + tid; i < n; i += nt) Z[k * n + i] -= K * A[i * n + k];  // w
-    __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += nt) {
-      const double vi = A[i * n + k], wi = Z[k * n + i];
-      for (int j = k + 1; j < n; ++j) A[i * n + j] -= vi * Z[k * n + j] + wi * A[j * n + k];
-    }
-    __syncthreads();
   }
-  for (int i = tid; i < n; i += nt) d[i] = A[i * n + i];
-  if (tid == 0) {
-    if (n >= 2) e[n - 2] = A[(n - 1) * n + n - 2];
-    e[n - 1] = 0.0;
-    if (n >= 2) beta[n - 2] = 0.0;
-    beta[n - 1] = 0.0;
+  if (own) dr = A[i * n + i];
+  if (i == n - 2) {
+    er = A[(n - 1) * n + i];
+    br = 0.0;
   }
-  __syncthreads();
-  // --- accumulate Q: Z = I, then Z <- H_k Z for k = n-3 .. 0
-  for (int x = tid; x < n * n; x += nt) Z[x] = (x / n == x % n) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const double bk = beta[k];
+  if (i == n - 1) {
+    er = 0.0;
+    br = 0.0;
+  }
+  // --- Q = H_0 H_1 ... H_{n-3}, accumulated from the right into Zt
+  if (own)
+    for (int c = 0; c < n; ++c) Zt[c * n + i] = c == i ? 1.0 : 0.0;
+  for (int k = 0; k + 2 < n; ++k) {
+    const double bk = wave_bcast(br, k);
     if (bk == 0.0) continue;
-    for (int j = k + 1 + tid; j < n; j += nt) {
-      double u = 0.0;
-      for (int i = k + 1; i < n; ++i) u += A[i * n + k] * Z[i * n + j];
-      u *= bk;
-      for (int i = k + 1; i < n; ++i) Z[i * n + j] -= u * A[i * n + k];
+    const double v = (own && i > k) ? A[k * n + i] : 0.0;
+    double y = 0.0;
+    for (int c = k + 1; c < n; ++c) y += Zt[c * n + ic] * wave_bcast(v, c);
+    y *= bk;
+    for (int c = k + 1; c < n; ++c) {
+      const double vc = wave_bcast(v, c);
+      if (own) Zt[c * n + i] -= y * vc;
     }
-    __syncthreads();
   }
-  // --- implicit QL with shifts on (d, e), rotations accumulated into Z
+  // --- implicit QL on (d, e); plane rotations applied to the vectors of Zt,
+  // the moving vector carried in a register
   int fail = 0;
   for (int l = 0; l < n; ++l) {
     for (int iter = 0;; ++iter) {
-      int m = l;
-      for (; m + 1 < n; ++m) {
-        const double dd = fabs(d[m]) + fabs(d[m + 1]);
-        if (fabs(e[m]) <= 1e-16 * dd || e[m] == 0.0) break;
-      }
+      // smallest m >= l with e_m negligible (m = n - 1 always qualifies)
+      const double dn = __shfl_down(dr, 1, 64);
+      const bool neg = i + 1 >= n || er == 0.0 || fabs(er) <= 1e-16 * (fabs(dr) + fabs(dn));
+      const int m = wave_first(neg && i >= l);
       if (m == l) break;
       if (iter >= 60) {
         fail = 1;
         break;
       }
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      const double dl = wave_bcast(dr, l), el = wave_bcast(er, l);
+      double g = (wave_bcast(dr, l + 1) - dl) / (2.0 * el);
       double r = sqrt(g * g + 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      g = wave_bcast(dr, m) - dl + el / (g + (g >= 0.0 ? r : -r));
       double sn = 1.0, cs = 1.0, p = 0.0;
+      double zc = Zt[m * n + ic];
+      double znext = Zt[(m - 1) * n + ic];
       bool early = false;
-      for (int i = m - 1; i >= l; --i) {
-        const double f = sn * e[i], b = cs * e[i];
-        r = sqrt(f * f + g * g);  // |f|, |g| stay O(1) for a normalised matrix
-        e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] -= p;
-          e[m] = 0.0;
+      int j = m - 1;
+      for (; j >= l; --j) {
+        // vector j was loaded one step ahead; vector j - 1 is not written
+        // before it is used at the next step
+        const double zj = znext;
+        znext = Zt[(j > l ? j - 1 : l) * n + ic];
+        const double ej = wave_bcast(er, j);
+        const double f = sn * ej, b = cs * ej;
+        const double t = f * f + g * g;  // |f|, |g| stay O(1) for a normalised matrix
+        if (t == 0.0) {
+          if (i == j + 1) {
+            er = 0.0;
+            dr -= p;
+          }
+          if (i == m) er = 0.0;
           early = true;
           break;
         }
-        const double ir = 1.0 / r;
+        const double ir = rsqrt(t);
+        if (i == j + 1) er = t * ir;
         sn = f * ir;
         cs = g * ir;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * sn + 2.0 * cs * b;
+        g = wave_bcast(dr, j + 1) - p;
+        r = (wave_bcast(dr, j) - g) * sn + 2.0 * cs * b;
         p = sn * r;
-        d[i + 1] = g + p;
+        if (i == j + 1) dr = g + p;
         g = cs * r - b;
-        for (int kr = tid; kr < n; kr += nt) {
-          const double zt = Z[kr * n + i + 1], zi = Z[kr * n + i];
-          Z[kr * n + i + 1] = sn * zi + cs * zt;
-          Z[kr * n + i] = cs * zi - sn * zt;
-        }
+        if (own) Zt[(j + 1) * n + i] = sn * zj + cs * zc;
+        zc = cs * zj - sn * zc;
       }
+      if (own) Zt[(early ? j + 1 : l) * n + i] = zc;
       if (early) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[m] = 0.0;
+      if (i == l) {
+        dr -= p;
+        er = g;
+      }
+      if (i == m) er = 0.0;
     }
   }
-  __syncthreads();
+  if (own) d[i] = dr;
   return fail;
 }
 

@@ -541,6 +541,29 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y) {
   }
 }
 
+// Rank rule on the sorted singular values Sout of the smaller family, then the
+// kept vectors into Fv (nv x Dn, row-major): component r of the vector with
+// the c-th largest value is Zv[ord[c] * cs + r * rs].  Records Dn and the flags.
+__device__ void zip_keep(const ZipArgs& Z, int s, int* zd, int nv, const double* Sout, const int* ord,
+                         const double* Zv, int cs, int rs, int nsw) {
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
+  bool bad = false;
+  if (Dn < 1) {
+    Dn = 1;
+    bad = true;
+  }
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
+  for (int e = threadIdx.x; e < nv * Dn; e += blockDim.x) Fv[e] = Zv[ord[e % Dn] * cs + (e / Dn) * rs];
+  if (threadIdx.x == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], nsw);
+    uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (nsw >= 40 ? 8u : 0u);
+    if (f) atomicOr(&Z.flags[s], f);
+  }
+}
+
+// FP64 mode: one-sided Jacobi SVD of the smaller family of Theta.
 __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_doubles) {
   extern __shared__ double zsm[];
   __shared__ double S[1024];
@@ -554,82 +577,67 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   const int nv = zd[7], len = rows ? C : R;
   double* Th = Z.Th + int64_t(s) * Z.bigcap;
   double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
-  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   double* Sout = Z.zS + int64_t(s) * 1024;
-  int nsw = 0;
-  const double* Zv = nullptr;  // eigen / singular vectors of the family, columns
-  if (Z.gram_path && nv > ZBIG) return;  // k_zip_bbig takes it
-  if (Z.gram_path) {
-    // symmetric eigenproblem of the PSD Gram: eigenvalues S^2, eigenvectors Fv
-    double* G = Z.Gm + int64_t(s) * Z.bigcap;
-    const bool fits = 2 * int64_t(nv) * nv + 3 * nv <= lds_doubles;
-    double* A = fits ? zsm : G;
-    double* Zm = fits ? zsm + nv * nv : Jm;
-    double* dv = fits ? zsm + 2 * nv * nv : zsm;
-    // normalise to the largest diagonal entry (eigenvalues rescaled below)
-    if (tid == 0) {
-      double mx = 0.0;
-      for (int i = 0; i < nv; ++i) mx = fmax(mx, G[i * nv + i]);
-      red[4] = mx > 0.0 ? mx : 1.0;
+  double* A;
+  double* J;
+  long vs, es;
+  const bool fits = int64_t(nv) * len + int64_t(nv) * nv <= lds_doubles;
+  if (fits) {
+    A = zsm;
+    J = zsm + nv * len;
+    for (int e = tid; e < nv * len; e += ZBT) {
+      const int v = e / len, k = e % len;
+      A[e] = rows ? Th[v * C + k] : Th[k * C + v];
     }
-    __syncthreads();
-    const double gsc = red[4], igs = 1.0 / gsc;
-    for (int e = tid; e < nv * nv; e += ZBT) A[e] = G[e] * igs;
-    __syncthreads();
-    const int fail = wave_sym_eig(A, nv, Zm, dv, dv + nv, dv + 2 * nv, red);
-    for (int v = tid; v < nv; v += ZBT) dv[v] *= gsc;
-    for (int v = tid; v < nv; v += ZBT) {
-      const double lv = dv[v];
-      int rk = 0;
-      for (int u = 0; u < nv; ++u)
-        if (dv[u] > lv || (dv[u] == lv && u < v)) ++rk;
-      ord[rk] = v;
-    }
-    __syncthreads();
-    for (int m = tid; m < nv; m += ZBT) Sout[m] = sqrt(fmax(dv[ord[m]], 0.0));
-    nsw = fail ? 40 : 1;
-    Zv = Zm;
+    vs = len;
+    es = 1;
   } else {
-    double* A;
-    double* J;
-    long vs, es;
-    const bool fits = int64_t(nv) * len + int64_t(nv) * nv <= lds_doubles;
-    if (fits) {
-      A = zsm;
-      J = zsm + nv * len;
-      for (int e = tid; e < nv * len; e += ZBT) {
-        const int v = e / len, k = e % len;
-        A[e] = rows ? Th[v * C + k] : Th[k * C + v];
-      }
-      vs = len;
-      es = 1;
-    } else {
-      A = Th;
-      J = Jm;
-      vs = rows ? C : 1;
-      es = rows ? 1 : C;
-    }
-    __syncthreads();
-    nsw = block_jacobi(A, vs, es, nv, len, J, Z.jtol, Z.jfloor, 40, flag, red);
-    block_norms_sorted(A, vs, es, nv, len, S, ord);
-    for (int m = tid; m < nv; m += ZBT) Sout[m] = S[ord[m]];
-    Zv = J;
+    A = Th;
+    J = Jm;
+    vs = rows ? C : 1;
+    es = rows ? 1 : C;
   }
   __syncthreads();
-  int split = 0;
-  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
-  bool bad = false;
-  if (Dn < 1) {
-    Dn = 1;
-    bad = true;
+  const int nsw = block_jacobi(A, vs, es, nv, len, J, Z.jtol, Z.jfloor, 40, flag, red);
+  block_norms_sorted(A, vs, es, nv, len, S, ord);
+  for (int m = tid; m < nv; m += ZBT) Sout[m] = S[ord[m]];
+  __syncthreads();
+  zip_keep(Z, s, zd, nv, Sout, ord, J, 1, nv, nsw);
+}
+
+// FP32 mode, families of at most ZBIG vectors: symmetric eigenproblem of the
+// PSD Gram (eigenvalues S^2) in one wavefront, eigenvectors contiguous in LDS.
+// The Gram is normalised in place to its largest diagonal entry; lane i scales
+// column i, the only column of G it touches in the solver.
+__global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
+  extern __shared__ double zsm[];  // ZBIG * ZBIG
+  __shared__ double S[ZBIG];
+  __shared__ int ord[ZBIG];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* zd = Z.zdim + int64_t(s) * 12;
+  const int nv = zd[7];
+  if (nv > ZBIG) return;  // k_zip_bbig takes it
+  double* G = Z.Gm + int64_t(s) * Z.bigcap;
+  double* Sout = Z.zS + int64_t(s) * 1024;
+  double gd = tid < nv ? G[tid * nv + tid] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) gd = fmax(gd, __shfl_xor(gd, o, 64));
+  const double gsc = gd > 0.0 ? gd : 1.0, igs = 1.0 / gsc;
+  if (tid < nv)
+    for (int j = 0; j < nv; ++j) G[j * nv + tid] *= igs;
+  const int fail = wave_sym_eig(G, nv, zsm, S);
+  if (tid < nv) S[tid] *= gsc;
+  __syncthreads();
+  if (tid < nv) {
+    const double lv = S[tid];
+    int rk = 0;
+    for (int u = 0; u < nv; ++u)
+      if (S[u] > lv || (S[u] == lv && u < tid)) ++rk;
+    ord[rk] = tid;
   }
-  for (int e = tid; e < nv * Dn; e += ZBT) Fv[e] = Zv[(e / Dn) * nv + ord[e % Dn]];
-  if (tid == 0) {
-    zd[8] = Dn;
-    atomicMax(&Z.sweeps_max[1], nsw);
-    uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (nsw >= 40 ? 8u : 0u);
-    if (f) atomicOr(&Z.flags[s], f);
-  }
+  __syncthreads();
+  if (tid < nv) Sout[tid] = sqrt(fmax(S[ord[tid]], 0.0));
+  __syncthreads();
+  zip_keep(Z, s, zd, nv, Sout, ord, zsm, nv, 1, fail ? 40 : 1);
 }
 
 // Decomposition of the Gram blocks larger than ZBIG (FP32 mode) with the
@@ -644,7 +652,6 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
   if (nv <= ZBIG) return;
   double* G = Z.Gm + int64_t(s) * Z.bigcap;
   double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
-  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
   double* Sout = Z.zS + int64_t(s) * 1024;
   const int nw = ZNT / 64;
   const int small = 3 * nv + 2 * nw * nv;  // d, e, beta, per-wavefront (d, e)
@@ -667,20 +674,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
   __syncthreads();
   for (int m = tid; m < nv; m += ZNT) Sout[m] = sqrt(fmax(dv[ord[m]], 0.0));
   __syncthreads();
-  int split = 0;
-  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
-  bool bad = false;
-  if (Dn < 1) {
-    Dn = 1;
-    bad = true;
-  }
-  for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = Zm[(e / Dn) * nv + ord[e % Dn]];
-  if (tid == 0) {
-    zd[8] = Dn;
-    atomicMax(&Z.sweeps_max[1], fail ? 40 : 1);
-    uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (fail ? 8u : 0u);
-    if (f) atomicOr(&Z.flags[s], f);
-  }
+  zip_keep(Z, s, zd, nv, Sout, ord, Zm, 1, nv, fail ? 40 : 1);
 }
 
 __global__ __launch_bounds__(ZNT) void k_zip_c(ZipArgs Z, int x, int y) {
@@ -923,24 +917,21 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
-  const int lds = Z.gram_path ? 256 : 18432;  // doubles; FP32 mode: Gram and vectors stay in L2, many workgroups per CU
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
                               18432 * 8);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              19200 * 8);
     attr = true;
   }
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
-    hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(lds) * 8, st, Z, x, y, lds);
     if (Z.gram_path) {
-      static bool attr2 = false;
-      if (!attr2) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 19200 * 8);
-        attr2 = true;
-      }
+      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(ZBIG) * ZBIG * 8, st, Z, x, y);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
+    } else {
+      hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
     }
   }
   hipLaunchKernelGGL(k_zip_c, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
