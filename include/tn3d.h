@@ -9,7 +9,7 @@
  *     p_{m,L} = sum_{x : Hx = m, l.x = L} prod_i p_i^{x_i} (1 - p_i)^{1 - x_i}
  * and the optimal decision is argmax_L p_{m,L}.  The library evaluates
  * log p_{m,L} with the paper's method (Sec. 4): the detector-picture network
- * (Sec. 3.1, 3.3, 3.5) is arranged as a stack of layers, a 2D network absorbs
+ * (Sec. 3.1, 3.3, 3.4) is arranged as a stack of layers, a 2D network absorbs
  * one layer at a time as two-site gates, every gated bond is truncated back to
  * at most chi with simple-update environments, and the remaining 2D network is
  * contracted with a boundary MPS of bond chi_m.  The value is exact when chi

@@ -11,7 +11,7 @@ Tiers (each module's header says what pins it):
               O-2 exact frontier contraction (variable elimination) of the same
               sum, in FP64 with a log-scale accumulator.
   network.py  the layered networks of the configurations, written from the
-              paper's detector picture (Sec. 3.1, 3.3-3.5, 5.1).
+              paper's detector picture (Sec. 3.1, 3.3, 3.4, 5.1).
   sweep.py    O-3 the fixed-chi boundary sweep with simple-update truncation
               (Sec. 4) followed by the boundary-MPS contraction of the final 2D
               network, with LAPACK QR/SVD.

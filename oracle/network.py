@@ -1,6 +1,6 @@
 """Layered 3D tensor networks whose contraction is p_{m,L}, built per syndrome.
 
-These are the detector-picture networks of the paper (Sec. 3.1, 3.3, 3.5) for
+These are the detector-picture networks of the paper (Sec. 3.1, 3.3, 3.4) for
 independent flips on CSS codes, arranged as stacks of identical layers over a
 2D grid (Sec. 4: layered networks; Sec. 5.1: bond tensors on horizontal bonds
 go into two-site gates, those on vertical bonds are contracted exactly between

@@ -1,5 +1,5 @@
 // Layered op programs for the detector-picture networks of the paper
-// (Sec. 3.1, 3.3, 3.5, 5.1) arranged for a boundary sweep (Sec. 4).
+// (Sec. 3.1, 3.3, 3.4, 5.1) arranged for a boundary sweep (Sec. 4).
 //
 // Every physical leg carries flip parities, so a flip mechanism shared by two
 // sites is the gate (1-p) I (x) I + p X (x) X (operator-Schmidt rank 2), a

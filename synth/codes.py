@@ -5,7 +5,7 @@ over F2 (detectors x mechanisms), a probability p_i per independent error
 mechanism, and logical indicator rows l (observables x mechanisms).  For a CSS
 code under independent flips of one Pauli type the decoding problem is a DEM
 whose mechanisms are the qubits and whose detectors are the checks of the other
-type (paper, Sec. 3.3 and Sec. 3.5).
+type (paper, Sec. 3.3 and Sec. 3.4).
 
 Every builder documents its canonical numbering of detectors and mechanisms;
 the C-ABI family builders use the same numbering, so a syndrome vector produced
