@@ -400,29 +400,44 @@ __device__ __forceinline__ int wave_first(bool pred) {
   return m ? __builtin_ctzll(m) : 64;
 }
 
-// Eigen-decomposition of a symmetric n x n matrix, n <= 64, by Householder
-// reduction to tridiagonal form and the implicit QL algorithm with
-// Wilkinson-type shifts (the tridiagonal QL method of Bowdler, Martin, Reinsch
-// and Wilkinson, 1968), for a workgroup of exactly one wavefront.
-//   A  n x n row-major, symmetric, scaled to O(1) entries (destroyed; row k
-//      ends up holding the k-th Householder vector).
-//   Zt n x n: eigenvector j is stored contiguously at Zt[j n .. j n + n).
-//   d  n eigenvalues, unsorted.
-// Lane i owns index i: it only reads and writes column i of A and component i
-// of every vector in Zt, so every access of the wavefront is one contiguous
-// row and no barrier is needed.  The tridiagonal matrix (d_i, e_i) and the
-// Householder scalars live in lane i's registers; the scalar QL recurrence
-// runs redundantly in all lanes on values broadcast with readlane.  Returns 0,
-// or 1 if an eigenvalue took more than 60 QL iterations.
-__device__ int wave_sym_eig(double* A, int n, double* Zt, double* d) {
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Leading eigenpairs of a symmetric matrix of order n <= 64 in one wavefront
+// (64 threads): Householder reduction to a tridiagonal T = Q^T A Q, the K
+// largest eigenvalues of T by multisection on Sturm sequence counts, their
+// eigenvectors by inverse iteration, and the back-transformation by Q.  Only
+// the leading pairs are computed, so every lane works on its own eigenvalue or
+// vector instead of all lanes repeating one scalar recurrence.
+// ---------------------------------------------------------------------------
+
+// Steps k in [kb, ke) of the Householder reduction with the matrix in
+// registers: lane i holds column i in a[0..63].  J0 <= kb, so rows below J0
+// are finished and every index into a[] is a compile-time constant; row k of
+// the current matrix is picked out of the 16 rows [J0, J0 + 16).  v and w of a
+// step are broadcast through vw (2 * 64 doubles of LDS).  The Householder
+// vector of step k is kept in row k of Hv (stride n); lane i writes only
+// column i, the column it read from the input.
+template <int J0>
+__device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke, double* vw, double* Hv,
+                                          double& er, double& br) {
   const int i = threadIdx.x;
   const bool own = i < n;
-  const int ic = own ? i : n - 1;  // clamped column for loads of lanes >= n
-  double dr = 0.0, er = 0.0, br = 0.0;
-  // --- Householder tridiagonalisation, A = Q T Q^T with Q = H_0 ... H_{n-3}
-  for (int k = 0; k + 2 < n; ++k) {
+  for (int k = kb; k < ke; ++k) {
+    double ak = 0.0;
+#pragma unroll
+    for (int j = J0; j < J0 + 16; ++j)
+      if (j == k) ak = a[j];
     const bool act = own && i > k;
-    double v = act ? A[k * n + i] : 0.0;  // row k = column k (symmetry)
+    double v = act ? ak : 0.0;
     const double sigma = team_sum(v * v, 64);
     const double x0 = wave_bcast(v, k + 1);
     if (!(sigma > 0.0) || sigma - x0 * x0 <= 1e-300) {
@@ -439,105 +454,273 @@ __device__ int wave_sym_eig(double* A, int n, double* Zt, double* d) {
       er = alpha;
       br = bk;
     }
-    if (act) A[k * n + i] = v;
-    // p = bk A' v, K = bk/2 p.v, w = p - K v; A' <- A' - v w^T - w v^T
-    double pi = 0.0;
-    for (int j = k + 1; j < n; ++j) pi += A[j * n + ic] * wave_bcast(v, j);
-    pi *= bk;
-    const double K = 0.5 * bk * team_sum(pi * v, 64);
-    const double w = pi - K * v;
-    for (int j = k + 1; j < n; ++j) {
-      const double vj = wave_bcast(v, j), wj = wave_bcast(w, j);
-      if (act) A[j * n + i] -= v * wj + w * vj;
-    }
+    if (own) Hv[k * n + i] = v;
+    vw[2 * i] = v;
+    __syncthreads();
+    // p = bk A v, K = bk/2 p.v, w = p - K v; A <- A - v w^T - w v^T
+    double p = 0.0;
+#pragma unroll
+    for (int j = J0; j < 64; ++j) p += a[j] * vw[2 * j];
+    p *= bk;
+    const double K = 0.5 * bk * team_sum(p * v, 64);
+    const double w = act ? p - K * v : 0.0;
+    vw[2 * i + 1] = w;
+    __syncthreads();
+#pragma unroll
+    for (int j = J0; j < 64; ++j) a[j] -= v * vw[2 * j + 1] + w * vw[2 * j];
+    __syncthreads();
   }
-  if (own) dr = A[i * n + i];
+}
+
+// Householder reduction of the symmetric n x n matrix G (row-major) times gs.
+// Lane i returns d_i = T[i][i], e_i = T[i][i+1] (0 for i >= n - 1) and the
+// scalar beta_i of reflector i (0 when step i needed no reflection); Hv
+// receives the reflectors (row k, stride n, components k+1 .. n-1) and may
+// alias G.
+__device__ void wave_tridiag(const double* G, double gs, int n, double* vw, double* Hv, double& dr, double& er,
+                             double& br) {
+  const int i = threadIdx.x;
+  double a[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) a[j] = (j < n && i < n) ? G[j * n + i] * gs : 0.0;
+  er = 0.0;
+  br = 0.0;
+  const int ke = n - 2;
+  tri_block<0>(a, n, 0, ke < 16 ? ke : 16, vw, Hv, er, br);
+  tri_block<16>(a, n, 16, ke < 32 ? ke : 32, vw, Hv, er, br);
+  tri_block<32>(a, n, 32, ke < 48 ? ke : 48, vw, Hv, er, br);
+  tri_block<48>(a, n, 48, ke, vw, Hv, er, br);
+  double di = 0.0, en = 0.0;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    if (j == i) di = a[j];
+    if (j == n - 1) en = a[j];
+  }
+  dr = i < n ? di : 0.0;
   if (i == n - 2) {
-    er = A[(n - 1) * n + i];
+    er = en;
     br = 0.0;
   }
-  if (i == n - 1) {
+  if (i >= n - 1) {
     er = 0.0;
     br = 0.0;
   }
-  // --- Q = H_0 H_1 ... H_{n-3}, accumulated from the right into Zt
-  if (own)
-    for (int c = 0; c < n; ++c) Zt[c * n + i] = c == i ? 1.0 : 0.0;
-  for (int k = 0; k + 2 < n; ++k) {
+}
+
+// Number of eigenvalues of T below x: negative pivots of T - x I (Sturm
+// sequence), tri[2i] = d_i, tri[2i+1] = e_{i-1}^2 (e_{-1} = 0).  Pivots
+// smaller than pivmin in magnitude are replaced by -pivmin.
+__device__ __forceinline__ int sturm_count(const double* tri, int n, double x, double pivmin) {
+  int c = 0;
+  double q = 1.0;
+  for (int r = 0; r < n; ++r) {
+    q = (tri[2 * r] - x) - tri[2 * r + 1] / q;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    c += q < 0.0 ? 1 : 0;
+  }
+  return c;
+}
+
+// The K (<= n) largest eigenvalues of T (lane i holds d_i, e_i) into lam[0..K)
+// in decreasing order, by multisection of the Gershgorin interval: g = 64 / K
+// lanes (at most 3) share an eigenvalue and each evaluates one interior point
+// per round, until the bracket is within a few ulps of the eigenvalue or of
+// the norm of T.  tri: 2 * 64 doubles, xs: 64 doubles, cs: 64 ints (LDS).
+// Returns the norm bound max |Gershgorin end|.
+__device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri, double* xs, int* cs, double* lam) {
+  const int i = threadIdx.x;
+  const bool own = i < n;
+  const double eu = __shfl_up(er, 1, 64);
+  const double el = (own && i > 0) ? eu : 0.0;
+  const double ei = (own && i + 1 < n) ? er : 0.0;
+  if (own) {
+    tri[2 * i] = dr;
+    tri[2 * i + 1] = el * el;
+  }
+  double lo = wave_min(own ? dr - fabs(el) - fabs(ei) : 1e300);
+  double hi = wave_max(own ? dr + fabs(el) + fabs(ei) : -1e300);
+  const double nrm = fmax(fabs(lo), fabs(hi));
+  const double atol = 4.0 * 2.220446049250313e-16 * nrm;
+  const double pivmin = 1e-290 * fmax(1.0, nrm * nrm);
+  lo -= atol + pivmin;
+  hi += atol + pivmin;
+  __syncthreads();
+  const int g = K >= 1 && 64 / K < 3 ? 64 / K : 3;
+  const int t = i / g, r = i - t * g;
+  const bool act = t < K;
+  const int sidx = n - 1 - t;  // position of the target in ascending order
+  for (int it = 0; it < 128; ++it) {
+    const double x = lo + (hi - lo) * double(r + 1) / double(g + 1);
+    const int c = sturm_count(tri, n, x, pivmin);
+    xs[i] = x;
+    cs[i] = c;
+    __syncthreads();
+    if (act) {
+      double nlo = lo, nhi = hi;
+      for (int q = 0; q < g; ++q) {
+        const double xq = xs[t * g + q];
+        if (cs[t * g + q] <= sidx)
+          nlo = fmax(nlo, xq);
+        else
+          nhi = fmin(nhi, xq);
+      }
+      lo = nlo;
+      hi = nhi;
+    }
+    __syncthreads();
+    const bool done = !act || hi - lo <= fmax(atol, 4.5e-16 * fmax(fabs(lo), fabs(hi)));
+    if (wave_first(!done) == 64) break;
+  }
+  if (act && r == 0) lam[t] = 0.5 * (lo + hi);
+  __syncthreads();
+  return nrm;
+}
+
+// One inverse-iteration solve (T - lam I) y = y for lane j's vector
+// Y[r * ys + j], with the LU factors of lane j at U[(5 r + c) ys + j] (c = 0
+// pivot, 1 and 2 the next two entries of U's row, 3 the multiplier, 4 the row
+// swap flag), then y normalised.
+__device__ __forceinline__ void tri_solve(int n, const double* U, double* Y, int ys, int j) {
+  double cur = Y[j];
+  for (int r = 0; r + 1 < n; ++r) {
+    const double* u = U + size_t(5 * r) * ys + j;
+    const double nxt = Y[(r + 1) * ys + j];
+    const bool sw = u[4 * ys] != 0.0;
+    const double top = sw ? nxt : cur, bot = sw ? cur : nxt;
+    Y[r * ys + j] = top;
+    cur = bot - u[3 * ys] * top;
+  }
+  Y[(n - 1) * ys + j] = cur;
+  double y1 = 0.0, y2 = 0.0, ss = 0.0;
+  for (int r = n - 1; r >= 0; --r) {
+    const double* u = U + size_t(5 * r) * ys + j;
+    double yr = (Y[r * ys + j] - u[ys] * y1 - u[2 * ys] * y2) / u[0];
+    if (fabs(yr) > 1e150) {  // keep the partial solution representable
+      for (int q = r + 1; q < n; ++q) Y[q * ys + j] *= 1e-150;
+      y1 *= 1e-150;
+      y2 *= 1e-150;
+      ss *= 1e-300;
+      yr *= 1e-150;
+    }
+    Y[r * ys + j] = yr;
+    ss += yr * yr;
+    y2 = y1;
+    y1 = yr;
+  }
+  const double sc = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  for (int r = 0; r < n; ++r) Y[r * ys + j] *= sc;
+}
+
+// Modified Gram-Schmidt over the D vectors of Y in order (lane j owns vector j).
+__device__ __forceinline__ void wave_mgs(int n, int D, double* Y, int ys) {
+  const int j = threadIdx.x;
+  for (int c = 0; c < D; ++c) {
+    if (j == c) {
+      double ss = 0.0;
+      for (int r = 0; r < n; ++r) ss += Y[r * ys + c] * Y[r * ys + c];
+      const double sc = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+      for (int r = 0; r < n; ++r) Y[r * ys + c] *= sc;
+    }
+    __syncthreads();
+    if (j > c && j < D) {
+      double dot = 0.0;
+      for (int r = 0; r < n; ++r) dot += Y[r * ys + j] * Y[r * ys + c];
+      for (int r = 0; r < n; ++r) Y[r * ys + j] -= dot * Y[r * ys + c];
+    }
+    __syncthreads();
+  }
+}
+
+// Eigenvectors of T for lam[0..D) (D <= 64) by inverse iteration: lane j
+// factors T - lam_j I by Gaussian elimination with partial pivoting (pivots
+// below tiny = 4 ulp * nrm raised to tiny) and solves three times from a
+// pseudo-random start; the D vectors are orthonormalised by modified
+// Gram-Schmidt (twice), solved once more (which removes what the
+// orthogonalisation of a nearly dependent member of a cluster amplified
+// outside the cluster) and orthonormalised again.  Vector j is
+// Y[r * ys + j] (LDS); de: 2 * 64 doubles of LDS; U: 5 * n * ys doubles of
+// scratch private to each lane.
+__device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm, const double* lam, double* de,
+                                 double* Y, int ys, double* U) {
+  const int j = threadIdx.x;
+  if (j < n) {
+    de[2 * j] = dr;
+    de[2 * j + 1] = j + 1 < n ? er : 0.0;
+  }
+  __syncthreads();
+  const double tiny = 4.0 * 2.220446049250313e-16 * fmax(nrm, 1e-300);
+  if (j < D) {
+    const double lj = lam[j];
+    double cp = de[0] - lj, cq = de[1], cr = 0.0;
+    for (int r = 0; r + 1 < n; ++r) {
+      const double sub = de[2 * r + 1], nd = de[2 * r + 2] - lj, ns = de[2 * r + 3];
+      double* u = U + size_t(5 * r) * ys + j;
+      if (fabs(cp) >= fabs(sub)) {
+        const double piv = fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp;
+        const double m = sub / piv;
+        u[0] = piv;
+        u[ys] = cq;
+        u[2 * ys] = cr;
+        u[3 * ys] = m;
+        u[4 * ys] = 0.0;
+        const double ncp = nd - m * cq, ncq = ns - m * cr;
+        cp = ncp;
+        cq = ncq;
+      } else {
+        const double m = cp / sub;
+        u[0] = sub;
+        u[ys] = nd;
+        u[2 * ys] = ns;
+        u[3 * ys] = m;
+        u[4 * ys] = 1.0;
+        const double ncp = cq - m * nd, ncq = cr - m * ns;
+        cp = ncp;
+        cq = ncq;
+      }
+      cr = 0.0;
+    }
+    {
+      double* u = U + size_t(5 * (n - 1)) * ys + j;
+      u[0] = fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp;
+      u[ys] = 0.0;
+      u[2 * ys] = 0.0;
+    }
+    for (int r = 0; r < n; ++r) {  // start vector: an integer mixing hash of (r, j)
+      unsigned h = unsigned(r) * 0x9e3779b1u + unsigned(j) * 0x85ebca77u + 0x165667b1u;
+      h ^= h >> 15;
+      h *= 0x2c1b3c6du;
+      h ^= h >> 12;
+      h *= 0x297a2d39u;
+      h ^= h >> 15;
+      Y[r * ys + j] = double(h >> 8) * (1.0 / 16777216.0) - 0.5;
+    }
+    for (int it = 0; it < 3; ++it) tri_solve(n, U, Y, ys, j);
+  }
+  __syncthreads();
+  wave_mgs(n, D, Y, ys);
+  wave_mgs(n, D, Y, ys);
+  if (j < D) tri_solve(n, U, Y, ys, j);
+  __syncthreads();
+  wave_mgs(n, D, Y, ys);
+}
+
+// x <- Q x for the D vectors of Y (lane j owns vector j), Q = H_0 ... H_{n-3}
+// with H_k = I - beta_k v_k v_k^T, v_k in row k of Hv (stride n) and beta_k in
+// lane k's br.
+__device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D, double* Y, int ys) {
+  const int j = threadIdx.x;
+  for (int k = n - 3; k >= 0; --k) {
     const double bk = wave_bcast(br, k);
     if (bk == 0.0) continue;
-    const double v = (own && i > k) ? A[k * n + i] : 0.0;
-    double y = 0.0;
-    for (int c = k + 1; c < n; ++c) y += Zt[c * n + ic] * wave_bcast(v, c);
-    y *= bk;
-    for (int c = k + 1; c < n; ++c) {
-      const double vc = wave_bcast(v, c);
-      if (own) Zt[c * n + i] -= y * vc;
+    if (j < D) {
+      const double* v = Hv + k * n;
+      double sdot = 0.0;
+      for (int r = k + 1; r < n; ++r) sdot += v[r] * Y[r * ys + j];
+      sdot *= bk;
+      for (int r = k + 1; r < n; ++r) Y[r * ys + j] -= sdot * v[r];
     }
   }
-  // --- implicit QL on (d, e); plane rotations applied to the vectors of Zt,
-  // the moving vector carried in a register
-  int fail = 0;
-  for (int l = 0; l < n; ++l) {
-    for (int iter = 0;; ++iter) {
-      // smallest m >= l with e_m negligible (m = n - 1 always qualifies)
-      const double dn = __shfl_down(dr, 1, 64);
-      const bool neg = i + 1 >= n || er == 0.0 || fabs(er) <= 1e-16 * (fabs(dr) + fabs(dn));
-      const int m = wave_first(neg && i >= l);
-      if (m == l) break;
-      if (iter >= 60) {
-        fail = 1;
-        break;
-      }
-      const double dl = wave_bcast(dr, l), el = wave_bcast(er, l);
-      double g = (wave_bcast(dr, l + 1) - dl) / (2.0 * el);
-      double r = sqrt(g * g + 1.0);
-      g = wave_bcast(dr, m) - dl + el / (g + (g >= 0.0 ? r : -r));
-      double sn = 1.0, cs = 1.0, p = 0.0;
-      double zc = Zt[m * n + ic];
-      double znext = Zt[(m - 1) * n + ic];
-      bool early = false;
-      int j = m - 1;
-      for (; j >= l; --j) {
-        // vector j was loaded one step ahead; vector j - 1 is not written
-        // before it is used at the next step
-        const double zj = znext;
-        znext = Zt[(j > l ? j - 1 : l) * n + ic];
-        const double ej = wave_bcast(er, j);
-        const double f = sn * ej, b = cs * ej;
-        const double t = f * f + g * g;  // |f|, |g| stay O(1) for a normalised matrix
-        if (t == 0.0) {
-          if (i == j + 1) {
-            er = 0.0;
-            dr -= p;
-          }
-          if (i == m) er = 0.0;
-          early = true;
-          break;
-        }
-        const double ir = rsqrt(t);
-        if (i == j + 1) er = t * ir;
-        sn = f * ir;
-        cs = g * ir;
-        g = wave_bcast(dr, j + 1) - p;
-        r = (wave_bcast(dr, j) - g) * sn + 2.0 * cs * b;
-        p = sn * r;
-        if (i == j + 1) dr = g + p;
-        g = cs * r - b;
-        if (own) Zt[(j + 1) * n + i] = sn * zj + cs * zc;
-        zc = cs * zj - sn * zc;
-      }
-      if (own) Zt[(early ? j + 1 : l) * n + i] = zc;
-      if (early) continue;
-      if (i == l) {
-        dr -= p;
-        er = g;
-      }
-      if (i == m) er = 0.0;
-    }
-  }
-  if (own) d[i] = dr;
-  return fail;
+  __syncthreads();
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {

@@ -141,7 +141,8 @@ struct Layout {
   int legcap, ncap, kdcap, mcap_chi;
   std::vector<int64_t> site_off, fin_off;
   int64_t sweep_stride = 0, fin_stride = 0;
-  int64_t mcap = 0, kcap = 0, bigcap = 0;
+  int64_t mcap = 0, kcap = 0, bigcap = 0, jcap = 0;
+  int eig_ys = 1;
   size_t per_sweep_bytes = 0;
 };
 
@@ -171,13 +172,17 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   L.mcap = int64_t(cm) * L.legcap * cm;
   L.kcap = int64_t(cm) * cm * L.legcap;
   L.bigcap = int64_t(cm) * L.legcap * int64_t(cm) * L.legcap;
+  // FP32 boundary MPS: eigenvectors of families of up to 64 vectors in LDS
+  // with row stride eig_ys, and the inverse-iteration factors per vector
+  L.eig_ys = std::min(cm, 64);
+  L.jcap = std::max<int64_t>(L.bigcap, int64_t(5) * std::min<int64_t>(64, int64_t(cm) * L.legcap) * L.eig_ys);
   const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;
   b += P.n_bonds * (4 + 8 + 8 * size_t(chi)) + P.Lx * P.Ly * 8 + 4;
   b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8;
   b += L.fin_stride * 8;
-  b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 4 * L.bigcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
+  b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + L.jcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
   L.per_sweep_bytes = b + 64 * 20;
   return L;
 }
@@ -253,7 +258,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_kdim = cv.take<int32_t>(nsw_max * 3);
   size_t o_L4 = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Th = cv.take<double>(nsw_max * L.bigcap);
-  size_t o_Jm = cv.take<double>(nsw_max * L.bigcap);
+  size_t o_Jm = cv.take<double>(nsw_max * L.jcap);
   size_t o_Gm = cv.take<double>(prec == TN3D_PREC_FP64 ? 1 : nsw_max * L.bigcap);
   size_t o_zdim = cv.take<int32_t>(nsw_max * 12);
   size_t o_zS = cv.take<double>(nsw_max * 1024);
@@ -364,6 +369,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.Th = reinterpret_cast<double*>(ws + o_Th);
     Z.Jm = reinterpret_cast<double*>(ws + o_Jm);
     Z.bigcap = L.bigcap;
+    Z.jcap = L.jcap;
+    Z.eig_ys = L.eig_ys;
     Z.logm = reinterpret_cast<double*>(ws + o_logm);
     Z.flags = reinterpret_cast<uint32_t*>(ws + o_zfl);
     Z.eps = pr.eps_rel;

@@ -576,7 +576,7 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   const bool rows = zd[6] != 0;
   const int nv = zd[7], len = rows ? C : R;
   double* Th = Z.Th + int64_t(s) * Z.bigcap;
-  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
+  double* Jm = Z.Jm + int64_t(s) * Z.jcap;
   double* Sout = Z.zS + int64_t(s) * 1024;
   double* A;
   double* J;
@@ -605,39 +605,45 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   zip_keep(Z, s, zd, nv, Sout, ord, J, 1, nv, nsw);
 }
 
-// FP32 mode, families of at most ZBIG vectors: symmetric eigenproblem of the
-// PSD Gram (eigenvalues S^2) in one wavefront, eigenvectors contiguous in LDS.
-// The Gram is normalised in place to its largest diagonal entry; lane i scales
-// column i, the only column of G it touches in the solver.
+// FP32 mode, families of at most ZBIG vectors: leading eigenpairs of the PSD
+// Gram (eigenvalues S^2) in one wavefront.  The Gram is scaled by its largest
+// diagonal entry; only the min(nv, chi_m + 1) largest eigenvalues (all the
+// rank rule reads) and the vectors it keeps are computed.  The reflectors of
+// the tridiagonal reduction overwrite the Gram; the kept vectors sit in LDS
+// (row stride eig_ys) and are copied to Fv.
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
-  extern __shared__ double zsm[];  // ZBIG * ZBIG
-  __shared__ double S[ZBIG];
-  __shared__ int ord[ZBIG];
+  extern __shared__ double zsm[];  // 64 * eig_ys
+  __shared__ double vw[128], tri[128], de[128], xs[64], lam[64];
+  __shared__ int cs[64];
   const int s = blockIdx.x, tid = threadIdx.x;
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
   if (nv > ZBIG) return;  // k_zip_bbig takes it
   double* G = Z.Gm + int64_t(s) * Z.bigcap;
   double* Sout = Z.zS + int64_t(s) * 1024;
-  double gd = tid < nv ? G[tid * nv + tid] : 0.0;
-  for (int o = 32; o > 0; o >>= 1) gd = fmax(gd, __shfl_xor(gd, o, 64));
-  const double gsc = gd > 0.0 ? gd : 1.0, igs = 1.0 / gsc;
-  if (tid < nv)
-    for (int j = 0; j < nv; ++j) G[j * nv + tid] *= igs;
-  const int fail = wave_sym_eig(G, nv, zsm, S);
-  if (tid < nv) S[tid] *= gsc;
+  const double gd = wave_max(tid < nv ? G[tid * nv + tid] : 0.0);
+  const double gsc = gd > 0.0 ? gd : 1.0;
+  double dr, er, br;
+  wave_tridiag(G, 1.0 / gsc, nv, vw, G, dr, er, br);
+  const int K = nv < Z.chi_m + 1 ? nv : Z.chi_m + 1;
+  const double nrm = wave_tri_topk(dr, er, nv, K, tri, xs, cs, lam);
+  if (tid < K) Sout[tid] = sqrt(fmax(lam[tid] * gsc, 0.0));
   __syncthreads();
-  if (tid < nv) {
-    const double lv = S[tid];
-    int rk = 0;
-    for (int u = 0; u < nv; ++u)
-      if (S[u] > lv || (S[u] == lv && u < tid)) ++rk;
-    ord[rk] = tid;
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
+  const bool bad = Dn < 1;
+  if (bad) Dn = 1;
+  const int ys = Z.eig_ys;
+  wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, Z.Jm + int64_t(s) * Z.jcap);
+  wave_tri_backtransform(G, br, nv, Dn, zsm, ys);
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
+  for (int e = tid; e < nv * Dn; e += 64) Fv[e] = zsm[(e / Dn) * ys + e % Dn];
+  if (tid == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], 1);
+    const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u);
+    if (f) atomicOr(&Z.flags[s], f);
   }
-  __syncthreads();
-  if (tid < nv) Sout[tid] = sqrt(fmax(S[ord[tid]], 0.0));
-  __syncthreads();
-  zip_keep(Z, s, zd, nv, Sout, ord, zsm, nv, 1, fail ? 40 : 1);
 }
 
 // Decomposition of the Gram blocks larger than ZBIG (FP32 mode) with the
@@ -651,7 +657,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
   const int nv = zd[7];
   if (nv <= ZBIG) return;
   double* G = Z.Gm + int64_t(s) * Z.bigcap;
-  double* Jm = Z.Jm + int64_t(s) * Z.bigcap;
+  double* Jm = Z.Jm + int64_t(s) * Z.jcap;
   double* Sout = Z.zS + int64_t(s) * 1024;
   const int nw = ZNT / 64;
   const int small = 3 * nv + 2 * nw * nv;  // d, e, beta, per-wavefront (d, e)
@@ -928,7 +934,7 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
-      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(ZBIG) * ZBIG * 8, st, Z, x, y);
+      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64) * Z.eig_ys * 8, st, Z, x, y);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
