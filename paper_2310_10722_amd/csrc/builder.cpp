@@ -287,6 +287,9 @@ class Assembler {
       pd.dout = dout;
       if (det >= 0) pd.det = det;
     }
+    // the one-site kernel holds the matrix in 256 doubles and a row of the
+    // input in 16 registers
+    if (pd.din > 16 || pd.dout > 16 || pd.din * pd.dout > 256) return "one-site op larger than 16 x 16";
     if (is_pre) staged[s] = dout;
     return "";
   }

@@ -217,7 +217,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   const int max_g = std::max(1, n->max_gates_class);
   Layout L = make_layout(P, pr.chi, pr.chi_mps, prec, max_g);
   // the kernels' fixed-size LDS arrays bound these (sweep.hip)
-  if (L.ncap > 120) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 120 on a gated site");
+  if (L.ncap > 64) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 64 on a gated site");
   if (L.kdcap > 64) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 64");
   if (int64_t(pr.chi_mps) * L.legcap > 1024) return fail(c, TN3D_E_UNSUPPORTED, "chi_mps x chi above 1024");
   if (P.Lx * P.Ly > 65535) return fail(c, TN3D_E_UNSUPPORTED, "grid too large");

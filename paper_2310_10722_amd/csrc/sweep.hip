@@ -106,109 +106,143 @@ __global__ __launch_bounds__(NT) void k_onesite(SweepArgs A, const DevOneSite* o
   __syncthreads();
   int D[4];
   site_dims(A, sweep, op.site, D);
-  const int64_t rows = int64_t(D[0]) * D[1] * D[2] * D[3];
+  const int rows = D[0] * D[1] * D[2] * D[3];  // at most legcap^4 * d elements: 32-bit
   const T* in = tens<T>(A, op.src, sweep, op.site);
   T* out = tens<T>(A, op.src ^ 1, sweep, op.site);
-  for (int64_t e = threadIdx.x; e < rows * op.dout; e += blockDim.x) {
-    const int64_t r = e / op.dout;
-    const int q = int(e % op.dout);
-    double s = 0.0;
-    for (int p = 0; p < op.din; ++p) s += M[q * op.din + p] * double(in[r * op.din + p]);
-    out[e] = T(s);
+  const int din = op.din, dout = op.dout;
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    double v[16];  // din <= 16 (checked when the network is built)
+    for (int p = 0; p < din; ++p) v[p] = double(in[r * din + p]);
+    for (int q = 0; q < dout; ++q) {
+      double s = 0.0;
+      for (int p = 0; p < din; ++p) s += M[q * din + p] * v[p];
+      out[r * dout + q] = T(s);
+    }
   }
 }
 
-// View of a site tensor stored [w][e][n][s][p] for the bond on leg `leg`:
-// element (a, x, c, p) at ((a * Dx + x) * Cp + c) * d + p, a running over the
-// legs before `leg`, c over the legs after it.
-struct View {
-  int Dx, Cp, d;
-  int64_t Apre, rows;
-};
-
-__device__ __forceinline__ View make_view(const int D[4], int leg, int d) {
-  View v;
-  v.Dx = D[leg];
-  v.d = d;
-  v.Apre = 1;
-  v.Cp = 1;
-  for (int l = 0; l < leg; ++l) v.Apre *= D[l];
-  for (int l = leg + 1; l < 4; ++l) v.Cp *= D[l];
-  v.rows = v.Apre * v.Cp;
-  return v;
-}
+// Site tensors are stored [w][e][n][s][p].  For the bond on leg `leg` the
+// element (a, x, c, p) sits at ((a * Dx + x) * Cp + c) * d + p, a running over
+// the legs before `leg`, c over the legs after it.
 
 // ---------------------------------------------------------------------------
 // Gram of one side of each gated bond, FP64 accumulation
 // ---------------------------------------------------------------------------
-template <typename T, int NACC>
-__global__ __launch_bounds__(NT) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap) {
-  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y;
+// Element offsets of the (legs before, gated leg, legs after, physical) view of
+// a site tensor: row r = (a, c) starts at (a * Dx * Cp + c) * d and column
+// col = p * Dx + x sits at x * Cp * d + p from there.  Rows are split once per
+// tile and columns once per workgroup, so the element loops use no division.
+struct Split {
+  int Dx, Cp, d, rows;
+};
+
+__device__ __forceinline__ Split make_split(const int D[4], int leg, int d) {
+  Split v;
+  v.Dx = D[leg];
+  v.d = d;
+  int apre = 1;
+  v.Cp = 1;
+  for (int l = 0; l < leg; ++l) apre *= D[l];
+  for (int l = leg + 1; l < 4; ++l) v.Cp *= D[l];
+  v.rows = apre * v.Cp;
+  return v;
+}
+
+constexpr int GTR = 16;  // rows per tile of the Gram kernel
+
+// One wavefront per (gate side, sweep).  Threads are grouped: group g of
+// ngrp = 64 / ncols groups owns Gram rows i = 0..ncols-1 (one per thread) and
+// the column block [g cw, g cw + cw), cw = ceil(ncols / ngrp), so every
+// thread keeps at most NMAX accumulators in registers and the loops over the
+// block are uniform.  Tiles of GTR rows are staged in LDS with the row weights
+// applied; columns beyond ncols are zero.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap) {
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
   const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
   int D[4];
   site_dims(A, sweep, site, D);
-  const View v = make_view(D, leg, d);
+  const Split v = make_split(D, leg, d);
   const int ncols = d * v.Dx;
+  const int ngrp = ncols <= 64 ? 64 / ncols : 1;
+  const int cw = (ncols + ngrp - 1) / ngrp;
+  const int tw = ngrp * cw;  // tile width (>= ncols, padded with zeros)
   __shared__ double slam[4][MAXCHI];
-  __shared__ double tile[TR * 128];
-  for (int e = threadIdx.x; e < 4 * MAXCHI; e += NT) {
+  __shared__ double tile[GTR * NMAX];  // tw <= 64 when ncols <= 64
+  __shared__ int colofs[NMAX];
+  __shared__ int rowbase[GTR];
+  __shared__ double rowsc[GTR];
+  for (int e = tid; e < 4 * MAXCHI; e += 64) {
     const int l = e / MAXCHI, k = e % MAXCHI;
     const int b = A.leg_bond[site * 4 + l];
     double val = 1.0;
     if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
     slam[l][k] = val;
   }
-  double acc[NACC];
+  for (int col = tid; col < tw; col += 64) {
+    const int p = col / v.Dx, x = col - p * v.Dx;
+    colofs[col] = col < ncols ? x * v.Cp * d + p : -1;
+  }
+  const int grp = tid / ncols, i = tid - grp * ncols, j0 = grp * cw;
+  const bool act = grp < ngrp;
+  double acc[NMAX];
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+  for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
   const T* t = tens<T>(A, par, sweep, site);
-  for (int64_t r0 = 0; r0 < v.rows; r0 += TR) {
+  for (int r0 = 0; r0 < v.rows; r0 += GTR) {
     __syncthreads();
-    for (int e = threadIdx.x; e < TR * ncols; e += NT) {
-      const int rl = e % TR, col = e / TR;
-      const int64_t r = r0 + rl;
-      double val = 0.0;
+    if (tid < GTR) {
+      // row r = (a, c): base offset and the product of sqrt(lambda) over the
+      // three other legs (the simple-update environment)
+      const int r = r0 + tid;
+      int base = 0;
+      double sc = 0.0;
       if (r < v.rows) {
-        const int p = col / v.Dx, x = col % v.Dx;
-        const int64_t a = r / v.Cp, c = r % v.Cp;
-        val = double(t[((a * v.Dx + x) * v.Cp + c) * d + p]);
-        double sc = 1.0;
-        int64_t aa = a, cc = c;
+        const int a = r / v.Cp, c = r - a * v.Cp;
+        base = (a * v.Dx * v.Cp + c) * d;
+        sc = 1.0;
+        int cc = c;
         for (int l = 3; l > leg; --l) {
-          sc *= slam[l][cc % D[l]];
-          cc /= D[l];
+          const int q = cc / D[l];
+          sc *= slam[l][cc - q * D[l]];
+          cc = q;
         }
+        int aa = a;
         for (int l = leg - 1; l >= 0; --l) {
-          sc *= slam[l][aa % D[l]];
-          aa /= D[l];
+          const int q = aa / D[l];
+          sc *= slam[l][aa - q * D[l]];
+          aa = q;
         }
-        val *= sc;
       }
-      tile[rl * ncols + col] = val;
+      rowbase[tid] = base;
+      rowsc[tid] = sc;
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) {
-      const int e = threadIdx.x + k * NT;
-      if (e < ncols * ncols) {
-        const int i = e / ncols, j = e % ncols;
-        double s = 0.0;
-#pragma unroll 8
-        for (int rl = 0; rl < TR; ++rl) s += tile[rl * ncols + i] * tile[rl * ncols + j];
-        acc[k] += s;
-      }
+    const int nr = v.rows - r0 < GTR ? v.rows - r0 : GTR;
+    for (int e = tid; e < GTR * tw; e += 64) {
+      const int rl = e & (GTR - 1), col = e / GTR;
+      const int off = colofs[col];
+      tile[rl * tw + col] = (rl < nr && off >= 0) ? double(t[rowbase[rl] + off]) * rowsc[rl] : 0.0;
     }
-  }
-  if (A.bytes_ctr && threadIdx.x == 0)
-    atomicAdd(A.bytes_ctr, (unsigned long long)(v.rows * ncols * int64_t(sizeof(T))));
-  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
+    __syncthreads();
+    if (act)
+      for (int rl = 0; rl < nr; ++rl) {
+        const double* tr = tile + rl * tw;
+        const double ti = tr[i];
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const int e = threadIdx.x + k * NT;
-    if (e < ncols * ncols) out[e] = acc[k];
+        for (int k = 0; k < NMAX; ++k)
+          if (k < cw) acc[k] += ti * tr[j0 + k];
+      }
   }
+  if (A.bytes_ctr && tid == 0)
+    atomicAdd(A.bytes_ctr, (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
+  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
+  if (act)
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+      if (k < cw && j0 + k < ncols) out[i * ncols + j0 + k] = acc[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -339,10 +373,26 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
 // reabsorption T' = T W on the (p, bond) columns
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_reabsorb(SweepArgs A, const DevGate* gates, int n_g, const double* win,
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+// One wavefront per (gate side, sweep), one thread per tensor row: the row's
+// nin entries are held in registers in the storage type T (the arithmetic of
+// the absorption) and multiplied by W, staged in LDS with its rows padded to a
+// multiple of 4 and read by all lanes at the same address, four outputs at a
+// time.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gates, int n_g, const double* win,
                                                  int ncap) {
-  extern __shared__ double sm[];
-  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y;
+  using V4 = typename Vec4<T>::type;
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
   const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
@@ -351,38 +401,52 @@ __global__ __launch_bounds__(NT) void k_reabsorb(SweepArgs A, const DevGate* gat
   int D[4];
   site_dims(A, sweep, site, D);
   D[leg] = Dold;
-  const View v = make_view(D, leg, d);
-  const int nin = d * Dold, nout = d * Dn;
-  double* Ws = sm;
-  double* tile = Ws + nin * nout;
-  for (int e = threadIdx.x; e < nin * nout; e += NT) Ws[e] = W[2 + e];
+  const Split v = make_split(D, leg, d);
+  const int nin = d * Dold, nout = d * Dn, nst = (nout + 3) & ~3;
+  __shared__ V4 Ws4[NMAX * NMAX / 4];
+  __shared__ int colin[NMAX], colout[NMAX];
+  T* Ws = reinterpret_cast<T*>(Ws4);
+  for (int e = tid; e < nin * nst; e += 64) {
+    const int k = e / nst, q = e - k * nst;
+    Ws[e] = q < nout ? T(W[2 + k * nout + q]) : T(0);
+  }
+  for (int col = tid; col < nin; col += 64) {
+    const int p = col / Dold, x = col - p * Dold;
+    colin[col] = x * v.Cp * d + p;
+  }
+  for (int col = tid; col < nout; col += 64) {
+    const int p = col / Dn, m = col - p * Dn;
+    colout[col] = m * v.Cp * d + p;
+  }
+  __syncthreads();
   const T* in = tens<T>(A, par, sweep, site);
   T* out = tens<T>(A, par ^ 1, sweep, site);
-  if (A.bytes_ctr && threadIdx.x == 0)
-    atomicAdd(A.bytes_ctr, (unsigned long long)(v.rows * (nin + nout) * int64_t(sizeof(T))));
-  for (int64_t r0 = 0; r0 < v.rows; r0 += TR) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < TR * nin; e += NT) {
-      const int rl = e % TR, col = e / TR;
-      const int64_t r = r0 + rl;
-      double val = 0.0;
-      if (r < v.rows) {
-        const int p = col / Dold, x = col % Dold;
-        const int64_t a = r / v.Cp, c = r % v.Cp;
-        val = double(in[((a * Dold + x) * v.Cp + c) * d + p]);
-      }
-      tile[rl * nin + col] = val;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < TR * nout; e += NT) {
-      const int rl = e % TR, col = e / TR;
-      const int64_t r = r0 + rl;
-      if (r >= v.rows) continue;
-      double s = 0.0;
-      for (int c = 0; c < nin; ++c) s += tile[rl * nin + c] * Ws[c * nout + col];
-      const int p2 = col / Dn, m = col % Dn;
-      const int64_t a = r / v.Cp, c = r % v.Cp;
-      out[((a * Dn + m) * v.Cp + c) * d + p2] = T(s);
+  if (A.bytes_ctr && tid == 0)
+    atomicAdd(A.bytes_ctr, (unsigned long long)(int64_t(v.rows) * (nin + nout) * int64_t(sizeof(T))));
+  const int n4 = nst / 4;
+  for (int r = tid; r < v.rows; r += 64) {
+    const int a = r / v.Cp, c = r - a * v.Cp;
+    const T* src = in + (a * Dold * v.Cp + c) * d;
+    T* dst = out + (a * Dn * v.Cp + c) * d;
+    T x[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) x[k] = k < nin ? src[colin[k]] : T(0);
+    for (int q4 = 0; q4 < n4; ++q4) {
+      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k)
+        if (k < nin) {
+          const V4 w = Ws4[k * n4 + q4];
+          s0 += x[k] * w.x;
+          s1 += x[k] * w.y;
+          s2 += x[k] * w.z;
+          s3 += x[k] * w.w;
+        }
+      const int q = 4 * q4;
+      dst[colout[q]] = s0;
+      if (q + 1 < nout) dst[colout[q + 1]] = s1;
+      if (q + 2 < nout) dst[colout[q + 2]] = s2;
+      if (q + 3 < nout) dst[colout[q + 3]] = s3;
     }
   }
 }
@@ -822,6 +886,17 @@ __global__ void k_decode(int n_items, int n_cosets, const int32_t* items, const 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Raise a kernel's dynamic-LDS limit to what a launch needs when that exceeds
+// the default.  A refused request is cleared here, so that the launch itself
+// reports the failure instead of a later unrelated check.
+static void need_dyn_lds(const void* f, size_t bytes, size_t& granted) {
+  if (bytes <= granted || bytes <= 64 * 1024) return;
+  if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess)
+    granted = bytes;
+  else
+    (void)hipGetLastError();
+}
+
 void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
                  const int32_t* bond_dim0, hipStream_t st) {
   dim3 g(A.n_sites, A.n_sweeps);
@@ -844,16 +919,8 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 template <typename T>
 static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
                           hipStream_t st) {
-  dim3 g(2 * n_g, A.n_sweeps);
-  const int nacc = (ncap * ncap + NT - 1) / NT;
-  if (nacc <= 4)
-    hipLaunchKernelGGL((k_gram<T, 4>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
-  else if (nacc <= 16)
-    hipLaunchKernelGGL((k_gram<T, 16>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
-  else if (nacc <= 36)
-    hipLaunchKernelGGL((k_gram<T, 36>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
-  else
-    hipLaunchKernelGGL((k_gram<T, 64>), g, dim3(NT), 0, st, A, gates, n_g, gout, ncap);
+  // ncap <= 64 is checked by the host before any launch
+  hipLaunchKernelGGL((k_gram<T, 64>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap);
 }
 
 void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
@@ -869,32 +936,19 @@ void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const doubl
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
   const size_t lds = size_t(4) * kdcap * kdcap * 8 + size_t(2) * kdcap * 8 + 32 + size_t(2 * kdcap + 4) * 4;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr = true;
-  }
+  static size_t granted = 0;
+  need_dyn_lds(reinterpret_cast<const void*>(k_solve), lds, granted);
   hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), lds, st, A, gates, n_g, gin, wout, ncap);
 }
 
 void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
                      hipStream_t st) {
   if (n_g <= 0) return;
-  const size_t lds = size_t(ncap) * ncap * 8 + size_t(TR) * ncap * 8;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reabsorb<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reabsorb<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
   dim3 g(2 * n_g, A.n_sweeps);
   if (prec == 0)
-    hipLaunchKernelGGL(k_reabsorb<double>, g, dim3(NT), lds, st, A, gates, n_g, win, ncap);
+    hipLaunchKernelGGL((k_reabsorb<double, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap);
   else
-    hipLaunchKernelGGL(k_reabsorb<float>, g, dim3(NT), lds, st, A, gates, n_g, win, ncap);
+    hipLaunchKernelGGL((k_reabsorb<float, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap);
 }
 
 void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
@@ -923,14 +977,9 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              18432 * 8);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              19200 * 8);
-    attr = true;
-  }
+  static size_t granted_b = 0, granted_big = 0;
+  need_dyn_lds(reinterpret_cast<const void*>(k_zip_b), size_t(18432) * 8, granted_b);
+  need_dyn_lds(reinterpret_cast<const void*>(k_zip_bbig), size_t(19200) * 8, granted_big);
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
