@@ -248,6 +248,35 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
 // ---------------------------------------------------------------------------
 // truncation of each gated bond: FP64, one workgroup per bond
 // ---------------------------------------------------------------------------
+// Z_A, Z_B (n x n, n = K D) of a gated bond from the Grams of its two sides:
+// Z[(k,b),(k',b')] = sum_{p,q} (O_k^T O_k')[p,q] G[(p,b),(q,b')].
+__device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const double* gin, int ncap, int n_g,
+                                  int gi, int sweep, int D, double* ZA, double* ZB) {
+  const int K = g.K, dA = g.dA, dB = g.dB, n = K * D;
+  const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
+  const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
+  const double* PA = A.pool + g.pA;
+  const double* PB = A.pool + g.pB;
+  const int nA = dA * D, nB = dB * D;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
+    double za = 0.0, zb = 0.0;
+    for (int p = 0; p < dA; ++p)
+      for (int q = 0; q < dA; ++q) {
+        const double w = PA[((k * K + k2) * dA + p) * dA + q];
+        if (w != 0.0) za += w * GA[(p * D + b) * nA + q * D + b2];
+      }
+    for (int p = 0; p < dB; ++p)
+      for (int q = 0; q < dB; ++q) {
+        const double w = PB[((k * K + k2) * dB + p) * dB + q];
+        if (w != 0.0) zb += w * GB[(p * D + b) * nB + q * D + b2];
+      }
+    ZA[e] = za;
+    ZB[e] = zb;
+  }
+}
+
 __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
                                               double* wout, int ncap) {
   extern __shared__ double sm[];
@@ -266,28 +295,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
   int* ord = reinterpret_cast<int*>(red + 4);
   int* perm = ord + n;
   int* flag = perm + n;
-  const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
-  const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
-  const double* PA = A.pool + g.pA;
-  const double* PB = A.pool + g.pB;
   const int nA = dA * D, nB = dB * D;
-  for (int e = tid; e < n * n; e += SNT) {
-    const int r = e / n, c = e % n;
-    const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
-    double za = 0.0, zb = 0.0;
-    for (int p = 0; p < dA; ++p)
-      for (int q = 0; q < dA; ++q) {
-        const double w = PA[((k * K + k2) * dA + p) * dA + q];
-        if (w != 0.0) za += w * GA[(p * D + b) * nA + q * D + b2];
-      }
-    for (int p = 0; p < dB; ++p)
-      for (int q = 0; q < dB; ++q) {
-        const double w = PB[((k * K + k2) * dB + p) * dB + q];
-        if (w != 0.0) zb += w * GB[(p * D + b) * nB + q * D + b2];
-      }
-    ZA[e] = za;
-    ZB[e] = zb;
-  }
+  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB);
   __syncthreads();
   const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
   const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
