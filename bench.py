@@ -158,7 +158,8 @@ def main():
                               "mean_smallest_lambda": stats[3], "max_jacobi_sweeps": stats[4],
                               "max_jacobi_sweeps_boundary": stats[5]},
         "flags": {"numeric": int(np.sum(flags & 1 != 0)), "trunc_cluster": int(np.sum(flags & 2 != 0)),
-                  "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0))},
+                  "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0)),
+                  "reswept_fp64": int(np.sum(flags & 16 != 0))},
     }
     if not a.no_cpu:
         n = min(a.cpu_sample, B)

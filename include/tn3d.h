@@ -53,6 +53,7 @@ typedef enum {
 #define TN3D_FLAG_TRUNC_CLUSTER 2u /* a truncation cut inside a cluster of equal singular values */
 #define TN3D_FLAG_NEAR_TIE 4u      /* |log ratio| of the decision below params.near_tie */
 #define TN3D_FLAG_NO_CONVERGE 8u   /* a Jacobi SVD stopped at its sweep limit */
+#define TN3D_FLAG_RESWEPT 16u      /* decode: contracted again in FP64 (near tie of an FP32 pass) */
 
 /* Arithmetic of the layer absorption (site tensors and their contractions).
  * The truncation factorisations, singular values and log accumulators are
@@ -143,8 +144,13 @@ tn3d_status tn3d_contract_cosets(tn3d_ctx ctx, int32_t batch, const tn3d_net* ne
 /* Decode (paper Sec. 2.3, eq. optimal_decoder): as tn3d_contract_cosets, then
  * per item coset_dev[i] = argmax_L log p_{m,L} (lowest index on exact ties),
  * logratio_dev[i] = log p of the chosen coset minus the largest other one
- * (>= 0), TN3D_FLAG_NEAR_TIE when logratio < params->near_tie.  logp_dev and
- * flags_dev may be NULL. */
+ * (>= 0), TN3D_FLAG_NEAR_TIE when logratio < params->near_tie.  With
+ * precision TN3D_PREC_FP32 and near_tie > 0, every item whose log-ratio is
+ * below near_tie (or not a number) is contracted again in FP64 at the same chi
+ * and chi_mps with the FP64 defaults of tn3d_params_default for eps_rel and
+ * tau_gap; its logp row, flags (those of the FP64 pass plus TN3D_FLAG_RESWEPT)
+ * and decision are replaced.  This synchronises the context stream once.
+ * logp_dev and flags_dev may be NULL. */
 tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
                         const uint8_t* syndromes_dev, const int64_t* offsets_dev,
                         const tn3d_params* params, int32_t* coset_dev, double* logratio_dev,
@@ -166,7 +172,8 @@ tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);
  * swept 2D network, out[1] = largest, out[2] = number of sweeps, out[3] = mean
  * over sweeps of the smallest kept lambda (relative to its bond's largest),
  * out[4] = most Jacobi sweeps any truncation needed, out[5] = same for the
- * boundary MPS.
+ * boundary MPS, out[6] = items the last tn3d_decode re-swept in FP64 (n <= 7
+ * values are written).
  * Returns TN3D_E_INVALID if timing was not enabled. */
 tn3d_status tn3d_last_stats(tn3d_ctx ctx, double* out, int32_t n);
 

@@ -26,6 +26,7 @@ struct tn3d_ctx_s {
   double timing_out[5] = {0, 0, 0, 0, 0};
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
+  int last_resweeps = 0;           // items the last decode re-swept in FP64
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> hot_ev;  // pairs around Gram / reabsorption launches
   char* aux = nullptr;             // decode scratch
@@ -602,6 +603,39 @@ tn3d_status tn3d_contract_cosets(tn3d_ctx c, int32_t batch, const tn3d_net* nets
   return contract_impl(c, batch, nets, synd, offs, pr, logp, flags);
 }
 
+// Decision for each item of a batch from its coset log-probabilities, grouped
+// by coset count when networks differ.  items: device scratch of batch ints.
+static tn3d_status decide(tn3d_ctx c, int32_t n, const tn3d_net* nets, const int32_t* host_items, int32_t* d_items,
+                          const double* lp, double near_tie, int32_t* coset, double* logratio, uint32_t* flags) {
+  // host_items == nullptr: the items are 0 .. n-1 of nets
+  int ncs0 = nets[host_items ? host_items[0] : 0]->P.n_cosets;
+  bool uniform = true;
+  for (int i = 1; i < n; ++i)
+    if (nets[host_items ? host_items[i] : i]->P.n_cosets != ncs0) uniform = false;
+  if (uniform) {
+    if (host_items)
+      HIPCHK(c, hipMemcpyAsync(d_items, host_items, size_t(n) * 4, hipMemcpyHostToDevice, c->stream));
+    else
+      hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, c->stream, d_items, n, 0);
+    launch_decode(n, ncs0, d_items, lp, near_tie, coset, logratio, flags, c->stream);
+  } else {
+    std::vector<int32_t> idx;
+    for (int ncs = 2; ncs <= 4; ++ncs) {
+      idx.clear();
+      for (int i = 0; i < n; ++i) {
+        const int it = host_items ? host_items[i] : i;
+        if (nets[it]->P.n_cosets == ncs) idx.push_back(it);
+      }
+      if (idx.empty()) continue;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      HIPCHK(c, hipMemcpy(d_items, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+      launch_decode(int(idx.size()), ncs, d_items, lp, near_tie, coset, logratio, flags, c->stream);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return TN3D_OK;
+}
+
 tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
                         const int64_t* offs, const tn3d_params* pr, int32_t* coset, double* logratio,
                         double* logp, uint32_t* flags) {
@@ -609,8 +643,12 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   if (batch > 0 && (!coset || !logratio)) return fail(c, TN3D_E_INVALID, "null output");
   if (batch <= 0) return contract_impl(c, batch, nets, synd, offs, pr, logp, flags);
   HIPCHK(c, hipSetDevice(c->device));
-  // context-owned scratch: log p (when the caller passes none) and item lists
-  const size_t need = size_t(batch) * 4 * 8 + size_t(batch) * 4 + 512;
+  // context-owned scratch: log p (when the caller passes none), item lists,
+  // and the near-tie re-sweep's offsets, log p and flags
+  const size_t b = size_t(batch);
+  const size_t o_lp = 0, o_items = align256(b * 32), o_cnt = o_items + align256(b * 4),
+               o_offs = o_cnt + 256, o_lps = o_offs + align256(b * 8), o_fls = o_lps + align256(b * 32),
+               need = o_fls + align256(b * 4);
   if (c->aux_bytes < need) {
     if (c->aux) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -621,31 +659,45 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
     if (hipMalloc(&c->aux, need) != hipSuccess) return fail(c, TN3D_E_OOM, "decode scratch");
     c->aux_bytes = need;
   }
-  double* lp = logp ? logp : reinterpret_cast<double*>(c->aux);
-  int32_t* d_items = reinterpret_cast<int32_t*>(c->aux + align256(size_t(batch) * 4 * 8));
+  double* lp = logp ? logp : reinterpret_cast<double*>(c->aux + o_lp);
+  int32_t* d_items = reinterpret_cast<int32_t*>(c->aux + o_items);
+  c->last_resweeps = 0;
   tn3d_status s = contract_impl(c, batch, nets, synd, offs, pr, lp, flags);
   if (s != TN3D_OK) return s;
-  int ncs0 = nets[0]->P.n_cosets;
-  bool uniform = true;
-  for (int i = 1; i < batch; ++i)
-    if (nets[i]->P.n_cosets != ncs0) uniform = false;
-  if (uniform) {
-    hipLaunchKernelGGL(k_iota, dim3((batch + 255) / 256), dim3(256), 0, c->stream, d_items, batch, 0);
-    launch_decode(batch, ncs0, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
-  } else {
-    std::vector<int32_t> idx;
-    for (int ncs = 2; ncs <= 4; ++ncs) {
-      idx.clear();
-      for (int i = 0; i < batch; ++i)
-        if (nets[i]->P.n_cosets == ncs) idx.push_back(i);
-      if (idx.empty()) continue;
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      HIPCHK(c, hipMemcpy(d_items, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
-      launch_decode(int(idx.size()), ncs, d_items, lp, pr->near_tie, coset, logratio, flags, c->stream);
-    }
-  }
-  HIPCHK(c, hipGetLastError());
-  return TN3D_OK;
+  s = decide(c, batch, nets, nullptr, d_items, lp, pr->near_tie, coset, logratio, flags);
+  if (s != TN3D_OK) return s;
+  if (pr->precision == TN3D_PREC_FP64 || !(pr->near_tie > 0.0)) return TN3D_OK;
+  // near ties of the reduced-precision pass are contracted again in FP64
+  int32_t* d_cnt = reinterpret_cast<int32_t*>(c->aux + o_cnt);
+  HIPCHK(c, hipMemsetAsync(d_cnt, 0, 4, c->stream));
+  launch_pick_ties(batch, logratio, pr->near_tie, d_items, d_cnt, c->stream);
+  int32_t cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, d_cnt, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (cnt <= 0) return TN3D_OK;
+  std::vector<int32_t> ties(cnt);
+  HIPCHK(c, hipMemcpy(ties.data(), d_items, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+  std::sort(ties.begin(), ties.end());
+  HIPCHK(c, hipMemcpy(d_items, ties.data(), size_t(cnt) * 4, hipMemcpyHostToDevice));
+  std::vector<tn3d_net> sub(cnt);
+  for (int i = 0; i < cnt; ++i) sub[i] = nets[ties[i]];
+  int64_t* d_offs = reinterpret_cast<int64_t*>(c->aux + o_offs);
+  double* lps = reinterpret_cast<double*>(c->aux + o_lps);
+  uint32_t* fls = reinterpret_cast<uint32_t*>(c->aux + o_fls);
+  launch_gather_offsets(cnt, d_items, offs, d_offs, c->stream);
+  HIPCHK(c, hipMemsetAsync(fls, 0, size_t(cnt) * 4, c->stream));
+  tn3d_params p64;
+  tn3d_params_default(&p64, pr->chi, pr->chi_mps, TN3D_PREC_FP64);
+  p64.near_tie = pr->near_tie;
+  p64.workspace_bytes = pr->workspace_bytes;
+  const bool timing = c->timing;
+  c->timing = false;  // the timing figures stay those of the main pass
+  s = contract_impl(c, cnt, sub.data(), synd, d_offs, &p64, lps, fls);
+  c->timing = timing;
+  if (s != TN3D_OK) return s;
+  launch_scatter_resweep(cnt, d_items, lps, fls, lp, flags, c->stream);
+  c->last_resweeps = cnt;
+  return decide(c, cnt, nets, ties.data(), d_items, lp, pr->near_tie, coset, logratio, flags);
 }
 
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
@@ -658,10 +710,11 @@ tn3d_status tn3d_last_stats(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
   if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
   const double ns = c->stats_out[2] > 0 ? c->stats_out[2] : 1.0;
-  double v[6] = {0, c->stats_out[1], c->stats_out[2], c->stats_out[3] / ns, c->stats_out[4], c->stats_out[5]};
+  double v[7] = {0, c->stats_out[1], c->stats_out[2], c->stats_out[3] / ns, c->stats_out[4], c->stats_out[5],
+                 double(c->last_resweeps)};
   // mean over all bonds of all sweeps
   v[0] = c->stats_out[0] / (ns * (c->nb_last > 0 ? c->nb_last : 1));
-  for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
+  for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
   return TN3D_OK;
 }
 

@@ -80,6 +80,14 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
 void launch_zip_init(const ZipArgs& Z, hipStream_t st);
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
+// Near-tie FP64 re-sweep helpers: the items whose log-ratio is below
+// near_tie (or NaN), their syndrome offsets, and the write-back of the
+// re-swept rows (flags of the FP64 sweep plus the re-swept bit 16).
+void launch_pick_ties(int n_items, const double* logratio, double near_tie, int32_t* list, int32_t* count,
+                      hipStream_t st);
+void launch_gather_offsets(int n, const int32_t* items, const int64_t* offs, int64_t* out, hipStream_t st);
+void launch_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,
+                            double* logp, uint32_t* flags, hipStream_t st);
 void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,
                    int32_t* coset, double* logratio, uint32_t* flags, hipStream_t st);
 

@@ -890,6 +890,30 @@ __global__ void k_decode(int n_items, int n_cosets, const int32_t* items, const 
   if (flags && !(lr >= near_tie)) flags[it] |= 4u;
 }
 
+// Items whose decision is within the near-tie band (or not a number), for the
+// FP64 re-sweep; the list order is arbitrary (the host sorts it).
+__global__ void k_pick_ties(int n_items, const double* logratio, double near_tie, int32_t* list, int32_t* count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const double lr = logratio[i];
+  if (!(lr >= near_tie)) list[atomicAdd(count, 1)] = i;
+}
+
+__global__ void k_gather_offsets(int n, const int32_t* items, const int64_t* offs, int64_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = offs[items[i]];
+}
+
+// Results of the re-sweep (row i of logp_sub, flags_sub) back to items[i].
+__global__ void k_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,
+                                  double* logp, uint32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int it = items[i];
+  for (int c = 0; c < 4; ++c) logp[int64_t(it) * 4 + c] = logp_sub[int64_t(i) * 4 + c];
+  if (flags) flags[it] = flags_sub[i] | 16u;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1007,6 +1031,22 @@ void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t*
   if (flags_out)
     hipLaunchKernelGGL(k_collect_flags, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, A.n_cosets, A.items,
                        A.flags, flags_out);
+}
+
+void launch_pick_ties(int n_items, const double* logratio, double near_tie, int32_t* list, int32_t* count,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_pick_ties, dim3((n_items + 255) / 256), dim3(256), 0, st, n_items, logratio, near_tie, list,
+                     count);
+}
+
+void launch_gather_offsets(int n, const int32_t* items, const int64_t* offs, int64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_offsets, dim3((n + 255) / 256), dim3(256), 0, st, n, items, offs, out);
+}
+
+void launch_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,
+                            double* logp, uint32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_resweep, dim3((n + 255) / 256), dim3(256), 0, st, n, items, logp_sub, flags_sub, logp,
+                     flags);
 }
 
 void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,

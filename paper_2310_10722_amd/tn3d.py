@@ -22,6 +22,7 @@ FLAG_NUMERIC = 1
 FLAG_TRUNC_CLUSTER = 2
 FLAG_NEAR_TIE = 4
 FLAG_NO_CONVERGE = 8
+FLAG_RESWEPT = 16
 
 STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OOM", -5: "DEVICE",
           -6: "NUMERIC"}
@@ -153,8 +154,8 @@ class Context:
         return list(out)
 
     def last_stats(self):
-        out = (ctypes.c_double * 6)()
-        _check(self.lib, self.h, self.lib.tn3d_last_stats(self.h, out, 6))
+        out = (ctypes.c_double * 7)()
+        _check(self.lib, self.h, self.lib.tn3d_last_stats(self.h, out, 7))
         return list(out)
 
 

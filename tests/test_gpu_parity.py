@@ -165,3 +165,71 @@ def test_deterministic_and_empty(ctx):
     assert np.array_equal(a, b)
     e, f = gpu_logp(ctx, net, m[:0], prm)
     assert e.shape == (0, 4)
+
+
+def test_near_tie_fp64_resweep(ctx):
+    """FP32 decode with a wide near-tie band: exactly the items whose FP32
+    log-ratio falls inside it are contracted again in FP64 (same chi, FP64
+    rank rule) and then agree with the FP64 oracle to 1e-9; the others keep
+    the FP32 result (1e-3)."""
+    from paper_2310_10722_amd import tn3d
+    say("case: near-tie re-sweep, point sector L=3 p=0.15 chi=4 fp32, band 0.5")
+    dem, m, _, _ = synth.config_workload(1)
+    net = tn3d.tn3d_net_surface3d_point(ctx, 3, dem.p)
+    syn = torch.from_numpy(np.ascontiguousarray(m)).cuda()
+    p32 = tn3d.tn3d_params_default(4, 4, tn3d.PREC_FP32)
+    p32.near_tie = 0.0
+    _, lr32, _, _ = tn3d.tn3d_decode(ctx, net, syn, p32)
+    p32.near_tie = 0.5
+    coset, lr, logp, flags = tn3d.tn3d_decode(ctx, net, syn, p32)
+    torch.cuda.synchronize()
+    lr32, lr, logp, flags, coset = (t.cpu().numpy() for t in (lr32, lr, logp, flags, coset))
+    band = lr32 < 0.5
+    resw = (flags & tn3d.FLAG_RESWEPT) != 0
+    say("  re-swept", int(resw.sum()), "of", len(resw))
+    assert band.sum() > 0 and np.array_equal(resw, band)
+    p64 = tn3d.tn3d_params_default(4, 4, tn3d.PREC_FP64)
+    ref64 = oracle_point(dem, 3, m[band], p64)
+    assert np.max(np.abs(logp[band, :2] - ref64)) <= 1e-9
+    ref32 = oracle_point(dem, 3, m[~band], p32)
+    assert np.max(np.abs(logp[~band, :2] - ref32)) <= 1e-3
+    ref = np.empty((len(m), 2))
+    ref[band], ref[~band] = ref64, ref32
+    best = np.argmax(ref, axis=1)
+    agree = (coset == best) | (np.abs(ref[:, 0] - ref[:, 1]) <= 2e-3)
+    assert agree.all()
+    assert np.allclose(lr, np.abs(logp[:, 0] - logp[:, 1]))
+
+
+def test_rotated_d5_full_batch_sampled(ctx):
+    """The full 1024-syndrome batch of the rotated d=5 workload in one decode
+    call (the launch configuration of the benchmark), checked item by item
+    against the FP32-rule oracle on a sample spread over the batch."""
+    from paper_2310_10722_amd import tn3d
+    say("case: rotated d=5 T=5 chi=16 fp32, full batch of 1024, 24 sampled items")
+    dem, m, _, _ = synth.config_workload(2)
+    assert m.shape[0] == 1024
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP32)
+    coset, lr, logp, flags = tn3d.tn3d_decode(ctx, net, torch.from_numpy(m).cuda(), prm)
+    torch.cuda.synchronize()
+    coset, logp, flags = coset.cpu().numpy(), logp.cpu().numpy(), flags.cpu().numpy()
+    assert np.all(np.isfinite(logp[:, :2]).all(axis=1) | ((flags & tn3d.FLAG_NUMERIC) != 0))
+    idx = np.linspace(0, 1023, 24).astype(int)
+    ref = oracle_rot(dem, m[idx], prm)
+    err = np.abs(logp[idx, :2] - ref)
+    say("  max |d log p| =", err.max())
+    assert err.max() <= 1e-3
+    best = np.argmax(ref, axis=1)
+    assert np.all((coset[idx] == best) | (np.abs(ref[:, 0] - ref[:, 1]) <= 2e-3))
+
+
+def test_unsupported_width_is_refused(ctx):
+    """A gated site wider than the kernels hold (physical dim x chi > 64) is
+    refused with TN3D_E_UNSUPPORTED before any launch."""
+    from paper_2310_10722_amd import tn3d
+    dem, m, _, _ = synth.config_workload(2, n=2)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    prm = tn3d.tn3d_params_default(32, 32, tn3d.PREC_FP32)
+    with pytest.raises(tn3d.Tn3dError, match="UNSUPPORTED"):
+        gpu_logp(ctx, net, m, prm)
