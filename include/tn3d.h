@@ -156,25 +156,45 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
                         const tn3d_params* params, int32_t* coset_dev, double* logratio_dev,
                         double* logp_dev, uint32_t* flags_dev);
 
-/* Kernel-time breakdown of the last contraction on this context, measured
- * with HIP events on the context stream: out[0] = layer absorption (one-site
- * ops, Grams, truncations, reabsorption, rescaling), out[1] = final boundary
- * MPS, out[2] = Gram + reabsorption kernels only, out[3] = number of Gram +
- * reabsorption launches, out[4] = algorithmic bytes those launches moved
- * (each site tensor read by the Gram, read and written by the
- * reabsorption).  Milliseconds for times.  Returns TN3D_E_INVALID if timing
- * was not enabled with tn3d_ctx_set_timing. */
+/* Timing of the contractions on this context: enable = 0 off, 1 kernel times,
+ * 2 kernel times and bond statistics (tn3d_last_stats; this level copies the
+ * bond dimensions and lambdas of every sweep to the host after each call).
+ * Times come from device wall-clock stamps written by one-thread kernels
+ * enqueued between the launches, so they are taken on the context stream,
+ * inside captured graphs as well.  tn3d_last_timing: out[0] = layer
+ * absorption (one-site ops, Grams, truncations, reabsorption, rescaling),
+ * out[1] = final boundary MPS, out[2] = Gram + reabsorption kernels only,
+ * out[3] = number of Gram + reabsorption launches, out[4] = algorithmic bytes
+ * those launches moved (each site tensor read by the Gram, read and written
+ * by the reabsorption).  Milliseconds for times; n <= 5 values are written.
+ * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);
 
-/* Bond statistics of the last contraction with timing enabled, over all its
+/* Launch-sequence replay (on by default).  The first contraction of a chunk
+ * shape for a network, parameter set and timing level captures its whole
+ * kernel sequence into a HIP graph that reads and writes only the context
+ * workspace; later calls of the same shape copy the syndromes in, replay the
+ * graph and copy the results out, instead of issuing each launch.  Capture
+ * runs on a stream the context owns, so any caller stream (the legacy default
+ * one included) can replay.  Graphs are dropped when the workspace is
+ * reallocated, the network destroyed or replay switched off; if capture fails
+ * the context launches eagerly from then on.  Results are identical either
+ * way.  Errors: TN3D_E_INVALID (null ctx). */
+tn3d_status tn3d_ctx_set_graphs(tn3d_ctx ctx, int32_t enable);
+/* Number of captured launch sequences the context holds (0 when replay is
+ * off or capture was refused; setting TN3D_VERBOSE in the environment prints
+ * the reason of a refusal to stderr). */
+int32_t tn3d_ctx_graphs_cached(tn3d_ctx ctx);
+
+/* Bond statistics of the last contraction with timing level 2, over all its
  * sweeps, taken after the last layer: out[0] = mean bond dimension of the
  * swept 2D network, out[1] = largest, out[2] = number of sweeps, out[3] = mean
  * over sweeps of the smallest kept lambda (relative to its bond's largest),
  * out[4] = most Jacobi sweeps any truncation needed, out[5] = same for the
  * boundary MPS, out[6] = items the last tn3d_decode re-swept in FP64 (n <= 7
  * values are written).
- * Returns TN3D_E_INVALID if timing was not enabled. */
+ * Returns TN3D_E_INVALID if the timing level is below 2. */
 tn3d_status tn3d_last_stats(tn3d_ctx ctx, double* out, int32_t n);
 
 #ifdef __cplusplus

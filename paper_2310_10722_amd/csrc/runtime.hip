@@ -4,10 +4,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tn3d.h"
@@ -16,25 +19,52 @@
 
 using namespace tn3d;
 
+// A captured per-chunk launch sequence is valid for one network, parameter
+// set, chunk shape, timing mode and workspace allocation.
+struct GraphKey {
+  uint64_t net;
+  int prec, chi, chi_mps;
+  double eps, tau;
+  int ni;
+  int64_t chunk;
+  int timing;
+  char* ws;
+  size_t ws_bytes;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes) <
+           std::tie(o.net, o.prec, o.chi, o.chi_mps, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws, o.ws_bytes);
+  }
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec;
+  size_t hot_i;  // timing events the sequence records
+  double hot_l;  // Gram + reabsorption launches in it
+};
+
 struct tn3d_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  bool timing = false;
+  int timing = 0;                  // 1: kernel times, 2: also bond statistics
+  int wclk_khz = 100000;           // device wall-clock rate
   double timing_out[5] = {0, 0, 0, 0, 0};
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
   int last_resweeps = 0;           // items the last decode re-swept in FP64
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<hipEvent_t> hot_ev;  // pairs around Gram / reabsorption launches
   char* aux = nullptr;             // decode scratch
   size_t aux_bytes = 0;
+  bool graphs = true;              // replay captured launch sequences
+  hipStream_t cap_stream = nullptr;  // private stream the sequences are captured on
+  uint64_t next_serial = 1;
+  std::map<GraphKey, GraphEntry> gcache;
 };
 
 struct tn3d_net_s {
   tn3d_ctx ctx = nullptr;
+  uint64_t serial = 0;  // identifies the network in the context's graph cache
   Program P;
   char* dev = nullptr;  // one allocation holding every device array below
   DevOneSite* d_ones = nullptr;
@@ -126,6 +156,7 @@ tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* 
   tn3d_net n = new (std::nothrow) tn3d_net_s;
   if (!n) return fail(c, TN3D_E_OOM, "host allocation");
   n->ctx = c;
+  n->serial = c->next_serial++;
   n->P = std::move(P);
   tn3d_status s = upload_net(n);
   if (s != TN3D_OK) {
@@ -193,10 +224,23 @@ __global__ void k_iota(int32_t* out, int n, int base) {
   if (i < n) out[i] = base + i;
 }
 
+// Destroys the cached graphs of one network (net != 0) or all of them.
+void drop_graphs(tn3d_ctx c, uint64_t net) {
+  for (auto it = c->gcache.begin(); it != c->gcache.end();) {
+    if (net == 0 || it->first.net == net) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = c->gcache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 tn3d_status ensure_ws(tn3d_ctx c, size_t bytes) {
   if (c->ws_bytes >= bytes) return TN3D_OK;
   if (c->ws) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c, 0);
     (void)hipFree(c->ws);
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -265,7 +309,15 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_zS = cv.take<double>(nsw_max * 1024);
   size_t o_logm = cv.take<double>(nsw_max);
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
-  size_t o_ctr = cv.take<unsigned long long>(2);
+  // 64 byte counters (spread to keep atomics uncontended), then the sweep maxima
+  size_t o_ctr = cv.take<unsigned long long>(65);
+  const size_t n_stamp = 3 + P.layers.size() * 16;
+  size_t o_stamp = cv.take<unsigned long long>(n_stamp);
+  size_t o_gitems = cv.take<int32_t>(chunk_items);
+  size_t o_gsoff = cv.take<int64_t>(chunk_items);
+  size_t o_gsynd = cv.take<uint8_t>(chunk_items * std::max(1, P.n_det));
+  size_t o_glp = cv.take<double>(chunk_items * 4);
+  size_t o_gfl = cv.take<uint32_t>(chunk_items);
   tn3d_status st = ensure_ws(c, cv.off);
   if (st != TN3D_OK) return st;
   char* ws = c->ws;
@@ -276,7 +328,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   for (size_t i = 1; i < items.size(); ++i)
     if (items[i] != items[0] + int32_t(i)) contiguous = false;
 
-  const bool timing = c->timing;
+  const int timing = c->timing;
   float t_layers = 0, t_final = 0, t_hot = 0;
   double hot_launches = 0, hot_bytes = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
@@ -289,6 +341,10 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       HIPCHK(c, hipMemcpy(d_items, items.data() + i0, size_t(ni) * 4, hipMemcpyHostToDevice));
     }
     SweepArgs A{};
+    ZipArgs Z{};
+    size_t hot_i = 0;
+    double hot_l = 0;
+    // workspace-derived arguments (the same for eager launches and replays)
     A.n_sweeps = ni * nc;
     A.n_sites = P.Lx * P.Ly;
     A.n_bonds = P.n_bonds;
@@ -306,9 +362,6 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.logs = reinterpret_cast<double*>(ws + o_logs);
     A.flags = reinterpret_cast<uint32_t*>(ws + o_flags);
     A.leg_bond = n->d_leg_bond;
-    A.synd = synd;
-    A.synd_off = synd_off;
-    A.items = d_items;
     A.pool = n->d_pool;
     A.eps = pr.eps_rel;
     A.tau = pr.tau_gap;
@@ -316,13 +369,24 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.jtol = prec == TN3D_PREC_FP64 ? 1e-14 : 1e-10;
     A.jfloor = prec == TN3D_PREC_FP64 ? std::min(1e-13, 0.1 * pr.eps_rel) : std::min(1e-8, 0.1 * pr.eps_rel);
     A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
-    A.sweeps_max = reinterpret_cast<int32_t*>(ws + o_ctr + 8);
-    HIPCHK(c, hipMemsetAsync(ws + o_ctr, 0, 16, s));
+    A.sweeps_max = reinterpret_cast<int32_t*>(ws + o_ctr + 64 * 8);
+    // The whole per-chunk sequence; in graph mode it is captured once with the
+    // workspace copies of the inputs and outputs and replayed afterwards.
+    auto enqueue = [&](const int32_t* items_p, const uint8_t* synd_p, const int64_t* soff_p, double* logp_p,
+                       uint32_t* flags_p, hipStream_t st) -> tn3d_status {
+    const hipStream_t s = st;
+    hot_i = 0;
+    hot_l = 0;
+    Z = ZipArgs{};
+    A.synd = synd_p;
+    A.synd_off = soff_p;
+    A.items = items_p;
+    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 130, s);
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
-    if (timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
+    unsigned long long* stamp = reinterpret_cast<unsigned long long*>(ws + o_stamp);
+    if (timing) launch_stamp(stamp + 0, s);
     launch_init(prec, A, n->d_init_dims, n->d_init_off, n->d_bond_dim0, s);
-    size_t hot_i = 0;
     for (size_t li = 0; li < P.layers.size(); ++li) {
       const LayerRange& R = P.layers[li];
       launch_onesite(prec, A, n->d_ones + R.pre0, R.pre1 - R.pre0, s);
@@ -330,26 +394,25 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         const int ng = R.gate1[k] - R.gate0[k];
         if (ng <= 0) continue;
         const DevGate* gp = n->d_gates + R.gate0[k];
-        if (timing && hot_i + 1 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i], s));
+        if (timing) launch_stamp(stamp + 3 + hot_i, s);
         launch_gram(prec, A, gp, ng, gram, L.ncap, s);
-        if (timing && hot_i + 1 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 1], s));
+        if (timing) launch_stamp(stamp + 4 + hot_i, s);
         launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
-        if (timing && hot_i + 3 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 2], s));
+        if (timing) launch_stamp(stamp + 5 + hot_i, s);
         launch_reabsorb(prec, A, gp, ng, wbuf, L.ncap, s);
-        if (timing && hot_i + 3 < c->hot_ev.size()) HIPCHK(c, hipEventRecord(c->hot_ev[hot_i + 3], s));
+        if (timing) launch_stamp(stamp + 6 + hot_i, s);
         hot_i += 4;
-        hot_launches += 2;
+        hot_l += 2;
       }
       launch_onesite(prec, A, n->d_ones + R.post0, R.post1 - R.post0, s);
       launch_rescale(prec, A, n->d_d_after + li * A.n_sites, n->d_par_after + li * A.n_sites, s);
     }
     HIPCHK(c, hipGetLastError());
-    if (timing) HIPCHK(c, hipEventRecord(c->ev[1], s));
+    if (timing) launch_stamp(stamp + 1, s);
     const int32_t* par_final = n->d_par_after + (P.layers.size() - 1) * A.n_sites;
     double* fin = reinterpret_cast<double*>(ws + o_fin);
     launch_finalize(prec, A, n->d_d_final, n->d_f_off, par_final, fin, L.fin_stride,
                     reinterpret_cast<int64_t*>(ws + o_foff), s);
-    ZipArgs Z{};
     Z.n_sweeps = A.n_sweeps;
     Z.Lx = P.Lx;
     Z.Ly = P.Ly;
@@ -386,19 +449,83 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
       for (int x = 0; x < P.Lx; ++x) launch_zip_step(Z, x, y, s);
-    launch_finish(A, Z, logp, flags_out, s);
+    launch_finish(A, Z, logp_p, flags_p, s);
+    if (timing) launch_stamp(stamp + 2, s);
     HIPCHK(c, hipGetLastError());
+    return TN3D_OK;
+    };
+    bool done = false;
+    if (c->graphs) {
+      // inputs into the workspace, replay (capturing first if needed), results out
+      int32_t* g_items = reinterpret_cast<int32_t*>(ws + o_gitems);
+      int64_t* g_soff = reinterpret_cast<int64_t*>(ws + o_gsoff);
+      uint8_t* g_synd = reinterpret_cast<uint8_t*>(ws + o_gsynd);
+      double* g_lp = reinterpret_cast<double*>(ws + o_glp);
+      uint32_t* g_fl = reinterpret_cast<uint32_t*>(ws + o_gfl);
+      launch_gather_synd(ni, d_items, synd, synd_off, P.n_det, g_synd, s);
+      HIPCHK(c, hipGetLastError());
+      const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
+                         c->ws, c->ws_bytes};
+      auto it = c->gcache.find(key);
+      if (it == c->gcache.end()) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        tn3d_status es = TN3D_OK;
+        // captured on a private stream (the caller's may be the legacy default
+        // stream, which cannot be captured); replayed on the caller's
+        hipError_t ce = hipSuccess;
+        if (!c->cap_stream) ce = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (ce == hipSuccess) ce = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+          launch_seq(ni, g_items, g_soff, P.n_det, c->cap_stream);
+          es = enqueue(g_items, g_synd, g_soff, g_lp, g_fl, c->cap_stream);
+          ce = hipStreamEndCapture(c->cap_stream, &gr);
+        }
+        if (ce == hipSuccess && es == TN3D_OK && gr) ce = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (ce != hipSuccess || es != TN3D_OK || !ex) {
+          // capture is not available for this sequence: launch eagerly from now on
+          if (std::getenv("TN3D_VERBOSE"))
+            std::fprintf(stderr, "tn3d: launch capture failed (%s%s%s); launching eagerly\n",
+                         hipGetErrorString(ce), es != TN3D_OK ? "; " : "", es != TN3D_OK ? c->err.c_str() : "");
+          (void)hipGetLastError();
+          if (ex) (void)hipGraphExecDestroy(ex);
+          c->graphs = false;
+          c->err.clear();
+        } else {
+          it = c->gcache.emplace(key, GraphEntry{ex, hot_i, hot_l}).first;
+        }
+      }
+      if (c->graphs) {
+        HIPCHK(c, hipGraphLaunch(it->second.exec, s));
+        hot_i = it->second.hot_i;
+        hot_l = it->second.hot_l;
+        launch_scatter_out(ni, d_items, g_lp, g_fl, logp, flags_out, s);
+        HIPCHK(c, hipGetLastError());
+        done = true;
+      }
+    }
+    if (!done) {
+      tn3d_status es = enqueue(d_items, synd, synd_off, logp, flags_out, s);
+      if (es != TN3D_OK) return es;
+    }
+    hot_launches += hot_l;
     if (timing) {
-      HIPCHK(c, hipEventRecord(c->ev[2], s));
-      HIPCHK(c, hipEventSynchronize(c->ev[2]));
-      float a = 0, b = 0;
-      HIPCHK(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
-      HIPCHK(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
-      t_layers += a;
-      t_final += b;
-      unsigned long long nb = 0;
-      HIPCHK(c, hipMemcpy(&nb, A.bytes_ctr, 8, hipMemcpyDeviceToHost));
-      hot_bytes += double(nb);
+      // stamps: 0 start, 1 after the layers, 2 end; 3 + 4 g .. 6 + 4 g around
+      // the Gram and reabsorption launches of gate class g
+      std::vector<unsigned long long> st(3 + hot_i);
+      HIPCHK(c, hipMemcpyAsync(st.data(), ws + o_stamp, st.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      const double ms_per_tick = 1.0 / double(c->wclk_khz);
+      t_layers += double(st[1] - st[0]) * ms_per_tick;
+      t_final += double(st[2] - st[1]) * ms_per_tick;
+      for (size_t h = 0; h + 3 < hot_i; h += 4)
+        t_hot += double(st[3 + h + 1] - st[3 + h] + st[3 + h + 3] - st[3 + h + 2]) * ms_per_tick;
+      unsigned long long nb[64];
+      HIPCHK(c, hipMemcpy(nb, A.bytes_ctr, sizeof(nb), hipMemcpyDeviceToHost));
+      for (unsigned long long v : nb) hot_bytes += double(v);
+    }
+    if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
       std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
       HIPCHK(c, hipMemcpy(bd.data(), A.bond_dim, bd.size() * 4, hipMemcpyDeviceToHost));
@@ -419,12 +546,6 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       c->stats_out[4] = std::max(c->stats_out[4], double(smax[0]));
       c->stats_out[5] = std::max(c->stats_out[5], double(smax[1]));
       c->nb_last = P.n_bonds;
-      for (size_t h = 0; h + 3 < hot_i && h + 3 < c->hot_ev.size(); h += 4) {
-        float g = 0, r = 0;
-        HIPCHK(c, hipEventElapsedTime(&g, c->hot_ev[h], c->hot_ev[h + 1]));
-        HIPCHK(c, hipEventElapsedTime(&r, c->hot_ev[h + 2], c->hot_ev[h + 3]));
-        t_hot += g + r;
-      }
     }
   }
   if (timing) {
@@ -480,13 +601,6 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
   if (c->timing) {
     for (int k = 0; k < 5; ++k) c->timing_out[k] = 0;
     for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
-    size_t need = 0;
-    for (int i = 0; i < batch; ++i) need = std::max(need, nets[i]->P.layers.size() * 16 + 4);
-    while (c->hot_ev.size() < need) {
-      hipEvent_t e;
-      HIPCHK(c, hipEventCreate(&e));
-      c->hot_ev.push_back(e);
-    }
   }
   std::map<tn3d_net, std::vector<int32_t>> groups;
   std::vector<tn3d_net> order;
@@ -536,11 +650,15 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
   if (!c) return TN3D_E_OOM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
-  for (auto& e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
-      delete c;
-      return TN3D_E_DEVICE;
-    }
+  bool ok = set_kernel_lds_limits() == hipSuccess;
+  int rate = 0;
+  ok = ok && hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0;
+  if (!ok) {
+    (void)hipGetLastError();
+    delete c;
+    return TN3D_E_DEVICE;
+  }
+  c->wclk_khz = rate;
   *out = c;
   return TN3D_OK;
 }
@@ -552,10 +670,9 @@ void tn3d_ctx_destroy(tn3d_ctx c) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->ws);
   }
-  for (auto& e : c->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (auto& e : c->hot_ev) (void)hipEventDestroy(e);
   if (c->aux) (void)hipFree(c->aux);
+  drop_graphs(c, 0);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -593,9 +710,23 @@ void tn3d_net_destroy(tn3d_net n) {
   if (n->dev) {
     (void)hipSetDevice(n->ctx->device);
     (void)hipStreamSynchronize(n->ctx->stream);
+    drop_graphs(n->ctx, n->serial);
     (void)hipFree(n->dev);
   }
   delete n;
+}
+
+int32_t tn3d_ctx_graphs_cached(tn3d_ctx c) { return c ? int32_t(c->gcache.size()) : 0; }
+
+tn3d_status tn3d_ctx_set_graphs(tn3d_ctx c, int32_t enable) {
+  if (!c) return TN3D_E_INVALID;
+  (void)hipSetDevice(c->device);
+  if (!enable) {
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c, 0);
+  }
+  c->graphs = enable != 0;
+  return TN3D_OK;
 }
 
 tn3d_status tn3d_contract_cosets(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
@@ -702,13 +833,13 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
 
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   if (!c) return TN3D_E_INVALID;
-  c->timing = enable != 0;
+  c->timing = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
   return TN3D_OK;
 }
 
 tn3d_status tn3d_last_stats(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
-  if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
+  if (c->timing < 2) return fail(c, TN3D_E_INVALID, "bond statistics need timing level 2");
   const double ns = c->stats_out[2] > 0 ? c->stats_out[2] : 1.0;
   double v[7] = {0, c->stats_out[1], c->stats_out[2], c->stats_out[3] / ns, c->stats_out[4], c->stats_out[5],
                  double(c->last_resweeps)};

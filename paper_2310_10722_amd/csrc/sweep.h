@@ -28,7 +28,7 @@ struct SweepArgs {
   const double* pool;       // op matrices and initial tensors
   double eps, tau, pchol_tol;
   double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
-  unsigned long long* bytes_ctr;
+  unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
 };
 
@@ -62,6 +62,10 @@ struct ZipArgs {
   double* zS;               // [sweep][1024] singular values of the step
 };
 
+// Raises the dynamic-LDS limits of the kernels that need more than 64 KB;
+// call once per device before any launch (and outside stream capture).
+hipError_t set_kernel_lds_limits();
+
 // Launchers (all enqueue on `st`).  T: 0 = double, 1 = float storage.
 void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
                  const int32_t* bond_dim0, hipStream_t st);
@@ -80,6 +84,17 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
 void launch_zip_init(const ZipArgs& Z, hipStream_t st);
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
+// Graph replay helpers: gather each item's syndrome into a dense buffer,
+// local item indices with their offsets, zero a counter block (no memset
+// node in a captured graph), and scatter the local results to the caller.
+void launch_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
+                        uint8_t* out, hipStream_t st);
+void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_t st);
+// Writes the device wall clock (hipDeviceAttributeWallClockRate ticks) to *out.
+void launch_stamp(unsigned long long* out, hipStream_t st);
+void launch_zero_words(uint32_t* p, int n, hipStream_t st);
+void launch_scatter_out(int n, const int32_t* items, const double* lp_local, const uint32_t* fl_local, double* logp,
+                        uint32_t* flags, hipStream_t st);
 // Near-tie FP64 re-sweep helpers: the items whose log-ratio is below
 // near_tie (or NaN), their syndrome offsets, and the write-back of the
 // re-swept rows (flags of the FP64 sweep plus the re-swept bit 16).

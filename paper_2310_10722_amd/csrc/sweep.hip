@@ -237,7 +237,8 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
       }
   }
   if (A.bytes_ctr && tid == 0)
-    atomicAdd(A.bytes_ctr, (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
+    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
+              (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
   double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
   if (act)
 #pragma unroll
@@ -431,7 +432,8 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
   const T* in = tens<T>(A, par, sweep, site);
   T* out = tens<T>(A, par ^ 1, sweep, site);
   if (A.bytes_ctr && tid == 0)
-    atomicAdd(A.bytes_ctr, (unsigned long long)(int64_t(v.rows) * (nin + nout) * int64_t(sizeof(T))));
+    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
+              (unsigned long long)(int64_t(v.rows) * (nin + nout) * int64_t(sizeof(T))));
   const int n4 = nst / 4;
   for (int r = tid; r < v.rows; r += 64) {
     const int a = r / v.Cp, c = r - a * v.Cp;
@@ -914,20 +916,65 @@ __global__ void k_scatter_resweep(int n, const int32_t* items, const double* log
   if (flags) flags[it] = flags_sub[i] | 16u;
 }
 
+// Device wall-clock stamp, for timing that also works inside a captured graph
+// (events recorded in a graph cannot be read back as elapsed times).
+__global__ void k_stamp(unsigned long long* out) {
+  if (threadIdx.x == 0) *out = wall_clock64();
+}
+
+// Graph replay support: the captured sequence reads and writes only
+// workspace buffers, filled and drained by these kernels outside it.
+__global__ void k_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
+                              uint8_t* out) {
+  const int i = blockIdx.y;
+  const int64_t src = offs[items[i]];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_det; k += gridDim.x * blockDim.x)
+    out[int64_t(i) * n_det + k] = synd[src + k];
+}
+
+__global__ void k_seq(int n, int32_t* items, int64_t* offs, int64_t stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    items[i] = i;
+    offs[i] = int64_t(i) * stride;
+  }
+}
+
+__global__ void k_zero_words(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_scatter_out(int n, const int32_t* items, const double* lp_local, const uint32_t* fl_local,
+                              double* logp, uint32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int it = items[i];
+  for (int c = 0; c < 4; ++c) logp[int64_t(it) * 4 + c] = lp_local[int64_t(i) * 4 + c];
+  if (flags) flags[it] = fl_local[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// Raise a kernel's dynamic-LDS limit to what a launch needs when that exceeds
-// the default.  A refused request is cleared here, so that the launch itself
-// reports the failure instead of a later unrelated check.
-static void need_dyn_lds(const void* f, size_t bytes, size_t& granted) {
-  if (bytes <= granted || bytes <= 64 * 1024) return;
-  if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess)
-    granted = bytes;
-  else
-    (void)hipGetLastError();
+// Dynamic-LDS limits of the kernels that can need more than the default
+// 64 KB, set once per device to the most any launch requests (static LDS
+// included stays within the 160 KB of a workgroup).  Setting attributes is not
+// allowed while a stream is being captured, so no launcher does it.
+hipError_t set_kernel_lds_limits() {
+  const int kmax = 64;  // gate rank x chi, checked by the host
+  const int solve = 4 * kmax * kmax * 8 + 2 * kmax * 8 + 32 + (2 * kmax + 4) * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, solve);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            18432 * 8);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            19200 * 8);
+  return e;
 }
 
 void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
@@ -969,8 +1016,6 @@ void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const doubl
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
   const size_t lds = size_t(4) * kdcap * kdcap * 8 + size_t(2) * kdcap * 8 + 32 + size_t(2 * kdcap + 4) * 4;
-  static size_t granted = 0;
-  need_dyn_lds(reinterpret_cast<const void*>(k_solve), lds, granted);
   hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), lds, st, A, gates, n_g, gin, wout, ncap);
 }
 
@@ -1010,9 +1055,6 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
-  static size_t granted_b = 0, granted_big = 0;
-  need_dyn_lds(reinterpret_cast<const void*>(k_zip_b), size_t(18432) * 8, granted_b);
-  need_dyn_lds(reinterpret_cast<const void*>(k_zip_bbig), size_t(19200) * 8, granted_big);
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
@@ -1031,6 +1073,30 @@ void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t*
   if (flags_out)
     hipLaunchKernelGGL(k_collect_flags, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, A.n_cosets, A.items,
                        A.flags, flags_out);
+}
+
+void launch_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
+                        uint8_t* out, hipStream_t st) {
+  if (n <= 0 || n_det <= 0) return;
+  hipLaunchKernelGGL(k_gather_synd, dim3((n_det + 255) / 256, n), dim3(256), 0, st, n, items, synd, offs, n_det, out);
+}
+
+void launch_stamp(unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, st, out);
+}
+
+void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_t st) {
+  hipLaunchKernelGGL(k_seq, dim3((n + 255) / 256), dim3(256), 0, st, n, items, offs, stride);
+}
+
+void launch_zero_words(uint32_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+}
+
+void launch_scatter_out(int n, const int32_t* items, const double* lp_local, const uint32_t* fl_local, double* logp,
+                        uint32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_out, dim3((n + 255) / 256), dim3(256), 0, st, n, items, lp_local, fl_local, logp,
+                     flags);
 }
 
 void launch_pick_ties(int n_items, const double* logratio, double near_tie, int32_t* list, int32_t* count,

@@ -33,6 +33,7 @@ SYMBOLS = [
     "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_last_stats",
+    "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached",
 ]
 
 
@@ -79,11 +80,14 @@ def load_library(path: str | None = None):
     lib.tn3d_decode.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params), c_p, c_p, c_p,
                                 c_p]
     lib.tn3d_ctx_set_timing.argtypes = [c_p, i32]
+    lib.tn3d_ctx_set_graphs.argtypes = [c_p, i32]
+    lib.tn3d_ctx_graphs_cached.argtypes = [c_p]
+    lib.tn3d_ctx_graphs_cached.restype = i32
     lib.tn3d_last_timing.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_contract_cosets",
-              "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing"):
+              "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_ctx_set_graphs"):
         getattr(lib, f).restype = i32
     if path is None:
         _lib = lib
@@ -145,8 +149,15 @@ class Context:
         except Exception:
             pass
 
-    def set_timing(self, on: bool = True):
-        _check(self.lib, self.h, self.lib.tn3d_ctx_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, level=True):
+        """0/False off, 1/True kernel times, 2 times and bond statistics."""
+        _check(self.lib, self.h, self.lib.tn3d_ctx_set_timing(self.h, int(level)))
+
+    def set_graphs(self, on: bool = True):
+        _check(self.lib, self.h, self.lib.tn3d_ctx_set_graphs(self.h, 1 if on else 0))
+
+    def graphs_cached(self) -> int:
+        return int(self.lib.tn3d_ctx_graphs_cached(self.h))
 
     def last_timing(self):
         out = (ctypes.c_double * 5)()

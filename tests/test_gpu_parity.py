@@ -233,3 +233,38 @@ def test_unsupported_width_is_refused(ctx):
     prm = tn3d.tn3d_params_default(32, 32, tn3d.PREC_FP32)
     with pytest.raises(tn3d.Tn3dError, match="UNSUPPORTED"):
         gpu_logp(ctx, net, m, prm)
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Captured launch sequences: the first call of a shape captures, later
+    calls replay.  Every replay, with other device work and synchronisations
+    in between, equals the eager launches bit for bit; a new batch size
+    captures a new graph; timing mode (stamp kernels in the sequence)
+    replays too."""
+    from paper_2310_10722_amd import tn3d
+    say("case: graph replay vs eager, rotated d=5 chi=16 fp32")
+    dem, m, _, _ = synth.config_workload(2, n=40)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP32)
+    eager = tn3d.Context(0)
+    eager.set_graphs(False)
+    net_e = tn3d.tn3d_net_rotated_phenom(eager, 5, 5, dem.p)
+    assert eager.graphs_cached() == 0
+    for n in (40, 17):
+        ref, ref_f = gpu_logp(eager, net_e, m[:n], prm)
+        for rep in range(3):
+            got, got_f = gpu_logp(ctx, net, m[:n], prm)
+            x = torch.randn(256, 256, device="cuda:0")
+            (x @ x).sum().item()
+            torch.cuda.synchronize()
+            assert np.array_equal(got, ref) and np.array_equal(got_f, ref_f), (n, rep)
+            assert ctx.graphs_cached() >= 1
+    ctx.set_timing(1)  # stamps are captured with the sequence: a new graph, same results
+    n0 = ctx.graphs_cached()
+    for rep in range(2):
+        got, _ = gpu_logp(ctx, net, m[:17], prm)
+        assert np.array_equal(got, gpu_logp(eager, net_e, m[:17], prm)[0])
+        t = ctx.last_timing()
+        assert t[0] > 0 and t[1] > 0 and 0 < t[2] < t[0] and t[3] > 0 and t[4] > 0
+    assert ctx.graphs_cached() == n0 + 1
+    ctx.set_timing(0)
