@@ -212,7 +212,7 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;
   b += P.n_bonds * (4 + 8 + 8 * size_t(chi)) + P.Lx * P.Ly * 8 + 4;
-  b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8;
+  b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8 + size_t(max_g) * 4;
   b += L.fin_stride * 8;
   b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + L.jcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
   L.per_sweep_bytes = b + 64 * 20;
@@ -295,6 +295,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_flags = cv.take<uint32_t>(nsw_max);
   size_t o_gram = cv.take<double>(nsw_max * max_g * 2 * L.ncap * L.ncap);
   size_t o_w = cv.take<double>(nsw_max * max_g * 2 * (2 + L.ncap * L.ncap));
+  size_t o_gn = cv.take<int32_t>(nsw_max * max_g);
   size_t o_fin = cv.take<double>(nsw_max * L.fin_stride);
   size_t o_mps0 = cv.take<double>(nsw_max * P.Lx * L.mcap);
   size_t o_mps1 = cv.take<double>(nsw_max * P.Lx * L.mcap);
@@ -370,6 +371,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.jfloor = prec == TN3D_PREC_FP64 ? std::min(1e-13, 0.1 * pr.eps_rel) : std::min(1e-8, 0.1 * pr.eps_rel);
     A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
     A.sweeps_max = reinterpret_cast<int32_t*>(ws + o_ctr + 64 * 8);
+    A.gate_n = reinterpret_cast<int32_t*>(ws + o_gn);
     // The whole per-chunk sequence; in graph mode it is captured once with the
     // workspace copies of the inputs and outputs and replayed afterwards.
     auto enqueue = [&](const int32_t* items_p, const uint8_t* synd_p, const int64_t* soff_p, double* logp_p,

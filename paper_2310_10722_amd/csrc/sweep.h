@@ -30,6 +30,7 @@ struct SweepArgs {
   double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
   unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
+  int32_t* gate_n;                // [sweep][gate of the class] K D before the gate (set by the Gram)
 };
 
 struct ZipArgs {

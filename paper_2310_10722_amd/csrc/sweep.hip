@@ -156,8 +156,11 @@ constexpr int GTR = 16;  // rows per tile of the Gram kernel
 // thread keeps at most NMAX accumulators in registers and the loops over the
 // block are uniform.  Tiles of GTR rows are staged in LDS with the row weights
 // applied; columns beyond ncols are zero.
+// A launch handles the Grams whose column block cw lies in (cwlo, NMAX]: a
+// variant with few accumulators (more waves per SIMD) takes the narrow Grams.
 template <typename T, int NMAX>
-__global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap) {
+__global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
+                                             int cwlo) {
   const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
@@ -169,9 +172,10 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   const int ngrp = ncols <= 64 ? 64 / ncols : 1;
   const int cw = (ncols + ngrp - 1) / ngrp;
   const int tw = ngrp * cw;  // tile width (>= ncols, padded with zeros)
+  if (cw <= cwlo || cw > NMAX) return;
   __shared__ double slam[4][MAXCHI];
-  __shared__ double tile[GTR * NMAX];  // tw <= 64 when ncols <= 64
-  __shared__ int colofs[NMAX];
+  __shared__ double tile[GTR * 64];  // tw <= 64 when ncols <= 64
+  __shared__ int colofs[64];
   __shared__ int rowbase[GTR];
   __shared__ double rowsc[GTR];
   for (int e = tid; e < 4 * MAXCHI; e += 64) {
@@ -239,6 +243,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   if (A.bytes_ctr && tid == 0)
     atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
               (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
+  if (side == 0 && tid == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
   double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
   if (act)
 #pragma unroll
@@ -278,14 +283,20 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
   }
 }
 
+// Gates with nlo < K D <= nhi only: the launch's LDS holds matrices of order
+// nhi, so small gates run in a launch with small LDS and many workgroups per CU.
 __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
-                                              double* wout, int ncap) {
+                                              double* wout, int ncap, int nlo, int nhi) {
   extern __shared__ double sm[];
   const int gi = blockIdx.x, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
   const int64_t bidx = int64_t(sweep) * A.n_bonds + g.bond;
   const int D = A.bond_dim[bidx];
   const int K = g.K, dA = g.dA, dB = g.dB, n = K * D;
+  // the size class is decided on the order the Gram recorded (the other
+  // launch of the pair may already have changed this bond's dimension)
+  const int n0 = A.gate_n[int64_t(sweep) * n_g + gi];
+  if (n0 <= nlo || n0 > nhi) return;
   double* ZA = sm;
   double* ZB = ZA + n * n;
   double* CM = ZB + n * n;
@@ -1000,7 +1011,9 @@ template <typename T>
 static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
                           hipStream_t st) {
   // ncap <= 64 is checked by the host before any launch
-  hipLaunchKernelGGL((k_gram<T, 64>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap);
+  hipLaunchKernelGGL((k_gram<T, 16>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
+  if (ncap > 32)
+    hipLaunchKernelGGL((k_gram<T, 64>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 16);
 }
 
 void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
@@ -1012,11 +1025,20 @@ void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, do
     gram_dispatch<float>(A, gates, n_g, gout, ncap, st);
 }
 
+static size_t solve_lds(int n) {
+  return size_t(4) * n * n * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
+}
+
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
-  const size_t lds = size_t(4) * kdcap * kdcap * 8 + size_t(2) * kdcap * 8 + 32 + size_t(2 * kdcap + 4) * 4;
-  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), lds, st, A, gates, n_g, gin, wout, ncap);
+  // two size classes: order <= 16 (8 KB of LDS) and the rest up to kdcap
+  const int nsmall = kdcap < 16 ? kdcap : 16;
+  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin, wout,
+                     ncap, 0, nsmall);
+  if (kdcap > nsmall)
+    hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(kdcap), st, A, gates, n_g, gin, wout,
+                       ncap, nsmall, kdcap);
 }
 
 void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
