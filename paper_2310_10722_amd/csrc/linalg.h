@@ -611,37 +611,59 @@ __device__ __forceinline__ void tri_solve(int n, const double* U, double* Y, int
   for (int r = 0; r < n; ++r) Y[r * ys + j] *= sc;
 }
 
-// Modified Gram-Schmidt over the D vectors of Y in order (lane j owns vector j).
-__device__ __forceinline__ void wave_mgs(int n, int D, double* Y, int ys) {
+// Orthonormalises the D vectors of Y in order, Y <- Y R^-1 with R^T R = Y^T Y
+// (Cholesky QR: vector j keeps the part of itself orthogonal to vectors
+// 0..j-1, as in Gram-Schmidt).  Lane j forms column j of the Gram matrix,
+// the factorisation runs by rows of R, and lane r then solves row r of Y
+// against R; ys should be odd so that both the column and the row accesses of
+// Y avoid LDS bank conflicts.  R: ys * ys doubles of LDS.  A vector that is
+// dependent on its predecessors (pivot below 1e-28 of its squared norm) is
+// left unnormalised and unused by the later ones.  One pass loses about
+// eps * cond(Y)^2 of orthogonality; call it twice.
+__device__ void wave_cholqr(int n, int D, double* Y, int ys, double* R) {
   const int j = threadIdx.x;
-  for (int c = 0; c < D; ++c) {
-    if (j == c) {
-      double ss = 0.0;
-      for (int r = 0; r < n; ++r) ss += Y[r * ys + c] * Y[r * ys + c];
-      const double sc = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
-      for (int r = 0; r < n; ++r) Y[r * ys + c] *= sc;
+  double gjj = 0.0;  // squared norm of vector j, for the breakdown test
+  if (j < D)
+    for (int i = 0; i <= j; ++i) {
+      double g = 0.0;
+      for (int r = 0; r < n; ++r) g += Y[r * ys + i] * Y[r * ys + j];
+      R[i * ys + j] = g;
+      gjj = g;
     }
+  __syncthreads();
+  for (int k = 0; k < D; ++k) {
+    const double g0 = R[k * ys + k];
+    const bool ok = g0 > 1e-28 * wave_bcast(gjj, k) && g0 > 0.0;
+    const double rkk = ok ? sqrt(g0) : 1.0;
     __syncthreads();
-    if (j > c && j < D) {
-      double dot = 0.0;
-      for (int r = 0; r < n; ++r) dot += Y[r * ys + j] * Y[r * ys + c];
-      for (int r = 0; r < n; ++r) Y[r * ys + j] -= dot * Y[r * ys + c];
+    if (j >= k && j < D) R[k * ys + j] = j == k ? rkk : (ok ? R[k * ys + j] / rkk : 0.0);
+    __syncthreads();
+    if (j > k && j < D) {
+      const double rkj = R[k * ys + j];
+      for (int i = k + 1; i <= j; ++i) R[i * ys + j] -= R[k * ys + i] * rkj;
     }
     __syncthreads();
   }
+  if (j < n)
+    for (int c = 0; c < D; ++c) {
+      double v = Y[j * ys + c];
+      for (int i = 0; i < c; ++i) v -= Y[j * ys + i] * R[i * ys + c];
+      Y[j * ys + c] = v / R[c * ys + c];
+    }
+  __syncthreads();
 }
 
 // Eigenvectors of T for lam[0..D) (D <= 64) by inverse iteration: lane j
 // factors T - lam_j I by Gaussian elimination with partial pivoting (pivots
-// below tiny = 4 ulp * nrm raised to tiny) and solves three times from a
-// pseudo-random start; the D vectors are orthonormalised by modified
-// Gram-Schmidt (twice), solved once more (which removes what the
-// orthogonalisation of a nearly dependent member of a cluster amplified
-// outside the cluster) and orthonormalised again.  Vector j is
-// Y[r * ys + j] (LDS); de: 2 * 64 doubles of LDS; U: 5 * n * ys doubles of
-// scratch private to each lane.
+// below tiny = 4 ulp * nrm raised to tiny) and solves twice from a
+// pseudo-random start; the D vectors are orthonormalised (Cholesky QR, twice),
+// solved once more (which removes what the orthogonalisation of a nearly
+// dependent member of a cluster amplified outside the cluster) and
+// orthonormalised again.  Vector j is Y[r * ys + j] (LDS, ys odd); R: ys * ys
+// doubles of LDS; de: 2 * 64 doubles of LDS; U: 5 * n * ys doubles of scratch
+// private to each lane.
 __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm, const double* lam, double* de,
-                                 double* Y, int ys, double* U) {
+                                 double* Y, int ys, double* R, double* U) {
   const int j = threadIdx.x;
   if (j < n) {
     de[2 * j] = dr;
@@ -694,14 +716,15 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
       h ^= h >> 15;
       Y[r * ys + j] = double(h >> 8) * (1.0 / 16777216.0) - 0.5;
     }
-    for (int it = 0; it < 3; ++it) tri_solve(n, U, Y, ys, j);
+    for (int it = 0; it < 2; ++it) tri_solve(n, U, Y, ys, j);
   }
   __syncthreads();
-  wave_mgs(n, D, Y, ys);
-  wave_mgs(n, D, Y, ys);
+  wave_cholqr(n, D, Y, ys, R);
+  wave_cholqr(n, D, Y, ys, R);
   if (j < D) tri_solve(n, U, Y, ys, j);
   __syncthreads();
-  wave_mgs(n, D, Y, ys);
+  wave_cholqr(n, D, Y, ys, R);
+  wave_cholqr(n, D, Y, ys, R);
 }
 
 // x <- Q x for the D vectors of Y (lane j owns vector j), Q = H_0 ... H_{n-3}

@@ -51,7 +51,7 @@ struct ZipArgs {
   double* Jm;               // [sweep][jcap] Jacobi vectors (FP64) / solver scratch (FP32)
   int64_t bigcap;
   int64_t jcap;
-  int32_t eig_ys;           // FP32: row stride of the eigenvector block, >= min(chi_m, 64)
+  int32_t eig_ys;           // FP32: row stride of the eigenvector block, odd, >= min(chi_m, 64)
   double* logm;             // [sweep]
   uint32_t* flags;
   double eps, tau;

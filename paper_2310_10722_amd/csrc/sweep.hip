@@ -698,7 +698,7 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
 // the tridiagonal reduction overwrite the Gram; the kept vectors sit in LDS
 // (row stride eig_ys) and are copied to Fv.
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
-  extern __shared__ double zsm[];  // 64 * eig_ys
+  extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
   __shared__ double vw[128], tri[128], de[128], xs[64], lam[64];
   __shared__ int cs[64];
   const int s = blockIdx.x, tid = threadIdx.x;
@@ -720,7 +720,7 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   const bool bad = Dn < 1;
   if (bad) Dn = 1;
   const int ys = Z.eig_ys;
-  wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, Z.Jm + int64_t(s) * Z.jcap);
+  wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, zsm + 64 * ys, Z.Jm + int64_t(s) * Z.jcap);
   wave_tri_backtransform(G, br, nv, Dn, zsm, ys);
   double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   for (int e = tid; e < nv * Dn; e += 64) Fv[e] = zsm[(e / Dn) * ys + e % Dn];
@@ -1080,7 +1080,8 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
-      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64) * Z.eig_ys * 8, st, Z, x, y);
+      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64 + Z.eig_ys) * Z.eig_ys * 8, st, Z, x,
+                         y);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
