@@ -400,6 +400,33 @@ __device__ __forceinline__ int wave_first(bool pred) {
   return m ? __builtin_ctzll(m) : 64;
 }
 
+// v moved across lanes by a DPP pattern (a compile-time dpp_ctrl code).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes, the same value in every lane: butterflies within each
+// row of 16 lanes (quad permutations, half-row and row mirrors), then the four
+// row sums read out in a fixed order.  Every lane must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (wave_bcast(v, 0) + wave_bcast(v, 16)) + (wave_bcast(v, 32) + wave_bcast(v, 48));
+}
+
+// 1 / q from the hardware reciprocal and two Newton steps (a few ulps).
+__device__ __forceinline__ double approx_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
 __device__ __forceinline__ double wave_min(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
   return v;
@@ -438,7 +465,7 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
       if (j == k) ak = a[j];
     const bool act = own && i > k;
     double v = act ? ak : 0.0;
-    const double sigma = team_sum(v * v, 64);
+    const double sigma = wave_sum(v * v);
     const double x0 = wave_bcast(v, k + 1);
     if (!(sigma > 0.0) || sigma - x0 * x0 <= 1e-300) {
       if (i == k) {
@@ -458,11 +485,11 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
     vw[2 * i] = v;
     __syncthreads();
     // p = bk A v, K = bk/2 p.v, w = p - K v; A <- A - v w^T - w v^T
-    double p = 0.0;
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: no single 64-long chain
 #pragma unroll
-    for (int j = J0; j < 64; ++j) p += a[j] * vw[2 * j];
-    p *= bk;
-    const double K = 0.5 * bk * team_sum(p * v, 64);
+    for (int j = J0; j < 64; ++j) p4[j & 3] += a[j] * vw[2 * j];
+    const double p = ((p4[0] + p4[1]) + (p4[2] + p4[3])) * bk;
+    const double K = 0.5 * bk * wave_sum(p * v);
     const double w = act ? p - K * v : 0.0;
     vw[2 * i + 1] = w;
     __syncthreads();
@@ -507,25 +534,33 @@ __device__ void wave_tridiag(const double* G, double gs, int n, double* vw, doub
   }
 }
 
-// Number of eigenvalues of T below x: negative pivots of T - x I (Sturm
-// sequence), tri[2i] = d_i, tri[2i+1] = e_{i-1}^2 (e_{-1} = 0).  Pivots
-// smaller than pivmin in magnitude are replaced by -pivmin.
-__device__ __forceinline__ int sturm_count(const double* tri, int n, double x, double pivmin) {
-  int c = 0;
-  double q = 1.0;
+// Numbers of eigenvalues of T below xa and below xb: negative pivots of
+// T - x I (Sturm sequences), the two recurrences interleaved.  tri[2i] = d_i,
+// tri[2i+1] = e_{i-1}^2 (e_{-1} = 0), read by all lanes at the same LDS
+// address.  Pivots smaller than pivmin in
+// magnitude are replaced by -pivmin; 1/q is the approximate reciprocal, whose
+// few-ulp error perturbs the count like a relative change of e^2 of that size.
+__device__ __forceinline__ void sturm_count2(const double* tri, int n, double xa, double xb, double pivmin, int& ca,
+                                             int& cb) {
+  ca = 0;
+  cb = 0;
+  double qa = 1.0, qb = 1.0;
   for (int r = 0; r < n; ++r) {
-    q = (tri[2 * r] - x) - tri[2 * r + 1] / q;
-    if (fabs(q) <= pivmin) q = -pivmin;
-    c += q < 0.0 ? 1 : 0;
+    const double d = tri[2 * r], e2 = tri[2 * r + 1];
+    qa = (d - xa) - e2 * approx_rcp(qa);
+    qb = (d - xb) - e2 * approx_rcp(qb);
+    if (fabs(qa) <= pivmin) qa = -pivmin;
+    if (fabs(qb) <= pivmin) qb = -pivmin;
+    ca += qa < 0.0 ? 1 : 0;
+    cb += qb < 0.0 ? 1 : 0;
   }
-  return c;
 }
 
 // The K (<= n) largest eigenvalues of T (lane i holds d_i, e_i) into lam[0..K)
 // in decreasing order, by multisection of the Gershgorin interval: g = 64 / K
-// lanes (at most 3) share an eigenvalue and each evaluates one interior point
+// lanes (at most 3) share an eigenvalue and each evaluates two interior points
 // per round, until the bracket is within a few ulps of the eigenvalue or of
-// the norm of T.  tri: 2 * 64 doubles, xs: 64 doubles, cs: 64 ints (LDS).
+// the norm of T.  tri: 2 * 64 doubles, xs: 128 doubles, cs: 128 ints (LDS).
 // Returns the norm bound max |Gershgorin end|.
 __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri, double* xs, int* cs, double* lam) {
   const int i = threadIdx.x;
@@ -549,17 +584,22 @@ __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri,
   const int t = i / g, r = i - t * g;
   const bool act = t < K;
   const int sidx = n - 1 - t;  // position of the target in ascending order
+  const int npt = 2 * g;       // points per eigenvalue and round
   for (int it = 0; it < 128; ++it) {
-    const double x = lo + (hi - lo) * double(r + 1) / double(g + 1);
-    const int c = sturm_count(tri, n, x, pivmin);
-    xs[i] = x;
-    cs[i] = c;
+    const double w = (hi - lo) / double(npt + 1);
+    const double xa = lo + w * double(2 * r + 1), xb = lo + w * double(2 * r + 2);
+    int ca, cb;
+    sturm_count2(tri, n, xa, xb, pivmin, ca, cb);
+    xs[2 * i] = xa;
+    xs[2 * i + 1] = xb;
+    cs[2 * i] = ca;
+    cs[2 * i + 1] = cb;
     __syncthreads();
     if (act) {
       double nlo = lo, nhi = hi;
-      for (int q = 0; q < g; ++q) {
-        const double xq = xs[t * g + q];
-        if (cs[t * g + q] <= sidx)
+      for (int q = 0; q < npt; ++q) {
+        const double xq = xs[2 * t * g + q];
+        if (cs[2 * t * g + q] <= sidx)
           nlo = fmax(nlo, xq);
         else
           nhi = fmin(nhi, xq);
@@ -727,20 +767,46 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
   wave_cholqr(n, D, Y, ys, R);
 }
 
-// x <- Q x for the D vectors of Y (lane j owns vector j), Q = H_0 ... H_{n-3}
-// with H_k = I - beta_k v_k v_k^T, v_k in row k of Hv (stride n) and beta_k in
-// lane k's br.
+// x <- Q x for the D vectors of Y, Q = H_0 ... H_{n-3} with
+// H_k = I - beta_k v_k v_k^T, v_k in row k of Hv (stride n) and beta_k in lane
+// k's br.  lpv = 4, 2 or 1 consecutive lanes share a vector (D <= 16, 32, 64),
+// each taking every lpv-th component.
 __device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D, double* Y, int ys) {
-  const int j = threadIdx.x;
+  const int lane = threadIdx.x;
+  const int lpv = D <= 16 ? 4 : (D <= 32 ? 2 : 1);
+  const int j = lane / lpv, q = lane - j * lpv;
+  const bool act = j < D;
   for (int k = n - 3; k >= 0; --k) {
     const double bk = wave_bcast(br, k);
     if (bk == 0.0) continue;
-    if (j < D) {
-      const double* v = Hv + k * n;
+    const double* v = Hv + k * n;
+    if (lpv == 4) {
+      // the lane's components of v_k (at most 16) loaded together first
+      double vv[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int r = k + 1 + q + 4 * t;
+        vv[t] = (act && r < n) ? v[r] : 0.0;
+      }
       double sdot = 0.0;
-      for (int r = k + 1; r < n; ++r) sdot += v[r] * Y[r * ys + j];
-      sdot *= bk;
-      for (int r = k + 1; r < n; ++r) Y[r * ys + j] -= sdot * v[r];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int r = k + 1 + q + 4 * t;
+        if (act && r < n) sdot += vv[t] * Y[r * ys + j];
+      }
+      sdot = bk * team_sum(sdot, 4);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int r = k + 1 + q + 4 * t;
+        if (act && r < n) Y[r * ys + j] -= sdot * vv[t];
+      }
+    } else {
+      double sdot = 0.0;
+      if (act)
+        for (int r = k + 1 + q; r < n; r += lpv) sdot += v[r] * Y[r * ys + j];
+      sdot = bk * team_sum(sdot, lpv);
+      if (act)
+        for (int r = k + 1 + q; r < n; r += lpv) Y[r * ys + j] -= sdot * v[r];
     }
   }
   __syncthreads();

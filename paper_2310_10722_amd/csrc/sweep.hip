@@ -699,8 +699,8 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
 // (row stride eig_ys) and are copied to Fv.
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
-  __shared__ double vw[128], tri[128], de[128], xs[64], lam[64];
-  __shared__ int cs[64];
+  __shared__ double vw[128], tri[128], de[128], xs[128], lam[64];
+  __shared__ int cs[128];
   const int s = blockIdx.x, tid = threadIdx.x;
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
