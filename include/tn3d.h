@@ -77,8 +77,10 @@ typedef struct {
   uint32_t reserved1;
 } tn3d_params;
 
-/* Fill *p with the defaults for a precision: eps_rel 1e-12 / 1e-6, tau_gap
- * 1e-9 / 1e-4, near_tie 4e-3, no workspace cap. */
+/* Fill *p with the defaults for a precision: eps_rel 1e-9 (FP64) / 1e-6
+ * (FP32), tau_gap 1e-6 / 1e-4, near_tie 4e-3, no workspace cap.  The gap
+ * threshold stays well above the rounding of the smallest singular value the
+ * rule can keep, so two correct implementations take the same cuts. */
 void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t precision);
 
 /* Create a context on HIP device `device`, enqueueing on `stream` (a

@@ -305,7 +305,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_L4 = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Th = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Jm = cv.take<double>(nsw_max * L.jcap);
-  size_t o_Gm = cv.take<double>(prec == TN3D_PREC_FP64 ? 1 : nsw_max * L.bigcap);
+  // boundary-MPS steps through the Gram of the smaller family when the rank
+  // rule never needs singular values below 1e-8 of the largest (their squares
+  // stay well above the FP64 rounding of the Gram); one-sided Jacobi otherwise
+  const bool gram_path = prec != TN3D_PREC_FP64 || pr.eps_rel >= 1e-8;
+  size_t o_Gm = cv.take<double>(gram_path ? nsw_max * L.bigcap : 1);
   size_t o_zdim = cv.take<int32_t>(nsw_max * 12);
   size_t o_zS = cv.take<double>(nsw_max * 1024);
   size_t o_logm = cv.take<double>(nsw_max);
@@ -443,7 +447,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.tau = pr.tau_gap;
     Z.jtol = A.jtol;
     Z.jfloor = A.jfloor;
-    Z.gram_path = prec == TN3D_PREC_FP64 ? 0 : 1;
+    Z.gram_path = gram_path ? 1 : 0;
     Z.sweeps_max = A.sweeps_max;
     Z.zdim = reinterpret_cast<int32_t*>(ws + o_zdim);
     Z.zS = reinterpret_cast<double*>(ws + o_zS);
@@ -636,8 +640,10 @@ void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t p
   p->chi_mps = chi_mps;
   p->precision = precision;
   const bool f64 = precision == TN3D_PREC_FP64;
-  p->eps_rel = f64 ? 1e-12 : 1e-6;
-  p->tau_gap = f64 ? 1e-9 : 1e-4;
+  // the smallest kept singular value must carry rounding well below the gap
+  // that decides a cut: about 1e-7 relative at 1e-9 of the largest in FP64
+  p->eps_rel = f64 ? 1e-9 : 1e-6;
+  p->tau_gap = f64 ? 1e-6 : 1e-4;
   p->near_tie = 4e-3;
   p->workspace_bytes = 0;
 }

@@ -393,43 +393,32 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
 // ---------------------------------------------------------------------------
 // reabsorption T' = T W on the (p, bond) columns
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-  using type = float4;
-};
-template <>
-struct Vec4<double> {
-  using type = double4;
-};
-
 // One wavefront per (gate side, sweep), one thread per tensor row: the row's
-// nin entries are held in registers in the storage type T (the arithmetic of
-// the absorption) and multiplied by W, staged in LDS with its rows padded to a
-// multiple of 4 and read by all lanes at the same address, four outputs at a
-// time.
+// nin entries are held in registers in FP64 and multiplied by W (FP64, staged
+// in LDS and read by all lanes at the same address), four outputs at a time;
+// only the result is rounded to the storage type.  A launch handles the gates
+// with nlo < nin <= NMAX, so narrow gates run with fewer registers.
 template <typename T, int NMAX>
 __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gates, int n_g, const double* win,
-                                                 int ncap) {
-  using V4 = typename Vec4<T>::type;
+                                                 int ncap, int nlo) {
   const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
   const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
   const double* W = win + (int64_t(sweep * n_g + gi) * 2 + side) * (2 + ncap * ncap);
   const int Dold = int(W[0]), Dn = int(W[1]);
+  const int nin = d * Dold, nout = d * Dn, nst = (nout + 3) & ~3;
+  if (nin <= nlo || nin > NMAX) return;
   int D[4];
   site_dims(A, sweep, site, D);
   D[leg] = Dold;
   const Split v = make_split(D, leg, d);
-  const int nin = d * Dold, nout = d * Dn, nst = (nout + 3) & ~3;
-  __shared__ V4 Ws4[NMAX * NMAX / 4];
-  __shared__ int colin[NMAX], colout[NMAX];
-  T* Ws = reinterpret_cast<T*>(Ws4);
+  __shared__ double4 Ws4[NMAX * 64 / 4];
+  __shared__ int colin[NMAX], colout[64];
+  double* Ws = reinterpret_cast<double*>(Ws4);
   for (int e = tid; e < nin * nst; e += 64) {
     const int k = e / nst, q = e - k * nst;
-    Ws[e] = q < nout ? T(W[2 + k * nout + q]) : T(0);
+    Ws[e] = q < nout ? W[2 + k * nout + q] : 0.0;
   }
   for (int col = tid; col < nin; col += 64) {
     const int p = col / Dold, x = col - p * Dold;
@@ -450,25 +439,25 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
     const int a = r / v.Cp, c = r - a * v.Cp;
     const T* src = in + (a * Dold * v.Cp + c) * d;
     T* dst = out + (a * Dn * v.Cp + c) * d;
-    T x[NMAX];
+    double x[NMAX];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) x[k] = k < nin ? src[colin[k]] : T(0);
+    for (int k = 0; k < NMAX; ++k) x[k] = k < nin ? double(src[colin[k]]) : 0.0;
     for (int q4 = 0; q4 < n4; ++q4) {
-      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
       for (int k = 0; k < NMAX; ++k)
         if (k < nin) {
-          const V4 w = Ws4[k * n4 + q4];
+          const double4 w = Ws4[k * n4 + q4];
           s0 += x[k] * w.x;
           s1 += x[k] * w.y;
           s2 += x[k] * w.z;
           s3 += x[k] * w.w;
         }
       const int q = 4 * q4;
-      dst[colout[q]] = s0;
-      if (q + 1 < nout) dst[colout[q + 1]] = s1;
-      if (q + 2 < nout) dst[colout[q + 2]] = s2;
-      if (q + 3 < nout) dst[colout[q + 3]] = s3;
+      dst[colout[q]] = T(s0);
+      if (q + 1 < nout) dst[colout[q + 1]] = T(s1);
+      if (q + 2 < nout) dst[colout[q + 2]] = T(s2);
+      if (q + 3 < nout) dst[colout[q + 3]] = T(s3);
     }
   }
 }
@@ -1045,10 +1034,14 @@ void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g
                      hipStream_t st) {
   if (n_g <= 0) return;
   dim3 g(2 * n_g, A.n_sweeps);
-  if (prec == 0)
-    hipLaunchKernelGGL((k_reabsorb<double, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap);
-  else
-    hipLaunchKernelGGL((k_reabsorb<float, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap);
+  // two size classes: rows of at most 32 entries, then the rest up to 64
+  if (prec == 0) {
+    hipLaunchKernelGGL((k_reabsorb<double, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<double, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+  } else {
+    hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<float, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+  }
 }
 
 void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,

@@ -38,7 +38,7 @@ def test_params_defaults(lib_path):
     assert (p.chi, p.chi_mps, p.precision) == (16, 16, 1)
     assert p.eps_rel == 1e-6 and p.tau_gap == 1e-4 and p.flags == 0
     p = tn3d.tn3d_params_default(4, 8, tn3d.PREC_FP64)
-    assert p.eps_rel == 1e-12 and p.tau_gap == 1e-9 and p.chi_mps == 8
+    assert p.eps_rel == 1e-9 and p.tau_gap == 1e-6 and p.chi_mps == 8
 
 
 def test_context_rejects_missing_device(lib_path):
