@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 
 METRIC = "syndromes decoded/sec at fixed chi + coset log-prob error vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 
 
 def workload(cfg: int):
@@ -146,7 +147,7 @@ def main():
     # with device wall-clock stamps between the launches for the kernel times
     ctx.set_timing(1)
     tn3d.tn3d_decode(ctx, net, syn, prm)  # captures the timed variant of the sequence
-    hot_ms = hot_bytes = hot_launch = lay_ms = fin_ms = 0.0
+    hot_ms = hot_bytes = hot_launch = lay_ms = fin_ms = eig_ms = eig_launch = eig_flops = 0.0
     results = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,6 +159,9 @@ def main():
         hot_ms += tl[2]
         hot_launch += tl[3]
         hot_bytes += tl[4]
+        eig_ms += tl[5]
+        eig_launch += tl[6]
+        eig_flops += tl[7]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
@@ -203,6 +207,14 @@ def main():
     value = a.steps * B / dt
     coset, lr, logp, flags = [t.cpu().numpy() for t in results]
     achieved = hot_bytes / (hot_ms * 1e-3) / 1e9 if hot_ms > 0 else None
+    # the dominant kernel: the boundary-MPS eigen-decomposition, FP64 vector ALU work
+    roof = None
+    if eig_ms > 0:
+        tf = eig_flops / (eig_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_zip_beig (boundary-MPS leading eigenpairs, FP64)",
+                "achieved": tf, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": tf / FP64_VALU_PEAK_TFS,
+                "algorithmic_flops_per_launch": eig_flops / eig_launch, "avg_launch_ms": eig_ms / eig_launch,
+                "traffic": None}
     out = {
         "metric": METRIC,
         "value": value,
@@ -224,11 +236,12 @@ def main():
         "rank_rule": {"eps_rel": prm.eps_rel, "tau_gap": prm.tau_gap},
         "phases_ms_per_step": {"layer_absorption": lay_ms / a.steps, "boundary_mps": fin_ms / a.steps,
                                "gram_plus_reabsorb": hot_ms / a.steps},
-        "roofline": {"bound": "hbm", "kernel": "k_gram + k_reabsorb (site-tensor streaming)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "algorithmic_bytes_per_launch": hot_bytes / max(hot_launch, 1),
-                     "avg_launch_ms": hot_ms / max(hot_launch, 1), "traffic": None},
+        "roofline": roof,
+        "roofline_streaming": {"bound": "hbm", "kernel": "k_gram + k_reabsorb (site-tensor streaming)",
+                               "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                               "algorithmic_bytes_per_launch": hot_bytes / max(hot_launch, 1),
+                               "avg_launch_ms": hot_ms / max(hot_launch, 1), "traffic": None},
         "bonds_after_sweep": {"mean_dim": stats[0], "max_dim": stats[1],
                               "mean_smallest_lambda": stats[3], "max_jacobi_sweeps": stats[4],
                               "max_jacobi_sweeps_boundary": stats[5]},

@@ -168,7 +168,11 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * out[1] = final boundary MPS, out[2] = Gram + reabsorption kernels only,
  * out[3] = number of Gram + reabsorption launches, out[4] = algorithmic bytes
  * those launches moved (each site tensor read by the Gram, read and written
- * by the reabsorption).  Milliseconds for times; n <= 5 values are written.
+ * by the reabsorption), out[5] = time of the boundary-MPS eigen-decomposition
+ * launches (when the rank rule allows that path), out[6] = their number,
+ * out[7] = their algorithmic flops (per problem of order n keeping D vectors:
+ * 4n^3/3 + 2Dn^2 + 10Dn + 16D^2n).  Milliseconds for times; n <= 8 values are
+ * written.
  * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);

@@ -50,7 +50,7 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   int timing = 0;                  // 1: kernel times, 2: also bond statistics
   int wclk_khz = 100000;           // device wall-clock rate
-  double timing_out[5] = {0, 0, 0, 0, 0};
+  double timing_out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
   int last_resweeps = 0;           // items the last decode re-swept in FP64
@@ -315,8 +315,10 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_logm = cv.take<double>(nsw_max);
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
   // 64 byte counters (spread to keep atomics uncontended), then the sweep maxima
-  size_t o_ctr = cv.take<unsigned long long>(65);
-  const size_t n_stamp = 3 + P.layers.size() * 16;
+  // 64 byte counters, the sweep maxima, 64 flop counters (spread to keep atomics uncontended)
+  size_t o_ctr = cv.take<unsigned long long>(129);
+  const size_t zip_stamp0 = 3 + P.layers.size() * 16;
+  const size_t n_stamp = zip_stamp0 + 2 * size_t(P.Lx) * P.Ly;
   size_t o_stamp = cv.take<unsigned long long>(n_stamp);
   size_t o_gitems = cv.take<int32_t>(chunk_items);
   size_t o_gsoff = cv.take<int64_t>(chunk_items);
@@ -335,7 +337,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
 
   const int timing = c->timing;
   float t_layers = 0, t_final = 0, t_hot = 0;
-  double hot_launches = 0, hot_bytes = 0;
+  double hot_launches = 0, hot_bytes = 0, t_eig = 0, eig_launches = 0, eig_flops = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
     const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
     int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
@@ -387,7 +389,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.synd = synd_p;
     A.synd_off = soff_p;
     A.items = items_p;
-    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 130, s);
+    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 258, s);
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     unsigned long long* stamp = reinterpret_cast<unsigned long long*>(ws + o_stamp);
@@ -451,10 +453,12 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.sweeps_max = A.sweeps_max;
     Z.zdim = reinterpret_cast<int32_t*>(ws + o_zdim);
     Z.zS = reinterpret_cast<double*>(ws + o_zS);
+    Z.flop_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 65 * 8) : nullptr;
     Z.Gm = reinterpret_cast<double*>(ws + o_Gm);
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
-      for (int x = 0; x < P.Lx; ++x) launch_zip_step(Z, x, y, s);
+      for (int x = 0; x < P.Lx; ++x)
+        launch_zip_step(Z, x, y, timing ? stamp + zip_stamp0 + 2 * (size_t(y) * P.Lx + x) : nullptr, s);
     launch_finish(A, Z, logp_p, flags_p, s);
     if (timing) launch_stamp(stamp + 2, s);
     HIPCHK(c, hipGetLastError());
@@ -519,7 +523,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (timing) {
       // stamps: 0 start, 1 after the layers, 2 end; 3 + 4 g .. 6 + 4 g around
       // the Gram and reabsorption launches of gate class g
-      std::vector<unsigned long long> st(3 + hot_i);
+      std::vector<unsigned long long> st(n_stamp);
       HIPCHK(c, hipMemcpyAsync(st.data(), ws + o_stamp, st.size() * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
       const double ms_per_tick = 1.0 / double(c->wclk_khz);
@@ -527,9 +531,17 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       t_final += double(st[2] - st[1]) * ms_per_tick;
       for (size_t h = 0; h + 3 < hot_i; h += 4)
         t_hot += double(st[3 + h + 1] - st[3 + h] + st[3 + h + 3] - st[3 + h + 2]) * ms_per_tick;
-      unsigned long long nb[64];
-      HIPCHK(c, hipMemcpy(nb, A.bytes_ctr, sizeof(nb), hipMemcpyDeviceToHost));
-      for (unsigned long long v : nb) hot_bytes += double(v);
+      if (gram_path)
+        for (int y = 0; y < P.Ly; ++y)
+          for (int x = 0; x + 1 < P.Lx; ++x) {
+            const size_t b = zip_stamp0 + 2 * (size_t(y) * P.Lx + x);
+            t_eig += double(st[b + 1] - st[b]) * ms_per_tick;
+            eig_launches += 1;
+          }
+      unsigned long long nb[129];
+      HIPCHK(c, hipMemcpy(nb, ws + o_ctr, sizeof(nb), hipMemcpyDeviceToHost));
+      for (int k = 0; k < 64; ++k) hot_bytes += double(nb[k]);
+      for (int k = 65; k < 129; ++k) eig_flops += double(nb[k]);
     }
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
@@ -560,6 +572,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     c->timing_out[2] += t_hot;
     c->timing_out[3] += hot_launches;
     c->timing_out[4] += hot_bytes;
+    c->timing_out[5] += t_eig;
+    c->timing_out[6] += eig_launches;
+    c->timing_out[7] += eig_flops;
   }
   return TN3D_OK;
 }
@@ -605,7 +620,7 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
     if (!nets[i] || nets[i]->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
   HIPCHK(c, hipSetDevice(c->device));
   if (c->timing) {
-    for (int k = 0; k < 5; ++k) c->timing_out[k] = 0;
+    for (int k = 0; k < 8; ++k) c->timing_out[k] = 0;
     for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
   }
   std::map<tn3d_net, std::vector<int32_t>> groups;
@@ -860,7 +875,7 @@ tn3d_status tn3d_last_stats(tn3d_ctx c, double* out, int32_t n) {
 tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
   if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
-  for (int i = 0; i < n && i < 5; ++i) out[i] = c->timing_out[i];
+  for (int i = 0; i < n && i < 8; ++i) out[i] = c->timing_out[i];
   return TN3D_OK;
 }
 

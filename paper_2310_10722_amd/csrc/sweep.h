@@ -61,6 +61,7 @@ struct ZipArgs {
   double* Gm;               // [sweep][bigcap] that Gram
   int32_t* zdim;            // [sweep][12] shapes passed between the step kernels
   double* zS;               // [sweep][1024] singular values of the step
+  unsigned long long* flop_ctr;  // 64 counters of algorithmic flops of the decomposition, or null
 };
 
 // Raises the dynamic-LDS limits of the kernels that need more than 64 KB;
@@ -83,7 +84,8 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
                      const int32_t* par_final, double* fin, int64_t fin_stride, const int64_t* fin_off,
                      hipStream_t st);
 void launch_zip_init(const ZipArgs& Z, hipStream_t st);
-void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
+// stamps (or null): two wall-clock stamps around the decomposition launch
+void launch_zip_step(const ZipArgs& Z, int x, int y, unsigned long long* stamps, hipStream_t st);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
 // Graph replay helpers: gather each item's syndrome into a dense buffer,
 // local item indices with their offsets, zero a counter block (no memset

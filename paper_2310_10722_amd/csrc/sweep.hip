@@ -711,6 +711,13 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   const int ys = Z.eig_ys;
   wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, zsm + 64 * ys, Z.Jm + int64_t(s) * Z.jcap);
   wave_tri_backtransform(G, br, nv, Dn, zsm, ys);
+  if (Z.flop_ctr && tid == 0) {
+    // algorithmic flops: Householder reduction 4n^3/3, back-transform 2Dn^2,
+    // inverse-iteration solves 10Dn, four Cholesky-QR passes 16D^2n
+    const double n = nv, D = Dn;
+    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 10.0 * D * n + 16.0 * D * D * n;
+    atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
+  }
   double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   for (int e = tid; e < nv * Dn; e += 64) Fv[e] = zsm[(e / Dn) * ys + e % Dn];
   if (tid == 0) {
@@ -1069,12 +1076,14 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_init, dim3(Z.n_sweeps), dim3(64), 0, st, Z);
 }
 
-void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
+void launch_zip_step(const ZipArgs& Z, int x, int y, unsigned long long* stamps, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
+      if (stamps) launch_stamp(stamps, st);
       hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64 + Z.eig_ys) * Z.eig_ys * 8, st, Z, x,
                          y);
+      if (stamps) launch_stamp(stamps + 1, st);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
