@@ -450,14 +450,18 @@ __device__ __forceinline__ double wave_max(double v) {
 // registers: lane i holds column i in a[0..63].  J0 <= kb, so rows below J0
 // are finished and every index into a[] is a compile-time constant; row k of
 // the current matrix is picked out of the 16 rows [J0, J0 + 16).  v and w of a
-// step are broadcast through vw (2 * 64 doubles of LDS).  The Householder
-// vector of step k is kept in row k of Hv (stride n); lane i writes only
-// column i, the column it read from the input.
+// step are broadcast through vw (v in vw[0, 64), w in vw[64, 128), 16-byte
+// aligned LDS), read two at a time with the next group's reads issued before
+// the current group's FMAs.  The Householder vector of step k is kept in row k
+// of Hv (stride n); lane i writes only column i, the column it read from the
+// input.
 template <int J0>
 __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke, double* vw, double* Hv,
                                           double& er, double& br) {
   const int i = threadIdx.x;
   const bool own = i < n;
+  const double2* v2 = reinterpret_cast<const double2*>(vw);
+  const double2* w2 = reinterpret_cast<const double2*>(vw + 64);
   for (int k = kb; k < ke; ++k) {
     double ak = 0.0;
 #pragma unroll
@@ -482,34 +486,91 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
       br = bk;
     }
     if (own) Hv[k * n + i] = v;
-    vw[2 * i] = v;
+    vw[i] = v;
     __syncthreads();
-    // p = bk A v, K = bk/2 p.v, w = p - K v; A <- A - v w^T - w v^T
-    double p4[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: no single 64-long chain
+    // p = bk A v in four partial sums, v read 16 rows at a time
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};
+    double2 c[8];
 #pragma unroll
-    for (int j = J0; j < 64; ++j) p4[j & 3] += a[j] * vw[2 * j];
+    for (int t = 0; t < 8; ++t) c[t] = v2[J0 / 2 + t];
+#pragma unroll
+    for (int g = J0; g < 64; g += 16) {
+      double2 nx[8];
+      if (g + 16 < 64) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) nx[t] = v2[(g + 16) / 2 + t];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        p4[(2 * t) & 3] = fma(a[g + 2 * t], c[t].x, p4[(2 * t) & 3]);
+        p4[(2 * t + 1) & 3] = fma(a[g + 2 * t + 1], c[t].y, p4[(2 * t + 1) & 3]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (g + 16 < 64) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) c[t] = nx[t];
+      }
+    }
     const double p = ((p4[0] + p4[1]) + (p4[2] + p4[3])) * bk;
     const double K = 0.5 * bk * wave_sum(p * v);
     const double w = act ? p - K * v : 0.0;
-    vw[2 * i + 1] = w;
+    vw[64 + i] = w;
     __syncthreads();
+    // A <- A - v w^T - w v^T, v and w read 8 rows at a time
+    double2 cv[4], cw[4];
 #pragma unroll
-    for (int j = J0; j < 64; ++j) a[j] -= v * vw[2 * j + 1] + w * vw[2 * j];
+    for (int t = 0; t < 4; ++t) {
+      cv[t] = v2[J0 / 2 + t];
+      cw[t] = w2[J0 / 2 + t];
+    }
+#pragma unroll
+    for (int g = J0; g < 64; g += 8) {
+      double2 nv[4], nw[4];
+      if (g + 8 < 64) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          nv[t] = v2[(g + 8) / 2 + t];
+          nw[t] = w2[(g + 8) / 2 + t];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[g + 2 * t] = fma(-v, cw[t].x, fma(-w, cv[t].x, a[g + 2 * t]));
+        a[g + 2 * t + 1] = fma(-v, cw[t].y, fma(-w, cv[t].y, a[g + 2 * t + 1]));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (g + 8 < 64) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          cv[t] = nv[t];
+          cw[t] = nw[t];
+        }
+      }
+    }
     __syncthreads();
   }
 }
 
-// Householder reduction of the symmetric n x n matrix G (row-major) times gs.
-// Lane i returns d_i = T[i][i], e_i = T[i][i+1] (0 for i >= n - 1) and the
-// scalar beta_i of reflector i (0 when step i needed no reflection); Hv
-// receives the reflectors (row k, stride n, components k+1 .. n-1) and may
-// alias G.
+// Householder reduction of the symmetric n x n matrix G (row-major, n >= 1)
+// times gs.  Lane i returns d_i = T[i][i], e_i = T[i][i+1] (0 for i >= n - 1)
+// and the scalar beta_i of reflector i (0 when step i needed no reflection);
+// Hv receives the reflectors (row k, stride n, components k+1 .. n-1, zeros
+// before) and may alias G.  vw: 128 doubles of 16-byte aligned LDS.
 __device__ void wave_tridiag(const double* G, double gs, int n, double* vw, double* Hv, double& dr, double& er,
                              double& br) {
   const int i = threadIdx.x;
   double a[64];
+  // every lane loads all 64 entries (clamped into the matrix) so that the loads
+  // are issued together; entries outside the n x n block are zeroed after
+  const int ic = i < n ? i : n - 1;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) a[j] = (j < n && i < n) ? G[j * n + i] * gs : 0.0;
+  for (int j = 0; j < 64; ++j) {
+    const int jc = j < n ? j : n - 1;
+    const double g = G[jc * n + ic];
+    a[j] = (j < n && i < n) ? g * gs : 0.0;
+  }
   er = 0.0;
   br = 0.0;
   const int ke = n - 2;
@@ -534,33 +595,57 @@ __device__ void wave_tridiag(const double* G, double gs, int n, double* vw, doub
   }
 }
 
-// Numbers of eigenvalues of T below xa and below xb: negative pivots of
-// T - x I (Sturm sequences), the two recurrences interleaved.  tri[2i] = d_i,
-// tri[2i+1] = e_{i-1}^2 (e_{-1} = 0), read by all lanes at the same LDS
-// address.  Pivots smaller than pivmin in
-// magnitude are replaced by -pivmin; 1/q is the approximate reciprocal, whose
-// few-ulp error perturbs the count like a relative change of e^2 of that size.
-__device__ __forceinline__ void sturm_count2(const double* tri, int n, double xa, double xb, double pivmin, int& ca,
-                                             int& cb) {
-  ca = 0;
-  cb = 0;
-  double qa = 1.0, qb = 1.0;
-  for (int r = 0; r < n; ++r) {
-    const double d = tri[2 * r], e2 = tri[2 * r + 1];
-    qa = (d - xa) - e2 * approx_rcp(qa);
-    qb = (d - xb) - e2 * approx_rcp(qb);
-    if (fabs(qa) <= pivmin) qa = -pivmin;
-    if (fabs(qb) <= pivmin) qb = -pivmin;
-    ca += qa < 0.0 ? 1 : 0;
-    cb += qb < 0.0 ? 1 : 0;
+// Numbers of eigenvalues of T below xa and below xb: sign changes along the
+// leading principal minors m_0 = 1, m_1, ..., m_n of T - x I, from the
+// three-term recurrence m_{r+1} = (d_r - x) m_r - e_{r-1}^2 m_{r-1} (two
+// recurrences interleaved, no division; a zero minor counts as non-negative).
+// Every four rows both carried minors are scaled by the same power of two so
+// that they stay in range.  tri[2i] = d_i, tri[2i+1] = e_{i-1}^2 raised to at
+// least 2^-700 (so that a zero minor cannot zero the rest of the sequence; for
+// T scaled to norm about 1 the change is far below rounding), read by all
+// lanes at the same 16-byte aligned LDS address.  Rows are taken four at a
+// time: rows n .. 63 must hold d = 4, e^2 = 0, which adds no sign change for
+// |x| < 2.
+__device__ __forceinline__ void sturm_count2(const double* tri, int n, double xa, double xb, int& ca, int& cb) {
+  const double2* t2 = reinterpret_cast<const double2*>(tri);
+  double a1 = 1.0, a2 = 0.0, b1 = 1.0, b2 = 0.0;
+  int na = 0, nb = 0;
+  double2 de[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) de[t] = t2[t];
+  for (int r0 = 0; r0 < n; r0 += 4) {
+    double2 dn[4];  // the next four rows, read while these are used
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dn[t] = t2[(r0 + 4 + t) & 63];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double pa = fma(de[t].x - xa, a1, -de[t].y * a2);
+      const double pb = fma(de[t].x - xb, b1, -de[t].y * b2);
+      na += (pa < 0.0) != (a1 < 0.0) ? 1 : 0;
+      nb += (pb < 0.0) != (b1 < 0.0) ? 1 : 0;
+      a2 = a1;
+      a1 = pa;
+      b2 = b1;
+      b1 = pb;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) de[t] = dn[t];
+    const int sa = -__builtin_amdgcn_frexp_exp(a1), sb = -__builtin_amdgcn_frexp_exp(b1);
+    a1 = __builtin_amdgcn_ldexp(a1, sa);
+    a2 = __builtin_amdgcn_ldexp(a2, sa);
+    b1 = __builtin_amdgcn_ldexp(b1, sb);
+    b2 = __builtin_amdgcn_ldexp(b2, sb);
   }
+  ca = na;
+  cb = nb;
 }
 
 // The K (<= n) largest eigenvalues of T (lane i holds d_i, e_i) into lam[0..K)
 // in decreasing order, by multisection of the Gershgorin interval: g = 64 / K
 // lanes (at most 3) share an eigenvalue and each evaluates two interior points
 // per round, until the bracket is within a few ulps of the eigenvalue or of
-// the norm of T.  tri: 2 * 64 doubles, xs: 128 doubles, cs: 128 ints (LDS).
+// the norm of T.  tri: 2 * 64 doubles (16-byte aligned), xs: 128 doubles, cs:
+// 128 ints (LDS).
 // Returns the norm bound max |Gershgorin end|.
 __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri, double* xs, int* cs, double* lam) {
   const int i = threadIdx.x;
@@ -568,28 +653,34 @@ __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri,
   const double eu = __shfl_up(er, 1, 64);
   const double el = (own && i > 0) ? eu : 0.0;
   const double ei = (own && i + 1 < n) ? er : 0.0;
-  if (own) {
-    tri[2 * i] = dr;
-    tri[2 * i + 1] = el * el;
-  }
   double lo = wave_min(own ? dr - fabs(el) - fabs(ei) : 1e300);
   double hi = wave_max(own ? dr + fabs(el) + fabs(ei) : -1e300);
   const double nrm = fmax(fabs(lo), fabs(hi));
-  const double atol = 4.0 * 2.220446049250313e-16 * nrm;
-  const double pivmin = 1e-290 * fmax(1.0, nrm * nrm);
-  lo -= atol + pivmin;
-  hi += atol + pivmin;
-  __syncthreads();
   const int g = K >= 1 && 64 / K < 3 ? 64 / K : 3;
   const int t = i / g, r = i - t * g;
   const bool act = t < K;
+  if (!(nrm > 0.0)) {  // T = 0
+    if (act && r == 0) lam[t] = 0.0;
+    __syncthreads();
+    return nrm;
+  }
+  // the counts run on T / 2^e with 2^e the power of two at or above ||T||, so
+  // the minors stay near 1 whatever the scale of T
+  const double sc = __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(nrm));
+  tri[2 * i] = own ? dr * sc : 4.0;  // rows past n: no sign change for |x| < 2
+  tri[2 * i + 1] = own ? fmax(el * el * (sc * sc), 0x1p-700) : 0.0;
+  const double atol = 4.0 * 2.220446049250313e-16 * nrm;
+  const double pad = 1e-290 * fmax(1.0, nrm * nrm);
+  lo -= atol + pad;
+  hi += atol + pad;
+  __syncthreads();
   const int sidx = n - 1 - t;  // position of the target in ascending order
   const int npt = 2 * g;       // points per eigenvalue and round
   for (int it = 0; it < 128; ++it) {
     const double w = (hi - lo) / double(npt + 1);
     const double xa = lo + w * double(2 * r + 1), xb = lo + w * double(2 * r + 2);
     int ca, cb;
-    sturm_count2(tri, n, xa, xb, pivmin, ca, cb);
+    sturm_count2(tri, n, xa * sc, xb * sc, ca, cb);
     xs[2 * i] = xa;
     xs[2 * i + 1] = xb;
     cs[2 * i] = ca;
@@ -617,35 +708,77 @@ __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri,
 }
 
 // One inverse-iteration solve (T - lam I) y = y for lane j's vector
-// Y[r * ys + j], with the LU factors of lane j at U[(5 r + c) ys + j] (c = 0
-// pivot, 1 and 2 the next two entries of U's row, 3 the multiplier, 4 the row
-// swap flag), then y normalised.
-__device__ __forceinline__ void tri_solve(int n, const double* U, double* Y, int ys, int j) {
+// Y[r * ys + j], with the LU factors of lane j at U[(r * ys + j) * 4 + c]
+// (c = 0 the reciprocal pivot, 1 and 2 the next two entries of U's row, 3 the
+// multiplier) and the row swaps in the bits of swm, then y normalised.  The
+// rows are taken in groups of eight held in registers: after a row is used its
+// slot is refilled with the row eight further on, so eight rows of loads are
+// always in flight.
+__device__ __forceinline__ void tri_solve(int n, const double* U, double* Y, int ys, int j,
+                                          unsigned long long swm) {
+  const double* Uj = U + 4 * j;
+  const int rs = 4 * ys;
   double cur = Y[j];
-  for (int r = 0; r + 1 < n; ++r) {
-    const double* u = U + size_t(5 * r) * ys + j;
-    const double nxt = Y[(r + 1) * ys + j];
-    const bool sw = u[4 * ys] != 0.0;
-    const double top = sw ? nxt : cur, bot = sw ? cur : nxt;
-    Y[r * ys + j] = top;
-    cur = bot - u[3 * ys] * top;
+  const int last = n - 2;  // rows 0 .. n-2 carry an elimination step
+  if (last >= 0) {
+    double mA[8], yA[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = t < last ? t : last;
+      mA[t] = Uj[r * rs + 3];
+      yA[t] = Y[(r + 1) * ys + j];
+    }
+    for (int r0 = 0; r0 <= last; r0 += 8) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int r = r0 + t;
+        if (r <= last) {
+          const bool sw = (swm >> r) & 1ull;
+          const double top = sw ? yA[t] : cur, bot = sw ? cur : yA[t];
+          Y[r * ys + j] = top;
+          cur = fma(-mA[t], top, bot);
+        }
+        const int rn = r + 8 < last ? r + 8 : last;
+        mA[t] = Uj[rn * rs + 3];
+        yA[t] = Y[(rn + 1) * ys + j];
+      }
+    }
   }
   Y[(n - 1) * ys + j] = cur;
   double y1 = 0.0, y2 = 0.0, ss = 0.0;
-  for (int r = n - 1; r >= 0; --r) {
-    const double* u = U + size_t(5 * r) * ys + j;
-    double yr = (Y[r * ys + j] - u[ys] * y1 - u[2 * ys] * y2) / u[0];
-    if (fabs(yr) > 1e150) {  // keep the partial solution representable
-      for (int q = r + 1; q < n; ++q) Y[q * ys + j] *= 1e-150;
-      y1 *= 1e-150;
-      y2 *= 1e-150;
-      ss *= 1e-300;
-      yr *= 1e-150;
+  double pA[8], uA[8], vA[8], yB[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int r = n - 1 - t >= 0 ? n - 1 - t : 0;
+    pA[t] = Uj[r * rs];
+    uA[t] = Uj[r * rs + 1];
+    vA[t] = Uj[r * rs + 2];
+    yB[t] = Y[r * ys + j];
+  }
+  for (int r0 = n - 1; r0 >= 0; r0 -= 8) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = r0 - t;
+      if (r >= 0) {
+        double yr = (yB[t] - uA[t] * y1 - vA[t] * y2) * pA[t];
+        if (fabs(yr) > 1e150) {  // keep the partial solution representable
+          for (int q = r + 1; q < n; ++q) Y[q * ys + j] *= 1e-150;
+          y1 *= 1e-150;
+          y2 *= 1e-150;
+          ss *= 1e-300;
+          yr *= 1e-150;
+        }
+        Y[r * ys + j] = yr;
+        ss = fma(yr, yr, ss);
+        y2 = y1;
+        y1 = yr;
+      }
+      const int rn = r - 8 >= 0 ? r - 8 : 0;
+      pA[t] = Uj[rn * rs];
+      uA[t] = Uj[rn * rs + 1];
+      vA[t] = Uj[rn * rs + 2];
+      yB[t] = Y[rn * ys + j];
     }
-    Y[r * ys + j] = yr;
-    ss += yr * yr;
-    y2 = y1;
-    y1 = yr;
   }
   const double sc = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
   for (int r = 0; r < n; ++r) Y[r * ys + j] *= sc;
@@ -653,15 +786,91 @@ __device__ __forceinline__ void tri_solve(int n, const double* U, double* Y, int
 
 // Orthonormalises the D vectors of Y in order, Y <- Y R^-1 with R^T R = Y^T Y
 // (Cholesky QR: vector j keeps the part of itself orthogonal to vectors
-// 0..j-1, as in Gram-Schmidt).  Lane j forms column j of the Gram matrix,
-// the factorisation runs by rows of R, and lane r then solves row r of Y
-// against R; ys should be odd so that both the column and the row accesses of
-// Y avoid LDS bank conflicts.  R: ys * ys doubles of LDS.  A vector that is
-// dependent on its predecessors (pivot below 1e-28 of its squared norm) is
-// left unnormalised and unused by the later ones.  One pass loses about
-// eps * cond(Y)^2 of orthogonality; call it twice.
-__device__ void wave_cholqr(int n, int D, double* Y, int ys, double* R) {
-  const int j = threadIdx.x;
+// 0..j-1, as in Gram-Schmidt).  A vector that is dependent on its
+// predecessors (pivot below 1e-28 of its squared norm) is left unnormalised
+// and unused by the later ones.  One pass loses about eps * cond(Y)^2 of
+// orthogonality; call it twice.  R: ys * ys doubles of LDS (ys odd, so that
+// the row and the column accesses of Y avoid bank conflicts), rk: 64 doubles
+// of LDS.
+//
+// D <= 16: lane (i4, j) = (lane / 16, lane % 16) forms the Gram entries
+// (i4 + 4u, j), four independent sums over the rows; lane j then factors
+// column j of the Gram in registers, row k of R broadcast through rk, and
+// every lane solves its row of Y against R.  Larger D: lane j forms column j
+// of the Gram and the factorisation runs by rows of R in LDS.
+__device__ __forceinline__ void wave_cholqr(int n, int D, double* Y, int ys, double* R, double* rk) {
+  const int lane = threadIdx.x;
+  if (D <= 16) {
+    const int jj = lane & 15, iq = lane >> 4;
+    const int jc = jj < D ? jj : D - 1;
+    int ic[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ic[u] = iq + 4 * u < D ? iq + 4 * u : D - 1;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int r = 0; r < n; ++r) {
+      const double yj = Y[r * ys + jc];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g[u] = fma(Y[r * ys + ic[u]], yj, g[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (iq + 4 * u < D && jj < D) R[(iq + 4 * u) * ys + jj] = g[u];
+    __syncthreads();
+    const bool col = lane < D;
+    const int cl = col ? lane : 0;
+    double c[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[i] = (col && i < D) ? R[(i < D ? i : 0) * ys + cl] : 0.0;
+    const double gjj = R[cl * ys + cl];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < D) {  // uniform; no early exit, so the loops unroll fully
+        const double g0 = wave_bcast(c[k], k);
+        const bool ok = g0 > 1e-28 * wave_bcast(gjj, k) && g0 > 0.0;
+        const double rkk = ok ? sqrt(g0) : 1.0;
+        const double rinv = 1.0 / rkk;
+        const double rkj = lane == k ? rkk : (lane > k && ok ? c[k] * rinv : 0.0);
+        c[k] = rkj;
+        rk[lane] = rkj;
+        __syncthreads();
+        double rr[16];
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) rr[i] = rk[i];
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) c[i] = lane >= i ? fma(-rr[i], rkj, c[i]) : c[i];
+        __syncthreads();
+      }
+    }
+    // column j of R back to LDS, with the reciprocal diagonal in rk
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (col && i <= lane) R[i * ys + cl] = c[i];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i == lane && col) rk[lane] = 1.0 / c[i];
+    __syncthreads();
+    if (lane < n) {
+      double y[16];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) y[cc] = cc < D ? Y[lane * ys + cc] : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        if (cc < D) {
+          double v = y[cc];
+#pragma unroll
+          for (int i = 0; i < cc; ++i) v = fma(-y[i], R[i * ys + cc], v);
+          y[cc] = v * rk[cc];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc)
+        if (cc < D) Y[lane * ys + cc] = y[cc];
+    }
+    __syncthreads();
+    return;
+  }
+  const int j = lane;
   double gjj = 0.0;  // squared norm of vector j, for the breakdown test
   if (j < D)
     for (int i = 0; i <= j; ++i) {
@@ -700,10 +909,10 @@ __device__ void wave_cholqr(int n, int D, double* Y, int ys, double* R) {
 // solved once more (which removes what the orthogonalisation of a nearly
 // dependent member of a cluster amplified outside the cluster) and
 // orthonormalised again.  Vector j is Y[r * ys + j] (LDS, ys odd); R: ys * ys
-// doubles of LDS; de: 2 * 64 doubles of LDS; U: 5 * n * ys doubles of scratch
-// private to each lane.
+// doubles of LDS; de: 2 * 64 doubles of LDS; rk: 64 doubles of LDS; U:
+// 4 * n * ys doubles of scratch, four per row and lane.
 __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm, const double* lam, double* de,
-                                 double* Y, int ys, double* R, double* U) {
+                                 double* Y, int ys, double* R, double* rk, double* U) {
   const int j = threadIdx.x;
   if (j < n) {
     de[2 * j] = dr;
@@ -711,42 +920,32 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
   }
   __syncthreads();
   const double tiny = 4.0 * 2.220446049250313e-16 * fmax(nrm, 1e-300);
+  unsigned long long swm = 0;
   if (j < D) {
     const double lj = lam[j];
-    double cp = de[0] - lj, cq = de[1], cr = 0.0;
+    double cp = de[0] - lj, cq = de[1];
+#pragma unroll 4
     for (int r = 0; r + 1 < n; ++r) {
       const double sub = de[2 * r + 1], nd = de[2 * r + 2] - lj, ns = de[2 * r + 3];
-      double* u = U + size_t(5 * r) * ys + j;
-      if (fabs(cp) >= fabs(sub)) {
-        const double piv = fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp;
-        const double m = sub / piv;
-        u[0] = piv;
-        u[ys] = cq;
-        u[2 * ys] = cr;
-        u[3 * ys] = m;
-        u[4 * ys] = 0.0;
-        const double ncp = nd - m * cq, ncq = ns - m * cr;
-        cp = ncp;
-        cq = ncq;
-      } else {
-        const double m = cp / sub;
-        u[0] = sub;
-        u[ys] = nd;
-        u[2 * ys] = ns;
-        u[3 * ys] = m;
-        u[4 * ys] = 1.0;
-        const double ncp = cq - m * nd, ncq = cr - m * ns;
-        cp = ncp;
-        cq = ncq;
-      }
-      cr = 0.0;
+      const bool sw = fabs(cp) < fabs(sub);
+      const double piv = sw ? sub : (fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp);
+      const double rp = approx_rcp(piv);
+      const double m = (sw ? cp : sub) * rp;
+      double* u = U + (r * ys + j) * 4;
+      u[0] = rp;
+      u[1] = sw ? nd : cq;
+      u[2] = sw ? ns : 0.0;
+      u[3] = m;
+      if (sw) swm |= 1ull << r;
+      const double ncp = sw ? fma(-m, nd, cq) : fma(-m, cq, nd);
+      cq = sw ? -m * ns : ns;
+      cp = ncp;
     }
-    {
-      double* u = U + size_t(5 * (n - 1)) * ys + j;
-      u[0] = fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp;
-      u[ys] = 0.0;
-      u[2 * ys] = 0.0;
-    }
+    double* u = U + ((n - 1) * ys + j) * 4;
+    u[0] = approx_rcp(fabs(cp) < tiny ? (cp < 0.0 ? -tiny : tiny) : cp);
+    u[1] = 0.0;
+    u[2] = 0.0;
+    u[3] = 0.0;
     for (int r = 0; r < n; ++r) {  // start vector: an integer mixing hash of (r, j)
       unsigned h = unsigned(r) * 0x9e3779b1u + unsigned(j) * 0x85ebca77u + 0x165667b1u;
       h ^= h >> 15;
@@ -756,57 +955,125 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
       h ^= h >> 15;
       Y[r * ys + j] = double(h >> 8) * (1.0 / 16777216.0) - 0.5;
     }
-    for (int it = 0; it < 2; ++it) tri_solve(n, U, Y, ys, j);
   }
-  __syncthreads();
-  wave_cholqr(n, D, Y, ys, R);
-  wave_cholqr(n, D, Y, ys, R);
-  if (j < D) tri_solve(n, U, Y, ys, j);
-  __syncthreads();
-  wave_cholqr(n, D, Y, ys, R);
-  wave_cholqr(n, D, Y, ys, R);
+  // two solves and two orthonormalisations, then one solve and two more (one
+  // inlined copy of each step)
+  for (int round = 0; round < 2; ++round) {
+    if (j < D)
+      for (int it = round; it < 2; ++it) tri_solve(n, U, Y, ys, j, swm);
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) wave_cholqr(n, D, Y, ys, R, rk);
+  }
 }
 
-// x <- Q x for the D vectors of Y, Q = H_0 ... H_{n-3} with
-// H_k = I - beta_k v_k v_k^T, v_k in row k of Hv (stride n) and beta_k in lane
-// k's br.  lpv = 4, 2 or 1 consecutive lanes share a vector (D <= 16, 32, 64),
-// each taking every lpv-th component.
-__device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D, double* Y, int ys) {
+template <int T>
+__device__ __forceinline__ double quad_sum(double v) {
+  if (T >= 2) v += dpp_move<0xB1>(v);  // quad_perm [1,0,3,2]
+  if (T >= 4) v += dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+
+// x <- Q x for the D <= 64 / LPV vectors of Y, Q = H_0 ... H_{n-3} with
+// H_k = I - beta_k v_k v_k^T, v_k in row k of Hv (stride n, zero at and above
+// component k) and beta_k in lane k's br.  LPV consecutive lanes share a
+// vector, each holding 64 / LPV consecutive rows of it in registers.  The
+// reflectors are staged through hb (8 * 72 doubles of 16-byte aligned LDS, a
+// padded row per reflector) eight at a time, the next eight loaded from
+// global memory into registers while the current eight are applied.
+template <int LPV>
+__device__ void tri_backtransform_regs(const double* Hv, double br, int n, int D, double* Y, int ys, double* hb) {
+  constexpr int RPL = 64 / LPV;
   const int lane = threadIdx.x;
-  const int lpv = D <= 16 ? 4 : (D <= 32 ? 2 : 1);
-  const int j = lane / lpv, q = lane - j * lpv;
+  const int j = lane / LPV, q = lane - j * LPV;
   const bool act = j < D;
+  const int r0 = q * RPL;
+  const int off = r0 + 2 * (r0 / 16);  // padded position of row r0 in an hb row
+  const int jc = act ? j : 0;
+  double y[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = r0 + t;
+    y[t] = (act && r < n) ? Y[(r < n ? r : 0) * ys + jc] : 0.0;
+  }
+  const int nk = n - 2;  // reflectors k = n-3 .. 0
+  const int ng = nk > 0 ? (nk + 7) / 8 : 0;
+  const int lc = lane < n ? lane : n - 1;
+  const int lpos = lane + 2 * (lane / 16);
+  double pf[8];
+  if (ng > 0) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = n - 3 - s;
+      const double x = Hv[(k >= 0 ? k : 0) * n + lc];
+      pf[s] = (k >= 0 && lane < n) ? x : 0.0;
+    }
+  }
+  for (int g = 0; g < ng; ++g) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) hb[s * 72 + lpos] = pf[s];
+    if (g + 1 < ng) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = n - 3 - 8 * (g + 1) - s;
+        const double x = Hv[(k >= 0 ? k : 0) * n + lc];
+        pf[s] = (k >= 0 && lane < n) ? x : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = n - 3 - 8 * g - s;
+      if (k < 0) break;
+      const double bk = wave_bcast(br, k);
+      const double2* h2 = reinterpret_cast<const double2*>(hb + s * 72 + off);
+      double vv[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL / 2; ++t) {
+        const double2 x = h2[t + t / 8];  // rows r0 + 2t, r0 + 2t + 1 (two pad doubles per 16 rows)
+        vv[2 * t] = x.x;
+        vv[2 * t + 1] = x.y;
+      }
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; t += 2) {
+        d0 = fma(vv[t], y[t], d0);
+        d1 = fma(vv[t + 1], y[t + 1], d1);
+      }
+      const double sd = quad_sum<LPV>(d0 + d1) * bk;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) y[t] = fma(-sd, vv[t], y[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = r0 + t;
+    if (act && r < n) Y[r * ys + j] = y[t];
+  }
+  __syncthreads();
+}
+
+// x <- Q x for the D vectors of Y (see tri_backtransform_regs); one lane per
+// vector for D > 32.
+__device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D, double* Y, int ys, double* hb) {
+  if (D <= 16) {
+    tri_backtransform_regs<4>(Hv, br, n, D, Y, ys, hb);
+    return;
+  }
+  if (D <= 32) {
+    tri_backtransform_regs<2>(Hv, br, n, D, Y, ys, hb);
+    return;
+  }
+  const int j = threadIdx.x;
   for (int k = n - 3; k >= 0; --k) {
     const double bk = wave_bcast(br, k);
     if (bk == 0.0) continue;
     const double* v = Hv + k * n;
-    if (lpv == 4) {
-      // the lane's components of v_k (at most 16) loaded together first
-      double vv[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int r = k + 1 + q + 4 * t;
-        vv[t] = (act && r < n) ? v[r] : 0.0;
-      }
+    if (j < D) {
       double sdot = 0.0;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int r = k + 1 + q + 4 * t;
-        if (act && r < n) sdot += vv[t] * Y[r * ys + j];
-      }
-      sdot = bk * team_sum(sdot, 4);
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int r = k + 1 + q + 4 * t;
-        if (act && r < n) Y[r * ys + j] -= sdot * vv[t];
-      }
-    } else {
-      double sdot = 0.0;
-      if (act)
-        for (int r = k + 1 + q; r < n; r += lpv) sdot += v[r] * Y[r * ys + j];
-      sdot = bk * team_sum(sdot, lpv);
-      if (act)
-        for (int r = k + 1 + q; r < n; r += lpv) Y[r * ys + j] -= sdot * v[r];
+      for (int r = k + 1; r < n; ++r) sdot += v[r] * Y[r * ys + j];
+      sdot *= bk;
+      for (int r = k + 1; r < n; ++r) Y[r * ys + j] -= sdot * v[r];
     }
   }
   __syncthreads();

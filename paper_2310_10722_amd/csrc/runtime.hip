@@ -207,7 +207,7 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   // FP32 boundary MPS: eigenvectors of families of up to 64 vectors in LDS
   // with row stride eig_ys, and the inverse-iteration factors per vector
   L.eig_ys = std::min(cm, 64) | 1;  // odd: conflict-free row and column access
-  L.jcap = std::max<int64_t>(L.bigcap, int64_t(5) * std::min<int64_t>(64, int64_t(cm) * L.legcap) * L.eig_ys);
+  L.jcap = std::max<int64_t>(L.bigcap, int64_t(4) * std::min<int64_t>(64, int64_t(cm) * L.legcap) * L.eig_ys);
   const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;

@@ -680,16 +680,25 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   zip_keep(Z, s, zd, nv, Sout, ord, J, 1, nv, nsw);
 }
 
-// FP32 mode, families of at most ZBIG vectors: leading eigenpairs of the PSD
-// Gram (eigenvalues S^2) in one wavefront.  The Gram is scaled by its largest
-// diagonal entry; only the min(nv, chi_m + 1) largest eigenvalues (all the
+// Families of at most ZBIG vectors when the rank rule allows the Gram route:
+// leading eigenpairs of the PSD Gram (eigenvalues S^2) in one wavefront.  The
+// Gram is scaled by its largest diagonal entry; only the min(nv, chi_m + 1) largest eigenvalues (all the
 // rank rule reads) and the vectors it keeps are computed.  The reflectors of
 // the tridiagonal reduction overwrite the Gram; the kept vectors sit in LDS
 // (row stride eig_ys) and are copied to Fv.
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
-  __shared__ double vw[128], tri[128], de[128], xs[128], lam[64];
+  // one 16-byte aligned block for the phases' scratch: the broadcast vectors
+  // of the reduction, the tridiagonal and the bisection points, the
+  // factorisation's rows, and (once those are dead) the staged reflectors
+  __shared__ __attribute__((aligned(16))) double scr[576];
+  __shared__ double lam[64];
   __shared__ int cs[128];
+  double* vw = scr;
+  double* tri = scr + 128;
+  double* de = scr + 256;
+  double* xs = scr + 384;
+  double* rk = scr + 512;
   const int s = blockIdx.x, tid = threadIdx.x;
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
@@ -709,8 +718,8 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   const bool bad = Dn < 1;
   if (bad) Dn = 1;
   const int ys = Z.eig_ys;
-  wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, zsm + 64 * ys, Z.Jm + int64_t(s) * Z.jcap);
-  wave_tri_backtransform(G, br, nv, Dn, zsm, ys);
+  wave_tri_vectors(dr, er, nv, Dn, nrm, lam, de, zsm, ys, zsm + 64 * ys, rk, Z.Jm + int64_t(s) * Z.jcap);
+  wave_tri_backtransform(G, br, nv, Dn, zsm, ys, scr);
   if (Z.flop_ctr && tid == 0) {
     // algorithmic flops: Householder reduction 4n^3/3, back-transform 2Dn^2,
     // inverse-iteration solves 10Dn, four Cholesky-QR passes 16D^2n
