@@ -7,8 +7,39 @@
 
 namespace tn3d {
 
+// Value of v in lane src (uniform) of the wavefront, in every lane.
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lowest lane whose pred is true (64 if none).
+__device__ __forceinline__ int wave_first(bool pred) {
+  const unsigned long long m = __ballot(pred);
+  return m ? __builtin_ctzll(m) : 64;
+}
+
+// v moved across lanes by a DPP pattern (a compile-time dpp_ctrl code).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over aligned teams of `team` (a power of two up to 64) consecutive
+// lanes, the same value in every lane of a team: DPP moves within rows of 16
+// lanes, lane shuffles across rows.  Every lane of a team must be active.
 __device__ __forceinline__ double team_sum(double v, int team) {
-  for (int o = team >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (team >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (team >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (team >= 8) v += dpp_move<0x141>(v);  // row_half_mirror: the other quad of the 8
+  if (team >= 16) v += dpp_move<0x140>(v); // row_mirror: the other 8 of the row
+  if (team >= 32) v += __shfl_xor(v, 16, 64);
+  if (team >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -16,31 +47,36 @@ __device__ __forceinline__ double team_sum(double v, int team) {
 // (row-major, leading dimension n; destroyed).  Writes F (r x n, row-major,
 // leading dimension n) with F^T F = Z up to the dropped trailing part, in the
 // original column order, and returns the rank r: elimination stops when the
-// largest remaining diagonal is <= tol * max(diag Z).  perm is scratch of n
-// ints, red scratch of 2 doubles.
+// largest remaining diagonal is <= tol * max(diag Z).  n <= 64.  perm is
+// scratch of n ints, red scratch of 2 doubles.
 __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < n; i += nt) perm[i] = i;
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, Z[i * n + i]);
-    red[0] = m;
+  if (tid < 64) {  // n <= 64: the first wavefront scans the diagonal
+    double m = tid < n ? Z[tid * n + tid] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (tid == 0) red[0] = fmax(m, 0.0);
   }
   __syncthreads();
   const double thr = tol * red[0];
   __syncthreads();
   int r = 0;
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      int j = k;
-      double best = Z[k * n + k];
-      for (int i = k + 1; i < n; ++i)
-        if (Z[i * n + i] > best) {
-          best = Z[i * n + i];
-          j = i;
+    if (tid < 64) {  // pivot: the largest remaining diagonal, lowest index on ties
+      double best = (tid >= k && tid < n) ? Z[tid * n + tid] : -1e300;
+      int j = tid;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double b2 = __shfl_xor(best, o, 64);
+        const int j2 = __shfl_xor(j, o, 64);
+        if (b2 > best || (b2 == best && j2 < j)) {
+          best = b2;
+          j = j2;
         }
-      red[1] = double(j);
-      red[0] = best;
+      }
+      if (tid == 0) {
+        red[1] = double(j);
+        red[0] = best;
+      }
     }
     __syncthreads();
     const int j = int(red[1]);
@@ -264,149 +300,6 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
         }
     }
   __syncthreads();
-}
-
-// Left-looking pivoted Cholesky of the n x n symmetric PSD matrix G (any
-// memory, row-major, read only): rows of F (r x n, leading dimension n, in
-// fast memory) with F^T F = G up to a remainder whose largest diagonal is
-// <= tol * max(diag G).  Stops at rmax rows; *complete is 0 if the remainder
-// was still above the threshold then.  diag: n doubles, used: n ints scratch.
-__device__ int block_pchol_ll(const double* G, int n, double* F, int rmax, double tol, double* diag,
-                              int* used, double* red, int* complete) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < n; i += nt) {
-    diag[i] = G[i * n + i];
-    used[i] = 0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, diag[i]);
-    red[0] = m;
-  }
-  __syncthreads();
-  const double thr = tol * red[0];
-  __syncthreads();
-  int r = 0;
-  int done = 0;
-  for (int k = 0; k < rmax; ++k) {
-    if (tid == 0) {
-      int p = -1;
-      double best = -1.0;
-      for (int i = 0; i < n; ++i)
-        if (!used[i] && diag[i] > best) {
-          best = diag[i];
-          p = i;
-        }
-      red[1] = double(p);
-      red[0] = best;
-      if (p >= 0) used[p] = 1;
-    }
-    __syncthreads();
-    const int p = int(red[1]);
-    const double piv = red[0];
-    if (p < 0 || !(piv > thr)) {
-      done = 1;
-      break;
-    }
-    const double rp = sqrt(piv);
-    for (int i = tid; i < n; i += nt) {
-      double v = G[p * n + i];
-      for (int j = 0; j < k; ++j) v -= F[j * n + p] * F[j * n + i];
-      v = used[i] ? 0.0 : v / rp;
-      if (i == p) v = rp;
-      F[k * n + i] = v;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += nt) diag[i] = used[i] ? 0.0 : diag[i] - F[k * n + i] * F[k * n + i];
-    __syncthreads();
-    r = k + 1;
-  }
-  if (!done && r == rmax) {
-    // check the remainder once more
-    if (tid == 0) {
-      double m = 0.0;
-      for (int i = 0; i < n; ++i)
-        if (!used[i]) m = fmax(m, diag[i]);
-      red[0] = m;
-    }
-    __syncthreads();
-    done = red[0] <= thr;
-    __syncthreads();
-  }
-  *complete = done;
-  return r;
-}
-
-// Orthonormalises the b columns of X (n x b, row-major, leading dimension b)
-// in place by classical Gram-Schmidt applied twice per column.  A column whose
-// norm falls below 1e-13 of its norm before projection is set to zero.
-// dots: b doubles scratch.
-__device__ void block_cgs2(double* X, int n, int b, double* dots, double* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  for (int j = 0; j < b; ++j) {
-    // norm before projection
-    if (tid == 0) red[2] = 0.0;
-    __syncthreads();
-    if (wv == 0) {
-      double q = 0.0;
-      for (int e = lane; e < n; e += 64) q += X[e * b + j] * X[e * b + j];
-      q = team_sum(q, 64);
-      if (lane == 0) red[2] = q;
-    }
-    __syncthreads();
-    const double n0 = sqrt(red[2]);
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = wv; i < j; i += nw) {
-        double d = 0.0;
-        for (int e = lane; e < n; e += 64) d += X[e * b + i] * X[e * b + j];
-        d = team_sum(d, 64);
-        if (lane == 0) dots[i] = d;
-      }
-      __syncthreads();
-      for (int e = tid; e < n; e += nt) {
-        double v = X[e * b + j];
-        for (int i = 0; i < j; ++i) v -= dots[i] * X[e * b + i];
-        X[e * b + j] = v;
-      }
-      __syncthreads();
-    }
-    if (wv == 0) {
-      double q = 0.0;
-      for (int e = lane; e < n; e += 64) q += X[e * b + j] * X[e * b + j];
-      q = team_sum(q, 64);
-      if (lane == 0) red[2] = q;
-    }
-    __syncthreads();
-    const double nj = sqrt(red[2]);
-    const double inv = (nj > 1e-13 * n0 && nj > 0.0) ? 1.0 / nj : 0.0;
-    for (int e = tid; e < n; e += nt) X[e * b + j] *= inv;
-    __syncthreads();
-  }
-}
-
-// Value of v in lane src (uniform) of the wavefront, in every lane.
-__device__ __forceinline__ double wave_bcast(double v, int src) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Lowest lane whose pred is true (64 if none).
-__device__ __forceinline__ int wave_first(bool pred) {
-  const unsigned long long m = __ballot(pred);
-  return m ? __builtin_ctzll(m) : 64;
-}
-
-// v moved across lanes by a DPP pattern (a compile-time dpp_ctrl code).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Sum over the 64 lanes, the same value in every lane: butterflies within each

@@ -26,7 +26,8 @@ namespace tn3d {
 namespace {
 
 constexpr int NT = 256;
-constexpr int SNT = 64;    // one wavefront per bond truncation: barriers stay cheap
+constexpr int SNT = 64;       // one wavefront per small bond truncation: barriers stay cheap
+constexpr int SNT_BIG = 256;  // four wavefronts per large one
 constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
 constexpr int MAXCHI = 64;
 
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   const int tw = ngrp * cw;  // tile width (>= ncols, padded with zeros)
   if (cw <= cwlo || cw > NMAX) return;
   __shared__ double slam[4][MAXCHI];
-  __shared__ double tile[GTR * 64];  // tw <= 64 when ncols <= 64
+  __shared__ double tile[GTR * 65];  // rows of tw <= 64 entries, stride tw + 1 (no bank conflicts)
   __shared__ int colofs[64];
   __shared__ int rowbase[GTR];
   __shared__ double rowsc[GTR];
@@ -228,12 +229,12 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
     for (int e = tid; e < GTR * tw; e += 64) {
       const int rl = e & (GTR - 1), col = e / GTR;
       const int off = colofs[col];
-      tile[rl * tw + col] = (rl < nr && off >= 0) ? double(t[rowbase[rl] + off]) * rowsc[rl] : 0.0;
+      tile[rl * (tw + 1) + col] = (rl < nr && off >= 0) ? double(t[rowbase[rl] + off]) * rowsc[rl] : 0.0;
     }
     __syncthreads();
     if (act)
       for (int rl = 0; rl < nr; ++rl) {
-        const double* tr = tile + rl * tw;
+        const double* tr = tile + rl * (tw + 1);
         const double ti = tr[i];
 #pragma unroll
         for (int k = 0; k < NMAX; ++k)
@@ -264,20 +265,47 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
   const double* PA = A.pool + g.pA;
   const double* PB = A.pool + g.pB;
   const int nA = dA * D, nB = dB * D;
+  if (dA <= 4 && dB <= 4) {
+    // one bond pair (b, b2) per thread: its dA^2 and dB^2 Gram entries loaded
+    // together into registers, then every (k, k2) block entry from them (the
+    // gate tables are read at thread-uniform addresses)
+    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+      const int b = e / D, b2 = e - b * D;
+      double ga[16], gb[16];
+#pragma unroll
+      for (int pq = 0; pq < 16; ++pq) {
+        const int p = pq >> 2, q = pq & 3;
+        const int pa = p < dA ? p : 0, qa = q < dA ? q : 0, pb = p < dB ? p : 0, qb = q < dB ? q : 0;
+        const double xa = GA[(pa * D + b) * nA + qa * D + b2];
+        const double xb = GB[(pb * D + b) * nB + qb * D + b2];
+        ga[pq] = (p < dA && q < dA) ? xa : 0.0;
+        gb[pq] = (p < dB && q < dB) ? xb : 0.0;
+      }
+      for (int k = 0; k < K; ++k)
+        for (int k2 = 0; k2 < K; ++k2) {
+          const double* wa = PA + (k * K + k2) * dA * dA;
+          const double* wb = PB + (k * K + k2) * dB * dB;
+          double za = 0.0, zb = 0.0;
+#pragma unroll
+          for (int pq = 0; pq < 16; ++pq) {
+            const int p = pq >> 2, q = pq & 3;
+            if (p < dA && q < dA) za = fma(wa[p * dA + q], ga[pq], za);
+            if (p < dB && q < dB) zb = fma(wb[p * dB + q], gb[pq], zb);
+          }
+          ZA[(k * D + b) * n + k2 * D + b2] = za;
+          ZB[(k * D + b) * n + k2 * D + b2] = zb;
+        }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int r = e / n, c = e % n;
     const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
     double za = 0.0, zb = 0.0;
     for (int p = 0; p < dA; ++p)
-      for (int q = 0; q < dA; ++q) {
-        const double w = PA[((k * K + k2) * dA + p) * dA + q];
-        if (w != 0.0) za += w * GA[(p * D + b) * nA + q * D + b2];
-      }
+      for (int q = 0; q < dA; ++q) za = fma(PA[((k * K + k2) * dA + p) * dA + q], GA[(p * D + b) * nA + q * D + b2], za);
     for (int p = 0; p < dB; ++p)
-      for (int q = 0; q < dB; ++q) {
-        const double w = PB[((k * K + k2) * dB + p) * dB + q];
-        if (w != 0.0) zb += w * GB[(p * D + b) * nB + q * D + b2];
-      }
+      for (int q = 0; q < dB; ++q) zb = fma(PB[((k * K + k2) * dB + p) * dB + q], GB[(p * D + b) * nB + q * D + b2], zb);
     ZA[e] = za;
     ZB[e] = zb;
   }
@@ -285,8 +313,9 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
 
 // Gates with nlo < K D <= nhi only: the launch's LDS holds matrices of order
 // nhi, so small gates run in a launch with small LDS and many workgroups per CU.
-__global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
-                                              double* wout, int ncap, int nlo, int nhi) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
+                                             double* wout, int ncap, int nlo, int nhi) {
   extern __shared__ double sm[];
   const int gi = blockIdx.x, sweep = blockIdx.y, tid = threadIdx.x;
   const DevGate g = gates[gi];
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
   const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
   const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
   // C = F_A F_B^T (rA x rB) into ZA
-  for (int e = tid; e < rA * rB; e += SNT) {
+  for (int e = tid; e < rA * rB; e += NT) {
     const int i = e / rB, j = e % rB;
     double s = 0.0;
     for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
@@ -329,7 +358,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
       if (nsw >= 40) atomicOr(&A.flags[sweep], 8u);
     }
     block_norms_sorted(ZA, 1, rB, rB, rA, S, ord);
-    for (int m = tid; m < rB; m += SNT) Ss[m] = S[ord[m]];
+    for (int m = tid; m < rB; m += NT) Ss[m] = S[ord[m]];
     __syncthreads();
     Dn = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &split);
     s1 = Ss[0];
@@ -352,41 +381,71 @@ __global__ __launch_bounds__(SNT) void k_solve(SweepArgs A, const DevGate* gates
     if (split) f |= 2u;
     if (f) atomicOr(&A.flags[sweep], f);
   }
-  for (int m = tid; m < Dn; m += SNT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
   const double* OA = A.pool + g.oA;
   const double* OB = A.pool + g.oB;
   const int ncA = dA * Dn, ncB = dB * Dn;
-  for (int e = tid; e < nA * ncA; e += SNT) {
-    double w = 0.0;
-    if (!bad) {
+  if (bad) {
+    for (int e = tid; e < nA * ncA; e += NT) WA[2 + e] = 0.0;
+    for (int e = tid; e < nB * ncB; e += NT) WB[2 + e] = 0.0;
+  } else if (K <= 4) {
+    // one (bond index b, kept vector m) pair per thread: the K projections
+    // phi_k(b, m) of side B's factor (for W_A) and of side A's (for W_B) onto
+    // the kept singular vector once, then every (p, p2) entry from them
+    for (int e = tid; e < D * Dn; e += NT) {
+      const int b = e / Dn, m = e - b * Dn, om = ord[m];
+      double phA[4], phB[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double pa = 0.0, pb = 0.0;
+        if (k < K) {
+          for (int j = 0; j < rB; ++j) pa = fma(VM[j * n + k * D + b], ZB[j * rB + om], pa);
+          for (int i = 0; i < rA; ++i) pb = fma(CM[i * n + k * D + b], ZA[i * rB + om], pb);
+        }
+        phA[k] = pa;
+        phB[k] = pb;
+      }
+      const double sA = sqrt(Ss[m] / s1) / Ss[m], sB = sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]);
+      for (int p = 0; p < dA; ++p)
+        for (int p2 = 0; p2 < dA; ++p2) {
+          double w = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < K) w = fma(OA[(k * dA + p2) * dA + p], phA[k], w);
+          WA[2 + (p * D + b) * ncA + p2 * Dn + m] = w * sA;
+        }
+      for (int p = 0; p < dB; ++p)
+        for (int p2 = 0; p2 < dB; ++p2) {
+          double w = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < K) w = fma(OB[(k * dB + p2) * dB + p], phB[k], w);
+          WB[2 + (p * D + b) * ncB + p2 * Dn + m] = w * sB;
+        }
+    }
+  } else {
+    for (int e = tid; e < nA * ncA; e += NT) {
       const int row = e / ncA, col = e % ncA;
       const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      double w = 0.0;
       for (int k = 0; k < K; ++k) {
-        const double o = OA[(k * dA + p2) * dA + p];
-        if (o == 0.0) continue;
         double phi = 0.0;
-        for (int j = 0; j < rB; ++j) phi += VM[j * n + k * D + b] * ZB[j * rB + ord[m]];
-        w += o * phi;
+        for (int j = 0; j < rB; ++j) phi = fma(VM[j * n + k * D + b], ZB[j * rB + ord[m]], phi);
+        w = fma(OA[(k * dA + p2) * dA + p], phi, w);
       }
-      w *= sqrt(Ss[m] / s1) / Ss[m];
+      WA[2 + e] = w * (sqrt(Ss[m] / s1) / Ss[m]);
     }
-    WA[2 + e] = w;
-  }
-  for (int e = tid; e < nB * ncB; e += SNT) {
-    double w = 0.0;
-    if (!bad) {
+    for (int e = tid; e < nB * ncB; e += NT) {
       const int row = e / ncB, col = e % ncB;
       const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      double w = 0.0;
       for (int k = 0; k < K; ++k) {
-        const double o = OB[(k * dB + p2) * dB + p];
-        if (o == 0.0) continue;
         double phi = 0.0;
-        for (int i = 0; i < rA; ++i) phi += CM[i * n + k * D + b] * ZA[i * rB + ord[m]];
-        w += o * phi;
+        for (int i = 0; i < rA; ++i) phi = fma(CM[i * n + k * D + b], ZA[i * rB + ord[m]], phi);
+        w = fma(OB[(k * dB + p2) * dB + p], phi, w);
       }
-      w *= sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]);
+      WB[2 + e] = w * (sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]));
     }
-    WB[2 + e] = w;
   }
 }
 
@@ -982,8 +1041,11 @@ __global__ void k_scatter_out(int n, const int32_t* items, const double* lp_loca
 hipError_t set_kernel_lds_limits() {
   const int kmax = 64;  // gate rank x chi, checked by the host
   const int solve = 4 * kmax * kmax * 8 + 2 * kmax * 8 + 32 + (2 * kmax + 4) * 4;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve<SNT>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, solve);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve<SNT_BIG>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            solve);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_b), hipFuncAttributeMaxDynamicSharedMemorySize,
                             18432 * 8);
@@ -1037,13 +1099,15 @@ static size_t solve_lds(int n) {
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
-  // two size classes: order <= 16 (8 KB of LDS) and the rest up to kdcap
+  // two size classes: order <= 16 (8 KB of LDS, one wavefront) and the rest
+  // up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
+  // wavefronts share each problem)
   const int nsmall = kdcap < 16 ? kdcap : 16;
-  hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin, wout,
-                     ncap, 0, nsmall);
+  hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
+                     wout, ncap, 0, nsmall);
   if (kdcap > nsmall)
-    hipLaunchKernelGGL(k_solve, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(kdcap), st, A, gates, n_g, gin, wout,
-                       ncap, nsmall, kdcap);
+    hipLaunchKernelGGL(k_solve<SNT_BIG>, dim3(n_g, A.n_sweeps), dim3(SNT_BIG), solve_lds(kdcap), st, A, gates, n_g,
+                       gin, wout, ncap, nsmall, kdcap);
 }
 
 void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
