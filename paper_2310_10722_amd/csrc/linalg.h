@@ -268,16 +268,30 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
   for (int m0 = 0; m0 < M; m0 += 64)
     for (int n0 = 0; n0 < N; n0 += 64) {
       double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      // this thread's four A and four B operands of a K slice, fetched into
+      // registers one slice ahead so that their loads overlap the FMAs
+      double ra[4], rb[4];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = tid + 512 * i;
+          const int kk = e >> 6, mm = e & 63;
+          const int m = m0 + mm, n = n0 + mm, k = k0 + kk;
+          ra[i] = (m < M && k < K) ? a_at(m, k) : 0.0;
+          rb[i] = (n < N && k < K) ? b_at(k, n) : 0.0;
+        }
+      };
+      __syncthreads();  // the previous tile's stores land before this tile's loads
+      fetch(0);
       for (int k0 = 0; k0 < K; k0 += 32) {
         __syncthreads();
-        for (int e = tid; e < 2048; e += 512) {
-          const int kk = e >> 6, mm = e & 63;
-          const int m = m0 + mm, k = k0 + kk;
-          As[e] = (m < M && k < K) ? a_at(m, k) : 0.0;
-          const int n = n0 + mm;
-          Bs[e] = (n < N && k < K) ? b_at(k, n) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          As[tid + 512 * i] = ra[i];
+          Bs[tid + 512 * i] = rb[i];
         }
         __syncthreads();
+        if (k0 + 32 < K) fetch(k0 + 32);
 #pragma unroll 8
         for (int kk = 0; kk < 32; ++kk) {
           double a[4], b[2];
