@@ -132,7 +132,10 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
 // floor_rel * (largest initial norm) are left alone: such vectors hold only
 // rounding noise of the large ones, cannot be orthogonalised to relative
 // precision tol, and lie below the truncation threshold.  Returns the number
-// of sweeps; max_sweeps means no convergence.  red: 2 doubles scratch.
+// of sweeps before the last; max_sweeps means no convergence.  A sweep whose
+// rotations all had |a_i . a_j| <= sqrt(tol) |a_i| |a_j| ends the iteration:
+// one-sided Jacobi converges quadratically, so what it leaves is of order
+// tol.  red: 2 doubles scratch, flag: 2 ints.
 __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double* J, double tol,
                             double floor_rel, int max_sweeps, int* flag, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -157,9 +160,13 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
   __syncthreads();
   const double floor2 = floor_rel * floor_rel * red[0];
   __syncthreads();
+  const double sqrt_tol = sqrt(tol);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) *flag = 0;
+    if (tid == 0) {
+      flag[0] = 0;  // a rotation was applied
+      flag[1] = 0;  // a rotation had cosine of the angle above sqrt(tol)
+    }
     __syncthreads();
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
       for (int pp = pair; pp < npairs; pp += nt / team) {
@@ -167,9 +174,11 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
         if (pp == 0) {
           i = ne - 1;
           j = rnd;
-        } else {
-          i = (rnd + pp) % (ne - 1);
-          j = (rnd - pp + ne - 1) % (ne - 1);
+        } else {  // (rnd + pp) and (rnd - pp) mod (ne - 1), both in range after one correction
+          i = rnd + pp;
+          i = i >= ne - 1 ? i - (ne - 1) : i;
+          j = rnd - pp + ne - 1;
+          j = j >= ne - 1 ? j - (ne - 1) : j;
         }
         if (i >= nv || j >= nv) continue;
         if (i > j) {
@@ -187,7 +196,8 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
         a = team_sum(a, team);
         b = team_sum(b, team);
         g = team_sum(g, team);
-        if (a > floor2 && b > floor2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+        const double sab = sqrt(a) * sqrt(b);
+        if (a > floor2 && b > floor2 && fabs(g) > tol * sab) {
           double zeta = (b - a) / (2.0 * g);
           double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -201,12 +211,16 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
             J[e * nv + i] = cs * x - sn * y;
             J[e * nv + j] = sn * x + cs * y;
           }
-          if (lane == 0) *flag = 1;
+          if (lane == 0) {
+            flag[0] = 1;
+            if (fabs(g) > sqrt_tol * sab) flag[1] = 1;
+          }
         }
       }
       __syncthreads();
     }
-    if (*flag == 0) break;
+    if (flag[0] == 0) break;
+    if (flag[1] == 0) break;  // every cosine below sqrt(tol): the next sweep would only square them
     __syncthreads();
   }
   __syncthreads();
@@ -469,14 +483,14 @@ __device__ void wave_tridiag(const double* G, double gs, int n, double* vw, doub
                              double& br) {
   const int i = threadIdx.x;
   double a[64];
-  // every lane loads all 64 entries (clamped into the matrix) so that the loads
-  // are issued together; entries outside the n x n block are zeroed after
+  // every lane loads all 64 entries (clamped into the matrix) and scales them by
+  // gs or by 0 outside the n x n block: every loaded value is used, so the
+  // loads cannot be moved behind branches and are issued together
   const int ic = i < n ? i : n - 1;
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
     const int jc = j < n ? j : n - 1;
-    const double g = G[jc * n + ic];
-    a[j] = (j < n && i < n) ? g * gs : 0.0;
+    a[j] = G[jc * n + ic] * ((j < n && i < n) ? gs : 0.0);
   }
   er = 0.0;
   br = 0.0;
@@ -911,8 +925,7 @@ __device__ void tri_backtransform_regs(const double* Hv, double br, int n, int D
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int k = n - 3 - s;
-      const double x = Hv[(k >= 0 ? k : 0) * n + lc];
-      pf[s] = (k >= 0 && lane < n) ? x : 0.0;
+      pf[s] = Hv[(k >= 0 ? k : 0) * n + lc] * ((k >= 0 && lane < n) ? 1.0 : 0.0);
     }
   }
   for (int g = 0; g < ng; ++g) {
@@ -923,8 +936,7 @@ __device__ void tri_backtransform_regs(const double* Hv, double br, int n, int D
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int k = n - 3 - 8 * (g + 1) - s;
-        const double x = Hv[(k >= 0 ? k : 0) * n + lc];
-        pf[s] = (k >= 0 && lane < n) ? x : 0.0;
+        pf[s] = Hv[(k >= 0 ? k : 0) * n + lc] * ((k >= 0 && lane < n) ? 1.0 : 0.0);
       }
     }
     __syncthreads();

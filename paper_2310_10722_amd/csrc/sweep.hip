@@ -276,10 +276,10 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
       for (int pq = 0; pq < 16; ++pq) {
         const int p = pq >> 2, q = pq & 3;
         const int pa = p < dA ? p : 0, qa = q < dA ? q : 0, pb = p < dB ? p : 0, qb = q < dB ? q : 0;
-        const double xa = GA[(pa * D + b) * nA + qa * D + b2];
-        const double xb = GB[(pb * D + b) * nB + qb * D + b2];
-        ga[pq] = (p < dA && q < dA) ? xa : 0.0;
-        gb[pq] = (p < dB && q < dB) ? xb : 0.0;
+        // multiplied by a 0/1 mask rather than selected, so that every load is
+        // issued together (a selected value lets the compiler branch around it)
+        ga[pq] = GA[(pa * D + b) * nA + qa * D + b2] * ((p < dA && q < dA) ? 1.0 : 0.0);
+        gb[pq] = GB[(pb * D + b) * nB + qb * D + b2] * ((p < dB && q < dB) ? 1.0 : 0.0);
       }
       for (int k = 0; k < K; ++k)
         for (int k2 = 0; k2 < K; ++k2) {
@@ -326,6 +326,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   // launch of the pair may already have changed this bond's dimension)
   const int n0 = A.gate_n[int64_t(sweep) * n_g + gi];
   if (n0 <= nlo || n0 > nhi) return;
+  const double logb_in = A.logb[bidx];  // loaded early, used at the end
   double* ZA = sm;
   double* ZB = ZA + n * n;
   double* CM = ZB + n * n;
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     WA[0] = WB[0] = double(D);
     WA[1] = WB[1] = double(Dn);
     A.bond_dim[bidx] = Dn;
-    A.logb[bidx] += log(s1);
+    A.logb[bidx] = logb_in + log(s1);
     uint32_t f = 0;
     if (bad) f |= 1u;
     if (split) f |= 2u;

@@ -1,7 +1,9 @@
 """GPU parity: the HIP sweep (through the C-ABI) against the CPU oracle.
 
 Tolerances: FP64 path |d log p| <= 1e-9 against the fixed-chi oracle at the
-same chi / chi_m / rank rule; FP32 path |d log p| <= 1e-3 against the same
+same chi / chi_m / rank rule (the default FP64 rule, Jacobi everywhere);
+FP64 with the reduced-precision rule that the benchmark times (Gram route in
+the boundary MPS) <= 1e-6; FP32 path |d log p| <= 1e-3 against the same
 oracle; untruncated chi against the exact frontier contraction <= 1e-9.
 """
 
@@ -222,6 +224,36 @@ def test_rotated_d5_full_batch_sampled(ctx):
     assert err.max() <= 1e-3
     best = np.argmax(ref, axis=1)
     assert np.all((coset[idx] == best) | (np.abs(ref[:, 0] - ref[:, 1]) <= 2e-3))
+
+
+def test_rotated_d5_full_batch_headline_fp64(ctx):
+    """The benchmark's timed configuration: the full 1024-syndrome batch,
+    FP64 site tensors, rank rule eps_rel 1e-6 / tau_gap 1e-4 (the boundary MPS
+    then takes the Gram route), one decode call with graph replay.  Sampled
+    items against the oracle at the same chi and rule.  Bound 1e-6: the Gram
+    route keeps the kept singular values to about eps_64 / eps_rel^2 relative
+    (5e-5 for the smallest, far less for the large ones that carry log p); the
+    measured maximum over the whole batch is below 1e-7."""
+    from paper_2310_10722_amd import tn3d
+    say("case: rotated d=5 T=5 chi=16 fp64, rule 1e-6/1e-4, full batch of 1024, 24 sampled items")
+    dem, m, _, _ = synth.config_workload(2)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    syn = torch.from_numpy(m).cuda()
+    for _ in range(2):  # the second call replays the captured sequence
+        coset, lr, logp, flags = tn3d.tn3d_decode(ctx, net, syn, prm)
+    torch.cuda.synchronize()
+    coset, logp, flags = coset.cpu().numpy(), logp.cpu().numpy(), flags.cpu().numpy()
+    assert np.all(np.isfinite(logp[:, :2]).all(axis=1) | ((flags & tn3d.FLAG_NUMERIC) != 0))
+    idx = np.linspace(0, 1023, 24).astype(int)
+    ref = oracle_rot(dem, m[idx], prm)
+    fin = np.isfinite(ref).all(axis=1)
+    err = np.abs(logp[idx, :2] - ref)[fin]
+    say("  max |d log p| =", err.max())
+    assert err.max() <= 1e-6
+    best = np.argmax(ref[fin], axis=1)
+    assert np.all((coset[idx][fin] == best) | (np.abs(ref[fin, 0] - ref[fin, 1]) <= 2e-6))
 
 
 def test_unsupported_width_is_refused(ctx):
