@@ -43,6 +43,34 @@ __device__ __forceinline__ double team_sum(double v, int team) {
   return v;
 }
 
+// The largest v over the wavefront and the lowest lane holding it, in every
+// lane: DPP exchanges within rows of 16 lanes, then the four row winners read
+// out in order.  Every lane must be active.
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+  auto step = [&](double w, int j) {
+    if (w > v || (w == v && j < idx)) {
+      v = w;
+      idx = j;
+    }
+  };
+  step(dpp_move<0xB1>(v), __builtin_amdgcn_update_dpp(0, idx, 0xB1, 0xF, 0xF, false));
+  step(dpp_move<0x4E>(v), __builtin_amdgcn_update_dpp(0, idx, 0x4E, 0xF, 0xF, false));
+  step(dpp_move<0x141>(v), __builtin_amdgcn_update_dpp(0, idx, 0x141, 0xF, 0xF, false));
+  step(dpp_move<0x140>(v), __builtin_amdgcn_update_dpp(0, idx, 0x140, 0xF, 0xF, false));
+  double bv = wave_bcast(v, 0);
+  int bi = __builtin_amdgcn_readlane(idx, 0);
+  for (int r = 16; r < 64; r += 16) {
+    const double w = wave_bcast(v, r);
+    const int j = __builtin_amdgcn_readlane(idx, r);
+    if (w > bv || (w == bv && j < bi)) {
+      bv = w;
+      bi = j;
+    }
+  }
+  v = bv;
+  idx = bi;
+}
+
 // Pivoted Cholesky of the symmetric positive semidefinite n x n matrix Z
 // (row-major, leading dimension n; destroyed).  Writes F (r x n, row-major,
 // leading dimension n) with F^T F = Z up to the dropped trailing part, in the
@@ -65,14 +93,7 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
     if (tid < 64) {  // pivot: the largest remaining diagonal, lowest index on ties
       double best = (tid >= k && tid < n) ? Z[tid * n + tid] : -1e300;
       int j = tid;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double b2 = __shfl_xor(best, o, 64);
-        const int j2 = __shfl_xor(j, o, 64);
-        if (b2 > best || (b2 == best && j2 < j)) {
-          best = b2;
-          j = j2;
-        }
-      }
+      wave_argmax(best, j);
       if (tid == 0) {
         red[1] = double(j);
         red[0] = best;

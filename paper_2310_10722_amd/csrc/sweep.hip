@@ -834,7 +834,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
   zip_keep(Z, s, zd, nv, Sout, ord, Zm, 1, nv, fail ? 40 : 1);
 }
 
-__global__ __launch_bounds__(ZNT) void k_zip_c(ZipArgs Z, int x, int y) {
+// (at most 80 registers: six wavefronts per SIMD)
+__global__ __launch_bounds__(ZNT) __attribute__((amdgpu_waves_per_eu(6))) void k_zip_c(ZipArgs Z, int x, int y) {
   __shared__ double gst[4096];
   __shared__ double red[8];
   const int s = blockIdx.x, tid = threadIdx.x;
@@ -1100,12 +1101,17 @@ static size_t solve_lds(int n) {
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
-  // two size classes: order <= 16 (8 KB of LDS, one wavefront) and the rest
-  // up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
+  // three size classes: order <= 8 and <= 16 (2 and 8 KB of LDS, one
+  // wavefront: the smaller the LDS, the more workgroups share a CU) and the
+  // rest up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
   // wavefronts share each problem)
+  const int ntiny = kdcap < 8 ? kdcap : 8;
   const int nsmall = kdcap < 16 ? kdcap : 16;
-  hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
-                     wout, ncap, 0, nsmall);
+  hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(ntiny), st, A, gates, n_g, gin, wout,
+                     ncap, 0, ntiny);
+  if (nsmall > ntiny)
+    hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
+                       wout, ncap, ntiny, nsmall);
   if (kdcap > nsmall)
     hipLaunchKernelGGL(k_solve<SNT_BIG>, dim3(n_g, A.n_sweeps), dim3(SNT_BIG), solve_lds(kdcap), st, A, gates, n_g,
                        gin, wout, ncap, nsmall, kdcap);
