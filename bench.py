@@ -10,11 +10,16 @@ reduced-precision rank rule (eps_rel 1e-6, tau_gap 1e-4); the same batch
 with FP32 site tensors is reported beside it (same rule).
 
 Prints one JSON line.  Besides throughput it reports
-  roofline      the Gram + reabsorption kernels (the layer-absorption
+  roofline      the dominant kernel, k_zip_beig (leading eigenpairs of the
+                boundary-MPS Grams): algorithmic FP64 flops counted on the
+                device over its time inside the timed steps (device wall-clock
+                stamps around its launches), against the FP64 vector peak;
+                traffic from the committed rocprofv3 counter summary when it
+                matches the kernel sources;
+  roofline_streaming  the Gram + reabsorption kernels (the layer-absorption
                 contractions that stream the site tensors): algorithmic bytes
                 (every site tensor read by its Gram and read + written by its
-                reabsorption, counted by the kernels) over their time inside
-                the timed steps (device wall-clock stamps between launches),
+                reabsorption, counted by the kernels) over their stamped time,
                 against 8 TB/s HBM;
   cpu_baseline  the CPU oracle (fixed-chi FP64 sweep, same rule) on the same
                 syndromes, one process per core;
@@ -60,6 +65,41 @@ def workload(cfg: int):
         return dem, m, dict(family="point", L=3, chi=4, chi_mps=4, prec=0, dtype="f64", rule=None, alt_prec=None,
                             desc=desc)
     raise SystemExit(f"no benchmark workload {cfg}")
+
+
+PMC_PROFILE = os.path.join(ROOT, "profiles", "pmc_k_zip_beig_rotated_d5_chi16_fp64.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_10722_amd", "csrc", f) for f in ("linalg.h", "sweep.hip")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of k_zip_beig from the committed counter summary
+    (2 x FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        with open(PMC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    rec = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    if rec.get("kernel source sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def params(tn3d, w, prec):
@@ -214,7 +254,9 @@ def main():
         roof = {"bound": "alu", "kernel": "k_zip_beig (boundary-MPS leading eigenpairs, FP64)",
                 "achieved": tf, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": tf / FP64_VALU_PEAK_TFS,
                 "algorithmic_flops_per_launch": eig_flops / eig_launch, "avg_launch_ms": eig_ms / eig_launch,
-                "traffic": None}
+                "traffic": recorded_traffic(),
+                "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE (copy-calibrated), "
+                                "null unless taken on the current kernel sources"}
     out = {
         "metric": METRIC,
         "value": value,
