@@ -128,10 +128,11 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
       else if (i > k) Z[k * n + i] /= rk;
     }
     __syncthreads();
-    const int m = n - k - 1;
-    for (int e = tid; e < m * m; e += nt) {
-      int a = k + 1 + e / m, b = k + 1 + e % m;
-      Z[a * n + b] -= Z[k * n + a] * Z[k * n + b];
+    // trailing update: 16 columns per pass of a row, nt / 16 rows per pass
+    // (no integer division in the loop)
+    for (int a = k + 1 + (tid >> 4); a < n; a += nt >> 4) {
+      const double za = Z[k * n + a];
+      for (int b = k + 1 + (tid & 15); b < n; b += 16) Z[a * n + b] -= za * Z[k * n + b];
     }
     __syncthreads();
     r = k + 1;
@@ -160,7 +161,8 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
 __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double* J, double tol,
                             double floor_rel, int max_sweeps, int* flag, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < nv * nv; e += nt) J[e] = (e / nv == e % nv) ? 1.0 : 0.0;
+  for (int r = tid >> 4; r < nv; r += nt >> 4)
+    for (int c = tid & 15; c < nv; c += 16) J[r * nv + c] = r == c ? 1.0 : 0.0;
   const int ne = nv + (nv & 1);
   const int npairs = ne / 2;
   int team = 64;
@@ -248,6 +250,15 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
   return sweep;
 }
 
+// Strict total order for a descending sort with ties broken by index: a NaN
+// sorts after every number, so the ranks it gives always form a permutation
+// (indices taken from them stay in range whatever the data).
+__device__ __forceinline__ bool sorts_before(double a, int ia, double b, int ib) {
+  const bool na = a != a, nb = b != b;
+  if (na || nb) return !na && nb ? true : (na && nb && ia < ib);
+  return a > b || (a == b && ia < ib);
+}
+
 // Norms of the nv vectors into S and the permutation `order` that sorts them
 // descending (ties by index).
 __device__ void block_norms_sorted(const double* A, long vs, long es, int nv, int len, double* S,
@@ -265,7 +276,7 @@ __device__ void block_norms_sorted(const double* A, long vs, long es, int nv, in
   for (int v = tid; v < nv; v += nt) {
     int rank = 0;
     for (int u = 0; u < nv; ++u)
-      if (S[u] > S[v] || (S[u] == S[v] && u < v)) ++rank;
+      if (sorts_before(S[u], u, S[v], v)) ++rank;
     order[rank] = v;
   }
   __syncthreads();

@@ -343,12 +343,12 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
   const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
   // C = F_A F_B^T (rA x rB) into ZA
-  for (int e = tid; e < rA * rB; e += NT) {
-    const int i = e / rB, j = e % rB;
-    double s = 0.0;
-    for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
-    ZA[e] = s;
-  }
+  for (int i = tid >> 4; i < rA; i += NT >> 4)
+    for (int j = tid & 15; j < rB; j += 16) {
+      double s = 0.0;
+      for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
+      ZA[i * rB + j] = s;
+    }
   __syncthreads();
   int Dn = 0, split = 0;
   double s1 = 0.0;
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
     const double lv = dv[v];
     int rk = 0;
     for (int u = 0; u < nv; ++u)
-      if (dv[u] > lv || (dv[u] == lv && u < v)) ++rk;
+      if (sorts_before(dv[u], u, lv, v)) ++rk;
     ord[rk] = v;
   }
   __syncthreads();
