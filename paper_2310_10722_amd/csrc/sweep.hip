@@ -501,7 +501,8 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
     T* dst = out + (a * Dn * v.Cp + c) * d;
     double x[NMAX];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) x[k] = k < nin ? double(src[colin[k]]) : 0.0;
+    for (int k = 0; k < NMAX; ++k)  // every load issued (a valid address, times 0 past nin)
+      x[k] = double(src[colin[k < nin ? k : 0]]) * (k < nin ? 1.0 : 0.0);
     for (int q4 = 0; q4 < n4; ++q4) {
       double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
