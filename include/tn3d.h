@@ -161,9 +161,15 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
 /* Timing of the contractions on this context: enable = 0 off, 1 kernel times,
  * 2 kernel times and bond statistics (tn3d_last_stats; this level copies the
  * bond dimensions and lambdas of every sweep to the host after each call).
- * Times come from device wall-clock stamps written by one-thread kernels
- * enqueued between the launches, so they are taken on the context stream,
- * inside captured graphs as well.  tn3d_last_timing: out[0] = layer
+ * Every call of tn3d_ctx_set_timing restarts the sums; tn3d_last_timing and
+ * tn3d_last_stats report the sums over the contractions since then.  Level 1
+ * keeps its sums on the device (no host synchronisation per contraction);
+ * tn3d_last_timing waits for the context stream.
+ * Times come from the device wall clock: the phase times from one-thread
+ * kernels enqueued at the phase boundaries, the kernel times from execution
+ * windows the kernels record themselves (earliest workgroup start to latest
+ * workgroup end of the launch), so they hold inside captured graphs as well
+ * and add no launches around the kernels.  tn3d_last_timing: out[0] = layer
  * absorption (one-site ops, Grams, truncations, reabsorption, rescaling),
  * out[1] = final boundary MPS, out[2] = Gram + reabsorption kernels only,
  * out[3] = number of Gram + reabsorption launches, out[4] = algorithmic bytes

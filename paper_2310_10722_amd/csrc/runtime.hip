@@ -38,7 +38,6 @@ struct GraphKey {
 
 struct GraphEntry {
   hipGraphExec_t exec;
-  size_t hot_i;  // timing events the sequence records
   double hot_l;  // Gram + reabsorption launches in it
 };
 
@@ -50,7 +49,8 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   int timing = 0;                  // 1: kernel times, 2: also bond statistics
   int wclk_khz = 100000;           // device wall-clock rate
-  double timing_out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double timing_out[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // launch counts (3, 6) kept on the host
+  double* tacc = nullptr;          // device sums of the times, bytes and flops since timing was set
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
   int last_resweeps = 0;           // items the last decode re-swept in FP64
@@ -317,9 +317,14 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   // 64 byte counters (spread to keep atomics uncontended), then the sweep maxima
   // 64 byte counters, the sweep maxima, 64 flop counters (spread to keep atomics uncontended)
   size_t o_ctr = cv.take<unsigned long long>(129);
-  const size_t zip_stamp0 = 3 + P.layers.size() * 16;
-  const size_t n_stamp = zip_stamp0 + 2 * size_t(P.Lx) * P.Ly;
+  // timing: stamps 0 start, 1 after the layers, 2 end; execution windows of
+  // the Gram and reabsorption launches of each gate class (2 per class) and
+  // of the decomposition launch of each boundary-MPS step
+  const size_t n_stamp = 3;
   size_t o_stamp = cv.take<unsigned long long>(n_stamp);
+  const int n_cls_win = int(P.layers.size()) * 4 * 2;
+  const int n_win = n_cls_win + P.Lx * P.Ly;
+  size_t o_win = cv.take<unsigned long long>(size_t(n_win) * 128);
   size_t o_gitems = cv.take<int32_t>(chunk_items);
   size_t o_gsoff = cv.take<int64_t>(chunk_items);
   size_t o_gsynd = cv.take<uint8_t>(chunk_items * std::max(1, P.n_det));
@@ -336,8 +341,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (items[i] != items[0] + int32_t(i)) contiguous = false;
 
   const int timing = c->timing;
-  float t_layers = 0, t_final = 0, t_hot = 0;
-  double hot_launches = 0, hot_bytes = 0, t_eig = 0, eig_launches = 0, eig_flops = 0;
+  double hot_launches = 0, eig_launches = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
     const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
     int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
@@ -349,7 +353,6 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     }
     SweepArgs A{};
     ZipArgs Z{};
-    size_t hot_i = 0;
     double hot_l = 0;
     // workspace-derived arguments (the same for eager launches and replays)
     A.n_sweeps = ni * nc;
@@ -383,7 +386,6 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     auto enqueue = [&](const int32_t* items_p, const uint8_t* synd_p, const int64_t* soff_p, double* logp_p,
                        uint32_t* flags_p, hipStream_t st) -> tn3d_status {
     const hipStream_t s = st;
-    hot_i = 0;
     hot_l = 0;
     Z = ZipArgs{};
     A.synd = synd_p;
@@ -393,7 +395,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     unsigned long long* stamp = reinterpret_cast<unsigned long long*>(ws + o_stamp);
-    if (timing) launch_stamp(stamp + 0, s);
+    unsigned long long* win = reinterpret_cast<unsigned long long*>(ws + o_win);
+    if (timing) {
+      launch_win_init(win, n_win, s);
+      launch_stamp(stamp + 0, s);
+    }
     launch_init(prec, A, n->d_init_dims, n->d_init_off, n->d_bond_dim0, s);
     for (size_t li = 0; li < P.layers.size(); ++li) {
       const LayerRange& R = P.layers[li];
@@ -402,14 +408,14 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         const int ng = R.gate1[k] - R.gate0[k];
         if (ng <= 0) continue;
         const DevGate* gp = n->d_gates + R.gate0[k];
-        if (timing) launch_stamp(stamp + 3 + hot_i, s);
+        const int cls = int(li) * 4 + k;
+        A.win = timing ? win + size_t(2 * cls) * 128 : nullptr;
         launch_gram(prec, A, gp, ng, gram, L.ncap, s);
-        if (timing) launch_stamp(stamp + 4 + hot_i, s);
+        A.win = nullptr;
         launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
-        if (timing) launch_stamp(stamp + 5 + hot_i, s);
+        A.win = timing ? win + size_t(2 * cls + 1) * 128 : nullptr;
         launch_reabsorb(prec, A, gp, ng, wbuf, L.ncap, s);
-        if (timing) launch_stamp(stamp + 6 + hot_i, s);
-        hot_i += 4;
+        A.win = nullptr;
         hot_l += 2;
       }
       launch_onesite(prec, A, n->d_ones + R.post0, R.post1 - R.post0, s);
@@ -458,9 +464,18 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
       for (int x = 0; x < P.Lx; ++x)
-        launch_zip_step(Z, x, y, timing ? stamp + zip_stamp0 + 2 * (size_t(y) * P.Lx + x) : nullptr, s);
+      {
+        Z.win = timing ? win + size_t(n_cls_win + y * P.Lx + x) * 128 : nullptr;
+        launch_zip_step(Z, x, y, s);
+      }
+    Z.win = nullptr;
     launch_finish(A, Z, logp_p, flags_p, s);
-    if (timing) launch_stamp(stamp + 2, s);
+    if (timing) {
+      launch_stamp(stamp + 2, s);
+      launch_timing_reduce(stamp, win, n_cls_win, P.Lx, P.Ly, gram_path ? 1 : 0,
+                           reinterpret_cast<const unsigned long long*>(ws + o_ctr), 1.0 / double(c->wclk_khz),
+                           c->tacc, s);
+    }
     HIPCHK(c, hipGetLastError());
     return TN3D_OK;
     };
@@ -503,12 +518,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
           c->graphs = false;
           c->err.clear();
         } else {
-          it = c->gcache.emplace(key, GraphEntry{ex, hot_i, hot_l}).first;
+          it = c->gcache.emplace(key, GraphEntry{ex, hot_l}).first;
         }
       }
       if (c->graphs) {
         HIPCHK(c, hipGraphLaunch(it->second.exec, s));
-        hot_i = it->second.hot_i;
         hot_l = it->second.hot_l;
         launch_scatter_out(ni, d_items, g_lp, g_fl, logp, flags_out, s);
         HIPCHK(c, hipGetLastError());
@@ -520,29 +534,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       if (es != TN3D_OK) return es;
     }
     hot_launches += hot_l;
-    if (timing) {
-      // stamps: 0 start, 1 after the layers, 2 end; 3 + 4 g .. 6 + 4 g around
-      // the Gram and reabsorption launches of gate class g
-      std::vector<unsigned long long> st(n_stamp);
-      HIPCHK(c, hipMemcpyAsync(st.data(), ws + o_stamp, st.size() * 8, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      const double ms_per_tick = 1.0 / double(c->wclk_khz);
-      t_layers += double(st[1] - st[0]) * ms_per_tick;
-      t_final += double(st[2] - st[1]) * ms_per_tick;
-      for (size_t h = 0; h + 3 < hot_i; h += 4)
-        t_hot += double(st[3 + h + 1] - st[3 + h] + st[3 + h + 3] - st[3 + h + 2]) * ms_per_tick;
-      if (gram_path)
-        for (int y = 0; y < P.Ly; ++y)
-          for (int x = 0; x + 1 < P.Lx; ++x) {
-            const size_t b = zip_stamp0 + 2 * (size_t(y) * P.Lx + x);
-            t_eig += double(st[b + 1] - st[b]) * ms_per_tick;
-            eig_launches += 1;
-          }
-      unsigned long long nb[129];
-      HIPCHK(c, hipMemcpy(nb, ws + o_ctr, sizeof(nb), hipMemcpyDeviceToHost));
-      for (int k = 0; k < 64; ++k) hot_bytes += double(nb[k]);
-      for (int k = 65; k < 129; ++k) eig_flops += double(nb[k]);
-    }
+    if (timing && gram_path) eig_launches += double(P.Ly) * (P.Lx - 1);
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
       std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
@@ -566,15 +558,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       c->nb_last = P.n_bonds;
     }
   }
-  if (timing) {
-    c->timing_out[0] += t_layers;
-    c->timing_out[1] += t_final;
-    c->timing_out[2] += t_hot;
+  if (timing) {  // times, bytes and flops are summed on the device (tacc)
     c->timing_out[3] += hot_launches;
-    c->timing_out[4] += hot_bytes;
-    c->timing_out[5] += t_eig;
     c->timing_out[6] += eig_launches;
-    c->timing_out[7] += eig_flops;
   }
   return TN3D_OK;
 }
@@ -619,10 +605,6 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
   for (int i = 0; i < batch; ++i)
     if (!nets[i] || nets[i]->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
   HIPCHK(c, hipSetDevice(c->device));
-  if (c->timing) {
-    for (int k = 0; k < 8; ++k) c->timing_out[k] = 0;
-    for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
-  }
   std::map<tn3d_net, std::vector<int32_t>> groups;
   std::vector<tn3d_net> order;
   for (int i = 0; i < batch; ++i) {
@@ -636,10 +618,6 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
   for (tn3d_net n : order) {
     tn3d_status s = run_group(c, n, groups[n], synd, offs, *pr, logp, flags, pr->precision);
     if (s != TN3D_OK) return s;
-  }
-  if (c->timing) {
-    // algorithmic bytes of the Gram + reabsorption launches are filled in by
-    // the caller-side accounting (see tn3d_last_timing)
   }
   return TN3D_OK;
 }
@@ -682,6 +660,12 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
     return TN3D_E_DEVICE;
   }
   c->wclk_khz = rate;
+  if (hipMalloc(&c->tacc, 8 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 8 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->tacc) (void)hipFree(c->tacc);
+    delete c;
+    return TN3D_E_DEVICE;
+  }
   *out = c;
   return TN3D_OK;
 }
@@ -694,6 +678,10 @@ void tn3d_ctx_destroy(tn3d_ctx c) {
     (void)hipFree(c->ws);
   }
   if (c->aux) (void)hipFree(c->aux);
+  if (c->tacc) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->tacc);
+  }
   drop_graphs(c, 0);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -856,7 +844,12 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
 
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   if (!c) return TN3D_E_INVALID;
+  HIPCHK(c, hipSetDevice(c->device));
   c->timing = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
+  // the sums restart here (ordered after the work already on the stream)
+  for (int k = 0; k < 8; ++k) c->timing_out[k] = 0;
+  for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
+  HIPCHK(c, hipMemsetAsync(c->tacc, 0, 8 * sizeof(double), c->stream));
   return TN3D_OK;
 }
 
@@ -875,7 +868,13 @@ tn3d_status tn3d_last_stats(tn3d_ctx c, double* out, int32_t n) {
 tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
   if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
-  for (int i = 0; i < n && i < 8; ++i) out[i] = c->timing_out[i];
+  HIPCHK(c, hipSetDevice(c->device));
+  double d[8];
+  HIPCHK(c, hipMemcpyAsync(d, c->tacc, sizeof(d), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  d[3] = c->timing_out[3];
+  d[6] = c->timing_out[6];
+  for (int i = 0; i < n && i < 8; ++i) out[i] = d[i];
   return TN3D_OK;
 }
 

@@ -31,6 +31,7 @@ struct SweepArgs {
   unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
   int32_t* gate_n;                // [sweep][gate of the class] K D before the gate (set by the Gram)
+  unsigned long long* win;        // execution window of this launch (see k_win_init) or null
 };
 
 struct ZipArgs {
@@ -62,6 +63,7 @@ struct ZipArgs {
   int32_t* zdim;            // [sweep][12] shapes passed between the step kernels
   double* zS;               // [sweep][1024] singular values of the step
   unsigned long long* flop_ctr;  // 64 counters of algorithmic flops of the decomposition, or null
+  unsigned long long* win;       // execution window of the decomposition launch, or null
 };
 
 // Raises the dynamic-LDS limits of the kernels that need more than 64 KB;
@@ -85,7 +87,7 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
                      hipStream_t st);
 void launch_zip_init(const ZipArgs& Z, hipStream_t st);
 // stamps (or null): two wall-clock stamps around the decomposition launch
-void launch_zip_step(const ZipArgs& Z, int x, int y, unsigned long long* stamps, hipStream_t st);
+void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
 // Graph replay helpers: gather each item's syndrome into a dense buffer,
 // local item indices with their offsets, zero a counter block (no memset
@@ -95,6 +97,17 @@ void launch_gather_synd(int n, const int32_t* items, const uint8_t* synd, const 
 void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_t st);
 // Writes the device wall clock (hipDeviceAttributeWallClockRate ticks) to *out.
 void launch_stamp(unsigned long long* out, hipStream_t st);
+// Execution windows: n windows of 128 words, words 0..63 the earliest start
+// and 64..127 the latest end (device wall clock) over the workgroups of the
+// launches that record into it, spread over 64 slots by workgroup.
+void launch_win_init(unsigned long long* win, int n, hipStream_t st);
+// Adds one contraction's times to acc: acc[0] layers (stamps 0..1), acc[1]
+// boundary MPS (stamps 1..2), acc[2] the windows [0, n_cls_win) (Gram and
+// reabsorption), acc[4] bytes (ctr[0..64)), acc[5] the decomposition windows
+// of steps x < Lx - 1 (if eig), acc[7] flops (ctr[65..129)); milliseconds.
+void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
+                          int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
+                          hipStream_t st);
 void launch_zero_words(uint32_t* p, int n, hipStream_t st);
 void launch_scatter_out(int n, const int32_t* items, const double* lp_local, const uint32_t* fl_local, double* logp,
                         uint32_t* flags, hipStream_t st);

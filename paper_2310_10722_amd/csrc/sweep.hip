@@ -149,6 +149,23 @@ __device__ __forceinline__ Split make_split(const int D[4], int leg, int d) {
   return v;
 }
 
+// A workgroup's start and end in the execution window of its launch (slot by
+// workgroup so that few atomics share an address).  The start is read at entry
+// and recorded together with the end, so the workgroup never waits for the
+// clock read on its way.  win_close must be reached by every thread.
+__device__ __forceinline__ int win_slot() { return (blockIdx.x + 7 * blockIdx.y) & 63; }
+__device__ __forceinline__ unsigned long long win_open(const unsigned long long* win) {
+  return win ? (unsigned long long)wall_clock64() : 0ull;
+}
+__device__ __forceinline__ void win_close(unsigned long long* win, unsigned long long t0) {
+  if (!win) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMin(win + win_slot(), t0);
+    atomicMax(win + 64 + win_slot(), (unsigned long long)wall_clock64());
+  }
+}
+
 constexpr int GTR = 16;  // rows per tile of the Gram kernel
 
 // One wavefront per (gate side, sweep).  Threads are grouped: group g of
@@ -174,6 +191,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   const int cw = (ncols + ngrp - 1) / ngrp;
   const int tw = ngrp * cw;  // tile width (>= ncols, padded with zeros)
   if (cw <= cwlo || cw > NMAX) return;
+  const unsigned long long w0 = win_open(A.win);
   __shared__ double slam[4][MAXCHI];
   __shared__ double tile[GTR * 65];  // rows of tw <= 64 entries, stride tw + 1 (no bank conflicts)
   __shared__ int colofs[64];
@@ -250,6 +268,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
 #pragma unroll
     for (int k = 0; k < NMAX; ++k)
       if (k < cw && j0 + k < ncols) out[i * ncols + j0 + k] = acc[k];
+  win_close(A.win, w0);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,6 +488,7 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
   const int Dold = int(W[0]), Dn = int(W[1]);
   const int nin = d * Dold, nout = d * Dn, nst = (nout + 3) & ~3;
   if (nin <= nlo || nin > NMAX) return;
+  const unsigned long long w0 = win_open(A.win);
   int D[4];
   site_dims(A, sweep, site, D);
   D[leg] = Dold;
@@ -521,6 +541,7 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
       if (q + 3 < nout) dst[colout[q + 3]] = T(s3);
     }
   }
+  win_close(A.win, w0);
 }
 
 // ---------------------------------------------------------------------------
@@ -764,6 +785,7 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
   if (nv > ZBIG) return;  // k_zip_bbig takes it
+  const unsigned long long w0 = win_open(Z.win);
   double* G = Z.Gm + int64_t(s) * Z.bigcap;
   double* Sout = Z.zS + int64_t(s) * 1024;
   const double gd = wave_max(tid < nv ? G[tid * nv + tid] : 0.0);
@@ -796,6 +818,7 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
     const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u);
     if (f) atomicOr(&Z.flags[s], f);
   }
+  win_close(Z.win, w0);
 }
 
 // Decomposition of the Gram blocks larger than ZBIG (FP32 mode) with the
@@ -1000,6 +1023,44 @@ __global__ void k_stamp(unsigned long long* out) {
   if (threadIdx.x == 0) *out = wall_clock64();
 }
 
+__global__ void k_win_init(unsigned long long* win, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * 128) win[e] = (e & 127) < 64 ? ~0ull : 0ull;
+}
+
+// One workgroup per window (the last one also takes the stamps and counters):
+// the window's span, added to its accumulator.
+__global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win,
+                                int Lx, int Ly, int eig, const unsigned long long* ctr, double ms_per_tick,
+                                double* acc) {
+  const int w = blockIdx.x, l = threadIdx.x;
+  const int n_win = n_cls_win + Lx * Ly;
+  if (w < n_win) {
+    const bool zip = w >= n_cls_win;
+    const int xy = w - n_cls_win;
+    if (zip && (!eig || xy % Lx + 1 >= Lx)) return;
+    unsigned long long t0 = win[size_t(w) * 128 + l], t1 = win[size_t(w) * 128 + 64 + l];
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long u0 = __shfl_xor(t0, o, 64), u1 = __shfl_xor(t1, o, 64);
+      t0 = u0 < t0 ? u0 : t0;
+      t1 = u1 > t1 ? u1 : t1;
+    }
+    if (l == 0 && t1 > t0) atomicAdd(acc + (zip ? 5 : 2), double(t1 - t0) * ms_per_tick);
+    return;
+  }
+  unsigned long long b = ctr[l], f = ctr[65 + l];
+  for (int o = 32; o > 0; o >>= 1) {
+    b += __shfl_xor(b, o, 64);
+    f += __shfl_xor(f, o, 64);
+  }
+  if (l == 0) {
+    acc[0] += double(stamps[1] - stamps[0]) * ms_per_tick;
+    acc[1] += double(stamps[2] - stamps[1]) * ms_per_tick;
+    acc[4] += double(b);
+    acc[7] += double(f);
+  }
+}
+
 // Graph replay support: the captured sequence reads and writes only
 // workspace buffers, filled and drained by these kernels outside it.
 __global__ void k_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
@@ -1157,14 +1218,12 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_init, dim3(Z.n_sweeps), dim3(64), 0, st, Z);
 }
 
-void launch_zip_step(const ZipArgs& Z, int x, int y, unsigned long long* stamps, hipStream_t st) {
+void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
-      if (stamps) launch_stamp(stamps, st);
       hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64 + Z.eig_ys) * Z.eig_ys * 8, st, Z, x,
                          y);
-      if (stamps) launch_stamp(stamps + 1, st);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
@@ -1193,6 +1252,17 @@ void launch_stamp(unsigned long long* out, hipStream_t st) {
 
 void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_t st) {
   hipLaunchKernelGGL(k_seq, dim3((n + 255) / 256), dim3(256), 0, st, n, items, offs, stride);
+}
+
+void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
+                          int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_timing_reduce, dim3(n_cls_win + Lx * Ly + 1), dim3(64), 0, st, stamps, win, n_cls_win, Lx, Ly,
+                     eig, ctr, ms_per_tick, acc);
+}
+
+void launch_win_init(unsigned long long* win, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_win_init, dim3((n * 128 + 255) / 256), dim3(256), 0, st, win, n);
 }
 
 void launch_zero_words(uint32_t* p, int n, hipStream_t st) {

@@ -293,10 +293,16 @@ def test_graph_replay_matches_eager(ctx):
             assert ctx.graphs_cached() >= 1
     ctx.set_timing(1)  # stamps are captured with the sequence: a new graph, same results
     n0 = ctx.graphs_cached()
+    launches = []
     for rep in range(2):
         got, _ = gpu_logp(ctx, net, m[:17], prm)
         assert np.array_equal(got, gpu_logp(eager, net_e, m[:17], prm)[0])
-        t = ctx.last_timing()
+        t = ctx.last_timing()  # sums since set_timing: both calls by the second round
         assert t[0] > 0 and t[1] > 0 and 0 < t[2] < t[0] and t[3] > 0 and t[4] > 0
+        assert 0 < t[5] < t[1] and t[6] > 0 and t[7] > 0  # the Gram route's eigen-decompositions
+        launches.append(t[3])
+    assert launches[1] == 2 * launches[0]
     assert ctx.graphs_cached() == n0 + 1
+    ctx.set_timing(1)  # restarts the sums
+    assert all(v == 0 for v in ctx.last_timing())
     ctx.set_timing(0)
