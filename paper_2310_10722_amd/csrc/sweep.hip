@@ -277,7 +277,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
 // Z_A, Z_B (n x n, n = K D) of a gated bond from the Grams of its two sides:
 // Z[(k,b),(k',b')] = sum_{p,q} (O_k^T O_k')[p,q] G[(p,b),(q,b')].
 __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const double* gin, int ncap, int n_g,
-                                  int gi, int sweep, int D, double* ZA, double* ZB) {
+                                  int gi, int sweep, int D, double* ZA, double* ZB, int first, int stride) {
   const int K = g.K, dA = g.dA, dB = g.dB, n = K * D;
   const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
   const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
@@ -288,7 +288,7 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
     // one bond pair (b, b2) per thread: its dA^2 and dB^2 Gram entries loaded
     // together into registers, then every (k, k2) block entry from them (the
     // gate tables are read at thread-uniform addresses)
-    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+    for (int e = first; e < D * D; e += stride) {
       const int b = e / D, b2 = e - b * D;
       double ga[16], gb[16];
 #pragma unroll
@@ -317,7 +317,7 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
     }
     return;
   }
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+  for (int e = first; e < n * n; e += stride) {
     const int r = e / n, c = e % n;
     const int k = r / D, b = r % D, k2 = c / D, b2 = c % D;
     double za = 0.0, zb = 0.0;
@@ -327,6 +327,79 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
       for (int q = 0; q < dB; ++q) zb = fma(PB[((k * K + k2) * dB + p) * dB + q], GB[(p * D + b) * nB + q * D + b2], zb);
     ZA[e] = za;
     ZB[e] = zb;
+  }
+}
+
+// W_A, W_B of a truncation (the kept singular vectors of C mapped back
+// through the gate), threads first, first + stride, ... of the caller.
+__device__ void write_w(const SweepArgs& A, const DevGate& g, int D, int Dn, bool bad, int n, int rA, int rB,
+                        const double* CM, const double* VM, const double* ZA, const double* ZB, const int* ord,
+                        const double* Ss, double s1, double* WA, double* WB, int first, int stride) {
+  const int K = g.K, dA = g.dA, dB = g.dB, nA = dA * D, nB = dB * D;
+  const double* OA = A.pool + g.oA;
+  const double* OB = A.pool + g.oB;
+  const int ncA = dA * Dn, ncB = dB * Dn;
+  if (bad) {
+    for (int e = first; e < nA * ncA; e += stride) WA[2 + e] = 0.0;
+    for (int e = first; e < nB * ncB; e += stride) WB[2 + e] = 0.0;
+  } else if (K <= 4) {
+    // one (bond index b, kept vector m) pair per thread: the K projections
+    // phi_k(b, m) of side B's factor (for W_A) and of side A's (for W_B) onto
+    // the kept singular vector once, then every (p, p2) entry from them
+    for (int e = first; e < D * Dn; e += stride) {
+      const int b = e / Dn, m = e - b * Dn, om = ord[m];
+      double phA[4], phB[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double pa = 0.0, pb = 0.0;
+        if (k < K) {
+          for (int j = 0; j < rB; ++j) pa = fma(VM[j * n + k * D + b], ZB[j * rB + om], pa);
+          for (int i = 0; i < rA; ++i) pb = fma(CM[i * n + k * D + b], ZA[i * rB + om], pb);
+        }
+        phA[k] = pa;
+        phB[k] = pb;
+      }
+      const double sA = sqrt(Ss[m] / s1) / Ss[m], sB = sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]);
+      for (int p = 0; p < dA; ++p)
+        for (int p2 = 0; p2 < dA; ++p2) {
+          double w = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < K) w = fma(OA[(k * dA + p2) * dA + p], phA[k], w);
+          WA[2 + (p * D + b) * ncA + p2 * Dn + m] = w * sA;
+        }
+      for (int p = 0; p < dB; ++p)
+        for (int p2 = 0; p2 < dB; ++p2) {
+          double w = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < K) w = fma(OB[(k * dB + p2) * dB + p], phB[k], w);
+          WB[2 + (p * D + b) * ncB + p2 * Dn + m] = w * sB;
+        }
+    }
+  } else {
+    for (int e = first; e < nA * ncA; e += stride) {
+      const int row = e / ncA, col = e % ncA;
+      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      double w = 0.0;
+      for (int k = 0; k < K; ++k) {
+        double phi = 0.0;
+        for (int j = 0; j < rB; ++j) phi = fma(VM[j * n + k * D + b], ZB[j * rB + ord[m]], phi);
+        w = fma(OA[(k * dA + p2) * dA + p], phi, w);
+      }
+      WA[2 + e] = w * (sqrt(Ss[m] / s1) / Ss[m]);
+    }
+    for (int e = first; e < nB * ncB; e += stride) {
+      const int row = e / ncB, col = e % ncB;
+      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
+      double w = 0.0;
+      for (int k = 0; k < K; ++k) {
+        double phi = 0.0;
+        for (int i = 0; i < rA; ++i) phi = fma(CM[i * n + k * D + b], ZA[i * rB + ord[m]], phi);
+        w = fma(OB[(k * dB + p2) * dB + p], phi, w);
+      }
+      WB[2 + e] = w * (sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]));
+    }
   }
 }
 
@@ -357,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   int* perm = ord + n;
   int* flag = perm + n;
   const int nA = dA * D, nB = dB * D;
-  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB);
+  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, tid, NT);
   __syncthreads();
   const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
   const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
@@ -402,71 +475,259 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (f) atomicOr(&A.flags[sweep], f);
   }
   for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
-  const double* OA = A.pool + g.oA;
-  const double* OB = A.pool + g.oB;
-  const int ncA = dA * Dn, ncB = dB * Dn;
-  if (bad) {
-    for (int e = tid; e < nA * ncA; e += NT) WA[2 + e] = 0.0;
-    for (int e = tid; e < nB * ncB; e += NT) WB[2 + e] = 0.0;
-  } else if (K <= 4) {
-    // one (bond index b, kept vector m) pair per thread: the K projections
-    // phi_k(b, m) of side B's factor (for W_A) and of side A's (for W_B) onto
-    // the kept singular vector once, then every (p, p2) entry from them
-    for (int e = tid; e < D * Dn; e += NT) {
-      const int b = e / Dn, m = e - b * Dn, om = ord[m];
-      double phA[4], phB[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double pa = 0.0, pb = 0.0;
-        if (k < K) {
-          for (int j = 0; j < rB; ++j) pa = fma(VM[j * n + k * D + b], ZB[j * rB + om], pa);
-          for (int i = 0; i < rA; ++i) pb = fma(CM[i * n + k * D + b], ZA[i * rB + om], pb);
-        }
-        phA[k] = pa;
-        phB[k] = pb;
-      }
-      const double sA = sqrt(Ss[m] / s1) / Ss[m], sB = sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]);
-      for (int p = 0; p < dA; ++p)
-        for (int p2 = 0; p2 < dA; ++p2) {
-          double w = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (k < K) w = fma(OA[(k * dA + p2) * dA + p], phA[k], w);
-          WA[2 + (p * D + b) * ncA + p2 * Dn + m] = w * sA;
-        }
-      for (int p = 0; p < dB; ++p)
-        for (int p2 = 0; p2 < dB; ++p2) {
-          double w = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (k < K) w = fma(OB[(k * dB + p2) * dB + p], phB[k], w);
-          WB[2 + (p * D + b) * ncB + p2 * Dn + m] = w * sB;
-        }
+  write_w(A, g, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT);
+}
+
+// ---------------------------------------------------------------------------
+// truncations of order K D <= 8: eight per wavefront
+// ---------------------------------------------------------------------------
+// The steps of k_solve (gated Grams, pivoted Cholesky of both, C = F_A F_B^T,
+// one-sided Jacobi SVD of C, rank rule, W_A, W_B) for small gates, each on a
+// team of TL = 8 lanes of one wavefront: team t of a workgroup takes sweep
+// blockIdx.y * TSW + t of gate blockIdx.x.  Teams share nothing.  Inside a
+// team, values move through the team's LDS, ordered by team_sync (one
+// wavefront executes its LDS accesses in order, so a wavefront-scope fence
+// that keeps the compiler from moving them suffices), or by DPP moves within
+// the team's eight lanes.  All lanes of a team take the same branches.
+constexpr int TL = 8;
+constexpr int TSW = 64 / TL;
+
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Over the eight lanes of a team: quad butterflies, then the half-row mirror
+// (lane i <-> 7 - i) brings in the other quad.
+__device__ __forceinline__ double team8_max(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  return fmax(v, dpp_move<0x141>(v));
+}
+
+__device__ __forceinline__ void team8_argmax(double& v, int& idx) {
+  auto step = [&](double w, int j) {
+    if (w > v || (w == v && j < idx)) {
+      v = w;
+      idx = j;
     }
-  } else {
-    for (int e = tid; e < nA * ncA; e += NT) {
-      const int row = e / ncA, col = e % ncA;
-      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
-      double w = 0.0;
-      for (int k = 0; k < K; ++k) {
-        double phi = 0.0;
-        for (int j = 0; j < rB; ++j) phi = fma(VM[j * n + k * D + b], ZB[j * rB + ord[m]], phi);
-        w = fma(OA[(k * dA + p2) * dA + p], phi, w);
+  };
+  step(dpp_move<0xB1>(v), __builtin_amdgcn_update_dpp(0, idx, 0xB1, 0xF, 0xF, false));
+  step(dpp_move<0x4E>(v), __builtin_amdgcn_update_dpp(0, idx, 0x4E, 0xF, 0xF, false));
+  step(dpp_move<0x141>(v), __builtin_amdgcn_update_dpp(0, idx, 0x141, 0xF, 0xF, false));
+}
+
+// Pivoted Cholesky (as block_pchol) of the n x n Z (n <= TL) by one team:
+// lane l owns column l.  Returns the rank; F (r x n) as in block_pchol.
+__device__ int team_pchol(double* Z, double* F, int n, double tol, int* perm, int l) {
+  if (l < n) perm[l] = l;
+  const double thr = tol * fmax(team8_max(l < n ? Z[l * n + l] : 0.0), 0.0);
+  team_sync();
+  int r = 0;
+  for (int k = 0; k < n; ++k) {
+    double piv = (l >= k && l < n) ? Z[l * n + l] : -1e300;
+    int j = l;
+    team8_argmax(piv, j);
+    if (!(piv > thr)) break;
+    if (j != k) {
+      if (l < n) {  // columns k, j
+        const double t = Z[l * n + k];
+        Z[l * n + k] = Z[l * n + j];
+        Z[l * n + j] = t;
       }
-      WA[2 + e] = w * (sqrt(Ss[m] / s1) / Ss[m]);
-    }
-    for (int e = tid; e < nB * ncB; e += NT) {
-      const int row = e / ncB, col = e % ncB;
-      const int p = row / D, b = row % D, p2 = col / Dn, m = col % Dn;
-      double w = 0.0;
-      for (int k = 0; k < K; ++k) {
-        double phi = 0.0;
-        for (int i = 0; i < rA; ++i) phi = fma(CM[i * n + k * D + b], ZA[i * rB + ord[m]], phi);
-        w = fma(OB[(k * dB + p2) * dB + p], phi, w);
+      team_sync();
+      if (l < n) {  // rows k, j
+        const double t = Z[k * n + l];
+        Z[k * n + l] = Z[j * n + l];
+        Z[j * n + l] = t;
       }
-      WB[2 + e] = w * (sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]));
+      if (l == 0) {
+        const int t = perm[k];
+        perm[k] = perm[j];
+        perm[j] = t;
+      }
+      team_sync();
     }
+    const double rk = sqrt(piv), rinv = 1.0 / rk;
+    if (l == k) Z[k * n + k] = rk;
+    if (l > k && l < n) Z[k * n + l] *= rinv;
+    team_sync();
+    if (l > k && l < n) {
+      const double zl = Z[k * n + l];
+      for (int a = k + 1; a < n; ++a) Z[a * n + l] -= Z[k * n + a] * zl;
+    }
+    team_sync();
+    r = k + 1;
   }
+  if (l < n)
+    for (int i = 0; i < r; ++i) F[i * n + perm[l]] = l >= i ? Z[i * n + l] : 0.0;
+  team_sync();
+  return r;
+}
+
+// One-sided Jacobi (as block_jacobi) on the nv <= TL columns of length len of
+// A (column v, entry e at A[v + e * nv]) by one team, with J (nv x nv): the
+// pairs of a round take two lanes each (each lane half of the entries, the
+// sums exchanged within the pair).  t: the team's index in the wavefront.
+__device__ int team_jacobi(double* A, int nv, int len, double* J, double tol, double floor_rel, int max_sweeps,
+                           int l, int t) {
+  if (l < nv)
+    for (int c = 0; c < nv; ++c) J[l * nv + c] = l == c ? 1.0 : 0.0;
+  double s = 0.0;
+  if (l < nv)
+    for (int e = 0; e < len; ++e) s += A[l + e * nv] * A[l + e * nv];
+  const double floor2 = floor_rel * floor_rel * team8_max(s);
+  const double sqrt_tol = sqrt(tol);
+  team_sync();
+  const int ne = nv + (nv & 1), npairs = ne / 2;
+  const int pp = l >> 1, h = l & 1;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    bool rot = false, big = false;
+    for (int rnd = 0; rnd < ne - 1; ++rnd) {
+      int i = -1, j = -1;
+      if (pp < npairs) {
+        if (pp == 0) {
+          i = ne - 1;
+          j = rnd;
+        } else {
+          i = rnd + pp;
+          i = i >= ne - 1 ? i - (ne - 1) : i;
+          j = rnd - pp + ne - 1;
+          j = j >= ne - 1 ? j - (ne - 1) : j;
+        }
+        if (i > j) {
+          const int q = i;
+          i = j;
+          j = q;
+        }
+      }
+      const bool live = pp < npairs && j < nv;  // the same in both lanes of a pair
+      double a = 0.0, b = 0.0, g = 0.0;
+      if (live)
+        for (int e = h; e < len; e += 2) {
+          const double x = A[i + e * nv], y = A[j + e * nv];
+          a += x * x;
+          b += y * y;
+          g += x * y;
+        }
+      // the pair's two halves (lanes 2p, 2p + 1), every lane active
+      a += dpp_move<0xB1>(a);
+      b += dpp_move<0xB1>(b);
+      g += dpp_move<0xB1>(g);
+      const double sab = sqrt(a) * sqrt(b);
+      if (live && a > floor2 && b > floor2 && fabs(g) > tol * sab) {
+        const double zeta = (b - a) / (2.0 * g);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int e = h; e < len; e += 2) {
+          const double x = A[i + e * nv], y = A[j + e * nv];
+          A[i + e * nv] = cs * x - sn * y;
+          A[j + e * nv] = sn * x + cs * y;
+        }
+        for (int e = h; e < nv; e += 2) {
+          const double x = J[e * nv + i], y = J[e * nv + j];
+          J[e * nv + i] = cs * x - sn * y;
+          J[e * nv + j] = sn * x + cs * y;
+        }
+        rot = true;
+        if (fabs(g) > sqrt_tol * sab) big = true;
+      }
+      team_sync();
+    }
+    const unsigned long long rb = __ballot(rot), bb = __ballot(big);
+    if (!((rb >> (t * TL)) & 0xFFull)) break;
+    if (!((bb >> (t * TL)) & 0xFFull)) break;
+  }
+  return sweep;
+}
+
+__global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
+                                                   double* wout, int ncap) {
+  __shared__ double tz[TSW][4 * TL * TL + 2 * TL];  // Z_A, Z_B, F_A, F_B, S, Ss
+  __shared__ int ti[TSW][2 * TL + 2];                // ord, perm, rank rule result
+  const int gi = blockIdx.x, tid = threadIdx.x;
+  const int t = tid / TL, l = tid - t * TL;
+  const int sweep = blockIdx.y * TSW + t;
+  if (sweep >= A.n_sweeps) return;  // the whole team
+  const DevGate g = gates[gi];
+  const int64_t bidx = int64_t(sweep) * A.n_bonds + g.bond;
+  // the class is decided on the order the Gram recorded (see k_solve)
+  const int n0 = A.gate_n[int64_t(sweep) * n_g + gi];
+  if (n0 <= 0 || n0 > TL) return;
+  const int D = A.bond_dim[bidx];
+  const int K = g.K, n = K * D;
+  const double logb_in = A.logb[bidx];
+  double* ZA = tz[t];
+  double* ZB = ZA + TL * TL;
+  double* CM = ZB + TL * TL;
+  double* VM = CM + TL * TL;
+  double* S = VM + TL * TL;
+  double* Ss = S + TL;
+  int* ord = ti[t];
+  int* perm = ord + TL;
+  int* rr = perm + TL;
+  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, l, TL);
+  team_sync();
+  const int rA = team_pchol(ZA, CM, n, A.pchol_tol, perm, l);
+  const int rB = team_pchol(ZB, VM, n, A.pchol_tol, perm, l);
+  if (l < rB)  // C = F_A F_B^T (rA x rB) into Z_A, lane j takes column j
+    for (int i = 0; i < rA; ++i) {
+      double c = 0.0;
+      for (int k = 0; k < n; ++k) c += CM[i * n + k] * VM[l * n + k];
+      ZA[i * rB + l] = c;
+    }
+  team_sync();
+  int Dn = 0, split = 0;
+  double s1 = 0.0;
+  if (rA > 0 && rB > 0) {
+    const int nsw = team_jacobi(ZA, rB, rA, ZB, A.jtol, A.jfloor, 40, l, t);  // columns of C; V' in Z_B
+    if (l == 0) {
+      atomicMax(&A.sweeps_max[0], nsw);
+      if (nsw >= 40) atomicOr(&A.flags[sweep], 8u);
+    }
+    if (l < rB) {
+      double q = 0.0;
+      for (int e = 0; e < rA; ++e) q += ZA[l + e * rB] * ZA[l + e * rB];
+      S[l] = sqrt(q);
+    }
+    team_sync();
+    if (l < rB) {
+      int rank = 0;
+      for (int u = 0; u < rB; ++u)
+        if (sorts_before(S[u], u, S[l], l)) ++rank;
+      ord[rank] = l;
+    }
+    team_sync();
+    if (l < rB) Ss[l] = S[ord[l]];
+    team_sync();
+    if (l == 0) {
+      rr[0] = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &rr[1]);
+    }
+    team_sync();
+    Dn = rr[0];
+    split = rr[1];
+    s1 = Ss[0];
+  }
+  const bool bad = !(Dn > 0) || !(s1 > 0.0) || !isfinite(s1);
+  if (bad) {
+    Dn = 1;
+    s1 = 1.0;
+  }
+  double* WA = wout + (int64_t(sweep * n_g + gi) * 2 + 0) * (2 + ncap * ncap);
+  double* WB = wout + (int64_t(sweep * n_g + gi) * 2 + 1) * (2 + ncap * ncap);
+  if (l == 0) {
+    WA[0] = WB[0] = double(D);
+    WA[1] = WB[1] = double(Dn);
+    A.bond_dim[bidx] = Dn;
+    A.logb[bidx] = logb_in + log(s1);
+    uint32_t f = 0;
+    if (bad) f |= 1u;
+    if (split) f |= 2u;
+    if (f) atomicOr(&A.flags[sweep], f);
+  }
+  for (int m = l; m < Dn; m += TL) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  write_w(A, g, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, l, TL);
 }
 
 // ---------------------------------------------------------------------------
@@ -1163,14 +1424,14 @@ static size_t solve_lds(int n) {
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
-  // three size classes: order <= 8 and <= 16 (2 and 8 KB of LDS, one
-  // wavefront: the smaller the LDS, the more workgroups share a CU) and the
-  // rest up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
-  // wavefronts share each problem)
-  const int ntiny = kdcap < 8 ? kdcap : 8;
+  // three size classes: order <= 8 (eight problems per wavefront, a team of
+  // eight lanes each), <= 16 (one wavefront, 8 KB of LDS) and the rest up to
+  // kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four wavefronts
+  // share each problem)
+  const int ntiny = kdcap < TL ? kdcap : TL;
   const int nsmall = kdcap < 16 ? kdcap : 16;
-  hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(ntiny), st, A, gates, n_g, gin, wout,
-                     ncap, 0, ntiny);
+  hipLaunchKernelGGL(k_solve_team, dim3(n_g, (A.n_sweeps + TSW - 1) / TSW), dim3(64), 0, st, A, gates, n_g, gin,
+                     wout, ncap);
   if (nsmall > ntiny)
     hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
                        wout, ncap, ntiny, nsmall);
