@@ -26,8 +26,8 @@ namespace tn3d {
 namespace {
 
 constexpr int NT = 256;
-constexpr int SNT = 64;       // one wavefront per small bond truncation: barriers stay cheap
-constexpr int SNT_BIG = 256;  // four wavefronts per large one
+constexpr int SNT = 64;       // one wavefront per bond truncation of order 9 to 16
+constexpr int SNT_BIG = 256;  // four wavefronts per bond truncation of order above 16
 constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
 constexpr int MAXCHI = 64;
 
@@ -479,33 +479,36 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
 }
 
 // ---------------------------------------------------------------------------
-// truncations of order K D <= 8: eight per wavefront
+// truncations of order K D <= 16: four or eight per wavefront
 // ---------------------------------------------------------------------------
 // The steps of k_solve (gated Grams, pivoted Cholesky of both, C = F_A F_B^T,
-// one-sided Jacobi SVD of C, rank rule, W_A, W_B) for small gates, each on a
-// team of TL = 8 lanes of one wavefront: team t of a workgroup takes sweep
-// blockIdx.y * TSW + t of gate blockIdx.x.  Teams share nothing.  Inside a
-// team, values move through the team's LDS, ordered by team_sync (one
-// wavefront executes its LDS accesses in order, so a wavefront-scope fence
-// that keeps the compiler from moving them suffices), or by DPP moves within
-// the team's eight lanes.  All lanes of a team take the same branches.
-constexpr int TL = 8;
-constexpr int TSW = 64 / TL;
-
+// one-sided Jacobi SVD of C, rank rule, W_A, W_B) for gates of order n with
+// nlo < n <= TL (8 or 16), each on a team of TL lanes of one wavefront: team t
+// of a workgroup takes sweep blockIdx.y * (64 / TL) + t of gate blockIdx.x.
+// Teams share nothing.  Inside a team, values move through the team's LDS,
+// ordered by team_sync (one wavefront executes its LDS accesses in order, so a
+// wavefront-scope fence that keeps the compiler from moving them suffices), or
+// by DPP moves within the team's lanes.  All lanes of a team take the same
+// branches.
 __device__ __forceinline__ void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
-// Over the eight lanes of a team: quad butterflies, then the half-row mirror
-// (lane i <-> 7 - i) brings in the other quad.
-__device__ __forceinline__ double team8_max(double v) {
+// Over the TL (8 or 16) lanes of a team: quad butterflies, then the half-row
+// mirror (lane i <-> 7 - i) brings in the other quad, and for 16 the row
+// mirror the other half-row.
+template <int TL>
+__device__ __forceinline__ double team_max(double v) {
   v = fmax(v, dpp_move<0xB1>(v));
   v = fmax(v, dpp_move<0x4E>(v));
-  return fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  if (TL == 16) v = fmax(v, dpp_move<0x140>(v));
+  return v;
 }
 
-__device__ __forceinline__ void team8_argmax(double& v, int& idx) {
+template <int TL>
+__device__ __forceinline__ void team_argmax(double& v, int& idx) {
   auto step = [&](double w, int j) {
     if (w > v || (w == v && j < idx)) {
       v = w;
@@ -515,19 +518,21 @@ __device__ __forceinline__ void team8_argmax(double& v, int& idx) {
   step(dpp_move<0xB1>(v), __builtin_amdgcn_update_dpp(0, idx, 0xB1, 0xF, 0xF, false));
   step(dpp_move<0x4E>(v), __builtin_amdgcn_update_dpp(0, idx, 0x4E, 0xF, 0xF, false));
   step(dpp_move<0x141>(v), __builtin_amdgcn_update_dpp(0, idx, 0x141, 0xF, 0xF, false));
+  if (TL == 16) step(dpp_move<0x140>(v), __builtin_amdgcn_update_dpp(0, idx, 0x140, 0xF, 0xF, false));
 }
 
 // Pivoted Cholesky (as block_pchol) of the n x n Z (n <= TL) by one team:
 // lane l owns column l.  Returns the rank; F (r x n) as in block_pchol.
+template <int TL>
 __device__ int team_pchol(double* Z, double* F, int n, double tol, int* perm, int l) {
   if (l < n) perm[l] = l;
-  const double thr = tol * fmax(team8_max(l < n ? Z[l * n + l] : 0.0), 0.0);
+  const double thr = tol * fmax(team_max<TL>(l < n ? Z[l * n + l] : 0.0), 0.0);
   team_sync();
   int r = 0;
   for (int k = 0; k < n; ++k) {
     double piv = (l >= k && l < n) ? Z[l * n + l] : -1e300;
     int j = l;
-    team8_argmax(piv, j);
+    team_argmax<TL>(piv, j);
     if (!(piv > thr)) break;
     if (j != k) {
       if (l < n) {  // columns k, j
@@ -569,6 +574,7 @@ __device__ int team_pchol(double* Z, double* F, int n, double tol, int* perm, in
 // A (column v, entry e at A[v + e * nv]) by one team, with J (nv x nv): the
 // pairs of a round take two lanes each (each lane half of the entries, the
 // sums exchanged within the pair).  t: the team's index in the wavefront.
+template <int TL>
 __device__ int team_jacobi(double* A, int nv, int len, double* J, double tol, double floor_rel, int max_sweeps,
                            int l, int t) {
   if (l < nv)
@@ -576,7 +582,7 @@ __device__ int team_jacobi(double* A, int nv, int len, double* J, double tol, do
   double s = 0.0;
   if (l < nv)
     for (int e = 0; e < len; ++e) s += A[l + e * nv] * A[l + e * nv];
-  const double floor2 = floor_rel * floor_rel * team8_max(s);
+  const double floor2 = floor_rel * floor_rel * team_max<TL>(s);
   const double sqrt_tol = sqrt(tol);
   team_sync();
   const int ne = nv + (nv & 1), npairs = ne / 2;
@@ -636,14 +642,17 @@ __device__ int team_jacobi(double* A, int nv, int len, double* J, double tol, do
       team_sync();
     }
     const unsigned long long rb = __ballot(rot), bb = __ballot(big);
-    if (!((rb >> (t * TL)) & 0xFFull)) break;
-    if (!((bb >> (t * TL)) & 0xFFull)) break;
+    const unsigned long long tm = (1ull << TL) - 1;
+    if (!((rb >> (t * TL)) & tm)) break;
+    if (!((bb >> (t * TL)) & tm)) break;
   }
   return sweep;
 }
 
+template <int TL>
 __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* gates, int n_g, const double* gin,
-                                                   double* wout, int ncap) {
+                                                   double* wout, int ncap, int nlo) {
+  constexpr int TSW = 64 / TL;  // problems per workgroup
   __shared__ double tz[TSW][4 * TL * TL + 2 * TL];  // Z_A, Z_B, F_A, F_B, S, Ss
   __shared__ int ti[TSW][2 * TL + 2];                // ord, perm, rank rule result
   const int gi = blockIdx.x, tid = threadIdx.x;
@@ -654,7 +663,7 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
   const int64_t bidx = int64_t(sweep) * A.n_bonds + g.bond;
   // the class is decided on the order the Gram recorded (see k_solve)
   const int n0 = A.gate_n[int64_t(sweep) * n_g + gi];
-  if (n0 <= 0 || n0 > TL) return;
+  if (n0 <= nlo || n0 > TL) return;
   const int D = A.bond_dim[bidx];
   const int K = g.K, n = K * D;
   const double logb_in = A.logb[bidx];
@@ -669,8 +678,8 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
   int* rr = perm + TL;
   build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, l, TL);
   team_sync();
-  const int rA = team_pchol(ZA, CM, n, A.pchol_tol, perm, l);
-  const int rB = team_pchol(ZB, VM, n, A.pchol_tol, perm, l);
+  const int rA = team_pchol<TL>(ZA, CM, n, A.pchol_tol, perm, l);
+  const int rB = team_pchol<TL>(ZB, VM, n, A.pchol_tol, perm, l);
   if (l < rB)  // C = F_A F_B^T (rA x rB) into Z_A, lane j takes column j
     for (int i = 0; i < rA; ++i) {
       double c = 0.0;
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
   int Dn = 0, split = 0;
   double s1 = 0.0;
   if (rA > 0 && rB > 0) {
-    const int nsw = team_jacobi(ZA, rB, rA, ZB, A.jtol, A.jfloor, 40, l, t);  // columns of C; V' in Z_B
+    const int nsw = team_jacobi<TL>(ZA, rB, rA, ZB, A.jtol, A.jfloor, 40, l, t);  // columns of C; V' in Z_B
     if (l == 0) {
       atomicMax(&A.sweeps_max[0], nsw);
       if (nsw >= 40) atomicOr(&A.flags[sweep], 8u);
@@ -1425,16 +1434,16 @@ void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const doubl
                   int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
   // three size classes: order <= 8 (eight problems per wavefront, a team of
-  // eight lanes each), <= 16 (one wavefront, 8 KB of LDS) and the rest up to
-  // kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four wavefronts
-  // share each problem)
-  const int ntiny = kdcap < TL ? kdcap : TL;
+  // eight lanes each; most gates), <= 16 (one wavefront, 8 KB of LDS) and the
+  // rest up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
+  // wavefronts share each problem).  A team of 16 lanes for the middle class
+  // measured slower than one wavefront per problem.
   const int nsmall = kdcap < 16 ? kdcap : 16;
-  hipLaunchKernelGGL(k_solve_team, dim3(n_g, (A.n_sweeps + TSW - 1) / TSW), dim3(64), 0, st, A, gates, n_g, gin,
-                     wout, ncap);
-  if (nsmall > ntiny)
+  hipLaunchKernelGGL(k_solve_team<8>, dim3(n_g, (A.n_sweeps + 7) / 8), dim3(64), 0, st, A, gates, n_g, gin, wout,
+                     ncap, 0);
+  if (nsmall > 8)
     hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
-                       wout, ncap, ntiny, nsmall);
+                       wout, ncap, 8, nsmall);
   if (kdcap > nsmall)
     hipLaunchKernelGGL(k_solve<SNT_BIG>, dim3(n_g, A.n_sweeps), dim3(SNT_BIG), solve_lds(kdcap), st, A, gates, n_g,
                        gin, wout, ncap, nsmall, kdcap);
