@@ -166,7 +166,7 @@ __device__ __forceinline__ void win_close(unsigned long long* win, unsigned long
   }
 }
 
-constexpr int GTR = 16;  // rows per tile of the Gram kernel
+constexpr int GTR = 8;  // rows per tile of the Gram kernel
 
 // One wavefront per (gate side, sweep).  Threads are grouped: group g of
 // ngrp = 64 / ncols groups owns Gram rows i = 0..ncols-1 (one per thread) and
@@ -1453,12 +1453,15 @@ void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g
                      hipStream_t st) {
   if (n_g <= 0) return;
   dim3 g(2 * n_g, A.n_sweeps);
-  // two size classes: rows of at most 32 entries, then the rest up to 64
+  // three size classes: rows of at most 16 and 32 entries, then the rest up to
+  // 64 (the W staging takes 8, 16 and 32 KB of LDS)
   if (prec == 0) {
-    hipLaunchKernelGGL((k_reabsorb<double, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    hipLaunchKernelGGL((k_reabsorb<double, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    if (ncap > 16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
     if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<double, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   } else {
-    hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    hipLaunchKernelGGL((k_reabsorb<float, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    if (ncap > 16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
     if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<float, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   }
 }
