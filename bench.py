@@ -150,6 +150,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed and instrumented steps (no statistics, eager, other-precision or "
+                         "one-syndrome runs): the short run a profiler traces")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer once (the calibration run for the HBM byte "
                          "counters of a profiler) and exit")
@@ -205,6 +208,18 @@ def main():
     torch.cuda.synchronize()
     i1 = time.perf_counter()
     lay_ms, fin_ms, hot_ms, hot_launch, hot_bytes, eig_ms, eig_launch, eig_flops = ctx.last_timing()
+    if a.headline_only:
+        ctx.set_timing(0)
+        coset, lr, logp, flags = [t.cpu().numpy() for t in results]
+        tf = eig_flops / (eig_ms * 1e-3) / 1e12 if eig_ms > 0 else None
+        print(json.dumps({"metric": METRIC, "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1,
+                          "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
+                          "higher_is_better": True, "dtype": w["dtype"], "headline_only": True,
+                          "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VALU_PEAK_TFS,
+                                       "unit": "TFLOP/s", "algorithmic_flops_per_launch":
+                                           eig_flops / eig_launch if eig_launch else None,
+                                       "avg_launch_ms": eig_ms / eig_launch if eig_launch else None}}))
+        return
     # bond statistics (an extra call: they copy every sweep's bonds to the host)
     ctx.set_timing(2)
     tn3d.tn3d_decode(ctx, net, syn, prm)
