@@ -301,22 +301,32 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
   return top;
 }
 
-// C[m][n] = sum_k A(m, k) B(k, n) for a 512-thread workgroup, FP64, through
-// 64 x 64 output tiles and 32-deep K slices staged in LDS (lds: 4096 doubles).
-// Each thread owns a 4 x 2 block of the tile.  a_at / b_at return operands
-// (any layout); c_put(m, n, v) stores.
+// C[m][n] = sum_k A(m, k) B(k, n) for a 512-thread workgroup, FP64 on the
+// matrix cores, through 64 x 64 output tiles and 32-deep K slices staged in
+// LDS (lds: 4096 doubles), each slice's global loads issued into registers
+// while the previous slice is multiplied.  a_at / b_at return operands (any
+// layout); c_put(m, n, v) stores.  v_mfma_f64_16x16x4f64 takes a 16 x 4
+// block of A (lane i + 16 k holds A[i][k]) and a 4 x 16 block of B (lane
+// j + 16 k holds B[k][j]) and accumulates the 16 x 16 block of C, item r of
+// lane j + 16 q holding row q + 4 r of column j.  The 64 x 64 output tile
+// is split over the eight wavefronts as four 16-row bands times two 32-column
+// halves (two accumulator blocks each); a wavefront whose band or half lies
+// outside M x N skips the products, and a K slice runs only as many 4-deep
+// steps as it holds.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <class FA, class FB, class FC>
 __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, double* lds) {
-  const int tid = threadIdx.x;
-  const int ty = tid >> 5, tx = tid & 31;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int rb = (wv & 3) * 16, cb = (wv >> 2) * 32;
   double* As = lds;         // [32][64]  (k, m)
   double* Bs = lds + 2048;  // [32][64]  (k, n)
   for (int m0 = 0; m0 < M; m0 += 64)
     for (int n0 = 0; n0 < N; n0 += 64) {
-      double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-      // this thread's four A and four B operands of a K slice, fetched into
-      // registers one slice ahead so that their loads overlap the FMAs
-      double ra[4], rb[4];
+      const bool act = m0 + rb < M && n0 + cb < N;  // uniform per wavefront
+      const bool act2 = n0 + cb + 16 < N;
+      dbl4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      double ra[4], rb4[4];
       auto fetch = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -324,7 +334,7 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
           const int kk = e >> 6, mm = e & 63;
           const int m = m0 + mm, n = n0 + mm, k = k0 + kk;
           ra[i] = (m < M && k < K) ? a_at(m, k) : 0.0;
-          rb[i] = (n < N && k < K) ? b_at(k, n) : 0.0;
+          rb4[i] = (n < N && k < K) ? b_at(k, n) : 0.0;
         }
       };
       __syncthreads();  // the previous tile's stores land before this tile's loads
@@ -334,30 +344,36 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           As[tid + 512 * i] = ra[i];
-          Bs[tid + 512 * i] = rb[i];
+          Bs[tid + 512 * i] = rb4[i];
         }
         __syncthreads();
         if (k0 + 32 < K) fetch(k0 + 32);
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) {
-          double a[4], b[2];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = As[kk * 64 + ty * 4 + i];
-#pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = Bs[kk * 64 + tx * 2 + j];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] += a[i] * b[j];
+        if (act) {
+          const int nks = K - k0 >= 32 ? 8 : (K - k0 + 3) >> 2;
+          const double* ap = As + lq * 64 + rb + li;
+          const double* bp = Bs + lq * 64 + cb + li;
+          if (act2) {
+            for (int ks = 0; ks < nks; ++ks) {
+              const double a = ap[ks * 256], b0 = bp[ks * 256], b1 = bp[ks * 256 + 16];
+              c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, c0, 0, 0, 0);
+              c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, c1, 0, 0, 0);
+            }
+          } else {
+            for (int ks = 0; ks < nks; ++ks)
+              c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks * 256], bp[ks * 256], c0, 0, 0, 0);
+          }
         }
       }
+      if (act) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int m = m0 + ty * 4 + i, n = n0 + tx * 2 + j;
-          if (m < M && n < N) c_put(m, n, acc[i][j]);
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + rb + lq + 4 * r, n = n0 + cb + li;
+          if (m < M) {
+            if (n < N) c_put(m, n, c0[r]);
+            if (n + 16 < N) c_put(m, n + 16, c1[r]);
+          }
         }
+      }
     }
   __syncthreads();
 }
@@ -405,10 +421,11 @@ __device__ __forceinline__ double wave_max(double v) {
 // the current matrix is picked out of the 16 rows [J0, J0 + 16).  v and w of a
 // step are broadcast through vw (v in vw[0, 64), w in vw[64, 128), 16-byte
 // aligned LDS), read two at a time with the next group's reads issued before
-// the current group's FMAs.  The Householder vector of step k is kept in row k
+// the current group's FMAs.  Only rows below NR (n rounded up to 16) are
+// visited: past n the matrix, v and w are zero.  The Householder vector of step k is kept in row k
 // of Hv (stride n); lane i writes only column i, the column it read from the
 // input.
-template <int J0>
+template <int J0, int NR>
 __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke, double* vw, double* Hv,
                                           double& er, double& br) {
   const int i = threadIdx.x;
@@ -447,9 +464,9 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
 #pragma unroll
     for (int t = 0; t < 8; ++t) c[t] = v2[J0 / 2 + t];
 #pragma unroll
-    for (int g = J0; g < 64; g += 16) {
+    for (int g = J0; g < NR; g += 16) {
       double2 nx[8];
-      if (g + 16 < 64) {
+      if (g + 16 < NR) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) nx[t] = v2[(g + 16) / 2 + t];
       }
@@ -460,7 +477,7 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
         p4[(2 * t + 1) & 3] = fma(a[g + 2 * t + 1], c[t].y, p4[(2 * t + 1) & 3]);
       }
       __builtin_amdgcn_sched_barrier(0);
-      if (g + 16 < 64) {
+      if (g + 16 < NR) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) c[t] = nx[t];
       }
@@ -478,9 +495,9 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
       cw[t] = w2[J0 / 2 + t];
     }
 #pragma unroll
-    for (int g = J0; g < 64; g += 8) {
+    for (int g = J0; g < NR; g += 8) {
       double2 nv[4], nw[4];
-      if (g + 8 < 64) {
+      if (g + 8 < NR) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           nv[t] = v2[(g + 8) / 2 + t];
@@ -494,7 +511,7 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
         a[g + 2 * t + 1] = fma(-v, cw[t].y, fma(-w, cv[t].y, a[g + 2 * t + 1]));
       }
       __builtin_amdgcn_sched_barrier(0);
-      if (g + 8 < 64) {
+      if (g + 8 < NR) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           cv[t] = nv[t];
@@ -507,33 +524,52 @@ __device__ __forceinline__ void tri_block(double (&a)[64], int n, int kb, int ke
 }
 
 // Householder reduction of the symmetric n x n matrix G (row-major, n >= 1)
-// times gs.  Lane i returns d_i = T[i][i], e_i = T[i][i+1] (0 for i >= n - 1)
-// and the scalar beta_i of reflector i (0 when step i needed no reflection);
-// Hv receives the reflectors (row k, stride n, components k+1 .. n-1, zeros
-// before) and may alias G.  vw: 128 doubles of 16-byte aligned LDS.
-__device__ void wave_tridiag(const double* G, double gs, int n, double* vw, double* Hv, double& dr, double& er,
-                             double& br) {
+// times gs, for n <= NR.  Lane i returns d_i = T[i][i], e_i = T[i][i+1] (0 for
+// i >= n - 1) and the scalar beta_i of reflector i (0 when step i needed no
+// reflection); Hv receives the reflectors (row k, stride n, components
+// k+1 .. n-1, zeros before) and may alias G.  vw: 128 doubles of 16-byte
+// aligned LDS.
+template <int NR>
+__device__ __forceinline__ void tridiag_nr(const double* G, double gs, int n, double* vw, double* Hv, double& dr,
+                                           double& er, double& br) {
   const int i = threadIdx.x;
   double a[64];
-  // every lane loads all 64 entries (clamped into the matrix) and scales them by
-  // gs or by 0 outside the n x n block: every loaded value is used, so the
-  // loads cannot be moved behind branches and are issued together
+  // every lane loads the NR entries of its column (clamped into the matrix)
+  // and scales them by gs or by 0 outside the n x n block: every loaded value
+  // is used, so the loads cannot be moved behind branches and are issued
+  // together; entries past NR are zero and never read
   const int ic = i < n ? i : n - 1;
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
-    const int jc = j < n ? j : n - 1;
-    a[j] = G[jc * n + ic] * ((j < n && i < n) ? gs : 0.0);
+    if (j < NR) {
+      const int jc = j < n ? j : n - 1;
+      a[j] = G[jc * n + ic] * ((j < n && i < n) ? gs : 0.0);
+    } else {
+      a[j] = 0.0;
+    }
   }
   er = 0.0;
   br = 0.0;
   const int ke = n - 2;
-  tri_block<0>(a, n, 0, ke < 16 ? ke : 16, vw, Hv, er, br);
-  tri_block<16>(a, n, 16, ke < 32 ? ke : 32, vw, Hv, er, br);
-  tri_block<32>(a, n, 32, ke < 48 ? ke : 48, vw, Hv, er, br);
-  tri_block<48>(a, n, 48, ke, vw, Hv, er, br);
+  if (NR > 16) {
+    tri_block<0, NR>(a, n, 0, 16, vw, Hv, er, br);
+    if (NR > 32) {
+      tri_block<16, NR>(a, n, 16, 32, vw, Hv, er, br);
+      if (NR > 48) {
+        tri_block<32, NR>(a, n, 32, 48, vw, Hv, er, br);
+        tri_block<48, NR>(a, n, 48, ke, vw, Hv, er, br);
+      } else {
+        tri_block<32, NR>(a, n, 32, ke, vw, Hv, er, br);
+      }
+    } else {
+      tri_block<16, NR>(a, n, 16, ke, vw, Hv, er, br);
+    }
+  } else {
+    tri_block<0, NR>(a, n, 0, ke, vw, Hv, er, br);
+  }
   double di = 0.0, en = 0.0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < NR; ++j) {
     if (j == i) di = a[j];
     if (j == n - 1) en = a[j];
   }
@@ -548,21 +584,42 @@ __device__ void wave_tridiag(const double* G, double gs, int n, double* vw, doub
   }
 }
 
-// Numbers of eigenvalues of T below xa and below xb: sign changes along the
-// leading principal minors m_0 = 1, m_1, ..., m_n of T - x I, from the
-// three-term recurrence m_{r+1} = (d_r - x) m_r - e_{r-1}^2 m_{r-1} (two
-// recurrences interleaved, no division; a zero minor counts as non-negative).
-// Every four rows both carried minors are scaled by the same power of two so
-// that they stay in range.  tri[2i] = d_i, tri[2i+1] = e_{i-1}^2 raised to at
-// least 2^-700 (so that a zero minor cannot zero the rest of the sequence; for
-// T scaled to norm about 1 the change is far below rounding), read by all
-// lanes at the same 16-byte aligned LDS address.  Rows are taken four at a
-// time: rows n .. 63 must hold d = 4, e^2 = 0, which adds no sign change for
-// |x| < 2.
-__device__ __forceinline__ void sturm_count2(const double* tri, int n, double xa, double xb, int& ca, int& cb) {
+// The reduction above with the row bound NR = n rounded up to 16: rows past n
+// hold zeros, so the shorter loops give the same result.
+__device__ void wave_tridiag(const double* G, double gs, int n, double* vw, double* Hv, double& dr, double& er,
+                             double& br) {
+  if (n > 48)
+    tridiag_nr<64>(G, gs, n, vw, Hv, dr, er, br);
+  else if (n > 32)
+    tridiag_nr<48>(G, gs, n, vw, Hv, dr, er, br);
+  else if (n > 16)
+    tridiag_nr<32>(G, gs, n, vw, Hv, dr, er, br);
+  else
+    tridiag_nr<16>(G, gs, n, vw, Hv, dr, er, br);
+}
+
+// Numbers of eigenvalues of T below each of the P points x[q]: sign changes
+// along the leading principal minors m_0 = 1, m_1, ..., m_n of T - x I, from
+// the three-term recurrence m_{r+1} = (d_r - x) m_r - e_{r-1}^2 m_{r-1} (P
+// recurrences interleaved on the same rows, no division; a zero minor counts
+// as non-negative).  Every four rows the two carried minors of each point are
+// scaled by the same power of two so that they stay in range.  tri[2i] = d_i,
+// tri[2i+1] = e_{i-1}^2 raised to at least 2^-700 (so that a zero minor cannot
+// zero the rest of the sequence; for T scaled to norm about 1 the change is
+// far below rounding), read by all lanes at the same 16-byte aligned LDS
+// address.  Rows are taken four at a time: rows n .. 63 must hold d = 4,
+// e^2 = 0, which adds no sign change for |x| < 2.
+template <int P>
+__device__ __forceinline__ void sturm_count(const double* tri, int n, const double (&x)[P], int (&cnt)[P]) {
   const double2* t2 = reinterpret_cast<const double2*>(tri);
-  double a1 = 1.0, a2 = 0.0, b1 = 1.0, b2 = 0.0;
-  int na = 0, nb = 0;
+  double m1[P], m2[P];
+  int nc[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    m1[q] = 1.0;
+    m2[q] = 0.0;
+    nc[q] = 0;
+  }
   double2 de[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) de[t] = t2[t];
@@ -571,35 +628,35 @@ __device__ __forceinline__ void sturm_count2(const double* tri, int n, double xa
 #pragma unroll
     for (int t = 0; t < 4; ++t) dn[t] = t2[(r0 + 4 + t) & 63];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double pa = fma(de[t].x - xa, a1, -de[t].y * a2);
-      const double pb = fma(de[t].x - xb, b1, -de[t].y * b2);
-      na += (pa < 0.0) != (a1 < 0.0) ? 1 : 0;
-      nb += (pb < 0.0) != (b1 < 0.0) ? 1 : 0;
-      a2 = a1;
-      a1 = pa;
-      b2 = b1;
-      b1 = pb;
-    }
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const double pq = fma(de[t].x - x[q], m1[q], -de[t].y * m2[q]);
+        nc[q] += (pq < 0.0) != (m1[q] < 0.0) ? 1 : 0;
+        m2[q] = m1[q];
+        m1[q] = pq;
+      }
 #pragma unroll
     for (int t = 0; t < 4; ++t) de[t] = dn[t];
-    const int sa = -__builtin_amdgcn_frexp_exp(a1), sb = -__builtin_amdgcn_frexp_exp(b1);
-    a1 = __builtin_amdgcn_ldexp(a1, sa);
-    a2 = __builtin_amdgcn_ldexp(a2, sa);
-    b1 = __builtin_amdgcn_ldexp(b1, sb);
-    b2 = __builtin_amdgcn_ldexp(b2, sb);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int e = -__builtin_amdgcn_frexp_exp(m1[q]);
+      m1[q] = __builtin_amdgcn_ldexp(m1[q], e);
+      m2[q] = __builtin_amdgcn_ldexp(m2[q], e);
+    }
   }
-  ca = na;
-  cb = nb;
+#pragma unroll
+  for (int q = 0; q < P; ++q) cnt[q] = nc[q];
 }
 
 // The K (<= n) largest eigenvalues of T (lane i holds d_i, e_i) into lam[0..K)
 // in decreasing order, by multisection of the Gershgorin interval: g = 64 / K
-// lanes (at most 3) share an eigenvalue and each evaluates two interior points
+// lanes (at most 3) share an eigenvalue and each evaluates SP interior points
 // per round, until the bracket is within a few ulps of the eigenvalue or of
-// the norm of T.  tri: 2 * 64 doubles (16-byte aligned), xs: 128 doubles, cs:
-// 128 ints (LDS).
+// the norm of T.  tri: 2 * 64 doubles (16-byte aligned), xs: 64 * SP doubles,
+// cs: 64 * SP ints (LDS).
 // Returns the norm bound max |Gershgorin end|.
+constexpr int SP = 2;
 __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri, double* xs, int* cs, double* lam) {
   const int i = threadIdx.x;
   const bool own = i < n;
@@ -628,25 +685,31 @@ __device__ double wave_tri_topk(double dr, double er, int n, int K, double* tri,
   hi += atol + pad;
   __syncthreads();
   const int sidx = n - 1 - t;  // position of the target in ascending order
-  const int npt = 2 * g;       // points per eigenvalue and round
+  const int npt = SP * g;      // points per eigenvalue and round
   for (int it = 0; it < 128; ++it) {
     const double w = (hi - lo) / double(npt + 1);
-    const double xa = lo + w * double(2 * r + 1), xb = lo + w * double(2 * r + 2);
-    int ca, cb;
-    sturm_count2(tri, n, xa * sc, xb * sc, ca, cb);
-    xs[2 * i] = xa;
-    xs[2 * i + 1] = xb;
-    cs[2 * i] = ca;
-    cs[2 * i + 1] = cb;
+    double xq[SP], xsc[SP];
+    int cq[SP];
+#pragma unroll
+    for (int q = 0; q < SP; ++q) {
+      xq[q] = lo + w * double(SP * r + q + 1);
+      xsc[q] = xq[q] * sc;
+    }
+    sturm_count<SP>(tri, n, xsc, cq);
+#pragma unroll
+    for (int q = 0; q < SP; ++q) {
+      xs[SP * i + q] = xq[q];
+      cs[SP * i + q] = cq[q];
+    }
     __syncthreads();
     if (act) {
       double nlo = lo, nhi = hi;
       for (int q = 0; q < npt; ++q) {
-        const double xq = xs[2 * t * g + q];
-        if (cs[2 * t * g + q] <= sidx)
-          nlo = fmax(nlo, xq);
+        const double xv = xs[SP * t * g + q];
+        if (cs[SP * t * g + q] <= sidx)
+          nlo = fmax(nlo, xv);
         else
-          nhi = fmin(nhi, xq);
+          nhi = fmin(nhi, xv);
       }
       lo = nlo;
       hi = nhi;

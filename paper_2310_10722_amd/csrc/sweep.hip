@@ -1041,16 +1041,18 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
   // one 16-byte aligned block for the phases' scratch: the broadcast vectors
-  // of the reduction, the tridiagonal and the bisection points, the
-  // factorisation's rows, and (once those are dead) the staged reflectors
+  // of the reduction, the tridiagonal and the bisection points, then the
+  // factorisation's rows (over the dead points), and (once those are dead)
+  // the staged reflectors
   __shared__ __attribute__((aligned(16))) double scr[576];
   __shared__ double lam[64];
-  __shared__ int cs[128];
+  __shared__ int cs[64 * SP];
   double* vw = scr;
   double* tri = scr + 128;
+  double* xs = scr + 256;  // 64 * SP
   double* de = scr + 256;
-  double* xs = scr + 384;
   double* rk = scr + 512;
+  static_assert(256 + 64 * SP <= 512, "bisection points overlap rk");
   const int s = blockIdx.x, tid = threadIdx.x;
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
