@@ -1093,6 +1093,96 @@ __device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D
   __syncthreads();
 }
 
+// All eigenpairs of a symmetric n x n matrix (1 <= n <= 16) in one wavefront
+// by the cyclic Jacobi method: n rounded up to even, nn, players meet in the
+// round-robin order, nn / 2 disjoint plane rotations per step and nn - 1
+// steps per sweep, each rotation the one that zeroes its off-diagonal pair
+// (the symmetric Schur decomposition of the 2 x 2 block).  A pair is skipped
+// when its entry is below 2^-53 sqrt(|a_pp a_qq|) or below 1e-18 (the matrix
+// is expected scaled to a largest diagonal entry of about 1); the sweeps stop
+// when a whole sweep is skipped, after at most 40.  Lane (q, c) = (lane / 16,
+// lane % 16) applies the rotations to rows q, q + 4, q + 8, q + 12 of column
+// c.  A and V: 16 x 17 doubles of LDS each (row stride 17); A holds the
+// matrix, zero outside n x n; on return its diagonal holds the eigenvalues and
+// column i of V the eigenvector of A[i][i].  rot: 32 doubles of LDS, part: 16
+// ints of LDS.  Returns the number of sweeps.
+__device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part) {
+  const int lane = threadIdx.x, c = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) V[(q + 4 * t) * 17 + c] = q + 4 * t == c ? 1.0 : 0.0;
+  __syncthreads();
+  if (n < 2) return 0;
+  const int nn = (n + 1) & ~1, m = nn - 1;
+  int sw = 0;
+  for (; sw < 40; ++sw) {
+    bool turned = false;
+    for (int st = 0; st < m; ++st) {
+      if (lane < nn) {
+        // partner of player i in step st: the last player meets st, the others
+        // i and j with i + j = 2 st (mod nn - 1)
+        const int i = lane;
+        int p;
+        if (i == m) {
+          p = st;
+        } else {
+          int j = (2 * st - i) % m;
+          if (j < 0) j += m;
+          p = j == i ? m : j;
+        }
+        const int lo = i < p ? i : p, hi = i < p ? p : i;
+        const double a = A[lo * 18], b = A[hi * 18], o = A[lo * 17 + hi];
+        double cr = 1.0, sr = 0.0;
+        if (fabs(o) > 1e-18 && fabs(o) > 0x1p-53 * sqrt(fabs(a * b))) {
+          const double tau = (b - a) / (2.0 * o);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double cv = 1.0 / sqrt(1.0 + t * t);
+          cr = cv;
+          sr = i == lo ? -t * cv : t * cv;  // new column i = cr col_i + sr col_p
+          turned = true;
+        }
+        part[i] = p;
+        rot[i] = cr;
+        rot[16 + i] = sr;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      const bool cin = c < nn;
+      const int pc = cin ? part[c] : c;
+      const double cc = cin ? rot[c] : 1.0, sc = cin ? rot[16 + c] : 0.0;
+      double h[4], v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = q + 4 * t;
+        h[t] = fma(cc, A[r * 17 + c], sc * A[r * 17 + pc]);
+        v[t] = fma(cc, V[r * 17 + c], sc * V[r * 17 + pc]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = q + 4 * t;
+        A[r * 17 + c] = h[t];
+        V[r * 17 + c] = v[t];
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = q + 4 * t;
+        const bool rin = r < nn;
+        const int pr = rin ? part[r] : r;
+        const double cq = rin ? rot[r] : 1.0, sq = rin ? rot[16 + r] : 0.0;
+        h[t] = fma(cq, A[r * 17 + c], sq * A[pr * 17 + c]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A[(q + 4 * t) * 17 + c] = h[t];
+      __syncthreads();
+    }
+    if (wave_first(turned) == 64) break;
+  }
+  return sw;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = team_sum(v, 64);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;

@@ -166,20 +166,21 @@ __device__ __forceinline__ void win_close(unsigned long long* win, unsigned long
   }
 }
 
-constexpr int GTR = 8;  // rows per tile of the Gram kernel
-
-// One wavefront per (gate side, sweep).  Threads are grouped: group g of
-// ngrp = 64 / ncols groups owns Gram rows i = 0..ncols-1 (one per thread) and
-// the column block [g cw, g cw + cw), cw = ceil(ncols / ngrp), so every
-// thread keeps at most NMAX accumulators in registers and the loops over the
-// block are uniform.  Tiles of GTR rows are staged in LDS with the row weights
-// applied; columns beyond ncols are zero.
-// A launch handles the Grams whose column block cw lies in (cwlo, NMAX]: a
-// variant with few accumulators (more waves per SIMD) takes the narrow Grams.
-template <typename T, int NMAX>
+// One wavefront per (gate side, sweep): G = X^T X for the row-weighted view X
+// (rows x ncols) of the site tensor, on the matrix cores.  Rows are taken 64
+// at a time: lane l finds the offset and the weight (the product of
+// sqrt(lambda) over the three other legs, the simple-update environment) of
+// row r0 + l, kept in LDS.  Then sixteen steps of four rows: lane
+// (li, lq) = (lane % 16, lane / 16) loads X[r][16 b + li] of its row
+// r = r0 + 4 s + lq for every 16-column block b, and one
+// v_mfma_f64_16x16x4f64 per block pair b1 <= b2 accumulates X_b1^T X_b2 (the
+// A and B operands are the same loaded values; item q of a lane holds row
+// lq + 4 q of the block).  Loads are issued four steps ahead of their
+// products.  The launch handles the Grams with ncols in (nlo, 16 NB].
+template <typename T, int NB>
 __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
-                                             int cwlo) {
-  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, tid = threadIdx.x;
+                                             int nlo) {
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
   const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
@@ -187,39 +188,34 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   site_dims(A, sweep, site, D);
   const Split v = make_split(D, leg, d);
   const int ncols = d * v.Dx;
-  const int ngrp = ncols <= 64 ? 64 / ncols : 1;
-  const int cw = (ncols + ngrp - 1) / ngrp;
-  const int tw = ngrp * cw;  // tile width (>= ncols, padded with zeros)
-  if (cw <= cwlo || cw > NMAX) return;
+  if (ncols <= nlo || ncols > 16 * NB) return;
   const unsigned long long w0 = win_open(A.win);
   __shared__ double slam[4][MAXCHI];
-  __shared__ double tile[GTR * 65];  // rows of tw <= 64 entries, stride tw + 1 (no bank conflicts)
-  __shared__ int colofs[64];
-  __shared__ int rowbase[GTR];
-  __shared__ double rowsc[GTR];
-  for (int e = tid; e < 4 * MAXCHI; e += 64) {
+  __shared__ int rowbase[64];
+  __shared__ double rowsc[64];
+  for (int e = lane; e < 4 * MAXCHI; e += 64) {
     const int l = e / MAXCHI, k = e % MAXCHI;
     const int b = A.leg_bond[site * 4 + l];
     double val = 1.0;
     if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
     slam[l][k] = val;
   }
-  for (int col = tid; col < tw; col += 64) {
-    const int p = col / v.Dx, x = col - p * v.Dx;
-    colofs[col] = col < ncols ? x * v.Cp * d + p : -1;
-  }
-  const int grp = tid / ncols, i = tid - grp * ncols, j0 = grp * cw;
-  const bool act = grp < ngrp;
-  double acc[NMAX];
+  const int li = lane & 15, lq = lane >> 4;
+  int cofs[NB];
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+  for (int b = 0; b < NB; ++b) {
+    const int col = 16 * b + li, p = col / v.Dx, x = col - p * v.Dx;
+    cofs[b] = col < ncols ? x * v.Cp * d + p : -1;
+  }
+  constexpr int NP = NB * (NB + 1) / 2;
+  dbl4 acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   const T* t = tens<T>(A, par, sweep, site);
-  for (int r0 = 0; r0 < v.rows; r0 += GTR) {
-    __syncthreads();
-    if (tid < GTR) {
-      // row r = (a, c): base offset and the product of sqrt(lambda) over the
-      // three other legs (the simple-update environment)
-      const int r = r0 + tid;
+  __syncthreads();
+  for (int r0 = 0; r0 < v.rows; r0 += 64) {
+    {
+      const int r = r0 + lane;
       int base = 0;
       double sc = 0.0;
       if (r < v.rows) {
@@ -239,35 +235,57 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
           aa = q;
         }
       }
-      rowbase[tid] = base;
-      rowsc[tid] = sc;
+      rowbase[lane] = base;
+      rowsc[lane] = sc;
     }
     __syncthreads();
-    const int nr = v.rows - r0 < GTR ? v.rows - r0 : GTR;
-    for (int e = tid; e < GTR * tw; e += 64) {
-      const int rl = e & (GTR - 1), col = e / GTR;
-      const int off = colofs[col];
-      tile[rl * (tw + 1) + col] = (rl < nr && off >= 0) ? double(t[rowbase[rl] + off]) * rowsc[rl] : 0.0;
-    }
-    __syncthreads();
-    if (act)
-      for (int rl = 0; rl < nr; ++rl) {
-        const double* tr = tile + rl * (tw + 1);
-        const double ti = tr[i];
+    const int nleft = v.rows - r0;
+    for (int s0 = 0; s0 < 16; s0 += 4) {
+      if (4 * s0 >= nleft) break;  // uniform
+      double xv[4][NB];
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k)
-          if (k < cw) acc[k] += ti * tr[j0 + k];
+      for (int u = 0; u < 4; ++u) {
+        const int rl = 4 * (s0 + u) + lq;
+        const bool ok = rl < nleft;
+        const int base = rowbase[rl];
+        const double sc = rowsc[rl];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) xv[u][b] = (ok && cofs[b] >= 0) ? double(t[base + cofs[b]]) * sc : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int q = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+          for (int b2 = b1; b2 < NB; ++b2) {
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][b1], xv[u][b2], acc[q], 0, 0, 0);
+            ++q;
+          }
+      }
+    }
+    __syncthreads();  // the next chunk's offsets replace these
   }
-  if (A.bytes_ctr && tid == 0)
+  if (A.bytes_ctr && lane == 0)
     atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
               (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
-  if (side == 0 && tid == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
+  if (side == 0 && lane == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
   double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
-  if (act)
+  int q = 0;
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-      if (k < cw && j0 + k < ncols) out[i * ncols + j0 + k] = acc[k];
+  for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+    for (int b2 = b1; b2 < NB; ++b2) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int i = 16 * b1 + lq + 4 * it, j = 16 * b2 + li;
+        if (i < ncols && j < ncols) {
+          out[i * ncols + j] = acc[q][it];
+          if (b1 != b2) out[j * ncols + i] = acc[q][it];
+        }
+      }
+      ++q;
+    }
   win_close(A.win, w0);
 }
 
@@ -1033,11 +1051,66 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
 }
 
 // Families of at most ZBIG vectors when the rank rule allows the Gram route:
+// The small-order branch of k_zip_beig (nv <= 16): the scaled Gram into a
+// 16 x 17 LDS block, all eigenpairs by wave_jacobi16, the values sorted
+// descending into Sout, the rank rule, the kept vectors into Fv.  A separate
+// function so that its registers do not weigh on the large-order path.
+__device__ __noinline__ void zip_beig_small(const ZipArgs& Z, int s, int* zd, int nv, const double* G, double gsc,
+                                            double* Sout, double* Fv, double* zsm, double* scr, int* cs) {
+  const int tid = threadIdx.x;
+  double* Aj = zsm;
+  double* Vj = zsm + 272;
+  int* part = cs;
+  int* ord = cs + 16;
+  const int c = tid & 15, q = tid >> 4;
+  const double gs = 1.0 / gsc;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = q + 4 * t;
+    Aj[r * 17 + c] = (r < nv && c < nv) ? G[r * nv + c] * gs : 0.0;
+  }
+  const int nsw = wave_jacobi16(Aj, Vj, nv, scr, part);
+  if (tid < nv) {
+    const double li = Aj[tid * 18];
+    int rank = 0;
+    for (int j = 0; j < nv; ++j) rank += sorts_before(Aj[j * 18], j, li, tid) ? 1 : 0;
+    ord[rank] = tid;
+    Sout[rank] = sqrt(fmax(li * gsc, 0.0));
+  }
+  __syncthreads();
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
+  const bool bad = Dn < 1;
+  if (bad) Dn = 1;
+  for (int e = tid; e < nv * Dn; e += 64) Fv[e] = Vj[(e / Dn) * 17 + ord[e % Dn]];
+  if (Z.flop_ctr && tid == 0) {
+    const double n = nv, D = Dn;
+    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 10.0 * D * n + 16.0 * D * D * n;
+    atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
+  }
+  if (tid == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], nsw);
+    const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (nsw >= 40 ? 8u : 0u);
+    if (f) atomicOr(&Z.flags[s], f);
+  }
+}
+
+// Dynamic LDS of k_zip_beig: the eigenvectors and the orthogonalisation's
+// triangle at row stride ys, and at least the two 16 x 17 blocks of the
+// small-order path.
+static inline size_t beig_lds_bytes(int ys) {
+  const size_t d = size_t(64 + ys) * ys;
+  return (d > 544 ? d : 544) * sizeof(double);
+}
+
 // leading eigenpairs of the PSD Gram (eigenvalues S^2) in one wavefront.  The
-// Gram is scaled by its largest diagonal entry; only the min(nv, chi_m + 1) largest eigenvalues (all the
-// rank rule reads) and the vectors it keeps are computed.  The reflectors of
-// the tridiagonal reduction overwrite the Gram; the kept vectors sit in LDS
-// (row stride eig_ys) and are copied to Fv.
+// Gram is scaled by its largest diagonal entry.  Orders up to 16 take every
+// eigenpair by Jacobi rotations.  Larger ones compute only the
+// min(nv, chi_m + 1) largest eigenvalues (all the rank rule reads) and the
+// vectors it keeps; the reflectors of the tridiagonal reduction overwrite the
+// Gram and the kept vectors sit in LDS (row stride eig_ys) before they are
+// copied to Fv.
 __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
   // one 16-byte aligned block for the phases' scratch: the broadcast vectors
@@ -1062,6 +1135,7 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
   double* Sout = Z.zS + int64_t(s) * 1024;
   const double gd = wave_max(tid < nv ? G[tid * nv + tid] : 0.0);
   const double gsc = gd > 0.0 ? gd : 1.0;
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   double dr, er, br;
   wave_tridiag(G, 1.0 / gsc, nv, vw, G, dr, er, br);
   const int K = nv < Z.chi_m + 1 ? nv : Z.chi_m + 1;
@@ -1082,7 +1156,6 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
     const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 10.0 * D * n + 16.0 * D * D * n;
     atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
   }
-  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   for (int e = tid; e < nv * Dn; e += 64) Fv[e] = zsm[(e / Dn) * ys + e % Dn];
   if (tid == 0) {
     zd[8] = Dn;
@@ -1413,10 +1486,11 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 template <typename T>
 static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
                           hipStream_t st) {
-  // ncap <= 64 is checked by the host before any launch
-  hipLaunchKernelGGL((k_gram<T, 16>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
+  // ncap <= 64 is checked by the host before any launch; Grams of up to 32
+  // columns (three block pairs) and of 33 to 64 (ten) in separate launches
+  hipLaunchKernelGGL((k_gram<T, 2>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
   if (ncap > 32)
-    hipLaunchKernelGGL((k_gram<T, 64>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 16);
+    hipLaunchKernelGGL((k_gram<T, 4>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 32);
 }
 
 void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
@@ -1497,7 +1571,7 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
-      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), size_t(64 + Z.eig_ys) * Z.eig_ys * 8, st, Z, x,
+      hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), beig_lds_bytes(Z.eig_ys), st, Z, x,
                          y);
       hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
