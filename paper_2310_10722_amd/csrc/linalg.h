@@ -1093,19 +1093,29 @@ __device__ void wave_tri_backtransform(const double* Hv, double br, int n, int D
   __syncthreads();
 }
 
+// 1 / sqrt(x) for x >= 1 from the hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // All eigenpairs of a symmetric n x n matrix (1 <= n <= 16) in one wavefront
 // by the cyclic Jacobi method: n rounded up to even, nn, players meet in the
 // round-robin order, nn / 2 disjoint plane rotations per step and nn - 1
 // steps per sweep, each rotation the one that zeroes its off-diagonal pair
-// (the symmetric Schur decomposition of the 2 x 2 block).  A pair is skipped
-// when its entry is below 2^-53 sqrt(|a_pp a_qq|) or below 1e-18 (the matrix
-// is expected scaled to a largest diagonal entry of about 1); the sweeps stop
-// when a whole sweep is skipped, after at most 40.  Lane (q, c) = (lane / 16,
-// lane % 16) applies the rotations to rows q, q + 4, q + 8, q + 12 of column
-// c.  A and V: 16 x 17 doubles of LDS each (row stride 17); A holds the
-// matrix, zero outside n x n; on return its diagonal holds the eigenvalues and
-// column i of V the eigenvector of A[i][i].  rot: 32 doubles of LDS, part: 16
-// ints of LDS.  Returns the number of sweeps.
+// (the symmetric Schur decomposition of the 2 x 2 block; cos = 1 / sqrt(1 +
+// t^2) to working precision, so the rotation is orthogonal whatever the
+// rounding of t).  A pair is skipped when its entry is below 2^-53
+// sqrt(|a_pp a_qq|) or below 1e-18 (the matrix is expected scaled to a
+// largest diagonal entry of about 1); the sweeps stop when a whole sweep is
+// skipped, after at most 40.  Lane (q, c) = (lane / 16, lane % 16) updates rows
+// q, q + 4, q + 8, q + 12 of column c of A <- J^T A J and of V <- V J in one
+// pass from the old entries.  A and V: 16 x 17 doubles of LDS each (row stride
+// 17); A holds the matrix, zero outside n x n; on return its diagonal holds
+// the eigenvalues and column i of V the eigenvector of A[i][i].  rot: 32
+// doubles of LDS, part: 16 ints of LDS.  Returns the number of sweeps.
 __device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part) {
   const int lane = threadIdx.x, c = lane & 15, q = lane >> 4;
 #pragma unroll
@@ -1133,9 +1143,18 @@ __device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part
         const double a = A[lo * 18], b = A[hi * 18], o = A[lo * 17 + hi];
         double cr = 1.0, sr = 0.0;
         if (fabs(o) > 1e-18 && fabs(o) > 0x1p-53 * sqrt(fabs(a * b))) {
-          const double tau = (b - a) / (2.0 * o);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cv = 1.0 / sqrt(1.0 + t * t);
+          const double tau = (b - a) * approx_rcp(2.0 * o);
+          const double at = fabs(tau);
+          // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), the smaller root
+          double t;
+          if (at < 1e100) {
+            const double x = fma(tau, tau, 1.0);
+            t = approx_rcp(at + x * rsqrt_nr(x));
+          } else {
+            t = 0.5 / at;
+          }
+          if (tau < 0.0) t = -t;
+          const double cv = rsqrt_nr(fma(t, t, 1.0));
           cr = cv;
           sr = i == lo ? -t * cv : t * cv;  // new column i = cr col_i + sr col_p
           turned = true;
@@ -1145,7 +1164,7 @@ __device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part
         rot[16 + i] = sr;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
+      // A'[r][c] = sum over r0 in {r, pr}, c0 in {c, pc} of J[r0][r] A[r0][c0] J[c0][c]
       const bool cin = c < nn;
       const int pc = cin ? part[c] : c;
       const double cc = cin ? rot[c] : 1.0, sc = cin ? rot[16 + c] : 0.0;
@@ -1153,7 +1172,12 @@ __device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = q + 4 * t;
-        h[t] = fma(cc, A[r * 17 + c], sc * A[r * 17 + pc]);
+        const bool rin = r < nn;
+        const int pr = rin ? part[r] : r;
+        const double cq = rin ? rot[r] : 1.0, sq = rin ? rot[16 + r] : 0.0;
+        const double rowr = fma(cc, A[r * 17 + c], sc * A[r * 17 + pc]);
+        const double rowp = fma(cc, A[pr * 17 + c], sc * A[pr * 17 + pc]);
+        h[t] = (pr == c && r != c && sq != 0.0) ? 0.0 : fma(cq, rowr, sq * rowp);
         v[t] = fma(cc, V[r * 17 + c], sc * V[r * 17 + pc]);
       }
       __syncthreads();
@@ -1163,19 +1187,6 @@ __device__ int wave_jacobi16(double* A, double* V, int n, double* rot, int* part
         A[r * 17 + c] = h[t];
         V[r * 17 + c] = v[t];
       }
-      __syncthreads();
-      // rows: A <- J^T A
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = q + 4 * t;
-        const bool rin = r < nn;
-        const int pr = rin ? part[r] : r;
-        const double cq = rin ? rot[r] : 1.0, sq = rin ? rot[16 + r] : 0.0;
-        h[t] = fma(cq, A[r * 17 + c], sq * A[pr * 17 + c]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < 4; ++t) A[(q + 4 * t) * 17 + c] = h[t];
       __syncthreads();
     }
     if (wave_first(turned) == 64) break;

@@ -1053,9 +1053,8 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
 // Families of at most ZBIG vectors when the rank rule allows the Gram route:
 // The small-order branch of k_zip_beig (nv <= 16): the scaled Gram into a
 // 16 x 17 LDS block, all eigenpairs by wave_jacobi16, the values sorted
-// descending into Sout, the rank rule, the kept vectors into Fv.  A separate
-// function so that its registers do not weigh on the large-order path.
-__device__ __noinline__ void zip_beig_small(const ZipArgs& Z, int s, int* zd, int nv, const double* G, double gsc,
+// descending into Sout, the rank rule, the kept vectors into Fv.
+__device__ __forceinline__ void zip_beig_small(const ZipArgs& Z, int s, int* zd, int nv, const double* G, double gsc,
                                             double* Sout, double* Fv, double* zsm, double* scr, int* cs) {
   const int tid = threadIdx.x;
   double* Aj = zsm;
@@ -1111,31 +1110,19 @@ static inline size_t beig_lds_bytes(int ys) {
 // vectors it keeps; the reflectors of the tridiagonal reduction overwrite the
 // Gram and the kept vectors sit in LDS (row stride eig_ys) before they are
 // copied to Fv.
-__global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
-  extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
-  // one 16-byte aligned block for the phases' scratch: the broadcast vectors
-  // of the reduction, the tridiagonal and the bisection points, then the
-  // factorisation's rows (over the dead points), and (once those are dead)
-  // the staged reflectors
-  __shared__ __attribute__((aligned(16))) double scr[576];
-  __shared__ double lam[64];
-  __shared__ int cs[64 * SP];
+// The order-17-and-up branch of k_zip_beig: Householder reduction, the
+// leading eigenvalues by multisection, the rank rule, the kept vectors by
+// inverse iteration and the back-transformation, copied to Fv.
+__device__ __forceinline__ void zip_beig_large(const ZipArgs& Z, int s, int* zd, int nv, double* G, double gsc,
+                                            double* Sout, double* Fv, double* zsm, double* scr, double* lam,
+                                            int* cs) {
+  const int tid = threadIdx.x;
   double* vw = scr;
   double* tri = scr + 128;
   double* xs = scr + 256;  // 64 * SP
   double* de = scr + 256;
   double* rk = scr + 512;
   static_assert(256 + 64 * SP <= 512, "bisection points overlap rk");
-  const int s = blockIdx.x, tid = threadIdx.x;
-  int* zd = Z.zdim + int64_t(s) * 12;
-  const int nv = zd[7];
-  if (nv > ZBIG) return;  // k_zip_bbig takes it
-  const unsigned long long w0 = win_open(Z.win);
-  double* G = Z.Gm + int64_t(s) * Z.bigcap;
-  double* Sout = Z.zS + int64_t(s) * 1024;
-  const double gd = wave_max(tid < nv ? G[tid * nv + tid] : 0.0);
-  const double gsc = gd > 0.0 ? gd : 1.0;
-  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
   double dr, er, br;
   wave_tridiag(G, 1.0 / gsc, nv, vw, G, dr, er, br);
   const int K = nv < Z.chi_m + 1 ? nv : Z.chi_m + 1;
@@ -1163,6 +1150,33 @@ __global__ __launch_bounds__(64) void k_zip_beig(ZipArgs Z, int x, int y) {
     const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u);
     if (f) atomicOr(&Z.flags[s], f);
   }
+}
+
+// (at most 256 registers: two wavefronts per SIMD, the launch's 2048
+// problems resident at once)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_zip_beig(ZipArgs Z, int x, int y) {
+  extern __shared__ double zsm[];  // 64 * eig_ys vectors, then eig_ys^2 for the orthogonalisation
+  // one 16-byte aligned block for the phases' scratch: the broadcast vectors
+  // of the reduction, the tridiagonal and the bisection points, then the
+  // factorisation's rows (over the dead points), and (once those are dead)
+  // the staged reflectors
+  __shared__ __attribute__((aligned(16))) double scr[576];
+  __shared__ double lam[64];
+  __shared__ int cs[64 * SP];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* zd = Z.zdim + int64_t(s) * 12;
+  const int nv = zd[7];
+  if (nv > ZBIG) return;  // k_zip_bbig takes it
+  const unsigned long long w0 = win_open(Z.win);
+  double* G = Z.Gm + int64_t(s) * Z.bigcap;
+  double* Sout = Z.zS + int64_t(s) * 1024;
+  const double gd = wave_max(tid < nv ? G[tid * nv + tid] : 0.0);
+  const double gsc = gd > 0.0 ? gd : 1.0;
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;  // L4 is dead after kernel a
+  if (nv <= 16)
+    zip_beig_small(Z, s, zd, nv, G, gsc, Sout, Fv, zsm, scr, cs);
+  else
+    zip_beig_large(Z, s, zd, nv, G, gsc, Sout, Fv, zsm, scr, lam, cs);
   win_close(Z.win, w0);
 }
 
