@@ -189,9 +189,17 @@ class Assembler {
     R.pre1 = int(P.ones.size());
     for (int c = 0; c < 4; ++c) {
       R.gate0[c] = int(P.gates.size());
-      for (auto& g : gates) {
-        int cls = g.kind == 0 ? (g.x % 2) : 2 + (g.y % 2);
-        if (cls != c) continue;
+      // the bonds of a class are disjoint, so their order is free: gates with
+      // the larger physical dims first, so that the launches for wide Grams
+      // and reabsorptions cover a prefix of the class only
+      std::vector<const PGate*> cg;
+      for (auto& g : gates)
+        if ((g.kind == 0 ? (g.x % 2) : 2 + (g.y % 2)) == c) cg.push_back(&g);
+      std::stable_sort(cg.begin(), cg.end(), [](const PGate* a, const PGate* b) {
+        return std::max(a->dA, a->dB) > std::max(b->dA, b->dB);
+      });
+      for (const PGate* gpt : cg) {
+        const PGate& g = *gpt;
         int sa = g.y * Lx + g.x, sb = g.kind == 0 ? sa + 1 : sa + Lx;
         if (g.dA != d[sa] || g.dB != d[sb]) return "gate dims do not match site dims";
         DevGate G{};

@@ -409,12 +409,20 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         if (ng <= 0) continue;
         const DevGate* gp = n->d_gates + R.gate0[k];
         const int cls = int(li) * 4 + k;
+        // gates come ordered by physical dim, largest first: the ones whose
+        // Gram or reabsorbed rows (d times a bond of at most legcap) can pass
+        // a width form a prefix
+        auto n_wider = [&](int w) {
+          int c = 0;
+          while (c < ng && std::max(P.gates[R.gate0[k] + c].dA, P.gates[R.gate0[k] + c].dB) * L.legcap > w) ++c;
+          return c;
+        };
         A.win = timing ? win + size_t(2 * cls) * 128 : nullptr;
-        launch_gram(prec, A, gp, ng, gram, L.ncap, s);
+        launch_gram(prec, A, gp, ng, n_wider(32), gram, L.ncap, s);
         A.win = nullptr;
         launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
         A.win = timing ? win + size_t(2 * cls + 1) * 128 : nullptr;
-        launch_reabsorb(prec, A, gp, ng, wbuf, L.ncap, s);
+        launch_reabsorb(prec, A, gp, ng, n_wider(16), n_wider(32), wbuf, L.ncap, s);
         A.win = nullptr;
         hot_l += 2;
       }

@@ -74,12 +74,14 @@ hipError_t set_kernel_lds_limits();
 void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const int32_t* init_off,
                  const int32_t* bond_dim0, hipStream_t st);
 void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_ops, hipStream_t st);
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+// n_wide (and n_w16, n_w32 below): the leading gates of the class whose Grams
+// (rows) can be wider than 32 (16, 32) entries; the others are never wider
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
                  hipStream_t st);
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout,
                   int ncap, int kdcap, hipStream_t st);
-void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win,
-                     int ncap, hipStream_t st);
+void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
+                     const double* win, int ncap, hipStream_t st);
 void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
                     hipStream_t st);
 void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const int32_t* f_off,

@@ -1498,22 +1498,24 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 }
 
 template <typename T>
-static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
                           hipStream_t st) {
   // ncap <= 64 is checked by the host before any launch; Grams of up to 32
-  // columns (three block pairs) and of 33 to 64 (ten) in separate launches
+  // columns (three block pairs) and of 33 to 64 (ten) in separate launches,
+  // the second over the leading n_wide gates (the only ones that can be wide)
   hipLaunchKernelGGL((k_gram<T, 2>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
-  if (ncap > 32)
-    hipLaunchKernelGGL((k_gram<T, 4>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 32);
+  if (ncap > 32 && n_wide > 0)
+    hipLaunchKernelGGL((k_gram<T, 4>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap,
+                       32);
 }
 
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, double* gout, int ncap,
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
                  hipStream_t st) {
   if (n_g <= 0) return;
   if (prec == 0)
-    gram_dispatch<double>(A, gates, n_g, gout, ncap, st);
+    gram_dispatch<double>(A, gates, n_g, n_wide, gout, ncap, st);
   else
-    gram_dispatch<float>(A, gates, n_g, gout, ncap, st);
+    gram_dispatch<float>(A, gates, n_g, n_wide, gout, ncap, st);
 }
 
 static size_t solve_lds(int n) {
@@ -1539,20 +1541,22 @@ void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const doubl
                        gin, wout, ncap, nsmall, kdcap);
 }
 
-void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, const double* win, int ncap,
-                     hipStream_t st) {
+void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
+                     const double* win, int ncap, hipStream_t st) {
   if (n_g <= 0) return;
-  dim3 g(2 * n_g, A.n_sweeps);
+  dim3 g(2 * n_g, A.n_sweeps), g16(2 * n_w16, A.n_sweeps), g32(2 * n_w32, A.n_sweeps);
   // three size classes: rows of at most 16 and 32 entries, then the rest up to
-  // 64 (the W staging takes 8, 16 and 32 KB of LDS)
+  // 64 (the W staging takes 8, 16 and 32 KB of LDS); the wider classes run
+  // over the leading gates that can have such rows
+  const bool w16 = ncap > 16 && n_w16 > 0, w32 = ncap > 32 && n_w32 > 0;
   if (prec == 0) {
     hipLaunchKernelGGL((k_reabsorb<double, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
-    if (ncap > 16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
-    if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<double, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    if (w16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    if (w32) hipLaunchKernelGGL((k_reabsorb<double, 64>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   } else {
     hipLaunchKernelGGL((k_reabsorb<float, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
-    if (ncap > 16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
-    if (ncap > 32) hipLaunchKernelGGL((k_reabsorb<float, 64>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    if (w16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    if (w32) hipLaunchKernelGGL((k_reabsorb<float, 64>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   }
 }
 
