@@ -474,7 +474,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       for (int x = 0; x < P.Lx; ++x)
       {
         Z.win = timing ? win + size_t(n_cls_win + y * P.Lx + x) * 128 : nullptr;
-        launch_zip_step(Z, x, y, s);
+        launch_zip_step(Z, x, y, L.legcap, s);
       }
     Z.win = nullptr;
     launch_finish(A, Z, logp_p, flags_p, s);

@@ -88,8 +88,9 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
                      const int32_t* par_final, double* fin, int64_t fin_stride, const int64_t* fin_off,
                      hipStream_t st);
 void launch_zip_init(const ZipArgs& Z, hipStream_t st);
-// stamps (or null): two wall-clock stamps around the decomposition launch
-void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st);
+// one zip-up step (x, y) of the boundary MPS: contraction, decomposition (all
+// but the last column), new site and carry; legcap bounds the network's bonds
+void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
 // Graph replay helpers: gather each item's syndrome into a dense buffer,
 // local item indices with their offsets, zero a counter block (no memset

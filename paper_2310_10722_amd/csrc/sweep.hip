@@ -1585,13 +1585,20 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_init, dim3(Z.n_sweeps), dim3(64), 0, st, Z);
 }
 
-void launch_zip_step(const ZipArgs& Z, int x, int y, hipStream_t st) {
+void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
   if (x + 1 < Z.Lx) {
     if (Z.gram_path) {
       hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), beig_lds_bytes(Z.eig_ys), st, Z, x,
                          y);
-      hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
+      // the order min(R, C) of the Gram, R = nu sD and C = aR wR, is bounded by
+      // the structure: nu = 1 in the first column, aR = 1 in the first row,
+      // sD = 1 in the last row; the larger-order kernel runs only where the
+      // bound passes ZBIG
+      const int64_t rcap = int64_t(x == 0 ? 1 : Z.chi_m) * (y + 1 == Z.Ly ? 1 : legcap);
+      const int64_t ccap = int64_t(y == 0 ? 1 : Z.chi_m) * legcap;
+      if ((rcap < ccap ? rcap : ccap) > ZBIG)
+        hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
     }
