@@ -124,6 +124,27 @@ def test_rotated_d5_fp32_chi16(ctx):
     assert err.max() <= 1e-3
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rotated_d5_boundary_chi32_gram_route(ctx, prec):
+    """chi_m = 32 with the reduced-precision rule (eps_rel 1e-6, tau_gap 1e-4),
+    so the boundary MPS takes the Gram route: the interior steps reach Gram
+    orders 96 to 128 (measured on the oracle for this workload) and take the
+    512-thread decomposition, the first and last rows and the first column stay
+    on the one-wavefront solver (Jacobi up to order 16, tridiagonal above).
+    Bounds as for chi_m = 16: 1e-6 in FP64 (the Gram route), 1e-3 in FP32."""
+    from paper_2310_10722_amd import tn3d
+    say(f"case: rotated d=5 T=5 chi=16 chi_m=32 {prec}, rule 1e-6/1e-4, 6 syndromes")
+    dem, m, _, _ = synth.config_workload(2, n=6)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    prm = tn3d.tn3d_params_default(16, 32, tn3d.PREC_FP64 if prec == "fp64" else tn3d.PREC_FP32)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    got, _ = gpu_logp(ctx, net, m, prm)
+    ref = oracle_rot(dem, m, prm)
+    err = np.abs(got[:, :2] - ref)
+    say("  max |d log p| =", err.max())
+    assert err.max() <= (1e-6 if prec == "fp64" else 1e-3)
+
+
 def test_decode_and_ragged_batch(ctx):
     from paper_2310_10722_amd import tn3d
     say("case: ragged batch L=2 / L=3 decode fp64")
