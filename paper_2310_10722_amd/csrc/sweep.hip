@@ -929,8 +929,13 @@ __device__ __forceinline__ void zip_dims(const ZipArgs& Z, int s, int x, int y, 
   sD = y + 1 < Ly ? zbd(Z, s, nbh + y * Lx + x) : 1;
 }
 
-__global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y) {
+// inline_dec: the step's decomposition is done here, not by a launch of its
+// own: in the last row R = nu sD = 1 (the carry starts at 1 and stays at the
+// rank 1 of its family; the bond below is 1), so the family is Th's one row,
+// its singular value the row's norm and its vector [1].
+__global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inline_dec) {
   __shared__ double gst[4096];
+  __shared__ double red[16];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int cur = y & 1;
   const double* Mold = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Z.Lx + x) * Z.mcap;
@@ -961,7 +966,17 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y) {
       [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; }, gst);
   const bool rows = R <= C;
   const int nv = rows ? R : C;
-  if (x + 1 < Z.Lx && Z.gram_path) {
+  if (inline_dec) {
+    double q = 0.0;
+    for (int k = tid; k < C; k += ZNT) q = fma(Th[k], Th[k], q);
+    const double S0 = sqrt(block_sum(q, red));
+    if (tid == 0) {
+      Z.zS[int64_t(s) * 1024] = S0;
+      Z.L4[int64_t(s) * Z.bigcap] = 1.0;  // Fv: L4 is dead after the second product
+      // a zero row is the rank rule's empty case; R != 1 cannot happen
+      if (!(S0 > 0.0) || R != 1) atomicOr(&Z.flags[s], 3u);
+    }
+  } else if (x + 1 < Z.Lx && Z.gram_path) {
     double* G = Z.Gm + int64_t(s) * Z.bigcap;
     if (rows)
       block_gemm512(
@@ -1586,8 +1601,9 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
 }
 
 void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st) {
-  hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y);
-  if (x + 1 < Z.Lx) {
+  const int inline_dec = (x + 1 < Z.Lx && y + 1 == Z.Ly) ? 1 : 0;
+  hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y, inline_dec);
+  if (x + 1 < Z.Lx && !inline_dec) {
     if (Z.gram_path) {
       hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), beig_lds_bytes(Z.eig_ys), st, Z, x,
                          y);
