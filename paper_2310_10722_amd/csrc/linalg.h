@@ -921,10 +921,10 @@ __device__ __forceinline__ void wave_cholqr(int n, int D, double* Y, int ys, dou
 // Eigenvectors of T for lam[0..D) (D <= 64) by inverse iteration: lane j
 // factors T - lam_j I by Gaussian elimination with partial pivoting (pivots
 // below tiny = 4 ulp * nrm raised to tiny) and solves twice from a
-// pseudo-random start; the D vectors are orthonormalised (Cholesky QR, twice),
-// solved once more (which removes what the orthogonalisation of a nearly
-// dependent member of a cluster amplified outside the cluster) and
-// orthonormalised again.  Vector j is Y[r * ys + j] (LDS, ys odd); R: ys * ys
+// pseudo-random start; the D vectors are orthonormalised (Cholesky QR once:
+// it only has to separate the members of a cluster), solved once more (which
+// removes what the orthogonalisation of a nearly dependent member amplified
+// outside the cluster) and orthonormalised again, twice.  Vector j is Y[r * ys + j] (LDS, ys odd); R: ys * ys
 // doubles of LDS; de: 2 * 64 doubles of LDS; rk: 64 doubles of LDS; U:
 // 4 * n * ys doubles of scratch, four per row and lane.
 __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm, const double* lam, double* de,
@@ -972,13 +972,13 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
       Y[r * ys + j] = double(h >> 8) * (1.0 / 16777216.0) - 0.5;
     }
   }
-  // two solves and two orthonormalisations, then one solve and two more (one
+  // two solves and one orthonormalisation, then one solve and two more (one
   // inlined copy of each step)
   for (int round = 0; round < 2; ++round) {
     if (j < D)
       for (int it = round; it < 2; ++it) tri_solve(n, U, Y, ys, j, swm);
     __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) wave_cholqr(n, D, Y, ys, R, rk);
+    for (int pass = 1 - round; pass < 2; ++pass) wave_cholqr(n, D, Y, ys, R, rk);
   }
 }
 
