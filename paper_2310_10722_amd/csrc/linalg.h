@@ -920,8 +920,9 @@ __device__ __forceinline__ void wave_cholqr(int n, int D, double* Y, int ys, dou
 
 // Eigenvectors of T for lam[0..D) (D <= 64) by inverse iteration: lane j
 // factors T - lam_j I by Gaussian elimination with partial pivoting (pivots
-// below tiny = 4 ulp * nrm raised to tiny) and solves twice from a
-// pseudo-random start; the D vectors are orthonormalised (Cholesky QR once:
+// below tiny = 4 ulp * nrm raised to tiny) and solves once from a
+// pseudo-random start (the shift is within a few ulps of the norm, so one
+// solve already leaves other eigenvectors at about ulp / gap); the D vectors are orthonormalised (Cholesky QR once:
 // it only has to separate the members of a cluster), solved once more (which
 // removes what the orthogonalisation of a nearly dependent member amplified
 // outside the cluster) and orthonormalised again, twice.  Vector j is Y[r * ys + j] (LDS, ys odd); R: ys * ys
@@ -972,11 +973,11 @@ __device__ void wave_tri_vectors(double dr, double er, int n, int D, double nrm,
       Y[r * ys + j] = double(h >> 8) * (1.0 / 16777216.0) - 0.5;
     }
   }
-  // two solves and one orthonormalisation, then one solve and two more (one
+  // a solve and one orthonormalisation, then a solve and two more (one
   // inlined copy of each step)
   for (int round = 0; round < 2; ++round) {
     if (j < D)
-      for (int it = round; it < 2; ++it) tri_solve(n, U, Y, ys, j, swm);
+      tri_solve(n, U, Y, ys, j, swm);
     __syncthreads();
     for (int pass = 1 - round; pass < 2; ++pass) wave_cholqr(n, D, Y, ys, R, rk);
   }
