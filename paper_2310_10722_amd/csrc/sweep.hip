@@ -1099,7 +1099,7 @@ __device__ __forceinline__ void zip_beig_small(const ZipArgs& Z, int s, int* zd,
   for (int e = tid; e < nv * Dn; e += 64) Fv[e] = Vj[(e / Dn) * 17 + ord[e % Dn]];
   if (Z.flop_ctr && tid == 0) {
     const double n = nv, D = Dn;
-    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 10.0 * D * n + 16.0 * D * D * n;
+    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 7.0 * D * n + 12.0 * D * D * n;
     atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
   }
   if (tid == 0) {
@@ -1153,9 +1153,10 @@ __device__ __forceinline__ void zip_beig_large(const ZipArgs& Z, int s, int* zd,
   wave_tri_backtransform(G, br, nv, Dn, zsm, ys, scr);
   if (Z.flop_ctr && tid == 0) {
     // algorithmic flops: Householder reduction 4n^3/3, back-transform 2Dn^2,
-    // inverse-iteration solves 10Dn, four Cholesky-QR passes 16D^2n
+    // factorisation and two inverse-iteration solves 7Dn, three Cholesky-QR
+    // passes 12D^2n
     const double n = nv, D = Dn;
-    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 10.0 * D * n + 16.0 * D * D * n;
+    const double f = 4.0 / 3.0 * n * n * n + 2.0 * D * n * n + 7.0 * D * n + 12.0 * D * D * n;
     atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
   }
   for (int e = tid; e < nv * Dn; e += 64) Fv[e] = zsm[(e / Dn) * ys + e % Dn];
