@@ -177,7 +177,7 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * by the reabsorption), out[5] = time of the boundary-MPS eigen-decomposition
  * launches (when the rank rule allows that path), out[6] = their number,
  * out[7] = their algorithmic flops (per problem of order n keeping D vectors:
- * 4n^3/3 + 2Dn^2 + 10Dn + 16D^2n).  Milliseconds for times; n <= 8 values are
+ * 4n^3/3 + 2Dn^2 + 7Dn + 12D^2n).  Milliseconds for times; n <= 8 values are
  * written.
  * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
