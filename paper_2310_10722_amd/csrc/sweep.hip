@@ -26,6 +26,7 @@ namespace tn3d {
 namespace {
 
 constexpr int NT = 256;
+constexpr int ET = 64;  // one-site ops, rescaling, final vectors: one wavefront per (site, sweep)
 constexpr int SNT = 64;       // one wavefront per bond truncation of order 9 to 16
 constexpr int SNT_BIG = 256;  // four wavefronts per bond truncation of order above 16
 constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
@@ -97,7 +98,7 @@ __global__ void k_init_bonds(SweepArgs A, const int32_t* bond_dim0) {
 // one-site ops: T'[r, p'] = sum_p M[p', p] T[r, p]
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_onesite(SweepArgs A, const DevOneSite* ops) {
+__global__ __launch_bounds__(ET) void k_onesite(SweepArgs A, const DevOneSite* ops) {
   const DevOneSite op = ops[blockIdx.x];
   const int sweep = blockIdx.y;
   __shared__ double M[256];
@@ -836,7 +837,7 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
 // per-site rescale after each layer
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_rescale(SweepArgs A, const int32_t* d_after, const int32_t* par_after) {
+__global__ __launch_bounds__(ET) void k_rescale(SweepArgs A, const int32_t* d_after, const int32_t* par_after) {
   __shared__ double red[8];
   const int site = blockIdx.x, sweep = blockIdx.y;
   int D[4];
@@ -844,12 +845,12 @@ __global__ __launch_bounds__(NT) void k_rescale(SweepArgs A, const int32_t* d_af
   const int64_t n = int64_t(d_after[site]) * D[0] * D[1] * D[2] * D[3];
   T* t = tens<T>(A, par_after[site], sweep, site);
   double m = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += NT) m = fmax(m, fabs(double(t[e])));
+  for (int64_t e = threadIdx.x; e < n; e += ET) m = fmax(m, fabs(double(t[e])));
   m = block_max_abs_reduce(m, red);
   const bool bad = !(m > 0.0) || !isfinite(m);
   const double c = bad ? 1.0 : m;
   const double inv = 1.0 / c;
-  for (int64_t e = threadIdx.x; e < n; e += NT) t[e] = T(double(t[e]) * inv);
+  for (int64_t e = threadIdx.x; e < n; e += ET) t[e] = T(double(t[e]) * inv);
   if (threadIdx.x == 0) {
     A.logs[int64_t(sweep) * A.n_sites + site] += log(c);
     if (bad) atomicOr(&A.flags[sweep], 1u);
@@ -860,7 +861,7 @@ __global__ __launch_bounds__(NT) void k_rescale(SweepArgs A, const int32_t* d_af
 // final stage: contract f_s into the physical leg (FP64 output)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_finalize(SweepArgs A, const int32_t* d_final, const int32_t* f_off,
+__global__ __launch_bounds__(ET) void k_finalize(SweepArgs A, const int32_t* d_final, const int32_t* f_off,
                                                  const int32_t* par_final, double* fin, int64_t fin_stride,
                                                  const int64_t* fin_off) {
   const int site = blockIdx.x, sweep = blockIdx.y;
@@ -871,7 +872,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SweepArgs A, const int32_t* d_f
   const double* f = A.pool + f_off[site];
   const T* t = tens<T>(A, par_final[site], sweep, site);
   double* o = fin + int64_t(sweep) * fin_stride + fin_off[site];
-  for (int64_t r = threadIdx.x; r < rows; r += NT) {
+  for (int64_t r = threadIdx.x; r < rows; r += ET) {
     double s = 0.0;
     for (int p = 0; p < d; ++p) s += f[p] * double(t[r * d + p]);
     o[r] = s;
@@ -1508,9 +1509,9 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
   if (n_ops <= 0) return;
   dim3 g(n_ops, A.n_sweeps);
   if (prec == 0)
-    hipLaunchKernelGGL(k_onesite<double>, g, dim3(NT), 0, st, A, ops);
+    hipLaunchKernelGGL(k_onesite<double>, g, dim3(ET), 0, st, A, ops);
   else
-    hipLaunchKernelGGL(k_onesite<float>, g, dim3(NT), 0, st, A, ops);
+    hipLaunchKernelGGL(k_onesite<float>, g, dim3(ET), 0, st, A, ops);
 }
 
 template <typename T>
@@ -1580,9 +1581,9 @@ void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const 
                     hipStream_t st) {
   dim3 g(A.n_sites, A.n_sweeps);
   if (prec == 0)
-    hipLaunchKernelGGL(k_rescale<double>, g, dim3(NT), 0, st, A, d_after, par_after);
+    hipLaunchKernelGGL(k_rescale<double>, g, dim3(ET), 0, st, A, d_after, par_after);
   else
-    hipLaunchKernelGGL(k_rescale<float>, g, dim3(NT), 0, st, A, d_after, par_after);
+    hipLaunchKernelGGL(k_rescale<float>, g, dim3(ET), 0, st, A, d_after, par_after);
 }
 
 void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const int32_t* f_off,
@@ -1590,10 +1591,10 @@ void launch_finalize(int prec, const SweepArgs& A, const int32_t* d_final, const
                      hipStream_t st) {
   dim3 g(A.n_sites, A.n_sweeps);
   if (prec == 0)
-    hipLaunchKernelGGL(k_finalize<double>, g, dim3(NT), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
+    hipLaunchKernelGGL(k_finalize<double>, g, dim3(ET), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
                        fin_off);
   else
-    hipLaunchKernelGGL(k_finalize<float>, g, dim3(NT), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
+    hipLaunchKernelGGL(k_finalize<float>, g, dim3(ET), 0, st, A, d_final, f_off, par_final, fin, fin_stride,
                        fin_off);
 }
 
