@@ -303,9 +303,12 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
 
 // C[m][n] = sum_k A(m, k) B(k, n) for a 512-thread workgroup, FP64 on the
 // matrix cores, through 64 x 64 output tiles and 32-deep K slices staged in
-// LDS (lds: 4096 doubles), each slice's global loads issued into registers
-// while the previous slice is multiplied.  a_at / b_at return operands (any
-// layout); c_put(m, n, v) stores.  v_mfma_f64_16x16x4f64 takes a 16 x 4
+// LDS (lds: GEMM_LDS doubles, k-major rows of 65 so that both fetch orders
+// store with few bank conflicts), each slice's global loads issued into
+// registers while the previous slice is multiplied.  a_at / b_at return
+// operands (any layout); c_put(m, n, v) stores.  KA (KB): A's (B's) elements
+// are contiguous along k, so the lanes of a fetch run along k rather than
+// along m (n), and a load instruction touches few cache lines.  v_mfma_f64_16x16x4f64 takes a 16 x 4
 // block of A (lane i + 16 k holds A[i][k]) and a 4 x 16 block of B (lane
 // j + 16 k holds B[k][j]) and accumulates the 16 x 16 block of C, item r of
 // lane j + 16 q holding row q + 4 r of column j.  The 64 x 64 output tile
@@ -314,13 +317,19 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
 // outside M x N skips the products, and a K slice runs only as many 4-deep
 // steps as it holds.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-template <class FA, class FB, class FC>
+constexpr int GEMM_LS = 65;                 // LDS row stride of a staged slice
+constexpr int GEMM_LDS = 2 * 32 * GEMM_LS;  // doubles of LDS block_gemm512 takes
+template <bool KA = false, bool KB = false, class FA, class FB, class FC>
 __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, double* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int rb = (wv & 3) * 16, cb = (wv >> 2) * 32;
-  double* As = lds;         // [32][64]  (k, m)
-  double* Bs = lds + 2048;  // [32][64]  (k, n)
+  double* As = lds;                 // [32][65]  (k, m)
+  double* Bs = lds + 32 * GEMM_LS;  // [32][65]  (k, n)
+  // element e of a thread's four: (k, m) = (e / 64, e % 64) along m, or
+  // (e % 32, e / 32) along k
+  auto kk_of = [](int e, bool alongk) { return alongk ? (e & 31) : (e >> 6); };
+  auto mm_of = [](int e, bool alongk) { return alongk ? (e >> 5) : (e & 63); };
   for (int m0 = 0; m0 < M; m0 += 64)
     for (int n0 = 0; n0 < N; n0 += 64) {
       const bool act = m0 + rb < M && n0 + cb < N;  // uniform per wavefront
@@ -331,10 +340,10 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int e = tid + 512 * i;
-          const int kk = e >> 6, mm = e & 63;
-          const int m = m0 + mm, n = n0 + mm, k = k0 + kk;
-          ra[i] = (m < M && k < K) ? a_at(m, k) : 0.0;
-          rb4[i] = (n < N && k < K) ? b_at(k, n) : 0.0;
+          const int ka = k0 + kk_of(e, KA), m = m0 + mm_of(e, KA);
+          const int kb = k0 + kk_of(e, KB), n = n0 + mm_of(e, KB);
+          ra[i] = (m < M && ka < K) ? a_at(m, ka) : 0.0;
+          rb4[i] = (n < N && kb < K) ? b_at(kb, n) : 0.0;
         }
       };
       __syncthreads();  // the previous tile's stores land before this tile's loads
@@ -343,24 +352,26 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          As[tid + 512 * i] = ra[i];
-          Bs[tid + 512 * i] = rb4[i];
+          const int e = tid + 512 * i;
+          As[kk_of(e, KA) * GEMM_LS + mm_of(e, KA)] = ra[i];
+          Bs[kk_of(e, KB) * GEMM_LS + mm_of(e, KB)] = rb4[i];
         }
         __syncthreads();
         if (k0 + 32 < K) fetch(k0 + 32);
         if (act) {
           const int nks = K - k0 >= 32 ? 8 : (K - k0 + 3) >> 2;
-          const double* ap = As + lq * 64 + rb + li;
-          const double* bp = Bs + lq * 64 + cb + li;
+          constexpr int KS = 4 * GEMM_LS;  // LDS distance of one 4-deep step
+          const double* ap = As + lq * GEMM_LS + rb + li;
+          const double* bp = Bs + lq * GEMM_LS + cb + li;
           if (act2) {
             for (int ks = 0; ks < nks; ++ks) {
-              const double a = ap[ks * 256], b0 = bp[ks * 256], b1 = bp[ks * 256 + 16];
+              const double a = ap[ks * KS], b0 = bp[ks * KS], b1 = bp[ks * KS + 16];
               c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, c0, 0, 0, 0);
               c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, c1, 0, 0, 0);
             }
           } else {
             for (int ks = 0; ks < nks; ++ks)
-              c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks * 256], bp[ks * 256], c0, 0, 0, 0);
+              c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks * KS], bp[ks * KS], c0, 0, 0, 0);
           }
         }
       }

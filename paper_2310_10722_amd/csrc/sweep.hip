@@ -935,7 +935,7 @@ __device__ __forceinline__ void zip_dims(const ZipArgs& Z, int s, int x, int y, 
 // rank 1 of its family; the bond below is 1), so the family is Th's one row,
 // its singular value the row's norm and its vector [1].
 __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inline_dec) {
-  __shared__ double gst[4096];
+  __shared__ double gst[GEMM_LDS];
   __shared__ double red[16];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int cur = y & 1;
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
   } else if (x + 1 < Z.Lx && Z.gram_path) {
     double* G = Z.Gm + int64_t(s) * Z.bigcap;
     if (rows)
-      block_gemm512(
+      block_gemm512<true, true>(
           R, R, C, [&](int m, int k) { return Th[m * C + k]; }, [&](int k, int n) { return Th[n * C + k]; },
           [&](int m, int n, double v) { G[m * R + n] = v; }, gst);
     else
@@ -1236,7 +1236,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
 
 // (at most 80 registers: six wavefronts per SIMD)
 __global__ __launch_bounds__(ZNT) __attribute__((amdgpu_waves_per_eu(6))) void k_zip_c(ZipArgs Z, int x, int y) {
-  __shared__ double gst[4096];
+  __shared__ double gst[GEMM_LDS];
   __shared__ double red[8];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int Lx = Z.Lx, cur = y & 1;
