@@ -303,8 +303,8 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
 
 // C[m][n] = sum_k A(m, k) B(k, n) for a 512-thread workgroup, FP64 on the
 // matrix cores, through 64 x 64 output tiles and 32-deep K slices staged in
-// LDS (lds: GEMM_LDS doubles, k-major rows of 65 so that both fetch orders
-// store with few bank conflicts), each slice's global loads issued into
+// LDS (lds: GEMM_LDS doubles, k-major rows of 64, or of 65 when a fetch runs
+// along k so that its stores spread over the banks), each slice's global loads issued into
 // registers while the previous slice is multiplied.  a_at / b_at return
 // operands (any layout); c_put(m, n, v) stores.  KA (KB): A's (B's) elements
 // are contiguous along k, so the lanes of a fetch run along k rather than
@@ -317,15 +317,15 @@ __device__ __forceinline__ int rank_rule(const double* Ss, int n, int chi, doubl
 // outside M x N skips the products, and a K slice runs only as many 4-deep
 // steps as it holds.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int GEMM_LS = 65;                 // LDS row stride of a staged slice
-constexpr int GEMM_LDS = 2 * 32 * GEMM_LS;  // doubles of LDS block_gemm512 takes
+constexpr int GEMM_LDS = 2 * 32 * 65;  // doubles of LDS block_gemm512 takes
 template <bool KA = false, bool KB = false, class FA, class FB, class FC>
 __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, double* lds) {
+  constexpr int GEMM_LS = (KA || KB) ? 65 : 64;  // LDS row stride of a staged slice
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int rb = (wv & 3) * 16, cb = (wv >> 2) * 32;
-  double* As = lds;                 // [32][65]  (k, m)
-  double* Bs = lds + 32 * GEMM_LS;  // [32][65]  (k, n)
+  double* As = lds;                 // [32][GEMM_LS]  (k, m)
+  double* Bs = lds + 32 * GEMM_LS;  // [32][GEMM_LS]  (k, n)
   // element e of a thread's four: (k, m) = (e / 64, e % 64) along m, or
   // (e % 32, e / 32) along k
   auto kk_of = [](int e, bool alongk) { return alongk ? (e & 31) : (e >> 6); };
