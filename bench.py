@@ -168,7 +168,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
         return
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the batch would shard by syndrome with no exchange during a sweep).", file=sys.stderr)
         sys.exit(2)
     import numpy as np

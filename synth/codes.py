@@ -251,10 +251,6 @@ def surface2d_bitflip(d: int, p) -> Dem:
     return Dem(f"surface2d_d{d}", H, _rates(p, n), obs, coord, {"d": d})
 
 
-def surface3d_depolarizing(L: int, p):
-    raise NotImplementedError("depolarizing 3D network is not part of this build yet")
-
-
 def five_qubit_stabilizers():
     """Generators and logicals of the [[5,1,3]] code as Pauli strings (paper, Sec. 3.1).
 
