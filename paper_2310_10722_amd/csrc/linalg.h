@@ -352,9 +352,9 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int e = tid + 512 * i;
-          As[kk_of(e, KA) * GEMM_LS + mm_of(e, KA)] = ra[i];
-          Bs[kk_of(e, KB) * GEMM_LS + mm_of(e, KB)] = rb4[i];
+          const int e = tid + 512 * i;  // with rows of 64 and m-ordered fetches the position is e itself
+          As[(KA || GEMM_LS != 64) ? kk_of(e, KA) * GEMM_LS + mm_of(e, KA) : e] = ra[i];
+          Bs[(KB || GEMM_LS != 64) ? kk_of(e, KB) * GEMM_LS + mm_of(e, KB) : e] = rb4[i];
         }
         __syncthreads();
         if (k0 + 32 < K) fetch(k0 + 32);
