@@ -1066,7 +1066,6 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
   zip_keep(Z, s, zd, nv, Sout, ord, J, 1, nv, nsw);
 }
 
-// Families of at most ZBIG vectors when the rank rule allows the Gram route:
 // The small-order branch of k_zip_beig (nv <= 16): the scaled Gram into a
 // 16 x 17 LDS block, all eigenpairs by wave_jacobi16, the values sorted
 // descending into Sout, the rank rule, the kept vectors into Fv.
@@ -1119,6 +1118,7 @@ static inline size_t beig_lds_bytes(int ys) {
   return (d > 544 ? d : 544) * sizeof(double);
 }
 
+// Families of at most ZBIG vectors when the rank rule allows the Gram route:
 // leading eigenpairs of the PSD Gram (eigenvalues S^2) in one wavefront.  The
 // Gram is scaled by its largest diagonal entry.  Orders up to 16 take every
 // eigenpair by Jacobi rotations.  Larger ones compute only the
