@@ -145,6 +145,36 @@ def test_rotated_d5_boundary_chi32_gram_route(ctx, prec):
     assert err.max() <= (1e-6 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("mode", ["fp64_default", "fp64_reduced", "fp32_reduced"])
+def test_point_L5_chi32_golden(ctx, mode):
+    """3D planar code, point sector, L=5, p=0.2, chi = 32, chi_m = 4: the
+    layer bonds reach 32, so the widest layer classes run (Grams of 64
+    columns, truncations of order 64, reabsorption rows of 64); chi_m = 4 keeps
+    the boundary-MPS families at 128 vectors or fewer (one-sided Jacobi on the
+    FP64 default rule, the 512-thread Gram decomposition above 64 on the
+    reduced one).  Against stored oracle values
+    (tests/golden/make_point_L5_chi32.py, which calls only the oracle).  Bounds
+    as for the other workloads: 1e-9 (FP64 default rule), 1e-6 (Gram route),
+    1e-3 (FP32)."""
+    import json
+    import os
+    from paper_2310_10722_amd import tn3d
+    say(f"case: point sector L=5 p=0.2 chi=32 chi_m=4 {mode}, 4 stored syndromes")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "point_L5_chi32.json")))
+    rule = "fp64_default" if mode == "fp64_default" else "reduced"
+    m = np.array(gold["syndromes"], dtype=np.uint8)
+    ref = np.array(gold["logp"][rule])
+    dem = synth.surface3d_point(gold["L"], gold["p"])
+    net = tn3d.tn3d_net_surface3d_point(ctx, gold["L"], dem.p)
+    prm = tn3d.tn3d_params_default(gold["chi"], gold["chi_mps"],
+                                   tn3d.PREC_FP32 if mode == "fp32_reduced" else tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = gold["rules"][rule]
+    got, _ = gpu_logp(ctx, net, m, prm)
+    err = np.abs(got[:, :2] - ref)
+    say("  max |d log p| =", err.max())
+    assert err.max() <= {"fp64_default": 1e-9, "fp64_reduced": 1e-6, "fp32_reduced": 1e-3}[mode]
+
+
 def test_decode_and_ragged_batch(ctx):
     from paper_2310_10722_amd import tn3d
     say("case: ragged batch L=2 / L=3 decode fp64")
