@@ -1227,9 +1227,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 __device__ int block_sym_eig(double* A, int n, double* Z, double* d, double* e, double* beta, double* dw,
                              double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  // A stays symmetric (the whole trailing block is updated), so row k stands
+  // for column k and thread i updates column i: every access below runs
+  // along a row across the threads
   for (int k = 0; k + 2 < n; ++k) {
     double q = 0.0;
-    for (int i = k + 1 + tid; i < n; i += nt) q += A[i * n + k] * A[i * n + k];
+    for (int i = k + 1 + tid; i < n; i += nt) q += A[k * n + i] * A[k * n + i];
     const double sigma = block_sum(q, red);
     const double x0 = A[(k + 1) * n + k];
     __syncthreads();
@@ -1244,7 +1247,8 @@ __device__ int block_sym_eig(double* A, int n, double* Z, double* d, double* e, 
     const double alpha = x0 >= 0.0 ? -sqrt(sigma) : sqrt(sigma);
     const double bk = 1.0 / (sigma - x0 * alpha);
     if (tid == 0) {
-      A[(k + 1) * n + k] = x0 - alpha;
+      A[(k + 1) * n + k] = x0 - alpha;  // the reflector, in column k (read back below)
+      A[k * n + k + 1] = x0 - alpha;    // and in row k (read here)
       e[k] = alpha;
       beta[k] = bk;
     }
@@ -1252,17 +1256,17 @@ __device__ int block_sym_eig(double* A, int n, double* Z, double* d, double* e, 
     double pv = 0.0;
     for (int i = k + 1 + tid; i < n; i += nt) {
       double acc = 0.0;
-      for (int j = k + 1; j < n; ++j) acc += A[i * n + j] * A[j * n + k];
+      for (int j = k + 1; j < n; ++j) acc += A[j * n + i] * A[k * n + j];
       acc *= bk;
       Z[k * n + i] = acc;
-      pv += acc * A[i * n + k];
+      pv += acc * A[k * n + i];
     }
     const double K = 0.5 * bk * block_sum(pv, red);
-    for (int i = k + 1 + tid; i < n; i += nt) Z[k * n + i] -= K * A[i * n + k];
+    for (int i = k + 1 + tid; i < n; i += nt) Z[k * n + i] -= K * A[k * n + i];
     __syncthreads();
     for (int i = k + 1 + tid; i < n; i += nt) {
-      const double vi = A[i * n + k], wi = Z[k * n + i];
-      for (int j = k + 1; j < n; ++j) A[i * n + j] -= vi * Z[k * n + j] + wi * A[j * n + k];
+      const double vi = A[k * n + i], wi = Z[k * n + i];
+      for (int j = k + 1; j < n; ++j) A[j * n + i] -= A[k * n + j] * wi + Z[k * n + j] * vi;
     }
     __syncthreads();
   }
