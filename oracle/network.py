@@ -319,3 +319,175 @@ def rotated_network(d, T, checks, p, m, coset):
     assert all(len(h) == 0 for h in held)
     final = [np.ones(1) for _ in range(Lx * Ly)]
     return LayeredNet(Lx, Ly, init, layers, final)
+
+
+# ---------------------------------------------------------------------------
+# 3D planar code, depolarizing noise: mixed picture, sweep along z
+# ---------------------------------------------------------------------------
+
+def _faces3d(L):
+    """Face checks as edge lists (the canonical face order of the depolarizing
+    syndrome: xy-faces by level, then xz-faces, then yz-faces, each x fastest)."""
+    nz, nx = L ** 3, L * (L - 1) ** 2
+
+    def zedge(x, y, z):
+        return z * L * L + y * L + x
+
+    def xedge(x, y, z):
+        return nz + ((z - 1) * L + y) * (L - 1) + x
+
+    def yedge(x, y, z):
+        return nz + nx + ((z - 1) * (L - 1) + y) * L + x
+
+    out = []
+    for z in range(1, L):
+        for y in range(L - 1):
+            for x in range(L - 1):
+                out.append([xedge(x, y, z), xedge(x, y + 1, z), yedge(x, y, z), yedge(x + 1, y, z)])
+    for z in range(L):
+        for y in range(L):
+            for x in range(L - 1):
+                out.append([zedge(x, y, z), zedge(x + 1, y, z)]
+                           + ([xedge(x, y, z)] if z >= 1 else [])
+                           + ([xedge(x, y, z + 1)] if z + 1 < L else []))
+    for z in range(L):
+        for y in range(L - 1):
+            for x in range(L):
+                out.append([zedge(x, y, z), zedge(x, y + 1, z)]
+                           + ([yedge(x, y, z)] if z >= 1 else [])
+                           + ([yedge(x, y, z + 1)] if z + 1 < L else []))
+    return out
+
+
+def gf2_solve(A, b):
+    """One solution x of A x = b over F2 (Gauss-Jordan elimination), or None
+    when the system is inconsistent.  Free variables are set to zero."""
+    A = (np.asarray(A, dtype=np.uint8) & 1).copy()
+    b = (np.asarray(b, dtype=np.uint8) & 1).copy()
+    rows, cols = A.shape
+    pivots = []
+    r = 0
+    for c in range(cols):
+        hits = np.nonzero(A[r:, c])[0]
+        if hits.size == 0:
+            continue
+        k = r + hits[0]
+        A[[r, k]] = A[[k, r]]
+        b[[r, k]] = b[[k, r]]
+        for i in np.nonzero(A[:, c])[0]:
+            if i != r:
+                A[i] ^= A[r]
+                b[i] ^= b[r]
+        pivots.append(c)
+        r += 1
+        if r == rows:
+            break
+    if np.any(b[r:]):
+        return None
+    x = np.zeros(cols, dtype=np.uint8)
+    for i, c in enumerate(pivots):
+        x[c] = b[i]
+    return x
+
+
+def depol3d_network(L, p, m, coset, rep=None):
+    """Depolarizing network of the 3D planar code (both sectors), coset
+    c = a + 2 b, swept along z over the L x L vertex grid.
+
+    Mixed picture.  Z parts of the errors (seen by the vertex X-checks) are
+    summed in the detector picture as in point3d_network.  X parts u (seen by
+    the face Z-checks) are summed in the generator picture (Sec. 3.3): every u
+    with face syndrome m_Z and class a is r + sum_v g_v s_v for one fixed
+    representative r of that class and a unique set of vertex stabilizers s_v
+    (X on the edges at vertex v; they are independent here), so one bit g_v
+    per vertex replaces the sum over u.  An edge e between vertices v, w then
+    carries X part r_e + g_v + g_w, and its Pauli weight is
+    W(u, v) = P(X part u, Z part v): 1-p for I, p/3 for X, Y, Z.
+
+    Physical leg of site (x, y): (g, s) with index 2 g + s, where g is the
+    generator bit of the vertex last absorbed (0 below level 1) and s the
+    Z-part flip of the z-edge entering the next vertex.  Layer z:
+      pre   the z-edge below vertex (x, y, z): (g, s) -> (g', s) with weight
+            W(r_e + g + g', s), g' the new vertex's bit;
+      gates per in-plane edge, summed over its Z part t:
+            s_A ^= t, s_B ^= t, weight W(r_e + g_A + g_B, t);
+      post  X^{m} on s (the vertex check fixes the up edge's Z part).
+    Final: the top dangling edge, f[(g, s)] = W(r_e + g, s).  Initial state:
+    g = 0, the bottom dangling edges' Z parts chained to parity b.  The class
+    of u is its parity on the vertical string above (0, 0); r is a solution of
+    H_Z r = m_Z, plus the bottom membrane of edges when its class differs from
+    a.
+
+    p: depolarizing rate, scalar or per qubit (edge numbering of
+    surface3d_point).  m: vertex syndrome then face syndrome.  rep: a
+    solution of H_Z r = m_Z to start from instead of the elimination's.
+    """
+    nq = L ** 3 + 2 * L * (L - 1) ** 2
+    pq = np.broadcast_to(np.asarray(p, dtype=np.float64), (nq,))
+    nv = L * L * (L - 1)
+    m = np.asarray(m, dtype=np.uint8)
+    faces = _faces3d(L)
+    HZ = np.zeros((len(faces), nq), dtype=np.uint8)
+    for f, es in enumerate(faces):
+        HZ[f, es] = 1
+    r = gf2_solve(HZ, m[nv:]) if rep is None else np.array(rep, dtype=np.uint8)
+    if r is None or np.any(((HZ.astype(np.int64) @ r) & 1) != m[nv:]):
+        raise ValueError("face syndrome violates a cube relation")
+    a, b = coset & 1, coset >> 1
+    string = [z * L * L for z in range(L)]
+    if int(r[string].sum()) % 2 != a:
+        r[: L * L] ^= 1
+
+    def W(e, u, v):
+        return 1.0 - pq[e] if (u == 0 and v == 0) else pq[e] / 3.0
+
+    base = snake_state(L, L, [np.ones(2)] * (L * L), b)
+    init = []
+    for T in base:
+        T4 = np.zeros((4,) + T.shape[1:])
+        T4[0:2] = T            # g = 0
+        init.append(T4)
+
+    nz, nx = L ** 3, L * (L - 1) ** 2
+    X2 = np.array([[0.0, 1.0], [1.0, 0.0]])
+    layers = []
+    for z in range(1, L):
+        lay = Layer()
+        for y in range(L):
+            for x in range(L):
+                e = (z - 1) * L * L + y * L + x
+                O = np.zeros((4, 4))
+                for g in range(2):
+                    for g2 in range(2):
+                        for s in range(2):
+                            O[2 * g2 + s, 2 * g + s] = W(e, r[e] ^ g ^ g2, s)
+                lay.pre[y * L + x] = O
+
+        def gate(e):
+            G = np.zeros((4, 4, 4, 4))
+            for ga in range(2):
+                for gb in range(2):
+                    for sa in range(2):
+                        for sb in range(2):
+                            for t in range(2):
+                                G[2 * ga + (sa ^ t), 2 * gb + (sb ^ t), 2 * ga + sa, 2 * gb + sb] += \
+                                    W(e, r[e] ^ ga ^ gb, t)
+            return G
+
+        for y in range(L):
+            for x in range(L - 1):
+                lay.gates.append(("H", x, y, gate(nz + ((z - 1) * L + y) * (L - 1) + x)))
+        for y in range(L - 1):
+            for x in range(L):
+                lay.gates.append(("V", x, y, gate(nz + nx + ((z - 1) * (L - 1) + y) * L + x)))
+        for y in range(L):
+            for x in range(L):
+                mm = int(m[((z - 1) * L + y) * L + x])
+                lay.post[y * L + x] = np.kron(np.eye(2), X2 if mm else np.eye(2))
+        layers.append(lay)
+    final = []
+    for y in range(L):
+        for x in range(L):
+            e = (L - 1) * L * L + y * L + x
+            final.append(np.array([W(e, r[e] ^ g, s) for g in range(2) for s in range(2)]))
+    return LayeredNet(L, L, init, layers, final)

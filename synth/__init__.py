@@ -11,9 +11,11 @@ oracle and the GPU path may consume what it produces without sharing code.
 from .codes import (  # noqa: F401
     Dem,
     surface3d_point,
+    surface3d_faces,
+    surface3d_depolarizing,
     rotated_phenom,
     repetition_line,
     surface2d_bitflip,
     five_qubit_stabilizers,
 )
-from .sample import sample_syndromes, config_workload, CONFIG_SEED_BASE  # noqa: F401
+from .sample import sample_syndromes, sample_pauli, config_workload, CONFIG_SEED_BASE  # noqa: F401

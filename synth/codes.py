@@ -109,6 +109,110 @@ def surface3d_point(L: int, p) -> Dem:
 
 
 # --------------------------------------------------------------------------
+# 3D planar surface code, depolarizing noise (both sectors)
+# --------------------------------------------------------------------------
+
+def surface3d_faces(L: int):
+    """Face (Z-type) checks of the 3D planar code of size L as edge lists, in
+    canonical order (edge numbering as in surface3d_point):
+      xy-face (x..x+1, y..y+1) at level z in [1, L)  -> ((z-1)(L-1) + y)(L-1) + x
+      xz-face (x..x+1, y, z..z+1), z in [0, L)       -> (L-1)^3 + (z L + y)(L-1) + x
+      yz-face (x, y..y+1, z..z+1), z in [0, L)       -> (L-1)^3 + L^2 (L-1) + (z (L-1) + y) L + x
+    Faces between a rough boundary and level 1 (or level L-1 and the top) have
+    three edges.  (L-1)^3 + 2 L^2 (L-1) faces; the six faces of a cube are
+    dependent, so consistent syndromes satisfy one parity per cube.
+    """
+    nz = L ** 3
+    nx = L * (L - 1) ** 2
+
+    def ze(x, y, z):
+        return z * L * L + y * L + x
+
+    def xe(x, y, z):
+        return nz + ((z - 1) * L + y) * (L - 1) + x
+
+    def ye(x, y, z):
+        return nz + nx + ((z - 1) * (L - 1) + y) * L + x
+
+    faces = []
+    for z in range(1, L):
+        for y in range(L - 1):
+            for x in range(L - 1):
+                faces.append((xe(x, y, z), xe(x, y + 1, z), ye(x, y, z), ye(x + 1, y, z)))
+    for z in range(L):
+        for y in range(L):
+            for x in range(L - 1):
+                f = [ze(x, y, z), ze(x + 1, y, z)]
+                if z >= 1:
+                    f.append(xe(x, y, z))
+                if z + 1 <= L - 1:
+                    f.append(xe(x, y, z + 1))
+                faces.append(tuple(f))
+    for z in range(L):
+        for y in range(L - 1):
+            for x in range(L):
+                f = [ze(x, y, z), ze(x, y + 1, z)]
+                if z >= 1:
+                    f.append(ye(x, y, z))
+                if z + 1 <= L - 1:
+                    f.append(ye(x, y, z + 1))
+                faces.append(tuple(f))
+    return faces
+
+
+def surface3d_depolarizing(L: int, p) -> Dem:
+    """3D planar surface code of size L under depolarizing noise: each qubit
+    independently suffers X, Y or Z with probability p/3 each (I with 1-p).
+
+    Both check types are decoded together.  A Pauli with X part u and Z part v
+    (bit vectors over the n qubits) has syndrome (H_X v, H_Z u): the vertex
+    X-checks of surface3d_point see the Z part, the face Z-checks of
+    surface3d_faces see the X part.  Its logical class is c = a + 2 b with
+    a = the parity of u on the vertical string of z-edges above (0, 0) (a Z
+    logical) and b = the parity of v on the L^2 bottom dangling z-edges (the X
+    logical membrane).
+
+    As a DEM (paper, Sec. 2.4): three independent mechanisms per qubit, X, Y
+    and Z, each of rate r with r (1 - r) = p/3, i.e. r = (1 - sqrt(1 - 4p/3)) / 2;
+    the product of the three draws is the depolarizing channel.
+      detector: vertex (x, y, z) as in surface3d_point, then face f -> L^2 (L-1) + f
+      mechanism: X on qubit e -> e, Y -> n + e, Z -> 2 n + e
+      observables: row 0 is a, row 1 is b, so the observable integer is c.
+    params["p_qubit"] holds the per-qubit depolarizing rates.
+    """
+    if L < 2:
+        raise ValueError("L >= 2")
+    pt = surface3d_point(L, 0.0)
+    HX = pt.H
+    n = HX.shape[1]
+    faces = surface3d_faces(L)
+    HZ = np.zeros((len(faces), n), dtype=np.uint8)
+    for f, es in enumerate(faces):
+        HZ[f, list(es)] = 1
+    nv = HX.shape[0]
+    H = np.zeros((nv + len(faces), 3 * n), dtype=np.uint8)
+    H[nv:, 0:n] = HZ          # X
+    H[:nv, n:2 * n] = HX      # Y: both
+    H[nv:, n:2 * n] = HZ
+    H[:nv, 2 * n:] = HX       # Z
+    zbar = np.zeros(n, dtype=np.uint8)
+    zbar[[z * L * L for z in range(L)]] = 1
+    xbar = np.zeros(n, dtype=np.uint8)
+    xbar[: L * L] = 1
+    obs = np.zeros((2, 3 * n), dtype=np.uint8)
+    obs[0, 0:n] = zbar
+    obs[0, n:2 * n] = zbar
+    obs[1, n:2 * n] = xbar
+    obs[1, 2 * n:] = xbar
+    pq = _rates(p, n)
+    r = 0.5 * (1.0 - np.sqrt(1.0 - 4.0 * pq / 3.0))
+    coord = np.concatenate([pt.det_coord, np.full((len(faces), 3), -1, dtype=np.int64)])
+    return Dem(f"surface3d_depolarizing_L{L}", H, np.concatenate([r, r, r]), obs, coord,
+               {"L": L, "n_qubits": n, "p_qubit": pq, "HX": HX, "HZ": HZ,
+                "zbar": zbar, "xbar": xbar})
+
+
+# --------------------------------------------------------------------------
 # Rotated surface code, one sector, phenomenological noise
 # --------------------------------------------------------------------------
 

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .codes import Dem, rotated_phenom, surface3d_point
+from .codes import Dem, rotated_phenom, surface3d_depolarizing, surface3d_point
 
 CONFIG_SEED_BASE = 2310107220
 
@@ -21,6 +21,25 @@ def sample_syndromes(dem: Dem, n: int, seed: int):
     m = ((x.astype(np.int64) @ H.T) & 1).astype(np.uint8)
     obs = ((x.astype(np.int64) @ dem.obs.T.astype(np.int64)) & 1).astype(np.uint8)
     return m, obs
+
+
+def sample_pauli(dem: Dem, n: int, seed: int):
+    """Depolarizing sampling for a code built by surface3d_depolarizing: per
+    qubit, u < 1-p gives I, otherwise X, Y, Z by equal thirds of [1-p, 1).
+    Returns (syndromes uint8 [n, n_det], coset int64 [n]) with coset = a + 2b."""
+    pr = dem.params
+    pq = pr["p_qubit"]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    uni = rng.random((n, pq.size))
+    hit = uni >= 1.0 - pq[None, :]
+    kind = np.minimum(((uni - (1.0 - pq[None, :])) / (pq[None, :] / 3.0)).astype(np.int64), 2)
+    xp = (hit & (kind <= 1)).astype(np.int64)   # X or Y
+    zp = (hit & (kind >= 1)).astype(np.int64)   # Y or Z
+    m = np.concatenate([(zp @ pr["HX"].T.astype(np.int64)) & 1,
+                        (xp @ pr["HZ"].T.astype(np.int64)) & 1], axis=1).astype(np.uint8)
+    a = (xp @ pr["zbar"].astype(np.int64)) & 1
+    b = (zp @ pr["xbar"].astype(np.int64)) & 1
+    return m, a + 2 * b
 
 
 def rotated_rates(d: int, T: int, seed: int, lo: float = 0.005, hi: float = 0.05):
@@ -39,6 +58,9 @@ def config_workload(cfg: int, n: int | None = None):
     1: 3D planar code L=3, point sector, i.i.d. p=0.15, 64 syndromes.
     2: rotated d=5, p=q=0.03, 5 noisy + 1 perfect round, 1024 syndromes.
     3: 3D planar code L=8, point sector, p=0.2, 256 syndromes.
+    4: 3D planar code, depolarizing p=0.15, L=4 (pass n; the ragged
+       L in {4, 5, 6} mix is one call per L), coset labels instead of
+       observables.
     5: rotated d=7, 7 noisy + 1 perfect round, per-qubit / per-measurement
        rates log-uniform in [0.005, 0.05] (drawn first, seed + 100), 256 syndromes.
     Returns (dem, syndromes, observables, seed).
@@ -53,6 +75,11 @@ def config_workload(cfg: int, n: int | None = None):
     elif cfg == 3:
         dem = surface3d_point(8, 0.2)
         n = 256 if n is None else n
+    elif cfg == 4:
+        dem = surface3d_depolarizing(4, 0.15)
+        n = 512 if n is None else n
+        m, cos = sample_pauli(dem, n, seed)
+        return dem, m, cos, seed
     elif cfg == 5:
         pq, qm = rotated_rates(7, 7, seed + 100)
         dem = rotated_phenom(7, 7, pq, qm)
