@@ -122,6 +122,29 @@ tn3d_status tn3d_net_surface3d_point(tn3d_ctx ctx, int32_t L, const double* p_me
 tn3d_status tn3d_net_rotated_phenom(tn3d_ctx ctx, int32_t d, int32_t T, const double* p_mech,
                                     tn3d_net* out);
 
+/* The 3D planar surface code of size L (qubit numbering and vertex checks as
+ * in tn3d_net_surface3d_point) under depolarizing noise, both error types
+ * decoded at once (paper Sec. 2.1-2.3 for the coset probabilities, Sec. 3.3
+ * for the generator picture, Sec. 5.1 for the code).  Qubit e suffers X, Y
+ * or Z with probability p_qubit[e]/3 each.  Syndrome: the L^2 (L-1) vertex
+ * checks (detector ((z-1) L + y) L + x, they see the Z parts), then the
+ * face checks (they see the X parts), offset by L^2 (L-1):
+ *   xy-face (x..x+1, y..y+1) at level z in [1, L)  -> ((z-1)(L-1) + y)(L-1) + x
+ *   xz-face (x..x+1, y, z..z+1), z in [0, L)       -> (L-1)^3 + (z L + y)(L-1) + x
+ *   yz-face (x, y..y+1, z..z+1), z in [0, L)       -> (L-1)^3 + L^2 (L-1) + (z (L-1) + y) L + x
+ * (faces at the rough top and bottom have three edges).  Four cosets,
+ * c = a + 2 b: a is the parity of the X part on the z-edges above (0, 0),
+ * b that of the Z part on the bottom dangling z-edges.  The network uses the
+ * detector picture for the Z parts and the generator picture over the
+ * vertex stabilizers for the X parts (physical dim 4 on every site, gates
+ * of operator-Schmidt rank 3 whose terms depend on a representative of the
+ * face syndrome, derived on the device per item by a fixed GF(2) map), so
+ * contractions need 4 chi <= 64.  A face syndrome that violates a cube
+ * relation is not detected: its result has no meaning.
+ * Errors: TN3D_E_INVALID (L < 2, a rate outside [0, 3/4], null pointer),
+ * TN3D_E_UNSUPPORTED (more than 4096 faces). */
+tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx ctx, int32_t L, const double* p_qubit, tn3d_net* out);
+
 int32_t tn3d_net_num_detectors(tn3d_net net);
 int32_t tn3d_net_num_mechanisms(tn3d_net net);
 int32_t tn3d_net_num_cosets(tn3d_net net);

@@ -104,7 +104,10 @@ class Assembler {
   // Parity chain over the sites in boustrophedon order: value
   // prod_s w_s(b_s) if the parity of all bits is `coset`; w[s] empty for a
   // site without a bit (physical dim 1).
-  void snake_init(const std::vector<std::vector<double>>& w, int coset) {
+  // With dfull > 0 every site has physical dim dfull and its bit sits at
+  // index base + bit.  The state is stored as coset `slot` (default: coset).
+  void snake_init(const std::vector<std::vector<double>>& w, int coset, int dfull = 0, int base = 0, int slot = -1) {
+    const int sl = slot >= 0 ? slot : coset;
     int ns = Lx * Ly;
     std::vector<std::pair<int, int>> order;
     for (int y = 0; y < Ly; ++y)
@@ -115,18 +118,19 @@ class Assembler {
       if (b.second == a.second + 1) return int(LEG_S);
       return int(LEG_N);
     };
-    if (int(P.init_dims.size()) < (coset + 1) * ns * 5) {
-      P.init_dims.resize(size_t(coset + 1) * ns * 5, 1);
-      P.init_off.resize(size_t(coset + 1) * ns, 0);
+    if (int(P.init_dims.size()) < (sl + 1) * ns * 5) {
+      P.init_dims.resize(size_t(sl + 1) * ns * 5, 1);
+      P.init_off.resize(size_t(sl + 1) * ns, 0);
     }
     P.bond_dim0.assign(P.n_bonds, 1);
     for (int k = 0; k < ns; ++k) {
       auto [x, y] = order[k];
       int s = y * Lx + x;
       int dp = w[s].empty() ? 1 : 2;
+      int dphys = dfull > 0 ? dfull : dp;
       int lin = k > 0 ? leg_to(order[k], order[k - 1]) : -1;
       int lout = k + 1 < ns ? leg_to(order[k], order[k + 1]) : -1;
-      int dims[5] = {dp, 1, 1, 1, 1};
+      int dims[5] = {dphys, 1, 1, 1, 1};
       if (lin >= 0) dims[1 + lin] = 2;
       if (lout >= 0) dims[1 + lout] = 2;
       if (lout >= 0) P.bond_dim0[P.leg_bond[s * 4 + lout]] = 2;
@@ -140,13 +144,14 @@ class Assembler {
           int idx[4] = {0, 0, 0, 0};
           if (lin >= 0) idx[lin] = cin;
           if (lout >= 0) idx[lout] = cout;
-          size_t off = ((((size_t(idx[0]) * dims[2] + idx[1]) * dims[3] + idx[2]) * dims[4] + idx[3]) * dp) + b;
+          size_t off = ((((size_t(idx[0]) * dims[2] + idx[1]) * dims[3] + idx[2]) * dims[4] + idx[3]) * dphys) +
+                       (dfull > 0 ? base : 0) + b;
           t[off] = w[s].empty() ? 1.0 : w[s][b];
         }
-      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(coset) * ns + s) * 5 + i] = dims[i];
-      P.init_off[size_t(coset) * ns + s] = put(t);
-      d[s] = dp;
-      P.dmax[s] = std::max(P.dmax[s], dp);
+      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(sl) * ns + s) * 5 + i] = dims[i];
+      P.init_off[size_t(sl) * ns + s] = put(t);
+      d[s] = dphys;
+      P.dmax[s] = std::max(P.dmax[s], dphys);
     }
   }
 
@@ -159,6 +164,8 @@ class Assembler {
   struct PGate {
     int kind, x, y, dA, dB;
     std::vector<Term> terms;
+    int det;
+    std::vector<Term> terms1;  // when the per-item bit det is set
   };
 
   void begin_layer() {
@@ -176,9 +183,9 @@ class Assembler {
   std::string add_post(int s, const Mat& M0, int dout, int det = -1, const Mat& M1 = {}) {
     return compose(post[s], s, M0, M1, dout, det, false);
   }
-  void add_gate(int kind, int x, int y, std::vector<Term> terms) {
+  void add_gate(int kind, int x, int y, std::vector<Term> terms, int det = -1, std::vector<Term> terms1 = {}) {
     int sa = y * Lx + x, sb = kind == 0 ? sa + 1 : sa + Lx;
-    gates.push_back({kind, x, y, staged_pre(sa), staged_pre(sb), std::move(terms)});
+    gates.push_back({kind, x, y, staged_pre(sa), staged_pre(sb), std::move(terms), det, std::move(terms1)});
   }
 
   std::string end_layer() {
@@ -211,11 +218,7 @@ class Assembler {
         G.dB = g.dB;
         G.K = int(g.terms.size());
         G.bond = g.kind == 0 ? hbond(g.x, g.y) : vbond(g.x, g.y);
-        Mat oa, ob, pa, pb;
-        for (auto& t : g.terms) {
-          oa.insert(oa.end(), t.A.begin(), t.A.end());
-          ob.insert(ob.end(), t.B.begin(), t.B.end());
-        }
+        if (g.det >= 0 && g.terms1.size() != g.terms.size()) return "the two term sets of a gate differ in count";
         // P_kk'[p][q] = sum_p' O_k[p'][p] O_k'[p'][q]
         auto gram = [](const std::vector<Term>& ts, bool sideA, int dd) {
           Mat out;
@@ -232,12 +235,27 @@ class Assembler {
             }
           return out;
         };
-        pa = gram(g.terms, true, g.dA);
-        pb = gram(g.terms, false, g.dB);
-        G.oA = put(oa);
-        G.oB = put(ob);
-        G.pA = put(pa);
-        G.pB = put(pb);
+        auto put_terms = [&](const std::vector<Term>& ts, int32_t& oA, int32_t& oB, int32_t& pA, int32_t& pB) {
+          Mat oa, ob;
+          for (auto& t : ts) {
+            oa.insert(oa.end(), t.A.begin(), t.A.end());
+            ob.insert(ob.end(), t.B.begin(), t.B.end());
+          }
+          oA = put(oa);
+          oB = put(ob);
+          pA = put(gram(ts, true, g.dA));
+          pB = put(gram(ts, false, g.dB));
+        };
+        put_terms(g.terms, G.oA, G.oB, G.pA, G.pB);
+        G.det = g.det;
+        if (g.det >= 0)
+          put_terms(g.terms1, G.oA1, G.oB1, G.pA1, G.pB1);
+        else {
+          G.oA1 = G.oA;
+          G.oB1 = G.oB;
+          G.pA1 = G.pA;
+          G.pB1 = G.pB;
+        }
         G.srcA = par[sa];
         G.srcB = par[sb];
         par[sa] ^= 1;
@@ -550,6 +568,199 @@ std::string build_rotated_phenom(int32_t d, int32_t T, const double* p, Program&
   for (auto& h : held)
     if (!h.empty()) return "internal: open checks left after the sweep";
   A.finish(std::vector<Mat>(ns, Mat{1.0}));
+  return "";
+}
+
+// ---------------------------------------------------------------------------
+// 3D planar code under depolarizing noise, both sectors at once (coset
+// c = a + 2b: a the class of the X part, read on the vertical string of
+// z-edges above (0, 0); b that of the Z part, read on the bottom membrane).
+// Sweep along z over the L x L vertex grid; the physical index of a site is
+// s + 2 g with
+//   s  the Z part of the z-edge entering the next vertex (detector picture,
+//      as in the point sector), and
+//   g  the generator bit of the vertex last absorbed: the X parts of a coset
+//      are u = r + sum_v g_v S_v over the vertex stabilizers S_v, for one
+//      representative r of the coset's face syndrome and class.
+// An edge e between vertices v, w carries the Pauli with X part
+// r_e + g_v + g_w and Z part t, weight W = 1-p_e (I) or p_e/3 (X, Y, Z).
+// Its gate, summed over t, is
+//   sum_t X_s^t (x) X_s^t [alpha_t + beta_t (-1)^{r_e} Z_g (x) Z_g]
+// with alpha_t, beta_t the even and odd parts of W(., t) in the X part:
+// operator-Schmidt rank 3 (beta_1 = 0), and r_e flips the sign of the Z_g
+// term.  r = B m_Z for a fixed GF(2) map B with zero on the string above
+// (0, 0) and on the top dangling edges, so the class a enters only through
+// the bottom edges' weights: the initial generator bit below level 1 is a
+// (r + a times the bottom membrane).  The r bits are derived per item from
+// the face syndrome on the device (Program::ext_rows).
+// ---------------------------------------------------------------------------
+namespace {
+
+using Bits = std::vector<uint64_t>;
+
+inline void bx(Bits& a, const Bits& b) {
+  for (size_t i = 0; i < a.size(); ++i) a[i] ^= b[i];
+}
+inline int bget(const Bits& a, int i) { return int((a[i >> 6] >> (i & 63)) & 1u); }
+inline void bflip(Bits& a, int i) { a[i >> 6] ^= uint64_t(1) << (i & 63); }
+
+}  // namespace
+
+std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
+  if (L < 2) return "L must be >= 2";
+  if (!p) return "null rates";
+  const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
+  const int n = nz + 2 * nx;
+  for (int i = 0; i < n; ++i)
+    if (!(p[i] >= 0.0 && p[i] <= 0.75)) return "depolarizing rate outside [0, 3/4]";
+  auto ze = [&](int x, int y, int z) { return z * L * L + y * L + x; };
+  auto xe = [&](int x, int y, int z) { return nz + ((z - 1) * L + y) * (L - 1) + x; };
+  auto ye = [&](int x, int y, int z) { return nz + nx + ((z - 1) * (L - 1) + y) * L + x; };
+  // face checks in the canonical order
+  std::vector<std::vector<int>> faces;
+  for (int z = 1; z < L; ++z)
+    for (int y = 0; y + 1 < L; ++y)
+      for (int x = 0; x + 1 < L; ++x) faces.push_back({xe(x, y, z), xe(x, y + 1, z), ye(x, y, z), ye(x + 1, y, z)});
+  for (int z = 0; z < L; ++z)
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x + 1 < L; ++x) {
+        std::vector<int> f = {ze(x, y, z), ze(x + 1, y, z)};
+        if (z >= 1) f.push_back(xe(x, y, z));
+        if (z + 1 < L) f.push_back(xe(x, y, z + 1));
+        faces.push_back(f);
+      }
+  for (int z = 0; z < L; ++z)
+    for (int y = 0; y + 1 < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        std::vector<int> f = {ze(x, y, z), ze(x, y + 1, z)};
+        if (z >= 1) f.push_back(ye(x, y, z));
+        if (z + 1 < L) f.push_back(ye(x, y, z + 1));
+        faces.push_back(f);
+      }
+  const int nf = int(faces.size()), nv = L * L * (L - 1);
+  const int wq = (n + 63) / 64, wf = (nf + 63) / 64;
+
+  // Gauss-Jordan on H_Z (rows = faces, bit columns = qubits), tracking the
+  // row operations E, so that E H_Z is reduced: for a consistent m_Z,
+  // r[pivot col of row i] = (E m_Z)_i and zero elsewhere.
+  std::vector<Bits> H(nf, Bits(wq, 0)), E(nf, Bits(wf, 0));
+  for (int f = 0; f < nf; ++f) {
+    for (int e : faces[f]) bflip(H[f], e);
+    bflip(E[f], f);
+  }
+  std::vector<Bits> B(n, Bits(wf, 0));
+  std::vector<int> pcol;
+  int rank = 0;
+  for (int col = 0; col < n && rank < nf; ++col) {
+    int piv = -1;
+    for (int r = rank; r < nf; ++r)
+      if (bget(H[r], col)) {
+        piv = r;
+        break;
+      }
+    if (piv < 0) continue;
+    std::swap(H[piv], H[rank]);
+    std::swap(E[piv], E[rank]);
+    for (int r = 0; r < nf; ++r)
+      if (r != rank && bget(H[r], col)) {
+        bx(H[r], H[rank]);
+        bx(E[r], E[rank]);
+      }
+    pcol.push_back(col);
+    ++rank;
+  }
+  for (int i = 0; i < rank; ++i) B[pcol[i]] = E[i];
+  // class a of r is its parity on the string above (0, 0); remove it by
+  // adding the bottom membrane (which meets the string once)
+  Bits zrow(wf, 0);
+  for (int z = 0; z < L; ++z) bx(zrow, B[ze(0, 0, z)]);
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) bx(B[ze(x, y, 0)], zrow);
+  // clear the top dangling edges with the stabilizers of the top vertices
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const Bits t = B[ze(x, y, L - 1)];
+      std::vector<int> st = {ze(x, y, L - 1), ze(x, y, L - 2)};
+      if (x > 0) st.push_back(xe(x - 1, y, L - 1));
+      if (x + 1 < L) st.push_back(xe(x, y, L - 1));
+      if (y > 0) st.push_back(ye(x, y - 1, L - 1));
+      if (y + 1 < L) st.push_back(ye(x, y, L - 1));
+      for (int e : st) bx(B[e], t);
+    }
+
+  P = Program{};
+  P.name = "surface3d_depolarizing_L" + std::to_string(L);
+  P.n_det = nv + nf;
+  P.n_mech = n;
+  P.n_cosets = 4;
+  P.n_ext = n;
+  P.ext_src0 = nv;
+  P.ext_src_n = nf;
+  P.ext_words = wf;
+  P.ext_rows.resize(size_t(n) * wf);
+  for (int e = 0; e < n; ++e)
+    for (int w = 0; w < wf; ++w) P.ext_rows[size_t(e) * wf + w] = B[e][w];
+
+  auto W = [&](int e, int u, int v) { return (u == 0 && v == 0) ? 1.0 - p[e] : p[e] / 3.0; };
+  auto I4 = eye(4);
+  Mat Zg(16, 0.0), Xs = xmask(4, 1);
+  for (int i = 0; i < 4; ++i) Zg[i * 4 + i] = (i >> 1) ? -1.0 : 1.0;
+  auto gate_terms = [&](int e, int sgn) {
+    const double al = 0.5 * (W(e, 0, 0) + W(e, 1, 0)), be = 0.5 * (W(e, 0, 0) - W(e, 1, 0)), t1 = W(e, 0, 1);
+    std::vector<Term> ts;
+    ts.push_back({scaled(I4, std::sqrt(al)), scaled(I4, std::sqrt(al))});
+    if (be != 0.0)
+      ts.push_back({scaled(Zg, be > 0 ? std::sqrt(be) : -std::sqrt(-be)), scaled(Zg, sgn * std::sqrt(std::fabs(be)))});
+    if (t1 != 0.0) ts.push_back({scaled(Xs, std::sqrt(t1)), scaled(Xs, std::sqrt(t1))});
+    return ts;
+  };
+
+  Assembler A(P, L, L);
+  for (int c = 0; c < 4; ++c) {
+    A.d.assign(L * L, 1);
+    A.snake_init(std::vector<std::vector<double>>(L * L, {1.0, 1.0}), c >> 1, 4, 2 * (c & 1), c);
+  }
+  const int ndet = P.n_det;
+  for (int z = 1; z < L; ++z) {
+    A.begin_layer();
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        const int e = ze(x, y, z - 1);
+        Mat M0(16, 0.0), M1(16, 0.0);
+        for (int g = 0; g < 2; ++g)
+          for (int g2 = 0; g2 < 2; ++g2)
+            for (int sb = 0; sb < 2; ++sb) {
+              M0[(sb + 2 * g2) * 4 + sb + 2 * g] = W(e, g ^ g2, sb);
+              M1[(sb + 2 * g2) * 4 + sb + 2 * g] = W(e, 1 ^ g ^ g2, sb);
+            }
+        std::string er = A.add_pre(y * L + x, M0, 4, ndet + e, M1);
+        if (!er.empty()) return er;
+      }
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x + 1 < L; ++x) {
+        const int e = xe(x, y, z);
+        A.add_gate(0, x, y, gate_terms(e, 1), ndet + e, gate_terms(e, -1));
+      }
+    for (int y = 0; y + 1 < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        const int e = ye(x, y, z);
+        A.add_gate(1, x, y, gate_terms(e, 1), ndet + e, gate_terms(e, -1));
+      }
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        std::string er = A.add_post(y * L + x, I4, 4, ((z - 1) * L + y) * L + x, Xs);
+        if (!er.empty()) return er;
+      }
+    std::string er = A.end_layer();
+    if (!er.empty()) return er;
+  }
+  std::vector<Mat> f;
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const int e = ze(x, y, L - 1);
+      f.push_back({W(e, 0, 0), W(e, 0, 1), W(e, 1, 0), W(e, 1, 1)});
+    }
+  A.finish(f);
   return "";
 }
 

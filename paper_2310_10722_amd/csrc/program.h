@@ -10,7 +10,9 @@
 //   post-ops, then a per-site rescale.
 // A one-site op may depend on one syndrome bit (it is then M1 when the bit is
 // set, else M0).  A gate is given by its operator-Schmidt terms
-// sum_k OA_k (x) OB_k.
+// sum_k OA_k (x) OB_k, and may also depend on one per-item bit (a second set
+// of terms of the same count).  Per-item bits are the syndrome followed by
+// bits derived from it by a fixed GF(2) map (ext_rows).
 #pragma once
 
 #include <cstdint>
@@ -37,6 +39,9 @@ struct DevGate {
   int32_t oA, oB;      // pool: K matrices [k][p'][p] of dA x dA / dB x dB
   int32_t pA, pB;      // pool: K*K matrices OA_k^T OA_k' ([k][k'][p][q]) / same for B
   int32_t srcA, srcB;  // buffer parities read
+  int32_t det;         // >= 0: the terms depend on this per-item bit (set: oA1 .. pB1)
+  int32_t oA1, oB1, pA1, pB1;
+  int32_t pad[3];
 };
 
 struct LayerRange {
@@ -67,10 +72,16 @@ struct Program {
   std::vector<int32_t> f_off;      // per site pool offset of the final vector
   std::vector<double> pool;
   int32_t max_K = 0, max_dgate = 0;
+  // Derived per-item bits: bit n_det + e of an item is the parity of
+  // ext_rows[e] (ext_words 64-bit words) with syndrome bits
+  // [ext_src0, ext_src0 + 64 ext_words), for e in [0, n_ext).
+  int32_t n_ext = 0, ext_src0 = 0, ext_src_n = 0, ext_words = 0;
+  std::vector<uint64_t> ext_rows;
 };
 
 // Builders; return an empty string on success, else an error message.
 std::string build_surface3d_point(int32_t L, const double* p_mech, Program& out);
 std::string build_rotated_phenom(int32_t d, int32_t T, const double* p_mech, Program& out);
+std::string build_surface3d_depol(int32_t L, const double* p_qubit, Program& out);
 
 }  // namespace tn3d

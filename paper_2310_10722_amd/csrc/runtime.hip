@@ -72,6 +72,7 @@ struct tn3d_net_s {
   double* d_pool = nullptr;
   int32_t *d_leg_bond = nullptr, *d_init_dims = nullptr, *d_init_off = nullptr, *d_bond_dim0 = nullptr;
   int32_t *d_d_after = nullptr, *d_par_after = nullptr, *d_d_final = nullptr, *d_f_off = nullptr;
+  uint64_t* d_ext = nullptr;  // derived-bit rows (Program::ext_rows), or null
   int max_gates_class = 0;
 };
 
@@ -117,6 +118,10 @@ tn3d_status upload_net(tn3d_net n) {
   size_t o_pafter = cv.take<int32_t>(P.par_after.size());
   size_t o_dfin = cv.take<int32_t>(P.d_final.size());
   size_t o_foff = cv.take<int32_t>(P.f_off.size());
+  size_t o_ext = cv.take<uint64_t>(std::max<size_t>(1, P.ext_rows.size()));
+  if (P.n_ext > 0 && (P.ext_words > EXT_MAXW || P.ext_words * 64 < P.ext_src_n ||
+                      P.ext_rows.size() != size_t(P.n_ext) * P.ext_words || P.ext_src0 + P.ext_src_n > P.n_det))
+    return fail(c, TN3D_E_UNSUPPORTED, "derived-bit map too large or inconsistent");
   HIPCHK(c, hipSetDevice(c->device));
   if (hipMalloc(&n->dev, cv.off) != hipSuccess) return fail(c, TN3D_E_OOM, "device allocation of the network");
   auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
@@ -134,6 +139,7 @@ tn3d_status upload_net(tn3d_net n) {
   HIPCHK(c, put(o_pafter, P.par_after.data(), P.par_after.size() * 4));
   HIPCHK(c, put(o_dfin, P.d_final.data(), P.d_final.size() * 4));
   HIPCHK(c, put(o_foff, P.f_off.data(), P.f_off.size() * 4));
+  HIPCHK(c, put(o_ext, P.ext_rows.data(), P.ext_rows.size() * 8));
   n->d_ones = reinterpret_cast<DevOneSite*>(n->dev + o_ones);
   n->d_gates = reinterpret_cast<DevGate*>(n->dev + o_gates);
   n->d_pool = reinterpret_cast<double*>(n->dev + o_pool);
@@ -145,6 +151,7 @@ tn3d_status upload_net(tn3d_net n) {
   n->d_par_after = reinterpret_cast<int32_t*>(n->dev + o_pafter);
   n->d_d_final = reinterpret_cast<int32_t*>(n->dev + o_dfin);
   n->d_f_off = reinterpret_cast<int32_t*>(n->dev + o_foff);
+  n->d_ext = P.n_ext > 0 ? reinterpret_cast<uint64_t*>(n->dev + o_ext) : nullptr;
   n->max_gates_class = 0;
   for (auto& L : P.layers)
     for (int k = 0; k < 4; ++k) n->max_gates_class = std::max(n->max_gates_class, L.gate1[k] - L.gate0[k]);
@@ -327,7 +334,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_win = cv.take<unsigned long long>(size_t(n_win) * 128);
   size_t o_gitems = cv.take<int32_t>(chunk_items);
   size_t o_gsoff = cv.take<int64_t>(chunk_items);
-  size_t o_gsynd = cv.take<uint8_t>(chunk_items * std::max(1, P.n_det));
+  // per-item bits: the syndrome, then the bits derived from it
+  const int64_t bstride = std::max(1, P.n_det + P.n_ext);
+  size_t o_gsynd = cv.take<uint8_t>(chunk_items * bstride);
   size_t o_glp = cv.take<double>(chunk_items * 4);
   size_t o_gfl = cv.take<uint32_t>(chunk_items);
   tn3d_status st = ensure_ws(c, cv.off);
@@ -488,14 +497,18 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     return TN3D_OK;
     };
     bool done = false;
+    int32_t* g_items = reinterpret_cast<int32_t*>(ws + o_gitems);
+    int64_t* g_soff = reinterpret_cast<int64_t*>(ws + o_gsoff);
+    uint8_t* g_synd = reinterpret_cast<uint8_t*>(ws + o_gsynd);
+    double* g_lp = reinterpret_cast<double*>(ws + o_glp);
+    uint32_t* g_fl = reinterpret_cast<uint32_t*>(ws + o_gfl);
+    auto gather_inputs = [&]() {
+      launch_gather_synd(ni, d_items, synd, synd_off, P.n_det, bstride, g_synd, s);
+      launch_ext_bits(ni, g_synd, bstride, P.n_det, P.ext_src0, P.ext_src_n, P.ext_words, n->d_ext, P.n_ext, s);
+    };
     if (c->graphs) {
       // inputs into the workspace, replay (capturing first if needed), results out
-      int32_t* g_items = reinterpret_cast<int32_t*>(ws + o_gitems);
-      int64_t* g_soff = reinterpret_cast<int64_t*>(ws + o_gsoff);
-      uint8_t* g_synd = reinterpret_cast<uint8_t*>(ws + o_gsynd);
-      double* g_lp = reinterpret_cast<double*>(ws + o_glp);
-      uint32_t* g_fl = reinterpret_cast<uint32_t*>(ws + o_gfl);
-      launch_gather_synd(ni, d_items, synd, synd_off, P.n_det, g_synd, s);
+      gather_inputs();
       HIPCHK(c, hipGetLastError());
       const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
                          c->ws, c->ws_bytes};
@@ -510,7 +523,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         if (!c->cap_stream) ce = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
         if (ce == hipSuccess) ce = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
         if (ce == hipSuccess) {
-          launch_seq(ni, g_items, g_soff, P.n_det, c->cap_stream);
+          launch_seq(ni, g_items, g_soff, bstride, c->cap_stream);
           es = enqueue(g_items, g_synd, g_soff, g_lp, g_fl, c->cap_stream);
           ce = hipStreamEndCapture(c->cap_stream, &gr);
         }
@@ -537,7 +550,15 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         done = true;
       }
     }
-    if (!done) {
+    if (!done && P.n_ext > 0) {
+      // the derived bits live in the workspace copy of the inputs
+      gather_inputs();
+      launch_seq(ni, g_items, g_soff, bstride, s);
+      tn3d_status es = enqueue(g_items, g_synd, g_soff, g_lp, g_fl, s);
+      if (es != TN3D_OK) return es;
+      launch_scatter_out(ni, d_items, g_lp, g_fl, logp, flags_out, s);
+      HIPCHK(c, hipGetLastError());
+    } else if (!done) {
       tn3d_status es = enqueue(d_items, synd, synd_off, logp, flags_out, s);
       if (es != TN3D_OK) return es;
     }
@@ -711,6 +732,14 @@ tn3d_status tn3d_net_rotated_phenom(tn3d_ctx c, int32_t d, int32_t T, const doub
   *out = nullptr;
   Program P;
   std::string e = build_rotated_phenom(d, T, p, P);
+  return make_net(c, e, std::move(P), out);
+}
+
+tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  Program P;
+  std::string e = build_surface3d_depol(L, p, P);
   return make_net(c, e, std::move(P), out);
 }
 

@@ -96,7 +96,12 @@ void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t*
 // local item indices with their offsets, zero a counter block (no memset
 // node in a captured graph), and scatter the local results to the caller.
 void launch_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
-                        uint8_t* out, hipStream_t st);
+                        int64_t stride, uint8_t* out, hipStream_t st);
+// Derived bits n_det + e, e < n_ext, of n items laid out at `stride` bytes
+// (Program::ext_rows; words <= EXT_MAXW).
+constexpr int EXT_MAXW = 64;
+void launch_ext_bits(int n, uint8_t* bits, int64_t stride, int n_det, int src0, int src_n, int words,
+                     const uint64_t* rows, int n_ext, hipStream_t st);
 void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_t st);
 // Writes the device wall clock (hipDeviceAttributeWallClockRate ticks) to *out.
 void launch_stamp(unsigned long long* out, hipStream_t st);

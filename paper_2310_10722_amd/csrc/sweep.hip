@@ -51,6 +51,12 @@ __device__ __forceinline__ int synd_bit(const SweepArgs& A, int sweep, int det) 
   return A.synd[A.synd_off[item] + det] & 1;
 }
 
+// A gate whose terms depend on a per-item bit uses its second term set when
+// the bit is set.
+__device__ __forceinline__ bool gate_alt(const SweepArgs& A, const DevGate& g, int sweep) {
+  return g.det >= 0 && synd_bit(A, sweep, g.det);
+}
+
 __device__ double block_max_abs_reduce(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -300,8 +306,9 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
   const int K = g.K, dA = g.dA, dB = g.dB, n = K * D;
   const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
   const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
-  const double* PA = A.pool + g.pA;
-  const double* PB = A.pool + g.pB;
+  const bool alt = gate_alt(A, g, sweep);
+  const double* PA = A.pool + (alt ? g.pA1 : g.pA);
+  const double* PB = A.pool + (alt ? g.pB1 : g.pB);
   const int nA = dA * D, nB = dB * D;
   if (dA <= 4 && dB <= 4) {
     // one bond pair (b, b2) per thread: its dA^2 and dB^2 Gram entries loaded
@@ -351,12 +358,13 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
 
 // W_A, W_B of a truncation (the kept singular vectors of C mapped back
 // through the gate), threads first, first + stride, ... of the caller.
-__device__ void write_w(const SweepArgs& A, const DevGate& g, int D, int Dn, bool bad, int n, int rA, int rB,
+__device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, int Dn, bool bad, int n, int rA, int rB,
                         const double* CM, const double* VM, const double* ZA, const double* ZB, const int* ord,
                         const double* Ss, double s1, double* WA, double* WB, int first, int stride) {
   const int K = g.K, dA = g.dA, dB = g.dB, nA = dA * D, nB = dB * D;
-  const double* OA = A.pool + g.oA;
-  const double* OB = A.pool + g.oB;
+  const bool alt = gate_alt(A, g, sweep);
+  const double* OA = A.pool + (alt ? g.oA1 : g.oA);
+  const double* OB = A.pool + (alt ? g.oB1 : g.oB);
   const int ncA = dA * Dn, ncB = dB * Dn;
   if (bad) {
     for (int e = first; e < nA * ncA; e += stride) WA[2 + e] = 0.0;
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (f) atomicOr(&A.flags[sweep], f);
   }
   for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
-  write_w(A, g, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT);
+  write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,7 +763,7 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
     if (f) atomicOr(&A.flags[sweep], f);
   }
   for (int m = l; m < Dn; m += TL) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
-  write_w(A, g, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, l, TL);
+  write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, l, TL);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,10 +1061,16 @@ __global__ __launch_bounds__(ZBT) void k_zip_b(ZipArgs Z, int x, int y, int lds_
     vs = len;
     es = 1;
   } else {
-    A = Th;
+    // the next kernel reads Theta itself again: rotate a copy, in L4, which
+    // is free until the kept vectors are written over it (after the norms)
+    A = Z.L4 + int64_t(s) * Z.bigcap;
     J = Jm;
-    vs = rows ? C : 1;
-    es = rows ? 1 : C;
+    for (int e = tid; e < nv * len; e += ZBT) {
+      const int v = e / len, k = e % len;
+      A[e] = rows ? Th[v * C + k] : Th[k * C + v];
+    }
+    vs = len;
+    es = 1;
   }
   __syncthreads();
   const int nsw = block_jacobi(A, vs, es, nv, len, J, Z.jtol, Z.jfloor, 40, flag, red);
@@ -1440,11 +1454,36 @@ __global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned
 // Graph replay support: the captured sequence reads and writes only
 // workspace buffers, filled and drained by these kernels outside it.
 __global__ void k_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
-                              uint8_t* out) {
+                              int64_t stride, uint8_t* out) {
   const int i = blockIdx.y;
   const int64_t src = offs[items[i]];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_det; k += gridDim.x * blockDim.x)
-    out[int64_t(i) * n_det + k] = synd[src + k];
+    out[int64_t(i) * stride + k] = synd[src + k];
+}
+
+// Derived per-item bits: bit n_det + e of item i is the parity of
+// rows[e] & (syndrome bits [src0, src0 + src_n) packed 64 to a word).  One
+// workgroup of 256 per item; the packed syndrome goes through LDS.
+__global__ __launch_bounds__(256) void k_ext_bits(int n, uint8_t* bits, int64_t stride, int n_det, int src0,
+                                                  int src_n, int words, const uint64_t* rows, int n_ext) {
+  __shared__ uint64_t mw[EXT_MAXW];
+  const int i = blockIdx.x;
+  uint8_t* b = bits + int64_t(i) * stride;
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
+    uint64_t v = 0;
+    for (int k = 0; k < 64; ++k) {
+      const int j = w * 64 + k;
+      if (j < src_n) v |= uint64_t(b[src0 + j] & 1) << k;
+    }
+    mw[w] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n_ext; e += blockDim.x) {
+    const uint64_t* r = rows + int64_t(e) * words;
+    int par = 0;
+    for (int w = 0; w < words; ++w) par ^= __popcll(r[w] & mw[w]) & 1;
+    b[n_det + e] = uint8_t(par);
+  }
 }
 
 __global__ void k_seq(int n, int32_t* items, int64_t* offs, int64_t stride) {
@@ -1632,10 +1671,17 @@ void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t*
                        A.flags, flags_out);
 }
 
+void launch_ext_bits(int n, uint8_t* bits, int64_t stride, int n_det, int src0, int src_n, int words,
+                     const uint64_t* rows, int n_ext, hipStream_t st) {
+  if (n <= 0 || n_ext <= 0) return;
+  hipLaunchKernelGGL(k_ext_bits, dim3(n), dim3(256), 0, st, n, bits, stride, n_det, src0, src_n, words, rows, n_ext);
+}
+
 void launch_gather_synd(int n, const int32_t* items, const uint8_t* synd, const int64_t* offs, int n_det,
-                        uint8_t* out, hipStream_t st) {
+                        int64_t stride, uint8_t* out, hipStream_t st) {
   if (n <= 0 || n_det <= 0) return;
-  hipLaunchKernelGGL(k_gather_synd, dim3((n_det + 255) / 256, n), dim3(256), 0, st, n, items, synd, offs, n_det, out);
+  hipLaunchKernelGGL(k_gather_synd, dim3((n_det + 255) / 256, n), dim3(256), 0, st, n, items, synd, offs, n_det,
+                     stride, out);
 }
 
 void launch_stamp(unsigned long long* out, hipStream_t st) {

@@ -30,7 +30,8 @@ STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OO
 # every entry point declared in include/tn3d.h
 SYMBOLS = [
     "tn3d_params_default", "tn3d_ctx_create", "tn3d_ctx_destroy", "tn3d_last_error",
-    "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_num_detectors",
+    "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_surface3d_depolarizing",
+    "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_last_stats",
     "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached",
@@ -68,6 +69,7 @@ def load_library(path: str | None = None):
     lib.tn3d_last_error.restype = ctypes.c_char_p
     lib.tn3d_net_surface3d_point.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     lib.tn3d_net_rotated_phenom.argtypes = [c_p, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    lib.tn3d_net_surface3d_depolarizing.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     for f in ("tn3d_net_num_detectors", "tn3d_net_num_mechanisms", "tn3d_net_num_cosets"):
         getattr(lib, f).argtypes = [c_p]
         getattr(lib, f).restype = i32
@@ -86,7 +88,8 @@ def load_library(path: str | None = None):
     lib.tn3d_last_timing.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.restype = i32
-    for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_contract_cosets",
+    for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
+              "tn3d_net_surface3d_depolarizing", "tn3d_contract_cosets",
               "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_ctx_set_graphs"):
         getattr(lib, f).restype = i32
     if path is None:
@@ -212,6 +215,13 @@ def tn3d_net_rotated_phenom(ctx: Context, d: int, T: int, p_mech) -> Net:
     a, ptr = _rates(p_mech)
     h = ctypes.c_void_p()
     _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_rotated_phenom(ctx.h, d, T, ptr, ctypes.byref(h)))
+    return Net(ctx, h)
+
+
+def tn3d_net_surface3d_depolarizing(ctx: Context, L: int, p_qubit) -> Net:
+    a, ptr = _rates(p_qubit)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_depolarizing(ctx.h, L, ptr, ctypes.byref(h)))
     return Net(ctx, h)
 
 

@@ -1,0 +1,201 @@
+"""GPU parity for the depolarizing family of the 3D planar code (four
+cosets, physical dim 4, rank-3 gates whose terms depend on a per-item GF(2)
+representative of the face syndrome) against the oracle's mixed-picture
+network at equal chi, chi_m and rank rule.
+
+The two sides start from different representatives of each coset's face
+syndrome (the library's fixed GF(2) map, the oracle's elimination); they
+differ by vertex stabilizers, which only permute physical indices between
+layers, so the truncated contractions agree to rounding (pinned on the CPU in
+test_oracle_depol.py).
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.network import depol3d_network
+from oracle.sweep import sweep_logprob
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = 0.15
+SEED = synth.CONFIG_SEED_BASE + 4
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_10722_amd import tn3d
+    return tn3d.Context(0)
+
+
+def gpu_logp(ctx, net, m, prm):
+    from paper_2310_10722_amd import tn3d
+    syn = torch.from_numpy(np.ascontiguousarray(m)).to("cuda:0")
+    logp, flags = tn3d.tn3d_contract_cosets(ctx, net, syn, prm)
+    torch.cuda.synchronize()
+    return logp.cpu().numpy(), flags.cpu().numpy()
+
+
+def oracle(L, p, m, prm):
+    return np.array([[sweep_logprob(depol3d_network(L, p, m[k], c), prm.chi, prm.chi_mps, prm.eps_rel,
+                                    prm.tau_gap)[0] for c in range(4)] for k in range(m.shape[0])])
+
+
+def check(got, ref, tol_top, tol_all):
+    """The most likely coset (by the oracle) within tol_top, every coset
+    within tol_all, and the same decision where the oracle's top two are
+    apart by more than tol_top.  The other cosets sit 5-15 nats lower, carried
+    by singular values near the rank rule's cut, which amplifies rounding
+    differences (FP64) or the site tensors' rounding (FP32)."""
+    err = np.abs(got - ref)
+    top = np.argmax(ref, axis=1)
+    err_top = err[np.arange(len(ref)), top]
+    say("  max |d log p|: most likely coset", err_top.max(), " all cosets", err.max())
+    assert err_top.max() <= tol_top
+    assert err.max() <= tol_all
+    srt = np.sort(ref, axis=1)
+    clear = srt[:, -1] - srt[:, -2] > tol_top
+    assert np.array_equal(np.argmax(got, axis=1)[clear], top[clear])
+
+
+def workload(L, n, seed=SEED, rates=None):
+    dem = synth.surface3d_depolarizing(L, P if rates is None else rates)
+    m, cos = synth.sample_pauli(dem, n, seed)
+    return dem, m, cos
+
+
+def test_depol_L3_chi4_fp64(ctx):
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing L=3 p=0.15 chi=4 fp64 default rule, 32 syndromes")
+    dem, m, _ = workload(3, 32)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 3, dem.params["p_qubit"])
+    assert net.n_cosets == 4 and net.n_det == 18 + 44
+    prm = tn3d.tn3d_params_default(4, 4, tn3d.PREC_FP64)
+    got, flags = gpu_logp(ctx, net, m, prm)
+    ref = oracle(3, dem.params["p_qubit"], m, prm)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = np.all(np.isfinite(ref), axis=1)
+    assert np.all(flags[~ok] & 1)
+    check(got[ok], ref[ok], 1e-9, 1e-7)
+
+
+def test_depol_L3_chi16_and_exact(ctx):
+    """chi = chi_m = 16 on L = 3 (the widest bond the library holds at
+    physical dim 4): equal to the oracle at the same chi.  Against the stored
+    exact contractions (O-2 on the DEM form) the most likely coset is within
+    1e-3 and the decision agrees; the cosets of the other X class, about 15
+    nats lower, are off by up to 4 nats at chi_m = 16 on both sides (the
+    boundary MPS cut at 1e-9 relative drops what carries them; chi_m = 64 or
+    a 1e-12 cut recovers them in the oracle)."""
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing L=3 chi=16 fp64, stored exact syndromes + 12 sampled")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "depol_L3_exact.json")))
+    dem, m, _ = workload(3, 12, seed=7)
+    m = np.concatenate([np.array(gold["syndromes"], dtype=np.uint8), m])
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 3, dem.params["p_qubit"])
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
+    got, _ = gpu_logp(ctx, net, m, prm)
+    ref = oracle(3, dem.params["p_qubit"], m, prm)
+    check(got, ref, 1e-9, 1e-7)
+    exact = np.array(gold["logp"])
+    best = np.argmax(exact, axis=1)
+    ex = np.abs(got[:3] - exact)
+    say("  vs exact: most likely coset", ex[np.arange(3), best].max(), " all cosets", ex.max())
+    assert ex[np.arange(3), best].max() <= 1e-3
+    assert np.array_equal(np.argmax(got[:3], axis=1), best)
+
+
+@pytest.mark.parametrize("mode", ["fp64_default", "fp64_reduced", "fp32_reduced"])
+def test_depol_L4_chi8(ctx, mode):
+    from paper_2310_10722_amd import tn3d
+    say(f"case: depolarizing L=4 p=0.15 chi=8 {mode}, 8 syndromes")
+    dem, m, _ = workload(4, 8)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 4, dem.params["p_qubit"])
+    prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP32 if mode == "fp32_reduced" else tn3d.PREC_FP64)
+    if mode != "fp64_default":
+        prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    got, _ = gpu_logp(ctx, net, m, prm)
+    ref = oracle(4, dem.params["p_qubit"], m, prm)
+    # FP64 default rule at L = 4: 8.5e-9 / 4.1e-8 measured, while the oracle
+    # under two LAPACK SVD drivers agrees with itself to 1e-12, so this gap is
+    # the library's (its gate truncations factor the site tensors through
+    # their Grams, which squares the condition of the smallest kept values)
+    check(got, ref, *{"fp64_default": (1e-7, 1e-6), "fp64_reduced": (1e-6, 1e-4), "fp32_reduced": (1e-3, 0.5)}[mode])
+
+
+def test_depol_L4_chi16_nonuniform(ctx):
+    """chi = chi_m = 16 at L = 4 with per-qubit rates drawn in [0.05, 0.2]."""
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing L=4 chi=16 fp64 reduced rule, non-uniform rates, 4 syndromes")
+    n = 4 ** 3 + 2 * 4 * 9
+    rates = np.random.default_rng(3).uniform(0.05, 0.2, n)
+    dem, m, _ = workload(4, 4, rates=rates)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 4, rates)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    got, _ = gpu_logp(ctx, net, m, prm)
+    ref = oracle(4, rates, m, prm)
+    check(got, ref, 1e-6, 1e-4)
+
+
+def test_depol_ragged_decode_eager_and_graph(ctx):
+    """A batch mixing L = 3 and L = 4 (different syndrome widths), decoded
+    with captured launch sequences and eagerly: identical results, equal to
+    the oracle, decisions = argmax."""
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing ragged L=3/L=4 decode chi=8 fp64, graphs and eager")
+    d3, m3, _ = workload(3, 4, seed=31)
+    d4, m4, _ = workload(4, 4, seed=32)
+    width = max(d3.n_det, d4.n_det)
+    outs = []
+    for graphs in (True, False):
+        c = tn3d.Context(0)
+        c.set_graphs(graphs)
+        n3 = tn3d.tn3d_net_surface3d_depolarizing(c, 3, d3.params["p_qubit"])
+        n4 = tn3d.tn3d_net_surface3d_depolarizing(c, 4, d4.params["p_qubit"])
+        syn = np.zeros((8, width), dtype=np.uint8)
+        nets = []
+        for i in range(8):
+            if i % 2 == 0:
+                syn[i, :d3.n_det] = m3[i // 2]
+                nets.append(n3)
+            else:
+                syn[i, :d4.n_det] = m4[i // 2]
+                nets.append(n4)
+        prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP64)
+        res = tn3d.tn3d_decode(c, nets, torch.from_numpy(syn).cuda(), prm)
+        torch.cuda.synchronize()
+        outs.append([r.cpu().numpy() for r in res])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    coset, lr, logp, flags = outs[0]
+    prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP64)
+    for i in range(8):
+        L, dem, m = (3, d3, m3[i // 2]) if i % 2 == 0 else (4, d4, m4[i // 2])
+        ref = oracle(L, dem.params["p_qubit"], m[None], prm)[0]
+        check(logp[i][None], ref[None], 1e-7, 1e-6)
+        srt = np.sort(ref)
+        assert int(coset[i]) == int(np.argmax(ref)) or srt[-1] - srt[-2] <= 2e-9
+        assert float(lr[i]) == pytest.approx(srt[-1] - srt[-2], abs=1e-8)
+
+
+def test_depol_chi24_refused(ctx):
+    """Physical dim 4 times chi = 24 exceeds the 64 the kernels hold."""
+    from paper_2310_10722_amd import tn3d
+    dem, m, _ = workload(4, 2)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 4, dem.params["p_qubit"])
+    prm = tn3d.tn3d_params_default(24, 24, tn3d.PREC_FP32)
+    with pytest.raises(tn3d.Tn3dError, match="UNSUPPORTED"):
+        gpu_logp(ctx, net, m, prm)
