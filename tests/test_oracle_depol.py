@@ -121,3 +121,20 @@ def test_gf2_solve():
         assert x is not None and np.array_equal((A.astype(np.int64) @ x) & 1, b)
     A = np.array([[1, 1], [1, 1]], dtype=np.uint8)
     assert gf2_solve(A, np.array([1, 0])) is None
+
+
+def test_pauli_sampler_distribution():
+    # the seeded sampler draws I / X / Y / Z with 1-p, p/3, p/3, p/3 per qubit;
+    # its syndromes are those of the drawn Pauli, so every face syndrome is
+    # consistent (the oracle's elimination finds a representative)
+    L = 3
+    dem = synth.surface3d_depolarizing(L, 0.15)
+    pr = dem.params
+    nv = pr["HX"].shape[0]
+    m, cos = synth.sample_pauli(dem, 4000, 99)
+    # an X or Y on the vertical string flips a, so P(a = 1) = (1 - (1 - 4p/3)^L) / 2
+    pa = np.mean(cos & 1)
+    expect = 0.5 * (1 - (1 - 4 * 0.15 / 3) ** L)
+    assert abs(pa - expect) < 4 * np.sqrt(expect * (1 - expect) / 4000)
+    for k in range(50):
+        assert gf2_solve(pr["HZ"], m[k][nv:]) is not None
