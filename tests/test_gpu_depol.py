@@ -150,6 +150,26 @@ def test_depol_L4_chi16_nonuniform(ctx):
     check(got, ref, 1e-6, 1e-4)
 
 
+def test_depol_L6_chi8_sampled(ctx):
+    """The largest size of the depolarizing workload (L = 6, 36 sites, 5
+    layers, 665 detectors): 64 syndromes in one call at chi = chi_m = 8 with
+    the reduced rule (the benchmark's setting), three of them checked against
+    the oracle (all four cosets)."""
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing L=6 chi=8 fp64 reduced rule, 64 syndromes, 3 checked")
+    dem, m, _ = workload(6, 64, seed=SEED + 6)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 6, dem.params["p_qubit"])
+    assert net.n_det == 6 * 6 * 5 + 485
+    prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    got, flags = gpu_logp(ctx, net, m, prm)
+    pick = [0, 31, 63]
+    ref = oracle(6, dem.params["p_qubit"], m[pick], prm)
+    ok = np.all(np.isfinite(ref), axis=1)
+    assert np.all(flags[pick][~ok] & 1)
+    check(got[pick][ok], ref[ok], 1e-6, 1e-4)
+
+
 def test_depol_ragged_decode_eager_and_graph(ctx):
     """A batch mixing L = 3 and L = 4 (different syndrome widths), decoded
     with captured launch sequences and eagerly: identical results, equal to
