@@ -15,4 +15,12 @@ Tiers (each module's header says what pins it):
   sweep.py    O-3 the fixed-chi boundary sweep with simple-update truncation
               (Sec. 4) followed by the boundary-MPS contraction of the final 2D
               network, with LAPACK QR/SVD.
+  grad.py     O-4 the exact gradient of log P(m) with respect to every
+              mechanism rate (the affine split of P(m) in each rate, on O-2),
+              the chain rule to shared rates, and central finite differences
+              (of O-2, or of O-3 for the approximate value).
+
+Parity unpinned: the boundary-MPS truncation in rows after the first (the
+zip-up has no reduction to an optimal truncation there); it is pinned only
+by the exact limit.
 """

@@ -1,0 +1,99 @@
+"""O-4: gradients of the syndrome log-likelihood with respect to the rates.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The quantity (paper Sec. 2.4): for a DEM (H, p, l) and a syndrome m,
+
+    P(m) = sum_L p_{m,L} = sum over x with H x = m of prod_i p_i^{x_i} (1 - p_i)^{1 - x_i}.
+
+P(m) is affine in each p_i separately: splitting the sum by x_i,
+    P(m) = (1 - p_i) P(m | p_i = 0) + p_i P(m | p_i = 1),
+where P(m | p_i = c) is the same sum with rate i set to c.  Hence
+
+    d log P(m) / d p_i = (P(m | p_i = 1) - P(m | p_i = 0)) / P(m),
+
+which is the plain definition used here, evaluated with the exact frontier
+contraction (O-2) once per mechanism and value.  Equivalently it is
+(mu_i - p_i) / (p_i (1 - p_i)) with the posterior marginal
+mu_i = P(x_i = 1 | m) = p_i P(m | p_i = 1) / P(m).
+
+Rates shared by several mechanisms (one rate per data qubit over all rounds,
+one per measurement event) get the sum of their mechanisms' derivatives
+(chain rule through p_i = r_{k(i)}).
+
+Pins (tests/test_oracle_grad.py): brute-force posterior marginals on tiny
+codes (the marginal form above, enumerated independently), central finite
+differences of O-2, and a two-mechanism closed form.
+
+Also here: central finite differences of the fixed-chi sweep (O-3), the
+derivative of the *approximate* value that a reverse pass of the sweep
+computes (ranks held fixed between the two evaluations).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .exact import default_order, frontier_logprobs
+
+
+def _logsumexp(v):
+    v = np.asarray(v, dtype=np.float64)
+    m = np.max(v)
+    if not np.isfinite(m):
+        return m
+    return m + np.log(np.sum(np.exp(v - m)))
+
+
+def loglik_exact(H, p, obs, m, order=None):
+    """log P(m) = log sum_L p_{m,L} by the exact frontier contraction."""
+    return _logsumexp(frontier_logprobs(H, p, obs, m, order=order))
+
+
+def loglik_grad_exact(H, p, obs, m, order=None):
+    """(log P(m), d log P(m) / d p_i for every mechanism i), exactly."""
+    p = np.asarray(p, dtype=np.float64)
+    if order is None:
+        order = default_order(H)
+    lp = loglik_exact(H, p, obs, m, order)
+    g = np.empty(p.size)
+    for i in range(p.size):
+        q = p.copy()
+        q[i] = 1.0
+        l1 = loglik_exact(H, q, obs, m, order)
+        q[i] = 0.0
+        l0 = loglik_exact(H, q, obs, m, order)
+        g[i] = np.exp(l1 - lp) - np.exp(l0 - lp)
+    return lp, g
+
+
+def batch_loglik_grad_exact(H, p, obs, syndromes):
+    """sum_s log P(m_s) and its gradient over a batch of syndromes."""
+    order = default_order(H)
+    tot, g = 0.0, np.zeros(np.asarray(p).size)
+    for m in syndromes:
+        l, gi = loglik_grad_exact(H, p, obs, m, order)
+        tot += l
+        g += gi
+    return tot, g
+
+
+def reduce_to_rates(g_mech, rate_of_mech, n_rates):
+    """Chain rule for rates shared by mechanisms: g_r = sum_{i: k(i) = r} g_i."""
+    out = np.zeros(n_rates)
+    np.add.at(out, np.asarray(rate_of_mech), np.asarray(g_mech))
+    return out
+
+
+def central_difference(fun, p, indices, rel_step=1e-5):
+    """(f(p + h e_i) - f(p - h e_i)) / 2h with h = rel_step * p_i, for i in indices."""
+    p = np.asarray(p, dtype=np.float64)
+    out = np.empty(len(indices))
+    for k, i in enumerate(indices):
+        h = rel_step * p[i]
+        a = p.copy()
+        a[i] += h
+        b = p.copy()
+        b[i] -= h
+        out[k] = (fun(a) - fun(b)) / (2.0 * h)
+    return out

@@ -65,7 +65,7 @@ def _svd(A, driver):
 
 
 class Sweep:
-    def __init__(self, net: LayeredNet, chi, chi_m, eps_rel=1e-12, tau_gap=1e-9,
+    def __init__(self, net: LayeredNet, chi, chi_m, eps_rel=1e-9, tau_gap=1e-6,
                  svd_driver="gesdd"):
         self.net = net
         self.Lx, self.Ly = net.Lx, net.Ly
@@ -246,10 +246,12 @@ class Sweep:
         return self.logscale + self.boundary_mps(Ts)
 
 
-def sweep_logprob(net: LayeredNet, chi, chi_m=None, eps_rel=1e-12, tau_gap=1e-9,
+def sweep_logprob(net: LayeredNet, chi, chi_m=None, eps_rel=1e-9, tau_gap=1e-6,
                   svd_driver="gesdd"):
     """log of the approximate contraction value of one network; returns
-    (logp, flags, n_cluster_splits)."""
+    (logp, flags, n_cluster_splits).  The rank rule defaults to the FP64 rule
+    (eps_rel 1e-9, tau_gap 1e-6); a strict rule (1e-12, 1e-9) is passed
+    explicitly where the exact limit is compared."""
     sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver)
     try:
         lp = sw.run()

@@ -75,7 +75,7 @@ def test_sweep_exact_L2(l2):
     for k in range(8):
         ref = np.log(_lookup(table, dem, m[k]))
         for c in range(4):
-            lp, _, _ = sweep_logprob(depol3d_network(2, dem.params["p_qubit"], m[k], c), 64, 64)
+            lp, _, _ = sweep_logprob(depol3d_network(2, dem.params["p_qubit"], m[k], c), 64, 64, 1e-12, 1e-9)
             assert lp == pytest.approx(ref[c], abs=1e-11)
 
 
@@ -106,7 +106,7 @@ def test_representative_is_a_gauge():
         for v in (0, 4, 13):
             r2 = r ^ pr["HX"][v]
             for c in range(4):
-                lp = [sweep_logprob(depol3d_network(L, 0.15, m[k], c, rep=rr), 4, 8)[0]
+                lp = [sweep_logprob(depol3d_network(L, 0.15, m[k], c, rep=rr), 4, 8, 1e-12, 1e-9)[0]
                       for rr in (r, r2)]
                 assert lp[1] == pytest.approx(lp[0], abs=1e-11)
 

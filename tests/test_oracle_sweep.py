@@ -23,7 +23,7 @@ def test_point_sweep_exact_at_large_chi(L, chi, chi_m):
     for k in range(6):
         ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
         for c in range(2):
-            lp, flags, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), chi, chi_m)
+            lp, flags, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), chi, chi_m, 1e-12, 1e-9)
             assert lp == pytest.approx(ex[c], abs=1e-10)
 
 
@@ -35,7 +35,7 @@ def test_rotated_sweep_exact_at_large_chi(d, T):
         ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
         for c in range(2):
             net = rotated_network(d, T, dem.params["checks"], dem.p, m[k], c)
-            lp, flags, _ = sweep_logprob(net, 512)
+            lp, flags, _ = sweep_logprob(net, 512, None, 1e-12, 1e-9)
             assert lp == pytest.approx(ex[c], abs=1e-10)
 
 
@@ -47,7 +47,7 @@ def test_truncation_is_an_approximation():
     for k in range(8):
         ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
         for c in range(2):
-            lp, _, _ = sweep_logprob(point3d_network(3, dem.p, m[k], c), 4)
+            lp, _, _ = sweep_logprob(point3d_network(3, dem.p, m[k], c), 4, None, 1e-12, 1e-9)
             diffs.append(abs(lp - ex[c]))
     assert max(diffs) > 1e-6
     assert max(diffs) < 0.5
@@ -58,8 +58,8 @@ def test_svd_driver_independence():
     for k in range(6):
         for c in range(2):
             net = point3d_network(3, dem.p, m[k], c)
-            a, fa, na = sweep_logprob(net, 4, svd_driver="gesdd")
-            b, fb, nb = sweep_logprob(net, 4, svd_driver="gesvd")
+            a, fa, na = sweep_logprob(net, 4, None, 1e-12, 1e-9, svd_driver="gesdd")
+            b, fb, nb = sweep_logprob(net, 4, None, 1e-12, 1e-9, svd_driver="gesvd")
             if na == 0 and nb == 0:
                 assert a == pytest.approx(b, abs=1e-11)
 
@@ -72,7 +72,7 @@ def test_half_rate_point_sector():
     rank = dem.n_det + 1
     for k in range(3):
         for c in range(2):
-            lp, _, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), 64)
+            lp, _, _ = sweep_logprob(point3d_network(L, dem.p, m[k], c), 64, None, 1e-12, 1e-9)
             assert lp == pytest.approx(-rank * np.log(2), abs=1e-10)
 
 
