@@ -53,13 +53,23 @@ typedef enum {
 #define TN3D_FLAG_TRUNC_CLUSTER 2u /* a truncation cut inside a cluster of equal singular values */
 #define TN3D_FLAG_NEAR_TIE 4u      /* |log ratio| of the decision below params.near_tie */
 #define TN3D_FLAG_NO_CONVERGE 8u   /* a Jacobi SVD stopped at its sweep limit */
-#define TN3D_FLAG_RESWEPT 16u      /* decode: contracted again in FP64 (near tie of an FP32 pass) */
+#define TN3D_FLAG_RESWEPT 16u      /* decode: contracted again in FP64 (near tie of a reduced-precision pass) */
+#define TN3D_FLAG_INCONSISTENT 32u /* no error pattern has this syndrome: log p = -inf for every coset */
 
 /* Arithmetic of the layer absorption (site tensors and their contractions).
  * The truncation factorisations, singular values and log accumulators are
  * always FP64. */
 #define TN3D_PREC_FP64 0
 #define TN3D_PREC_FP32 1
+
+/* params.flags bits. */
+/* FP64 only: factor the truncations through Gram matrices (MFMA Grams,
+ * Cholesky, eigenpairs of boundary-MPS family Grams) instead of orthogonal
+ * factorisations (Householder QR of the gate sides, one-sided Jacobi SVD of
+ * the boundary-MPS families).  Faster at large chi; a Gram squares the
+ * condition of the smallest kept singular values, about 1e-8 in log p
+ * instead of about 1e-11.  Reduced precisions always use the Gram route. */
+#define TN3D_OPT_GRAM_FACTOR 1u
 
 typedef struct tn3d_ctx_s* tn3d_ctx;
 typedef struct tn3d_net_s* tn3d_net;
@@ -73,7 +83,7 @@ typedef struct {
   double tau_gap;    /* never cut where S_{D+1} >= (1 - tau_gap) S_D */
   double near_tie;   /* decode: flag items whose |log ratio| is below this */
   int64_t workspace_bytes; /* cap on the context workspace (0 = no cap) */
-  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t flags;    /* TN3D_OPT_* bits (0 = defaults) */
   uint32_t reserved1;
 } tn3d_params;
 
@@ -140,7 +150,9 @@ tn3d_status tn3d_net_rotated_phenom(tn3d_ctx ctx, int32_t d, int32_t T, const do
  * of operator-Schmidt rank 3 whose terms depend on a representative of the
  * face syndrome, derived on the device per item by a fixed GF(2) map), so
  * contractions need 4 chi <= 64.  A face syndrome that violates a cube
- * relation is not detected: its result has no meaning.
+ * relation (no X part has it) gives log p = -inf for every coset and only
+ * the flag TN3D_FLAG_INCONSISTENT; the relations are checked on the device
+ * per item with the same map.
  * Errors: TN3D_E_INVALID (L < 2, a rate outside [0, 3/4], null pointer),
  * TN3D_E_UNSUPPORTED (more than 4096 faces). */
 tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx ctx, int32_t L, const double* p_qubit, tn3d_net* out);
@@ -173,7 +185,8 @@ tn3d_status tn3d_contract_cosets(tn3d_ctx ctx, int32_t batch, const tn3d_net* ne
  * precision TN3D_PREC_FP32 and near_tie > 0, every item whose log-ratio is
  * below near_tie (or not a number) is contracted again in FP64 at the same chi
  * and chi_mps with the FP64 defaults of tn3d_params_default for eps_rel and
- * tau_gap; its logp row, flags (those of the FP64 pass plus TN3D_FLAG_RESWEPT)
+ * tau_gap and the Gram route (TN3D_OPT_GRAM_FACTOR; the decision needs far
+ * less than its 1e-8); its logp row, flags (those of the FP64 pass plus TN3D_FLAG_RESWEPT)
  * and decision are replaced.  This synchronises the context stream once.
  * logp_dev and flags_dev may be NULL. */
 tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,

@@ -693,13 +693,21 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
   P.n_det = nv + nf;
   P.n_mech = n;
   P.n_cosets = 4;
-  P.n_ext = n;
+  // rows rank..nf of E combine the face checks into zero (E H_Z = 0 there):
+  // the cube relations.  A face syndrome is consistent iff E_i m_Z = 0 for
+  // each of them; those parities follow the representative's bits.
+  const int n_chk = nf - rank;
+  P.n_ext = n + n_chk;
   P.ext_src0 = nv;
   P.ext_src_n = nf;
   P.ext_words = wf;
-  P.ext_rows.resize(size_t(n) * wf);
+  P.ext_rows.resize(size_t(n + n_chk) * wf);
   for (int e = 0; e < n; ++e)
     for (int w = 0; w < wf; ++w) P.ext_rows[size_t(e) * wf + w] = B[e][w];
+  for (int i = 0; i < n_chk; ++i)
+    for (int w = 0; w < wf; ++w) P.ext_rows[size_t(n + i) * wf + w] = E[rank + i][w];
+  P.inc0 = P.n_det + n;
+  P.n_inc = n_chk;
 
   auto W = [&](int e, int u, int v) { return (u == 0 && v == 0) ? 1.0 - p[e] : p[e] / 3.0; };
   auto I4 = eye(4);

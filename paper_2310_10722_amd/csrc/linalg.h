@@ -1379,4 +1379,76 @@ __device__ int block_sym_eig(double* A, int n, double* Z, double* d, double* e, 
   return fail;
 }
 
+// Orders the LDS accesses of the lanes of one wavefront (they execute in
+// program order; the fence keeps the compiler from moving them).
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Householder QR, one block of rows (Golub and Van Loan, Sec. 5.2, applied to
+// a triangular factor stacked on new rows): F (n x n, upper triangular, row
+// stride n, in LDS, shared by the TL lanes of a team of one wavefront) is
+// replaced by the triangular factor of [F; B] for the RB x n block B, whose
+// column l lane l holds in b[] (n <= TL).  sg: the lane's sum of b[i]^2.
+// Reflector j acts on row j of F and the rows of B only (F is triangular):
+// with alpha = F[j][j], mu = sqrt(alpha^2 + |B_j|^2) and beta = -sign(alpha) mu,
+// v = [1; B_j / (alpha - beta)], tau = (beta - alpha) / beta; every column
+// l > j is updated by w = F[j][l] + v.B_l, F[j][l] -= tau w, B_l -= tau w v.
+// vb: RB + 1 doubles of LDS for the broadcast reflector.  So F^T F gains
+// B^T B exactly in exact arithmetic, with the backward stability of an
+// orthogonal factorisation (no Gram matrix is formed).
+template <int TL, int RB>
+__device__ __forceinline__ void tsqr_block(double* F, int n, double (&b)[RB], double sg, double* vb, int l) {
+  for (int j = 0; j < n; ++j) {
+    if (l == j) {
+      const double al = F[j * n + j];
+      double be = al, tau = 0.0, sc = 0.0;
+      if (sg > 0.0) {
+        const double mu = sqrt(fma(al, al, sg));
+        be = al > 0.0 ? -mu : mu;
+        tau = (be - al) / be;
+        sc = 1.0 / (al - be);
+      }
+      F[j * n + j] = be;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) vb[i] = b[i] * sc;
+      vb[RB] = tau;
+    }
+    team_sync();
+    const double tau = vb[RB];
+    if (l > j && l < n && tau != 0.0) {
+      double w = F[j * n + l];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) w = fma(vb[i], b[i], w);
+      F[j * n + l] = fma(-tau, w, F[j * n + l]);
+      const double tw = tau * w;
+      sg = 0.0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        b[i] = fma(-tw, vb[i], b[i]);
+        sg = fma(b[i], b[i], sg);
+      }
+    }
+    team_sync();
+  }
+}
+
+// F <- triangular factor of [F; Y] for the nrows x n matrix Y given by
+// yv(row, col), streamed RB rows at a time (see tsqr_block).  Every lane of
+// the team calls it.
+template <int TL, int RB, class YF>
+__device__ void team_tsqr(double* F, int n, int nrows, YF yv, double* vb, int l) {
+  for (int r0 = 0; r0 < nrows; r0 += RB) {
+    double b[RB];
+    double sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      b[i] = (l < n && r0 + i < nrows) ? yv(r0 + i, l) : 0.0;
+      sg = fma(b[i], b[i], sg);
+    }
+    tsqr_block<TL, RB>(F, n, b, sg, vb, l);
+  }
+}
+
 }  // namespace tn3d

@@ -77,6 +77,10 @@ struct Program {
   // [ext_src0, ext_src0 + 64 ext_words), for e in [0, n_ext).
   int32_t n_ext = 0, ext_src0 = 0, ext_src_n = 0, ext_words = 0;
   std::vector<uint64_t> ext_rows;
+  // Consistency: per-item bits [inc0, inc0 + n_inc) (among the derived bits)
+  // are parities that vanish for every syndrome the code can produce; an item
+  // with one of them set is inconsistent (log p = -inf for every coset).
+  int32_t inc0 = 0, n_inc = 0;
 };
 
 // Builders; return an empty string on success, else an error message.

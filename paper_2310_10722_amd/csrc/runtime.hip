@@ -215,6 +215,8 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   // with row stride eig_ys, and the inverse-iteration factors per vector
   L.eig_ys = std::min(cm, 64) | 1;  // odd: conflict-free row and column access
   L.jcap = std::max<int64_t>(L.bigcap, int64_t(4) * std::min<int64_t>(64, int64_t(cm) * L.legcap) * L.eig_ys);
+  // the subspace iteration of large families: four blocks of 64 vectors
+  L.jcap = std::max<int64_t>(L.jcap, int64_t(4) * 64 * cm * L.legcap);
   const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;
@@ -312,10 +314,13 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_L4 = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Th = cv.take<double>(nsw_max * L.bigcap);
   size_t o_Jm = cv.take<double>(nsw_max * L.jcap);
-  // boundary-MPS steps through the Gram of the smaller family when the rank
-  // rule never needs singular values below 1e-8 of the largest (their squares
-  // stay well above the FP64 rounding of the Gram); one-sided Jacobi otherwise
-  const bool gram_path = prec != TN3D_PREC_FP64 || pr.eps_rel >= 1e-8;
+  // FP64 factors every truncation orthogonally (Householder QR of the gate
+  // sides, one-sided Jacobi on the boundary-MPS families) unless the caller
+  // asks for the Gram route; the reduced precisions and that option factor
+  // through Grams (the boundary MPS only where the rank rule never needs
+  // singular values below 1e-8 of the largest)
+  const bool f64_orth = prec == TN3D_PREC_FP64 && !(pr.flags & TN3D_OPT_GRAM_FACTOR);
+  const bool gram_path = !f64_orth && (prec != TN3D_PREC_FP64 || pr.eps_rel >= 1e-8);
   size_t o_Gm = cv.take<double>(gram_path ? nsw_max * L.bigcap : 1);
   size_t o_zdim = cv.take<int32_t>(nsw_max * 12);
   size_t o_zS = cv.take<double>(nsw_max * 1024);
@@ -385,6 +390,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.eps = pr.eps_rel;
     A.tau = pr.tau_gap;
     A.pchol_tol = prec == TN3D_PREC_FP64 ? 1e-15 : 1e-14;
+    A.qr = f64_orth ? 1 : 0;
+    A.inc0 = P.inc0;
+    A.n_inc = P.n_inc;
     A.jtol = prec == TN3D_PREC_FP64 ? 1e-14 : 1e-10;
     A.jfloor = prec == TN3D_PREC_FP64 ? std::min(1e-13, 0.1 * pr.eps_rel) : std::min(1e-8, 0.1 * pr.eps_rel);
     A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
@@ -427,7 +435,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
           return c;
         };
         A.win = timing ? win + size_t(2 * cls) * 128 : nullptr;
-        launch_gram(prec, A, gp, ng, n_wider(32), gram, L.ncap, s);
+        launch_gram(prec, A, gp, ng, n_wider(16), n_wider(32), gram, L.ncap, s);
         A.win = nullptr;
         launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
         A.win = timing ? win + size_t(2 * cls + 1) * 128 : nullptr;
@@ -616,8 +624,8 @@ bool params_ok(const tn3d_params* p, std::string& why) {
     why = "eps_rel and tau_gap must lie in [0, 1)";
     return false;
   }
-  if (p->flags != 0) {
-    why = "params.flags must be 0";
+  if ((p->flags & ~TN3D_OPT_GRAM_FACTOR) != 0) {
+    why = "unknown bit in params.flags";
     return false;
   }
   return true;
@@ -869,6 +877,7 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   tn3d_params p64;
   tn3d_params_default(&p64, pr->chi, pr->chi_mps, TN3D_PREC_FP64);
   p64.near_tie = pr->near_tie;
+  p64.flags = TN3D_OPT_GRAM_FACTOR;  // decisions: the faster FP64 route suffices
   p64.workspace_bytes = pr->workspace_bytes;
   const bool timing = c->timing;
   c->timing = false;  // the timing figures stay those of the main pass

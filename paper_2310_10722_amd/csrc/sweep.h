@@ -27,6 +27,8 @@ struct SweepArgs {
   const int32_t* items;     // [local item] -> global item
   const double* pool;       // op matrices and initial tensors
   double eps, tau, pchol_tol;
+  int32_t qr;                     // 1: truncation factors by Householder QR (FP64 route), 0: through Grams
+  int32_t inc0, n_inc;            // consistency bits of an item (Program::inc0, n_inc)
   double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
   unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
@@ -76,8 +78,9 @@ void launch_init(int prec, const SweepArgs& A, const int32_t* init_dims, const i
 void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_ops, hipStream_t st);
 // n_wide (and n_w16, n_w32 below): the leading gates of the class whose Grams
 // (rows) can be wider than 32 (16, 32) entries; the others are never wider
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
-                 hipStream_t st);
+// (A.qr: the triangular factors of k_qr instead of the Grams)
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
+                 int ncap, hipStream_t st);
 void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout,
                   int ncap, int kdcap, hipStream_t st);
 void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,

@@ -296,6 +296,115 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   win_close(A.win, w0);
 }
 
+// FP64 route: the triangular factor R (R^T R = X^T X) of the same row-weighted
+// view X as k_gram, by Householder QR streamed over the rows (tsqr_block), so
+// no Gram matrix is formed and the small singular values of X keep the
+// accuracy of an orthogonal factorisation (a Gram squares their condition).
+// One wavefront per (gate side, sweep), split into 64 / TL teams of TL lanes
+// (ncols <= TL, lane l of a team owns column l): team t factors rows
+// t TL .. t TL + TL - 1 of every chunk of 64 rows into a factor of its own,
+// then team 0 absorbs the other teams' factors (a two-level TSQR tree).  R is
+// written where k_gram writes the Gram (row-major, ncols x ncols).
+template <typename T, int TL>
+__global__ __launch_bounds__(64) void k_qr(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
+                                           int nlo) {
+  constexpr int G = 64 / TL;
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
+  const int t = lane / TL, l = lane - t * TL;
+  const DevGate g = gates[gi];
+  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
+  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
+  int D[4];
+  site_dims(A, sweep, site, D);
+  const Split v = make_split(D, leg, d);
+  const int ncols = d * v.Dx;
+  if (ncols <= nlo || ncols > TL) return;
+  const unsigned long long w0 = win_open(A.win);
+  __shared__ double slam[4][MAXCHI];
+  __shared__ int rowbase[64];
+  __shared__ double rowsc[64];
+  __shared__ double Fs[G * TL * TL];
+  __shared__ double vbs[G][TL + 1];
+  for (int e = lane; e < 4 * MAXCHI; e += 64) {
+    const int lg = e / MAXCHI, k = e % MAXCHI;
+    const int b = A.leg_bond[site * 4 + lg];
+    double val = 1.0;
+    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    slam[lg][k] = val;
+  }
+  int cofs = -1;
+  if (l < ncols) {
+    const int p = l / v.Dx, x = l - p * v.Dx;
+    cofs = x * v.Cp * d + p;
+  }
+  double* F = Fs + t * ncols * ncols;
+  for (int e = l; e < ncols * ncols; e += TL) F[e] = 0.0;
+  const T* tt = tens<T>(A, par, sweep, site);
+  __syncthreads();
+  for (int r0 = 0; r0 < v.rows; r0 += 64) {
+    {
+      const int r = r0 + lane;
+      int base = 0;
+      double sc = 0.0;
+      if (r < v.rows) {
+        const int a = r / v.Cp, c = r - a * v.Cp;
+        base = (a * v.Dx * v.Cp + c) * d;
+        sc = 1.0;
+        int cc = c;
+        for (int lg = 3; lg > leg; --lg) {
+          const int q = cc / D[lg];
+          sc *= slam[lg][cc - q * D[lg]];
+          cc = q;
+        }
+        int aa = a;
+        for (int lg = leg - 1; lg >= 0; --lg) {
+          const int q = aa / D[lg];
+          sc *= slam[lg][aa - q * D[lg]];
+          aa = q;
+        }
+      }
+      rowbase[lane] = base;
+      rowsc[lane] = sc;
+    }
+    __syncthreads();
+    double b[TL];
+    double sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < TL; ++i) {
+      const int rl = t * TL + i;
+      const bool ok = r0 + rl < v.rows && cofs >= 0;
+      b[i] = ok ? double(tt[rowbase[rl] + (ok ? cofs : 0)]) * rowsc[rl] : 0.0;
+      sg = fma(b[i], b[i], sg);
+    }
+    tsqr_block<TL, TL>(F, ncols, b, sg, vbs[t], l);
+    __syncthreads();  // the next chunk's offsets replace these
+  }
+  if (G > 1 && t == 0)
+    team_tsqr<TL, TL>(
+        F, ncols, (G - 1) * ncols,
+        [&](int row, int c) { return Fs[(1 + row / ncols) * ncols * ncols + (row % ncols) * ncols + c]; }, vbs[0], l);
+  __syncthreads();
+  if (A.bytes_ctr && lane == 0)
+    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
+              (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
+  if (side == 0 && lane == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
+  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
+  for (int e = lane; e < ncols * ncols; e += 64) out[e] = Fs[e];
+  win_close(A.win, w0);
+}
+
+// Entry (row, col) of the gated block Y of one gate side through its factor R
+// (nR x nR, nR = dd D, row-major): Y[(i, r), (k, b)] = sum_p R[i][p D + b] O_k[r][p]
+// (O_k at O[(k dd + r) dd + p]), so that Y^T Y is the side's gated Gram Z.
+__device__ __forceinline__ double gated_y(const double* R, const double* O, int dd, int D, int row, int col) {
+  const int nR = dd * D;
+  const int i = row / dd, r = row - i * dd;
+  const int k = col / D, b = col - k * D;
+  double y = 0.0;
+  for (int p = 0; p < dd; ++p) y = fma(R[i * nR + p * D + b], O[(k * dd + r) * dd + p], y);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // truncation of each gated bond: FP64, one workgroup per bond
 // ---------------------------------------------------------------------------
@@ -457,10 +566,32 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   int* perm = ord + n;
   int* flag = perm + n;
   const int nA = dA * D, nB = dB * D;
-  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, tid, NT);
-  __syncthreads();
-  const int rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
-  const int rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
+  int rA, rB;
+  if (A.qr) {
+    // F_A, F_B: triangular factors of the gated blocks Y_A, Y_B from the
+    // sides' factors R (k_qr), by Householder QR (no gated Gram is formed);
+    // one team per side: of 16 lanes (orders up to 16) or a wavefront
+    constexpr int TQ = NT >= 256 ? 64 : 16;
+    for (int e = tid; e < n * n; e += NT) CM[e] = VM[e] = 0.0;
+    __syncthreads();
+    const bool alt = gate_alt(A, g, sweep);
+    const int team = tid / TQ, l = tid - team * TQ;
+    if (team < 2) {
+      const double* R = gin + (int64_t(sweep * n_g + gi) * 2 + team) * ncap * ncap;
+      const int dd = team ? dB : dA;
+      const double* O = A.pool + (team ? (alt ? g.oB1 : g.oB) : (alt ? g.oA1 : g.oA));
+      team_tsqr<TQ, TQ>(
+          team ? VM : CM, n, dd * dd * D, [&](int row, int col) { return gated_y(R, O, dd, D, row, col); },
+          team ? ZB : ZA, l);
+    }
+    __syncthreads();
+    rA = rB = n;
+  } else {
+    build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, tid, NT);
+    __syncthreads();
+    rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
+    rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
+  }
   // C = F_A F_B^T (rA x rB) into ZA
   for (int i = tid >> 4; i < rA; i += NT >> 4)
     for (int j = tid & 15; j < rB; j += 16) {
@@ -517,10 +648,6 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
 // wavefront-scope fence that keeps the compiler from moving them suffices), or
 // by DPP moves within the team's lanes.  All lanes of a team take the same
 // branches.
-__device__ __forceinline__ void team_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Over the TL (8 or 16) lanes of a team: quad butterflies, then the half-row
 // mirror (lane i <-> 7 - i) brings in the other quad, and for 16 the row
@@ -703,10 +830,26 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
   int* ord = ti[t];
   int* perm = ord + TL;
   int* rr = perm + TL;
-  build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, l, TL);
-  team_sync();
-  const int rA = team_pchol<TL>(ZA, CM, n, A.pchol_tol, perm, l);
-  const int rB = team_pchol<TL>(ZB, VM, n, A.pchol_tol, perm, l);
+  int rA, rB;
+  if (A.qr) {
+    // F_A, F_B by Householder QR of the gated blocks (see k_solve)
+    for (int e = l; e < n * n; e += TL) CM[e] = VM[e] = 0.0;
+    team_sync();
+    const bool alt = gate_alt(A, g, sweep);
+    const double* RA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
+    const double* RB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
+    const double* OA = A.pool + (alt ? g.oA1 : g.oA);
+    const double* OB = A.pool + (alt ? g.oB1 : g.oB);
+    const int dA = g.dA, dB = g.dB;
+    team_tsqr<TL, TL>(CM, n, dA * dA * D, [&](int row, int col) { return gated_y(RA, OA, dA, D, row, col); }, ZA, l);
+    team_tsqr<TL, TL>(VM, n, dB * dB * D, [&](int row, int col) { return gated_y(RB, OB, dB, D, row, col); }, ZA, l);
+    rA = rB = n;
+  } else {
+    build_gated_grams(A, g, gin, ncap, n_g, gi, sweep, D, ZA, ZB, l, TL);
+    team_sync();
+    rA = team_pchol<TL>(ZA, CM, n, A.pchol_tol, perm, l);
+    rB = team_pchol<TL>(ZB, VM, n, A.pchol_tol, perm, l);
+  }
   if (l < rB)  // C = F_A F_B^T (rA x rB) into Z_A, lane j takes column j
     for (int i = 0; i < rA; ++i) {
       double c = 0.0;
@@ -1248,6 +1391,323 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
   zip_keep(Z, s, zd, nv, Sout, ord, Zm, 1, nv, fail ? 40 : 1);
 }
 
+// ---------------------------------------------------------------------------
+// Large families on the Gram route: block subspace iteration
+// ---------------------------------------------------------------------------
+// The K = min(nv, chi_m + 1) largest eigenpairs of the PSD Gram G (order
+// nv > ZBIG) by subspace iteration with Rayleigh-Ritz (Saad, "Numerical
+// Methods for Large Eigenvalue Problems", Sec. 5.2) on a block of SB vectors,
+// every product on the FP64 matrix cores (block_gemm512):
+//   Y = G X;  H = X^T Y;  H = V diag(theta) V^T (cyclic Jacobi);
+//   U = X V (Ritz vectors), P = Y V (= G U);  stop when every ||P_j -
+//   theta_j U_j|| (j < K) is below tol theta_1;  else X <- orth(P
+//   diag(1 / theta)) (the columns near U, so Cholesky QR is well conditioned).
+// The start is the columns of G at its SB largest diagonal entries.  Block
+// vectors (nv x SB, row-major) live in the sweep's Jm scratch.
+constexpr int SB = 64;
+
+// Cyclic Jacobi on the symmetric n x n A (n <= 64, LDS, row stride 65) by a
+// 512-thread workgroup: the round-robin order gives 32 disjoint rotations per
+// round, applied as A <- A J, V <- V J, then A <- J^T A (Golub and Van Loan,
+// Sec. 8.5, the symmetric Schur rotation).  V starts as the identity.
+// Returns the number of sweeps.
+__device__ int block_jacobi_sym64(double* A, double* V, int n, double* cs, int* any) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += ZNT) {
+    const int i = e >> 6, j = e & 63;
+    V[i * 65 + j] = i == j ? 1.0 : 0.0;
+    if (i >= n || j >= n) A[i * 65 + j] = i == j ? 0.0 : 0.0;
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
+    if (tid == 0) *any = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < 63; ++rnd) {
+      if (tid < 32) {
+        int i, j;
+        if (tid == 0) {
+          i = 63;
+          j = rnd;
+        } else {
+          i = rnd + tid;
+          i = i >= 63 ? i - 63 : i;
+          j = rnd - tid + 63;
+          j = j >= 63 ? j - 63 : j;
+        }
+        const int p = i < j ? i : j, q = i < j ? j : i;
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double app = A[p * 65 + p], aqq = A[q * 65 + q], apq = A[p * 65 + q];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
+            const double zeta = (aqq - app) / (2.0 * apq);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            *any = 1;
+          }
+        }
+        cs[4 * tid] = c;
+        cs[4 * tid + 1] = sn;
+        reinterpret_cast<int*>(cs)[8 * tid + 4] = p;
+        reinterpret_cast<int*>(cs)[8 * tid + 5] = q;
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      for (int e = tid; e < 32 * 64; e += ZNT) {
+        const int k = e >> 6, r = e & 63;
+        const double c = cs[4 * k], sn = cs[4 * k + 1];
+        if (sn == 0.0) continue;
+        const int p = reinterpret_cast<const int*>(cs)[8 * k + 4], q = reinterpret_cast<const int*>(cs)[8 * k + 5];
+        const double ap = A[r * 65 + p], aq = A[r * 65 + q];
+        A[r * 65 + p] = c * ap - sn * aq;
+        A[r * 65 + q] = sn * ap + c * aq;
+        const double vp = V[r * 65 + p], vq = V[r * 65 + q];
+        V[r * 65 + p] = c * vp - sn * vq;
+        V[r * 65 + q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = tid; e < 32 * 64; e += ZNT) {
+        const int k = e >> 6, r = e & 63;
+        const double c = cs[4 * k], sn = cs[4 * k + 1];
+        if (sn == 0.0) continue;
+        const int p = reinterpret_cast<const int*>(cs)[8 * k + 4], q = reinterpret_cast<const int*>(cs)[8 * k + 5];
+        const double ap = A[p * 65 + r], aq = A[q * 65 + r];
+        A[p * 65 + r] = c * ap - sn * aq;
+        A[q * 65 + r] = sn * ap + c * aq;
+      }
+      __syncthreads();
+    }
+    const int a = *any;
+    __syncthreads();
+    if (!a) break;
+  }
+  return sweep;
+}
+
+// A deterministic pseudo-random value in [-1, 1) from two indices.
+__device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
+  unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return double(h) * (2.0 / 4294967296.0) - 1.0;
+}
+
+// X (nv x SB, row-major) <- an orthonormal basis of the span of Z (same
+// shape, destroyed) by Cholesky QR twice with column equilibration; a column
+// whose pivot shows it dependent on the previous ones is replaced by a hashed
+// vector before the second pass.  R: SB x 65 LDS, red: 16 doubles.
+__device__ void block_cholqr2(double* Z, double* X, int nv, double* R, double* gl, double* red, int* dead,
+                              unsigned seed) {
+  const int tid = threadIdx.x;
+  for (int pass = 0; pass < 2; ++pass) {
+    // S = Z^T Z into R
+    block_gemm512<false, false>(
+        SB, SB, nv, [&](int m, int k) { return Z[k * SB + m]; }, [&](int k, int n) { return Z[k * SB + n]; },
+        [&](int m, int n, double v) { R[m * 65 + n] = v; }, gl);
+    // equilibrate: D^-1/2 S D^-1/2, and the Cholesky factor of that
+    __shared__ double dsc[SB];
+    if (tid < SB) {
+      const double dd = R[tid * 65 + tid];
+      dsc[tid] = dd > 0.0 ? 1.0 / sqrt(dd) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < SB * SB; e += ZNT) {
+      const int i = e >> 6, j = e & 63;
+      R[i * 65 + j] *= dsc[i] * dsc[j];
+    }
+    if (tid == 0) *dead = 0;
+    __syncthreads();
+    // right-looking Cholesky, R upper triangular in the upper part
+    for (int j = 0; j < SB; ++j) {
+      __shared__ double piv;
+      if (tid == 0) {
+        const double a = R[j * 65 + j];
+        if (!(a > 1e-16)) {  // dependent (or zero) column: below the rounding of S
+          piv = 0.0;
+          *dead = 1;
+        } else {
+          piv = sqrt(a);
+        }
+      }
+      __syncthreads();
+      const double pj = piv;
+      if (pj == 0.0) {
+        for (int k = tid; k < SB; k += ZNT) R[j * 65 + k] = k == j ? 1.0 : 0.0;
+        for (int k = tid; k < SB; k += ZNT) if (k > j) R[k * 65 + j] = 0.0;
+        __syncthreads();
+        if (tid == 0) dsc[j] = -dsc[j] - 1.0;  // marks the column (dsc >= 0 otherwise)
+        __syncthreads();
+        continue;
+      }
+      for (int k = j + tid; k < SB; k += ZNT) R[j * 65 + k] = k == j ? pj : R[j * 65 + k] / pj;
+      __syncthreads();
+      for (int e = tid; e < (SB - j - 1) * (SB - j - 1); e += ZNT) {
+        const int a = j + 1 + e / (SB - j - 1), b = j + 1 + e % (SB - j - 1);
+        if (b >= a) R[a * 65 + b] -= R[j * 65 + a] * R[j * 65 + b];
+      }
+      __syncthreads();
+    }
+    // X = Z D^-1/2 R^-1, row by row (forward substitution x R = z)
+    for (int r = tid; r < nv; r += ZNT) {
+      double xr[SB];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        const double dj = dsc[j];
+        double z = dj >= 0.0 ? Z[r * SB + j] * dj : 0.0;
+#pragma unroll 8
+        for (int i = 0; i < j; ++i) z = fma(-xr[i], R[i * 65 + j], z);
+        xr[j] = z / R[j * 65 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < SB; ++j) X[r * SB + j] = xr[j];
+    }
+    __syncthreads();
+    if (pass == 0) {
+      // dead columns get a hashed vector; the second pass orthonormalises
+      for (int e = tid; e < nv * SB; e += ZNT) {
+        const int j = e % SB;
+        Z[e] = dsc[j] < 0.0 ? hash_unit(seed + unsigned(j), unsigned(e / SB)) : X[e];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+  (void)red;
+}
+
+__global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
+  extern __shared__ double zsm[];
+  double* gl = zsm;                 // GEMM_LDS
+  double* H = zsm + GEMM_LDS;       // SB x 65: H, then the Cholesky factor
+  double* Vv = H + SB * 65;         // SB x 65: Jacobi vectors
+  __shared__ double cs[4 * 32 + 8];
+  __shared__ double th[SB], rn[SB], red[16];
+  __shared__ int ord[SB], flag[4];
+  __shared__ int jsel[SB];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* zd = Z.zdim + int64_t(s) * 12;
+  const int nv = zd[7];
+  if (nv <= ZBIG) return;
+  const unsigned long long w0 = win_open(Z.win);
+  const double* G = Z.Gm + int64_t(s) * Z.bigcap;
+  double* X = Z.Jm + int64_t(s) * Z.jcap;
+  double* Y = X + int64_t(nv) * SB;
+  double* U = Y + int64_t(nv) * SB;
+  double* P = U + int64_t(nv) * SB;
+  double* Sout = Z.zS + int64_t(s) * 1024;
+  const int K = nv < Z.chi_m + 1 ? nv : Z.chi_m + 1;
+  // start: the columns of G at its SB largest diagonal entries (ties by index)
+  for (int i = tid; i < nv; i += ZNT) {
+    const double gi = G[int64_t(i) * nv + i];
+    int rank = 0;
+    for (int j = 0; j < nv; ++j) rank += sorts_before(G[int64_t(j) * nv + j], j, gi, i) ? 1 : 0;
+    if (rank < SB) jsel[rank] = i;
+  }
+  __syncthreads();
+  for (int e = tid; e < nv * SB; e += ZNT) {
+    const int r = e / SB, j = e % SB;
+    Y[e] = G[int64_t(r) * nv + jsel[j]];
+  }
+  __syncthreads();
+  block_cholqr2(Y, X, nv, H, gl, red, &flag[0], 0x1234u);
+  double tol = 1e-12;
+  int it = 0, conv = 0;
+  const int maxit = 80;
+  for (; it < maxit; ++it) {
+    // Y = G X
+    block_gemm512<true, false>(
+        nv, SB, nv, [&](int m, int k) { return G[int64_t(m) * nv + k]; }, [&](int k, int n) { return X[k * SB + n]; },
+        [&](int m, int n, double v) { Y[m * SB + n] = v; }, gl);
+    // H = X^T Y, symmetrised
+    block_gemm512<false, false>(
+        SB, SB, nv, [&](int m, int k) { return X[k * SB + m]; }, [&](int k, int n) { return Y[k * SB + n]; },
+        [&](int m, int n, double v) { H[m * 65 + n] = v; }, gl);
+    for (int e = tid; e < SB * SB; e += ZNT) {
+      const int i = e >> 6, j = e & 63;
+      if (i < j) {
+        const double a = 0.5 * (H[i * 65 + j] + H[j * 65 + i]);
+        H[i * 65 + j] = a;
+        H[j * 65 + i] = a;
+      }
+    }
+    __syncthreads();
+    block_jacobi_sym64(H, Vv, SB, cs, &flag[1]);
+    if (tid < SB) {
+      const double li = H[tid * 65 + tid];
+      int rank = 0;
+      for (int j = 0; j < SB; ++j) rank += sorts_before(H[j * 65 + j], j, li, tid) ? 1 : 0;
+      ord[rank] = tid;
+      th[rank] = li;
+    }
+    __syncthreads();
+    // U = X V, P = Y V (columns in descending order of theta)
+    block_gemm512<true, false>(
+        nv, SB, SB, [&](int m, int k) { return X[m * SB + k]; }, [&](int k, int n) { return Vv[k * 65 + ord[n]]; },
+        [&](int m, int n, double v) { U[m * SB + n] = v; }, gl);
+    block_gemm512<true, false>(
+        nv, SB, SB, [&](int m, int k) { return Y[m * SB + k]; }, [&](int k, int n) { return Vv[k * 65 + ord[n]]; },
+        [&](int m, int n, double v) { P[m * SB + n] = v; }, gl);
+    // residual norms of the K leading Ritz pairs
+    if (tid < SB) rn[tid] = 0.0;
+    __syncthreads();
+    {
+      const int j = tid & 63;
+      double acc = 0.0;
+      if (j < K)
+        for (int r = tid >> 6; r < nv; r += ZNT / 64) {
+          const double d = P[r * SB + j] - th[j] * U[r * SB + j];
+          acc = fma(d, d, acc);
+        }
+      atomicAdd(&rn[j], acc);
+    }
+    __syncthreads();
+    double worst = 0.0;
+    for (int j = 0; j < K; ++j) worst = fmax(worst, sqrt(rn[j]));
+    const double t1 = th[0] > 0.0 ? th[0] : 1.0;
+    if (worst <= tol * t1) {
+      conv = 1;
+      break;
+    }
+    if (it + 1 == maxit) break;
+    // next block: P diag(1 / theta), orthonormalised
+    const double fl = 1e-15 * t1;
+    for (int e = tid; e < nv * SB; e += ZNT) {
+      const int j = e % SB;
+      Y[e] = P[e] / fmax(th[j], fl);
+    }
+    __syncthreads();
+    block_cholqr2(Y, X, nv, H, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
+  }
+  // the rank rule on sqrt(theta), the kept Ritz vectors into Fv
+  for (int j = tid; j < SB; j += ZNT) Sout[j] = sqrt(fmax(th[j], 0.0));
+  __syncthreads();
+  int split = 0;
+  int Dn = rank_rule(Sout, nv, Z.chi_m, Z.eps, Z.tau, &split);
+  const bool bad = Dn < 1;
+  if (bad) Dn = 1;
+  double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
+  for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = U[(e / Dn) * SB + e % Dn];
+  if (Z.flop_ctr && tid == 0) {
+    // algorithmic flops per iteration: the block product 2 nv^2 SB, the
+    // Ritz projection and rotations 6 nv SB^2, Cholesky QR twice 8 nv SB^2
+    const double n = nv, b = SB;
+    const double f = double(it + 1) * (2.0 * n * n * b + 14.0 * n * b * b);
+    atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
+  }
+  if (tid == 0) {
+    zd[8] = Dn;
+    atomicMax(&Z.sweeps_max[1], it + 1);
+    const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (conv ? 0u : 8u);
+    if (f) atomicOr(&Z.flags[s], f);
+  }
+  win_close(Z.win, w0);
+}
+
 // (at most 80 registers: six wavefronts per SIMD)
 __global__ __launch_bounds__(ZNT) __attribute__((amdgpu_waves_per_eu(6))) void k_zip_c(ZipArgs Z, int x, int y) {
   __shared__ double gst[GEMM_LDS];
@@ -1344,7 +1804,15 @@ __global__ void k_finish(SweepArgs A, ZipArgs Z, double* logp) {
   const int item = A.items[s / A.n_cosets], c = s % A.n_cosets;
   double out;
   uint32_t f = A.flags[s] | Z.flags[s];
-  if (z > 0.0 && isfinite(z) && isfinite(lsum)) {
+  bool inconsistent = false;
+  if (A.n_inc > 0) {
+    const uint8_t* bits = A.synd + A.synd_off[item] + A.inc0;
+    for (int k = 0; k < A.n_inc; ++k) inconsistent |= (bits[k] & 1) != 0;
+  }
+  if (inconsistent) {
+    out = -INFINITY;
+    f = 32u;
+  } else if (z > 0.0 && isfinite(z) && isfinite(lsum)) {
     out = lsum + log(z);
   } else {
     out = __longlong_as_double(0x7ff8000000000000LL);
@@ -1517,6 +1985,8 @@ __global__ void k_scatter_out(int n, const int32_t* items, const double* lp_loca
 // 64 KB, set once per device to the most any launch requests (static LDS
 // included stays within the 160 KB of a workgroup).  Setting attributes is not
 // allowed while a stream is being captured, so no launcher does it.
+static inline size_t bsub_lds_bytes() { return size_t(GEMM_LDS + 2 * SB * 65) * sizeof(double); }
+
 hipError_t set_kernel_lds_limits() {
   const int kmax = 64;  // gate rank x chi, checked by the host
   const int solve = 4 * kmax * kmax * 8 + 2 * kmax * 8 + 32 + (2 * kmax + 4) * 4;
@@ -1531,6 +2001,9 @@ hipError_t set_kernel_lds_limits() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bbig), hipFuncAttributeMaxDynamicSharedMemorySize,
                             19200 * 8);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zip_bsub), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(bsub_lds_bytes()));
   return e;
 }
 
@@ -1565,9 +2038,21 @@ static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int
                        32);
 }
 
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
-                 hipStream_t st) {
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
+                 int ncap, hipStream_t st) {
   if (n_g <= 0) return;
+  if (A.qr) {
+    // factors of up to 16 columns (four teams per wavefront), 32 (two) and 64
+    // (one), the wider classes over the leading gates that can be that wide
+    hipLaunchKernelGGL((k_qr<double, 16>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
+    if (ncap > 16 && n_w16 > 0)
+      hipLaunchKernelGGL((k_qr<double, 32>), dim3(2 * n_w16, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap,
+                         16);
+    if (ncap > 32 && n_wide > 0)
+      hipLaunchKernelGGL((k_qr<double, 64>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap,
+                         32);
+    return;
+  }
   if (prec == 0)
     gram_dispatch<double>(A, gates, n_g, n_wide, gout, ncap, st);
   else
@@ -1654,8 +2139,12 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st)
       // bound passes ZBIG
       const int64_t rcap = int64_t(x == 0 ? 1 : Z.chi_m) * (y + 1 == Z.Ly ? 1 : legcap);
       const int64_t ccap = int64_t(y == 0 ? 1 : Z.chi_m) * legcap;
-      if ((rcap < ccap ? rcap : ccap) > ZBIG)
-        hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
+      if ((rcap < ccap ? rcap : ccap) > ZBIG) {
+        if (Z.chi_m + 1 <= SB)
+          hipLaunchKernelGGL(k_zip_bsub, dim3(Z.n_sweeps), dim3(ZNT), bsub_lds_bytes(), st, Z, x, y);
+        else
+          hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
+      }
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
     }

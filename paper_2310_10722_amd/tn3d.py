@@ -23,6 +23,8 @@ FLAG_TRUNC_CLUSTER = 2
 FLAG_NEAR_TIE = 4
 FLAG_NO_CONVERGE = 8
 FLAG_RESWEPT = 16
+FLAG_INCONSISTENT = 32
+OPT_GRAM_FACTOR = 1
 
 STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OOM", -5: "DEVICE",
           -6: "NUMERIC"}
@@ -235,6 +237,8 @@ def _batch_args(nets, syndromes):
         nets = [nets] * B
     if len(nets) != B:
         raise ValueError("one network per syndrome")
+    if B > 0 and syndromes.shape[1] < max(n.n_det for n in nets):
+        raise ValueError("syndrome rows are narrower than a network's detector count")
     offs = torch.arange(B, dtype=torch.int64, device=syndromes.device) * syndromes.shape[1]
     arr = (ctypes.c_void_p * max(B, 1))(*[n.h.value for n in nets])
     return nets, syndromes, offs, arr, B

@@ -48,9 +48,9 @@ def gpu_logp(ctx, net, m, prm):
     return logp.cpu().numpy(), flags.cpu().numpy()
 
 
-def oracle(L, p, m, prm):
+def oracle(L, p, m, prm, driver="gesdd"):
     return np.array([[sweep_logprob(depol3d_network(L, p, m[k], c), prm.chi, prm.chi_mps, prm.eps_rel,
-                                    prm.tau_gap)[0] for c in range(4)] for k in range(m.shape[0])])
+                                    prm.tau_gap, svd_driver=driver)[0] for c in range(4)] for k in range(m.shape[0])])
 
 
 def check(got, ref, tol_top, tol_all):
@@ -88,7 +88,7 @@ def test_depol_L3_chi4_fp64(ctx):
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     ok = np.all(np.isfinite(ref), axis=1)
     assert np.all(flags[~ok] & 1)
-    check(got[ok], ref[ok], 1e-9, 1e-7)
+    check(got[ok], ref[ok], 1e-9, 1e-9)
 
 
 def test_depol_L3_chi16_and_exact(ctx):
@@ -108,7 +108,7 @@ def test_depol_L3_chi16_and_exact(ctx):
     prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle(3, dem.params["p_qubit"], m, prm)
-    check(got, ref, 1e-9, 1e-7)
+    check(got, ref, 1e-9, 1e-9)
     exact = np.array(gold["logp"])
     best = np.argmax(exact, axis=1)
     ex = np.abs(got[:3] - exact)
@@ -128,15 +128,16 @@ def test_depol_L4_chi8(ctx, mode):
         prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle(4, dem.params["p_qubit"], m, prm)
-    # FP64 default rule at L = 4: 8.5e-9 / 4.1e-8 measured, while the oracle
-    # under two LAPACK SVD drivers agrees with itself to 1e-12, so this gap is
-    # the library's (its gate truncations factor the site tensors through
-    # their Grams, which squares the condition of the smallest kept values)
-    check(got, ref, *{"fp64_default": (1e-7, 1e-6), "fp64_reduced": (1e-6, 1e-4), "fp32_reduced": (1e-3, 0.5)}[mode])
+    check(got, ref, *{"fp64_default": (1e-9, 1e-9), "fp64_reduced": (1e-9, 1e-9), "fp32_reduced": (1e-3, 0.5)}[mode])
 
 
 def test_depol_L4_chi16_nonuniform(ctx):
-    """chi = chi_m = 16 at L = 4 with per-qubit rates drawn in [0.05, 0.2]."""
+    """chi = chi_m = 16 at L = 4 with per-qubit rates drawn in [0.05, 0.2].
+    Here the FP64 rounding of the problem itself reaches the nanonat: the
+    oracle under two LAPACK SVD drivers (divide and conquer, QR iteration)
+    differs by up to 4e-9 on a minority coset.  Every value must be within
+    1e-9 of the oracle or within twice that driver spread of it, whichever is
+    larger."""
     from paper_2310_10722_amd import tn3d
     say("case: depolarizing L=4 chi=16 fp64 reduced rule, non-uniform rates, 4 syndromes")
     n = 4 ** 3 + 2 * 4 * 9
@@ -147,7 +148,12 @@ def test_depol_L4_chi16_nonuniform(ctx):
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle(4, rates, m, prm)
-    check(got, ref, 1e-6, 1e-4)
+    spread = np.abs(oracle(4, rates, m, prm, driver="gesvd") - ref)
+    err = np.abs(got - ref)
+    say("  max |d log p|", err.max(), " oracle driver spread", spread.max())
+    assert np.all(err <= np.maximum(1e-9, 2.0 * spread))
+    top = np.argmax(ref, axis=1)
+    assert err[np.arange(len(ref)), top].max() <= 1e-9
 
 
 def test_depol_L6_chi8_sampled(ctx):
@@ -167,7 +173,7 @@ def test_depol_L6_chi8_sampled(ctx):
     ref = oracle(6, dem.params["p_qubit"], m[pick], prm)
     ok = np.all(np.isfinite(ref), axis=1)
     assert np.all(flags[pick][~ok] & 1)
-    check(got[pick][ok], ref[ok], 1e-6, 1e-4)
+    check(got[pick][ok], ref[ok], 1e-9, 1e-9)
 
 
 def test_depol_ragged_decode_eager_and_graph(ctx):
@@ -205,7 +211,7 @@ def test_depol_ragged_decode_eager_and_graph(ctx):
     for i in range(8):
         L, dem, m = (3, d3, m3[i // 2]) if i % 2 == 0 else (4, d4, m4[i // 2])
         ref = oracle(L, dem.params["p_qubit"], m[None], prm)[0]
-        check(logp[i][None], ref[None], 1e-7, 1e-6)
+        check(logp[i][None], ref[None], 1e-9, 1e-9)
         srt = np.sort(ref)
         assert int(coset[i]) == int(np.argmax(ref)) or srt[-1] - srt[-2] <= 2e-9
         assert float(lr[i]) == pytest.approx(srt[-1] - srt[-2], abs=1e-8)
@@ -219,3 +225,26 @@ def test_depol_chi24_refused(ctx):
     prm = tn3d.tn3d_params_default(24, 24, tn3d.PREC_FP32)
     with pytest.raises(tn3d.Tn3dError, match="UNSUPPORTED"):
         gpu_logp(ctx, net, m, prm)
+
+
+def test_depol_inconsistent_face_syndrome(ctx):
+    """A face syndrome that breaks a cube relation has no error pattern: the
+    oracle refuses it, the library returns -inf for every coset with only the
+    INCONSISTENT flag; the consistent items of the same call are unaffected."""
+    from paper_2310_10722_amd import tn3d
+    say("case: depolarizing L=3 inconsistent face syndrome, chi=4 fp64")
+    dem, m, _ = workload(3, 4, seed=41)
+    bad = m.copy()
+    nv = 3 * 3 * 2
+    bad[1, nv + 5] ^= 1
+    bad[3, nv + 20] ^= 1
+    with pytest.raises(ValueError):
+        depol3d_network(3, dem.params["p_qubit"], bad[1], 0)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 3, dem.params["p_qubit"])
+    prm = tn3d.tn3d_params_default(4, 4, tn3d.PREC_FP64)
+    got, flags = gpu_logp(ctx, net, bad, prm)
+    for i in (1, 3):
+        assert np.all(np.isneginf(got[i])) and flags[i] == tn3d.FLAG_INCONSISTENT
+    ref = oracle(3, dem.params["p_qubit"], bad[[0, 2]], prm)
+    check(got[[0, 2]], ref, 1e-9, 1e-9)
+    assert np.all(flags[[0, 2]] & tn3d.FLAG_INCONSISTENT == 0)

@@ -1,10 +1,11 @@
 """GPU parity: the HIP sweep (through the C-ABI) against the CPU oracle.
 
 Tolerances: FP64 path |d log p| <= 1e-9 against the fixed-chi oracle at the
-same chi / chi_m / rank rule (the default FP64 rule, Jacobi everywhere);
-FP64 with the reduced-precision rule that the benchmark times (Gram route in
-the boundary MPS) <= 1e-6; FP32 path |d log p| <= 1e-3 against the same
-oracle; untruncated chi against the exact frontier contraction <= 1e-9.
+same chi / chi_m / rank rule, for every rule (the FP64 route factors every
+truncation orthogonally: Householder QR of the gate sides, one-sided Jacobi
+on the boundary-MPS families); the FP64 Gram route (TN3D_OPT_GRAM_FACTOR)
+<= 1e-6; FP32 path |d log p| <= 1e-3 against the same oracle; untruncated chi
+against the exact frontier contraction <= 1e-9.
 """
 
 import sys
@@ -46,10 +47,10 @@ def oracle_point(dem, L, m, prm):
                                     prm.tau_gap)[0] for c in range(2)] for k in range(m.shape[0])])
 
 
-def oracle_rot(dem, m, prm):
+def oracle_rot(dem, m, prm, driver="gesdd"):
     d, T = dem.params["d"], dem.params["T"]
     return np.array([[sweep_logprob(rotated_network(d, T, dem.params["checks"], dem.p, m[k], c), prm.chi,
-                                    prm.chi_mps, prm.eps_rel, prm.tau_gap)[0] for c in range(2)]
+                                    prm.chi_mps, prm.eps_rel, prm.tau_gap, svd_driver=driver)[0] for c in range(2)]
                      for k in range(m.shape[0])])
 
 
@@ -124,25 +125,29 @@ def test_rotated_d5_fp32_chi16(ctx):
     assert err.max() <= 1e-3
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64_gram", "fp32"])
 def test_rotated_d5_boundary_chi32_gram_route(ctx, prec):
     """chi_m = 32 with the reduced-precision rule (eps_rel 1e-6, tau_gap 1e-4),
-    so the boundary MPS takes the Gram route: the interior steps reach Gram
-    orders 96 to 128 (measured on the oracle for this workload) and take the
-    512-thread decomposition, the first and last rows and the first column stay
-    on the one-wavefront solver (Jacobi up to order 16, tridiagonal above).
-    Bounds as for chi_m = 16: 1e-6 in FP64 (the Gram route), 1e-3 in FP32."""
+    so FP32 (and FP64 with the Gram option) takes the Gram route in the
+    boundary MPS: the interior steps reach Gram orders 96 to 128 (measured on
+    the oracle for this workload) and take the 512-thread decomposition, the
+    first and last rows and the first column stay on the one-wavefront solver
+    (Jacobi up to order 16, tridiagonal above).  FP64 without the option
+    decomposes the families by one-sided Jacobi.  Bounds: 1e-9 in FP64,
+    1e-6 on the FP64 Gram route, 1e-3 in FP32."""
     from paper_2310_10722_amd import tn3d
     say(f"case: rotated d=5 T=5 chi=16 chi_m=32 {prec}, rule 1e-6/1e-4, 6 syndromes")
     dem, m, _, _ = synth.config_workload(2, n=6)
     net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
-    prm = tn3d.tn3d_params_default(16, 32, tn3d.PREC_FP64 if prec == "fp64" else tn3d.PREC_FP32)
+    prm = tn3d.tn3d_params_default(16, 32, tn3d.PREC_FP32 if prec == "fp32" else tn3d.PREC_FP64)
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    if prec == "fp64_gram":
+        prm.flags = tn3d.OPT_GRAM_FACTOR
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle_rot(dem, m, prm)
     err = np.abs(got[:, :2] - ref)
     say("  max |d log p| =", err.max())
-    assert err.max() <= (1e-6 if prec == "fp64" else 1e-3)
+    assert err.max() <= {"fp64": 1e-9, "fp64_gram": 1e-6, "fp32": 1e-3}[prec]
 
 
 @pytest.mark.parametrize("mode", ["fp64_default", "fp64_reduced", "fp32_reduced"])
@@ -154,8 +159,7 @@ def test_point_L5_chi32_golden(ctx, mode):
     FP64 default rule, the 512-thread Gram decomposition above 64 on the
     reduced one).  Against stored oracle values
     (tests/golden/make_point_L5_chi32.py, which calls only the oracle).  Bounds
-    as for the other workloads: 1e-9 (FP64 default rule), 1e-6 (Gram route),
-    1e-3 (FP32)."""
+    as for the other workloads: 1e-9 (FP64, either rule), 1e-3 (FP32)."""
     import json
     import os
     from paper_2310_10722_amd import tn3d
@@ -172,7 +176,7 @@ def test_point_L5_chi32_golden(ctx, mode):
     got, _ = gpu_logp(ctx, net, m, prm)
     err = np.abs(got[:, :2] - ref)
     say("  max |d log p| =", err.max())
-    assert err.max() <= {"fp64_default": 1e-9, "fp64_reduced": 1e-6, "fp32_reduced": 1e-3}[mode]
+    assert err.max() <= {"fp64_default": 1e-9, "fp64_reduced": 1e-9, "fp32_reduced": 1e-3}[mode]
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32"])
@@ -186,7 +190,10 @@ def test_rotated_d7_nonuniform_rates(ctx, mode):
     singular values, and the oracle's own values miss the exact ones by up to
     1.5 nats, while the reduced rule stays within the chi = 16 truncation
     error (at most 0.15 nats on the items checked against the exact
-    contraction).  FP64: every coset within 1e-6 (the Gram route).  FP32: the
+    contraction).  FP64: every coset within 1e-9 of the oracle or within
+    twice the oracle's own spread under two LAPACK SVD drivers (divide and
+    conquer, QR iteration), whichever is larger: on this workload the FP64
+    rounding of the problem itself reaches 8e-8 on minority cosets.  FP32: the
     majority coset within 1e-3 and the same decision; the minority coset, 10
     to 17 nats lower and carried by singular values that FP32 site tensors
     resolve poorly, measured up to 0.13 off and held to a sanity bound of
@@ -203,7 +210,9 @@ def test_rotated_d7_nonuniform_rates(ctx, mode):
     err = np.abs(got[:, :2] - ref)
     say("  max |d log p| =", err.max())
     if mode == "fp64":
-        assert err.max() <= 1e-6
+        spread = np.abs(oracle_rot(dem, m, prm, driver="gesvd") - ref)
+        say("  oracle driver spread", spread.max())
+        assert np.all(err <= np.maximum(1e-9, 2.0 * spread))
     else:
         maj = np.argmax(ref, axis=1)
         rows = np.arange(len(maj))
@@ -317,12 +326,9 @@ def test_rotated_d5_full_batch_sampled(ctx):
 
 def test_rotated_d5_full_batch_headline_fp64(ctx):
     """The benchmark's timed configuration: the full 1024-syndrome batch,
-    FP64 site tensors, rank rule eps_rel 1e-6 / tau_gap 1e-4 (the boundary MPS
-    then takes the Gram route), one decode call with graph replay.  Sampled
-    items against the oracle at the same chi and rule.  Bound 1e-6: the Gram
-    route keeps the kept singular values to about eps_64 / eps_rel^2 relative
-    (5e-5 for the smallest, far less for the large ones that carry log p); the
-    measured maximum over the whole batch is below 1e-7."""
+    FP64 site tensors, rank rule eps_rel 1e-6 / tau_gap 1e-4, one decode call
+    with graph replay.  Sampled items against the oracle at the same chi and
+    rule, bound 1e-9."""
     from paper_2310_10722_amd import tn3d
     say("case: rotated d=5 T=5 chi=16 fp64, rule 1e-6/1e-4, full batch of 1024, 24 sampled items")
     dem, m, _, _ = synth.config_workload(2)
@@ -340,9 +346,9 @@ def test_rotated_d5_full_batch_headline_fp64(ctx):
     fin = np.isfinite(ref).all(axis=1)
     err = np.abs(logp[idx, :2] - ref)[fin]
     say("  max |d log p| =", err.max())
-    assert err.max() <= 1e-6
+    assert err.max() <= 1e-9
     best = np.argmax(ref[fin], axis=1)
-    assert np.all((coset[idx][fin] == best) | (np.abs(ref[fin, 0] - ref[fin, 1]) <= 2e-6))
+    assert np.all((coset[idx][fin] == best) | (np.abs(ref[fin, 0] - ref[fin, 1]) <= 2e-9))
 
 
 def test_unsupported_width_is_refused(ctx):
@@ -395,3 +401,31 @@ def test_graph_replay_matches_eager(ctx):
     ctx.set_timing(1)  # restarts the sums
     assert all(v == 0 for v in ctx.last_timing())
     ctx.set_timing(0)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp64_gram"])
+def test_point_L8_chi32_full_batch_golden(ctx, mode):
+    """The 3D planar code at L=8, p=0.2, chi = chi_m = 32 (layer bonds of 32,
+    site tensors of 2 * 32^4 entries, boundary-MPS families of up to 1024
+    vectors on the subspace-iteration solver): the whole 256-syndrome batch in
+    one call, items 0, 85, 170, 255 against stored oracle values
+    (tests/golden/make_point_L8_chi32.py, reduced rule).  Bounds 1e-3 (FP32),
+    1e-6 (FP64 Gram route)."""
+    import json
+    import os
+    from paper_2310_10722_amd import tn3d
+    say(f"case: point sector L=8 p=0.2 chi=chi_m=32 {mode}, 256 syndromes, 4 stored")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "point_L8_chi32.json")))
+    dem, m, _, _ = synth.config_workload(3)
+    assert m.shape[0] == gold["n"]
+    assert np.array_equal(m[gold["items"]], np.array(gold["syndromes"], dtype=np.uint8))
+    net = tn3d.tn3d_net_surface3d_point(ctx, 8, dem.p)
+    prm = tn3d.tn3d_params_default(32, 32, tn3d.PREC_FP32 if mode == "fp32" else tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = gold["rule"]
+    if mode == "fp64_gram":
+        prm.flags = tn3d.OPT_GRAM_FACTOR
+    got, flags = gpu_logp(ctx, net, m, prm)
+    assert np.all(np.isfinite(got[:, :2]))
+    err = np.abs(got[gold["items"], :2] - np.array(gold["logp"]))
+    say("  max |d log p| =", err.max(), " flags", np.bincount(flags, minlength=1).tolist()[:16])
+    assert err.max() <= (1e-3 if mode == "fp32" else 1e-6)
