@@ -58,9 +58,17 @@ typedef enum {
 
 /* Arithmetic of the layer absorption (site tensors and their contractions).
  * The truncation factorisations, singular values and log accumulators are
- * always FP64. */
+ * always FP64.
+ *   FP64: FP64 site tensors, Grams on FP64 matrix cores, truncations factored
+ *         by Householder QR and one-sided Jacobi (see TN3D_OPT_GRAM_FACTOR).
+ *   FP32: FP32 site tensors, Grams on FP64 matrix cores.
+ *   BF16: FP32 site tensors, Grams on BF16 matrix cores with FP32
+ *         accumulation (per chunk of 32 rows; FP64 across chunks), every
+ *         operand split into three BF16 terms so the products keep FP32
+ *         accuracy; everything else as FP32. */
 #define TN3D_PREC_FP64 0
 #define TN3D_PREC_FP32 1
+#define TN3D_PREC_BF16 2
 
 /* params.flags bits. */
 /* FP64 only: factor the truncations through Gram matrices (MFMA Grams,

@@ -389,6 +389,116 @@ __device__ void block_gemm512(int M, int N, int K, FA a_at, FB b_at, FC c_put, d
   __syncthreads();
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// v = h + m + l exactly (to 24 bits) with three BF16 terms of 8 significant
+// bits each (round to nearest at every step; the residuals are exact).
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8& h, bf16x8& m, bf16x8& l) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 a = __bf16(v[t]);
+    const float r1 = v[t] - float(a);
+    const __bf16 b = __bf16(r1);
+    const float r2 = r1 - float(b);
+    h[t] = a;
+    m[t] = b;
+    l[t] = __bf16(r2);
+  }
+}
+
+// block_gemm512 on the BF16 matrix cores: the operands rounded to FP32, split
+// into three BF16 terms each (split3) and the six leading products (h.h, h.m,
+// m.h, h.l, m.m, l.h, the dropped ones below 2^-24 relative) accumulated in
+// FP32 over each 32-deep K slice, the slices summed in FP64.  Same tiling and
+// staging as block_gemm512; v_mfma_f32_16x16x32_bf16 takes A[i][8q .. 8q + 7]
+// in lane i + 16 q and B[8q .. 8q + 7][j] in lane j + 16 q, and item r of lane
+// j + 16 q is C[4 q + r][j].
+template <bool KA = false, bool KB = false, class FA, class FB, class FC>
+__device__ void block_gemm512_bf(int M, int N, int K, FA a_at, FB b_at, FC c_put, double* lds) {
+  constexpr int GEMM_LS = (KA || KB) ? 65 : 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int rb = (wv & 3) * 16, cb = (wv >> 2) * 32;
+  double* As = lds;
+  double* Bs = lds + 32 * GEMM_LS;
+  auto kk_of = [](int e, bool alongk) { return alongk ? (e & 31) : (e >> 6); };
+  auto mm_of = [](int e, bool alongk) { return alongk ? (e >> 5) : (e & 63); };
+  for (int m0 = 0; m0 < M; m0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) {
+      const bool act = m0 + rb < M && n0 + cb < N;
+      const bool act2 = n0 + cb + 16 < N;
+      dbl4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      double ra[4], rb4[4];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = tid + 512 * i;
+          const int ka = k0 + kk_of(e, KA), m = m0 + mm_of(e, KA);
+          const int kb = k0 + kk_of(e, KB), n = n0 + mm_of(e, KB);
+          ra[i] = (m < M && ka < K) ? a_at(m, ka) : 0.0;
+          rb4[i] = (n < N && kb < K) ? b_at(kb, n) : 0.0;
+        }
+      };
+      __syncthreads();
+      fetch(0);
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = tid + 512 * i;
+          As[(KA || GEMM_LS != 64) ? kk_of(e, KA) * GEMM_LS + mm_of(e, KA) : e] = ra[i];
+          Bs[(KB || GEMM_LS != 64) ? kk_of(e, KB) * GEMM_LS + mm_of(e, KB) : e] = rb4[i];
+        }
+        __syncthreads();
+        if (k0 + 32 < K) fetch(k0 + 32);
+        if (act) {
+          float va[8], vb0[8], vb1[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int kr = (8 * lq + u) * GEMM_LS;
+            va[u] = float(As[kr + rb + li]);
+            vb0[u] = float(Bs[kr + cb + li]);
+            vb1[u] = act2 ? float(Bs[kr + cb + 16 + li]) : 0.f;
+          }
+          bf16x8 ah, am, al, bh0, bm0, bl0, bh1, bm1, bl1;
+          split3(va, ah, am, al);
+          split3(vb0, bh0, bm0, bl0);
+          split3(vb1, bh1, bm1, bl1);
+          flt4 f0 = {0.f, 0.f, 0.f, 0.f}, f1 = {0.f, 0.f, 0.f, 0.f};
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, f1, 0, 0, 0);
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm1, f1, 0, 0, 0);
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, f1, 0, 0, 0);
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh1, f1, 0, 0, 0);
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm1, f1, 0, 0, 0);
+          f0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, f0, 0, 0, 0);
+          f1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, f1, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            c0[r] += double(f0[r]);
+            c1[r] += double(f1[r]);
+          }
+        }
+      }
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + rb + 4 * lq + r, n = n0 + cb + li;
+          if (m < M) {
+            if (n < N) c_put(m, n, c0[r]);
+            if (n + 16 < N) c_put(m, n + 16, c1[r]);
+          }
+        }
+      }
+    }
+  __syncthreads();
+}
+
 // Sum over the 64 lanes, the same value in every lane: butterflies within each
 // row of 16 lanes (quad permutations, half-row and row mirrors), then the four
 // row sums read out in a fixed order.  Every lane must be active.

@@ -481,6 +481,10 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.jtol = A.jtol;
     Z.jfloor = A.jfloor;
     Z.gram_path = gram_path ? 1 : 0;
+    // large boundary-MPS families: residuals of the leading Ritz pairs far
+    // below what the precision resolves (FP64) or needs (reduced precisions)
+    Z.sub_tol = prec == TN3D_PREC_FP64 ? 1e-12 : 1e-9;
+    Z.bf_theta = prec == TN3D_PREC_BF16 ? 1 : 0;
     Z.sweeps_max = A.sweeps_max;
     Z.zdim = reinterpret_cast<int32_t*>(ws + o_zdim);
     Z.zS = reinterpret_cast<double*>(ws + o_zS);
@@ -616,7 +620,7 @@ bool params_ok(const tn3d_params* p, std::string& why) {
     why = "chi_mps must be in [1, 64]";
     return false;
   }
-  if (p->precision != TN3D_PREC_FP64 && p->precision != TN3D_PREC_FP32) {
+  if (p->precision != TN3D_PREC_FP64 && p->precision != TN3D_PREC_FP32 && p->precision != TN3D_PREC_BF16) {
     why = "unknown precision";
     return false;
   }

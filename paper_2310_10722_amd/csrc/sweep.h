@@ -66,6 +66,8 @@ struct ZipArgs {
   double* zS;               // [sweep][1024] singular values of the step
   unsigned long long* flop_ctr;  // 64 counters of algorithmic flops of the decomposition, or null
   unsigned long long* win;       // execution window of the decomposition launch, or null
+  double sub_tol;                // subspace iteration: residual bound relative to the largest eigenvalue
+  int32_t bf_theta;              // 1: Theta on the BF16 matrix cores (reduced precisions)
 };
 
 // Raises the dynamic-LDS limits of the kernels that need more than 64 KB;

@@ -296,6 +296,196 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
   win_close(A.win, w0);
 }
 
+// The same Gram through LDS, for every storage type: each chunk of 32 rows of
+// the row-weighted view X is fetched in memory order (consecutive lanes read
+// consecutive addresses: along the rows when the legs after the gated one
+// hold more than one index, Cp > 1, else along the columns), scaled by the
+// rows' environment weights and stored column-major in LDS; the next chunk's
+// values are fetched into registers while the current one is multiplied.
+// BF = 0: FP64 matrix cores on the values (v_mfma_f64_16x16x4f64, as
+// k_gram).  BF = 1 (float storage): BF16 matrix cores with FP32
+// accumulation, each value split into three BF16 terms x = h + m + l (8
+// significant bits each, so the split is exact to 24 bits) and X^T X formed
+// from the six products h.h, h.m, m.h, h.l, m.m, l.h (the dropped ones are
+// below 2^-24 relative), per chunk in FP32, summed over chunks in FP64.
+constexpr int GR = 32;  // rows per chunk
+
+template <typename T, int NB, int BF>
+__global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
+                                              int nlo) {
+  constexpr int NC = 16 * NB;
+  constexpr int NL = GR * NC / 64;  // elements each lane fetches per chunk
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
+  const DevGate g = gates[gi];
+  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
+  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
+  int D[4];
+  site_dims(A, sweep, site, D);
+  const Split v = make_split(D, leg, d);
+  const int ncols = d * v.Dx;
+  if (ncols <= nlo || ncols > NC) return;
+  const unsigned long long w0 = win_open(A.win);
+  __shared__ double slam[4][MAXCHI];
+  __shared__ int rowbase[2][GR];
+  __shared__ double rowsc[2][GR];
+  __shared__ T Xs[NC * (GR + 1)];  // column-major, stride GR + 1
+  for (int e = lane; e < 4 * MAXCHI; e += 64) {
+    const int lg = e / MAXCHI, k = e % MAXCHI;
+    const int b = A.leg_bond[site * 4 + lg];
+    double val = 1.0;
+    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    slam[lg][k] = val;
+  }
+  // memory-order column mc = x d + p: offset x Cp d + p in a row, Gram column p Dx + x
+  __shared__ int coff[NC], ccan[NC];
+  for (int mc = lane; mc < NC; mc += 64) {
+    const int x = mc / d, p = mc - x * d;
+    coff[mc] = mc < ncols ? x * v.Cp * d + p : -1;
+    ccan[mc] = p * v.Dx + x;
+  }
+  for (int e = lane; e < NC * (GR + 1); e += 64) Xs[e] = T(0);
+  __syncthreads();
+  const bool rowfast = v.Cp > 1;
+  const T* t = tens<T>(A, par, sweep, site);
+  // row offsets and weights of a chunk, one lane per row, into buffer q
+  auto rows_of = [&](int r0, int q) {
+    if (lane < GR) {
+      const int r = r0 + lane;
+      int base = 0;
+      double sc = 0.0;
+      if (r < v.rows) {
+        const int a = r / v.Cp, c = r - a * v.Cp;
+        base = (a * v.Dx * v.Cp + c) * d;
+        sc = 1.0;
+        int cc = c;
+        for (int lg = 3; lg > leg; --lg) {
+          const int qq = cc / D[lg];
+          sc *= slam[lg][cc - qq * D[lg]];
+          cc = qq;
+        }
+        int aa = a;
+        for (int lg = leg - 1; lg >= 0; --lg) {
+          const int qq = aa / D[lg];
+          sc *= slam[lg][aa - qq * D[lg]];
+          aa = qq;
+        }
+      }
+      rowbase[q][lane] = base;
+      rowsc[q][lane] = sc;
+    }
+  };
+  constexpr int NP = NB * (NB + 1) / 2;
+  dbl4 acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // element j of a lane's fetch: local row and memory-order column; the next
+  // chunk's values are fetched into registers while the current one is used
+  T reg[NL];
+  auto fetch = [&](int r0, int q) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = lane + 64 * j;
+      const int rl = rowfast ? e % GR : e / NC, mc = rowfast ? e / GR : e % NC;
+      const int co = coff[mc];
+      reg[j] = (co >= 0 && r0 + rl < v.rows) ? t[rowbase[q][rl] + co] : T(0);
+    }
+  };
+  auto store = [&](int q) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = lane + 64 * j;
+      const int rl = rowfast ? e % GR : e / NC, mc = rowfast ? e / GR : e % NC;
+      if (coff[mc] >= 0) Xs[ccan[mc] * (GR + 1) + rl] = T(double(reg[j]) * rowsc[q][rl]);
+    }
+  };
+  rows_of(0, 0);
+  __syncthreads();
+  fetch(0, 0);
+  int q = 0;
+  for (int r0 = 0; r0 < v.rows; r0 += GR, q ^= 1) {
+    store(q);
+    if (r0 + GR < v.rows) rows_of(r0 + GR, q ^ 1);
+    __syncthreads();
+    if (r0 + GR < v.rows) fetch(r0 + GR, q ^ 1);
+    if (BF == 0) {
+      const int li = lane & 15, lq = lane >> 4;
+#pragma unroll
+      for (int s4 = 0; s4 < GR / 4; ++s4) {
+        double xv[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) xv[b] = double(Xs[(16 * b + li) * (GR + 1) + 4 * s4 + lq]);
+        int k = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+          for (int b2 = b1; b2 < NB; ++b2) {
+            acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[b1], xv[b2], acc[k], 0, 0, 0);
+            ++k;
+          }
+      }
+    } else {
+      const int li = lane & 15, kq = lane >> 4;
+      bf16x8 h[NB], m[NB], l[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[u] = float(Xs[(16 * b + li) * (GR + 1) + 8 * kq + u]);
+        split3(vv, h[b], m[b], l[b]);
+      }
+      flt4 c[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) c[k] = flt4{0.f, 0.f, 0.f, 0.f};
+      // the six products, smallest first, each over the NP independent block pairs
+      auto step = [&](const bf16x8 (&x)[NB], const bf16x8 (&y)[NB]) {
+        int k = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+          for (int b2 = b1; b2 < NB; ++b2) {
+            c[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[b1], y[b2], c[k], 0, 0, 0);
+            ++k;
+          }
+      };
+      step(l, h);
+      step(m, m);
+      step(h, l);
+      step(m, h);
+      step(h, m);
+      step(h, h);
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[k][r] += double(c[k][r]);
+    }
+    __syncthreads();  // this chunk's tile is read before the next one replaces it
+  }
+  if (A.bytes_ctr && lane == 0)
+    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
+              (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
+  if (side == 0 && lane == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
+  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
+  const int li = lane & 15, lq = lane >> 4;
+  int k = 0;
+#pragma unroll
+  for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+    for (int b2 = b1; b2 < NB; ++b2) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        // FP64 16x16x4: item r of lane j + 16 q is C[q + 4 r][j]; the BF16
+        // 16x16x32 one has C[4 q + r][j]
+        const int i = 16 * b1 + (BF ? 4 * lq + it : lq + 4 * it), j = 16 * b2 + li;
+        if (i < ncols && j < ncols) {
+          out[i * ncols + j] = acc[k][it];
+          if (b1 != b2) out[j * ncols + i] = acc[k][it];
+        }
+      }
+      ++k;
+    }
+  win_close(A.win, w0);
+}
+
 // FP64 route: the triangular factor R (R^T R = X^T X) of the same row-weighted
 // view X as k_gram, by Householder QR streamed over the rows (tsqr_block), so
 // no Gram matrix is formed and the small singular values of X keep the
@@ -984,6 +1174,195 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
   win_close(A.win, w0);
 }
 
+// The reabsorption T' = T W on the matrix cores, for rows of up to NMAX
+// (32 or 64) entries: one wavefront per (gate side, sweep), chunks of 32
+// rows.  A chunk of T is fetched in memory order (as k_gram2: consecutive
+// lanes at consecutive addresses) into LDS, multiplied by W, staged in LDS
+// again and written back in memory order.  BF = 0: FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// item r of lane j + 16 q is C[q + 4 r][j]); W sits in LDS in FP64.  BF = 1
+// (float storage): BF16 matrix cores with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane i + 16 q holds A[i][8 q .. 8 q + 7] and
+// B[8 q .. 8 q + 7][i]; item r of lane j + 16 q is C[4 q + r][j]), T and W
+// split into three BF16 terms each and the six leading products summed (as
+// k_gram2); W's terms stay in registers.
+template <typename T, int NMAX, int BF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_reabsorb2(SweepArgs A, const DevGate* gates, int n_g, const double* win,
+                                                  int ncap, int nlo) {
+  constexpr int NL = GR * NMAX / 64;  // elements a lane moves per chunk
+  constexpr int KB = BF ? NMAX / 32 : 1, KS = BF ? 1 : NMAX / 4;
+  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
+  const DevGate g = gates[gi];
+  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
+  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
+  const double* W = win + (int64_t(sweep * n_g + gi) * 2 + side) * (2 + ncap * ncap);
+  const int Dold = int(W[0]), Dn = int(W[1]);
+  const int nin = d * Dold, nout = d * Dn;
+  if (nin <= nlo || nin > NMAX) return;
+  const unsigned long long w0 = win_open(A.win);
+  int D[4];
+  site_dims(A, sweep, site, D);
+  D[leg] = Dold;
+  const Split v = make_split(D, leg, d);
+  // one chunk of T (row-major, canonical input columns), then of T' (canonical
+  // output columns) in the same place
+  constexpr int TS = NMAX + 1;
+  __shared__ T Tb[GR * TS];
+  __shared__ int rb_in[GR], rb_out[GR];
+  const T* in = tens<T>(A, par, sweep, site);
+  T* out = tens<T>(A, par ^ 1, sweep, site);
+  const bool rowfast = v.Cp > 1;
+  const int li = lane & 15, lq = lane >> 4;
+  // W in registers: BF16 terms (BF = 1) or FP64 values (BF = 0), per B operand
+  bf16x8 wh[KB][4], wm[KB][4], wl[KB][4];
+  double wd[BF ? 1 : 4][KS];
+  if (BF) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        float vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = 32 * kb + 8 * lq + u, n = 16 * nb + li;
+          vv[u] = (k < nin && n < nout) ? float(W[2 + k * nout + n]) : 0.f;
+        }
+        split3(vv, wh[kb][nb], wm[kb][nb], wl[kb][nb]);
+      }
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < (BF ? 1 : 4); ++nb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lq, n = 16 * nb + li;
+        wd[nb][ks] = (k < nin && n < nout) ? W[2 + k * nout + n] : 0.0;
+      }
+  }
+  // memory-order columns mc = x d + p: offsets in a row and canonical columns,
+  // of the input (bond Dold) and of the output (bond Dn)
+  __shared__ int ioff[NMAX], ican[NMAX], ooff[NMAX], ocan[NMAX];
+  for (int mc = lane; mc < NMAX; mc += 64) {
+    const int x = mc / d, p = mc - x * d;
+    ioff[mc] = mc < nin ? x * v.Cp * d + p : -1;
+    ican[mc] = p * Dold + x;
+    ooff[mc] = mc < nout ? x * v.Cp * d + p : -1;
+    ocan[mc] = p * Dn + x;
+  }
+  for (int e = lane; e < GR * TS; e += 64) Tb[e] = T(0);
+  if (A.bytes_ctr && lane == 0)
+    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
+              (unsigned long long)(int64_t(v.rows) * (nin + nout) * int64_t(sizeof(T))));
+  for (int r0 = 0; r0 < v.rows; r0 += GR) {
+    if (lane < GR) {
+      const int r = r0 + lane;
+      int bi = 0, bo = 0;
+      if (r < v.rows) {
+        const int a = r / v.Cp, c = r - a * v.Cp;
+        bi = (a * Dold * v.Cp + c) * d;
+        bo = (a * Dn * v.Cp + c) * d;
+      }
+      rb_in[lane] = bi;
+      rb_out[lane] = bo;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < NL; ++j) {
+      const int e = lane + 64 * j;
+      const int rl = rowfast ? e % GR : e / NMAX, mc = rowfast ? e / GR : e % NMAX;
+      const int io = ioff[mc];
+      if (io >= 0) Tb[rl * TS + ican[mc]] = r0 + rl < v.rows ? in[rb_in[rl] + io] : T(0);
+    }
+    __syncthreads();
+    // A operands of both 16-row blocks into registers, then the products into Tb
+    if (BF == 0) {
+      double a[2][KS];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a[mb][ks] = double(Tb[(16 * mb + li) * TS + 4 * ks + lq]);
+      __syncthreads();
+      const int nbn = (nout + 15) >> 4;
+      dbl4 c[2][4];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) c[mb][nb] = dbl4{0.0, 0.0, 0.0, 0.0};
+      // eight independent accumulators interleaved, so consecutive products
+      // never wait for each other
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          if (nb < nbn) {
+            c[0][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][ks], wd[nb][ks], c[0][nb], 0, 0, 0);
+            c[1][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][ks], wd[nb][ks], c[1][nb], 0, 0, 0);
+          }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          if (nb < nbn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Tb[(16 * mb + lq + 4 * r) * TS + 16 * nb + li] = T(c[mb][nb][r]);
+    } else {
+      bf16x8 ah[2][KB], am[2][KB], al[2][KB];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          float vv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) vv[u] = float(Tb[(16 * mb + li) * TS + 32 * kb + 8 * lq + u]);
+          split3(vv, ah[mb][kb], am[mb][kb], al[mb][kb]);
+        }
+      __syncthreads();
+      const int nbn = (nout + 15) >> 4;
+      flt4 c[2][4];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) c[mb][nb] = flt4{0.f, 0.f, 0.f, 0.f};
+      // the six products of a block pair, smallest first, each step over the
+      // eight independent accumulators
+      auto step = [&](const bf16x8 (&x)[2][KB], const bf16x8 (&y)[KB][4], int kb) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          if (nb < nbn) {
+            c[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0][kb], y[kb][nb], c[0][nb], 0, 0, 0);
+            c[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1][kb], y[kb][nb], c[1][nb], 0, 0, 0);
+          }
+      };
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        step(al, wh, kb);
+        step(am, wm, kb);
+        step(ah, wl, kb);
+        step(am, wh, kb);
+        step(ah, wm, kb);
+        step(ah, wh, kb);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          if (nb < nbn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Tb[(16 * mb + 4 * lq + r) * TS + 16 * nb + li] = T(c[mb][nb][r]);
+    }
+    __syncthreads();
+    // write back in memory order (output rows of nout entries)
+#pragma unroll 8
+    for (int j = 0; j < NL; ++j) {
+      const int e = lane + 64 * j;
+      const int rl = rowfast ? e % GR : e / NMAX, mc = rowfast ? e / GR : e % NMAX;
+      const int oo = ooff[mc];
+      if (oo >= 0 && r0 + rl < v.rows) out[rb_out[rl] + oo] = Tb[rl * TS + ocan[mc]];
+    }
+    __syncthreads();
+  }
+  win_close(A.win, w0);
+}
+
 // ---------------------------------------------------------------------------
 // per-site rescale after each layer
 // ---------------------------------------------------------------------------
@@ -1111,11 +1490,15 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
       nu * wL, sa, ka, [&](int m, int k) { return Kp[((m / wL) * ka + k) * wL + m % wL]; },
       [&](int k, int n) { return Mold[k * sa + n]; }, [&](int m, int n, double v) { L4[m * sa + n] = v; }, gst);
   const int R = nu * sD, C = aR * wR;
-  block_gemm512(
-      nu * aR, wR * sD, wL * sd,
-      [&](int m, int k) { return L4[(((m / aR) * wL + k / sd) * sd + k % sd) * aR + m % aR]; },
-      [&](int k, int n) { return Tt[(((k / sd) * wR + n / sD) * nU + k % sd) * sD + n % sD]; },
-      [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; }, gst);
+  auto l4_at = [&](int m, int k) { return L4[(((m / aR) * wL + k / sd) * sd + k % sd) * aR + m % aR]; };
+  auto t_at = [&](int k, int n) { return Tt[(((k / sd) * wR + n / sD) * nU + k % sd) * sD + n % sD]; };
+  auto th_put = [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; };
+  // the reduced precisions form Theta on the BF16 matrix cores (FP32-accurate
+  // products of the FP32-accurate tensors); FP64 on the FP64 ones
+  if (Z.bf_theta)
+    block_gemm512_bf(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+  else
+    block_gemm512(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
   const bool rows = R <= C;
   const int nv = rows ? R : C;
   if (inline_dec) {
@@ -1500,8 +1883,8 @@ __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
 // X (nv x SB, row-major) <- an orthonormal basis of the span of Z (same
 // shape, destroyed) by Cholesky QR twice with column equilibration; a column
 // whose pivot shows it dependent on the previous ones is replaced by a hashed
-// vector before the second pass.  R: SB x 65 LDS, red: 16 doubles.
-__device__ void block_cholqr2(double* Z, double* X, int nv, double* R, double* gl, double* red, int* dead,
+// vector before the second pass.  R, Ri: SB x 65 LDS, red: 16 doubles.
+__device__ void block_cholqr2(double* Z, double* X, int nv, double* R, double* Ri, double* gl, double* red, int* dead,
                               unsigned seed) {
   const int tid = threadIdx.x;
   for (int pass = 0; pass < 2; ++pass) {
@@ -1552,21 +1935,28 @@ __device__ void block_cholqr2(double* Z, double* X, int nv, double* R, double* g
       }
       __syncthreads();
     }
-    // X = Z D^-1/2 R^-1, row by row (forward substitution x R = z)
-    for (int r = tid; r < nv; r += ZNT) {
-      double xr[SB];
-#pragma unroll
-      for (int j = 0; j < SB; ++j) {
-        const double dj = dsc[j];
-        double z = dj >= 0.0 ? Z[r * SB + j] * dj : 0.0;
-#pragma unroll 8
-        for (int i = 0; i < j; ++i) z = fma(-xr[i], R[i * 65 + j], z);
-        xr[j] = z / R[j * 65 + j];
+    // R^-1 into Ri (column j by back substitution in thread j), then
+    // X = Z D^-1/2 R^-1 on the matrix cores
+    if (tid < SB) {
+      const int j = tid;
+      for (int i = SB - 1; i >= 0; --i) {
+        double y = 0.0;
+        if (i <= j) {
+          y = i == j ? 1.0 : 0.0;
+          for (int k = i + 1; k <= j; ++k) y = fma(-R[i * 65 + k], Ri[k * 65 + j], y);
+          y /= R[i * 65 + i];
+        }
+        Ri[i * 65 + j] = y;
       }
-#pragma unroll
-      for (int j = 0; j < SB; ++j) X[r * SB + j] = xr[j];
     }
     __syncthreads();
+    block_gemm512<true, false>(
+        nv, SB, SB,
+        [&](int m, int k) {
+          const double dk = dsc[k];
+          return dk >= 0.0 ? Z[m * SB + k] * dk : 0.0;
+        },
+        [&](int k, int n) { return Ri[k * 65 + n]; }, [&](int m, int n, double v) { X[m * SB + n] = v; }, gl);
     if (pass == 0) {
       // dead columns get a hashed vector; the second pass orthonormalises
       for (int e = tid; e < nv * SB; e += ZNT) {
@@ -1614,8 +2004,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
     Y[e] = G[int64_t(r) * nv + jsel[j]];
   }
   __syncthreads();
-  block_cholqr2(Y, X, nv, H, gl, red, &flag[0], 0x1234u);
-  double tol = 1e-12;
+  block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x1234u);
+  const double tol = Z.sub_tol;
   int it = 0, conv = 0;
   const int maxit = 80;
   for (; it < maxit; ++it) {
@@ -1681,7 +2071,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
       Y[e] = P[e] / fmax(th[j], fl);
     }
     __syncthreads();
-    block_cholqr2(Y, X, nv, H, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
+    block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
   }
   // the rank rule on sqrt(theta), the kept Ritz vectors into Fv
   for (int j = tid; j < SB; j += ZNT) Sout[j] = sqrt(fmax(th[j], 0.0));
@@ -2026,16 +2416,16 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
     hipLaunchKernelGGL(k_onesite<float>, g, dim3(ET), 0, st, A, ops);
 }
 
-template <typename T>
+template <typename T, int BF>
 static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
                           hipStream_t st) {
   // ncap <= 64 is checked by the host before any launch; Grams of up to 32
   // columns (three block pairs) and of 33 to 64 (ten) in separate launches,
   // the second over the leading n_wide gates (the only ones that can be wide)
-  hipLaunchKernelGGL((k_gram<T, 2>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
+  hipLaunchKernelGGL((k_gram2<T, 2, BF>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
   if (ncap > 32 && n_wide > 0)
-    hipLaunchKernelGGL((k_gram<T, 4>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap,
-                       32);
+    hipLaunchKernelGGL((k_gram2<T, 4, BF>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
+                       ncap, 32);
 }
 
 void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
@@ -2054,9 +2444,11 @@ void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, in
     return;
   }
   if (prec == 0)
-    gram_dispatch<double>(A, gates, n_g, n_wide, gout, ncap, st);
+    gram_dispatch<double, 0>(A, gates, n_g, n_wide, gout, ncap, st);
+  else if (prec == 2)
+    gram_dispatch<float, 1>(A, gates, n_g, n_wide, gout, ncap, st);
   else
-    gram_dispatch<float>(A, gates, n_g, n_wide, gout, ncap, st);
+    gram_dispatch<float, 0>(A, gates, n_g, n_wide, gout, ncap, st);
 }
 
 static size_t solve_lds(int n) {
@@ -2090,14 +2482,20 @@ void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g
   // 64 (the W staging takes 8, 16 and 32 KB of LDS); the wider classes run
   // over the leading gates that can have such rows
   const bool w16 = ncap > 16 && n_w16 > 0, w32 = ncap > 32 && n_w32 > 0;
+  // the widest class (rows of 33 to 64 entries) on the matrix cores
   if (prec == 0) {
     hipLaunchKernelGGL((k_reabsorb<double, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
     if (w16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
-    if (w32) hipLaunchKernelGGL((k_reabsorb<double, 64>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    if (w32) hipLaunchKernelGGL((k_reabsorb2<double, 64, 0>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   } else {
     hipLaunchKernelGGL((k_reabsorb<float, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
     if (w16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
-    if (w32) hipLaunchKernelGGL((k_reabsorb<float, 64>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    if (w32) {
+      if (prec == 2)
+        hipLaunchKernelGGL((k_reabsorb2<float, 64, 1>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+      else
+        hipLaunchKernelGGL((k_reabsorb2<float, 64, 0>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    }
   }
 }
 

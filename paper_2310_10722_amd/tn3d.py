@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtn3d.so")
 
 PREC_FP64 = 0
 PREC_FP32 = 1
+PREC_BF16 = 2
 FLAG_NUMERIC = 1
 FLAG_TRUNC_CLUSTER = 2
 FLAG_NEAR_TIE = 4

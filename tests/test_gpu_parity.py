@@ -112,12 +112,13 @@ def test_rotated_d5_fp64_chi16(ctx):
     assert err <= 1e-9
 
 
-def test_rotated_d5_fp32_chi16(ctx):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_rotated_d5_fp32_chi16(ctx, prec):
     from paper_2310_10722_amd import tn3d
-    say("case: rotated d=5 T=5 chi=16 fp32, 32 syndromes")
+    say(f"case: rotated d=5 T=5 chi=16 {prec}, 32 syndromes")
     dem, m, _, _ = synth.config_workload(2, n=32)
     net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
-    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP32)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP32 if prec == "fp32" else tn3d.PREC_BF16)
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle_rot(dem, m, prm)
     err = np.abs(got[:, :2] - ref)
@@ -150,7 +151,7 @@ def test_rotated_d5_boundary_chi32_gram_route(ctx, prec):
     assert err.max() <= {"fp64": 1e-9, "fp64_gram": 1e-6, "fp32": 1e-3}[prec]
 
 
-@pytest.mark.parametrize("mode", ["fp64_default", "fp64_reduced", "fp32_reduced"])
+@pytest.mark.parametrize("mode", ["fp64_default", "fp64_reduced", "fp32_reduced", "bf16_reduced"])
 def test_point_L5_chi32_golden(ctx, mode):
     """3D planar code, point sector, L=5, p=0.2, chi = 32, chi_m = 4: the
     layer bonds reach 32, so the widest layer classes run (Grams of 64
@@ -170,13 +171,13 @@ def test_point_L5_chi32_golden(ctx, mode):
     ref = np.array(gold["logp"][rule])
     dem = synth.surface3d_point(gold["L"], gold["p"])
     net = tn3d.tn3d_net_surface3d_point(ctx, gold["L"], dem.p)
-    prm = tn3d.tn3d_params_default(gold["chi"], gold["chi_mps"],
-                                   tn3d.PREC_FP32 if mode == "fp32_reduced" else tn3d.PREC_FP64)
+    prec = {"fp32_reduced": tn3d.PREC_FP32, "bf16_reduced": tn3d.PREC_BF16}.get(mode, tn3d.PREC_FP64)
+    prm = tn3d.tn3d_params_default(gold["chi"], gold["chi_mps"], prec)
     prm.eps_rel, prm.tau_gap = gold["rules"][rule]
     got, _ = gpu_logp(ctx, net, m, prm)
     err = np.abs(got[:, :2] - ref)
     say("  max |d log p| =", err.max())
-    assert err.max() <= {"fp64_default": 1e-9, "fp64_reduced": 1e-9, "fp32_reduced": 1e-3}[mode]
+    assert err.max() <= {"fp64_default": 1e-9, "fp64_reduced": 1e-9, "fp32_reduced": 1e-3, "bf16_reduced": 1e-3}[mode]
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32"])
@@ -403,7 +404,7 @@ def test_graph_replay_matches_eager(ctx):
     ctx.set_timing(0)
 
 
-@pytest.mark.parametrize("mode", ["fp32", "fp64_gram"])
+@pytest.mark.parametrize("mode", ["bf16", "fp32", "fp64_gram"])
 def test_point_L8_chi32_full_batch_golden(ctx, mode):
     """The 3D planar code at L=8, p=0.2, chi = chi_m = 32 (layer bonds of 32,
     site tensors of 2 * 32^4 entries, boundary-MPS families of up to 1024
@@ -420,7 +421,8 @@ def test_point_L8_chi32_full_batch_golden(ctx, mode):
     assert m.shape[0] == gold["n"]
     assert np.array_equal(m[gold["items"]], np.array(gold["syndromes"], dtype=np.uint8))
     net = tn3d.tn3d_net_surface3d_point(ctx, 8, dem.p)
-    prm = tn3d.tn3d_params_default(32, 32, tn3d.PREC_FP32 if mode == "fp32" else tn3d.PREC_FP64)
+    prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32, "fp64_gram": tn3d.PREC_FP64}[mode]
+    prm = tn3d.tn3d_params_default(32, 32, prec)
     prm.eps_rel, prm.tau_gap = gold["rule"]
     if mode == "fp64_gram":
         prm.flags = tn3d.OPT_GRAM_FACTOR
@@ -428,4 +430,4 @@ def test_point_L8_chi32_full_batch_golden(ctx, mode):
     assert np.all(np.isfinite(got[:, :2]))
     err = np.abs(got[gold["items"], :2] - np.array(gold["logp"]))
     say("  max |d log p| =", err.max(), " flags", np.bincount(flags, minlength=1).tolist()[:16])
-    assert err.max() <= (1e-3 if mode == "fp32" else 1e-6)
+    assert err.max() <= (1e-6 if mode == "fp64_gram" else 1e-3)
