@@ -191,10 +191,10 @@ tn3d_status tn3d_contract_cosets(tn3d_ctx ctx, int32_t batch, const tn3d_net* ne
  * logratio_dev[i] = log p of the chosen coset minus the largest other one
  * (>= 0), TN3D_FLAG_NEAR_TIE when logratio < params->near_tie.  With
  * precision TN3D_PREC_FP32 and near_tie > 0, every item whose log-ratio is
- * below near_tie (or not a number) is contracted again in FP64 at the same chi
- * and chi_mps with the FP64 defaults of tn3d_params_default for eps_rel and
- * tau_gap and the Gram route (TN3D_OPT_GRAM_FACTOR; the decision needs far
- * less than its 1e-8); its logp row, flags (those of the FP64 pass plus TN3D_FLAG_RESWEPT)
+ * below near_tie (or not a number) is contracted again in FP64 at the same chi,
+ * chi_mps and rank rule, through the Gram route (TN3D_OPT_GRAM_FACTOR; the
+ * decision needs far less than that route's accuracy); its logp row, flags
+ * (those of the FP64 pass plus TN3D_FLAG_RESWEPT)
  * and decision are replaced.  This synchronises the context stream once.
  * logp_dev and flags_dev may be NULL. */
 tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
@@ -221,8 +221,12 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * by the reabsorption), out[5] = time of the boundary-MPS eigen-decomposition
  * launches (when the rank rule allows that path), out[6] = their number,
  * out[7] = their algorithmic flops (per problem of order n keeping D vectors:
- * 4n^3/3 + 2Dn^2 + 7Dn + 12D^2n).  Milliseconds for times; n <= 8 values are
- * written.
+ * 4n^3/3 + 2Dn^2 + 7Dn + 12D^2n for the one-wavefront solver; per iteration
+ * 2n^2 b + 14 n b^2 with b = 64 for the subspace iteration of larger families),
+ * out[8] = time of the boundary-MPS contraction launches (the two
+ * contractions forming Theta and, on the Gram route, its Gram), out[9] = their
+ * algorithmic flops, out[10] = their number.  Milliseconds for times; n <= 11
+ * values are written.
  * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);

@@ -49,7 +49,7 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   int timing = 0;                  // 1: kernel times, 2: also bond statistics
   int wclk_khz = 100000;           // device wall-clock rate
-  double timing_out[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // launch counts (3, 6) kept on the host
+  double timing_out[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // launch counts (3, 6, 10) kept on the host
   double* tacc = nullptr;          // device sums of the times, bytes and flops since timing was set
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
@@ -328,14 +328,14 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
   // 64 byte counters (spread to keep atomics uncontended), then the sweep maxima
   // 64 byte counters, the sweep maxima, 64 flop counters (spread to keep atomics uncontended)
-  size_t o_ctr = cv.take<unsigned long long>(129);
+  size_t o_ctr = cv.take<unsigned long long>(193);
   // timing: stamps 0 start, 1 after the layers, 2 end; execution windows of
   // the Gram and reabsorption launches of each gate class (2 per class) and
   // of the decomposition launch of each boundary-MPS step
   const size_t n_stamp = 3;
   size_t o_stamp = cv.take<unsigned long long>(n_stamp);
   const int n_cls_win = int(P.layers.size()) * 4 * 2;
-  const int n_win = n_cls_win + P.Lx * P.Ly;
+  const int n_win = n_cls_win + 2 * P.Lx * P.Ly;
   size_t o_win = cv.take<unsigned long long>(size_t(n_win) * 128);
   size_t o_gitems = cv.take<int32_t>(chunk_items);
   size_t o_gsoff = cv.take<int64_t>(chunk_items);
@@ -355,7 +355,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (items[i] != items[0] + int32_t(i)) contiguous = false;
 
   const int timing = c->timing;
-  double hot_launches = 0, eig_launches = 0;
+  double hot_launches = 0, eig_launches = 0, zip_launches = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
     const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
     int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
@@ -408,7 +408,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.synd = synd_p;
     A.synd_off = soff_p;
     A.items = items_p;
-    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 258, s);
+    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 386, s);
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     unsigned long long* stamp = reinterpret_cast<unsigned long long*>(ws + o_stamp);
@@ -489,15 +489,18 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.zdim = reinterpret_cast<int32_t*>(ws + o_zdim);
     Z.zS = reinterpret_cast<double*>(ws + o_zS);
     Z.flop_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 65 * 8) : nullptr;
+    Z.flop_a = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 129 * 8) : nullptr;
     Z.Gm = reinterpret_cast<double*>(ws + o_Gm);
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
       for (int x = 0; x < P.Lx; ++x)
       {
         Z.win = timing ? win + size_t(n_cls_win + y * P.Lx + x) * 128 : nullptr;
+        Z.win_a = timing ? win + size_t(n_cls_win + P.Lx * P.Ly + y * P.Lx + x) * 128 : nullptr;
         launch_zip_step(Z, x, y, L.legcap, s);
       }
     Z.win = nullptr;
+    Z.win_a = nullptr;
     launch_finish(A, Z, logp_p, flags_p, s);
     if (timing) {
       launch_stamp(stamp + 2, s);
@@ -577,6 +580,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     hot_launches += hot_l;
     // the last row's decompositions are done inside the contraction kernel
     if (timing && gram_path) eig_launches += double(P.Ly - 1) * (P.Lx - 1);
+    if (timing) zip_launches += double(P.Ly) * P.Lx;
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
       std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
@@ -603,6 +607,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   if (timing) {  // times, bytes and flops are summed on the device (tacc)
     c->timing_out[3] += hot_launches;
     c->timing_out[6] += eig_launches;
+    c->timing_out[10] += zip_launches;
   }
   return TN3D_OK;
 }
@@ -702,7 +707,7 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
     return TN3D_E_DEVICE;
   }
   c->wclk_khz = rate;
-  if (hipMalloc(&c->tacc, 8 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 8 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&c->tacc, 10 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 10 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     if (c->tacc) (void)hipFree(c->tacc);
     delete c;
@@ -878,10 +883,11 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   uint32_t* fls = reinterpret_cast<uint32_t*>(c->aux + o_fls);
   launch_gather_offsets(cnt, d_items, offs, d_offs, c->stream);
   HIPCHK(c, hipMemsetAsync(fls, 0, size_t(cnt) * 4, c->stream));
-  tn3d_params p64;
-  tn3d_params_default(&p64, pr->chi, pr->chi_mps, TN3D_PREC_FP64);
-  p64.near_tie = pr->near_tie;
-  p64.flags = TN3D_OPT_GRAM_FACTOR;  // decisions: the faster FP64 route suffices
+  // the same chi, chi_mps and rank rule in FP64, through Grams (the decision
+  // needs far less than that route's accuracy)
+  tn3d_params p64 = *pr;
+  p64.precision = TN3D_PREC_FP64;
+  p64.flags = TN3D_OPT_GRAM_FACTOR;
   p64.workspace_bytes = pr->workspace_bytes;
   const bool timing = c->timing;
   c->timing = false;  // the timing figures stay those of the main pass
@@ -898,9 +904,9 @@ tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   HIPCHK(c, hipSetDevice(c->device));
   c->timing = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
   // the sums restart here (ordered after the work already on the stream)
-  for (int k = 0; k < 8; ++k) c->timing_out[k] = 0;
+  for (int k = 0; k < 11; ++k) c->timing_out[k] = 0;
   for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
-  HIPCHK(c, hipMemsetAsync(c->tacc, 0, 8 * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->tacc, 0, 10 * sizeof(double), c->stream));
   return TN3D_OK;
 }
 
@@ -920,12 +926,13 @@ tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
   if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
   HIPCHK(c, hipSetDevice(c->device));
-  double d[8];
-  HIPCHK(c, hipMemcpyAsync(d, c->tacc, sizeof(d), hipMemcpyDeviceToHost, c->stream));
+  double d[11];
+  HIPCHK(c, hipMemcpyAsync(d, c->tacc, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   d[3] = c->timing_out[3];
   d[6] = c->timing_out[6];
-  for (int i = 0; i < n && i < 8; ++i) out[i] = d[i];
+  d[10] = c->timing_out[10];
+  for (int i = 0; i < n && i < 11; ++i) out[i] = d[i];
   return TN3D_OK;
 }
 

@@ -68,6 +68,8 @@ struct ZipArgs {
   unsigned long long* win;       // execution window of the decomposition launch, or null
   double sub_tol;                // subspace iteration: residual bound relative to the largest eigenvalue
   int32_t bf_theta;              // 1: Theta on the BF16 matrix cores (reduced precisions)
+  unsigned long long* win_a;     // execution window of the contraction launch (k_zip_a), or null
+  unsigned long long* flop_a;    // 64 counters of the contraction's algorithmic flops, or null
 };
 
 // Raises the dynamic-LDS limits of the kernels that need more than 64 KB;
@@ -117,7 +119,9 @@ void launch_win_init(unsigned long long* win, int n, hipStream_t st);
 // Adds one contraction's times to acc: acc[0] layers (stamps 0..1), acc[1]
 // boundary MPS (stamps 1..2), acc[2] the windows [0, n_cls_win) (Gram and
 // reabsorption), acc[4] bytes (ctr[0..64)), acc[5] the decomposition windows
-// of steps x < Lx - 1 (if eig), acc[7] flops (ctr[65..129)); milliseconds.
+// of steps x < Lx - 1 (if eig, windows n_cls_win + step), acc[7] their flops
+// (ctr[65..129)), acc[8] the contraction windows (n_cls_win + Lx Ly + step),
+// acc[9] their flops (ctr[129..193)); milliseconds.
 void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
                           int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
                           hipStream_t st);

@@ -1468,6 +1468,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
   __shared__ double gst[GEMM_LDS];
   __shared__ double red[16];
   const int s = blockIdx.x, tid = threadIdx.x;
+  const unsigned long long w0 = win_open(Z.win_a);
   const int cur = y & 1;
   const double* Mold = (cur ? Z.mps1 : Z.mps0) + (int64_t(s) * Z.Lx + x) * Z.mcap;
   int sd, aR, wL, wR, nU, sD;
@@ -1522,6 +1523,12 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
           C, C, R, [&](int m, int k) { return Th[k * C + m]; }, [&](int k, int n) { return Th[k * C + n]; },
           [&](int m, int n, double v) { G[m * C + n] = v; }, gst);
   }
+  if (Z.flop_a && tid == 0) {
+    // algorithmic flops: the two contractions and, on the Gram route, the Gram
+    double f = 2.0 * (nu * wL) * double(sa) * ka + 2.0 * double(nu * aR) * double(wR * sD) * double(wL * sd);
+    if (!inline_dec && x + 1 < Z.Lx && Z.gram_path) f += rows ? 2.0 * R * double(R) * C : 2.0 * C * double(C) * R;
+    atomicAdd(Z.flop_a + (s & 63), (unsigned long long)f);
+  }
   if (tid == 0) {
     int* zd = Z.zdim + int64_t(s) * 12;
     zd[0] = R;
@@ -1534,6 +1541,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
     zd[7] = nv;
     zd[8] = 1;
   }
+  win_close(Z.win_a, w0);
 }
 
 // Rank rule on the sorted singular values Sout of the smaller family, then the
@@ -2282,30 +2290,32 @@ __global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned
                                 int Lx, int Ly, int eig, const unsigned long long* ctr, double ms_per_tick,
                                 double* acc) {
   const int w = blockIdx.x, l = threadIdx.x;
-  const int n_win = n_cls_win + Lx * Ly;
+  const int n_win = n_cls_win + 2 * Lx * Ly;
   if (w < n_win) {
-    const bool zip = w >= n_cls_win;
-    const int xy = w - n_cls_win;
-    if (zip && (!eig || xy % Lx + 1 >= Lx)) return;
+    const int kind = w < n_cls_win ? 0 : (w < n_cls_win + Lx * Ly ? 1 : 2);  // class, decomposition, contraction
+    const int xy = (w - n_cls_win) % (Lx * Ly);
+    if (kind == 1 && (!eig || xy % Lx + 1 >= Lx)) return;
     unsigned long long t0 = win[size_t(w) * 128 + l], t1 = win[size_t(w) * 128 + 64 + l];
     for (int o = 32; o > 0; o >>= 1) {
       const unsigned long long u0 = __shfl_xor(t0, o, 64), u1 = __shfl_xor(t1, o, 64);
       t0 = u0 < t0 ? u0 : t0;
       t1 = u1 > t1 ? u1 : t1;
     }
-    if (l == 0 && t1 > t0) atomicAdd(acc + (zip ? 5 : 2), double(t1 - t0) * ms_per_tick);
+    if (l == 0 && t1 > t0) atomicAdd(acc + (kind == 0 ? 2 : (kind == 1 ? 5 : 8)), double(t1 - t0) * ms_per_tick);
     return;
   }
-  unsigned long long b = ctr[l], f = ctr[65 + l];
+  unsigned long long b = ctr[l], f = ctr[65 + l], fa = ctr[129 + l];
   for (int o = 32; o > 0; o >>= 1) {
     b += __shfl_xor(b, o, 64);
     f += __shfl_xor(f, o, 64);
+    fa += __shfl_xor(fa, o, 64);
   }
   if (l == 0) {
     acc[0] += double(stamps[1] - stamps[0]) * ms_per_tick;
     acc[1] += double(stamps[2] - stamps[1]) * ms_per_tick;
     acc[4] += double(b);
     acc[7] += double(f);
+    acc[9] += double(fa);
   }
 }
 
@@ -2582,8 +2592,8 @@ void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_
 void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
                           int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_timing_reduce, dim3(n_cls_win + Lx * Ly + 1), dim3(64), 0, st, stamps, win, n_cls_win, Lx, Ly,
-                     eig, ctr, ms_per_tick, acc);
+  hipLaunchKernelGGL(k_timing_reduce, dim3(n_cls_win + 2 * Lx * Ly + 1), dim3(64), 0, st, stamps, win, n_cls_win, Lx,
+                     Ly, eig, ctr, ms_per_tick, acc);
 }
 
 void launch_win_init(unsigned long long* win, int n, hipStream_t st) {
