@@ -186,6 +186,22 @@ tn3d_status tn3d_contract_cosets(tn3d_ctx ctx, int32_t batch, const tn3d_net* ne
                                  const uint8_t* syndromes_dev, const int64_t* offsets_dev,
                                  const tn3d_params* params, double* logp_dev, uint32_t* flags_dev);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): tn3d_contract_cosets
+ * with the same arguments, results and errors, except that its workspace is
+ * a fixed device array of TN3D_NOALLOC_BYTES that the library holds on every
+ * GPU it runs on until the process ends (no hipMalloc, hipFree or graph
+ * instantiation: the launches are issued eagerly).  Items are processed in
+ * chunks that fit the array; an item that alone needs more returns
+ * TN3D_E_OOM with the sizes in tn3d_last_error.  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind (the kernels initialise
+ * what they read): calls that overlap in time on one GPU, from any context or
+ * thread, race and must be serialised by the caller. */
+#define TN3D_NOALLOC_BYTES (256ull << 20)
+tn3d_status tn3d_contract_cosets_noalloc(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
+                                         const uint8_t* syndromes_dev, const int64_t* offsets_dev,
+                                         const tn3d_params* params, double* logp_dev, uint32_t* flags_dev);
+
 /* Decode (paper Sec. 2.3, eq. optimal_decoder): as tn3d_contract_cosets, then
  * per item coset_dev[i] = argmax_L log p_{m,L} (lowest index on exact ties),
  * logratio_dev[i] = log p of the chosen coset minus the largest other one

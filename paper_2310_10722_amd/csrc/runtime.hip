@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -18,6 +19,15 @@
 #include "sweep.h"
 
 using namespace tn3d;
+
+// Workspace of tn3d_contract_cosets_noalloc: a fixed device array, one copy
+// per GPU the library runs on, held until the process ends.  Host code never
+// uses its name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device when a context is created on it.
+constexpr size_t NOALLOC_BYTES = size_t(256) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;  // device -> address of scratch there
 
 // A captured per-chunk launch sequence is valid for one network, parameter
 // set, chunk shape, timing mode and workspace allocation.
@@ -56,6 +66,7 @@ struct tn3d_ctx_s {
   int last_resweeps = 0;           // items the last decode re-swept in FP64
   char* aux = nullptr;             // decode scratch
   size_t aux_bytes = 0;
+  char* scratch = nullptr;         // this device's copy of the static scratch array
   bool graphs = true;              // replay captured launch sequences
   hipStream_t cap_stream = nullptr;  // private stream the sequences are captured on
   uint64_t next_serial = 1;
@@ -263,9 +274,11 @@ tn3d_status ensure_ws(tn3d_ctx c, size_t bytes) {
 }
 
 // Contracts items[0..n_items) (global item indices, all using net `n`).
+// noalloc: the workspace is the device's static scratch array (no device
+// allocation, eager launches: graph instantiation allocates).
 tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items, const uint8_t* synd,
                       const int64_t* synd_off, const tn3d_params& pr, double* logp, uint32_t* flags_out,
-                      int prec) {
+                      int prec, bool noalloc) {
   const Program& P = n->P;
   const int nc = P.n_cosets;
   const int max_g = std::max(1, n->max_gates_class);
@@ -276,7 +289,10 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   if (int64_t(pr.chi_mps) * L.legcap > 1024) return fail(c, TN3D_E_UNSUPPORTED, "chi_mps x chi above 1024");
   if (P.Lx * P.Ly > 65535) return fail(c, TN3D_E_UNSUPPORTED, "grid too large");
   size_t budget;
-  if (pr.workspace_bytes > 0) {
+  if (noalloc) {
+    budget = NOALLOC_BYTES;
+    if (pr.workspace_bytes > 0) budget = std::min(budget, size_t(pr.workspace_bytes));
+  } else if (pr.workspace_bytes > 0) {
     budget = size_t(pr.workspace_bytes);
   } else {
     size_t fr = 0, tot = 0;
@@ -284,7 +300,13 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     budget = size_t(0.85 * double(fr + c->ws_bytes));
   }
   const size_t fixed = size_t(items.size()) * 4 + (64 << 10);
-  if (budget <= fixed + L.per_sweep_bytes * nc) return fail(c, TN3D_E_OOM, "workspace cap below one item");
+  if (budget <= fixed + L.per_sweep_bytes * nc) {
+    if (noalloc)
+      return fail(c, TN3D_E_OOM, "one item needs " + std::to_string(fixed + L.per_sweep_bytes * nc) +
+                                     " bytes of workspace, beyond the " + std::to_string(budget) +
+                                     "-byte static scratch of tn3d_contract_cosets_noalloc");
+    return fail(c, TN3D_E_OOM, "workspace cap below one item");
+  }
   int64_t chunk_items = int64_t((budget - fixed) / (L.per_sweep_bytes * nc));
   chunk_items = std::max<int64_t>(1, std::min<int64_t>(chunk_items, int64_t(items.size())));
   chunk_items = std::min<int64_t>(chunk_items, 65535 / nc);  // grid y dimension
@@ -344,9 +366,15 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_gsynd = cv.take<uint8_t>(chunk_items * bstride);
   size_t o_glp = cv.take<double>(chunk_items * 4);
   size_t o_gfl = cv.take<uint32_t>(chunk_items);
-  tn3d_status st = ensure_ws(c, cv.off);
-  if (st != TN3D_OK) return st;
-  char* ws = c->ws;
+  char* ws = nullptr;
+  if (noalloc) {
+    if (!c->scratch || cv.off > NOALLOC_BYTES) return fail(c, TN3D_E_OOM, "static scratch unavailable or too small");
+    ws = c->scratch;
+  } else {
+    tn3d_status st = ensure_ws(c, cv.off);
+    if (st != TN3D_OK) return st;
+    ws = c->ws;
+  }
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(ws + o_soff, L.site_off.data(), L.site_off.size() * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(ws + o_foff, L.fin_off.data(), L.fin_off.size() * 8, hipMemcpyHostToDevice, s));
@@ -521,7 +549,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       launch_gather_synd(ni, d_items, synd, synd_off, P.n_det, bstride, g_synd, s);
       launch_ext_bits(ni, g_synd, bstride, P.n_det, P.ext_src0, P.ext_src_n, P.ext_words, n->d_ext, P.n_ext, s);
     };
-    if (c->graphs) {
+    if (c->graphs && !noalloc) {
       // inputs into the workspace, replay (capturing first if needed), results out
       gather_inputs();
       HIPCHK(c, hipGetLastError());
@@ -641,7 +669,8 @@ bool params_ok(const tn3d_params* p, std::string& why) {
 }
 
 tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
-                          const int64_t* offs, const tn3d_params* pr, double* logp, uint32_t* flags) {
+                          const int64_t* offs, const tn3d_params* pr, double* logp, uint32_t* flags,
+                          bool noalloc = false) {
   if (!c) return TN3D_E_INVALID;
   c->err.clear();
   std::string why;
@@ -663,7 +692,7 @@ tn3d_status contract_impl(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
     groups[nets[i]].push_back(i);
   }
   for (tn3d_net n : order) {
-    tn3d_status s = run_group(c, n, groups[n], synd, offs, *pr, logp, flags, pr->precision);
+    tn3d_status s = run_group(c, n, groups[n], synd, offs, *pr, logp, flags, pr->precision, noalloc);
     if (s != TN3D_OK) return s;
   }
   return TN3D_OK;
@@ -707,6 +736,21 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
     return TN3D_E_DEVICE;
   }
   c->wclk_khz = rate;
+  {
+    // this device's address of the static scratch array, taken once per device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        delete c;
+        return TN3D_E_DEVICE;
+      }
+      it = g_scratch_ptr.emplace(device, static_cast<char*>(ptr)).first;
+    }
+    c->scratch = it->second;
+  }
   if (hipMalloc(&c->tacc, 10 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 10 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     if (c->tacc) (void)hipFree(c->tacc);
@@ -798,6 +842,12 @@ tn3d_status tn3d_ctx_set_graphs(tn3d_ctx c, int32_t enable) {
 tn3d_status tn3d_contract_cosets(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
                                  const int64_t* offs, const tn3d_params* pr, double* logp, uint32_t* flags) {
   return contract_impl(c, batch, nets, synd, offs, pr, logp, flags);
+}
+
+tn3d_status tn3d_contract_cosets_noalloc(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
+                                         const int64_t* offs, const tn3d_params* pr, double* logp,
+                                         uint32_t* flags) {
+  return contract_impl(c, batch, nets, synd, offs, pr, logp, flags, true);
 }
 
 // Decision for each item of a batch from its coset log-probabilities, grouped

@@ -36,7 +36,8 @@ SYMBOLS = [
     "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_surface3d_depolarizing",
     "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
-    "tn3d_contract_cosets", "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_last_stats",
+    "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
+    "tn3d_last_timing", "tn3d_last_stats",
     "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached",
 ]
 
@@ -82,6 +83,7 @@ def load_library(path: str | None = None):
     lib.tn3d_net_destroy.restype = None
     lib.tn3d_contract_cosets.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params), c_p,
                                          c_p]
+    lib.tn3d_contract_cosets_noalloc.argtypes = lib.tn3d_contract_cosets.argtypes
     lib.tn3d_decode.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params), c_p, c_p, c_p,
                                 c_p]
     lib.tn3d_ctx_set_timing.argtypes = [c_p, i32]
@@ -92,7 +94,7 @@ def load_library(path: str | None = None):
     lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
-              "tn3d_net_surface3d_depolarizing", "tn3d_contract_cosets",
+              "tn3d_net_surface3d_depolarizing", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
               "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_ctx_set_graphs"):
         getattr(lib, f).restype = i32
     if path is None:
@@ -254,6 +256,23 @@ def tn3d_contract_cosets(ctx: Context, nets, syndromes, params: Params):
     st = ctx.lib.tn3d_contract_cosets(ctx.h, B, arr, ctypes.c_void_p(syn.data_ptr()),
                                       ctypes.c_void_p(offs.data_ptr()), ctypes.byref(params),
                                       ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(flags.data_ptr()))
+    _check(ctx.lib, ctx.h, st)
+    return logp, flags
+
+
+def tn3d_contract_cosets_noalloc(ctx: Context, nets, syndromes, params: Params, logp=None, flags=None):
+    """As tn3d_contract_cosets, on the library's static device scratch (no
+    device allocation inside the call); logp [batch, 4] float64 and flags
+    [batch] int32 CUDA tensors may be passed in, else they are made here."""
+    import torch
+    nets, syn, offs, arr, B = _batch_args(nets, syndromes)
+    if logp is None:
+        logp = torch.empty((B, 4), dtype=torch.float64, device=syn.device)
+    if flags is None:
+        flags = torch.zeros((B,), dtype=torch.int32, device=syn.device)
+    st = ctx.lib.tn3d_contract_cosets_noalloc(ctx.h, B, arr, ctypes.c_void_p(syn.data_ptr()),
+                                              ctypes.c_void_p(offs.data_ptr()), ctypes.byref(params),
+                                              ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(flags.data_ptr()))
     _check(ctx.lib, ctx.h, st)
     return logp, flags
 
