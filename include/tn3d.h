@@ -241,8 +241,11 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * 2n^2 b + 14 n b^2 with b = 64 for the subspace iteration of larger families),
  * out[8] = time of the boundary-MPS contraction launches (the two
  * contractions forming Theta and, on the Gram route, its Gram), out[9] = their
- * algorithmic flops, out[10] = their number.  Milliseconds for times; n <= 11
- * values are written.
+ * algorithmic flops, out[10] = their number, out[11] = time of the
+ * subspace-iteration launches (boundary-MPS families above 64 vectors on the
+ * Gram route; out[5] then covers only the one-wavefront solver), out[12] =
+ * their algorithmic flops, out[13] = their number.  Milliseconds for times;
+ * n <= 14 values are written.
  * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);

@@ -59,7 +59,7 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   int timing = 0;                  // 1: kernel times, 2: also bond statistics
   int wclk_khz = 100000;           // device wall-clock rate
-  double timing_out[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // launch counts (3, 6, 10) kept on the host
+  double timing_out[14] = {};  // launch counts (3, 6, 10, 13) kept on the host
   double* tacc = nullptr;          // device sums of the times, bytes and flops since timing was set
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
@@ -350,14 +350,14 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_zfl = cv.take<uint32_t>(nsw_max);
   // 64 byte counters (spread to keep atomics uncontended), then the sweep maxima
   // 64 byte counters, the sweep maxima, 64 flop counters (spread to keep atomics uncontended)
-  size_t o_ctr = cv.take<unsigned long long>(193);
+  size_t o_ctr = cv.take<unsigned long long>(257);
   // timing: stamps 0 start, 1 after the layers, 2 end; execution windows of
   // the Gram and reabsorption launches of each gate class (2 per class) and
   // of the decomposition launch of each boundary-MPS step
   const size_t n_stamp = 3;
   size_t o_stamp = cv.take<unsigned long long>(n_stamp);
   const int n_cls_win = int(P.layers.size()) * 4 * 2;
-  const int n_win = n_cls_win + 2 * P.Lx * P.Ly;
+  const int n_win = n_cls_win + 3 * P.Lx * P.Ly;
   size_t o_win = cv.take<unsigned long long>(size_t(n_win) * 128);
   size_t o_gitems = cv.take<int32_t>(chunk_items);
   size_t o_gsoff = cv.take<int64_t>(chunk_items);
@@ -383,7 +383,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (items[i] != items[0] + int32_t(i)) contiguous = false;
 
   const int timing = c->timing;
-  double hot_launches = 0, eig_launches = 0, zip_launches = 0;
+  double hot_launches = 0, eig_launches = 0, zip_launches = 0, bsub_launches = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
     const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
     int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
@@ -436,7 +436,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.synd = synd_p;
     A.synd_off = soff_p;
     A.items = items_p;
-    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 386, s);
+    launch_zero_words(reinterpret_cast<uint32_t*>(ws + o_ctr), 514, s);
     double* gram = reinterpret_cast<double*>(ws + o_gram);
     double* wbuf = reinterpret_cast<double*>(ws + o_w);
     unsigned long long* stamp = reinterpret_cast<unsigned long long*>(ws + o_stamp);
@@ -518,6 +518,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     Z.zS = reinterpret_cast<double*>(ws + o_zS);
     Z.flop_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 65 * 8) : nullptr;
     Z.flop_a = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 129 * 8) : nullptr;
+    Z.flop_b = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr + 193 * 8) : nullptr;
     Z.Gm = reinterpret_cast<double*>(ws + o_Gm);
     launch_zip_init(Z, s);
     for (int y = 0; y < P.Ly; ++y)
@@ -525,10 +526,12 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       {
         Z.win = timing ? win + size_t(n_cls_win + y * P.Lx + x) * 128 : nullptr;
         Z.win_a = timing ? win + size_t(n_cls_win + P.Lx * P.Ly + y * P.Lx + x) * 128 : nullptr;
+        Z.win_b = timing ? win + size_t(n_cls_win + 2 * P.Lx * P.Ly + y * P.Lx + x) * 128 : nullptr;
         launch_zip_step(Z, x, y, L.legcap, s);
       }
     Z.win = nullptr;
     Z.win_a = nullptr;
+    Z.win_b = nullptr;
     launch_finish(A, Z, logp_p, flags_p, s);
     if (timing) {
       launch_stamp(stamp + 2, s);
@@ -608,7 +611,17 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     hot_launches += hot_l;
     // the last row's decompositions are done inside the contraction kernel
     if (timing && gram_path) eig_launches += double(P.Ly - 1) * (P.Lx - 1);
-    if (timing) zip_launches += double(P.Ly) * P.Lx;
+    if (timing) {
+      // (from the host's own parameters: replays do not fill Z)
+      ZipArgs zq{};
+      zq.Lx = P.Lx;
+      zq.Ly = P.Ly;
+      zq.chi_m = pr.chi_mps;
+      zq.gram_path = gram_path ? 1 : 0;
+      zip_launches += double(P.Ly) * P.Lx;
+      for (int y = 0; y < P.Ly; ++y)
+        for (int x = 0; x < P.Lx; ++x) bsub_launches += zip_step_large(zq, x, y, L.legcap) == 1 ? 1 : 0;
+    }
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
       std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
@@ -636,6 +649,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     c->timing_out[3] += hot_launches;
     c->timing_out[6] += eig_launches;
     c->timing_out[10] += zip_launches;
+    c->timing_out[13] += bsub_launches;
   }
   return TN3D_OK;
 }
@@ -751,7 +765,7 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
     }
     c->scratch = it->second;
   }
-  if (hipMalloc(&c->tacc, 10 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 10 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&c->tacc, 12 * sizeof(double)) != hipSuccess || hipMemset(c->tacc, 0, 12 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     if (c->tacc) (void)hipFree(c->tacc);
     delete c;
@@ -954,9 +968,9 @@ tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   HIPCHK(c, hipSetDevice(c->device));
   c->timing = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
   // the sums restart here (ordered after the work already on the stream)
-  for (int k = 0; k < 11; ++k) c->timing_out[k] = 0;
+  for (int k = 0; k < 14; ++k) c->timing_out[k] = 0;
   for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
-  HIPCHK(c, hipMemsetAsync(c->tacc, 0, 10 * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->tacc, 0, 12 * sizeof(double), c->stream));
   return TN3D_OK;
 }
 
@@ -976,13 +990,18 @@ tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   if (!c || !out) return TN3D_E_INVALID;
   if (!c->timing) return fail(c, TN3D_E_INVALID, "timing not enabled");
   HIPCHK(c, hipSetDevice(c->device));
-  double d[11];
-  HIPCHK(c, hipMemcpyAsync(d, c->tacc, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double acc[12];
+  HIPCHK(c, hipMemcpyAsync(acc, c->tacc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  double d[14];
+  for (int i = 0; i < 10; ++i) d[i] = acc[i];
   d[3] = c->timing_out[3];
   d[6] = c->timing_out[6];
   d[10] = c->timing_out[10];
-  for (int i = 0; i < n && i < 11; ++i) out[i] = d[i];
+  d[11] = acc[10];
+  d[12] = acc[11];
+  d[13] = c->timing_out[13];
+  for (int i = 0; i < n && i < 14; ++i) out[i] = d[i];
   return TN3D_OK;
 }
 

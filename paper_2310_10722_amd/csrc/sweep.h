@@ -70,6 +70,8 @@ struct ZipArgs {
   int32_t bf_theta;              // 1: Theta on the BF16 matrix cores (reduced precisions)
   unsigned long long* win_a;     // execution window of the contraction launch (k_zip_a), or null
   unsigned long long* flop_a;    // 64 counters of the contraction's algorithmic flops, or null
+  unsigned long long* win_b;     // execution window of the subspace-iteration launch (k_zip_bsub), or null
+  unsigned long long* flop_b;    // 64 counters of its algorithmic flops, or null
 };
 
 // Raises the dynamic-LDS limits of the kernels that need more than 64 KB;
@@ -98,6 +100,9 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st);
 // one zip-up step (x, y) of the boundary MPS: contraction, decomposition (all
 // but the last column), new site and carry; legcap bounds the network's bonds
 void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st);
+// Whether step (x, y) decomposes a family above 64 vectors: 1 by subspace
+// iteration (k_zip_bsub), 2 by the full eigen-decomposition (k_zip_bbig), 0 not.
+int zip_step_large(const ZipArgs& Z, int x, int y, int legcap);
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st);
 // Graph replay helpers: gather each item's syndrome into a dense buffer,
 // local item indices with their offsets, zero a counter block (no memset
@@ -121,7 +126,9 @@ void launch_win_init(unsigned long long* win, int n, hipStream_t st);
 // reabsorption), acc[4] bytes (ctr[0..64)), acc[5] the decomposition windows
 // of steps x < Lx - 1 (if eig, windows n_cls_win + step), acc[7] their flops
 // (ctr[65..129)), acc[8] the contraction windows (n_cls_win + Lx Ly + step),
-// acc[9] their flops (ctr[129..193)); milliseconds.
+// acc[9] their flops (ctr[129..193)), acc[10] the subspace-iteration windows
+// (n_cls_win + 2 Lx Ly + step), acc[11] their flops (ctr[193..257));
+// milliseconds.
 void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
                           int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
                           hipStream_t st);

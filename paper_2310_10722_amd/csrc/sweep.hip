@@ -1487,19 +1487,47 @@ __global__ __launch_bounds__(ZNT) void k_zip_a(ZipArgs Z, int x, int y, int inli
   double* L4 = Z.L4 + int64_t(s) * Z.bigcap;
   double* Th = Z.Th + int64_t(s) * Z.bigcap;
   const int sa = sd * aR;
-  block_gemm512(
-      nu * wL, sa, ka, [&](int m, int k) { return Kp[((m / wL) * ka + k) * wL + m % wL]; },
-      [&](int k, int n) { return Mold[k * sa + n]; }, [&](int m, int n, double v) { L4[m * sa + n] = v; }, gst);
   const int R = nu * sD, C = aR * wR;
-  auto l4_at = [&](int m, int k) { return L4[(((m / aR) * wL + k / sd) * sd + k % sd) * aR + m % aR]; };
-  auto t_at = [&](int k, int n) { return Tt[(((k / sd) * wR + n / sD) * nU + k % sd) * sD + n % sD]; };
-  auto th_put = [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; };
-  // the reduced precisions form Theta on the BF16 matrix cores (FP32-accurate
-  // products of the FP32-accurate tensors); FP64 on the FP64 ones
-  if (Z.bf_theta)
-    block_gemm512_bf(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
-  else
-    block_gemm512(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+  // The operand offsets of both contractions separate into a row part and a
+  // column part (e.g. L4[nu, w, n, a'] at (m / aR) wL sd aR + m % aR + k aR);
+  // the parts are tabulated once in LDS so the fetches do no division.
+  constexpr int TAB = 1024;
+  __shared__ int tm[TAB], tk[TAB], tn[TAB], tn2[TAB];
+  const bool tabs = nu * wL <= TAB && nu * aR <= TAB && wL * sd <= TAB && wR * sD <= TAB;
+  if (tabs) {
+    for (int m = tid; m < nu * wL; m += ZNT) tm[m] = (m / wL) * ka * wL + m % wL;
+    __syncthreads();
+    block_gemm512(
+        nu * wL, sa, ka, [&](int m, int k) { return Kp[tm[m] + k * wL]; }, [&](int k, int n) { return Mold[k * sa + n]; },
+        [&](int m, int n, double v) { L4[m * sa + n] = v; }, gst);
+    for (int m = tid; m < nu * aR; m += ZNT) tm[m] = (m / aR) * wL * sd * aR + m % aR;
+    for (int k = tid; k < wL * sd; k += ZNT) tk[k] = (k / sd) * wR * nU * sD + (k % sd) * sD;
+    for (int n = tid; n < wR * sD; n += ZNT) {
+      tn[n] = (n / sD) * nU * sD + n % sD;
+      tn2[n] = (n % sD) * C + n / sD;
+    }
+    __syncthreads();
+    auto l4_at = [&](int m, int k) { return L4[tm[m] + k * aR]; };
+    auto t_at = [&](int k, int n) { return Tt[tk[k] + tn[n]]; };
+    auto th_put = [&](int m, int n, double v) { Th[(m / aR) * sD * C + (m % aR) * wR + tn2[n]] = v; };
+    // the reduced precisions form Theta on the BF16 matrix cores (FP32-accurate
+    // products of the FP32-accurate tensors); FP64 on the FP64 ones
+    if (Z.bf_theta)
+      block_gemm512_bf(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+    else
+      block_gemm512(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+  } else {
+    block_gemm512(
+        nu * wL, sa, ka, [&](int m, int k) { return Kp[((m / wL) * ka + k) * wL + m % wL]; },
+        [&](int k, int n) { return Mold[k * sa + n]; }, [&](int m, int n, double v) { L4[m * sa + n] = v; }, gst);
+    auto l4_at = [&](int m, int k) { return L4[(((m / aR) * wL + k / sd) * sd + k % sd) * aR + m % aR]; };
+    auto t_at = [&](int k, int n) { return Tt[(((k / sd) * wR + n / sD) * nU + k % sd) * sD + n % sD]; };
+    auto th_put = [&](int m, int n, double v) { Th[((m / aR) * sD + n % sD) * C + (m % aR) * wR + n / sD] = v; };
+    if (Z.bf_theta)
+      block_gemm512_bf(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+    else
+      block_gemm512(nu * aR, wR * sD, wL * sd, l4_at, t_at, th_put, gst);
+  }
   const bool rows = R <= C;
   const int nv = rows ? R : C;
   if (inline_dec) {
@@ -1991,7 +2019,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   int* zd = Z.zdim + int64_t(s) * 12;
   const int nv = zd[7];
   if (nv <= ZBIG) return;
-  const unsigned long long w0 = win_open(Z.win);
+  const unsigned long long w0 = win_open(Z.win_b);
   const double* G = Z.Gm + int64_t(s) * Z.bigcap;
   double* X = Z.Jm + int64_t(s) * Z.jcap;
   double* Y = X + int64_t(nv) * SB;
@@ -2090,12 +2118,12 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   if (bad) Dn = 1;
   double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
   for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = U[(e / Dn) * SB + e % Dn];
-  if (Z.flop_ctr && tid == 0) {
+  if (Z.flop_b && tid == 0) {
     // algorithmic flops per iteration: the block product 2 nv^2 SB, the
     // Ritz projection and rotations 6 nv SB^2, Cholesky QR twice 8 nv SB^2
     const double n = nv, b = SB;
     const double f = double(it + 1) * (2.0 * n * n * b + 14.0 * n * b * b);
-    atomicAdd(Z.flop_ctr + (s & 63), (unsigned long long)f);
+    atomicAdd(Z.flop_b + (s & 63), (unsigned long long)f);
   }
   if (tid == 0) {
     zd[8] = Dn;
@@ -2103,7 +2131,7 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
     const uint32_t f = (bad ? 1u : 0u) | (split ? 2u : 0u) | (conv ? 0u : 8u);
     if (f) atomicOr(&Z.flags[s], f);
   }
-  win_close(Z.win, w0);
+  win_close(Z.win_b, w0);
 }
 
 // (at most 80 registers: six wavefronts per SIMD)
@@ -2290,9 +2318,11 @@ __global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned
                                 int Lx, int Ly, int eig, const unsigned long long* ctr, double ms_per_tick,
                                 double* acc) {
   const int w = blockIdx.x, l = threadIdx.x;
-  const int n_win = n_cls_win + 2 * Lx * Ly;
+  const int n_win = n_cls_win + 3 * Lx * Ly;
   if (w < n_win) {
-    const int kind = w < n_cls_win ? 0 : (w < n_cls_win + Lx * Ly ? 1 : 2);  // class, decomposition, contraction
+    // class windows, then per boundary-MPS step: small decomposition,
+    // contraction, large decomposition (subspace iteration)
+    const int kind = w < n_cls_win ? 0 : 1 + (w - n_cls_win) / (Lx * Ly);
     const int xy = (w - n_cls_win) % (Lx * Ly);
     if (kind == 1 && (!eig || xy % Lx + 1 >= Lx)) return;
     unsigned long long t0 = win[size_t(w) * 128 + l], t1 = win[size_t(w) * 128 + 64 + l];
@@ -2301,14 +2331,16 @@ __global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned
       t0 = u0 < t0 ? u0 : t0;
       t1 = u1 > t1 ? u1 : t1;
     }
-    if (l == 0 && t1 > t0) atomicAdd(acc + (kind == 0 ? 2 : (kind == 1 ? 5 : 8)), double(t1 - t0) * ms_per_tick);
+    const int slot = kind == 0 ? 2 : (kind == 1 ? 5 : (kind == 2 ? 8 : 10));
+    if (l == 0 && t1 > t0) atomicAdd(acc + slot, double(t1 - t0) * ms_per_tick);
     return;
   }
-  unsigned long long b = ctr[l], f = ctr[65 + l], fa = ctr[129 + l];
+  unsigned long long b = ctr[l], f = ctr[65 + l], fa = ctr[129 + l], fb = ctr[193 + l];
   for (int o = 32; o > 0; o >>= 1) {
     b += __shfl_xor(b, o, 64);
     f += __shfl_xor(f, o, 64);
     fa += __shfl_xor(fa, o, 64);
+    fb += __shfl_xor(fb, o, 64);
   }
   if (l == 0) {
     acc[0] += double(stamps[1] - stamps[0]) * ms_per_tick;
@@ -2316,6 +2348,7 @@ __global__ void k_timing_reduce(const unsigned long long* stamps, const unsigned
     acc[4] += double(b);
     acc[7] += double(f);
     acc[9] += double(fa);
+    acc[11] += double(fb);
   }
 }
 
@@ -2534,6 +2567,18 @@ void launch_zip_init(const ZipArgs& Z, hipStream_t st) {
   hipLaunchKernelGGL(k_zip_init, dim3(Z.n_sweeps), dim3(64), 0, st, Z);
 }
 
+int zip_step_large(const ZipArgs& Z, int x, int y, int legcap) {
+  const int inline_dec = (x + 1 < Z.Lx && y + 1 == Z.Ly) ? 1 : 0;
+  if (!(x + 1 < Z.Lx && !inline_dec && Z.gram_path)) return 0;
+  // the order min(R, C) of the Gram, R = nu sD and C = aR wR, is bounded by
+  // the structure: nu = 1 in the first column, aR = 1 in the first row,
+  // sD = 1 in the last row
+  const int64_t rcap = int64_t(x == 0 ? 1 : Z.chi_m) * (y + 1 == Z.Ly ? 1 : legcap);
+  const int64_t ccap = int64_t(y == 0 ? 1 : Z.chi_m) * legcap;
+  if ((rcap < ccap ? rcap : ccap) <= ZBIG) return 0;
+  return Z.chi_m + 1 <= SB ? 1 : 2;
+}
+
 void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st) {
   const int inline_dec = (x + 1 < Z.Lx && y + 1 == Z.Ly) ? 1 : 0;
   hipLaunchKernelGGL(k_zip_a, dim3(Z.n_sweeps), dim3(ZNT), 0, st, Z, x, y, inline_dec);
@@ -2541,18 +2586,13 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st)
     if (Z.gram_path) {
       hipLaunchKernelGGL(k_zip_beig, dim3(Z.n_sweeps), dim3(64), beig_lds_bytes(Z.eig_ys), st, Z, x,
                          y);
-      // the order min(R, C) of the Gram, R = nu sD and C = aR wR, is bounded by
-      // the structure: nu = 1 in the first column, aR = 1 in the first row,
-      // sD = 1 in the last row; the larger-order kernel runs only where the
-      // bound passes ZBIG
-      const int64_t rcap = int64_t(x == 0 ? 1 : Z.chi_m) * (y + 1 == Z.Ly ? 1 : legcap);
-      const int64_t ccap = int64_t(y == 0 ? 1 : Z.chi_m) * legcap;
-      if ((rcap < ccap ? rcap : ccap) > ZBIG) {
-        if (Z.chi_m + 1 <= SB)
-          hipLaunchKernelGGL(k_zip_bsub, dim3(Z.n_sweeps), dim3(ZNT), bsub_lds_bytes(), st, Z, x, y);
-        else
-          hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
-      }
+      // the larger-order kernels run only where the structural bound on the
+      // family passes ZBIG
+      const int big = zip_step_large(Z, x, y, legcap);
+      if (big == 1)
+        hipLaunchKernelGGL(k_zip_bsub, dim3(Z.n_sweeps), dim3(ZNT), bsub_lds_bytes(), st, Z, x, y);
+      else if (big == 2)
+        hipLaunchKernelGGL(k_zip_bbig, dim3(Z.n_sweeps), dim3(ZNT), size_t(19200) * 8, st, Z, x, y, 19200);
     } else {
       hipLaunchKernelGGL(k_zip_b, dim3(Z.n_sweeps), dim3(ZBT), size_t(18432) * 8, st, Z, x, y, 18432);
     }
@@ -2592,7 +2632,7 @@ void launch_seq(int n, int32_t* items, int64_t* offs, int64_t stride, hipStream_
 void launch_timing_reduce(const unsigned long long* stamps, const unsigned long long* win, int n_cls_win, int Lx,
                           int Ly, int eig, const unsigned long long* ctr, double ms_per_tick, double* acc,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_timing_reduce, dim3(n_cls_win + 2 * Lx * Ly + 1), dim3(64), 0, st, stamps, win, n_cls_win, Lx,
+  hipLaunchKernelGGL(k_timing_reduce, dim3(n_cls_win + 3 * Lx * Ly + 1), dim3(64), 0, st, stamps, win, n_cls_win, Lx,
                      Ly, eig, ctr, ms_per_tick, acc);
 }
 

@@ -168,8 +168,8 @@ class Context:
         return int(self.lib.tn3d_ctx_graphs_cached(self.h))
 
     def last_timing(self):
-        out = (ctypes.c_double * 11)()
-        _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 11))
+        out = (ctypes.c_double * 14)()
+        _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 14))
         return list(out)
 
     def last_stats(self):
