@@ -491,3 +491,157 @@ def depol3d_network(L, p, m, coset, rep=None):
             e = (L - 1) * L * L + y * L + x
             final.append(np.array([W(e, r[e] ^ g, s) for g in range(2) for s in range(2)]))
     return LayeredNet(L, L, init, layers, final)
+
+
+# ---------------------------------------------------------------------------
+# 3D planar code, loop sector (bit flips seen by the face checks): generator
+# picture, sweep along z
+# ---------------------------------------------------------------------------
+
+def loop3d_dem_parts(L):
+    """(H_faces, string): the face checks of the 3D planar code as a
+    faces x edges F2 matrix (canonical face order) and the indicator of the
+    vertical string of z-edges above (0, 0), whose parity labels the coset of
+    a bit-flip error seen by the faces."""
+    nq = L ** 3 + 2 * L * (L - 1) ** 2
+    faces = _faces3d(L)
+    H = np.zeros((len(faces), nq), dtype=np.uint8)
+    for f, es in enumerate(faces):
+        H[f, es] = 1
+    string = np.zeros(nq, dtype=np.uint8)
+    string[[z * L * L for z in range(L)]] = 1
+    return H, string
+
+
+def loop3d_network(L, p, m, coset):
+    """Generator-picture network of the loop sector (paper Sec. 3.2 and the
+    loop-sector experiment of Sec. 5): bit flips u on the edges of the 3D
+    planar code, detected by the weight-3/4 face checks (syndrome m), class =
+    parity of u on the vertical string of z-edges above (0, 0).
+
+    Every u with face syndrome m and class c is r + sum_v g_v s_v for one
+    representative r of that class and exactly one set of vertex stabilizers
+    s_v (X on the edges at vertex v; independent here because every vertex
+    star holds dangling edges or an edge to a vertex with one), so a bit g_v
+    per vertex replaces the sum over u, and every term is a product of
+    non-negative edge weights W(e, u_e) = p_e^u_e (1 - p_e)^(1 - u_e) with
+    u_e = r_e + g_v + g_w (one endpoint for a dangling edge).
+
+    Physical leg of site (x, y): the generator bit g of the vertex last
+    absorbed (0 before level 1).  Layer z (levels 1..L-1):
+      pre   the z-edge below vertex (x, y, z): g -> g' with weight
+            W(e, r_e + g + g'), g' the bit of (x, y, z);
+      gates per in-plane edge of level z: diagonal, W(e, r_e + g_A + g_B).
+    Final: the top dangling edge, f[g] = W(e, r_e + g).  Initial state: g = 0
+    on every site (a product state).  r: a solution of H r = m from
+    elimination, plus the bottom membrane of dangling edges (which meets the
+    string once) when its class differs from `coset`.
+
+    p: per-edge flip rates (edge numbering of surface3d_point), or a scalar.
+    m: the face syndrome (canonical face order).
+    """
+    nq = L ** 3 + 2 * L * (L - 1) ** 2
+    pq = np.broadcast_to(np.asarray(p, dtype=np.float64), (nq,))
+    H, string = loop3d_dem_parts(L)
+    m = np.asarray(m, dtype=np.uint8)
+    r = gf2_solve(H, m)
+    if r is None:
+        raise ValueError("face syndrome violates a cube relation")
+    if int(r[string == 1].sum()) % 2 != coset:
+        r[: L * L] ^= 1
+    return _loop3d_from_rep(L, pq, r, [np.array([1.0, 0.0])] * (L * L))
+
+
+def _loop3d_from_rep(L, pq, r, init_vecs):
+    def W(e, u):
+        return pq[e] if u else 1.0 - pq[e]
+
+    init = [v.reshape(2, 1, 1, 1, 1).astype(np.float64) for v in init_vecs]
+    nz, nx = L ** 3, L * (L - 1) ** 2
+    layers = []
+    for z in range(1, L):
+        lay = Layer()
+        for y in range(L):
+            for x in range(L):
+                e = (z - 1) * L * L + y * L + x
+                lay.pre[y * L + x] = np.array([[W(e, r[e] ^ g ^ g2) for g in range(2)] for g2 in range(2)])
+
+        def gate(e):
+            G = np.zeros((2, 2, 2, 2))
+            for ga in range(2):
+                for gb in range(2):
+                    G[ga, gb, ga, gb] = W(e, r[e] ^ ga ^ gb)
+            return G
+
+        for y in range(L):
+            for x in range(L - 1):
+                lay.gates.append(("H", x, y, gate(nz + ((z - 1) * L + y) * (L - 1) + x)))
+        for y in range(L - 1):
+            for x in range(L):
+                lay.gates.append(("V", x, y, gate(nz + nx + ((z - 1) * (L - 1) + y) * L + x)))
+        layers.append(lay)
+    final = []
+    for y in range(L):
+        for x in range(L):
+            e = (L - 1) * L * L + y * L + x
+            final.append(np.array([W(e, r[e] ^ g) for g in range(2)]))
+    return LayeredNet(L, L, init, layers, final)
+
+
+# ---------------------------------------------------------------------------
+# Walsh-Hadamard variant (paper Sec. 3.1): signed networks Z_b with
+# P_L = (1/2) sum_b (-1)^(b L) Z_b
+# ---------------------------------------------------------------------------
+
+def point3d_network_wht(L, p, m, b):
+    """Z_b of the point sector: the sum over all flips x with H x = m of
+    (-1)^(b * class(x)) times the weight, class = the parity of the bottom
+    dangling z-edges.  The logical check node of the paper's network becomes
+    the sign (-1)^(b x_e) on each bottom dangling edge, so the initial state
+    is the product of the vectors (1 - q, (-1)^b q): no parity chain."""
+    net = point3d_network(L, p, m, 0)
+    pz = np.asarray(p, dtype=np.float64)
+    init = []
+    for y in range(L):
+        for x in range(L):
+            q = pz[y * L + x]
+            init.append(np.array([1.0 - q, (-1.0) ** b * q]).reshape(2, 1, 1, 1, 1))
+    return LayeredNet(net.Lx, net.Ly, init, net.layers, net.final)
+
+
+def loop3d_network_wht(L, p, m, b):
+    """Z_b of the loop sector: the sum over both classes a of (-1)^(a b) P_a.
+    With the class-0 representative, class a adds the bottom membrane, which
+    is the same as a generator bit a shared by every site below level 1; the
+    initial state is that shared bit with sign (-1)^(a b): a chain of equal
+    bits (bond 2) in boustrophedon order."""
+    nq = L ** 3 + 2 * L * (L - 1) ** 2
+    pq = np.broadcast_to(np.asarray(p, dtype=np.float64), (nq,))
+    H, string = loop3d_dem_parts(L)
+    r = gf2_solve(H, np.asarray(m, dtype=np.uint8))
+    if r is None:
+        raise ValueError("face syndrome violates a cube relation")
+    if int(r[string == 1].sum()) % 2 != 0:
+        r[: L * L] ^= 1
+    net = _loop3d_from_rep(L, pq, r, [np.array([1.0, 0.0])] * (L * L))
+    order = snake_order(L, L)
+    init = [None] * (L * L)
+    n = len(order)
+    for k, (x, y) in enumerate(order):
+        shape = [2, 1, 1, 1, 1]
+        lin = _leg_towards((x, y), order[k - 1]) if k > 0 else None
+        lout = _leg_towards((x, y), order[k + 1]) if k < n - 1 else None
+        if lin is not None:
+            shape[lin] = 2
+        if lout is not None:
+            shape[lout] = 2
+        T = np.zeros(shape)
+        for a in range(2):
+            idx = [a, 0, 0, 0, 0]
+            if lin is not None:
+                idx[lin] = a
+            if lout is not None:
+                idx[lout] = a
+            T[tuple(idx)] = (-1.0) ** (a * b) if k == 0 else 1.0
+        init[y * L + x] = T
+    return LayeredNet(net.Lx, net.Ly, init, net.layers, net.final)

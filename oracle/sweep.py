@@ -86,6 +86,8 @@ class Sweep:
         self.logscale = 0.0
         self.flags = 0
         self.n_split = 0
+        self.signed = False  # allow a negative contraction value (signed networks)
+        self.sign = 1.0
 
     # lambda of the bond on `leg` of site (x, y), or None at the grid edge
     def _lam(self, x, y, leg):
@@ -234,6 +236,9 @@ class Sweep:
         for x in range(Lx):
             v = v @ mps[x][:, 0, :]
         z = float(v[0])
+        if self.signed and z < 0.0:
+            self.sign = -1.0
+            z = -z
         if not z > 0.0:
             self.flags |= FLAG_NUMERIC
             return np.nan
@@ -258,3 +263,18 @@ def sweep_logprob(net: LayeredNet, chi, chi_m=None, eps_rel=1e-9, tau_gap=1e-6,
     except FloatingPointError:
         return np.nan, sw.flags | FLAG_NUMERIC, sw.n_split
     return lp, sw.flags, sw.n_split
+
+
+def sweep_signed(net: LayeredNet, chi, chi_m=None, eps_rel=1e-9, tau_gap=1e-6, svd_driver="gesdd"):
+    """The same sweep for a network whose value may be negative (the signed
+    Walsh-Hadamard networks of Sec. 3.1): returns (log |Z|, sign of Z, flags).
+    Site rescaling divides by positive maxima and the truncations keep
+    positive singular values, so the sign of Z is the sign of the final
+    boundary-MPS contraction."""
+    sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver)
+    sw.signed = True
+    try:
+        lp = sw.run()
+    except FloatingPointError:
+        return np.nan, 0.0, sw.flags | FLAG_NUMERIC
+    return lp, sw.sign, sw.flags

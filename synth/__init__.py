@@ -13,6 +13,7 @@ from .codes import (  # noqa: F401
     surface3d_point,
     surface3d_faces,
     surface3d_depolarizing,
+    surface3d_loop,
     rotated_phenom,
     repetition_line,
     surface2d_bitflip,

@@ -212,6 +212,29 @@ def surface3d_depolarizing(L: int, p) -> Dem:
                 "zbar": zbar, "xbar": xbar})
 
 
+def surface3d_loop(L: int, p) -> Dem:
+    """Loop sector of the 3D planar code of size L: i.i.d. bit flips of rate
+    p on every edge (qubit), detected by the face checks of surface3d_faces
+    (loop-like syndromes).  The logical indicator is the vertical string of
+    z-edges above (0, 0), which meets the X membrane of the bottom dangling
+    edges once and every vertex stabilizer an even number of times.
+      detector: face f (canonical face order)
+      mechanism: edge e (numbering of surface3d_point)
+    Consistent syndromes satisfy one parity per cube (six dependent faces).
+    """
+    if L < 2:
+        raise ValueError("L >= 2")
+    n = L ** 3 + 2 * L * (L - 1) ** 2
+    faces = surface3d_faces(L)
+    H = np.zeros((len(faces), n), dtype=np.uint8)
+    for f, es in enumerate(faces):
+        H[f, list(es)] = 1
+    obs = np.zeros((1, n), dtype=np.uint8)
+    obs[0, [z * L * L for z in range(L)]] = 1
+    coord = np.full((len(faces), 3), -1, dtype=np.int64)
+    return Dem(f"surface3d_loop_L{L}", H, _rates(p, n), obs, coord, {"L": L})
+
+
 # --------------------------------------------------------------------------
 # Rotated surface code, one sector, phenomenological noise
 # --------------------------------------------------------------------------

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .codes import Dem, rotated_phenom, surface3d_depolarizing, surface3d_point
+from .codes import surface3d_loop, Dem, rotated_phenom, surface3d_depolarizing, surface3d_point
 
 CONFIG_SEED_BASE = 2310107220
 
@@ -63,6 +63,8 @@ def config_workload(cfg: int, n: int | None = None):
        observables.
     5: rotated d=7, 7 noisy + 1 perfect round, per-qubit / per-measurement
        rates log-uniform in [0.005, 0.05] (drawn first, seed + 100), 256 syndromes.
+    6: 3D planar code L=8, loop sector (bit flips seen by the faces), p=0.2,
+       256 syndromes; the error draws of workload 3 (same seed and edges).
     Returns (dem, syndromes, observables, seed).
     """
     seed = CONFIG_SEED_BASE + cfg
@@ -80,6 +82,10 @@ def config_workload(cfg: int, n: int | None = None):
         n = 512 if n is None else n
         m, cos = sample_pauli(dem, n, seed)
         return dem, m, cos, seed
+    elif cfg == 6:
+        dem = surface3d_loop(8, 0.2)
+        n = 256 if n is None else n
+        seed = CONFIG_SEED_BASE + 3
     elif cfg == 5:
         pq, qm = rotated_rates(7, 7, seed + 100)
         dem = rotated_phenom(7, 7, pq, qm)
