@@ -7,9 +7,14 @@ BF16 precision mode (FP32 site tensors, the absorption Grams, reabsorption
 and boundary-MPS contraction on BF16 matrix cores with FP32 accumulation,
 truncations and log accumulators in FP64), rank rule eps_rel 1e-6 /
 tau_gap 1e-4.  A step is one tn3d_decode call over the whole batch with the
-syndromes already resident in HBM, replaying the captured launch sequence.
-The timed steps run with the kernels' device-side execution windows and
-work counters on (the roofline comes from those same steps).
+syndromes already resident in HBM, replaying the captured launch sequences:
+the BF16 contraction of every (syndrome, coset), the decision, and the FP64
+re-sweep (Gram route, same chi and rule) of every item whose BF16 log-ratio
+lies inside the library's near-tie band (4e-3).  At p = 0.2 the point sector
+is far above its threshold, the two cosets of every syndrome are equal to
+within FP64 rounding, and the whole batch is re-swept.  The timed steps run
+with the kernels' device-side execution windows and work counters on (the
+roofline comes from those same steps).
 
 The JSON line also reports
   roofline            the dominant kernel of the step, from the device
@@ -17,9 +22,8 @@ The JSON line also reports
   roofline_streaming  the layer-absorption Gram + reabsorption kernels
                       against HBM (algorithmic bytes: each site tensor read by
                       its Gram, read and written by its reabsorption);
-  near_tie_resweep    the same decode with the FP64 re-sweep of near ties
-                      (|log ratio| < 4e-3) switched on, and how many items it
-                      re-swept;
+  bf16_pass_only      the same decode without the re-sweep (one step), with
+                      the roofline of the boundary-MPS contraction k_zip_a;
   fp64_gram_route     the same batch in FP64 (Gram route), one step;
   one_syndrome_per_call  one syndrome per call (the unbatched path);
   cpu_baseline        the CPU oracle (fixed-chi FP64 sweep, same chi, chi_mps
@@ -28,8 +32,10 @@ The JSON line also reports
                       and the 4 stored ones (tests/golden/point_L8_chi32.json),
                       and the decision agreement (tie band 2e-3).
 
-Other workloads: --config 2 (rotated d=5, phenomenological, chi = 16, FP64
-headline), --config 4 (depolarizing, ragged L in {4, 5, 6}), --config 1.
+Other workloads: --config 6 (the same L = 8 code and error draws in the loop
+sector, bit flips seen by the faces, below its threshold at p = 0.2),
+--config 2 (rotated d=5, phenomenological, chi = 16, FP64), --config 4
+(depolarizing, ragged L in {4, 5, 6}).
 """
 
 from __future__ import annotations
@@ -106,6 +112,9 @@ def _oracle_one(args):
     from oracle.sweep import sweep_logprob
     if fam == "rotated":
         net = rotated_network(prm_fam["d"], prm_fam["T"], prm_fam["checks"], p, m, c)
+    elif fam == "loop":
+        from oracle.network import loop3d_network
+        net = loop3d_network(prm_fam["L"], p, m, c)
     else:
         net = point3d_network(prm_fam["L"], p, m, c)
     return sweep_logprob(net, chi, chi_m, eps, tau)[0]
@@ -157,15 +166,18 @@ def roof_entry(name, bound, work, ms, launches, peak, unit, traffic=None):
 
 def bench_point_L8(a, tn3d, np, torch):
     import synth
-    dem, m, _, _ = synth.config_workload(3)
+    loop = a.config == 6
+    sector = "loop" if loop else "point"
+    dem, m, _, _ = synth.config_workload(6 if loop else 3)
     B = m.shape[0]
     L, chi = 8, 32
     prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32}[a.precision]
     ctx = tn3d.Context(0)
-    net = tn3d.tn3d_net_surface3d_point(ctx, L, dem.p)
+    net = (tn3d.tn3d_net_surface3d_loop if loop else tn3d.tn3d_net_surface3d_point)(ctx, L, dem.p)
     prm = tn3d.tn3d_params_default(chi, chi, prec)
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
-    prm.near_tie = 0.0
+    # the library default near-tie band: every item whose BF16 log-ratio is
+    # below it is contracted again in FP64 (Gram route) inside the same call
     syn = torch.from_numpy(m).to("cuda:0")
     ctx.set_timing(1)  # device windows and work counters inside the captured sequence
     for i in range(a.warmup):
@@ -175,63 +187,67 @@ def bench_point_L8(a, tn3d, np, torch):
     ctx.set_timing(1)  # the sums restart: they cover the timed steps only
     results = None
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for i in range(a.steps):
         results = tn3d.tn3d_decode(ctx, net, syn, prm)
+        if a.steps > 1:
+            torch.cuda.synchronize()
+            say(f"timed step {i + 1}/{a.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     say(f"{a.steps} timed steps: {dt:.2f} s")
     t = ctx.last_timing()
     (lay_ms, fin_ms, hot_ms, hot_launch, hot_bytes, eig_ms, eig_launch, eig_flops, za_ms, za_flops, za_launch,
      sub_ms, sub_flops, sub_launch) = t
-    ctx.set_timing(0)
     coset, lr, logp, flags = [x.cpu().numpy() for x in results]
     rf_eig = roof_entry("k_zip_bsub (boundary-MPS leading eigenpairs of families above 64 vectors: subspace "
-                        "iteration with Rayleigh-Ritz on the FP64 matrix cores)", "mfma", sub_flops, sub_ms, sub_launch,
-                        FP64_PEAK_TFS, "TFLOP/s", recorded_traffic("pmc_k_zip_bsub_point_L8_chi32_bf16.md"))
-    za_peak = BF16_PEAK_TFS / 6.0 if prec == tn3d.PREC_BF16 else FP64_PEAK_TFS
-    rf_za = roof_entry("k_zip_a (boundary-MPS contraction Theta on the BF16 matrix cores, six BF16 products per "
-                       "FP32-accurate product, and its Gram on the FP64 ones)", "mfma", za_flops, za_ms, za_launch,
-                       za_peak, "TFLOP/s", None)
-    if rf_za:
-        rf_za["peak_note"] = ("BF16 dense peak / 6 (each FP32-accurate product takes six BF16 products); the Gram "
-                              "part runs on the FP64 matrix cores at 78.6")
-    cands = [r for r in (rf_eig, rf_za) if r]
-    dom = max(cands, key=lambda r: r["avg_launch_ms"] * (sub_launch if r is rf_eig else za_launch)) if cands else None
-    stream = roof_entry("k_gram2 + k_reabsorb2 + k_reabsorb (site-tensor streaming)", "hbm", hot_bytes, hot_ms,
-                        hot_launch, HBM_PEAK_GBS, "GB/s", None)
+                        "iteration with Rayleigh-Ritz on the FP64 matrix cores; BF16 pass and FP64 re-sweep)", "mfma",
+                        sub_flops, sub_ms, sub_launch, FP64_PEAK_TFS, "TFLOP/s",
+                        recorded_traffic("pmc_k_zip_bsub_point_L8_chi32_bf16.md"))
+    stream = roof_entry("k_gram2 + k_reabsorb2 + k_reabsorb (site-tensor streaming; BF16 pass and FP64 re-sweep)",
+                        "hbm", hot_bytes, hot_ms, hot_launch, HBM_PEAK_GBS, "GB/s", None)
     out = {"metric": METRIC, "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "bf16" if prec == tn3d.PREC_BF16 else "f32",
            "data": "synthetic (seeded Bernoulli flips of every qubit, p = 0.2)",
-           "config": {"workload": "3D planar surface code L=8, point sector, i.i.d. flips p=0.2, 8x8 grid x 7 layers, "
+           "config": {"workload": f"3D planar surface code L=8, {sector} sector, i.i.d. flips p=0.2, 8x8 grid x 7 layers, "
                                   "chi=32, chi_mps=32, 256 syndromes x 2 cosets, rank rule eps_rel 1e-6 / tau_gap "
-                                  "1e-4", "global_batch": B, "chi": chi, "chi_mps": chi,
-                      "precision": a.precision, "near_tie_resweep": "off in the timed steps (see near_tie_resweep)"},
-           "launch": "captured launch sequence replayed (HIP graph), device execution windows on",
+                                  "1e-4, FP64 re-sweep of near ties", "global_batch": B, "chi": chi, "chi_mps": chi,
+                      "precision": a.precision, "near_tie": prm.near_tie},
+           "launch": "captured launch sequences replayed (HIP graph), device execution windows on",
+           "items_reswept_fp64": int(np.sum(flags & 16 != 0)),
            "phases_ms_per_step": {"layer_absorption": lay_ms / a.steps, "boundary_mps": fin_ms / a.steps,
                                   "gram_plus_reabsorb": hot_ms / a.steps,
                                   "boundary_decomposition_small": eig_ms / a.steps,
                                   "boundary_decomposition_subspace": sub_ms / a.steps,
                                   "boundary_contraction": za_ms / a.steps},
-           "roofline": dom, "roofline_kernels": cands, "roofline_streaming": stream,
+           "roofline": rf_eig, "roofline_streaming": stream,
            "flags": {"numeric": int(np.sum(flags & 1 != 0)), "trunc_cluster": int(np.sum(flags & 2 != 0)),
                      "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0))}}
+    # the BF16 pass alone (no re-sweep), one instrumented step
+    p0 = tn3d.tn3d_params_default(chi, chi, prec)
+    p0.eps_rel, p0.tau_gap, p0.near_tie = 1e-6, 1e-4, 0.0
+    ctx.set_timing(1)
+    b0 = time.perf_counter()
+    r0 = tn3d.tn3d_decode(ctx, net, syn, p0)
+    torch.cuda.synchronize()
+    b1 = time.perf_counter()
+    t0s = ctx.last_timing()
+    ctx.set_timing(0)
+    say(f"BF16 pass alone: {b1 - b0:.2f} s")
+    za_peak = BF16_PEAK_TFS / 6.0 if prec == tn3d.PREC_BF16 else FP64_PEAK_TFS
+    rf_za = roof_entry("k_zip_a (boundary-MPS contraction Theta on the BF16 matrix cores, six BF16 products per "
+                       "FP32-accurate product, and its Gram on the FP64 ones)", "mfma", t0s[9], t0s[8], t0s[10],
+                       za_peak, "TFLOP/s", None)
+    if rf_za:
+        rf_za["peak_note"] = ("BF16 dense peak / 6 (each FP32-accurate product takes six BF16 products); the Gram "
+                              "part runs on the FP64 matrix cores at 78.6")
+    lp0 = r0[2].cpu().numpy()
+    out["bf16_pass_only"] = {"value": B / (b1 - b0), "ms_per_step": (b1 - b0) * 1e3,
+                             "note": "the same decode with near_tie = 0 (no FP64 re-sweep), one instrumented step",
+                             "roofline_k_zip_a": rf_za,
+                             "roofline_k_zip_bsub": roof_entry("k_zip_bsub", "mfma", t0s[12], t0s[11], t0s[13],
+                                                               FP64_PEAK_TFS, "TFLOP/s", None)}
     if not a.headline_only:
-        # the same decode with the FP64 re-sweep of near ties
-        pr2 = tn3d.tn3d_params_default(chi, chi, prec)
-        pr2.eps_rel, pr2.tau_gap = 1e-6, 1e-4
-        tn3d.tn3d_decode(ctx, net, syn, pr2)
-        torch.cuda.synchronize()
-        r0 = time.perf_counter()
-        res2 = tn3d.tn3d_decode(ctx, net, syn, pr2)
-        torch.cuda.synchronize()
-        r1 = time.perf_counter()
-        fl2 = res2[3].cpu().numpy()
-        say(f"near-tie re-sweep decode: {r1 - r0:.2f} s")
-        out["near_tie_resweep"] = {"value": B / (r1 - r0), "ms_per_step": (r1 - r0) * 1e3, "near_tie": pr2.near_tie,
-                                   "items_reswept": int(np.sum(fl2 & 16 != 0)),
-                                   "note": "every item whose log-ratio is below near_tie is contracted again in "
-                                           "FP64 (Gram route) in the same call"}
         # FP64 (Gram route), one step
         p64 = tn3d.tn3d_params_default(chi, chi, tn3d.PREC_FP64)
         p64.eps_rel, p64.tau_gap = 1e-6, 1e-4
@@ -257,17 +273,19 @@ def bench_point_L8(a, tn3d, np, torch):
         o1 = time.perf_counter()
         out["one_syndrome_per_call"] = {"value": n1 / (o1 - o0), "unit": "syndromes/s", "calls": n1}
         # accuracy against the stored oracle values
+    if not a.headline_only and not loop:
         gold = json.load(open(os.path.join(ROOT, "tests", "golden", "point_L8_chi32.json")))
         ref_g = np.array(gold["logp"])
         it = gold["items"]
         out["accuracy_stored"] = accuracy(np, logp[it, :2], ref_g, coset[it])
         out["accuracy_stored"]["vs"] = "oracle values stored by tests/golden/make_point_L8_chi32.py (items 0, 85, " \
                                        "170, 255)"
+        out["accuracy_stored"]["bf16_pass_max_abs_dlogp"] = float(np.max(np.abs(lp0[it, :2] - ref_g)))
         out["accuracy_stored"]["fp64_gram_route_max_abs_dlogp"] = float(np.max(np.abs(lp64[it, :2] - ref_g)))
     if not a.no_cpu:
         n = 8
         say(f"cpu baseline: {2 * n} oracle sweeps on {CPU_WORKERS} workers")
-        ref, cdt = cpu_oracle("point", {"L": L}, dem.p, m[:n], prm, CPU_WORKERS)
+        ref, cdt = cpu_oracle(sector, {"L": L}, dem.p, m[:n], prm, CPU_WORKERS)
         say(f"cpu baseline: {cdt:.1f} s")
         out["cpu_baseline"] = {"value": n / cdt, "unit": "syndromes/s", "cores": CPU_WORKERS, "kind": "oracle",
                                "cpu_model": cpu_model(),
@@ -276,6 +294,7 @@ def bench_point_L8(a, tn3d, np, torch):
                                          f"and rank rule; wall time of the pool"}
         out["accuracy"] = accuracy(np, logp[:n, :2], ref, coset[:n])
         out["accuracy"]["vs"] = "CPU oracle (fixed-chi FP64 sweep), the cpu_baseline sample"
+        out["accuracy"]["bf16_pass_max_abs_dlogp"] = float(np.max(np.abs(lp0[:n, :2] - ref)))
     print(json.dumps(out))
 
 
@@ -370,9 +389,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3,
-                    help="3: 3D planar L=8 point sector, chi 32 (the headline); 2: rotated d=5; 4: depolarizing, "
-                         "ragged L in {4, 5, 6}")
-    ap.add_argument("--precision", default="bf16", choices=("bf16", "fp32"), help="--config 3 only")
+                    help="3: 3D planar L=8 point sector, chi 32 (the headline); 6: the same in the loop sector; "
+                         "2: rotated d=5; 4: depolarizing, ragged L in {4, 5, 6}")
+    ap.add_argument("--precision", default="bf16", choices=("bf16", "fp32"), help="--config 3 and 6 only")
     ap.add_argument("--chi", type=int, default=8, help="chi = chi_mps for --config 4")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -402,7 +421,7 @@ def main():
 
     from paper_2310_10722_amd import tn3d
 
-    if a.config == 3:
+    if a.config in (3, 6):
         return bench_point_L8(a, tn3d, np, torch)
     if a.config == 2:
         return bench_rotated_d5(a, tn3d, np, torch)

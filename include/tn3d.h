@@ -79,6 +79,8 @@ typedef enum {
  * instead of about 1e-11.  Reduced precisions always use the Gram route. */
 #define TN3D_OPT_GRAM_FACTOR 1u
 
+#define TN3D_MAX_CHI_LAYERS 32
+
 typedef struct tn3d_ctx_s* tn3d_ctx;
 typedef struct tn3d_net_s* tn3d_net;
 
@@ -93,6 +95,13 @@ typedef struct {
   int64_t workspace_bytes; /* cap on the context workspace (0 = no cap) */
   uint32_t flags;    /* TN3D_OPT_* bits (0 = defaults) */
   uint32_t reserved1;
+  /* chi-schedule: when n_chi_layers > 0, the truncations of absorbed layer l
+   * (0-based) keep at most chi_layers[min(l, n_chi_layers - 1)] <= chi
+   * values; chi stays the capacity and the cap of layers past the list.
+   * 0 = the constant chi.  The schedule changes the computed value: a
+   * reference must run the same schedule. */
+  int32_t n_chi_layers;
+  int32_t chi_layers[TN3D_MAX_CHI_LAYERS];
 } tn3d_params;
 
 /* Fill *p with the defaults for a precision: eps_rel 1e-9 (FP64) / 1e-6
@@ -164,6 +173,40 @@ tn3d_status tn3d_net_rotated_phenom(tn3d_ctx ctx, int32_t d, int32_t T, const do
  * Errors: TN3D_E_INVALID (L < 2, a rate outside [0, 3/4], null pointer),
  * TN3D_E_UNSUPPORTED (more than 4096 faces). */
 tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx ctx, int32_t L, const double* p_qubit, tn3d_net* out);
+
+/* Loop sector of the 3D planar surface code of size L (the loop-sector
+ * experiment of paper Sec. 5, generator picture of Sec. 3.2): independent
+ * bit flips with rate p_mech[e] on every edge (qubit numbering of
+ * tn3d_net_surface3d_point, n = L^3 + 2 L (L-1)^2 rates), detected by the
+ * face checks only (face numbering of tn3d_net_surface3d_depolarizing
+ * without its vertex offset: n_det = (L-1)^3 + 2 L^2 (L-1)).  Two cosets: the
+ * parity of the flips on the vertical string of z-edges above (0, 0).  The
+ * network sums over one generator bit per vertex (physical dim 2 on every
+ * site); its gates depend on a representative of the face syndrome derived
+ * on the device per item, and a face syndrome that violates a cube relation
+ * gives log p = -inf for both cosets and TN3D_FLAG_INCONSISTENT.
+ * Errors: TN3D_E_INVALID (L < 2, a rate outside [0, 1], null pointer),
+ * TN3D_E_UNSUPPORTED (more than 4096 faces). */
+tn3d_status tn3d_net_surface3d_loop(tn3d_ctx ctx, int32_t L, const double* p_mech, tn3d_net* out);
+
+/* The Walsh-Hadamard form of the coset selection (paper Sec. 3.1) for the
+ * 3D planar code: instead of one non-negative network per coset, two signed
+ * networks per syndrome, Z_0 = P_0 + P_1 and Z_1 = P_0 - P_1 (the logical
+ * check node becomes a sign on the legs it joins), contracted with the same
+ * sweep, and log p_{m,L} = log((Z_0 + (-1)^L Z_1) / 2).  sector
+ * TN3D_SECTOR_POINT: the network of tn3d_net_surface3d_point with the
+ * product initial state of the signed bottom-edge weights (1 - q, (-1)^b q);
+ * TN3D_SECTOR_LOOP: that of tn3d_net_surface3d_loop with the generator bit
+ * below level 1 shared by all sites and signed (-1)^(a b).  Numbering,
+ * rates and syndromes as for those builders; results come back per coset
+ * like theirs.  The minority coset is a difference of two nearly equal
+ * values here: its relative error grows as e^gap times the precision of
+ * Z_b, so reduced precisions resolve it poorly.  A truncated |Z_1| above Z_0
+ * gives NaN with TN3D_FLAG_NUMERIC.
+ * Errors: TN3D_E_INVALID (unknown sector, and as the builders). */
+#define TN3D_SECTOR_POINT 0
+#define TN3D_SECTOR_LOOP 1
+tn3d_status tn3d_net_surface3d_wht(tn3d_ctx ctx, int32_t L, int32_t sector, const double* p_mech, tn3d_net* out);
 
 int32_t tn3d_net_num_detectors(tn3d_net net);
 int32_t tn3d_net_num_mechanisms(tn3d_net net);

@@ -66,10 +66,14 @@ def _svd(A, driver):
 
 class Sweep:
     def __init__(self, net: LayeredNet, chi, chi_m, eps_rel=1e-9, tau_gap=1e-6,
-                 svd_driver="gesdd"):
+                 svd_driver="gesdd", chi_layers=None):
         self.net = net
         self.Lx, self.Ly = net.Lx, net.Ly
         self.chi, self.chi_m = chi, chi_m
+        # chi-schedule: the gates of layer l keep at most
+        # chi_layers[min(l, len - 1)] values (None: chi for every layer)
+        self.chi_layers = list(chi_layers) if chi_layers else None
+        self.chi_cur = chi
         self.eps, self.tau = eps_rel, tau_gap
         self.driver = svd_driver
         self.G = [t.copy() for t in net.init]
@@ -141,7 +145,7 @@ class Sweep:
         RB3 = RB.reshape(rB, dB, D)
         theta = np.einsum("abpq,ipx,x,jqx->iajb", G4, RA3, lam, RB3).reshape(rA * dA, rB * dB)
         U, S, Vt = _svd(theta, self.driver)
-        Dn, split = rank_rule(S, self.chi, self.eps, self.tau)
+        Dn, split = rank_rule(S, self.chi_cur, self.eps, self.tau)
         if split:
             self.flags |= FLAG_TRUNC_CLUSTER
             self.n_split += 1
@@ -245,19 +249,21 @@ class Sweep:
         return logscale + np.log(z)
 
     def run(self):
-        for lay in self.net.layers:
+        for li, lay in enumerate(self.net.layers):
+            if self.chi_layers:
+                self.chi_cur = min(self.chi, self.chi_layers[min(li, len(self.chi_layers) - 1)])
             self.layer(lay)
         Ts = self.final_tensors()
         return self.logscale + self.boundary_mps(Ts)
 
 
 def sweep_logprob(net: LayeredNet, chi, chi_m=None, eps_rel=1e-9, tau_gap=1e-6,
-                  svd_driver="gesdd"):
+                  svd_driver="gesdd", chi_layers=None):
     """log of the approximate contraction value of one network; returns
     (logp, flags, n_cluster_splits).  The rank rule defaults to the FP64 rule
     (eps_rel 1e-9, tau_gap 1e-6); a strict rule (1e-12, 1e-9) is passed
     explicitly where the exact limit is compared."""
-    sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver)
+    sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver, chi_layers)
     try:
         lp = sw.run()
     except FloatingPointError:

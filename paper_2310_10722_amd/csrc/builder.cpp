@@ -155,6 +155,68 @@ class Assembler {
     }
   }
 
+  // Product state: site s holds the vector v[s] on its physical leg (dim
+  // v[s].size()), every bond of dimension 1; stored as coset `slot`.
+  void product_init(const std::vector<std::vector<double>>& v, int slot) {
+    int ns = Lx * Ly;
+    if (int(P.init_dims.size()) < (slot + 1) * ns * 5) {
+      P.init_dims.resize(size_t(slot + 1) * ns * 5, 1);
+      P.init_off.resize(size_t(slot + 1) * ns, 0);
+    }
+    P.bond_dim0.assign(P.n_bonds, 1);
+    for (int s = 0; s < ns; ++s) {
+      int dp = int(v[s].size());
+      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(slot) * ns + s) * 5 + i] = i == 0 ? dp : 1;
+      P.init_off[size_t(slot) * ns + s] = put(v[s]);
+      d[s] = dp;
+      P.dmax[s] = std::max(P.dmax[s], dp);
+    }
+  }
+
+  // Chain of equal bits in boustrophedon order (bond 2 along the chain,
+  // physical dim 2): value (-1)^(a sgn) when every site holds the same bit
+  // a, else 0; stored as coset `sgn`.
+  void copy_chain_init(int sgn) {
+    const int ns = Lx * Ly, slot = sgn;
+    std::vector<std::pair<int, int>> order;
+    for (int y = 0; y < Ly; ++y)
+      for (int i = 0; i < Lx; ++i) order.push_back({y % 2 == 0 ? i : Lx - 1 - i, y});
+    auto leg_to = [](std::pair<int, int> a, std::pair<int, int> b) {
+      if (b.first == a.first + 1) return int(LEG_E);
+      if (b.first == a.first - 1) return int(LEG_W);
+      if (b.second == a.second + 1) return int(LEG_S);
+      return int(LEG_N);
+    };
+    if (int(P.init_dims.size()) < (slot + 1) * ns * 5) {
+      P.init_dims.resize(size_t(slot + 1) * ns * 5, 1);
+      P.init_off.resize(size_t(slot + 1) * ns, 0);
+    }
+    P.bond_dim0.assign(P.n_bonds, 1);
+    for (int k = 0; k < ns; ++k) {
+      auto [x, y] = order[k];
+      const int s = y * Lx + x;
+      const int lin = k > 0 ? leg_to(order[k], order[k - 1]) : -1;
+      const int lout = k + 1 < ns ? leg_to(order[k], order[k + 1]) : -1;
+      int dims[5] = {2, 1, 1, 1, 1};
+      if (lin >= 0) dims[1 + lin] = 2;
+      if (lout >= 0) dims[1 + lout] = 2;
+      if (lout >= 0) P.bond_dim0[P.leg_bond[s * 4 + lout]] = 2;
+      Mat t(size_t(dims[0]) * dims[1] * dims[2] * dims[3] * dims[4], 0.0);
+      for (int a = 0; a < 2; ++a) {
+        int idx[4] = {0, 0, 0, 0};
+        if (lin >= 0) idx[lin] = a;
+        if (lout >= 0) idx[lout] = a;
+        // storage order [w][e][n][s][p], p fastest
+        size_t off = ((((size_t(idx[0]) * dims[2] + idx[1]) * dims[3] + idx[2]) * dims[4] + idx[3]) * 2) + a;
+        t[off] = (k == 0 && (a & sgn)) ? -1.0 : 1.0;
+      }
+      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(slot) * ns + s) * 5 + i] = dims[i];
+      P.init_off[size_t(slot) * ns + s] = put(t);
+      d[s] = 2;
+      P.dmax[s] = std::max(P.dmax[s], 2);
+    }
+  }
+
   // ---- layer assembly -------------------------------------------------
   struct Pending {
     bool has = false;
@@ -356,7 +418,7 @@ bool bad_rate(double p) { return !(p >= 0.0 && p <= 1.0); }
 // diag(1-q, q) X^{m} with q the rate of the edge leaving it upwards.  After
 // the last level the top dangling edges are summed: f = (1, 1).
 // ---------------------------------------------------------------------------
-std::string build_surface3d_point(int32_t L, const double* p, Program& P) {
+std::string build_surface3d_point(int32_t L, const double* p, Program& P, bool wht) {
   if (L < 2) return "L must be >= 2";
   if (!p) return "null rates";
   const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
@@ -368,16 +430,22 @@ std::string build_surface3d_point(int32_t L, const double* p, Program& P) {
   P.n_det = L * L * (L - 1);
   P.n_mech = n;
   P.n_cosets = 2;
+  P.wht = wht ? 1 : 0;
   Assembler A(P, L, L);
   for (int c = 0; c < 2; ++c) {
     std::vector<std::vector<double>> w(L * L);
     for (int y = 0; y < L; ++y)
       for (int x = 0; x < L; ++x) {
         double q = p[y * L + x];
-        w[y * L + x] = {1.0 - q, q};
+        // Walsh-Hadamard form: the logical check becomes the sign (-1)^(c x_e)
+        // on each bottom dangling edge, a product state
+        w[y * L + x] = {1.0 - q, (wht && c == 1) ? -q : q};
       }
     A.d.assign(L * L, 1);
-    A.snake_init(w, c);
+    if (wht)
+      A.product_init(w, c);
+    else
+      A.snake_init(w, c);
   }
   for (int z = 1; z < L; ++z) {
     A.begin_layer();
@@ -604,19 +672,24 @@ inline void bx(Bits& a, const Bits& b) {
 inline int bget(const Bits& a, int i) { return int((a[i >> 6] >> (i & 63)) & 1u); }
 inline void bflip(Bits& a, int i) { a[i >> 6] ^= uint64_t(1) << (i & 63); }
 
-}  // namespace
+// The face checks of the 3D planar code of size L (canonical order) and the
+// fixed GF(2) map B from a face syndrome to a representative bit-flip
+// pattern r = B m: r has that face syndrome when m is consistent, class 0
+// (even parity on the string of z-edges above (0, 0)) and zero on the top
+// dangling edges.  cube[i] (i < n_cube) are the rows of the elimination that
+// combine the face checks into zero: m is consistent iff every cube[i].m = 0.
+struct FaceMap {
+  int nf = 0, n = 0, wf = 0;
+  std::vector<Bits> B;     // [edge] bits over faces
+  std::vector<Bits> cube;  // cube relations, bits over faces
+};
 
-std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
-  if (L < 2) return "L must be >= 2";
-  if (!p) return "null rates";
+FaceMap face_map(int L) {
   const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
   const int n = nz + 2 * nx;
-  for (int i = 0; i < n; ++i)
-    if (!(p[i] >= 0.0 && p[i] <= 0.75)) return "depolarizing rate outside [0, 3/4]";
   auto ze = [&](int x, int y, int z) { return z * L * L + y * L + x; };
   auto xe = [&](int x, int y, int z) { return nz + ((z - 1) * L + y) * (L - 1) + x; };
   auto ye = [&](int x, int y, int z) { return nz + nx + ((z - 1) * (L - 1) + y) * L + x; };
-  // face checks in the canonical order
   std::vector<std::vector<int>> faces;
   for (int z = 1; z < L; ++z)
     for (int y = 0; y + 1 < L; ++y)
@@ -637,9 +710,12 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
         if (z + 1 < L) f.push_back(ye(x, y, z + 1));
         faces.push_back(f);
       }
-  const int nf = int(faces.size()), nv = L * L * (L - 1);
+  FaceMap M;
+  const int nf = int(faces.size());
   const int wq = (n + 63) / 64, wf = (nf + 63) / 64;
-
+  M.nf = nf;
+  M.n = n;
+  M.wf = wf;
   // Gauss-Jordan on H_Z (rows = faces, bit columns = qubits), tracking the
   // row operations E, so that E H_Z is reduced: for a consistent m_Z,
   // r[pivot col of row i] = (E m_Z)_i and zero elsewhere.
@@ -648,7 +724,7 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
     for (int e : faces[f]) bflip(H[f], e);
     bflip(E[f], f);
   }
-  std::vector<Bits> B(n, Bits(wf, 0));
+  M.B.assign(n, Bits(wf, 0));
   std::vector<int> pcol;
   int rank = 0;
   for (int col = 0; col < n && rank < nf; ++col) {
@@ -669,45 +745,67 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
     pcol.push_back(col);
     ++rank;
   }
-  for (int i = 0; i < rank; ++i) B[pcol[i]] = E[i];
-  // class a of r is its parity on the string above (0, 0); remove it by
-  // adding the bottom membrane (which meets the string once)
+  for (int i = 0; i < rank; ++i) M.B[pcol[i]] = E[i];
+  // class of r is its parity on the string above (0, 0); remove it by adding
+  // the bottom membrane (which meets the string once)
   Bits zrow(wf, 0);
-  for (int z = 0; z < L; ++z) bx(zrow, B[ze(0, 0, z)]);
+  for (int z = 0; z < L; ++z) bx(zrow, M.B[ze(0, 0, z)]);
   for (int y = 0; y < L; ++y)
-    for (int x = 0; x < L; ++x) bx(B[ze(x, y, 0)], zrow);
+    for (int x = 0; x < L; ++x) bx(M.B[ze(x, y, 0)], zrow);
   // clear the top dangling edges with the stabilizers of the top vertices
   for (int y = 0; y < L; ++y)
     for (int x = 0; x < L; ++x) {
-      const Bits t = B[ze(x, y, L - 1)];
+      const Bits t = M.B[ze(x, y, L - 1)];
       std::vector<int> st = {ze(x, y, L - 1), ze(x, y, L - 2)};
       if (x > 0) st.push_back(xe(x - 1, y, L - 1));
       if (x + 1 < L) st.push_back(xe(x, y, L - 1));
       if (y > 0) st.push_back(ye(x, y - 1, L - 1));
       if (y + 1 < L) st.push_back(ye(x, y, L - 1));
-      for (int e : st) bx(B[e], t);
+      for (int e : st) bx(M.B[e], t);
     }
+  // rows rank..nf of E combine the face checks into zero (E H_Z = 0 there)
+  for (int i = rank; i < nf; ++i) M.cube.push_back(E[i]);
+  return M;
+}
+
+// Per-item derived bits of a face-syndrome family: bit n_det + e is r_e
+// (e < n), then the cube-relation parities (INCONSISTENT when one is set).
+void set_face_ext(Program& P, const FaceMap& M, int src0) {
+  const int n_chk = int(M.cube.size());
+  P.n_ext = M.n + n_chk;
+  P.ext_src0 = src0;
+  P.ext_src_n = M.nf;
+  P.ext_words = M.wf;
+  P.ext_rows.resize(size_t(M.n + n_chk) * M.wf);
+  for (int e = 0; e < M.n; ++e)
+    for (int w = 0; w < M.wf; ++w) P.ext_rows[size_t(e) * M.wf + w] = M.B[e][w];
+  for (int i = 0; i < n_chk; ++i)
+    for (int w = 0; w < M.wf; ++w) P.ext_rows[size_t(M.n + i) * M.wf + w] = M.cube[i][w];
+  P.inc0 = P.n_det + M.n;
+  P.n_inc = n_chk;
+}
+
+}  // namespace
+
+std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
+  if (L < 2) return "L must be >= 2";
+  if (!p) return "null rates";
+  const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
+  const int n = nz + 2 * nx;
+  for (int i = 0; i < n; ++i)
+    if (!(p[i] >= 0.0 && p[i] <= 0.75)) return "depolarizing rate outside [0, 3/4]";
+  auto ze = [&](int x, int y, int z) { return z * L * L + y * L + x; };
+  auto xe = [&](int x, int y, int z) { return nz + ((z - 1) * L + y) * (L - 1) + x; };
+  auto ye = [&](int x, int y, int z) { return nz + nx + ((z - 1) * (L - 1) + y) * L + x; };
+  const FaceMap FM = face_map(L);
+  const int nf = FM.nf, nv = L * L * (L - 1);
 
   P = Program{};
   P.name = "surface3d_depolarizing_L" + std::to_string(L);
   P.n_det = nv + nf;
   P.n_mech = n;
   P.n_cosets = 4;
-  // rows rank..nf of E combine the face checks into zero (E H_Z = 0 there):
-  // the cube relations.  A face syndrome is consistent iff E_i m_Z = 0 for
-  // each of them; those parities follow the representative's bits.
-  const int n_chk = nf - rank;
-  P.n_ext = n + n_chk;
-  P.ext_src0 = nv;
-  P.ext_src_n = nf;
-  P.ext_words = wf;
-  P.ext_rows.resize(size_t(n + n_chk) * wf);
-  for (int e = 0; e < n; ++e)
-    for (int w = 0; w < wf; ++w) P.ext_rows[size_t(e) * wf + w] = B[e][w];
-  for (int i = 0; i < n_chk; ++i)
-    for (int w = 0; w < wf; ++w) P.ext_rows[size_t(n + i) * wf + w] = E[rank + i][w];
-  P.inc0 = P.n_det + n;
-  P.n_inc = n_chk;
+  set_face_ext(P, FM, nv);
 
   auto W = [&](int e, int u, int v) { return (u == 0 && v == 0) ? 1.0 - p[e] : p[e] / 3.0; };
   auto I4 = eye(4);
@@ -767,6 +865,102 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
     for (int x = 0; x < L; ++x) {
       const int e = ze(x, y, L - 1);
       f.push_back({W(e, 0, 0), W(e, 0, 1), W(e, 1, 0), W(e, 1, 1)});
+    }
+  A.finish(f);
+  return "";
+}
+
+// ---------------------------------------------------------------------------
+// 3D planar code, loop sector: bit flips on the edges seen by the face checks,
+// in the generator picture (paper Sec. 3.2; the loop-sector network of the
+// experiments has the cubic shape of the point sector with the roles of the
+// parity and copy nodes exchanged).  Every flip pattern u with face syndrome
+// m and class a is r + a (bottom membrane) + sum_v g_v s_v for the
+// representative r = B m of the face map and one bit g_v per vertex, so the
+// physical leg of a site is the generator bit g of the vertex last absorbed,
+// dimension 2.  The initial state of coset a is the product state g = a (the
+// bit of a virtual vertex below level 1, which adds the bottom membrane).
+// Layer z: pre-op per site for the z-edge below (x, y, z), g -> g' with weight
+// W(e, r_e + g + g'); a diagonal gate per in-plane edge, W(e, r_e + g_A +
+// g_B) = 1/2 + (1/2 - p_e) (-1)^r_e Z (x) Z (operator-Schmidt rank 2, the
+// sign of the Z term follows the per-item bit r_e).  Final vectors: the top
+// dangling edges, W(e, g) (r is zero there).
+// ---------------------------------------------------------------------------
+std::string build_surface3d_loop(int32_t L, const double* p, Program& P, bool wht) {
+  if (L < 2) return "L must be >= 2";
+  if (!p) return "null rates";
+  const int nz = L * L * L, nx = L * (L - 1) * (L - 1);
+  const int n = nz + 2 * nx;
+  for (int i = 0; i < n; ++i)
+    if (!(p[i] >= 0.0 && p[i] <= 1.0)) return "flip rate outside [0, 1]";
+  auto ze = [&](int x, int y, int z) { return z * L * L + y * L + x; };
+  auto xe = [&](int x, int y, int z) { return nz + ((z - 1) * L + y) * (L - 1) + x; };
+  auto ye = [&](int x, int y, int z) { return nz + nx + ((z - 1) * (L - 1) + y) * L + x; };
+  const FaceMap FM = face_map(L);
+
+  P = Program{};
+  P.name = "surface3d_loop_L" + std::to_string(L);
+  P.n_det = FM.nf;
+  P.n_mech = n;
+  P.n_cosets = 2;
+  set_face_ext(P, FM, 0);
+
+  auto W = [&](int e, int u) { return u ? p[e] : 1.0 - p[e]; };
+  Mat Zg = {1.0, 0.0, 0.0, -1.0};
+  auto gate_terms = [&](int e, int sgn) {
+    const double al = 0.5, be = 0.5 - p[e];
+    std::vector<Term> ts;
+    ts.push_back({scaled(eye(2), std::sqrt(al)), scaled(eye(2), std::sqrt(al))});
+    if (be != 0.0)
+      ts.push_back({scaled(Zg, be > 0 ? std::sqrt(be) : -std::sqrt(-be)), scaled(Zg, sgn * std::sqrt(std::fabs(be)))});
+    return ts;
+  };
+
+  P.wht = wht ? 1 : 0;
+  Assembler A(P, L, L);
+  for (int c = 0; c < 2; ++c) {
+    if (wht) {
+      // Z_c = sum_a (-1)^(a c) P_a: the bit a below level 1 is shared by
+      // every site, a chain of equal bits carrying the sign on its first site
+      A.copy_chain_init(c);
+    } else {
+      std::vector<std::vector<double>> v(L * L, {c == 0 ? 1.0 : 0.0, c == 0 ? 0.0 : 1.0});
+      A.product_init(v, c);
+    }
+  }
+  const int ndet = P.n_det;
+  for (int z = 1; z < L; ++z) {
+    A.begin_layer();
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        const int e = ze(x, y, z - 1);
+        Mat M0(4, 0.0), M1(4, 0.0);
+        for (int g = 0; g < 2; ++g)
+          for (int g2 = 0; g2 < 2; ++g2) {
+            M0[g2 * 2 + g] = W(e, g ^ g2);
+            M1[g2 * 2 + g] = W(e, 1 ^ g ^ g2);
+          }
+        std::string er = A.add_pre(y * L + x, M0, 2, ndet + e, M1);
+        if (!er.empty()) return er;
+      }
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x + 1 < L; ++x) {
+        const int e = xe(x, y, z);
+        A.add_gate(0, x, y, gate_terms(e, 1), ndet + e, gate_terms(e, -1));
+      }
+    for (int y = 0; y + 1 < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        const int e = ye(x, y, z);
+        A.add_gate(1, x, y, gate_terms(e, 1), ndet + e, gate_terms(e, -1));
+      }
+    std::string er = A.end_layer();
+    if (!er.empty()) return er;
+  }
+  std::vector<Mat> f;
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const int e = ze(x, y, L - 1);
+      f.push_back({W(e, 0), W(e, 1)});
     }
   A.finish(f);
   return "";

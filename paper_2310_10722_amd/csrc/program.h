@@ -81,11 +81,15 @@ struct Program {
   // are parities that vanish for every syndrome the code can produce; an item
   // with one of them set is inconsistent (log p = -inf for every coset).
   int32_t inc0 = 0, n_inc = 0;
+  // Walsh-Hadamard form: the two "cosets" are the signed networks Z_0, Z_1
+  // (their values may be negative) and log p_{m,L} = log((Z_0 + (-1)^L Z_1)/2).
+  int32_t wht = 0;
 };
 
 // Builders; return an empty string on success, else an error message.
-std::string build_surface3d_point(int32_t L, const double* p_mech, Program& out);
+std::string build_surface3d_point(int32_t L, const double* p_mech, Program& out, bool wht = false);
 std::string build_rotated_phenom(int32_t d, int32_t T, const double* p_mech, Program& out);
 std::string build_surface3d_depol(int32_t L, const double* p_qubit, Program& out);
+std::string build_surface3d_loop(int32_t L, const double* p_mech, Program& out, bool wht = false);
 
 }  // namespace tn3d

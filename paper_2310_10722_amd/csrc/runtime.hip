@@ -40,11 +40,20 @@ struct GraphKey {
   int timing;
   char* ws;
   size_t ws_bytes;
+  std::vector<int32_t> sched;  // chi-schedule (empty: constant chi)
   bool operator<(const GraphKey& o) const {
-    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes) <
-           std::tie(o.net, o.prec, o.chi, o.chi_mps, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws, o.ws_bytes);
+    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes, sched) <
+           std::tie(o.net, o.prec, o.chi, o.chi_mps, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws, o.ws_bytes,
+                    o.sched);
   }
 };
+
+// Rank-rule cap of absorbed layer li under the parameters' chi-schedule.
+int32_t layer_chi(const tn3d_params& pr, size_t li) {
+  if (pr.n_chi_layers <= 0) return pr.chi;
+  const int k = int(std::min<size_t>(li, size_t(pr.n_chi_layers - 1)));
+  return std::min(pr.chi, pr.chi_layers[k]);
+}
 
 struct GraphEntry {
   hipGraphExec_t exec;
@@ -305,7 +314,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       return fail(c, TN3D_E_OOM, "one item needs " + std::to_string(fixed + L.per_sweep_bytes * nc) +
                                      " bytes of workspace, beyond the " + std::to_string(budget) +
                                      "-byte static scratch of tn3d_contract_cosets_noalloc");
-    return fail(c, TN3D_E_OOM, "workspace cap below one item");
+    return fail(c, TN3D_E_OOM, "workspace cap below one item (one item needs " +
+                                   std::to_string(fixed + L.per_sweep_bytes * nc) + " bytes)");
   }
   int64_t chunk_items = int64_t((budget - fixed) / (L.per_sweep_bytes * nc));
   chunk_items = std::max<int64_t>(1, std::min<int64_t>(chunk_items, int64_t(items.size())));
@@ -402,6 +412,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.n_bonds = P.n_bonds;
     A.n_cosets = nc;
     A.chi = pr.chi;
+    A.chi_cut = pr.chi;
     A.Lx = P.Lx;
     A.Ly = P.Ly;
     A.sweep_stride = L.sweep_stride;
@@ -421,6 +432,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.qr = f64_orth ? 1 : 0;
     A.inc0 = P.inc0;
     A.n_inc = P.n_inc;
+    A.wht = P.wht;
     A.jtol = prec == TN3D_PREC_FP64 ? 1e-14 : 1e-10;
     A.jfloor = prec == TN3D_PREC_FP64 ? std::min(1e-13, 0.1 * pr.eps_rel) : std::min(1e-8, 0.1 * pr.eps_rel);
     A.bytes_ctr = timing ? reinterpret_cast<unsigned long long*>(ws + o_ctr) : nullptr;
@@ -448,6 +460,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     launch_init(prec, A, n->d_init_dims, n->d_init_off, n->d_bond_dim0, s);
     for (size_t li = 0; li < P.layers.size(); ++li) {
       const LayerRange& R = P.layers[li];
+      A.chi_cut = layer_chi(pr, li);
       launch_onesite(prec, A, n->d_ones + R.pre0, R.pre1 - R.pre0, s);
       for (int k = 0; k < 4; ++k) {
         const int ng = R.gate1[k] - R.gate0[k];
@@ -557,7 +570,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       gather_inputs();
       HIPCHK(c, hipGetLastError());
       const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
-                         c->ws, c->ws_bytes};
+                         c->ws, c->ws_bytes,
+                         std::vector<int32_t>(pr.chi_layers, pr.chi_layers + std::max(0, pr.n_chi_layers))};
       auto it = c->gcache.find(key);
       if (it == c->gcache.end()) {
         hipGraph_t gr = nullptr;
@@ -679,6 +693,15 @@ bool params_ok(const tn3d_params* p, std::string& why) {
     why = "unknown bit in params.flags";
     return false;
   }
+  if (p->n_chi_layers < 0 || p->n_chi_layers > TN3D_MAX_CHI_LAYERS) {
+    why = "n_chi_layers must lie in [0, TN3D_MAX_CHI_LAYERS]";
+    return false;
+  }
+  for (int i = 0; i < p->n_chi_layers; ++i)
+    if (p->chi_layers[i] < 1 || p->chi_layers[i] > p->chi) {
+      why = "chi_layers entries must lie in [1, chi]";
+      return false;
+    }
   return true;
 }
 
@@ -815,6 +838,23 @@ tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx c, int32_t L, const double*
   *out = nullptr;
   Program P;
   std::string e = build_surface3d_depol(L, p, P);
+  return make_net(c, e, std::move(P), out);
+}
+
+tn3d_status tn3d_net_surface3d_loop(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  Program P;
+  std::string e = build_surface3d_loop(L, p, P);
+  return make_net(c, e, std::move(P), out);
+}
+
+tn3d_status tn3d_net_surface3d_wht(tn3d_ctx c, int32_t L, int32_t sector, const double* p, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  if (sector != TN3D_SECTOR_POINT && sector != TN3D_SECTOR_LOOP) return fail(c, TN3D_E_INVALID, "unknown sector");
+  Program P;
+  std::string e = sector == TN3D_SECTOR_POINT ? build_surface3d_point(L, p, P, true) : build_surface3d_loop(L, p, P, true);
   return make_net(c, e, std::move(P), out);
 }
 

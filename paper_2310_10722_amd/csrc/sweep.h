@@ -29,6 +29,8 @@ struct SweepArgs {
   double eps, tau, pchol_tol;
   int32_t qr;                     // 1: truncation factors by Householder QR (FP64 route), 0: through Grams
   int32_t inc0, n_inc;            // consistency bits of an item (Program::inc0, n_inc)
+  int32_t wht;                    // 1: the two sweeps of an item are the signed networks Z_0, Z_1
+  int32_t chi_cut;                // rank-rule cap of the truncations of this layer (<= chi)
   double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
   unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)

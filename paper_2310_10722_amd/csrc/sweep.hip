@@ -31,6 +31,7 @@ constexpr int SNT = 64;       // one wavefront per bond truncation of order 9 to
 constexpr int SNT_BIG = 256;  // four wavefronts per bond truncation of order above 16
 constexpr int TR = 32;     // rows per tile in the Gram / reabsorption kernels
 constexpr int MAXCHI = 64;
+constexpr uint32_t WHT_NEG = 1u << 30;  // per-sweep flag: the signed network's value is negative
 
 template <typename T>
 __device__ __forceinline__ T* tens(const SweepArgs& A, int par, int sweep, int site) {
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     block_norms_sorted(ZA, 1, rB, rB, rA, S, ord);
     for (int m = tid; m < rB; m += NT) Ss[m] = S[ord[m]];
     __syncthreads();
-    Dn = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &split);
+    Dn = rank_rule(Ss, rB, A.chi_cut, A.eps, A.tau, &split);
     s1 = Ss[0];
   }
   const bool bad = !(Dn > 0) || !(s1 > 0.0) || !isfinite(s1);
@@ -1071,7 +1072,7 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
     if (l < rB) Ss[l] = S[ord[l]];
     team_sync();
     if (l == 0) {
-      rr[0] = rank_rule(Ss, rB, A.chi, A.eps, A.tau, &rr[1]);
+      rr[0] = rank_rule(Ss, rB, A.chi_cut, A.eps, A.tau, &rr[1]);
     }
     team_sync();
     Dn = rr[0];
@@ -2240,6 +2241,10 @@ __global__ void k_finish(SweepArgs A, ZipArgs Z, double* logp) {
     f = 32u;
   } else if (z > 0.0 && isfinite(z) && isfinite(lsum)) {
     out = lsum + log(z);
+  } else if (A.wht && z < 0.0 && isfinite(z) && isfinite(lsum)) {
+    // signed network: log |Z| here, the sign for k_wht_combine
+    out = lsum + log(-z);
+    f |= WHT_NEG;
   } else {
     out = __longlong_as_double(0x7ff8000000000000LL);
     f |= 1u;
@@ -2248,6 +2253,40 @@ __global__ void k_finish(SweepArgs A, ZipArgs Z, double* logp) {
   A.flags[s] = f;
   if (c == 0)
     for (int k = A.n_cosets; k < 4; ++k) logp[int64_t(item) * 4 + k] = -INFINITY;
+}
+
+// Walsh-Hadamard form (paper Sec. 3.1): the two sweeps of an item are the
+// signed networks Z_0 (the syndrome probability, positive) and Z_1 (the
+// difference of the two cosets), k_finish left log |Z_b| in the coset slots
+// and the sign of Z_b in WHT_NEG.  log p_{m,L} = log Z_0 + log1p((-1)^L r) -
+// log 2 with r = Z_1 / Z_0.  A truncated Z_1 beyond Z_0 in magnitude, or a
+// negative Z_0, is NUMERIC (NaN); equality gives -inf.
+__global__ void k_wht_combine(int n_items, const int32_t* items, double* logp, uint32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const int item = items[i];
+  uint32_t f0 = flags[int64_t(i) * 2], f1 = flags[int64_t(i) * 2 + 1];
+  double* lp = logp + int64_t(item) * 4;
+  const bool inc = ((f0 | f1) & 32u) != 0;
+  if (!inc) {
+    const double l0 = lp[0], l1 = lp[1];
+    double p0, p1;
+    if ((f0 & WHT_NEG) || isnan(l0) || isnan(l1) || !isfinite(l0)) {
+      p0 = p1 = __longlong_as_double(0x7ff8000000000000LL);
+    } else {
+      const double r = ((f1 & WHT_NEG) ? -1.0 : 1.0) * exp(l1 - l0);
+      p0 = l0 + log1p(r) - 0.69314718055994530942;
+      p1 = l0 + log1p(-r) - 0.69314718055994530942;
+    }
+    if (isnan(p0) || isnan(p1)) {
+      f0 |= 1u;
+      f1 |= 1u;
+    }
+    lp[0] = p0;
+    lp[1] = p1;
+  }
+  flags[int64_t(i) * 2] = f0 & ~WHT_NEG;
+  flags[int64_t(i) * 2 + 1] = f1 & ~WHT_NEG;
 }
 
 __global__ void k_collect_flags(int n_items, int n_cosets, const int32_t* items, const uint32_t* sweep_flags,
@@ -2603,6 +2642,8 @@ void launch_zip_step(const ZipArgs& Z, int x, int y, int legcap, hipStream_t st)
 void launch_finish(const SweepArgs& A, const ZipArgs& Z, double* logp, uint32_t* flags_out, hipStream_t st) {
   hipLaunchKernelGGL(k_finish, dim3((A.n_sweeps + 63) / 64), dim3(64), 0, st, A, Z, logp);
   const int n_items = A.n_sweeps / A.n_cosets;
+  if (A.wht && A.n_cosets == 2)
+    hipLaunchKernelGGL(k_wht_combine, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, A.items, logp, A.flags);
   if (flags_out)
     hipLaunchKernelGGL(k_collect_flags, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, A.n_cosets, A.items,
                        A.flags, flags_out);

@@ -34,7 +34,7 @@ STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OO
 SYMBOLS = [
     "tn3d_params_default", "tn3d_ctx_create", "tn3d_ctx_destroy", "tn3d_last_error",
     "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_surface3d_depolarizing",
-    "tn3d_net_num_detectors",
+    "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
     "tn3d_last_timing", "tn3d_last_stats",
@@ -42,13 +42,27 @@ SYMBOLS = [
 ]
 
 
+MAX_CHI_LAYERS = 32
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("chi", ctypes.c_int32), ("chi_mps", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("reserved0", ctypes.c_int32), ("eps_rel", ctypes.c_double), ("tau_gap", ctypes.c_double),
         ("near_tie", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32),
-        ("reserved1", ctypes.c_uint32),
+        ("reserved1", ctypes.c_uint32), ("n_chi_layers", ctypes.c_int32),
+        ("chi_layers", ctypes.c_int32 * MAX_CHI_LAYERS),
     ]
+
+    def set_chi_schedule(self, chis):
+        """Per-layer truncation caps (layer l uses chis[min(l, len - 1)]);
+        an empty sequence restores the constant chi."""
+        chis = [int(v) for v in chis]
+        if len(chis) > MAX_CHI_LAYERS:
+            raise ValueError(f"at most {MAX_CHI_LAYERS} entries")
+        self.n_chi_layers = len(chis)
+        for i, v in enumerate(chis):
+            self.chi_layers[i] = v
 
 
 _lib = None
@@ -74,6 +88,8 @@ def load_library(path: str | None = None):
     lib.tn3d_net_surface3d_point.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     lib.tn3d_net_rotated_phenom.argtypes = [c_p, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     lib.tn3d_net_surface3d_depolarizing.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    lib.tn3d_net_surface3d_loop.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    lib.tn3d_net_surface3d_wht.argtypes = [c_p, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     for f in ("tn3d_net_num_detectors", "tn3d_net_num_mechanisms", "tn3d_net_num_cosets"):
         getattr(lib, f).argtypes = [c_p]
         getattr(lib, f).restype = i32
@@ -94,7 +110,7 @@ def load_library(path: str | None = None):
     lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
-              "tn3d_net_surface3d_depolarizing", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
+              "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
               "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_ctx_set_graphs"):
         getattr(lib, f).restype = i32
     if path is None:
@@ -204,29 +220,55 @@ class Net:
             pass
 
 
-def _rates(p):
-    a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+def _rates(p, n):
+    """The rate array as contiguous float64 of exactly n entries (the
+    builders read n values through the pointer)."""
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.float64)).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"expected {n} rates, got {a.size}")
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _n_cubic(L):
+    return L ** 3 + 2 * L * (L - 1) ** 2 if L >= 2 else 0
+
+
 def tn3d_net_surface3d_point(ctx: Context, L: int, p_mech) -> Net:
-    a, ptr = _rates(p_mech)
+    a, ptr = _rates(p_mech, _n_cubic(L)) if L >= 2 else _rates(np.zeros(1), 1)
     h = ctypes.c_void_p()
     _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_point(ctx.h, L, ptr, ctypes.byref(h)))
     return Net(ctx, h)
 
 
 def tn3d_net_rotated_phenom(ctx: Context, d: int, T: int, p_mech) -> Net:
-    a, ptr = _rates(p_mech)
+    ok = d >= 3 and d % 2 == 1 and T >= 1
+    a, ptr = _rates(p_mech, T * d * d + T * (d * d - 1) // 2) if ok else _rates(np.zeros(1), 1)
     h = ctypes.c_void_p()
     _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_rotated_phenom(ctx.h, d, T, ptr, ctypes.byref(h)))
     return Net(ctx, h)
 
 
 def tn3d_net_surface3d_depolarizing(ctx: Context, L: int, p_qubit) -> Net:
-    a, ptr = _rates(p_qubit)
+    a, ptr = _rates(p_qubit, _n_cubic(L)) if L >= 2 else _rates(np.zeros(1), 1)
     h = ctypes.c_void_p()
     _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_depolarizing(ctx.h, L, ptr, ctypes.byref(h)))
+    return Net(ctx, h)
+
+
+def tn3d_net_surface3d_loop(ctx: Context, L: int, p_mech) -> Net:
+    a, ptr = _rates(p_mech, _n_cubic(L)) if L >= 2 else _rates(np.zeros(1), 1)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_loop(ctx.h, L, ptr, ctypes.byref(h)))
+    return Net(ctx, h)
+
+
+SECTOR_POINT, SECTOR_LOOP = 0, 1
+
+
+def tn3d_net_surface3d_wht(ctx: Context, L: int, sector: int, p_mech) -> Net:
+    a, ptr = _rates(p_mech, _n_cubic(L)) if L >= 2 else _rates(np.zeros(1), 1)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_surface3d_wht(ctx.h, L, sector, ptr, ctypes.byref(h)))
     return Net(ctx, h)
 
 

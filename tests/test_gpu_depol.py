@@ -64,7 +64,13 @@ def check(got, ref, tol_top, tol_all):
     err_top = err[np.arange(len(ref)), top]
     say("  max |d log p|: most likely coset", err_top.max(), " all cosets", err.max())
     assert err_top.max() <= tol_top
-    assert err.max() <= tol_all
+    if tol_all == "fp32":
+        # a coset e^-gap below the most likely one is read from site tensors
+        # rounded at about 4 eps_32 of the state: error <= 1e-3 + 4 eps_32 e^gap
+        gap = ref.max(axis=1, keepdims=True) - ref
+        assert np.all(err <= 1e-3 + 4.0 * 2.0 ** -24 * np.exp(gap))
+    else:
+        assert err.max() <= tol_all
     srt = np.sort(ref, axis=1)
     clear = srt[:, -1] - srt[:, -2] > tol_top
     assert np.array_equal(np.argmax(got, axis=1)[clear], top[clear])
@@ -128,7 +134,7 @@ def test_depol_L4_chi8(ctx, mode):
         prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
     got, _ = gpu_logp(ctx, net, m, prm)
     ref = oracle(4, dem.params["p_qubit"], m, prm)
-    check(got, ref, *{"fp64_default": (1e-9, 1e-9), "fp64_reduced": (1e-9, 1e-9), "fp32_reduced": (1e-3, 0.5)}[mode])
+    check(got, ref, *{"fp64_default": (1e-9, 1e-9), "fp64_reduced": (1e-9, 1e-9), "fp32_reduced": (1e-3, "fp32")}[mode])
 
 
 def test_depol_L4_chi16_nonuniform(ctx):

@@ -87,3 +87,27 @@ def test_rank_rule():
     assert rank_rule(np.array([1.0, 1e-5, 1e-5 * (1 - 1e-6)]), 2, 1e-12, 1e-4) == (1, False)
     assert rank_rule(np.array([1.0, 1.0, 1.0]), 2, 1e-12, 1e-9) == (2, True)
     assert rank_rule(np.array([2.0]), 1, 1e-12, 1e-9) == (1, False)
+
+
+def test_chi_schedule_pins():
+    """chi-schedule (per-layer truncation caps): a single entry k acts as the
+    constant chi = k for every layer; caps that never bind (bonds after layer
+    l are at most 2 * 2^(l+1) at L = 3, and chi_m = 64 holds the boundary MPS
+    of a 3-wide grid exactly) give the exact contraction."""
+    from oracle.network import point3d_network
+    from oracle.sweep import sweep_logprob
+    from oracle.exact import frontier_logprobs
+    dem = synth.surface3d_point(3, 0.1).with_p(np.random.default_rng(4).uniform(0.05, 0.25, 51))
+    m, _ = synth.sample_syndromes(dem, 2, 5)
+    for k in range(2):
+        for c in range(2):
+            net = point3d_network(3, dem.p, m[k], c)
+            a = sweep_logprob(net, 16, 8, 1e-9, 1e-6, chi_layers=[3])[0]
+            b = sweep_logprob(net, 3, 8, 1e-9, 1e-6)[0]
+            assert a == b
+            big = sweep_logprob(net, 16, 64, 1e-12, 1e-9, chi_layers=[4, 8])[0]
+            ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])[c]
+            assert abs(big - ex) <= 1e-10
+            # a binding cap in the first layer changes the value
+            cut = sweep_logprob(net, 16, 64, 1e-12, 1e-9, chi_layers=[2, 8])[0]
+            assert abs(cut - ex) > 1e-8
