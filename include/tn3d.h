@@ -208,6 +208,26 @@ tn3d_status tn3d_net_surface3d_loop(tn3d_ctx ctx, int32_t L, const double* p_mec
 #define TN3D_SECTOR_LOOP 1
 tn3d_status tn3d_net_surface3d_wht(tn3d_ctx ctx, int32_t L, int32_t sector, const double* p_mech, tn3d_net* out);
 
+/* Generic front end (paper Sec. 2.4 problem statement, Sec. 3.1 and 3.4
+ * detector picture): a detector error model given as the COO pattern of H
+ * (nnz pairs det_idx[k], mech_idx[k]; a pair listed twice cancels), rates
+ * p_mech[n_mech], one observable row obs[n_mech] (0/1) and detector
+ * coordinates det_coord[n_det][3] = (x, y, t) >= 0, which define the sweep:
+ * layers by t, one detector per (x, y, t) on an x-by-y grid.  Supported
+ * models are graph-like on that grid: every mechanism flips one detector, or
+ * two at grid-adjacent (x, y) of one layer, or two at one (x, y) in layers t
+ * and t + 1; parallel mechanisms are merged exactly.  The observable must
+ * consist of single-detector mechanisms of the first layer (the coset is
+ * chained over their flips).  The syndrome of an item is n_det bytes in
+ * detector order; two cosets.  All inputs are host pointers, copied.
+ * Errors: TN3D_E_INVALID (null pointers, index or rate out of range,
+ * negative coordinates, two detectors at one grid point),
+ * TN3D_E_UNSUPPORTED (a model outside that class, more than one
+ * observable). */
+tn3d_status tn3d_net_from_dem(tn3d_ctx ctx, int32_t n_det, int32_t n_mech, int64_t nnz, const int32_t* det_idx,
+                              const int32_t* mech_idx, const double* p_mech, int32_t n_obs, const uint8_t* obs,
+                              const int32_t* det_coord, tn3d_net* out);
+
 int32_t tn3d_net_num_detectors(tn3d_net net);
 int32_t tn3d_net_num_mechanisms(tn3d_net net);
 int32_t tn3d_net_num_cosets(tn3d_net net);
@@ -260,6 +280,23 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
                         const uint8_t* syndromes_dev, const int64_t* offsets_dev,
                         const tn3d_params* params, int32_t* coset_dev, double* logratio_dev,
                         double* logp_dev, uint32_t* flags_dev);
+
+/* Autotuner (batching): searches the launch shapes of the layer absorption
+ * (the size-class split points of the truncation kernels: teams of eight
+ * lanes for orders <= 8 on or off, one-wavefront truncations up to order 8
+ * or 16; a separate reabsorption class for rows of at most 16 entries on or
+ * off) by contracting the given batch under each candidate (twice: capture,
+ * then a timed replay), and caches the fastest for each network of the batch
+ * under params' precision, chi and chi_mps in the context; later contractions
+ * with those parameters use it.  A candidate whose decoded-coset log p leaves
+ * the default shape's by more than 1e-9 (FP64) or 1e-4 (reduced precisions),
+ * or that changes a decision, is not chosen.  out (nullable, n_out <= 6):
+ * chosen candidate index, team, mid, narrow, its time and the default
+ * shape's time (ms, one contraction of the batch).  The batch arguments are
+ * those of tn3d_contract_cosets; the call synchronises the context stream
+ * and allocates two result buffers.  Errors: as tn3d_contract_cosets. */
+tn3d_status tn3d_autotune(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets, const uint8_t* syndromes_dev,
+                          const int64_t* offsets_dev, const tn3d_params* params, double* out, int32_t n_out);
 
 /* Timing of the contractions on this context: enable = 0 off, 1 kernel times,
  * 2 kernel times and bond statistics (tn3d_last_stats; this level copies the

@@ -966,4 +966,175 @@ std::string build_surface3d_loop(int32_t L, const double* p, Program& P, bool wh
   return "";
 }
 
+// ---------------------------------------------------------------------------
+// Generic front end: the detector-picture network (paper Sec. 3.1, 3.4) of a
+// graph-like DEM whose detectors sit on a grid, swept along the detector
+// coordinate t (layers) over the (x, y) grid.  Every mechanism flips one or
+// two detectors: two at grid-adjacent sites of one layer (an in-plane gate
+// (1-p) I I + p X X), two at one site in consecutive layers (time-like: the
+// flip carried on the site's physical leg from the lower detector to the
+// upper one), or one (a boundary flip (1-p) I + p X on the detector's
+// parity).  Parallel mechanisms are merged exactly (the parity of independent
+// flips).  The physical leg of a site holds the parity of its current
+// detector; after the layer's gates the detector's check sets it to m_d:
+// with a time-like edge upwards the leg then carries that edge's flip
+// (weight diag(1-q, q)), otherwise it is projected on parity m_d and the site
+// holds no bit until its next detector.  The observable (one row) must
+// consist of boundary mechanisms of the first layer: their flips are the
+// initial bits, chained to the coset parity (as the bottom dangling edges of
+// the 3D planar code).
+// ---------------------------------------------------------------------------
+std::string build_from_dem(int32_t n_det, int32_t n_mech, int64_t nnz, const int32_t* det_idx,
+                           const int32_t* mech_idx, const double* p, int32_t n_obs, const uint8_t* obs,
+                           const int32_t* coord, Program& P) {
+  if (n_det < 1 || n_mech < 1 || nnz < 0) return "empty DEM";
+  if (!det_idx || !mech_idx || !p || !obs || !coord) return "null pointer";
+  if (n_obs != 1) return "UNSUPPORTED: exactly one observable row is supported";
+  for (int i = 0; i < n_mech; ++i)
+    if (!(p[i] >= 0.0 && p[i] <= 1.0)) return "rate outside [0, 1]";
+  // detectors of each mechanism (a detector listed twice cancels)
+  std::vector<std::vector<int>> md(n_mech);
+  for (int64_t k = 0; k < nnz; ++k) {
+    const int d = det_idx[k], m = mech_idx[k];
+    if (d < 0 || d >= n_det || m < 0 || m >= n_mech) return "COO index out of range";
+    auto& v = md[m];
+    auto it = std::find(v.begin(), v.end(), d);
+    if (it == v.end())
+      v.push_back(d);
+    else
+      v.erase(it);
+  }
+  int Lx = 0, Ly = 0, t0 = INT32_MAX, t1 = INT32_MIN;
+  for (int d = 0; d < n_det; ++d) {
+    const int x = coord[3 * d], y = coord[3 * d + 1], t = coord[3 * d + 2];
+    if (x < 0 || y < 0) return "negative detector coordinate";
+    Lx = std::max(Lx, x + 1);
+    Ly = std::max(Ly, y + 1);
+    t0 = std::min(t0, t);
+    t1 = std::max(t1, t);
+  }
+  if (int64_t(Lx) * Ly > 4096) return "UNSUPPORTED: grid above 4096 sites";
+  const int nl = t1 - t0 + 1, ns = Lx * Ly;
+  if (nl > 4096) return "UNSUPPORTED: more than 4096 layers";
+  std::vector<int> at(size_t(ns) * nl, -1);  // detector at (site, layer)
+  std::vector<int> dsite(n_det), dlay(n_det);
+  for (int d = 0; d < n_det; ++d) {
+    const int s = coord[3 * d + 1] * Lx + coord[3 * d], l = coord[3 * d + 2] - t0;
+    if (at[size_t(s) * nl + l] >= 0) return "two detectors share a grid point";
+    at[size_t(s) * nl + l] = d;
+    dsite[d] = s;
+    dlay[d] = l;
+  }
+  // merged odd-parity probabilities: q_odd of independent flips q_a, q_b
+  auto merge = [](double a, double b) { return a + b - 2.0 * a * b; };
+  std::vector<double> bnd(n_det, 0.0), up(n_det, 0.0), obs0(ns, 0.0);
+  std::vector<char> has_up(n_det, 0), has_obs(ns, 0);
+  std::map<std::pair<int, int>, double> inplane;  // (lower det, higher det) -> q
+  for (int m = 0; m < n_mech; ++m) {
+    const auto& v = md[m];
+    const bool in_obs = obs[m] != 0;
+    if (v.empty()) {
+      if (in_obs) return "UNSUPPORTED: a mechanism flips the observable but no detector";
+      continue;  // sums to one
+    }
+    if (v.size() > 2) return "UNSUPPORTED: a mechanism flips more than two detectors";
+    if (v.size() == 1) {
+      const int d = v[0];
+      if (in_obs) {
+        if (dlay[d] != 0) return "UNSUPPORTED: observable mechanisms must be boundary flips of the first layer";
+        obs0[dsite[d]] = merge(obs0[dsite[d]], p[m]);
+        has_obs[dsite[d]] = 1;
+      } else {
+        bnd[d] = merge(bnd[d], p[m]);
+      }
+      continue;
+    }
+    if (in_obs) return "UNSUPPORTED: observable mechanisms must be boundary flips of the first layer";
+    int a = v[0], b = v[1];
+    if (dlay[a] > dlay[b] || (dlay[a] == dlay[b] && dsite[a] > dsite[b])) std::swap(a, b);
+    const int xa = dsite[a] % Lx, ya = dsite[a] / Lx, xb = dsite[b] % Lx, yb = dsite[b] / Lx;
+    if (dlay[a] == dlay[b] && std::abs(xa - xb) + std::abs(ya - yb) == 1) {
+      auto key = std::make_pair(a, b);
+      auto it = inplane.find(key);
+      inplane[key] = it == inplane.end() ? p[m] : merge(it->second, p[m]);
+    } else if (dsite[a] == dsite[b] && dlay[b] == dlay[a] + 1) {
+      up[a] = merge(up[a], p[m]);
+      has_up[a] = 1;
+    } else {
+      return "UNSUPPORTED: a mechanism joins detectors that are neither grid neighbours of one layer nor one site "
+             "in consecutive layers";
+    }
+  }
+
+  P = Program{};
+  P.name = "dem_" + std::to_string(n_det) + "x" + std::to_string(n_mech);
+  P.n_det = n_det;
+  P.n_mech = n_mech;
+  P.n_cosets = 2;
+  Assembler A(P, Lx, Ly);
+  for (int c = 0; c < 2; ++c) {
+    std::vector<std::vector<double>> w(ns);
+    for (int s2 = 0; s2 < ns; ++s2)
+      if (has_obs[s2]) w[s2] = {1.0 - obs0[s2], obs0[s2]};
+    A.d.assign(ns, 1);
+    A.snake_init(w, c);
+  }
+  const Mat I2 = eye(2);
+  for (int l = 0; l < nl; ++l) {
+    A.begin_layer();
+    for (int s2 = 0; s2 < ns; ++s2) {
+      const int d = at[size_t(s2) * nl + l];
+      if (d < 0) continue;
+      if (A.staged_dim(s2) == 1) {
+        // no bit on the site yet: the detector's parity starts at 0
+        std::string er = A.add_pre(s2, Mat{1.0, 0.0}, 2);
+        if (!er.empty()) return er;
+      }
+      if (bnd[d] > 0.0) {
+        std::string er = A.add_pre(s2, flip_op(bnd[d], 2, 1), 2);
+        if (!er.empty()) return er;
+      }
+    }
+    for (const auto& kv : inplane) {
+      const int a = kv.first.first, b = kv.first.second;
+      if (dlay[a] != l) continue;
+      const int sa = dsite[a], sb = dsite[b];
+      const int xa = sa % Lx, ya = sa / Lx;
+      // the assembler's gate joins (x, y) with its east or south neighbour
+      if (sb == sa + 1)
+        A.add_gate(0, xa, ya, flip_gate(kv.second, 2, 1, 2, 1));
+      else if (sb == sa + Lx)
+        A.add_gate(1, xa, ya, flip_gate(kv.second, 2, 1, 2, 1));
+      else
+        return "internal: in-plane pair not ordered";
+    }
+    for (int s2 = 0; s2 < ns; ++s2) {
+      const int d = at[size_t(s2) * nl + l];
+      if (d < 0) continue;
+      std::string er;
+      if (has_up[d]) {
+        // the leg becomes the flip of the edge to the next detector: X^m,
+        // then its weight
+        const double q = up[d];
+        Mat wq = {1.0 - q, 0.0, 0.0, q};
+        er = A.add_post(s2, wq, 2, d, matmul(wq, 2, 2, xmask(2, 1), 2));
+      } else {
+        // parity must equal m_d: keep b = m_d, the site holds no bit after
+        er = A.add_post(s2, Mat{1.0, 0.0}, 1, d, Mat{0.0, 1.0});
+      }
+      if (!er.empty()) return er;
+    }
+    std::string er = A.end_layer();
+    if (!er.empty()) return er;
+  }
+  std::vector<Mat> f(ns);
+  for (int s2 = 0; s2 < ns; ++s2) {
+    if (A.d[s2] != 1) return "internal: a bit left after the last layer";
+    f[s2] = {1.0};
+  }
+  A.finish(f);
+  return "";
+}
+
 }  // namespace tn3d
+

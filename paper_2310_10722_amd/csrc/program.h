@@ -91,5 +91,8 @@ std::string build_surface3d_point(int32_t L, const double* p_mech, Program& out,
 std::string build_rotated_phenom(int32_t d, int32_t T, const double* p_mech, Program& out);
 std::string build_surface3d_depol(int32_t L, const double* p_qubit, Program& out);
 std::string build_surface3d_loop(int32_t L, const double* p_mech, Program& out, bool wht = false);
+std::string build_from_dem(int32_t n_det, int32_t n_mech, int64_t nnz, const int32_t* det_idx,
+                           const int32_t* mech_idx, const double* p_mech, int32_t n_obs, const uint8_t* obs,
+                           const int32_t* det_coord, Program& out);
 
 }  // namespace tn3d

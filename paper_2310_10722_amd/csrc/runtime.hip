@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -41,12 +42,24 @@ struct GraphKey {
   char* ws;
   size_t ws_bytes;
   std::vector<int32_t> sched;  // chi-schedule (empty: constant chi)
+  int tune;                    // launch-shape choice (LaunchTuning, packed)
   bool operator<(const GraphKey& o) const {
-    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes, sched) <
+    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes, sched, tune) <
            std::tie(o.net, o.prec, o.chi, o.chi_mps, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws, o.ws_bytes,
-                    o.sched);
+                    o.sched, o.tune);
   }
 };
+
+// The autotuner's cache key: a network under one precision, chi and chi_mps.
+struct TuneKey {
+  uint64_t net;
+  int prec, chi, chi_mps;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(net, prec, chi, chi_mps) < std::tie(o.net, o.prec, o.chi, o.chi_mps);
+  }
+};
+
+int pack_tuning(const LaunchTuning& T) { return T.team | (T.mid << 1) | (T.narrow << 8); }
 
 // Rank-rule cap of absorbed layer li under the parameters' chi-schedule.
 int32_t layer_chi(const tn3d_params& pr, size_t li) {
@@ -77,6 +90,7 @@ struct tn3d_ctx_s {
   size_t aux_bytes = 0;
   char* scratch = nullptr;         // this device's copy of the static scratch array
   bool graphs = true;              // replay captured launch sequences
+  std::map<TuneKey, LaunchTuning> tune;  // launch shapes chosen by tn3d_autotune
   hipStream_t cap_stream = nullptr;  // private stream the sequences are captured on
   uint64_t next_serial = 1;
   std::map<GraphKey, GraphEntry> gcache;
@@ -292,6 +306,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   const int nc = P.n_cosets;
   const int max_g = std::max(1, n->max_gates_class);
   Layout L = make_layout(P, pr.chi, pr.chi_mps, prec, max_g);
+  LaunchTuning TU;
+  {
+    auto it = c->tune.find(TuneKey{n->serial, prec, pr.chi, pr.chi_mps});
+    if (it != c->tune.end()) TU = it->second;
+  }
   // the kernels' fixed-size LDS arrays bound these (sweep.hip)
   if (L.ncap > 64) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 64 on a gated site");
   if (L.kdcap > 64) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 64");
@@ -330,7 +349,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_buf0 = cv.take<char>(nsw_max * L.sweep_stride * esz);
   size_t o_buf1 = cv.take<char>(nsw_max * L.sweep_stride * esz);
   size_t o_bd = cv.take<int32_t>(nsw_max * P.n_bonds);
-  size_t o_lam = cv.take<double>(nsw_max * P.n_bonds * pr.chi);
+  size_t o_lam = cv.take<double>(nsw_max * P.n_bonds * L.legcap);
   size_t o_logb = cv.take<double>(nsw_max * P.n_bonds);
   size_t o_logs = cv.take<double>(nsw_max * P.Lx * P.Ly);
   size_t o_flags = cv.take<uint32_t>(nsw_max);
@@ -413,6 +432,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.n_cosets = nc;
     A.chi = pr.chi;
     A.chi_cut = pr.chi;
+    A.lam_ld = L.legcap;
     A.Lx = P.Lx;
     A.Ly = P.Ly;
     A.sweep_stride = L.sweep_stride;
@@ -478,9 +498,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
         A.win = timing ? win + size_t(2 * cls) * 128 : nullptr;
         launch_gram(prec, A, gp, ng, n_wider(16), n_wider(32), gram, L.ncap, s);
         A.win = nullptr;
-        launch_solve(A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
+        launch_solve(TU, A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
         A.win = timing ? win + size_t(2 * cls + 1) * 128 : nullptr;
-        launch_reabsorb(prec, A, gp, ng, n_wider(16), n_wider(32), wbuf, L.ncap, s);
+        launch_reabsorb(TU, prec, A, gp, ng, n_wider(16), n_wider(32), wbuf, L.ncap, s);
         A.win = nullptr;
         hot_l += 2;
       }
@@ -571,7 +591,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       HIPCHK(c, hipGetLastError());
       const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
                          c->ws, c->ws_bytes,
-                         std::vector<int32_t>(pr.chi_layers, pr.chi_layers + std::max(0, pr.n_chi_layers))};
+                         std::vector<int32_t>(pr.chi_layers, pr.chi_layers + std::max(0, pr.n_chi_layers)),
+                         pack_tuning(TU)};
       auto it = c->gcache.find(key);
       if (it == c->gcache.end()) {
         hipGraph_t gr = nullptr;
@@ -638,7 +659,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     }
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
-      std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * pr.chi);
+      std::vector<double> lm(size_t(A.n_sweeps) * P.n_bonds * L.legcap);
       HIPCHK(c, hipMemcpy(bd.data(), A.bond_dim, bd.size() * 4, hipMemcpyDeviceToHost));
       HIPCHK(c, hipMemcpy(lm.data(), A.lam, lm.size() * 8, hipMemcpyDeviceToHost));
       for (int sw = 0; sw < A.n_sweeps; ++sw) {
@@ -647,7 +668,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
           const int D = bd[size_t(sw) * P.n_bonds + b];
           c->stats_out[0] += D;
           c->stats_out[1] = std::max(c->stats_out[1], double(D));
-          mn = std::min(mn, lm[(size_t(sw) * P.n_bonds + b) * pr.chi + D - 1]);
+          mn = std::min(mn, lm[(size_t(sw) * P.n_bonds + b) * L.legcap + D - 1]);
         }
         c->stats_out[3] += mn;
       }
@@ -858,6 +879,17 @@ tn3d_status tn3d_net_surface3d_wht(tn3d_ctx c, int32_t L, int32_t sector, const 
   return make_net(c, e, std::move(P), out);
 }
 
+tn3d_status tn3d_net_from_dem(tn3d_ctx c, int32_t n_det, int32_t n_mech, int64_t nnz, const int32_t* det_idx,
+                              const int32_t* mech_idx, const double* p_mech, int32_t n_obs, const uint8_t* obs,
+                              const int32_t* det_coord, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  Program P;
+  std::string e = build_from_dem(n_det, n_mech, nnz, det_idx, mech_idx, p_mech, n_obs, obs, det_coord, P);
+  if (e.rfind("UNSUPPORTED: ", 0) == 0) return fail(c, TN3D_E_UNSUPPORTED, e.substr(13));
+  return make_net(c, e, std::move(P), out);
+}
+
 int32_t tn3d_net_num_detectors(tn3d_net n) { return n ? n->P.n_det : -1; }
 int32_t tn3d_net_num_mechanisms(tn3d_net n) { return n ? n->P.n_mech : -1; }
 int32_t tn3d_net_num_cosets(tn3d_net n) { return n ? n->P.n_cosets : -1; }
@@ -902,6 +934,91 @@ tn3d_status tn3d_contract_cosets_noalloc(tn3d_ctx c, int32_t batch, const tn3d_n
                                          const int64_t* offs, const tn3d_params* pr, double* logp,
                                          uint32_t* flags) {
   return contract_impl(c, batch, nets, synd, offs, pr, logp, flags, true);
+}
+
+// Autotuner: every candidate launch shape runs the caller's batch twice (the
+// first run captures its launch sequence), the second is timed on the host
+// around a synchronised stream; candidates whose results leave the default
+// shape's decoded coset by more than the precision's rounding (1e-9 in FP64,
+// 1e-4 otherwise) or change a decision are rejected.
+tn3d_status tn3d_autotune(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const uint8_t* synd,
+                          const int64_t* offs, const tn3d_params* pr, double* out, int32_t n_out) {
+  if (!c) return TN3D_E_INVALID;
+  std::string why;
+  if (!params_ok(pr, why)) return fail(c, TN3D_E_INVALID, why);
+  if (batch <= 0 || !nets || !synd || !offs) return fail(c, TN3D_E_INVALID, "empty batch or null pointer");
+  std::vector<tn3d_net> uniq;
+  for (int i = 0; i < batch; ++i) {
+    if (!nets[i] || nets[i]->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
+    if (std::find(uniq.begin(), uniq.end(), nets[i]) == uniq.end()) uniq.push_back(nets[i]);
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  const int prec = pr->precision;
+  const std::vector<LaunchTuning> cand = {{1, 16, 1}, {0, 16, 1}, {1, 8, 1}, {1, 16, 0}, {0, 16, 0}, {0, 8, 0}};
+  double* d_lp = nullptr;
+  uint32_t* d_fl = nullptr;
+  if (hipMalloc(&d_lp, size_t(batch) * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&d_fl, size_t(batch) * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (d_lp) (void)hipFree(d_lp);
+    return fail(c, TN3D_E_OOM, "autotune result buffers");
+  }
+  std::vector<double> ref(size_t(batch) * 4), cur(size_t(batch) * 4);
+  const double tol = prec == TN3D_PREC_FP64 ? 1e-9 : 1e-4;
+  double best_ms = 0.0, def_ms = 0.0;
+  int best = 0;
+  tn3d_status st = TN3D_OK;
+  for (size_t k = 0; k < cand.size() && st == TN3D_OK; ++k) {
+    for (tn3d_net n : uniq) c->tune[TuneKey{n->serial, prec, pr->chi, pr->chi_mps}] = cand[k];
+    st = contract_impl(c, batch, nets, synd, offs, pr, d_lp, d_fl);
+    if (st != TN3D_OK) break;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      st = fail(c, TN3D_E_DEVICE, "autotune: stream synchronisation failed");
+      break;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    st = contract_impl(c, batch, nets, synd, offs, pr, d_lp, d_fl);
+    if (st != TN3D_OK) break;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      st = fail(c, TN3D_E_DEVICE, "autotune: stream synchronisation failed");
+      break;
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (hipMemcpy(cur.data(), d_lp, cur.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+      st = fail(c, TN3D_E_DEVICE, "autotune: result copy failed");
+      break;
+    }
+    bool ok = true;
+    if (k == 0) {
+      ref = cur;
+      def_ms = best_ms = ms;
+    } else {
+      const int nc = 4;
+      for (int i = 0; i < batch && ok; ++i) {
+        int a = 0, b = 0;
+        for (int q = 1; q < nc; ++q) {
+          if (ref[size_t(i) * nc + q] > ref[size_t(i) * nc + a]) a = q;
+          if (cur[size_t(i) * nc + q] > cur[size_t(i) * nc + b]) b = q;
+        }
+        const double x = ref[size_t(i) * nc + a], y = cur[size_t(i) * nc + a];
+        if (std::isnan(x) != std::isnan(y)) ok = false;
+        else if (std::isfinite(x) && !(std::fabs(x - y) <= tol)) ok = false;
+        else if (a != b && std::isfinite(x) && std::fabs(x - cur[size_t(i) * nc + b]) > tol) ok = false;
+      }
+      if (ok && ms < best_ms) {
+        best_ms = ms;
+        best = int(k);
+      }
+    }
+  }
+  (void)hipFree(d_lp);
+  (void)hipFree(d_fl);
+  for (tn3d_net n : uniq) c->tune[TuneKey{n->serial, prec, pr->chi, pr->chi_mps}] = cand[best];
+  if (st != TN3D_OK) return st;
+  const double vals[6] = {double(best), double(cand[best].team), double(cand[best].mid), double(cand[best].narrow),
+                          best_ms, def_ms};
+  for (int i = 0; out && i < n_out && i < 6; ++i) out[i] = vals[i];
+  return TN3D_OK;
 }
 
 // Decision for each item of a batch from its coset log-probabilities, grouped

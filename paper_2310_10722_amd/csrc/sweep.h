@@ -17,7 +17,8 @@ struct SweepArgs {
   void* buf0;               // site tensors, parity 0
   void* buf1;               // site tensors, parity 1
   int32_t* bond_dim;        // [sweep][n_bonds]
-  double* lam;              // [sweep][n_bonds][chi]
+  double* lam;              // [sweep][n_bonds][lam_ld]
+  int32_t lam_ld;           // entries per bond in lam: the bond capacity max(chi, 2)
   double* logb;             // [sweep][n_bonds] sum of log S_1 of the gates on the bond
   double* logs;             // [sweep][n_sites] sum of log rescale factors
   uint32_t* flags;          // [sweep]
@@ -89,9 +90,19 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 // (A.qr: the triangular factors of k_qr instead of the Grams)
 void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
                  int ncap, hipStream_t st);
-void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout,
+// Launch-shape choices of the layer absorption (the autotuner's search
+// space): team = 1 runs truncations of order <= 8 eight per wavefront;
+// truncations of order up to mid (8 or 16) run on one wavefront, larger ones
+// on four; narrow = 1 gives rows of at most 16 entries their own
+// reabsorption class.
+struct LaunchTuning {
+  int32_t team = 1, mid = 16, narrow = 1;
+};
+
+void launch_solve(const LaunchTuning& T, const SweepArgs& A, const DevGate* gates, int n_g, const double* gin,
+                  double* wout,
                   int ncap, int kdcap, hipStream_t st);
-void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
+void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
                      const double* win, int ncap, hipStream_t st);
 void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
                     hipStream_t st);

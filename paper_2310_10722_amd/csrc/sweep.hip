@@ -95,7 +95,7 @@ __global__ void k_init_bonds(SweepArgs A, const int32_t* bond_dim0) {
     const int64_t bi = int64_t(sweep) * A.n_bonds + b;
     A.bond_dim[bi] = bond_dim0[b];
     A.logb[bi] = 0.0;
-    for (int k = 0; k < A.chi; ++k) A.lam[bi * A.chi + k] = 1.0;
+    for (int k = 0; k < A.lam_ld; ++k) A.lam[bi * A.lam_ld + k] = 1.0;
   }
   for (int s = threadIdx.x; s < A.n_sites; s += blockDim.x) A.logs[int64_t(sweep) * A.n_sites + s] = 0.0;
   if (threadIdx.x == 0) A.flags[sweep] = 0u;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, 
     const int l = e / MAXCHI, k = e % MAXCHI;
     const int b = A.leg_bond[site * 4 + l];
     double val = 1.0;
-    if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.lam_ld + k]);
     slam[l][k] = val;
   }
   const int li = lane & 15, lq = lane >> 4;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates,
     const int lg = e / MAXCHI, k = e % MAXCHI;
     const int b = A.leg_bond[site * 4 + lg];
     double val = 1.0;
-    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.lam_ld + k]);
     slam[lg][k] = val;
   }
   // memory-order column mc = x d + p: offset x Cp d + p in a row, Gram column p Dx + x
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(64) void k_qr(SweepArgs A, const DevGate* gates, in
     const int lg = e / MAXCHI, k = e % MAXCHI;
     const int b = A.leg_bond[site * 4 + lg];
     double val = 1.0;
-    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.chi + k]);
+    if (lg != leg && b >= 0 && k < D[lg]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.lam_ld + k]);
     slam[lg][k] = val;
   }
   int cofs = -1;
@@ -823,7 +823,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (split) f |= 2u;
     if (f) atomicOr(&A.flags[sweep], f);
   }
-  for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.lam_ld + m] = bad ? 1.0 : Ss[m] / s1;
   write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT);
 }
 
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
     if (split) f |= 2u;
     if (f) atomicOr(&A.flags[sweep], f);
   }
-  for (int m = l; m < Dn; m += TL) A.lam[bidx * A.chi + m] = bad ? 1.0 : Ss[m] / s1;
+  for (int m = l; m < Dn; m += TL) A.lam[bidx * A.lam_ld + m] = bad ? 1.0 : Ss[m] / s1;
   write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, l, TL);
 }
 
@@ -1825,6 +1825,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bbig(ZipArgs Z, int x, int y, int l
 // The start is the columns of G at its SB largest diagonal entries.  Block
 // vectors (nv x SB, row-major) live in the sweep's Jm scratch.
 constexpr int SB = 64;
+constexpr int CHEB = 4;  // degree of the subspace iteration's Chebyshev filter
+static_assert(CHEB % 3 == 1, "the filter's buffer rotation ends in Y for CHEB = 1 (mod 3)");
 
 // Cyclic Jacobi on the symmetric n x n A (n <= 64, LDS, row stride 65) by a
 // 512-thread workgroup: the round-robin order gives 32 disjoint rotations per
@@ -2043,9 +2045,10 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   __syncthreads();
   block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x1234u);
   const double tol = Z.sub_tol;
-  int it = 0, conv = 0;
-  const int maxit = 80;
+  int it = 0, conv = 0, n_gemm = 0;
+  const int maxit = 48;
   for (; it < maxit; ++it) {
+    ++n_gemm;
     // Y = G X
     block_gemm512<true, false>(
         nv, SB, nv, [&](int m, int k) { return G[int64_t(m) * nv + k]; }, [&](int k, int n) { return X[k * SB + n]; },
@@ -2101,14 +2104,49 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
       break;
     }
     if (it + 1 == maxit) break;
-    // next block: P diag(1 / theta), orthonormalised
-    const double fl = 1e-15 * t1;
-    for (int e = tid; e < nv * SB; e += ZNT) {
-      const int j = e % SB;
-      Y[e] = P[e] / fmax(th[j], fl);
+    const double c_lo = th[SB - 1];
+    if (c_lo > 1e-12 * t1 && t1 > 1.05 * c_lo) {
+      // next block: a Chebyshev filter of degree CHEB applied to the Ritz
+      // vectors U (G U = P is at hand): T_CHEB((G - cen) / hw) damps the
+      // interval [0, c_lo] below the block's smallest Ritz value and grows
+      // the wanted end; the three-term recurrence is scaled so that the
+      // component at the largest Ritz value t1 stays near one (no overflow).
+      // One orthonormalisation and Rayleigh-Ritz step per CHEB products.
+      const double hw = 0.5 * c_lo, cen = 0.5 * c_lo;
+      const double sig1 = hw / (t1 - cen);
+      double sig = sig1;
+      for (int e = tid; e < nv * SB; e += ZNT) Y[e] = (P[e] - cen * U[e]) * (sig1 / hw);
+      __syncthreads();
+      double *pa = U, *pb = Y, *pt = X;  // steps j-1, j and the product buffer
+      for (int deg = 2; deg <= CHEB; ++deg) {
+        const double sn = 1.0 / (2.0 / sig1 - sig);
+        block_gemm512<true, false>(
+            nv, SB, nv, [&](int m, int k) { return G[int64_t(m) * nv + k]; },
+            [&](int k, int n) { return pb[k * SB + n]; }, [&](int m, int n, double v) { pt[m * SB + n] = v; }, gl);
+        __syncthreads();
+        const double ca = 2.0 * sn / hw, cb = sig * sn;
+        for (int e = tid; e < nv * SB; e += ZNT) pt[e] = ca * (pt[e] - cen * pb[e]) - cb * pa[e];
+        __syncthreads();
+        double* q = pa;
+        pa = pb;
+        pb = pt;
+        pt = q;
+        sig = sn;
+        ++n_gemm;
+      }
+      // CHEB = 1 (mod 3): the filtered block is back in Y
+      block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
+    } else {
+      // no interval to damp (a flat or rank-deficient block): a power step,
+      // P diag(1 / theta), orthonormalised
+      const double fl = 1e-15 * t1;
+      for (int e = tid; e < nv * SB; e += ZNT) {
+        const int j = e % SB;
+        Y[e] = P[e] / fmax(th[j], fl);
+      }
+      __syncthreads();
+      block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
     }
-    __syncthreads();
-    block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
   }
   // the rank rule on sqrt(theta), the kept Ritz vectors into Fv
   for (int j = tid; j < SB; j += ZNT) Sout[j] = sqrt(fmax(th[j], 0.0));
@@ -2120,10 +2158,11 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
   for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = U[(e / Dn) * SB + e % Dn];
   if (Z.flop_b && tid == 0) {
-    // algorithmic flops per iteration: the block product 2 nv^2 SB, the
-    // Ritz projection and rotations 6 nv SB^2, Cholesky QR twice 8 nv SB^2
+    // algorithmic flops: 2 nv^2 SB per block product by G (one per Ritz step
+    // and CHEB - 1 more per filter); per Ritz step the projection and
+    // rotations 6 nv SB^2 and Cholesky QR twice 8 nv SB^2
     const double n = nv, b = SB;
-    const double f = double(it + 1) * (2.0 * n * n * b + 14.0 * n * b * b);
+    const double f = double(n_gemm) * 2.0 * n * n * b + double(it + 1) * 14.0 * n * b * b;
     atomicAdd(Z.flop_b + (s & 63), (unsigned long long)f);
   }
   if (tid == 0) {
@@ -2537,41 +2576,53 @@ static size_t solve_lds(int n) {
   return size_t(4) * n * n * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
 }
 
-void launch_solve(const SweepArgs& A, const DevGate* gates, int n_g, const double* gin, double* wout, int ncap,
-                  int kdcap, hipStream_t st) {
+void launch_solve(const LaunchTuning& T, const SweepArgs& A, const DevGate* gates, int n_g, const double* gin,
+                  double* wout, int ncap, int kdcap, hipStream_t st) {
   if (n_g <= 0) return;
   // three size classes: order <= 8 (eight problems per wavefront, a team of
-  // eight lanes each; most gates), <= 16 (one wavefront, 8 KB of LDS) and the
-  // rest up to kdcap (up to 130 KB of LDS, so few workgroups fit a CU: four
-  // wavefronts share each problem).  A team of 16 lanes for the middle class
-  // measured slower than one wavefront per problem.
-  const int nsmall = kdcap < 16 ? kdcap : 16;
-  hipLaunchKernelGGL(k_solve_team<8>, dim3(n_g, (A.n_sweeps + 7) / 8), dim3(64), 0, st, A, gates, n_g, gin, wout,
-                     ncap, 0);
-  if (nsmall > 8)
-    hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(nsmall), st, A, gates, n_g, gin,
-                       wout, ncap, 8, nsmall);
-  if (kdcap > nsmall)
+  // eight lanes each; most gates), up to T.mid (one wavefront, at most 8 KB of
+  // LDS) and the rest up to kdcap (up to 130 KB of LDS, so few workgroups fit
+  // a CU: four wavefronts share each problem).  A team of 16 lanes for the
+  // middle class measured slower than one wavefront per problem.
+  const int lo = T.team ? 8 : 0;
+  const int mid = std::max(lo, std::min(kdcap, T.mid));
+  if (T.team)
+    hipLaunchKernelGGL(k_solve_team<8>, dim3(n_g, (A.n_sweeps + 7) / 8), dim3(64), 0, st, A, gates, n_g, gin, wout,
+                       ncap, 0);
+  if (mid > lo)
+    hipLaunchKernelGGL(k_solve<SNT>, dim3(n_g, A.n_sweeps), dim3(SNT), solve_lds(mid), st, A, gates, n_g, gin, wout,
+                       ncap, lo, mid);
+  if (kdcap > mid)
     hipLaunchKernelGGL(k_solve<SNT_BIG>, dim3(n_g, A.n_sweeps), dim3(SNT_BIG), solve_lds(kdcap), st, A, gates, n_g,
-                       gin, wout, ncap, nsmall, kdcap);
+                       gin, wout, ncap, mid, kdcap);
 }
 
-void launch_reabsorb(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
-                     const double* win, int ncap, hipStream_t st) {
+void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16,
+                     int n_w32, const double* win, int ncap, hipStream_t st) {
   if (n_g <= 0) return;
   dim3 g(2 * n_g, A.n_sweeps), g16(2 * n_w16, A.n_sweeps), g32(2 * n_w32, A.n_sweeps);
   // three size classes: rows of at most 16 and 32 entries, then the rest up to
   // 64 (the W staging takes 8, 16 and 32 KB of LDS); the wider classes run
-  // over the leading gates that can have such rows
+  // over the leading gates that can have such rows.  Without the narrow
+  // class (T.narrow = 0) the 32-entry kernel takes every row up to 32.
+  const bool merge = !T.narrow && ncap > 16;
   const bool w16 = ncap > 16 && n_w16 > 0, w32 = ncap > 32 && n_w32 > 0;
   // the widest class (rows of 33 to 64 entries) on the matrix cores
   if (prec == 0) {
-    hipLaunchKernelGGL((k_reabsorb<double, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
-    if (w16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    if (merge) {
+      hipLaunchKernelGGL((k_reabsorb<double, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    } else {
+      hipLaunchKernelGGL((k_reabsorb<double, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+      if (w16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    }
     if (w32) hipLaunchKernelGGL((k_reabsorb2<double, 64, 0>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
   } else {
-    hipLaunchKernelGGL((k_reabsorb<float, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
-    if (w16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    if (merge) {
+      hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+    } else {
+      hipLaunchKernelGGL((k_reabsorb<float, 16>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
+      if (w16) hipLaunchKernelGGL((k_reabsorb<float, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
+    }
     if (w32) {
       if (prec == 2)
         hipLaunchKernelGGL((k_reabsorb2<float, 64, 1>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);

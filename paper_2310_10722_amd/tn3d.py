@@ -34,10 +34,10 @@ STATUS = {0: "OK", -1: "INVALID", -2: "INCONSISTENT", -3: "UNSUPPORTED", -4: "OO
 SYMBOLS = [
     "tn3d_params_default", "tn3d_ctx_create", "tn3d_ctx_destroy", "tn3d_last_error",
     "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom", "tn3d_net_surface3d_depolarizing",
-    "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_num_detectors",
+    "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_from_dem", "tn3d_net_num_detectors",
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
-    "tn3d_last_timing", "tn3d_last_stats",
+    "tn3d_last_timing", "tn3d_last_stats", "tn3d_autotune",
     "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached",
 ]
 
@@ -90,6 +90,8 @@ def load_library(path: str | None = None):
     lib.tn3d_net_surface3d_depolarizing.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     lib.tn3d_net_surface3d_loop.argtypes = [c_p, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
     lib.tn3d_net_surface3d_wht.argtypes = [c_p, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(c_p)]
+    lib.tn3d_net_from_dem.argtypes = [c_p, i32, i32, ctypes.c_int64, c_p, c_p, ctypes.POINTER(f64), i32, c_p, c_p,
+                                      ctypes.POINTER(c_p)]
     for f in ("tn3d_net_num_detectors", "tn3d_net_num_mechanisms", "tn3d_net_num_cosets"):
         getattr(lib, f).argtypes = [c_p]
         getattr(lib, f).restype = i32
@@ -108,9 +110,12 @@ def load_library(path: str | None = None):
     lib.tn3d_ctx_graphs_cached.restype = i32
     lib.tn3d_last_timing.argtypes = [c_p, ctypes.POINTER(f64), i32]
     lib.tn3d_last_stats.argtypes = [c_p, ctypes.POINTER(f64), i32]
+    lib.tn3d_autotune.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params),
+                                  ctypes.POINTER(f64), i32]
+    lib.tn3d_autotune.restype = i32
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
-              "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
+              "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_from_dem", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
               "tn3d_decode", "tn3d_ctx_set_timing", "tn3d_last_timing", "tn3d_ctx_set_graphs"):
         getattr(lib, f).restype = i32
     if path is None:
@@ -262,6 +267,28 @@ def tn3d_net_surface3d_loop(ctx: Context, L: int, p_mech) -> Net:
     return Net(ctx, h)
 
 
+def tn3d_net_from_dem(ctx: Context, H, p_mech, obs, det_coord) -> Net:
+    """H: dense 0/1 [n_det, n_mech] (passed as its COO pattern), p_mech
+    [n_mech], obs [n_mech] (one observable row), det_coord [n_det, 3] ints."""
+    H = np.asarray(H, dtype=np.uint8)
+    n_det, n_mech = H.shape
+    d_idx, m_idx = np.nonzero(H & 1)
+    d_idx = np.ascontiguousarray(d_idx, dtype=np.int32)
+    m_idx = np.ascontiguousarray(m_idx, dtype=np.int32)
+    a, ptr = _rates(p_mech, n_mech)
+    ob = np.ascontiguousarray(np.asarray(obs, dtype=np.uint8).reshape(-1))
+    if ob.size != n_mech:
+        raise ValueError(f"expected {n_mech} observable entries, got {ob.size}")
+    co = np.ascontiguousarray(np.asarray(det_coord, dtype=np.int32).reshape(-1))
+    if co.size != 3 * n_det:
+        raise ValueError(f"expected {3 * n_det} coordinates, got {co.size}")
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_from_dem(ctx.h, n_det, n_mech, d_idx.size, d_idx.ctypes.data,
+                                                     m_idx.ctypes.data, ptr, 1, ob.ctypes.data, co.ctypes.data,
+                                                     ctypes.byref(h)))
+    return Net(ctx, h)
+
+
 SECTOR_POINT, SECTOR_LOOP = 0, 1
 
 
@@ -300,6 +327,17 @@ def tn3d_contract_cosets(ctx: Context, nets, syndromes, params: Params):
                                       ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(flags.data_ptr()))
     _check(ctx.lib, ctx.h, st)
     return logp, flags
+
+
+def tn3d_autotune(ctx: Context, nets, syndromes, params: Params):
+    """Chooses and caches the fastest launch shape for these networks and
+    parameters; returns (index, team, mid, narrow, best ms, default ms)."""
+    nets, syn, offs, arr, B = _batch_args(nets, syndromes)
+    out = (ctypes.c_double * 6)()
+    st = ctx.lib.tn3d_autotune(ctx.h, B, arr, ctypes.c_void_p(syn.data_ptr()), ctypes.c_void_p(offs.data_ptr()),
+                               ctypes.byref(params), out, 6)
+    _check(ctx.lib, ctx.h, st)
+    return tuple(out)
 
 
 def tn3d_contract_cosets_noalloc(ctx: Context, nets, syndromes, params: Params, logp=None, flags=None):

@@ -77,6 +77,7 @@ def test_loop_exact_chi(ctx, L):
     net = tn3d.tn3d_net_surface3d_loop(ctx, L, dem.p)
     assert net.n_det == dem.n_det
     prm = tn3d.tn3d_params_default(8, 64, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-12, 1e-9  # the strict rule: no singular value of the exact bonds is dropped
     got, flags = gpu_logp(ctx, net, m, prm)
     ex = np.array([frontier_logprobs(dem.H, dem.p, dem.obs, m[k], order=height_order(L)) for k in range(6)])
     err = np.abs(got - ex)

@@ -540,3 +540,29 @@ def test_chi_schedule(ctx):
     bad.set_chi_schedule([4, 9])
     with pytest.raises(tn3d.Tn3dError):
         gpu_logp(ctx, net, m, bad)
+
+
+def test_autotune_keeps_results(ctx):
+    """The autotuner times the launch-shape candidates on the rotated d = 5
+    workload (256 syndromes, chi = 16, FP64 and FP32) and caches the fastest;
+    contractions afterwards use it and stay within the precision's rounding
+    of the default shape (1e-9 FP64, 1e-4 FP32 on the decoded coset), with the
+    same decisions."""
+    from paper_2310_10722_amd import tn3d
+    dem, m, _, _ = synth.config_workload(2, n=256)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    for prec, tol in ((tn3d.PREC_FP64, 1e-9), (tn3d.PREC_FP32, 1e-4)):
+        say(f"case: autotune rotated d=5 chi=16 precision {prec}, 256 syndromes")
+        prm = tn3d.tn3d_params_default(16, 16, prec)
+        prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+        before, _ = gpu_logp(ctx, net, m, prm)
+        syn = torch.from_numpy(np.ascontiguousarray(m)).to("cuda:0")
+        res = tn3d.tn3d_autotune(ctx, net, syn, prm)
+        say(f"  chosen candidate {int(res[0])} (team {int(res[1])}, mid {int(res[2])}, narrow {int(res[3])}): "
+            f"{res[4]:.3f} ms against {res[5]:.3f} ms for the default shape")
+        after, _ = gpu_logp(ctx, net, m, prm)
+        b = np.argmax(before[:, :2], axis=1)
+        rows = np.arange(len(b))
+        assert np.array_equal(np.argmax(after[:, :2], axis=1), b)
+        assert np.max(np.abs(after[rows, b] - before[rows, b])) <= tol
+        assert res[4] <= res[5]

@@ -69,13 +69,25 @@ def height_order(L):
 
 
 def check_fp64(got, ref):
-    err = np.abs(got - ref)
-    maj = np.argmax(ref, axis=1)
+    """Where a truncated |Z_1| exceeds Z_0 the minority coset's value is not
+    positive (NaN with NUMERIC, reading C14) on both sides alike; the other
+    values are compared."""
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref).any(axis=1)
+    say("  items with a non-positive coset value (both sides):", int((~ok).sum()))
+    g, r = got[ok], ref[ok]
+    err = np.abs(g - r)
+    maj = np.argmax(r, axis=1)
     rows = np.arange(len(maj))
-    gap = np.abs(ref[:, 0] - ref[:, 1])
+    gap = np.abs(r[:, 0] - r[:, 1])
     say("  decoded coset", err[rows, maj].max(), " other", err[rows, 1 - maj].max(), " gap max", gap.max())
     assert err[rows, maj].max() <= 1e-9
     assert np.all(err[rows, 1 - maj] <= 1e-9 * (1.0 + np.exp(gap)))
+    bad = np.nonzero(~ok)[0]
+    if bad.size:
+        # the finite coset of such an item still agrees
+        fin = np.isfinite(ref[bad])
+        assert np.max(np.abs(got[bad][fin] - ref[bad][fin])) <= 1e-9
 
 
 @pytest.mark.parametrize("sector", ["point", "loop"])
@@ -87,6 +99,7 @@ def test_wht_exact_chi(ctx, sector):
     m, _ = synth.sample_syndromes(dem, 6, 19)
     net = tn3d.tn3d_net_surface3d_wht(ctx, 3, tn3d.SECTOR_POINT if sector == "point" else tn3d.SECTOR_LOOP, dem.p)
     prm = tn3d.tn3d_params_default(8, 64, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-12, 1e-9  # the strict rule: no singular value of the exact bonds is dropped
     got, flags = gpu_logp(ctx, net, m, prm)
     order = None if sector == "point" else height_order(3)
     ex = np.array([frontier_logprobs(dem.H, dem.p, dem.obs, m[k], order=order) for k in range(6)])
