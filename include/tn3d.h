@@ -114,6 +114,9 @@ void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t p
  * hipStream_t; NULL = default stream).  The context owns a device workspace
  * that grows on demand.  Errors: TN3D_E_INVALID, TN3D_E_DEVICE. */
 tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out);
+/* Frees the context.  Networks built on it should be destroyed first; any
+ * still alive lose their device arrays here and are detached: they can then
+ * only be passed to tn3d_net_destroy (which frees the handle). */
 void tn3d_ctx_destroy(tn3d_ctx ctx);
 /* Text of the last error on this context; owned by the context, valid until
  * its next call. */
@@ -233,6 +236,8 @@ int32_t tn3d_net_num_mechanisms(tn3d_net net);
 int32_t tn3d_net_num_cosets(tn3d_net net);
 /* Grid of the swept 2D network and number of absorbed layers. */
 void tn3d_net_shape(tn3d_net net, int32_t* lx, int32_t* ly, int32_t* n_layers);
+/* Frees the network (its device arrays, and the context's captured launch
+ * sequences that use it); valid after its context was destroyed as well. */
 void tn3d_net_destroy(tn3d_net net);
 
 /* log p_{m,L} for a batch of syndromes (paper Sec. 2.4 definition; Sec. 4

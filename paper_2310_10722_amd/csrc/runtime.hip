@@ -91,6 +91,7 @@ struct tn3d_ctx_s {
   char* scratch = nullptr;         // this device's copy of the static scratch array
   bool graphs = true;              // replay captured launch sequences
   std::map<TuneKey, LaunchTuning> tune;  // launch shapes chosen by tn3d_autotune
+  std::vector<tn3d_net> nets;             // live networks built on this context
   hipStream_t cap_stream = nullptr;  // private stream the sequences are captured on
   uint64_t next_serial = 1;
   std::map<GraphKey, GraphEntry> gcache;
@@ -205,6 +206,7 @@ tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* 
     delete n;
     return s;
   }
+  c->nets.push_back(n);
   *out = n;
   return TN3D_OK;
 }
@@ -822,6 +824,15 @@ tn3d_status tn3d_ctx_create(int32_t device, void* stream, tn3d_ctx* out) {
 void tn3d_ctx_destroy(tn3d_ctx c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  // networks the caller did not destroy first: free their device arrays now
+  // and detach them, so that a later tn3d_net_destroy only frees the handle
+  if (!c->nets.empty()) (void)hipStreamSynchronize(c->stream);
+  for (tn3d_net n : c->nets) {
+    if (n->dev) (void)hipFree(n->dev);
+    n->dev = nullptr;
+    n->ctx = nullptr;
+  }
+  c->nets.clear();
   if (c->ws) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->ws);
@@ -903,11 +914,13 @@ void tn3d_net_shape(tn3d_net n, int32_t* lx, int32_t* ly, int32_t* nl) {
 
 void tn3d_net_destroy(tn3d_net n) {
   if (!n) return;
-  if (n->dev) {
-    (void)hipSetDevice(n->ctx->device);
-    (void)hipStreamSynchronize(n->ctx->stream);
-    drop_graphs(n->ctx, n->serial);
-    (void)hipFree(n->dev);
+  if (n->ctx) {
+    tn3d_ctx c = n->ctx;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c, n->serial);
+    if (n->dev) (void)hipFree(n->dev);
+    c->nets.erase(std::remove(c->nets.begin(), c->nets.end(), n), c->nets.end());
   }
   delete n;
 }

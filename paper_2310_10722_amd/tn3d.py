@@ -9,6 +9,7 @@ is missing this module raises instead of computing anything itself.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -166,9 +167,13 @@ class Context:
         _check(self.lib, None, self.lib.tn3d_ctx_create(device, ctypes.c_void_p(stream.cuda_stream),
                                                         ctypes.byref(h)))
         self.h = h
+        self._nets = weakref.WeakSet()
 
     def close(self):
         if self.h:
+            # the networks of this context go first (the library's contract)
+            for net in list(self._nets):
+                net.close()
             self.lib.tn3d_ctx_destroy(self.h)
             self.h = None
 
@@ -205,6 +210,7 @@ class Net:
     def __init__(self, ctx: Context, h):
         self.ctx = ctx
         self.h = h
+        ctx._nets.add(self)
         lib = ctx.lib
         self.n_det = lib.tn3d_net_num_detectors(h)
         self.n_mech = lib.tn3d_net_num_mechanisms(h)
@@ -215,6 +221,8 @@ class Net:
 
     def close(self):
         if self.h:
+            # after its context was closed the handle is detached and only
+            # freed (the library released its device arrays then)
             self.ctx.lib.tn3d_net_destroy(self.h)
             self.h = None
 
