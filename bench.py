@@ -115,6 +115,9 @@ def _oracle_one(args):
     elif fam == "loop":
         from oracle.network import loop3d_network
         net = loop3d_network(prm_fam["L"], p, m, c)
+    elif fam == "depol":
+        from oracle.network import depol3d_network
+        net = depol3d_network(prm_fam["L"], p, m, c)
     else:
         net = point3d_network(prm_fam["L"], p, m, c)
     return sweep_logprob(net, chi, chi_m, eps, tau)[0]
@@ -151,6 +154,15 @@ def accuracy(np, got, ref, coset=None):
     return out
 
 
+def autotune_entry(tn3d, ctx, nets, syn, prm, what):
+    """Runs the library's autotuner on (nets, syn) for these parameters (the
+    choice is cached in the context and used by the timed steps after it)."""
+    r = tn3d.tn3d_autotune(ctx, nets, syn, prm)
+    return {"tuned_on": what, "choice": {"index": int(r[0]), "team8": int(r[1]), "mid": int(r[2]),
+                                        "narrow_reabsorb": int(r[3])},
+            "tuned_ms": r[4], "default_ms": r[5], "speedup": r[5] / r[4] if r[4] > 0 else None}
+
+
 def roof_entry(name, bound, work, ms, launches, peak, unit, traffic=None):
     if not ms or ms <= 0 or not launches:
         return None
@@ -171,6 +183,9 @@ def bench_point_L8(a, tn3d, np, torch):
     dem, m, _, _ = synth.config_workload(6 if loop else 3)
     B = m.shape[0]
     L, chi = 8, 32
+    a.precision = a.precision or "bf16"
+    if a.precision == "fp64":
+        raise SystemExit("the L = 8 workloads run in bf16 or fp32 (the FP64 Gram route is reported beside them)")
     prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32}[a.precision]
     ctx = tn3d.Context(0)
     net = (tn3d.tn3d_net_surface3d_loop if loop else tn3d.tn3d_net_surface3d_point)(ctx, L, dem.p)
@@ -179,6 +194,11 @@ def bench_point_L8(a, tn3d, np, torch):
     # the library default near-tie band: every item whose BF16 log-ratio is
     # below it is contracted again in FP64 (Gram route) inside the same call
     syn = torch.from_numpy(m).to("cuda:0")
+    tune = None
+    if not a.no_autotune:
+        say("autotune on 32 syndromes")
+        tune = autotune_entry(tn3d, ctx, net, syn[:32], prm, "syndromes 0..31 (the choice holds for the network "
+                                                             "and parameters)")
     ctx.set_timing(1)  # device windows and work counters inside the captured sequence
     for i in range(a.warmup):
         tn3d.tn3d_decode(ctx, net, syn, prm)
@@ -220,7 +240,7 @@ def bench_point_L8(a, tn3d, np, torch):
                                   "boundary_decomposition_small": eig_ms / a.steps,
                                   "boundary_decomposition_subspace": sub_ms / a.steps,
                                   "boundary_contraction": za_ms / a.steps},
-           "roofline": rf_eig, "roofline_streaming": stream,
+           "roofline": rf_eig, "roofline_streaming": stream, "autotune": tune,
            "flags": {"numeric": int(np.sum(flags & 1 != 0)), "trunc_cluster": int(np.sum(flags & 2 != 0)),
                      "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0))}}
     # the BF16 pass alone (no re-sweep), one instrumented step
@@ -310,6 +330,7 @@ def bench_rotated_d5(a, tn3d, np, torch):
     prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
     syn = torch.from_numpy(m).to("cuda:0")
+    tune = None if a.no_autotune else autotune_entry(tn3d, ctx, net, syn, prm, "the whole batch")
     for _ in range(a.warmup):
         tn3d.tn3d_decode(ctx, net, syn, prm)
     torch.cuda.synchronize()
@@ -324,7 +345,7 @@ def bench_rotated_d5(a, tn3d, np, torch):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Bernoulli error samples of the code's DEM)",
            "config": {"workload": "rotated d=5 surface code, phenomenological p=q=0.03, 5 noisy + 1 perfect rounds, "
                                   "5x6 grid x 4 layers, chi=16, chi_mps=16, 1024 syndromes x 2 cosets",
-                      "global_batch": B}, "roofline": None}
+                      "global_batch": B}, "roofline": None, "autotune": tune}
     if not a.no_cpu:
         n = min(a.cpu_sample, B)
         ref, cdt = cpu_oracle("rotated", dict(dem.params), dem.p, m[:n], prm, CPU_WORKERS)
@@ -337,13 +358,18 @@ def bench_rotated_d5(a, tn3d, np, torch):
 def bench_depolarizing(a, tn3d, np, torch):
     """3D planar code under depolarizing noise p = 0.15, 512 syndromes with
     L = 4, 5, 6 (171 / 171 / 170, shuffled by the seed) decoded in one ragged
-    call, four cosets each, FP64 site tensors, reduced rank rule.  chi =
-    chi_mps = --chi (at most 16: the dimension-4 sites hold 4 chi <= 64)."""
+    call, four cosets each, reduced rank rule, chi = chi_mps = --chi (24 by
+    default: gate sides of 4 x 24 = 96 columns), FP32 site tensors by default
+    (--precision; FP64 takes the Gram route there)."""
     import synth
     seed = synth.CONFIG_SEED_BASE + 4
     ctx = tn3d.Context(0)
-    prm = tn3d.tn3d_params_default(a.chi, a.chi, tn3d.PREC_FP64)
+    pr_name = a.precision or "fp32"
+    prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32, "fp64": tn3d.PREC_FP64}[pr_name]
+    prm = tn3d.tn3d_params_default(a.chi, a.chi, prec)
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    if prec == tn3d.PREC_FP64 and 4 * a.chi > 64:
+        prm.flags = tn3d.OPT_GRAM_FACTOR
     parts = []
     for L, n in ((4, 171), (5, 171), (6, 170)):
         dem = synth.surface3d_depolarizing(L, 0.15)
@@ -362,6 +388,7 @@ def bench_depolarizing(a, tn3d, np, torch):
     syn = torch.from_numpy(np.stack([rows[i] for i in perm])).to("cuda:0")
     nets = [nets[i] for i in perm]
     B = len(nets)
+    tune = None if a.no_autotune else autotune_entry(tn3d, ctx, nets, syn, prm, "the whole batch")
     for _ in range(a.warmup):
         tn3d.tn3d_decode(ctx, nets, syn, prm)
     torch.cuda.synchronize()
@@ -371,30 +398,56 @@ def bench_depolarizing(a, tn3d, np, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     flags = res[3].cpu().numpy()
-    print(json.dumps({"metric": METRIC, "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1,
-                      "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-                      "data": "synthetic (seeded depolarizing errors)",
-                      "config": {"workload": f"3D planar code, depolarizing p=0.15, ragged L in (4, 5, 6) x "
-                                             f"(171, 171, 170), chi={a.chi}, chi_mps={a.chi}, 512 syndromes x 4 "
-                                             f"cosets, reduced rank rule", "global_batch": B},
-                      "roofline": None,
-                      "flags": {"numeric": int(np.sum(flags & 1 != 0)),
-                                "inconsistent": int(np.sum(flags & 32 != 0))}}))
+    logp = res[2].cpu().numpy()
+    out = {"metric": METRIC, "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bf16": "bf16", "fp32": "f32", "fp64": "f64"}[pr_name],
+           "data": "synthetic (seeded depolarizing errors)",
+           "config": {"workload": f"3D planar code, depolarizing p=0.15, ragged L in (4, 5, 6) x "
+                                  f"(171, 171, 170), chi={a.chi}, chi_mps={a.chi}, 512 syndromes x 4 "
+                                  f"cosets, reduced rank rule", "global_batch": B, "precision": pr_name},
+           "roofline": None, "autotune": tune,
+           "flags": {"numeric": int(np.sum(flags & 1 != 0)), "inconsistent": int(np.sum(flags & 32 != 0))}}
+    if not a.no_cpu:
+        # the FP64 oracle on the first item of each L in the batch, all four
+        # cosets, one sweep per single-threaded worker
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+        inv = np.argsort(perm)
+        jobs, rows_at = [], []
+        for L, dem, m, _ in parts:
+            rows_at.append(int(inv[[i for i, (LL, k) in enumerate(src) if LL == L and k == 0][0]]))
+            jobs += [("depol", {"L": L}, dem.params["p_qubit"], m[0], c, a.chi, a.chi, prm.eps_rel, prm.tau_gap)
+                     for c in range(4)]
+        t_or = time.perf_counter()
+        with mp.get_context("spawn").Pool(min(CPU_WORKERS, len(jobs))) as pool:
+            res_or = np.array(pool.map(_oracle_one, jobs, chunksize=1)).reshape(len(parts), 4)
+        errs = []
+        for q, j in enumerate(rows_at):
+            b = int(np.argmax(res_or[q]))
+            errs.append(abs(logp[j, b] - res_or[q, b]))
+        out["accuracy"] = {"n_items": len(parts), "decoded_coset_max_abs_dlogp": float(max(errs)),
+                           "vs": "CPU oracle (fixed-chi FP64 sweep), item 0 of each L, four cosets",
+                           "oracle_seconds": time.perf_counter() - t_or}
+    print(json.dumps(out))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 3 for the L = 8 workloads, about a minute; 5 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1 for L = 8; 2 otherwise)")
     ap.add_argument("--config", type=int, default=3,
                     help="3: 3D planar L=8 point sector, chi 32 (the headline); 6: the same in the loop sector; "
                          "2: rotated d=5; 4: depolarizing, ragged L in {4, 5, 6}")
-    ap.add_argument("--precision", default="bf16", choices=("bf16", "fp32"), help="--config 3 and 6 only")
-    ap.add_argument("--chi", type=int, default=8, help="chi = chi_mps for --config 4")
+    ap.add_argument("--precision", default=None, choices=("bf16", "fp32", "fp64"),
+                    help="--config 3 and 6 (default bf16), --config 4 (default fp32)")
+    ap.add_argument("--chi", type=int, default=24, help="chi = chi_mps for --config 4")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed steps (no other-precision, re-sweep or one-syndrome runs): the short run "
                          "a profiler traces")
@@ -402,6 +455,11 @@ def main():
                     help="only copy a MIB-sized device buffer once (the calibration run for the HBM byte "
                          "counters of a profiler) and exit")
     a = ap.parse_args()
+    big = a.config in (3, 6)
+    if a.steps is None:
+        a.steps = 3 if big else 5
+    if a.warmup is None:
+        a.warmup = 1 if big else 2
     if a.copy_probe > 0:
         import torch
         n = a.copy_probe * (1 << 20) // 4

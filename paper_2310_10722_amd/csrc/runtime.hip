@@ -214,6 +214,7 @@ tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* 
 // Sizes of every per-sweep array for one network at given chi / chi_m.
 struct Layout {
   int legcap, ncap, kdcap, mcap_chi;
+  int64_t sbig = 0;  // doubles per (sweep, gate) of the order-above-64 truncation scratch
   std::vector<int64_t> site_off, fin_off;
   int64_t sweep_stride = 0, fin_stride = 0;
   int64_t mcap = 0, kcap = 0, bigcap = 0, jcap = 0;
@@ -256,8 +257,10 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;
-  b += P.n_bonds * (4 + 8 + 8 * size_t(chi)) + P.Lx * P.Ly * 8 + 4;
+  b += P.n_bonds * (4 + 8 + 8 * size_t(L.legcap)) + P.Lx * P.Ly * 8 + 4;
   b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8 + size_t(max_g) * 4;
+  L.sbig = L.kdcap > 64 ? int64_t(L.kdcap) * L.kdcap : 0;
+  b += size_t(max_g) * L.sbig * 8;
   b += L.fin_stride * 8;
   b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + L.jcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
   L.per_sweep_bytes = b + 64 * 20;
@@ -314,8 +317,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (it != c->tune.end()) TU = it->second;
   }
   // the kernels' fixed-size LDS arrays bound these (sweep.hip)
-  if (L.ncap > 64) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 64 on a gated site");
-  if (L.kdcap > 64) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 64");
+  if (L.ncap > 96) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 96 on a gated site");
+  if (L.kdcap > 72) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 72");
+  if ((L.ncap > 64 || L.kdcap > 64) && prec == TN3D_PREC_FP64 && !(pr.flags & TN3D_OPT_GRAM_FACTOR))
+    return fail(c, TN3D_E_UNSUPPORTED,
+                "physical dim x chi or gate rank x chi above 64 needs the Gram route in FP64 (TN3D_OPT_GRAM_FACTOR)");
   if (int64_t(pr.chi_mps) * L.legcap > 1024) return fail(c, TN3D_E_UNSUPPORTED, "chi_mps x chi above 1024");
   if (P.Lx * P.Ly > 65535) return fail(c, TN3D_E_UNSUPPORTED, "grid too large");
   size_t budget;
@@ -358,6 +364,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_gram = cv.take<double>(nsw_max * max_g * 2 * L.ncap * L.ncap);
   size_t o_w = cv.take<double>(nsw_max * max_g * 2 * (2 + L.ncap * L.ncap));
   size_t o_gn = cv.take<int32_t>(nsw_max * max_g);
+  size_t o_sbig = cv.take<double>(std::max<int64_t>(1, nsw_max * max_g * L.sbig));
   size_t o_fin = cv.take<double>(nsw_max * L.fin_stride);
   size_t o_mps0 = cv.take<double>(nsw_max * P.Lx * L.mcap);
   size_t o_mps1 = cv.take<double>(nsw_max * P.Lx * L.mcap);
@@ -435,6 +442,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.chi = pr.chi;
     A.chi_cut = pr.chi;
     A.lam_ld = L.legcap;
+    A.solve_big = reinterpret_cast<double*>(ws + o_sbig);
+    A.sbig_ld = L.sbig;
     A.Lx = P.Lx;
     A.Ly = P.Ly;
     A.sweep_stride = L.sweep_stride;
@@ -498,11 +507,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
           return c;
         };
         A.win = timing ? win + size_t(2 * cls) * 128 : nullptr;
-        launch_gram(prec, A, gp, ng, n_wider(16), n_wider(32), gram, L.ncap, s);
+        launch_gram(prec, A, gp, ng, n_wider(16), n_wider(32), n_wider(64), gram, L.ncap, s);
         A.win = nullptr;
         launch_solve(TU, A, gp, ng, gram, wbuf, L.ncap, L.kdcap, s);
         A.win = timing ? win + size_t(2 * cls + 1) * 128 : nullptr;
-        launch_reabsorb(TU, prec, A, gp, ng, n_wider(16), n_wider(32), wbuf, L.ncap, s);
+        launch_reabsorb(TU, prec, A, gp, ng, n_wider(16), n_wider(32), n_wider(64), wbuf, L.ncap, s);
         A.win = nullptr;
         hot_l += 2;
       }

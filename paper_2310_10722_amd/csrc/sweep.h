@@ -32,6 +32,8 @@ struct SweepArgs {
   int32_t inc0, n_inc;            // consistency bits of an item (Program::inc0, n_inc)
   int32_t wht;                    // 1: the two sweeps of an item are the signed networks Z_0, Z_1
   int32_t chi_cut;                // rank-rule cap of the truncations of this layer (<= chi)
+  double* solve_big;              // truncations of order above 64: one n x n matrix per (sweep, gate)
+  int64_t sbig_ld;                // its doubles per (sweep, gate)
   double jtol, jfloor;            // one-sided Jacobi: orthogonality tolerance, noise floor
   unsigned long long* bytes_ctr;  // 64 counters (indexed by workgroup) or null
   int32_t* sweeps_max;            // [2] most Jacobi sweeps (sweep truncations, boundary MPS)
@@ -88,8 +90,8 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 // n_wide (and n_w16, n_w32 below): the leading gates of the class whose Grams
 // (rows) can be wider than 32 (16, 32) entries; the others are never wider
 // (A.qr: the triangular factors of k_qr instead of the Grams)
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
-                 int ncap, hipStream_t st);
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, int n_w64,
+                 double* gout, int ncap, hipStream_t st);
 // Launch-shape choices of the layer absorption (the autotuner's search
 // space): team = 1 runs truncations of order <= 8 eight per wavefront;
 // truncations of order up to mid (8 or 16) run on one wavefront, larger ones
@@ -102,7 +104,8 @@ struct LaunchTuning {
 void launch_solve(const LaunchTuning& T, const SweepArgs& A, const DevGate* gates, int n_g, const double* gin,
                   double* wout,
                   int ncap, int kdcap, hipStream_t st);
-void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_w32,
+void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16,
+                     int n_w32, int n_w64,
                      const double* win, int ncap, hipStream_t st);
 void launch_rescale(int prec, const SweepArgs& A, const int32_t* d_after, const int32_t* par_after,
                     hipStream_t st);

@@ -746,9 +746,12 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   const int n0 = A.gate_n[int64_t(sweep) * n_g + gi];
   if (n0 <= nlo || n0 > nhi) return;
   const double logb_in = A.logb[bidx];  // loaded early, used at the end
+  // four n x n matrices; above order 64 (the Gram route only) the second one
+  // lives in the per-gate global scratch, so the rest fits the LDS
   double* ZA = sm;
-  double* ZB = ZA + n * n;
-  double* CM = ZB + n * n;
+  const bool zb_global = n > 64;
+  double* ZB = zb_global ? A.solve_big + int64_t(sweep * n_g + gi) * A.sbig_ld : ZA + n * n;
+  double* CM = zb_global ? ZA + n * n : ZB + n * n;
   double* VM = CM + n * n;
   double* S = VM + n * n;
   double* Ss = S + n;
@@ -1118,14 +1121,18 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
   const double* W = win + (int64_t(sweep * n_g + gi) * 2 + side) * (2 + ncap * ncap);
   const int Dold = int(W[0]), Dn = int(W[1]);
   const int nin = d * Dold, nout = d * Dn, nst = (nout + 3) & ~3;
-  if (nin <= nlo || nin > NMAX) return;
+  // classes by row width: nin in (nlo, NMAX] with at most 64 outputs, and
+  // the widest (NMAX > 64) every row with more than 64 inputs or outputs
+  constexpr int NO = NMAX > 64 ? NMAX : 64;
+  if (NMAX > 64 ? (nin <= 64 && nout <= 64) || nin > NMAX || nout > NMAX : nin <= nlo || nin > NMAX || nout > 64)
+    return;
   const unsigned long long w0 = win_open(A.win);
   int D[4];
   site_dims(A, sweep, site, D);
   D[leg] = Dold;
   const Split v = make_split(D, leg, d);
-  __shared__ double4 Ws4[NMAX * 64 / 4];
-  __shared__ int colin[NMAX], colout[64];
+  __shared__ double4 Ws4[NMAX * NO / 4];
+  __shared__ int colin[NMAX], colout[NO];
   double* Ws = reinterpret_cast<double*>(Ws4);
   for (int e = tid; e < nin * nst; e += 64) {
     const int k = e / nst, q = e - k * nst;
@@ -1199,7 +1206,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const double* W = win + (int64_t(sweep * n_g + gi) * 2 + side) * (2 + ncap * ncap);
   const int Dold = int(W[0]), Dn = int(W[1]);
   const int nin = d * Dold, nout = d * Dn;
-  if (nin <= nlo || nin > NMAX) return;
+  if (nin <= nlo || nin > NMAX || nout > 64) return;  // wider outputs: k_reabsorb<T, 96>
   const unsigned long long w0 = win_open(A.win);
   int D[4];
   site_dims(A, sweep, site, D);
@@ -2105,13 +2112,17 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
     }
     if (it + 1 == maxit) break;
     const double c_lo = th[SB - 1];
-    if (c_lo > 1e-12 * t1 && t1 > 1.05 * c_lo) {
+    if (c_lo > 1e-12 * t1 && t1 > 1.05 * c_lo && th[K - 1] >= 1e-2 * t1) {
       // next block: a Chebyshev filter of degree CHEB applied to the Ritz
       // vectors U (G U = P is at hand): T_CHEB((G - cen) / hw) damps the
       // interval [0, c_lo] below the block's smallest Ritz value and grows
       // the wanted end; the three-term recurrence is scaled so that the
       // component at the largest Ritz value t1 stays near one (no overflow).
       // One orthonormalisation and Rayleigh-Ritz step per CHEB products.
+      // Only where the wanted Ritz values span at most two decades: the
+      // filter grows the largest wanted component over the smallest by up to
+      // (t1 / theta_K)^CHEB, and a wider span would leave the smallest ones
+      // below the rounding of the block before it is orthonormalised again.
       const double hw = 0.5 * c_lo, cen = 0.5 * c_lo;
       const double sig1 = hw / (t1 - cen);
       double sig = sig1;
@@ -2538,8 +2549,8 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
 }
 
 template <typename T, int BF>
-static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, double* gout, int ncap,
-                          hipStream_t st) {
+static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, int n_w64, double* gout,
+                          int ncap, hipStream_t st) {
   // ncap <= 64 is checked by the host before any launch; Grams of up to 32
   // columns (three block pairs) and of 33 to 64 (ten) in separate launches,
   // the second over the leading n_wide gates (the only ones that can be wide)
@@ -2547,10 +2558,14 @@ static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int
   if (ncap > 32 && n_wide > 0)
     hipLaunchKernelGGL((k_gram2<T, 4, BF>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
                        ncap, 32);
+  // 65 to 96 columns (physical dim 4 at chi up to 24): 21 block pairs
+  if (ncap > 64 && n_w64 > 0)
+    hipLaunchKernelGGL((k_gram2<T, 6, BF>), dim3(2 * n_w64, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
+                       ncap, 64);
 }
 
-void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, double* gout,
-                 int ncap, hipStream_t st) {
+void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16, int n_wide, int n_w64,
+                 double* gout, int ncap, hipStream_t st) {
   if (n_g <= 0) return;
   if (A.qr) {
     // factors of up to 16 columns (four teams per wavefront), 32 (two) and 64
@@ -2565,15 +2580,22 @@ void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, in
     return;
   }
   if (prec == 0)
-    gram_dispatch<double, 0>(A, gates, n_g, n_wide, gout, ncap, st);
+    gram_dispatch<double, 0>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
   else if (prec == 2)
-    gram_dispatch<float, 1>(A, gates, n_g, n_wide, gout, ncap, st);
+    gram_dispatch<float, 1>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
   else
-    gram_dispatch<float, 0>(A, gates, n_g, n_wide, gout, ncap, st);
+    gram_dispatch<float, 0>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
 }
 
-static size_t solve_lds(int n) {
-  return size_t(4) * n * n * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
+// Dynamic LDS of a k_solve launch whose orders reach kd: four n x n matrices
+// up to order 64, three above (see k_solve), the most any order <= kd needs.
+static size_t solve_lds(int kd) {
+  auto need = [](int n, int mats) {
+    return size_t(mats) * n * n * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
+  };
+  size_t b = need(std::min(kd, 64), 4);
+  if (kd > 64) b = std::max(b, need(kd, 3));
+  return b;
 }
 
 void launch_solve(const LaunchTuning& T, const SweepArgs& A, const DevGate* gates, int n_g, const double* gin,
@@ -2598,9 +2620,12 @@ void launch_solve(const LaunchTuning& T, const SweepArgs& A, const DevGate* gate
 }
 
 void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const DevGate* gates, int n_g, int n_w16,
-                     int n_w32, const double* win, int ncap, hipStream_t st) {
+                     int n_w32, int n_w64, const double* win, int ncap, hipStream_t st) {
   if (n_g <= 0) return;
-  dim3 g(2 * n_g, A.n_sweeps), g16(2 * n_w16, A.n_sweeps), g32(2 * n_w32, A.n_sweeps);
+  dim3 g(2 * n_g, A.n_sweeps), g16(2 * n_w16, A.n_sweeps), g32(2 * n_w32, A.n_sweeps), g64(2 * n_w64, A.n_sweeps);
+  // rows with more than 64 inputs or outputs (physical dim 4 at chi up to 24):
+  // W staged in LDS, over the leading gates that can be that wide
+  const bool w64 = ncap > 64 && n_w64 > 0;
   // three size classes: rows of at most 16 and 32 entries, then the rest up to
   // 64 (the W staging takes 8, 16 and 32 KB of LDS); the wider classes run
   // over the leading gates that can have such rows.  Without the narrow
@@ -2616,6 +2641,7 @@ void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const 
       if (w16) hipLaunchKernelGGL((k_reabsorb<double, 32>), g16, dim3(64), 0, st, A, gates, n_g, win, ncap, 16);
     }
     if (w32) hipLaunchKernelGGL((k_reabsorb2<double, 64, 0>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
+    if (w64) hipLaunchKernelGGL((k_reabsorb<double, 96>), g64, dim3(64), 0, st, A, gates, n_g, win, ncap, 64);
   } else {
     if (merge) {
       hipLaunchKernelGGL((k_reabsorb<float, 32>), g, dim3(64), 0, st, A, gates, n_g, win, ncap, 0);
@@ -2629,6 +2655,7 @@ void launch_reabsorb(const LaunchTuning& T, int prec, const SweepArgs& A, const 
       else
         hipLaunchKernelGGL((k_reabsorb2<float, 64, 0>), g32, dim3(64), 0, st, A, gates, n_g, win, ncap, 32);
     }
+    if (w64) hipLaunchKernelGGL((k_reabsorb<float, 96>), g64, dim3(64), 0, st, A, gates, n_g, win, ncap, 64);
   }
 }
 

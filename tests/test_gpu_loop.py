@@ -154,3 +154,41 @@ def test_loop_rates_rejected(ctx):
         tn3d.tn3d_net_surface3d_loop(ctx, 3, np.full(synth.surface3d_loop(3, 0.1).n_mech, 1.5))
     with pytest.raises(RuntimeError):
         tn3d.tn3d_net_surface3d_loop(ctx, 1, np.full(1, 0.1))
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp64_gram"])
+def test_loop_L8_chi32_full_batch_golden(ctx, mode):
+    """The loop sector at L = 8, p = 0.2 (below its threshold, so the cosets
+    differ), chi = chi_m = 32: the whole 256-syndrome batch in one call, items
+    0, 85, 170, 255 against stored oracle values
+    (tests/golden/make_loop_L8_chi32.py, reduced rule).  BF16: the decoded
+    coset within 1e-3 and the same decision, the other within 1e-3 + 64
+    eps_32 e^gap; FP64 Gram route: 1e-6 on the decoded coset."""
+    import json
+    import os
+    from paper_2310_10722_amd import tn3d
+    say(f"case: loop sector L=8 p=0.2 chi=chi_m=32 {mode}, 256 syndromes, 4 stored")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "loop_L8_chi32.json")))
+    dem, m, _, _ = synth.config_workload(6)
+    assert m.shape[0] == gold["n"]
+    assert np.array_equal(m[gold["items"]], np.array(gold["syndromes"], dtype=np.uint8))
+    net = tn3d.tn3d_net_surface3d_loop(ctx, 8, dem.p)
+    prm = tn3d.tn3d_params_default(32, 32, tn3d.PREC_BF16 if mode == "bf16" else tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = gold["rule"]
+    if mode == "fp64_gram":
+        prm.flags = tn3d.OPT_GRAM_FACTOR
+    got, flags = gpu_logp(ctx, net, m, prm)
+    ref = np.array(gold["logp"])
+    g = got[gold["items"]]
+    maj = np.argmax(ref, axis=1)
+    rows = np.arange(len(maj))
+    err = np.abs(g - ref)
+    gap = np.abs(ref[:, 0] - ref[:, 1])
+    say("  decoded coset", err[rows, maj].max(), " other", err[rows, 1 - maj].max(), " gaps", np.round(gap, 3))
+    assert np.all(flags & 8 == 0)
+    if mode == "bf16":
+        assert err[rows, maj].max() <= 1e-3
+        assert np.array_equal(np.argmax(g, axis=1), maj)
+        assert np.all(err[rows, 1 - maj] <= 1e-3 + 64.0 * EPS32 * np.exp(gap))
+    else:
+        assert err[rows, maj].max() <= 1e-6
