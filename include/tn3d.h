@@ -62,10 +62,13 @@ typedef enum {
  *   FP64: FP64 site tensors, Grams on FP64 matrix cores, truncations factored
  *         by Householder QR and one-sided Jacobi (see TN3D_OPT_GRAM_FACTOR).
  *   FP32: FP32 site tensors, Grams on FP64 matrix cores.
- *   BF16: FP32 site tensors, Grams on BF16 matrix cores with FP32
- *         accumulation (per chunk of 32 rows; FP64 across chunks), every
- *         operand split into three BF16 terms so the products keep FP32
- *         accuracy; everything else as FP32. */
+ *   BF16: FP32 site tensors; the reabsorption products and the boundary-MPS
+ *         contraction Theta on BF16 matrix cores with FP32 accumulation (per
+ *         chunk of 32 rows; FP64 across chunks), every operand split into
+ *         three BF16 terms so the products keep FP32 accuracy; the Grams on
+ *         FP64 matrix cores from the FP32 values (a Gram accumulated in FP32
+ *         loses the singular values below about 3e-4 of the largest, which
+ *         the reduced rank rule keeps); everything else as FP32. */
 #define TN3D_PREC_FP64 0
 #define TN3D_PREC_FP32 1
 #define TN3D_PREC_BF16 2

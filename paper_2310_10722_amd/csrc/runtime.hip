@@ -1036,6 +1036,20 @@ tn3d_status tn3d_autotune(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const
   (void)hipFree(d_lp);
   (void)hipFree(d_fl);
   for (tn3d_net n : uniq) c->tune[TuneKey{n->serial, prec, pr->chi, pr->chi_mps}] = cand[best];
+  // the trial candidates' captured sequences are not needed any more
+  (void)hipStreamSynchronize(c->stream);
+  const int keep = pack_tuning(cand[best]);
+  for (auto it = c->gcache.begin(); it != c->gcache.end();) {
+    const bool ours = std::find_if(uniq.begin(), uniq.end(), [&](tn3d_net n) { return n->serial == it->first.net; }) !=
+                      uniq.end();
+    if (ours && it->first.prec == prec && it->first.chi == pr->chi && it->first.chi_mps == pr->chi_mps &&
+        it->first.tune != keep) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = c->gcache.erase(it);
+    } else {
+      ++it;
+    }
+  }
   if (st != TN3D_OK) return st;
   const double vals[6] = {double(best), double(cand[best].team), double(cand[best].mid), double(cand[best].narrow),
                           best_ms, def_ms};
