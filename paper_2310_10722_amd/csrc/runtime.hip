@@ -1146,10 +1146,8 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   p64.precision = TN3D_PREC_FP64;
   p64.flags = TN3D_OPT_GRAM_FACTOR;
   p64.workspace_bytes = pr->workspace_bytes;
-  const bool timing = c->timing;
-  c->timing = false;  // the timing figures stay those of the main pass
+  // (with timing on, the re-sweep's kernels add to the sums like the main pass's)
   s = contract_impl(c, cnt, sub.data(), synd, d_offs, &p64, lps, fls);
-  c->timing = timing;
   if (s != TN3D_OK) return s;
   launch_scatter_resweep(cnt, d_items, lps, fls, lp, flags, c->stream);
   c->last_resweeps = cnt;
