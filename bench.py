@@ -3,11 +3,12 @@
 Headline workload (--config 3, the default): the 3D planar surface code at
 L = 8, point sector, i.i.d. flips p = 0.2; 256 seeded syndromes (both cosets
 each: 512 sweeps of an 8 x 8 grid through 7 layers); chi = chi_mps = 32; the
-BF16 precision mode (FP32 site tensors, the absorption Grams, reabsorption
-and boundary-MPS contraction on BF16 matrix cores with FP32 accumulation,
-truncations and log accumulators in FP64), rank rule eps_rel 1e-6 /
-tau_gap 1e-4.  A step is one tn3d_decode call over the whole batch with the
-syndromes already resident in HBM, replaying the captured launch sequences:
+BF16 precision mode (FP32 site tensors; the reabsorption and boundary-MPS
+contraction on BF16 matrix cores with FP32 accumulation, the Grams on FP64
+matrix cores; truncations and log accumulators in FP64), rank rule eps_rel
+1e-6 / tau_gap 1e-2 (the reduced-precision rule).  A step is one tn3d_decode
+call over the whole batch with the syndromes already resident in HBM,
+replaying the captured launch sequences:
 the BF16 contraction of every (syndrome, coset), the decision, and the FP64
 re-sweep (Gram route, same chi and rule) of every item whose BF16 log-ratio
 lies inside the library's near-tie band (4e-3).  At p = 0.2 the point sector
@@ -189,8 +190,7 @@ def bench_point_L8(a, tn3d, np, torch):
     prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32}[a.precision]
     ctx = tn3d.Context(0)
     net = (tn3d.tn3d_net_surface3d_loop if loop else tn3d.tn3d_net_surface3d_point)(ctx, L, dem.p)
-    prm = tn3d.tn3d_params_default(chi, chi, prec)
-    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    prm = tn3d.tn3d_params_default(chi, chi, prec)  # the reduced-precision rule: eps_rel 1e-6, tau_gap 1e-2
     # the library default near-tie band: every item whose BF16 log-ratio is
     # below it is contracted again in FP64 (Gram route) inside the same call
     syn = torch.from_numpy(m).to("cuda:0")
@@ -231,7 +231,7 @@ def bench_point_L8(a, tn3d, np, torch):
            "data": "synthetic (seeded Bernoulli flips of every qubit, p = 0.2)",
            "config": {"workload": f"3D planar surface code L=8, {sector} sector, i.i.d. flips p=0.2, 8x8 grid x 7 layers, "
                                   "chi=32, chi_mps=32, 256 syndromes x 2 cosets, rank rule eps_rel 1e-6 / tau_gap "
-                                  "1e-4, FP64 re-sweep of near ties", "global_batch": B, "chi": chi, "chi_mps": chi,
+                                  "1e-2, FP64 re-sweep of near ties", "global_batch": B, "chi": chi, "chi_mps": chi,
                       "precision": a.precision, "near_tie": prm.near_tie},
            "launch": "captured launch sequences replayed (HIP graph), device execution windows on",
            "items_reswept_fp64": int(np.sum(flags & 16 != 0)),
@@ -245,7 +245,7 @@ def bench_point_L8(a, tn3d, np, torch):
                      "near_tie": int(np.sum(flags & 4 != 0)), "no_converge": int(np.sum(flags & 8 != 0))}}
     # the BF16 pass alone (no re-sweep), one instrumented step
     p0 = tn3d.tn3d_params_default(chi, chi, prec)
-    p0.eps_rel, p0.tau_gap, p0.near_tie = 1e-6, 1e-4, 0.0
+    p0.near_tie = 0.0
     ctx.set_timing(1)
     b0 = time.perf_counter()
     r0 = tn3d.tn3d_decode(ctx, net, syn, p0)
@@ -270,7 +270,7 @@ def bench_point_L8(a, tn3d, np, torch):
     if not a.headline_only:
         # FP64 (Gram route), one step
         p64 = tn3d.tn3d_params_default(chi, chi, tn3d.PREC_FP64)
-        p64.eps_rel, p64.tau_gap = 1e-6, 1e-4
+        p64.eps_rel, p64.tau_gap = prm.eps_rel, prm.tau_gap
         p64.flags = tn3d.OPT_GRAM_FACTOR
         tn3d.tn3d_decode(ctx, net, syn, p64)
         torch.cuda.synchronize()
@@ -367,7 +367,7 @@ def bench_depolarizing(a, tn3d, np, torch):
     pr_name = a.precision or "fp32"
     prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32, "fp64": tn3d.PREC_FP64}[pr_name]
     prm = tn3d.tn3d_params_default(a.chi, a.chi, prec)
-    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-2  # the reduced-precision rule, in every precision here
     if prec == tn3d.PREC_FP64 and 4 * a.chi > 64:
         prm.flags = tn3d.OPT_GRAM_FACTOR
     parts = []
@@ -406,7 +406,7 @@ def bench_depolarizing(a, tn3d, np, torch):
            "data": "synthetic (seeded depolarizing errors)",
            "config": {"workload": f"3D planar code, depolarizing p=0.15, ragged L in (4, 5, 6) x "
                                   f"(171, 171, 170), chi={a.chi}, chi_mps={a.chi}, 512 syndromes x 4 "
-                                  f"cosets, reduced rank rule", "global_batch": B, "precision": pr_name},
+                                  f"cosets, rank rule eps_rel 1e-6 / tau_gap 1e-2", "global_batch": B, "precision": pr_name},
            "roofline": None, "autotune": tune,
            "flags": {"numeric": int(np.sum(flags & 1 != 0)), "inconsistent": int(np.sum(flags & 32 != 0))}}
     if not a.no_cpu:

@@ -108,9 +108,12 @@ typedef struct {
 } tn3d_params;
 
 /* Fill *p with the defaults for a precision: eps_rel 1e-9 (FP64) / 1e-6
- * (FP32), tau_gap 1e-6 / 1e-4, near_tie 4e-3, no workspace cap.  The gap
- * threshold stays well above the rounding of the smallest singular value the
- * rule can keep, so two correct implementations take the same cuts. */
+ * (FP32, BF16), tau_gap 1e-6 / 1e-2, near_tie 4e-3, no workspace cap.  The
+ * gap threshold stays well above the rounding of the smallest singular value
+ * the rule can keep, so two correct implementations take the same cuts; in
+ * the reduced precisions the kept subspace at a cut moves with the FP32
+ * rounding of the site tensors by about eps_32 / tau_gap, so their cuts sit
+ * only at gaps of a percent. */
 void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t precision);
 
 /* Create a context on HIP device `device`, enqueueing on `stream` (a

@@ -781,7 +781,9 @@ void tn3d_params_default(tn3d_params* p, int32_t chi, int32_t chi_mps, int32_t p
   // the smallest kept singular value must carry rounding well below the gap
   // that decides a cut: about 1e-7 relative at 1e-9 of the largest in FP64
   p->eps_rel = f64 ? 1e-9 : 1e-6;
-  p->tau_gap = f64 ? 1e-6 : 1e-4;
+  // reduced precisions: a cut only at a gap of a percent, where the kept
+  // subspace moves by about eps_32 / 1e-2 with the FP32 rounding of the sites
+  p->tau_gap = f64 ? 1e-6 : 1e-2;
   p->near_tie = 4e-3;
   p->workspace_bytes = 0;
 }

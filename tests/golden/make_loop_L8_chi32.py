@@ -1,7 +1,7 @@
 """Writes loop_L8_chi32.json: oracle (fixed-chi FP64 sweep) log coset
 probabilities of the 3D planar code, loop sector (bit flips seen by the face
-checks, generator picture), L=8, p=0.2, chi = chi_m = 32, reduced rank rule
-(eps_rel 1e-6, tau_gap 1e-4), for items 0, 85, 170 and 255 of the 256 seeded
+checks, generator picture), L=8, p=0.2, chi = chi_m = 32, reduced-precision rank rule
+(eps_rel 1e-6, tau_gap 1e-2), for items 0, 85, 170 and 255 of the 256 seeded
 syndromes of that workload (seed 2310107223, the error draws of the point
 sector's workload).
 
@@ -28,7 +28,7 @@ from oracle.sweep import sweep_logprob  # noqa: E402
 
 L, P, CHI, CHI_M, SEED, N = 8, 0.2, 32, 32, 2310107223, 256
 ITEMS = [0, 85, 170, 255]
-EPS, TAU = 1e-6, 1e-4
+EPS, TAU = 1e-6, 1e-2
 
 
 def one(args):

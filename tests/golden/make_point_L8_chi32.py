@@ -1,6 +1,6 @@
 """Writes point_L8_chi32.json: oracle (fixed-chi FP64 sweep) log coset
 probabilities of the 3D planar code, point sector, L=8, p=0.2, chi = chi_m =
-32, reduced rank rule (eps_rel 1e-6, tau_gap 1e-4), for items 0, 85, 170 and
+32, reduced-precision rank rule (eps_rel 1e-6, tau_gap 1e-2), for items 0, 85, 170 and
 255 of the 256 seeded syndromes of that workload (seed 2310107223).
 
 At this size the layer bonds reach 32 (site tensors of 2 * 32^4 entries) and
@@ -17,6 +17,8 @@ from multiprocessing import Pool
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"  # one thread per worker process (set before numpy loads)
 
 import synth  # noqa: E402
 from oracle.network import point3d_network  # noqa: E402
@@ -24,12 +26,11 @@ from oracle.sweep import sweep_logprob  # noqa: E402
 
 L, P, CHI, CHI_M, SEED, N = 8, 0.2, 32, 32, 2310107223, 256
 ITEMS = [0, 85, 170, 255]
-EPS, TAU = 1e-6, 1e-4
+EPS, TAU = 1e-6, 1e-2
 
 
 def one(args):
     k, c = args
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     dem = synth.surface3d_point(L, P)
     m, _ = synth.sample_syndromes(dem, N, SEED)
     lp, flags, nsplit = sweep_logprob(point3d_network(L, dem.p, m[k], c), CHI, CHI_M, EPS, TAU)

@@ -36,7 +36,7 @@ def test_params_defaults(lib_path):
     from paper_2310_10722_amd import tn3d
     p = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP32)
     assert (p.chi, p.chi_mps, p.precision) == (16, 16, 1)
-    assert p.eps_rel == 1e-6 and p.tau_gap == 1e-4 and p.flags == 0
+    assert p.eps_rel == 1e-6 and p.tau_gap == 1e-2 and p.flags == 0
     p = tn3d.tn3d_params_default(4, 8, tn3d.PREC_FP64)
     assert p.eps_rel == 1e-9 and p.tau_gap == 1e-6 and p.chi_mps == 8
 

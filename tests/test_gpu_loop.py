@@ -161,13 +161,10 @@ def test_loop_L8_chi32_full_batch_golden(ctx, mode):
     """The loop sector at L = 8, p = 0.2 (below its threshold, so the cosets
     differ), chi = chi_m = 32: the whole 256-syndrome batch in one call, items
     0, 85, 170, 255 against stored oracle values
-    (tests/golden/make_loop_L8_chi32.py, reduced rule).  FP64 Gram route:
-    1e-6 on the decoded coset.  BF16 mode (FP32 site tensors): the same
-    decisions; the decoded coset is measured up to 3.2e-3 off here (FP32 mode
-    alike), above the 1e-3 target: these truncations keep many singular
-    values near the cut, whose subspaces the FP32 rounding of the site
-    tensors moves.  Held to 1e-2 (decoded) and 5e-2 (other coset) as a
-    regression bound on that measured accuracy."""
+    (tests/golden/make_loop_L8_chi32.py, the reduced-precision rule eps_rel
+    1e-6, tau_gap 1e-2).  FP64 Gram route: 1e-6 on the decoded coset.  BF16
+    mode (FP32 site tensors): the decoded coset within 1e-3 and the same
+    decisions, the other coset within 1e-3 + 64 eps_32 e^gap."""
     import json
     import os
     from paper_2310_10722_amd import tn3d
@@ -192,7 +189,7 @@ def test_loop_L8_chi32_full_batch_golden(ctx, mode):
     assert np.all(flags & 8 == 0)
     if mode == "bf16":
         assert np.array_equal(np.argmax(g, axis=1), maj)
-        assert err[rows, maj].max() <= 1e-2
-        assert err[rows, 1 - maj].max() <= 5e-2
+        assert err[rows, maj].max() <= 1e-3
+        assert np.all(err[rows, 1 - maj] <= 1e-3 + 64.0 * EPS32 * np.exp(gap))
     else:
         assert err[rows, maj].max() <= 1e-6
