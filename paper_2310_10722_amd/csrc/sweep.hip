@@ -175,143 +175,24 @@ __device__ __forceinline__ void win_close(unsigned long long* win, unsigned long
 }
 
 // One wavefront per (gate side, sweep): G = X^T X for the row-weighted view X
-// (rows x ncols) of the site tensor, on the matrix cores.  Rows are taken 64
-// at a time: lane l finds the offset and the weight (the product of
-// sqrt(lambda) over the three other legs, the simple-update environment) of
-// row r0 + l, kept in LDS.  Then sixteen steps of four rows: lane
-// (li, lq) = (lane % 16, lane / 16) loads X[r][16 b + li] of its row
-// r = r0 + 4 s + lq for every 16-column block b, and one
-// v_mfma_f64_16x16x4f64 per block pair b1 <= b2 accumulates X_b1^T X_b2 (the
-// A and B operands are the same loaded values; item q of a lane holds row
-// lq + 4 q of the block).  Loads are issued four steps ahead of their
-// products.  The launch handles the Grams with ncols in (nlo, 16 NB].
-template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_gram(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
-                                             int nlo) {
-  const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
-  const DevGate g = gates[gi];
-  const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
-  const int d = side ? g.dB : g.dA, par = side ? g.srcB : g.srcA;
-  int D[4];
-  site_dims(A, sweep, site, D);
-  const Split v = make_split(D, leg, d);
-  const int ncols = d * v.Dx;
-  if (ncols <= nlo || ncols > 16 * NB) return;
-  const unsigned long long w0 = win_open(A.win);
-  __shared__ double slam[4][MAXCHI];
-  __shared__ int rowbase[64];
-  __shared__ double rowsc[64];
-  for (int e = lane; e < 4 * MAXCHI; e += 64) {
-    const int l = e / MAXCHI, k = e % MAXCHI;
-    const int b = A.leg_bond[site * 4 + l];
-    double val = 1.0;
-    if (l != leg && b >= 0 && k < D[l]) val = sqrt(A.lam[(int64_t(sweep) * A.n_bonds + b) * A.lam_ld + k]);
-    slam[l][k] = val;
-  }
-  const int li = lane & 15, lq = lane >> 4;
-  int cofs[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int col = 16 * b + li, p = col / v.Dx, x = col - p * v.Dx;
-    cofs[b] = col < ncols ? x * v.Cp * d + p : -1;
-  }
-  constexpr int NP = NB * (NB + 1) / 2;
-  dbl4 acc[NP];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const T* t = tens<T>(A, par, sweep, site);
-  __syncthreads();
-  for (int r0 = 0; r0 < v.rows; r0 += 64) {
-    {
-      const int r = r0 + lane;
-      int base = 0;
-      double sc = 0.0;
-      if (r < v.rows) {
-        const int a = r / v.Cp, c = r - a * v.Cp;
-        base = (a * v.Dx * v.Cp + c) * d;
-        sc = 1.0;
-        int cc = c;
-        for (int l = 3; l > leg; --l) {
-          const int q = cc / D[l];
-          sc *= slam[l][cc - q * D[l]];
-          cc = q;
-        }
-        int aa = a;
-        for (int l = leg - 1; l >= 0; --l) {
-          const int q = aa / D[l];
-          sc *= slam[l][aa - q * D[l]];
-          aa = q;
-        }
-      }
-      rowbase[lane] = base;
-      rowsc[lane] = sc;
-    }
-    __syncthreads();
-    const int nleft = v.rows - r0;
-    for (int s0 = 0; s0 < 16; s0 += 4) {
-      if (4 * s0 >= nleft) break;  // uniform
-      double xv[4][NB];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int rl = 4 * (s0 + u) + lq;
-        const bool ok = rl < nleft;
-        const int base = rowbase[rl];
-        const double sc = rowsc[rl];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) xv[u][b] = (ok && cofs[b] >= 0) ? double(t[base + cofs[b]]) * sc : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int q = 0;
-#pragma unroll
-        for (int b1 = 0; b1 < NB; ++b1)
-#pragma unroll
-          for (int b2 = b1; b2 < NB; ++b2) {
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][b1], xv[u][b2], acc[q], 0, 0, 0);
-            ++q;
-          }
-      }
-    }
-    __syncthreads();  // the next chunk's offsets replace these
-  }
-  if (A.bytes_ctr && lane == 0)
-    atomicAdd(A.bytes_ctr + ((blockIdx.x + 7 * blockIdx.y) & 63),
-              (unsigned long long)(int64_t(v.rows) * ncols * int64_t(sizeof(T))));
-  if (side == 0 && lane == 0) A.gate_n[int64_t(sweep) * n_g + gi] = g.K * v.Dx;
-  double* out = gout + (int64_t(sweep * n_g + gi) * 2 + side) * ncap * ncap;
-  int q = 0;
-#pragma unroll
-  for (int b1 = 0; b1 < NB; ++b1)
-#pragma unroll
-    for (int b2 = b1; b2 < NB; ++b2) {
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int i = 16 * b1 + lq + 4 * it, j = 16 * b2 + li;
-        if (i < ncols && j < ncols) {
-          out[i * ncols + j] = acc[q][it];
-          if (b1 != b2) out[j * ncols + i] = acc[q][it];
-        }
-      }
-      ++q;
-    }
-  win_close(A.win, w0);
-}
-
-// The same Gram through LDS, for every storage type: each chunk of 32 rows of
-// the row-weighted view X is fetched in memory order (consecutive lanes read
-// consecutive addresses: along the rows when the legs after the gated one
-// hold more than one index, Cp > 1, else along the columns), scaled by the
-// rows' environment weights and stored column-major in LDS; the next chunk's
-// values are fetched into registers while the current one is multiplied.
-// BF = 0: FP64 matrix cores on the values (v_mfma_f64_16x16x4f64, as
-// k_gram).  BF = 1 (float storage): BF16 matrix cores with FP32
-// accumulation, each value split into three BF16 terms x = h + m + l (8
-// significant bits each, so the split is exact to 24 bits) and X^T X formed
-// from the six products h.h, h.m, m.h, h.l, m.m, l.h (the dropped ones are
-// below 2^-24 relative), per chunk in FP32, summed over chunks in FP64.
+// (rows x ncols) of the site tensor (each row scaled by the product of
+// sqrt(lambda) over the three other legs, the simple-update environment), on
+// the FP64 matrix cores for every storage type.  Each chunk of 32 rows is
+// fetched in memory order (consecutive lanes read consecutive addresses:
+// along the rows when the legs after the gated one hold more than one index,
+// Cp > 1, else along the columns), scaled by the rows' weights and stored
+// column-major in LDS; the next chunk's values are fetched into registers
+// while the current one is multiplied.  Lane (li, lq) = (lane % 16, lane / 16)
+// takes X[r][16 b + li] for the four rows r = 4 s + lq of a step and every
+// 16-column block b, and one v_mfma_f64_16x16x4f64 per block pair b1 <= b2
+// accumulates X_b1^T X_b2 (the A and B operands are the same values).  FP32
+// storage is multiplied as FP64: a Gram accumulated in FP32 (as a split-BF16
+// product would be) carries FP32 rounding into its small eigenvalues, the
+// squares of the small singular values the reduced rank rule keeps.  The
+// launch handles the Grams with ncols in (nlo, 16 NB].
 constexpr int GR = 32;  // rows per chunk
 
-template <typename T, int NB, int BF>
+template <typename T, int NB>
 __global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
                                               int nlo) {
   constexpr int NC = 16 * NB;
@@ -408,56 +289,20 @@ __global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates,
     if (r0 + GR < v.rows) rows_of(r0 + GR, q ^ 1);
     __syncthreads();
     if (r0 + GR < v.rows) fetch(r0 + GR, q ^ 1);
-    if (BF == 0) {
-      const int li = lane & 15, lq = lane >> 4;
+    const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
-      for (int s4 = 0; s4 < GR / 4; ++s4) {
-        double xv[NB];
+    for (int s4 = 0; s4 < GR / 4; ++s4) {
+      double xv[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) xv[b] = double(Xs[(16 * b + li) * (GR + 1) + 4 * s4 + lq]);
-        int k = 0;
+      for (int b = 0; b < NB; ++b) xv[b] = double(Xs[(16 * b + li) * (GR + 1) + 4 * s4 + lq]);
+      int k = 0;
 #pragma unroll
-        for (int b1 = 0; b1 < NB; ++b1)
+      for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
-          for (int b2 = b1; b2 < NB; ++b2) {
-            acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[b1], xv[b2], acc[k], 0, 0, 0);
-            ++k;
-          }
-      }
-    } else {
-      const int li = lane & 15, kq = lane >> 4;
-      bf16x8 h[NB], m[NB], l[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        float vv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = float(Xs[(16 * b + li) * (GR + 1) + 8 * kq + u]);
-        split3(vv, h[b], m[b], l[b]);
-      }
-      flt4 c[NP];
-#pragma unroll
-      for (int k = 0; k < NP; ++k) c[k] = flt4{0.f, 0.f, 0.f, 0.f};
-      // the six products, smallest first, each over the NP independent block pairs
-      auto step = [&](const bf16x8 (&x)[NB], const bf16x8 (&y)[NB]) {
-        int k = 0;
-#pragma unroll
-        for (int b1 = 0; b1 < NB; ++b1)
-#pragma unroll
-          for (int b2 = b1; b2 < NB; ++b2) {
-            c[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[b1], y[b2], c[k], 0, 0, 0);
-            ++k;
-          }
-      };
-      step(l, h);
-      step(m, m);
-      step(h, l);
-      step(m, h);
-      step(h, m);
-      step(h, h);
-#pragma unroll
-      for (int k = 0; k < NP; ++k)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[k][r] += double(c[k][r]);
+        for (int b2 = b1; b2 < NB; ++b2) {
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[b1], xv[b2], acc[k], 0, 0, 0);
+          ++k;
+        }
     }
     __syncthreads();  // this chunk's tile is read before the next one replaces it
   }
@@ -474,9 +319,8 @@ __global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates,
     for (int b2 = b1; b2 < NB; ++b2) {
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
-        // FP64 16x16x4: item r of lane j + 16 q is C[q + 4 r][j]; the BF16
-        // 16x16x32 one has C[4 q + r][j]
-        const int i = 16 * b1 + (BF ? 4 * lq + it : lq + 4 * it), j = 16 * b2 + li;
+        // FP64 16x16x4: item r of lane j + 16 q is C[q + 4 r][j]
+        const int i = 16 * b1 + lq + 4 * it, j = 16 * b2 + li;
         if (i < ncols && j < ncols) {
           out[i * ncols + j] = acc[k][it];
           if (b1 != b2) out[j * ncols + i] = acc[k][it];
@@ -488,14 +332,14 @@ __global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates,
 }
 
 // FP64 route: the triangular factor R (R^T R = X^T X) of the same row-weighted
-// view X as k_gram, by Householder QR streamed over the rows (tsqr_block), so
+// view X as k_gram2, by Householder QR streamed over the rows (tsqr_block), so
 // no Gram matrix is formed and the small singular values of X keep the
 // accuracy of an orthogonal factorisation (a Gram squares their condition).
 // One wavefront per (gate side, sweep), split into 64 / TL teams of TL lanes
 // (ncols <= TL, lane l of a team owns column l): team t factors rows
 // t TL .. t TL + TL - 1 of every chunk of 64 rows into a factor of its own,
 // then team 0 absorbs the other teams' factors (a two-level TSQR tree).  R is
-// written where k_gram writes the Gram (row-major, ncols x ncols).
+// written where k_gram2 writes the Gram (row-major, ncols x ncols).
 template <typename T, int TL>
 __global__ __launch_bounds__(64) void k_qr(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
                                            int nlo) {
@@ -2548,19 +2392,19 @@ void launch_onesite(int prec, const SweepArgs& A, const DevOneSite* ops, int n_o
     hipLaunchKernelGGL(k_onesite<float>, g, dim3(ET), 0, st, A, ops);
 }
 
-template <typename T, int BF>
+template <typename T>
 static void gram_dispatch(const SweepArgs& A, const DevGate* gates, int n_g, int n_wide, int n_w64, double* gout,
                           int ncap, hipStream_t st) {
   // ncap <= 64 is checked by the host before any launch; Grams of up to 32
   // columns (three block pairs) and of 33 to 64 (ten) in separate launches,
   // the second over the leading n_wide gates (the only ones that can be wide)
-  hipLaunchKernelGGL((k_gram2<T, 2, BF>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
+  hipLaunchKernelGGL((k_gram2<T, 2>), dim3(2 * n_g, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout, ncap, 0);
   if (ncap > 32 && n_wide > 0)
-    hipLaunchKernelGGL((k_gram2<T, 4, BF>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
+    hipLaunchKernelGGL((k_gram2<T, 4>), dim3(2 * n_wide, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
                        ncap, 32);
   // 65 to 96 columns (physical dim 4 at chi up to 24): 21 block pairs
   if (ncap > 64 && n_w64 > 0)
-    hipLaunchKernelGGL((k_gram2<T, 6, BF>), dim3(2 * n_w64, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
+    hipLaunchKernelGGL((k_gram2<T, 6>), dim3(2 * n_w64, A.n_sweeps), dim3(64), 0, st, A, gates, n_g, gout,
                        ncap, 64);
 }
 
@@ -2585,9 +2429,9 @@ void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, in
   // about 3e-4 of the largest, which the reduced rule keeps, came out wrong
   // (0.5 nats on the loop sector at L = 8, chi = 32)
   if (prec == 0)
-    gram_dispatch<double, 0>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
+    gram_dispatch<double>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
   else
-    gram_dispatch<float, 0>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
+    gram_dispatch<float>(A, gates, n_g, n_wide, n_w64, gout, ncap, st);
 }
 
 // Dynamic LDS of a k_solve launch whose orders reach kd: four n x n matrices
