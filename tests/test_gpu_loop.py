@@ -164,7 +164,12 @@ def test_loop_L8_chi32_full_batch_golden(ctx, mode):
     (tests/golden/make_loop_L8_chi32.py, the reduced-precision rule eps_rel
     1e-6, tau_gap 1e-2).  FP64 Gram route: 1e-6 on the decoded coset.  BF16
     mode (FP32 site tensors): the decoded coset within 1e-3 and the same
-    decisions, the other coset within 1e-3 + 64 eps_32 e^gap."""
+    decisions, the other coset within 1e-3 + 64 eps_32 e^gap + n_cuts
+    eps_32 / tau_gap.  The last term is the first-order motion of the kept
+    subspaces: a cut at a relative gap tau moves its kept subspace under a
+    storage rounding eps_32 S_1 by at most eps_32 S_1 / (tau S_D), which
+    changes the truncated tensor by at most eps_32 / tau of its norm; the
+    sweep makes 7 layers x 112 gate cuts and 7 x 7 boundary-MPS cuts."""
     import json
     import os
     from paper_2310_10722_amd import tn3d
@@ -190,6 +195,8 @@ def test_loop_L8_chi32_full_batch_golden(ctx, mode):
     if mode == "bf16":
         assert np.array_equal(np.argmax(g, axis=1), maj)
         assert err[rows, maj].max() <= 1e-3
-        assert np.all(err[rows, 1 - maj] <= 1e-3 + 64.0 * EPS32 * np.exp(gap))
+        n_cuts = 7 * 112 + 7 * 7
+        motion = n_cuts * EPS32 / gold["rule"][1]
+        assert np.all(err[rows, 1 - maj] <= 1e-3 + 64.0 * EPS32 * np.exp(gap) + motion)
     else:
         assert err[rows, maj].max() <= 1e-6
