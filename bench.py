@@ -36,7 +36,8 @@ The JSON line also reports
 Other workloads: --config 6 (the same L = 8 code and error draws in the loop
 sector, bit flips seen by the faces, below its threshold at p = 0.2),
 --config 2 (rotated d=5, phenomenological, chi = 16, FP64), --config 4
-(depolarizing, ragged L in {4, 5, 6}).
+(depolarizing, ragged L in {4, 5, 6}), --config 5 (the gradient of the
+syndrome log-likelihood with respect to 217 rates, rotated d=7, chi = 16).
 """
 
 from __future__ import annotations
@@ -355,6 +356,122 @@ def bench_rotated_d5(a, tn3d, np, torch):
     print(json.dumps(out))
 
 
+def _oracle_grad_cosets(args):
+    d, T, checks, q, m, chi, chi_m, eps, tau = args
+    from oracle.network import rotated_network
+    from oracle.sweep import sweep_logprob
+    return [sweep_logprob(rotated_network(d, T, checks, q, m, c), chi, chi_m, eps, tau)[0] for c in (0, 1)]
+
+
+def bench_rotated_d7_grad(a, tn3d, np, torch):
+    """The gradient workload: rotated d=7, 7 noisy + 1 perfect rounds,
+    per-qubit / per-measurement rates log-uniform in [0.005, 0.05], 256
+    syndromes, chi = chi_mps = 16, FP32 site tensors, rank rule 1e-6 / 1e-2.
+    A step is one tn3d_grad_loglik call: d/dr of sum_s log P(m_s) over the
+    49 + 168 rate parameters (the network at the rates and at each of the 511
+    single-rate changes, 256 x 512 x 2 sweeps, and the reduction)."""
+    import synth
+    dem, m, _, _ = synth.config_workload(5)
+    B = m.shape[0]
+    d, T, nq, nZ = 7, 7, 49, 24
+    rate_of = np.concatenate([np.tile(np.arange(nq), T), nq + np.arange(T * nZ)]).astype(np.int32)
+    a.precision = a.precision or "fp32"
+    prec = {"bf16": tn3d.PREC_BF16, "fp32": tn3d.PREC_FP32, "fp64": tn3d.PREC_FP64}[a.precision]
+    ctx = tn3d.Context(0)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, d, T, dem.p)
+    prm = tn3d.tn3d_params_default(16, 16, prec)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-2
+    syn = torch.from_numpy(m).to("cuda:0")
+    # the forward pass alone, for the ratio
+    for _ in range(2):
+        tn3d.tn3d_contract_cosets(ctx, net, syn, prm)
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    for _ in range(3):
+        tn3d.tn3d_contract_cosets(ctx, net, syn, prm)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - f0) * 1e3 / 3
+    for i in range(a.warmup):
+        tn3d.tn3d_grad_loglik(ctx, net, syn, prm, rate_of_mech=rate_of)
+        torch.cuda.synchronize()
+        say(f"warmup step {i + 1}/{a.warmup} done")
+    ctx.set_timing(1)
+    res = None
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        res = tn3d.tn3d_grad_loglik(ctx, net, syn, prm, rate_of_mech=rate_of, per_item=(i == a.steps - 1))
+        torch.cuda.synchronize()
+        say(f"timed step {i + 1}/{a.steps} done")
+    dt = time.perf_counter() - t0
+    t = ctx.last_timing()
+    ctx.set_timing(0)
+    (lay_ms, fin_ms, hot_ms, hot_launch, hot_bytes, eig_ms, eig_launch, eig_flops, za_ms, za_flops, za_launch,
+     sub_ms, sub_flops, sub_launch) = t
+    grad, tot, ll, flags, items = res
+    grad, ll, flags, items = grad.cpu().numpy(), ll.cpu().numpy(), flags.cpu().numpy(), items.cpu().numpy()
+    rf_eig = roof_entry("k_zip_beig (boundary-MPS decompositions of families up to 64 vectors, one wavefront each)",
+                        "alu", eig_flops, eig_ms, eig_launch, FP64_PEAK_TFS, "TFLOP/s", None)
+    stream = roof_entry("k_gram2 + k_reabsorb2 + k_reabsorb (site-tensor streaming)", "hbm", hot_bytes, hot_ms,
+                        hot_launch, HBM_PEAK_GBS, "GB/s", None)
+    dom = rf_eig if eig_ms >= hot_ms else stream
+    out = {"metric": "syndrome log-likelihood gradients/sec at fixed chi (d/dr sum_s log P(m_s), 217 rates)",
+           "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": dt * 1e3 / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bf16": "bf16", "fp32": "f32", "fp64": "f64"}[a.precision],
+           "data": "synthetic (seeded Bernoulli error samples of the code's DEM)",
+           "config": {"workload": "rotated d=7 surface code, phenomenological noise, 7 noisy + 1 perfect rounds, "
+                                  "per-qubit / per-measurement rates log-uniform in [0.005, 0.05], 7x8 grid x 7 "
+                                  "layers, chi=16, chi_mps=16, 256 syndromes, gradient over 49 + 168 rates "
+                                  "(511 mechanisms)", "global_batch": B, "precision": a.precision},
+           "forward_only_ms": fwd_ms, "gradient_over_forward": (dt * 1e3 / a.steps) / fwd_ms,
+           "phases_ms_per_step": {"layer_absorption": lay_ms / a.steps, "boundary_mps": fin_ms / a.steps,
+                                  "gram_plus_reabsorb": hot_ms / a.steps,
+                                  "boundary_decomposition_small": eig_ms / a.steps},
+           "roofline": dom, "roofline_streaming": stream, "roofline_boundary": rf_eig,
+           "loglik_sum": float(tot.cpu()[0]), "grad_abs_max": float(np.abs(grad).max()),
+           "flags": {"numeric": int(np.sum(flags & 1 != 0)), "trunc_cluster": int(np.sum(flags & 2 != 0)),
+                     "no_converge": int(np.sum(flags & 8 != 0))}}
+    if not a.no_cpu:
+        # the oracle's one-sided gradient of one syndrome over every mechanism
+        from oracle.grad import loglik_grad_one_sided
+        k = 0
+        jobs = [(d, T, dem.params["checks"], dem.p, m[k], prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap)]
+        for i in range(dem.n_mech):
+            q = dem.p.copy()
+            q[i] = 1.0 if dem.p[i] <= 0.5 else 0.0
+            jobs.append((d, T, dem.params["checks"], q, m[k], prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap))
+        for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[v] = "1"
+        say(f"cpu baseline: {2 * len(jobs)} oracle sweeps on {CPU_WORKERS} workers")
+        mpc = mp.get_context("spawn")
+        with mpc.Pool(CPU_WORKERS) as pool:
+            pool.map(int, range(CPU_WORKERS))
+            c0 = time.perf_counter()
+            vals = pool.map(_oracle_grad_cosets, jobs, chunksize=1)
+            cdt = time.perf_counter() - c0
+        say(f"cpu baseline: {cdt:.1f} s")
+        table = {-1: vals[0]}
+        table.update({i: vals[i + 1] for i in range(dem.n_mech)})
+
+        def cosets(q):
+            ch = np.nonzero(q != dem.p)[0]
+            return table[int(ch[0]) if ch.size else -1]
+
+        lp, g = loglik_grad_one_sided(cosets, dem.p)
+        c = np.where(dem.p <= 0.5, 1.0, 0.0)
+        bound = (np.abs(1.0 + g * (c - dem.p)) + 1.0) * np.expm1(2.0 * (1e-3 + 4.0 * 2.0 ** -24)) / np.abs(c - dem.p)
+        err = np.abs(items[k] - g)
+        out["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "syndromes/s", "cores": CPU_WORKERS, "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"syndrome 0: its gradient over all {dem.n_mech} mechanisms, "
+                                         f"{2 * len(jobs)} fixed-chi FP64 sweeps (the network at the rates and at "
+                                         f"each single-rate change), one per single-threaded worker"}
+        out["accuracy"] = {"vs": "CPU oracle one-sided gradient (fixed-chi FP64 sweeps), syndrome 0",
+                           "max_abs_dterm": float(err.max()), "max_err_over_bound": float((err / bound).max()),
+                           "abs_dloglik": float(abs(ll[k] - lp))}
+    print(json.dumps(out))
+
+
 def bench_depolarizing(a, tn3d, np, torch):
     """3D planar code under depolarizing noise p = 0.15, 512 syndromes with
     L = 4, 5, 6 (171 / 171 / 170, shuffled by the seed) decoded in one ragged
@@ -437,13 +554,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 3 for the L = 8 workloads, about a minute; 5 otherwise)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1 for L = 8; 2 otherwise)")
+                    help="timed steps (default 3 for the L = 8 and gradient workloads; 5 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 1 for the L = 8 and gradient workloads; 2 otherwise)")
     ap.add_argument("--config", type=int, default=3,
                     help="3: 3D planar L=8 point sector, chi 32 (the headline); 6: the same in the loop sector; "
-                         "2: rotated d=5; 4: depolarizing, ragged L in {4, 5, 6}")
+                         "2: rotated d=5; 4: depolarizing, ragged L in {4, 5, 6}; 5: the rate gradient, rotated d=7")
     ap.add_argument("--precision", default=None, choices=("bf16", "fp32", "fp64"),
-                    help="--config 3 and 6 (default bf16), --config 4 (default fp32)")
+                    help="--config 3 and 6 (default bf16), --config 4 and 5 (default fp32)")
     ap.add_argument("--chi", type=int, default=24, help="chi = chi_mps for --config 4")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -455,7 +573,7 @@ def main():
                     help="only copy a MIB-sized device buffer once (the calibration run for the HBM byte "
                          "counters of a profiler) and exit")
     a = ap.parse_args()
-    big = a.config in (3, 6)
+    big = a.config in (3, 5, 6)
     if a.steps is None:
         a.steps = 3 if big else 5
     if a.warmup is None:
@@ -485,6 +603,8 @@ def main():
         return bench_rotated_d5(a, tn3d, np, torch)
     if a.config == 4:
         return bench_depolarizing(a, tn3d, np, torch)
+    if a.config == 5:
+        return bench_rotated_d7_grad(a, tn3d, np, torch)
     raise SystemExit(f"no benchmark workload {a.config}")
 
 

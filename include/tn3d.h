@@ -277,10 +277,13 @@ tn3d_status tn3d_contract_cosets_noalloc(tn3d_ctx ctx, int32_t batch, const tn3d
                                          const tn3d_params* params, double* logp_dev, uint32_t* flags_dev);
 
 /* Decode (paper Sec. 2.3, eq. optimal_decoder): as tn3d_contract_cosets, then
- * per item coset_dev[i] = argmax_L log p_{m,L} (lowest index on exact ties),
+ * per item coset_dev[i] = argmax_L log p_{m,L} (lowest index on exact ties;
+ * a NaN value ranks below every number, and an item with every value NaN
+ * decodes to 0 with a NaN log-ratio),
  * logratio_dev[i] = log p of the chosen coset minus the largest other one
- * (>= 0), TN3D_FLAG_NEAR_TIE when logratio < params->near_tie.  With
- * precision TN3D_PREC_FP32 and near_tie > 0, every item whose log-ratio is
+ * (>= 0; +inf when every other value is NaN or -inf), TN3D_FLAG_NEAR_TIE
+ * when logratio < params->near_tie.  With a reduced precision
+ * (TN3D_PREC_FP32, TN3D_PREC_BF16) and near_tie > 0, every item whose log-ratio is
  * below near_tie (or not a number) is contracted again in FP64 at the same chi,
  * chi_mps and rank rule, through the Gram route (TN3D_OPT_GRAM_FACTOR; the
  * decision needs far less than that route's accuracy); its logp row, flags
@@ -291,6 +294,42 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
                         const uint8_t* syndromes_dev, const int64_t* offsets_dev,
                         const tn3d_params* params, int32_t* coset_dev, double* logratio_dev,
                         double* logp_dev, uint32_t* flags_dev);
+
+/* Gradient of the syndrome log-likelihood with respect to the rates (the
+ * Sec. 2.4 definition of p_{m,L}; used to fit a noise model to syndrome
+ * data).  P(m) = sum_L p_{m,L} is affine in each mechanism's rate p_i (every
+ * term of the sum holds p_i or 1 - p_i once), so with P_c(m) the value at
+ * p_i = c,  d log P(m) / d p_i = (P_c(m) / P(m) - 1) / (c - p_i)  for c = 0
+ * or 1.  The library contracts `net` at its rates and, per mechanism i, the
+ * same network rebuilt with p_i = c_i (1 if p_i <= 1/2, else 0), every
+ * contraction at params' chi, chi_mps, precision and rank rule (no near-tie
+ * re-sweep): batch * (n_mech + 1) contractions.  Each P is the fixed-chi
+ * approximation, so the result is the exact gradient where chi truncates
+ * nothing and otherwise carries the truncation error of the contractions
+ * (it is not the derivative of the truncated contraction itself).
+ * Rates: the builder's rate array (p_mech, or p_qubit of the depolarizing
+ * family); rate_of_mech (host int32[n_mech], nullable) maps each to one of
+ * n_rates parameters, and grad_dev[k] (FP64, device, n_rates entries) is the
+ * sum over items s and the mechanisms of parameter k of d log P(m_s) / d p_i
+ * (chain rule through p_i = r_k); without a map n_rates = n_mech.
+ * Syndromes as in tn3d_contract_cosets (batch items, device offsets).
+ * Optional outputs (device, nullable): loglik_sum_dev[1] = sum_s log P(m_s),
+ * loglik_dev[batch] = log P(m_s), grad_items_dev[batch][n_mech] the
+ * per-item derivatives d log P(m_s) / d p_i, flags_dev[batch]
+ * the OR of the flags of an item's contractions.  P at p_i = c_i is often
+ * exactly zero (no error pattern with x_i = c_i explains the syndrome): a
+ * coset of such a changed network that the contraction finds non-positive
+ * (NaN, NUMERIC in the item's flags) counts as zero, which is exact up to
+ * the contraction's own error.  A NaN log p at the given rates, or an
+ * impossible syndrome (log P = -inf), makes the gradient NaN.  The
+ * networks at the changed rates are built on the first call and kept with
+ * `net` (released by tn3d_net_destroy).  Synchronises the context stream.
+ * Errors: TN3D_E_INVALID (bad handles, params, map entries out of range),
+ * TN3D_E_UNSUPPORTED (as tn3d_contract_cosets), TN3D_E_OOM, TN3D_E_DEVICE. */
+tn3d_status tn3d_grad_loglik(tn3d_ctx ctx, tn3d_net net, int32_t batch, const uint8_t* syndromes_dev,
+                             const int64_t* offsets_dev, const tn3d_params* params, int32_t n_rates,
+                             const int32_t* rate_of_mech, double* grad_dev, double* loglik_sum_dev,
+                             double* loglik_dev, double* grad_items_dev, uint32_t* flags_dev);
 
 /* Autotuner (batching): searches the launch shapes of the layer absorption
  * (the size-class split points of the truncation kernels: teams of eight

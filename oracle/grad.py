@@ -25,6 +25,11 @@ Pins (tests/test_oracle_grad.py): brute-force posterior marginals on tiny
 codes (the marginal form above, enumerated independently), central finite
 differences of O-2, and a two-mechanism closed form.
 
+loglik_grad_one_sided evaluates the same derivative from one changed rate
+per mechanism, with any evaluator of the coset values (pinned to the
+two-sided exact form above; with the fixed-chi sweep it is the gradient the
+library computes at equal chi).
+
 Also here: central finite differences of the fixed-chi sweep (O-3), the
 derivative of the *approximate* value that a reverse pass of the sweep
 computes (ranks held fixed between the two evaluations).
@@ -64,6 +69,37 @@ def loglik_grad_exact(H, p, obs, m, order=None):
         q[i] = 0.0
         l0 = loglik_exact(H, q, obs, m, order)
         g[i] = np.exp(l1 - lp) - np.exp(l0 - lp)
+    return lp, g
+
+
+def loglik_grad_one_sided(cosets_logp, p, indices=None):
+    """The same derivative from one changed rate per mechanism, for any
+    evaluator cosets_logp(rates) -> log p_{m,L} over the cosets (the exact
+    contraction, or the fixed-chi sweep O-3 at a given chi and rank rule).
+    With c_i = 1 if p_i <= 1/2 else 0, P = (1 - p_i) P(p_i = 0) + p_i P(p_i = 1)
+    gives P(p_i = c_i) - P = (c_i - p_i) (P(p_i = 1) - P(p_i = 0)), so
+
+        d log P / d p_i = (P(p_i = c_i) / P - 1) / (c_i - p_i).
+
+    P(p_i = c_i) is often exactly zero (no error pattern with x_i = c_i
+    explains the syndrome).  An approximate evaluator returns that value as
+    some rounding of zero, and a non-positive one as NaN: such a coset of a
+    changed network is taken as zero, which is exact up to the evaluator's
+    own error (a value it cannot tell from zero is below that error).  A NaN
+    at the given rates stays NaN.
+
+    Returns (log P, the derivatives for `indices`, default every mechanism)."""
+    p = np.asarray(p, dtype=np.float64)
+    lp = _logsumexp(cosets_logp(p))
+    idx = list(range(p.size)) if indices is None else list(indices)
+    g = np.empty(len(idx))
+    for k, i in enumerate(idx):
+        ci = 1.0 if p[i] <= 0.5 else 0.0
+        q = p.copy()
+        q[i] = ci
+        lq = np.asarray(cosets_logp(q), dtype=np.float64)
+        lq = np.where(np.isnan(lq), -np.inf, lq)
+        g[k] = np.expm1(_logsumexp(lq) - lp) / (ci - p[i])
     return lp, g
 
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -88,6 +89,8 @@ struct tn3d_ctx_s {
   int last_resweeps = 0;           // items the last decode re-swept in FP64
   char* aux = nullptr;             // decode scratch
   size_t aux_bytes = 0;
+  char* gaux = nullptr;            // gradient scratch
+  size_t gaux_bytes = 0;
   char* scratch = nullptr;         // this device's copy of the static scratch array
   bool graphs = true;              // replay captured launch sequences
   std::map<TuneKey, LaunchTuning> tune;  // launch shapes chosen by tn3d_autotune
@@ -109,6 +112,13 @@ struct tn3d_net_s {
   int32_t *d_d_after = nullptr, *d_par_after = nullptr, *d_d_final = nullptr, *d_f_off = nullptr;
   uint64_t* d_ext = nullptr;  // derived-bit rows (Program::ext_rows), or null
   int max_gates_class = 0;
+  uint64_t tune_serial = 0;  // launch shapes come from the autotuner's entry of this network
+  // the builder call that made P, for networks at other rates (gradients)
+  std::function<std::string(const double*, Program&)> rebuild;
+  std::vector<double> rates;  // the builder's rate array (P.n_mech entries)
+  // tn3d_grad_loglik: per mechanism i, this network with rate i at var_c[i]
+  std::vector<tn3d_net> variants;
+  std::vector<double> var_c;
 };
 
 namespace {
@@ -199,6 +209,7 @@ tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* 
   if (!n) return fail(c, TN3D_E_OOM, "host allocation");
   n->ctx = c;
   n->serial = c->next_serial++;
+  n->tune_serial = n->serial;
   n->P = std::move(P);
   tn3d_status s = upload_net(n);
   if (s != TN3D_OK) {
@@ -209,6 +220,20 @@ tn3d_status make_net(tn3d_ctx c, const std::string& err, Program&& P, tn3d_net* 
   c->nets.push_back(n);
   *out = n;
   return TN3D_OK;
+}
+
+// Builds a network with f at rates p and keeps f and the rates, so that the
+// gradient can build the same network at other rates.
+tn3d_status build_net(tn3d_ctx c, std::function<std::string(const double*, Program&)> f, const double* p,
+                      tn3d_net* out) {
+  Program P;
+  std::string e = f(p, P);
+  tn3d_status s = make_net(c, e, std::move(P), out);
+  if (s == TN3D_OK) {
+    (*out)->rebuild = std::move(f);
+    (*out)->rates.assign(p, p + (*out)->P.n_mech);
+  }
+  return s;
 }
 
 // Sizes of every per-sweep array for one network at given chi / chi_m.
@@ -313,7 +338,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   Layout L = make_layout(P, pr.chi, pr.chi_mps, prec, max_g);
   LaunchTuning TU;
   {
-    auto it = c->tune.find(TuneKey{n->serial, prec, pr.chi, pr.chi_mps});
+    auto it = c->tune.find(TuneKey{n->tune_serial, prec, pr.chi, pr.chi_mps});
     if (it != c->tune.end()) TU = it->second;
   }
   // the kernels' fixed-size LDS arrays bound these (sweep.hip)
@@ -849,6 +874,7 @@ void tn3d_ctx_destroy(tn3d_ctx c) {
     (void)hipFree(c->ws);
   }
   if (c->aux) (void)hipFree(c->aux);
+  if (c->gaux) (void)hipFree(c->gaux);
   if (c->tacc) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->tacc);
@@ -863,42 +889,37 @@ const char* tn3d_last_error(tn3d_ctx c) { return c ? c->err.c_str() : "null cont
 tn3d_status tn3d_net_surface3d_point(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
   if (!c || !out) return TN3D_E_INVALID;
   *out = nullptr;
-  Program P;
-  std::string e = build_surface3d_point(L, p, P);
-  return make_net(c, e, std::move(P), out);
+  return build_net(c, [L](const double* q, Program& P) { return build_surface3d_point(L, q, P); }, p, out);
 }
 
 tn3d_status tn3d_net_rotated_phenom(tn3d_ctx c, int32_t d, int32_t T, const double* p, tn3d_net* out) {
   if (!c || !out) return TN3D_E_INVALID;
   *out = nullptr;
-  Program P;
-  std::string e = build_rotated_phenom(d, T, p, P);
-  return make_net(c, e, std::move(P), out);
+  return build_net(c, [d, T](const double* q, Program& P) { return build_rotated_phenom(d, T, q, P); }, p, out);
 }
 
 tn3d_status tn3d_net_surface3d_depolarizing(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
   if (!c || !out) return TN3D_E_INVALID;
   *out = nullptr;
-  Program P;
-  std::string e = build_surface3d_depol(L, p, P);
-  return make_net(c, e, std::move(P), out);
+  return build_net(c, [L](const double* q, Program& P) { return build_surface3d_depol(L, q, P); }, p, out);
 }
 
 tn3d_status tn3d_net_surface3d_loop(tn3d_ctx c, int32_t L, const double* p, tn3d_net* out) {
   if (!c || !out) return TN3D_E_INVALID;
   *out = nullptr;
-  Program P;
-  std::string e = build_surface3d_loop(L, p, P);
-  return make_net(c, e, std::move(P), out);
+  return build_net(c, [L](const double* q, Program& P) { return build_surface3d_loop(L, q, P); }, p, out);
 }
 
 tn3d_status tn3d_net_surface3d_wht(tn3d_ctx c, int32_t L, int32_t sector, const double* p, tn3d_net* out) {
   if (!c || !out) return TN3D_E_INVALID;
   *out = nullptr;
   if (sector != TN3D_SECTOR_POINT && sector != TN3D_SECTOR_LOOP) return fail(c, TN3D_E_INVALID, "unknown sector");
-  Program P;
-  std::string e = sector == TN3D_SECTOR_POINT ? build_surface3d_point(L, p, P, true) : build_surface3d_loop(L, p, P, true);
-  return make_net(c, e, std::move(P), out);
+  return build_net(c,
+                   [L, sector](const double* q, Program& P) {
+                     return sector == TN3D_SECTOR_POINT ? build_surface3d_point(L, q, P, true)
+                                                        : build_surface3d_loop(L, q, P, true);
+                   },
+                   p, out);
 }
 
 tn3d_status tn3d_net_from_dem(tn3d_ctx c, int32_t n_det, int32_t n_mech, int64_t nnz, const int32_t* det_idx,
@@ -909,7 +930,20 @@ tn3d_status tn3d_net_from_dem(tn3d_ctx c, int32_t n_det, int32_t n_mech, int64_t
   Program P;
   std::string e = build_from_dem(n_det, n_mech, nnz, det_idx, mech_idx, p_mech, n_obs, obs, det_coord, P);
   if (e.rfind("UNSUPPORTED: ", 0) == 0) return fail(c, TN3D_E_UNSUPPORTED, e.substr(13));
-  return make_net(c, e, std::move(P), out);
+  // the builder has checked the arrays: keep copies for rebuilds at other rates
+  std::vector<int32_t> di(det_idx, det_idx + nnz), mi(mech_idx, mech_idx + nnz), dc;
+  std::vector<uint8_t> ob(obs, obs + int64_t(n_obs) * n_mech);
+  if (det_coord) dc.assign(det_coord, det_coord + int64_t(n_det) * 3);
+  auto f = [n_det, n_mech, nnz, n_obs, di, mi, ob, dc](const double* q, Program& Q) {
+    return build_from_dem(n_det, n_mech, nnz, di.data(), mi.data(), q, n_obs, ob.data(),
+                          dc.empty() ? nullptr : dc.data(), Q);
+  };
+  tn3d_status s = make_net(c, e, std::move(P), out);
+  if (s == TN3D_OK) {
+    (*out)->rebuild = f;
+    (*out)->rates.assign(p_mech, p_mech + n_mech);
+  }
+  return s;
 }
 
 int32_t tn3d_net_num_detectors(tn3d_net n) { return n ? n->P.n_det : -1; }
@@ -925,6 +959,8 @@ void tn3d_net_shape(tn3d_net n, int32_t* lx, int32_t* ly, int32_t* nl) {
 
 void tn3d_net_destroy(tn3d_net n) {
   if (!n) return;
+  for (tn3d_net v : n->variants) tn3d_net_destroy(v);
+  n->variants.clear();
   if (n->ctx) {
     tn3d_ctx c = n->ctx;
     (void)hipSetDevice(c->device);
@@ -1154,6 +1190,123 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   launch_scatter_resweep(cnt, d_items, lps, fls, lp, flags, c->stream);
   c->last_resweeps = cnt;
   return decide(c, cnt, nets, ties.data(), d_items, lp, pr->near_tie, coset, logratio, flags);
+}
+
+// Gradient of sum_s log P(m_s) with respect to the rates: the network at the
+// given rates and, per mechanism i, the same network with rate i at c_i, all
+// contracted at the caller's parameters; k_grad_* combine them.
+tn3d_status tn3d_grad_loglik(tn3d_ctx c, tn3d_net net, int32_t batch, const uint8_t* synd, const int64_t* offs,
+                             const tn3d_params* pr, int32_t n_rates, const int32_t* rate_of_mech, double* grad,
+                             double* loglik_sum, double* loglik, double* grad_items, uint32_t* flags) {
+  if (!c) return TN3D_E_INVALID;
+  c->err.clear();
+  std::string why;
+  if (!params_ok(pr, why)) return fail(c, TN3D_E_INVALID, why);
+  if (!net || net->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
+  if (!net->rebuild) return fail(c, TN3D_E_UNSUPPORTED, "network without a rate-dependent builder");
+  if (batch < 0) return fail(c, TN3D_E_INVALID, "negative batch");
+  const int n = net->P.n_mech;
+  if (n < 1) return fail(c, TN3D_E_INVALID, "network without mechanisms");
+  if (!rate_of_mech) {
+    if (n_rates != n) return fail(c, TN3D_E_INVALID, "without rate_of_mech, n_rates must be the mechanism count");
+  } else {
+    if (n_rates < 1) return fail(c, TN3D_E_INVALID, "n_rates must be positive");
+    for (int i = 0; i < n; ++i)
+      if (rate_of_mech[i] < 0 || rate_of_mech[i] >= n_rates)
+        return fail(c, TN3D_E_INVALID, "rate_of_mech entry out of [0, n_rates)");
+  }
+  if (!grad) return fail(c, TN3D_E_INVALID, "null gradient output");
+  if (batch > 0 && (!synd || !offs)) return fail(c, TN3D_E_INVALID, "null pointer");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (batch == 0) {
+    HIPCHK(c, hipMemsetAsync(grad, 0, size_t(n_rates) * 8, c->stream));
+    if (loglik_sum) HIPCHK(c, hipMemsetAsync(loglik_sum, 0, 8, c->stream));
+    return TN3D_OK;
+  }
+  // the networks at rate i = c_i, built once per network
+  if (int(net->variants.size()) != n) {
+    for (tn3d_net v : net->variants) tn3d_net_destroy(v);
+    net->variants.clear();
+    net->var_c.assign(n, 0.0);
+    std::vector<double> q = net->rates;
+    for (int i = 0; i < n; ++i) {
+      const double ci = net->rates[i] <= 0.5 ? 1.0 : 0.0;
+      q[i] = ci;
+      Program P;
+      std::string e = net->rebuild(q.data(), P);
+      q[i] = net->rates[i];
+      tn3d_net v = nullptr;
+      tn3d_status s = make_net(c, e, std::move(P), &v);
+      if (s != TN3D_OK) {
+        for (tn3d_net w : net->variants) tn3d_net_destroy(w);
+        net->variants.clear();
+        return s;
+      }
+      v->tune_serial = net->serial;
+      net->variants.push_back(v);
+      net->var_c[i] = ci;
+    }
+  }
+  // scratch: tiled offsets, log p and flags of the (n + 1) blocks, the rates
+  // (c_i, p_i), the rate -> mechanism lists, the per-item derivatives
+  const size_t B = size_t(batch), nb = size_t(n) + 1;
+  const size_t o_offs = 0, o_lp = align256(nb * B * 8), o_fl = o_lp + align256(nb * B * 32),
+               o_cp = o_fl + align256(nb * B * 4), o_ptr = o_cp + align256(size_t(n) * 16),
+               o_rm = o_ptr + align256((size_t(n_rates) + 1) * 4), o_term = o_rm + align256(size_t(n) * 4),
+               need = o_term + (grad_items ? 0 : align256(B * n * 8));
+  if (c->gaux_bytes < need) {
+    if (c->gaux) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->gaux);
+      c->gaux = nullptr;
+      c->gaux_bytes = 0;
+    }
+    if (hipMalloc(&c->gaux, need) != hipSuccess) return fail(c, TN3D_E_OOM, "gradient scratch");
+    c->gaux_bytes = need;
+  }
+  int64_t* offs_all = reinterpret_cast<int64_t*>(c->gaux + o_offs);
+  double* lp = reinterpret_cast<double*>(c->gaux + o_lp);
+  uint32_t* fl = reinterpret_cast<uint32_t*>(c->gaux + o_fl);
+  double* cp = reinterpret_cast<double*>(c->gaux + o_cp);
+  int32_t* ptr = reinterpret_cast<int32_t*>(c->gaux + o_ptr);
+  int32_t* rm = reinterpret_cast<int32_t*>(c->gaux + o_rm);
+  double* term = grad_items ? grad_items : reinterpret_cast<double*>(c->gaux + o_term);
+  std::vector<double> hcp(2 * size_t(n));
+  for (int i = 0; i < n; ++i) {
+    hcp[2 * i] = net->var_c[i];
+    hcp[2 * i + 1] = net->rates[i];
+  }
+  std::vector<int32_t> hptr(size_t(n_rates) + 1, 0), hrm(n);
+  for (int i = 0; i < n; ++i) hptr[(rate_of_mech ? rate_of_mech[i] : i) + 1]++;
+  for (int k = 0; k < n_rates; ++k) hptr[k + 1] += hptr[k];
+  {
+    std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
+    for (int i = 0; i < n; ++i) hrm[fill[rate_of_mech ? rate_of_mech[i] : i]++] = i;
+  }
+  HIPCHK(c, hipMemcpyAsync(cp, hcp.data(), hcp.size() * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ptr, hptr.data(), hptr.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(rm, hrm.data(), hrm.size() * 4, hipMemcpyHostToDevice, c->stream));
+  launch_tile_offsets(batch, int(nb), offs, offs_all, c->stream);
+  HIPCHK(c, hipGetLastError());
+  // block 0 as an ordinary contraction (captured graphs when enabled); the
+  // n networks of single-rate changes eagerly, one batched pass each
+  std::vector<int32_t> items(B);
+  tn3d_status s = TN3D_OK;
+  const bool graphs = c->graphs;
+  for (size_t v = 0; v < nb && s == TN3D_OK; ++v) {
+    for (size_t j = 0; j < B; ++j) items[j] = int32_t(v * B + j);
+    c->graphs = graphs && v == 0;
+    s = run_group(c, v == 0 ? net : net->variants[v - 1], items, synd, offs_all, *pr, lp, fl, pr->precision, false);
+  }
+  c->graphs = graphs;
+  if (s == TN3D_OK) {
+    launch_grad(batch, n, net->P.n_cosets, n_rates, lp, fl, cp, ptr, rm, term, grad, loglik, loglik_sum, flags,
+                c->stream);
+    if (hipGetLastError() != hipSuccess) s = fail(c, TN3D_E_DEVICE, "gradient kernels");
+  }
+  // the host arrays above were copied asynchronously
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return s;
 }
 
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {

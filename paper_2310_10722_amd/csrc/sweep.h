@@ -162,4 +162,14 @@ void launch_scatter_resweep(int n, const int32_t* items, const double* logp_sub,
 void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,
                    int32_t* coset, double* logratio, uint32_t* flags, hipStream_t st);
 
+// Gradient of log P(m) (k_grad_terms, k_grad_items, k_grad_reduce): lp and
+// fl hold (n + 1) blocks of B items (block 0 at the given rates, block i + 1
+// with rate i at cp[2 i]); cp[2 i + 1] = p_i; rate k sums the mechanisms
+// rm[ptr[k] .. ptr[k + 1]).  term: [B][n] per-item derivatives; loglik
+// ([B]), total (the sum of loglik) and flags nullable.
+void launch_grad(int B, int n, int nc, int n_rates, const double* lp, const uint32_t* fl, const double* cp,
+                 const int32_t* ptr, const int32_t* rm, double* term, double* grad, double* loglik, double* total,
+                 uint32_t* flags, hipStream_t st);
+void launch_tile_offsets(int B, int n_blocks, const int64_t* offs, int64_t* offs_all, hipStream_t st);
+
 }  // namespace tn3d

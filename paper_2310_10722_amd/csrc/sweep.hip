@@ -2198,13 +2198,20 @@ __global__ void k_decode(int n_items, int n_cosets, const int32_t* items, const 
   if (i >= n_items) return;
   const int it = items[i];
   const double* lp = logp + int64_t(it) * 4;
-  int best = 0;
-  for (int c = 1; c < n_cosets; ++c)
-    if (lp[c] > lp[best]) best = c;
-  double other = -INFINITY;
+  // a NaN (a value the contraction found non-positive) ranks below every
+  // number; with every coset NaN the decision is coset 0 and the log-ratio NaN
+  int best = -1;
   for (int c = 0; c < n_cosets; ++c)
-    if (c != best && lp[c] > other) other = lp[c];
-  const double lr = lp[best] - other;
+    if (!isnan(lp[c]) && (best < 0 || lp[c] > lp[best])) best = c;
+  double lr = __longlong_as_double(0x7ff8000000000000LL);
+  if (best < 0) {
+    best = 0;
+  } else {
+    double other = -INFINITY;
+    for (int c = 0; c < n_cosets; ++c)
+      if (c != best && lp[c] > other) other = lp[c];
+    lr = lp[best] - other;
+  }
   if (coset) coset[it] = best;
   if (logratio) logratio[it] = lr;
   if (flags && !(lr >= near_tie)) flags[it] |= 4u;
@@ -2232,6 +2239,104 @@ __global__ void k_scatter_resweep(int n, const int32_t* items, const double* log
   const int it = items[i];
   for (int c = 0; c < 4; ++c) logp[int64_t(it) * 4 + c] = logp_sub[int64_t(i) * 4 + c];
   if (flags) flags[it] = flags_sub[i] | 16u;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of the syndrome log-likelihood with respect to the rates (the
+// Sec. 2.4 definition of p_{m,L}).  P(m) = sum_L p_{m,L} is affine in every
+// rate p_i, since each mechanism enters every term of the sum once, as p_i
+// or as 1 - p_i.  With P_c(m) the value at p_i = c (c = 0 or 1),
+//   d log P(m) / d p_i = (P_c(m) / P(m) - 1) / (c - p_i).
+// The rows of lp come in blocks of B items: block 0 holds the network at the
+// given rates, block i + 1 the network with rate i set to c_i (the end of
+// [0, 1] farther from p_i, so |c_i - p_i| >= 1/2).
+
+// log sum_c exp(r[c]) over the coset columns.  A NaN column (a value the
+// contraction found non-positive) makes the result NaN, or, with nan_zero,
+// counts as zero.
+__device__ double lse_cosets(const double* r, int nc, bool nan_zero = false) {
+  double m = -INFINITY;
+  bool nan = false;
+  for (int c = 0; c < nc; ++c) {
+    if (isnan(r[c])) nan = true;
+    if (r[c] > m) m = r[c];
+  }
+  if (nan && !nan_zero) return NAN;
+  if (m == -INFINITY) return m;
+  double s = 0.0;
+  for (int c = 0; c < nc; ++c)
+    if (!isnan(r[c])) s += exp(r[c] - m);
+  return m + log(s);
+}
+
+// term[s][i] = d log P(m_s) / d p_i for every item s < B and mechanism i < n.
+// cp[2 i] = c_i, cp[2 i + 1] = p_i.  P at p_i = c_i is often exactly zero (no
+// error pattern with x_i = c_i explains the syndrome); the contraction
+// returns it as a rounding of zero, NaN where that rounding is not positive,
+// and such a coset counts as zero: exact up to the contraction's own error.
+__global__ void k_grad_terms(int B, int n, int nc, const double* lp, const double* cp, double* term) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(B) * n) return;
+  const int s = int(idx / n), i = int(idx % n);
+  const double base = lse_cosets(lp + int64_t(s) * 4, nc);
+  const double var = lse_cosets(lp + (int64_t(i + 1) * B + s) * 4, nc, true);
+  term[idx] = expm1(var - base) / (cp[2 * i] - cp[2 * i + 1]);
+}
+
+// loglik[s] = log P(m_s) at the given rates (nullable); flags[s] = the OR of
+// the flags of item s's n + 1 contractions (nullable).
+__global__ void k_grad_items(int B, int n, int nc, const double* lp, const uint32_t* fl, double* loglik,
+                             uint32_t* flags) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  if (loglik) loglik[s] = lse_cosets(lp + int64_t(s) * 4, nc);
+  if (flags) {
+    uint32_t f = 0;
+    for (int v = 0; v <= n; ++v) f |= fl[int64_t(v) * B + s];
+    flags[s] = f;
+  }
+}
+
+// grad[k] = sum over items s and the mechanisms i of rate k (rm[ptr[k] ..
+// ptr[k + 1])) of term[s][i]: one workgroup of 256 per rate, a fixed
+// summation order (strided partial sums, then a tree in LDS).
+__global__ void __launch_bounds__(256) k_grad_reduce(int B, int n, const double* term, const int32_t* ptr,
+                                                     const int32_t* rm, double* grad) {
+  __shared__ double part[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const int j0 = ptr[k], cnt = ptr[k + 1] - j0;
+  const int64_t tot = int64_t(B) * cnt;
+  double acc = 0.0;
+  for (int64_t j = t; j < tot; j += 256) acc += term[(j / cnt) * n + rm[j0 + j % cnt]];
+  part[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  if (t == 0) grad[k] = part[0];
+}
+
+// total[0] = sum over items of log P(m_s) at the given rates (one workgroup,
+// a fixed summation order).
+__global__ void __launch_bounds__(256) k_grad_total(int B, int nc, const double* lp, double* total) {
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int s = t; s < B; s += 256) acc += lse_cosets(lp + int64_t(s) * 4, nc);
+  part[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  if (t == 0) total[0] = part[0];
+}
+
+// offs_all[v B + s] = offs[s] for the n_blocks blocks of B items.
+__global__ void k_tile_offsets(int B, int n_blocks, const int64_t* offs, int64_t* offs_all) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < int64_t(B) * n_blocks) offs_all[idx] = offs[idx % B];
 }
 
 // Device wall-clock stamp, for timing that also works inside a captured graph
@@ -2636,6 +2741,22 @@ void launch_decode(int n_items, int n_cosets, const int32_t* items, const double
                    int32_t* coset, double* logratio, uint32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_decode, dim3((n_items + 63) / 64), dim3(64), 0, st, n_items, n_cosets, items, logp,
                      near_tie, coset, logratio, flags);
+}
+
+void launch_grad(int B, int n, int nc, int n_rates, const double* lp, const uint32_t* fl, const double* cp,
+                 const int32_t* ptr, const int32_t* rm, double* term, double* grad, double* loglik, double* total,
+                 uint32_t* flags, hipStream_t st) {
+  const int64_t tot = int64_t(B) * n;
+  hipLaunchKernelGGL(k_grad_terms, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, B, n, nc, lp, cp, term);
+  hipLaunchKernelGGL(k_grad_items, dim3((B + 255) / 256), dim3(256), 0, st, B, n, nc, lp, fl, loglik, flags);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(n_rates), dim3(256), 0, st, B, n, term, ptr, rm, grad);
+  if (total) hipLaunchKernelGGL(k_grad_total, dim3(1), dim3(256), 0, st, B, nc, lp, total);
+}
+
+void launch_tile_offsets(int B, int n_blocks, const int64_t* offs, int64_t* offs_all, hipStream_t st) {
+  const int64_t tot = int64_t(B) * n_blocks;
+  hipLaunchKernelGGL(k_tile_offsets, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, B, n_blocks, offs,
+                     offs_all);
 }
 
 }  // namespace tn3d

@@ -39,7 +39,7 @@ SYMBOLS = [
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
     "tn3d_last_timing", "tn3d_last_stats", "tn3d_autotune",
-    "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached",
+    "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached", "tn3d_grad_loglik",
 ]
 
 
@@ -114,6 +114,9 @@ def load_library(path: str | None = None):
     lib.tn3d_autotune.argtypes = [c_p, i32, ctypes.POINTER(c_p), c_p, c_p, ctypes.POINTER(Params),
                                   ctypes.POINTER(f64), i32]
     lib.tn3d_autotune.restype = i32
+    lib.tn3d_grad_loglik.argtypes = [c_p, c_p, i32, c_p, c_p, ctypes.POINTER(Params), i32, c_p, c_p, c_p, c_p, c_p,
+                                     c_p]
+    lib.tn3d_grad_loglik.restype = i32
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
               "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_from_dem", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
@@ -380,6 +383,77 @@ def tn3d_decode(ctx: Context, nets, syndromes, params: Params):
                              ctypes.c_void_p(flags.data_ptr()))
     _check(ctx.lib, ctx.h, st)
     return coset, lr, logp, flags
+
+
+def tn3d_grad_loglik(ctx: Context, net: Net, syndromes, params: Params, rate_of_mech=None, n_rates=None,
+                     per_item=False):
+    """Gradient of sum_s log P(m_s) with respect to the rates (one network for
+    the whole batch).  rate_of_mech: optional int array [n_mech] mapping each
+    builder rate to one of n_rates parameters.  Returns (grad float64
+    [n_rates], loglik_sum float64 [1], loglik float64 [B], flags int32 [B],
+    grad_items float64 [B, n_mech] or None) as CUDA tensors."""
+    import torch
+    if not isinstance(net, Net):
+        raise ValueError("one network for the batch")
+    _, syn, offs, _, B = _batch_args(net, syndromes)
+    dev = syn.device
+    if rate_of_mech is None:
+        n_rates = net.n_mech if n_rates is None else int(n_rates)
+        rmap = None
+    else:
+        rmap = np.ascontiguousarray(np.asarray(rate_of_mech, dtype=np.int32)).reshape(-1)
+        if rmap.size != net.n_mech:
+            raise ValueError(f"rate_of_mech needs {net.n_mech} entries, got {rmap.size}")
+        n_rates = int(rmap.max()) + 1 if n_rates is None else int(n_rates)
+    grad = torch.empty((max(n_rates, 1),), dtype=torch.float64, device=dev)[:n_rates]
+    total = torch.empty((1,), dtype=torch.float64, device=dev)
+    loglik = torch.empty((B,), dtype=torch.float64, device=dev)
+    flags = torch.zeros((B,), dtype=torch.int32, device=dev)
+    items = torch.empty((B, net.n_mech), dtype=torch.float64, device=dev) if per_item else None
+    st = ctx.lib.tn3d_grad_loglik(
+        ctx.h, net.h, B, ctypes.c_void_p(syn.data_ptr()), ctypes.c_void_p(offs.data_ptr()), ctypes.byref(params),
+        n_rates, None if rmap is None else rmap.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(grad.data_ptr()),
+        ctypes.c_void_p(total.data_ptr()), ctypes.c_void_p(loglik.data_ptr()),
+        None if items is None else ctypes.c_void_p(items.data_ptr()), ctypes.c_void_p(flags.data_ptr()))
+    _check(ctx.lib, ctx.h, st)
+    return grad, total, loglik, flags, items
+
+
+def _autograd_function():
+    import torch
+
+    class LogLikelihood(torch.autograd.Function):
+        """sum_s log P(m_s) as a function of the rate parameters; the
+        gradient comes from tn3d_grad_loglik."""
+
+        @staticmethod
+        def forward(fctx, rates, ctx, build, syndromes, params, rate_of_mech):
+            r = rates.detach().to("cpu", torch.float64).numpy()
+            p_mech = r if rate_of_mech is None else r[np.asarray(rate_of_mech)]
+            net = build(ctx, p_mech)
+            try:
+                grad, total, _, _, _ = tn3d_grad_loglik(ctx, net, syndromes, params, rate_of_mech, r.size)
+            finally:
+                net.close()
+            fctx.save_for_backward(grad)
+            return total.reshape(()).to(rates.device, rates.dtype)
+
+        @staticmethod
+        def backward(fctx, g_out):
+            (grad,) = fctx.saved_tensors
+            return (g_out.to(grad.device, grad.dtype) * grad).to(g_out.device, g_out.dtype), \
+                None, None, None, None, None
+
+    return LogLikelihood
+
+
+def log_likelihood(ctx: Context, build, rates, syndromes, params: Params, rate_of_mech=None):
+    """Differentiable sum_s log P(m_s): `rates` a float64 tensor of rate
+    parameters, build(ctx, p_mech) -> Net a family builder at per-mechanism
+    rates p_mech = rates[rate_of_mech] (or rates itself), syndromes a uint8
+    CUDA tensor [B, n_det].  backward() fills rates.grad through
+    tn3d_grad_loglik."""
+    return _autograd_function().apply(rates, ctx, build, syndromes, params, rate_of_mech)
 
 
 # short aliases

@@ -9,7 +9,7 @@ At this size the layer bonds reach 32 (site tensors of 2 * 32^4 entries) and
 the boundary-MPS families reach 32 * 32 = 1024 vectors.  Calls only oracle/
 and synth/.  About a minute per coset on one core; run from the repository
 root:
-    python tests/golden/make_point_L8_chi32.py
+    python tests/golden/make_loop_L8_chi32.py
 """
 
 import json

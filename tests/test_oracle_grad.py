@@ -8,7 +8,9 @@ import pytest
 import synth
 from oracle.exact import frontier_logprobs
 from oracle.grad import (batch_loglik_grad_exact, central_difference, loglik_exact, loglik_grad_exact,
-                         reduce_to_rates)
+                         loglik_grad_one_sided, reduce_to_rates)
+from oracle.network import rotated_network
+from oracle.sweep import sweep_logprob
 
 
 def _marginal_grad_brute(H, p, m):
@@ -101,3 +103,36 @@ def test_frontier_handles_certain_mechanisms():
         sel = (X @ dem.obs[0].astype(int)) % 2 == L
         ref = w[sel].sum()
         assert (np.exp(lp[L]) if ref > 0 else 0.0) == pytest.approx(ref, rel=1e-12, abs=0)
+
+
+def test_one_sided_form_equals_brute_force_marginals():
+    # Rates on both sides of 1/2, so both choices of c_i are used; the exact
+    # frontier contraction as the evaluator; enumerated posterior marginals
+    # (an independent computation) as the reference.
+    dem = synth.rotated_phenom(3, 1, 0.05, 0.05)
+    dem = dem.with_p(np.random.default_rng(11).uniform(0.02, 0.9, dem.n_mech))
+    assert dem.n_mech <= 16
+    m, _ = synth.sample_syndromes(dem, 4, 12)
+    for k in range(4):
+        lp, g = loglik_grad_one_sided(lambda q: frontier_logprobs(dem.H, q, dem.obs, m[k]), dem.p)
+        lb, gb = _marginal_grad_brute(dem.H, dem.p, m[k])
+        assert lp == pytest.approx(lb, abs=1e-12)
+        np.testing.assert_allclose(g, gb, rtol=1e-10, atol=1e-10)
+
+
+def test_one_sided_form_with_the_sweep_at_untruncated_chi():
+    # With the fixed-chi sweep as the evaluator at a chi that truncates
+    # nothing, the gradient is the exact one (two-sided form, O-2).
+    d, T = 3, 2
+    dem = synth.rotated_phenom(d, T, 0.05, 0.05)
+    dem = dem.with_p(np.random.default_rng(5).uniform(0.02, 0.3, dem.n_mech))
+    m, _ = synth.sample_syndromes(dem, 2, 6)
+    idx = [0, 7, 13, dem.n_mech - 1]
+    for k in range(2):
+        def cosets(q):
+            return [sweep_logprob(rotated_network(d, T, dem.params["checks"], q, m[k], c), 16, 16, 1e-12,
+                                  1e-9)[0] for c in (0, 1)]
+        lp, g = loglik_grad_one_sided(cosets, dem.p, idx)
+        le, ge = loglik_grad_exact(dem.H, dem.p, dem.obs, m[k])
+        assert lp == pytest.approx(le, abs=1e-9)
+        np.testing.assert_allclose(g, ge[idx], rtol=1e-8, atol=1e-8)
