@@ -438,7 +438,7 @@ def bench_rotated_d7_grad(a, tn3d, np, torch):
         jobs = [(d, T, dem.params["checks"], dem.p, m[k], prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap)]
         for i in range(dem.n_mech):
             q = dem.p.copy()
-            q[i] = 1.0 if dem.p[i] <= 0.5 else 0.0
+            q[i] = dem.p[i] + 0.25 if dem.p[i] <= 0.5 else dem.p[i] - 0.25  # the oracle's changed rate
             jobs.append((d, T, dem.params["checks"], q, m[k], prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap))
         for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
             os.environ[v] = "1"
@@ -458,7 +458,7 @@ def bench_rotated_d7_grad(a, tn3d, np, torch):
             return table[int(ch[0]) if ch.size else -1]
 
         lp, g = loglik_grad_one_sided(cosets, dem.p)
-        c = np.where(dem.p <= 0.5, 1.0, 0.0)
+        c = np.where(dem.p <= 0.5, dem.p + 0.25, dem.p - 0.25)
         bound = (np.abs(1.0 + g * (c - dem.p)) + 1.0) * np.expm1(2.0 * (1e-3 + 4.0 * 2.0 ** -24)) / np.abs(c - dem.p)
         err = np.abs(items[k] - g)
         out["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "syndromes/s", "cores": CPU_WORKERS, "kind": "oracle",

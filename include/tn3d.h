@@ -298,12 +298,15 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
 /* Gradient of the syndrome log-likelihood with respect to the rates (the
  * Sec. 2.4 definition of p_{m,L}; used to fit a noise model to syndrome
  * data).  P(m) = sum_L p_{m,L} is affine in each mechanism's rate p_i (every
- * term of the sum holds p_i or 1 - p_i once), so with P_c(m) the value at
- * p_i = c,  d log P(m) / d p_i = (P_c(m) / P(m) - 1) / (c - p_i)  for c = 0
- * or 1.  The library contracts `net` at its rates and, per mechanism i, the
- * same network rebuilt with p_i = c_i (1 if p_i <= 1/2, else 0), every
- * contraction at params' chi, chi_mps, precision and rank rule (no near-tie
- * re-sweep): batch * (n_mech + 1) contractions.  Each P is the fixed-chi
+ * term of the sum holds p_i or 1 - p_i once), so for any c != p_i,
+ * d log P(m) / d p_i = (P_c(m) / P(m) - 1) / (c - p_i) with P_c(m) the value
+ * at p_i = c.  The library takes c_i a quarter of the rate range [0, r_max]
+ * away from p_i, towards its middle (r_max = 1, or 3/4 for the depolarizing
+ * family), where no term of the network vanishes, and contracts `net` at its
+ * rates and, per mechanism i, at p_i = c_i, every contraction at params' chi,
+ * chi_mps, precision and rank rule (no near-tie re-sweep): batch *
+ * (n_mech + 1) contractions, those of networks with the original's structure
+ * (the usual case) in one batched pass.  Each P is the fixed-chi
  * approximation, so the result is the exact gradient where chi truncates
  * nothing and otherwise carries the truncation error of the contractions
  * (it is not the derivative of the truncated contraction itself).
@@ -315,15 +318,15 @@ tn3d_status tn3d_decode(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets,
  * Syndromes as in tn3d_contract_cosets (batch items, device offsets).
  * Optional outputs (device, nullable): loglik_sum_dev[1] = sum_s log P(m_s),
  * loglik_dev[batch] = log P(m_s), grad_items_dev[batch][n_mech] the
- * per-item derivatives d log P(m_s) / d p_i, flags_dev[batch]
- * the OR of the flags of an item's contractions.  P at p_i = c_i is often
- * exactly zero (no error pattern with x_i = c_i explains the syndrome): a
- * coset of such a changed network that the contraction finds non-positive
- * (NaN, NUMERIC in the item's flags) counts as zero, which is exact up to
- * the contraction's own error.  A NaN log p at the given rates, or an
- * impossible syndrome (log P = -inf), makes the gradient NaN.  The
- * networks at the changed rates are built on the first call and kept with
- * `net` (released by tn3d_net_destroy).  Synchronises the context stream.
+ * per-item derivatives d log P(m_s) / d p_i, flags_dev[batch] the OR of the
+ * flags of an item's contractions.  A coset that a contraction finds
+ * non-positive (NaN, NUMERIC in the item's flags) counts as zero (its value
+ * is below the contraction's error); an item whose cosets at the given rates
+ * are all NaN, or whose syndrome is impossible (log P = -inf), makes the
+ * gradient NaN.  The changed networks are built on the first call and kept with `net`
+ * (released by tn3d_net_destroy); the pass allocates workspace like
+ * tn3d_contract_cosets over batch * (n_mech + 1) items and launches eagerly.
+ * Synchronises the context stream.
  * Errors: TN3D_E_INVALID (bad handles, params, map entries out of range),
  * TN3D_E_UNSUPPORTED (as tn3d_contract_cosets), TN3D_E_OOM, TN3D_E_DEVICE. */
 tn3d_status tn3d_grad_loglik(tn3d_ctx ctx, tn3d_net net, int32_t batch, const uint8_t* syndromes_dev,

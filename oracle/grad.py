@@ -26,9 +26,10 @@ codes (the marginal form above, enumerated independently), central finite
 differences of O-2, and a two-mechanism closed form.
 
 loglik_grad_one_sided evaluates the same derivative from one changed rate
-per mechanism, with any evaluator of the coset values (pinned to the
-two-sided exact form above; with the fixed-chi sweep it is the gradient the
-library computes at equal chi).
+per mechanism (a quarter of the admissible range away), with any evaluator
+of the coset values (pinned to brute-force marginals and to the exact form
+above; with the fixed-chi sweep it is the gradient the library computes at
+equal chi).
 
 Also here: central finite differences of the fixed-chi sweep (O-3), the
 derivative of the *approximate* value that a reverse pass of the sweep
@@ -72,29 +73,33 @@ def loglik_grad_exact(H, p, obs, m, order=None):
     return lp, g
 
 
-def loglik_grad_one_sided(cosets_logp, p, indices=None):
+def loglik_grad_one_sided(cosets_logp, p, indices=None, rate_max=1.0):
     """The same derivative from one changed rate per mechanism, for any
     evaluator cosets_logp(rates) -> log p_{m,L} over the cosets (the exact
     contraction, or the fixed-chi sweep O-3 at a given chi and rank rule).
-    With c_i = 1 if p_i <= 1/2 else 0, P = (1 - p_i) P(p_i = 0) + p_i P(p_i = 1)
-    gives P(p_i = c_i) - P = (c_i - p_i) (P(p_i = 1) - P(p_i = 0)), so
+    P is affine in p_i, so for any c_i != p_i
 
         d log P / d p_i = (P(p_i = c_i) / P - 1) / (c_i - p_i).
 
-    P(p_i = c_i) is often exactly zero (no error pattern with x_i = c_i
-    explains the syndrome).  An approximate evaluator returns that value as
-    some rounding of zero, and a non-positive one as NaN: such a coset of a
-    changed network is taken as zero, which is exact up to the evaluator's
-    own error (a value it cannot tell from zero is below that error).  A NaN
-    at the given rates stays NaN.
+    c_i steps a quarter of the admissible range [0, rate_max] away from p_i,
+    towards its middle: c_i = p_i + rate_max / 4 if p_i <= rate_max / 2, else
+    p_i - rate_max / 4.  Inside the range no term of a network vanishes that
+    did not vanish at p_i, and P(p_i = c_i) > 0 whenever P > 0.
+
+    An approximate evaluator returns a value it finds non-positive as NaN;
+    such a coset counts as zero (its value is below the evaluator's own
+    error).  If every coset is NaN, P at the given rates is NaN (and so the
+    derivatives); a changed network's P is then zero.
 
     Returns (log P, the derivatives for `indices`, default every mechanism)."""
     p = np.asarray(p, dtype=np.float64)
-    lp = _logsumexp(cosets_logp(p))
+    l0 = np.asarray(cosets_logp(p), dtype=np.float64)
+    lp = np.nan if np.all(np.isnan(l0)) else _logsumexp(np.where(np.isnan(l0), -np.inf, l0))
     idx = list(range(p.size)) if indices is None else list(indices)
+    h = 0.25 * rate_max
     g = np.empty(len(idx))
     for k, i in enumerate(idx):
-        ci = 1.0 if p[i] <= 0.5 else 0.0
+        ci = p[i] + h if p[i] <= 0.5 * rate_max else p[i] - h
         q = p.copy()
         q[i] = ci
         lq = np.asarray(cosets_logp(q), dtype=np.float64)

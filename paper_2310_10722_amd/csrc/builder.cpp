@@ -805,6 +805,7 @@ std::string build_surface3d_depol(int32_t L, const double* p, Program& P) {
   P.n_det = nv + nf;
   P.n_mech = n;
   P.n_cosets = 4;
+  P.rate_max = 0.75;
   set_face_ext(P, FM, nv);
 
   auto W = [&](int e, int u, int v) { return (u == 0 && v == 0) ? 1.0 - p[e] : p[e] / 3.0; };

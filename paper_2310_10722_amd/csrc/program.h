@@ -84,6 +84,8 @@ struct Program {
   // Walsh-Hadamard form: the two "cosets" are the signed networks Z_0, Z_1
   // (their values may be negative) and log p_{m,L} = log((Z_0 + (-1)^L Z_1)/2).
   int32_t wht = 0;
+  // every rate of the builder lies in [0, rate_max] (3/4 for depolarizing noise)
+  double rate_max = 1.0;
 };
 
 // Builders; return an empty string on success, else an error message.

@@ -116,9 +116,13 @@ struct tn3d_net_s {
   // the builder call that made P, for networks at other rates (gradients)
   std::function<std::string(const double*, Program&)> rebuild;
   std::vector<double> rates;  // the builder's rate array (P.n_mech entries)
-  // tn3d_grad_loglik: per mechanism i, this network with rate i at var_c[i]
-  std::vector<tn3d_net> variants;
+  // tn3d_grad_loglik: per mechanism i, this network with rate i at var_c[i],
+  // as pool copy var_slot[i] of d_pool_all (copy 0 is this network's pool)
+  // when the structure is the same, else as a network of its own variants[i]
   std::vector<double> var_c;
+  std::vector<int32_t> var_slot;
+  std::vector<tn3d_net> variants;
+  double* d_pool_all = nullptr;
 };
 
 namespace {
@@ -329,9 +333,18 @@ tn3d_status ensure_ws(tn3d_ctx c, size_t bytes) {
 // Contracts items[0..n_items) (global item indices, all using net `n`).
 // noalloc: the workspace is the device's static scratch array (no device
 // allocation, eager launches: graph instantiation allocates).
+// pools: null, or copies of the network's pool of equal layout (the same
+// network at other rates) with the copy each global item reads; then the
+// launches are eager.
+struct PoolSel {
+  const double* pool;   // device, copies of stride doubles
+  int64_t stride;
+  const int32_t* psel;  // device, per global item
+};
+
 tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items, const uint8_t* synd,
                       const int64_t* synd_off, const tn3d_params& pr, double* logp, uint32_t* flags_out,
-                      int prec, bool noalloc) {
+                      int prec, bool noalloc, const PoolSel* pools = nullptr) {
   const Program& P = n->P;
   const int nc = P.n_cosets;
   const int max_g = std::max(1, n->max_gates_class);
@@ -429,6 +442,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_gsynd = cv.take<uint8_t>(chunk_items * bstride);
   size_t o_glp = cv.take<double>(chunk_items * 4);
   size_t o_gfl = cv.take<uint32_t>(chunk_items);
+  size_t o_gpsel = cv.take<int32_t>(pools ? chunk_items : 1);
   char* ws = nullptr;
   if (noalloc) {
     if (!c->scratch || cv.off > NOALLOC_BYTES) return fail(c, TN3D_E_OOM, "static scratch unavailable or too small");
@@ -481,7 +495,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     A.logs = reinterpret_cast<double*>(ws + o_logs);
     A.flags = reinterpret_cast<uint32_t*>(ws + o_flags);
     A.leg_bond = n->d_leg_bond;
-    A.pool = n->d_pool;
+    A.pool = pools ? pools->pool : n->d_pool;
+    A.pool_stride = pools ? pools->stride : 0;
+    A.psel = pools ? pools->psel : nullptr;  // indexed by global item (direct launches)
     A.eps = pr.eps_rel;
     A.tau = pr.tau_gap;
     A.pchol_tol = prec == TN3D_PREC_FP64 ? 1e-15 : 1e-14;
@@ -621,7 +637,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       launch_gather_synd(ni, d_items, synd, synd_off, P.n_det, bstride, g_synd, s);
       launch_ext_bits(ni, g_synd, bstride, P.n_det, P.ext_src0, P.ext_src_n, P.ext_words, n->d_ext, P.n_ext, s);
     };
-    if (c->graphs && !noalloc) {
+    if (c->graphs && !noalloc && !pools) {
       // inputs into the workspace, replay (capturing first if needed), results out
       gather_inputs();
       HIPCHK(c, hipGetLastError());
@@ -670,6 +686,12 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (!done && P.n_ext > 0) {
       // the derived bits live in the workspace copy of the inputs
       gather_inputs();
+      if (pools) {
+        // the kernels index items locally here: the pool choices follow
+        int32_t* g_psel = reinterpret_cast<int32_t*>(ws + o_gpsel);
+        launch_gather_i32(ni, d_items, pools->psel, g_psel, s);
+        A.psel = g_psel;
+      }
       launch_seq(ni, g_items, g_soff, bstride, s);
       tn3d_status es = enqueue(g_items, g_synd, g_soff, g_lp, g_fl, s);
       if (es != TN3D_OK) return es;
@@ -865,7 +887,9 @@ void tn3d_ctx_destroy(tn3d_ctx c) {
   if (!c->nets.empty()) (void)hipStreamSynchronize(c->stream);
   for (tn3d_net n : c->nets) {
     if (n->dev) (void)hipFree(n->dev);
+    if (n->d_pool_all) (void)hipFree(n->d_pool_all);
     n->dev = nullptr;
+    n->d_pool_all = nullptr;
     n->ctx = nullptr;
   }
   c->nets.clear();
@@ -957,10 +981,11 @@ void tn3d_net_shape(tn3d_net n, int32_t* lx, int32_t* ly, int32_t* nl) {
   if (nl) *nl = int32_t(n->P.layers.size());
 }
 
+static void drop_variants(tn3d_net net);
+
 void tn3d_net_destroy(tn3d_net n) {
   if (!n) return;
-  for (tn3d_net v : n->variants) tn3d_net_destroy(v);
-  n->variants.clear();
+  drop_variants(n);
   if (n->ctx) {
     tn3d_ctx c = n->ctx;
     (void)hipSetDevice(c->device);
@@ -1192,9 +1217,43 @@ tn3d_status tn3d_decode(tn3d_ctx c, int32_t batch, const tn3d_net* nets, const u
   return decide(c, cnt, nets, ties.data(), d_items, lp, pr->near_tie, coset, logratio, flags);
 }
 
+// True when two programs differ at most in their pool values (then one
+// launch sequence serves both, each sweep reading its own pool copy).
+static bool same_structure(const Program& a, const Program& b) {
+  auto eqb = [](const auto& x, const auto& y) {
+    return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), x.size() * sizeof(x[0])) == 0);
+  };
+  return a.Lx == b.Lx && a.Ly == b.Ly && a.n_det == b.n_det && a.n_mech == b.n_mech && a.n_cosets == b.n_cosets &&
+         a.n_bonds_h == b.n_bonds_h && a.n_bonds == b.n_bonds && a.max_K == b.max_K && a.max_dgate == b.max_dgate &&
+         a.n_ext == b.n_ext && a.ext_src0 == b.ext_src0 && a.ext_src_n == b.ext_src_n && a.ext_words == b.ext_words &&
+         a.inc0 == b.inc0 && a.n_inc == b.n_inc && a.wht == b.wht && a.pool.size() == b.pool.size() &&
+         eqb(a.leg_bond, b.leg_bond) && eqb(a.dmax, b.dmax) && eqb(a.init_dims, b.init_dims) &&
+         eqb(a.init_off, b.init_off) && eqb(a.bond_dim0, b.bond_dim0) && eqb(a.ones, b.ones) && eqb(a.gates, b.gates) &&
+         eqb(a.layers, b.layers) && eqb(a.d_after, b.d_after) && eqb(a.par_after, b.par_after) &&
+         eqb(a.d_final, b.d_final) && eqb(a.f_off, b.f_off) && eqb(a.ext_rows, b.ext_rows);
+}
+
+// Releases the networks at changed rates of a network.
+static void drop_variants(tn3d_net net) {
+  for (tn3d_net v : net->variants)
+    if (v) tn3d_net_destroy(v);
+  net->variants.clear();
+  net->var_c.clear();
+  net->var_slot.clear();
+  if (net->d_pool_all && net->ctx) {
+    (void)hipSetDevice(net->ctx->device);
+    (void)hipStreamSynchronize(net->ctx->stream);
+    (void)hipFree(net->d_pool_all);
+  }
+  net->d_pool_all = nullptr;
+}
+
 // Gradient of sum_s log P(m_s) with respect to the rates: the network at the
 // given rates and, per mechanism i, the same network with rate i at c_i, all
-// contracted at the caller's parameters; k_grad_* combine them.
+// contracted at the caller's parameters; k_grad_* combine them.  Changed
+// networks of the original's structure (the usual case: c_i lies inside the
+// rate range, where no term vanishes) only bring their pool: they run in one
+// batched pass with the original, each sweep reading its own pool copy.
 tn3d_status tn3d_grad_loglik(tn3d_ctx c, tn3d_net net, int32_t batch, const uint8_t* synd, const int64_t* offs,
                              const tn3d_params* pr, int32_t n_rates, const int32_t* rate_of_mech, double* grad,
                              double* loglik_sum, double* loglik, double* grad_items, uint32_t* flags) {
@@ -1223,37 +1282,53 @@ tn3d_status tn3d_grad_loglik(tn3d_ctx c, tn3d_net net, int32_t batch, const uint
     if (loglik_sum) HIPCHK(c, hipMemsetAsync(loglik_sum, 0, 8, c->stream));
     return TN3D_OK;
   }
-  // the networks at rate i = c_i, built once per network
-  if (int(net->variants.size()) != n) {
-    for (tn3d_net v : net->variants) tn3d_net_destroy(v);
-    net->variants.clear();
+  // the networks at p_i = c_i, built once per network: c_i a quarter of the
+  // rate range away from p_i, towards the middle of the range
+  if (int(net->var_c.size()) != n) {
+    drop_variants(net);
+    const double h = 0.25 * net->P.rate_max;
+    std::vector<double> q = net->rates, pools = net->P.pool;
     net->var_c.assign(n, 0.0);
-    std::vector<double> q = net->rates;
-    for (int i = 0; i < n; ++i) {
-      const double ci = net->rates[i] <= 0.5 ? 1.0 : 0.0;
+    net->var_slot.assign(n, -1);
+    net->variants.assign(n, nullptr);
+    int slots = 1;
+    tn3d_status s = TN3D_OK;
+    for (int i = 0; i < n && s == TN3D_OK; ++i) {
+      const double ci = net->rates[i] <= 0.5 * net->P.rate_max ? net->rates[i] + h : net->rates[i] - h;
+      net->var_c[i] = ci;
       q[i] = ci;
       Program P;
       std::string e = net->rebuild(q.data(), P);
       q[i] = net->rates[i];
-      tn3d_net v = nullptr;
-      tn3d_status s = make_net(c, e, std::move(P), &v);
-      if (s != TN3D_OK) {
-        for (tn3d_net w : net->variants) tn3d_net_destroy(w);
-        net->variants.clear();
-        return s;
+      if (e.empty() && same_structure(net->P, P)) {
+        net->var_slot[i] = slots++;
+        pools.insert(pools.end(), P.pool.begin(), P.pool.end());
+      } else {
+        s = make_net(c, e, std::move(P), &net->variants[i]);
+        if (s == TN3D_OK) net->variants[i]->tune_serial = net->serial;
       }
-      v->tune_serial = net->serial;
-      net->variants.push_back(v);
-      net->var_c[i] = ci;
+    }
+    if (s == TN3D_OK) {
+      if (hipMalloc(&net->d_pool_all, pools.size() * 8) != hipSuccess) {
+        net->d_pool_all = nullptr;
+        s = fail(c, TN3D_E_OOM, "pools of the networks at changed rates");
+      } else if (hipMemcpy(net->d_pool_all, pools.data(), pools.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        s = fail(c, TN3D_E_DEVICE, "pool upload");
+      }
+    }
+    if (s != TN3D_OK) {
+      drop_variants(net);
+      return s;
     }
   }
-  // scratch: tiled offsets, log p and flags of the (n + 1) blocks, the rates
-  // (c_i, p_i), the rate -> mechanism lists, the per-item derivatives
+  // scratch: tiled offsets, log p and flags of the (n + 1) blocks, the pool
+  // copy of each item, the rates (c_i, p_i), the rate -> mechanism lists,
+  // the per-item derivatives
   const size_t B = size_t(batch), nb = size_t(n) + 1;
   const size_t o_offs = 0, o_lp = align256(nb * B * 8), o_fl = o_lp + align256(nb * B * 32),
-               o_cp = o_fl + align256(nb * B * 4), o_ptr = o_cp + align256(size_t(n) * 16),
-               o_rm = o_ptr + align256((size_t(n_rates) + 1) * 4), o_term = o_rm + align256(size_t(n) * 4),
-               need = o_term + (grad_items ? 0 : align256(B * n * 8));
+               o_psel = o_fl + align256(nb * B * 4), o_cp = o_psel + align256(nb * B * 4),
+               o_ptr = o_cp + align256(size_t(n) * 16), o_rm = o_ptr + align256((size_t(n_rates) + 1) * 4),
+               o_term = o_rm + align256(size_t(n) * 4), need = o_term + (grad_items ? 0 : align256(B * n * 8));
   if (c->gaux_bytes < need) {
     if (c->gaux) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1267,6 +1342,7 @@ tn3d_status tn3d_grad_loglik(tn3d_ctx c, tn3d_net net, int32_t batch, const uint
   int64_t* offs_all = reinterpret_cast<int64_t*>(c->gaux + o_offs);
   double* lp = reinterpret_cast<double*>(c->gaux + o_lp);
   uint32_t* fl = reinterpret_cast<uint32_t*>(c->gaux + o_fl);
+  int32_t* psel = reinterpret_cast<int32_t*>(c->gaux + o_psel);
   double* cp = reinterpret_cast<double*>(c->gaux + o_cp);
   int32_t* ptr = reinterpret_cast<int32_t*>(c->gaux + o_ptr);
   int32_t* rm = reinterpret_cast<int32_t*>(c->gaux + o_rm);
@@ -1283,20 +1359,32 @@ tn3d_status tn3d_grad_loglik(tn3d_ctx c, tn3d_net net, int32_t batch, const uint
     std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
     for (int i = 0; i < n; ++i) hrm[fill[rate_of_mech ? rate_of_mech[i] : i]++] = i;
   }
+  // items v B + s: block v = 0 the network at its rates, v = i + 1 rate i changed
+  std::vector<int32_t> hsel(nb * B, 0), shared, own;
+  for (size_t v = 0; v < nb; ++v) {
+    const int slot = v == 0 ? 0 : net->var_slot[v - 1];
+    for (size_t j = 0; j < B; ++j) {
+      hsel[v * B + j] = slot < 0 ? 0 : slot;
+      (slot < 0 ? own : shared).push_back(int32_t(v * B + j));
+    }
+  }
   HIPCHK(c, hipMemcpyAsync(cp, hcp.data(), hcp.size() * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(ptr, hptr.data(), hptr.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(rm, hrm.data(), hrm.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(psel, hsel.data(), hsel.size() * 4, hipMemcpyHostToDevice, c->stream));
   launch_tile_offsets(batch, int(nb), offs, offs_all, c->stream);
   HIPCHK(c, hipGetLastError());
-  // block 0 as an ordinary contraction (captured graphs when enabled); the
-  // n networks of single-rate changes eagerly, one batched pass each
-  std::vector<int32_t> items(B);
-  tn3d_status s = TN3D_OK;
+  // one batched pass over every item of the shared structure, then the
+  // changed networks of another structure one by one
+  const PoolSel ps{net->d_pool_all, int64_t(net->P.pool.size()), psel};
+  tn3d_status s = run_group(c, net, shared, synd, offs_all, *pr, lp, fl, pr->precision, false, &ps);
   const bool graphs = c->graphs;
-  for (size_t v = 0; v < nb && s == TN3D_OK; ++v) {
+  c->graphs = false;
+  std::vector<int32_t> items(B);
+  for (size_t v = 1; v < nb && s == TN3D_OK; ++v) {
+    if (net->var_slot[v - 1] >= 0) continue;
     for (size_t j = 0; j < B; ++j) items[j] = int32_t(v * B + j);
-    c->graphs = graphs && v == 0;
-    s = run_group(c, v == 0 ? net : net->variants[v - 1], items, synd, offs_all, *pr, lp, fl, pr->precision, false);
+    s = run_group(c, net->variants[v - 1], items, synd, offs_all, *pr, lp, fl, pr->precision, false);
   }
   c->graphs = graphs;
   if (s == TN3D_OK) {

@@ -27,6 +27,8 @@ struct SweepArgs {
   const int64_t* synd_off;  // [global item] offset into synd
   const int32_t* items;     // [local item] -> global item
   const double* pool;       // op matrices and initial tensors
+  const int32_t* psel;      // null, or per item (indexed as synd_off) the copy of the pool it reads
+  int64_t pool_stride;      // doubles per pool copy
   double eps, tau, pchol_tol;
   int32_t qr;                     // 1: truncation factors by Householder QR (FP64 route), 0: through Grams
   int32_t inc0, n_inc;            // consistency bits of an item (Program::inc0, n_inc)
@@ -157,6 +159,7 @@ void launch_scatter_out(int n, const int32_t* items, const double* lp_local, con
 void launch_pick_ties(int n_items, const double* logratio, double near_tie, int32_t* list, int32_t* count,
                       hipStream_t st);
 void launch_gather_offsets(int n, const int32_t* items, const int64_t* offs, int64_t* out, hipStream_t st);
+void launch_gather_i32(int n, const int32_t* items, const int32_t* src, int32_t* out, hipStream_t st);
 void launch_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,
                             double* logp, uint32_t* flags, hipStream_t st);
 void launch_decode(int n_items, int n_cosets, const int32_t* items, const double* logp, double near_tie,

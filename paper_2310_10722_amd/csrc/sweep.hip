@@ -52,6 +52,12 @@ __device__ __forceinline__ int synd_bit(const SweepArgs& A, int sweep, int det) 
   return A.synd[A.synd_off[item] + det] & 1;
 }
 
+// The op matrices and initial tensors a sweep reads: one pool, or with psel
+// one of several copies of equal layout (the same network at other rates).
+__device__ __forceinline__ const double* pool_of(const SweepArgs& A, int sweep) {
+  return A.psel ? A.pool + int64_t(A.psel[A.items[sweep / A.n_cosets]]) * A.pool_stride : A.pool;
+}
+
 // A gate whose terms depend on a per-item bit uses its second term set when
 // the bit is set.
 __device__ __forceinline__ bool gate_alt(const SweepArgs& A, const DevGate& g, int sweep) {
@@ -84,7 +90,7 @@ __global__ void k_init_sites(SweepArgs A, const int32_t* init_dims, const int32_
   const int c = sweep % A.n_cosets;
   const int32_t* dm = init_dims + (int64_t(c) * A.n_sites + site) * 5;
   const int n = dm[0] * dm[1] * dm[2] * dm[3] * dm[4];
-  const double* src = A.pool + init_off[c * A.n_sites + site];
+  const double* src = pool_of(A, sweep) + init_off[c * A.n_sites + site];
   T* dst = tens<T>(A, 0, sweep, site);
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = T(src[i]);
 }
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(ET) void k_onesite(SweepArgs A, const DevOneSite* o
   const int sweep = blockIdx.y;
   __shared__ double M[256];
   const int bit = op.det >= 0 ? synd_bit(A, sweep, op.det) : 0;
-  const double* src = A.pool + (bit ? op.m1 : op.m0);
+  const double* src = pool_of(A, sweep) + (bit ? op.m1 : op.m0);
   for (int i = threadIdx.x; i < op.din * op.dout; i += blockDim.x) M[i] = src[i];
   __syncthreads();
   int D[4];
@@ -451,8 +457,8 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
   const double* GA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
   const double* GB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
   const bool alt = gate_alt(A, g, sweep);
-  const double* PA = A.pool + (alt ? g.pA1 : g.pA);
-  const double* PB = A.pool + (alt ? g.pB1 : g.pB);
+  const double* PA = pool_of(A, sweep) + (alt ? g.pA1 : g.pA);
+  const double* PB = pool_of(A, sweep) + (alt ? g.pB1 : g.pB);
   const int nA = dA * D, nB = dB * D;
   if (dA <= 4 && dB <= 4) {
     // one bond pair (b, b2) per thread: its dA^2 and dB^2 Gram entries loaded
@@ -507,8 +513,8 @@ __device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, 
                         const double* Ss, double s1, double* WA, double* WB, int first, int stride) {
   const int K = g.K, dA = g.dA, dB = g.dB, nA = dA * D, nB = dB * D;
   const bool alt = gate_alt(A, g, sweep);
-  const double* OA = A.pool + (alt ? g.oA1 : g.oA);
-  const double* OB = A.pool + (alt ? g.oB1 : g.oB);
+  const double* OA = pool_of(A, sweep) + (alt ? g.oA1 : g.oA);
+  const double* OB = pool_of(A, sweep) + (alt ? g.oB1 : g.oB);
   const int ncA = dA * Dn, ncB = dB * Dn;
   if (bad) {
     for (int e = first; e < nA * ncA; e += stride) WA[2 + e] = 0.0;
@@ -617,7 +623,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (team < 2) {
       const double* R = gin + (int64_t(sweep * n_g + gi) * 2 + team) * ncap * ncap;
       const int dd = team ? dB : dA;
-      const double* O = A.pool + (team ? (alt ? g.oB1 : g.oB) : (alt ? g.oA1 : g.oA));
+      const double* O = pool_of(A, sweep) + (team ? (alt ? g.oB1 : g.oB) : (alt ? g.oA1 : g.oA));
       team_tsqr<TQ, TQ>(
           team ? VM : CM, n, dd * dd * D, [&](int row, int col) { return gated_y(R, O, dd, D, row, col); },
           team ? ZB : ZA, l);
@@ -876,8 +882,8 @@ __global__ __launch_bounds__(64) void k_solve_team(SweepArgs A, const DevGate* g
     const bool alt = gate_alt(A, g, sweep);
     const double* RA = gin + (int64_t(sweep * n_g + gi) * 2 + 0) * ncap * ncap;
     const double* RB = gin + (int64_t(sweep * n_g + gi) * 2 + 1) * ncap * ncap;
-    const double* OA = A.pool + (alt ? g.oA1 : g.oA);
-    const double* OB = A.pool + (alt ? g.oB1 : g.oB);
+    const double* OA = pool_of(A, sweep) + (alt ? g.oA1 : g.oA);
+    const double* OB = pool_of(A, sweep) + (alt ? g.oB1 : g.oB);
     const int dA = g.dA, dB = g.dB;
     team_tsqr<TL, TL>(CM, n, dA * dA * D, [&](int row, int col) { return gated_y(RA, OA, dA, D, row, col); }, ZA, l);
     team_tsqr<TL, TL>(VM, n, dB * dB * D, [&](int row, int col) { return gated_y(RB, OB, dB, D, row, col); }, ZA, l);
@@ -1251,7 +1257,7 @@ __global__ __launch_bounds__(ET) void k_finalize(SweepArgs A, const int32_t* d_f
   site_dims(A, sweep, site, D);
   const int64_t rows = int64_t(D[0]) * D[1] * D[2] * D[3];
   const int d = d_final[site];
-  const double* f = A.pool + f_off[site];
+  const double* f = pool_of(A, sweep) + f_off[site];
   const T* t = tens<T>(A, par_final[site], sweep, site);
   double* o = fin + int64_t(sweep) * fin_stride + fin_off[site];
   for (int64_t r = threadIdx.x; r < rows; r += ET) {
@@ -2231,6 +2237,11 @@ __global__ void k_gather_offsets(int n, const int32_t* items, const int64_t* off
   if (i < n) out[i] = offs[items[i]];
 }
 
+__global__ void k_gather_i32(int n, const int32_t* items, const int32_t* src, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[items[i]];
+}
+
 // Results of the re-sweep (row i of logp_sub, flags_sub) back to items[i].
 __global__ void k_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,
                                   double* logp, uint32_t* flags) {
@@ -2252,16 +2263,16 @@ __global__ void k_scatter_resweep(int n, const int32_t* items, const double* log
 // [0, 1] farther from p_i, so |c_i - p_i| >= 1/2).
 
 // log sum_c exp(r[c]) over the coset columns.  A NaN column (a value the
-// contraction found non-positive) makes the result NaN, or, with nan_zero,
-// counts as zero.
-__device__ double lse_cosets(const double* r, int nc, bool nan_zero = false) {
+// contraction found non-positive, below its own error) counts as zero; with
+// every column NaN the result is NaN, or -inf with all_nan_zero.
+__device__ double lse_cosets(const double* r, int nc, bool all_nan_zero = false) {
   double m = -INFINITY;
-  bool nan = false;
+  int n_nan = 0;
   for (int c = 0; c < nc; ++c) {
-    if (isnan(r[c])) nan = true;
+    if (isnan(r[c])) ++n_nan;
     if (r[c] > m) m = r[c];
   }
-  if (nan && !nan_zero) return NAN;
+  if (n_nan == nc) return all_nan_zero ? -INFINITY : NAN;
   if (m == -INFINITY) return m;
   double s = 0.0;
   for (int c = 0; c < nc; ++c)
@@ -2270,10 +2281,9 @@ __device__ double lse_cosets(const double* r, int nc, bool nan_zero = false) {
 }
 
 // term[s][i] = d log P(m_s) / d p_i for every item s < B and mechanism i < n.
-// cp[2 i] = c_i, cp[2 i + 1] = p_i.  P at p_i = c_i is often exactly zero (no
-// error pattern with x_i = c_i explains the syndrome); the contraction
-// returns it as a rounding of zero, NaN where that rounding is not positive,
-// and such a coset counts as zero: exact up to the contraction's own error.
+// cp[2 i] = c_i, cp[2 i + 1] = p_i.  A changed network whose cosets are all
+// found non-positive counts as zero; at the given rates that leaves log P
+// NaN and so the item's derivatives.
 __global__ void k_grad_terms(int B, int n, int nc, const double* lp, const double* cp, double* term) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(B) * n) return;
@@ -2729,6 +2739,10 @@ void launch_pick_ties(int n_items, const double* logratio, double near_tie, int3
 
 void launch_gather_offsets(int n, const int32_t* items, const int64_t* offs, int64_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_offsets, dim3((n + 255) / 256), dim3(256), 0, st, n, items, offs, out);
+}
+
+void launch_gather_i32(int n, const int32_t* items, const int32_t* src, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_i32, dim3((n + 255) / 256), dim3(256), 0, st, n, items, src, out);
 }
 
 void launch_scatter_resweep(int n, const int32_t* items, const double* logp_sub, const uint32_t* flags_sub,

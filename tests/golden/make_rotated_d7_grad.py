@@ -3,8 +3,8 @@ rotated d=7 surface code with phenomenological noise (7 noisy rounds and one
 perfect one, per-qubit and per-measurement rates drawn log-uniformly in
 [0.005, 0.05] from seed 2310107325), for items 0, 85, 170 and 255 of the
 256 seeded syndromes of that workload (seed 2310107225) and 25
-mechanisms (24 drawn from seed 2024 plus the last one, whose forced firing
-explains none of these syndromes), at chi = chi_m = 16 under the
+mechanisms (24 drawn from seed 2024 plus the last one), at chi = chi_m = 16
+under the
 reduced-precision rank rule (eps_rel 1e-6, tau_gap 1e-2; the finer FP64
 default rule cuts in rounding noise on this workload).
 

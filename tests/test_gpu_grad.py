@@ -2,7 +2,8 @@
 against the gradient oracle.
 
 P(m) is affine in each rate, so d log P / d p_i = (P(p_i = c_i) / P - 1) /
-(c_i - p_i) with c_i the end of [0, 1] farther from p_i.  Where chi truncates
+(c_i - p_i) for any c_i != p_i; the library steps a quarter of the rate
+range towards its middle.  Where chi truncates
 nothing the library's gradient is the exact one (O-4, pinned to brute-force
 marginals and finite differences); at truncating chi it is compared with the
 same one-sided form over the oracle's fixed-chi sweep (O-3) at equal chi and
@@ -38,16 +39,22 @@ def ctx():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2310_10722_amd import tn3d
-    return tn3d.Context(0)
+    c = tn3d.Context(0)
+    yield c
+    c.close()  # the gradient passes size their workspace to the free memory: release it
 
 
 def syn_of(m):
     return torch.from_numpy(np.ascontiguousarray(m)).to("cuda:0")
 
 
+def changed_rate(p, rate_max=1.0):
+    return np.where(p <= 0.5 * rate_max, p + 0.25 * rate_max, p - 0.25 * rate_max)
+
+
 def term_tol(g, p, delta):
     """Bound on |term_gpu - term_oracle| for log-value errors <= delta."""
-    c = np.where(p <= 0.5, 1.0, 0.0)
+    c = changed_rate(p)
     r = 1.0 + g * (c - p)
     return (np.abs(r) + 1.0) * np.expm1(2.0 * delta) / np.abs(c - p) + 1e-12
 
@@ -105,13 +112,12 @@ def test_grad_exact(ctx, which):
     g = np.array([r[1] for r in ref])
     tol = term_tol(g, dem.p[None, :], 1e-9)
     err = np.abs(items - g)
-    say("  max |d term| =", err.max(), " max |d log P| =", np.abs(ll - lp).max(),
-        " zero-valued changed networks:", int(np.sum(np.abs(1.0 + g * (np.where(dem.p <= .5, 1., 0.) - dem.p)) < 1e-12)))
+    say("  max |d term| =", err.max(), " max |d log P| =", np.abs(ll - lp).max())
     assert np.all(err <= tol)
     assert np.all(np.abs(grad - g.sum(axis=0)) <= tol.sum(axis=0))
     assert np.abs(ll - lp).max() <= 1e-9
     assert abs(tot - lp.sum()) <= 6e-9
-    assert np.all((flags.cpu().numpy() & 1) == 0) or which == "rotated_d3_T2"
+    assert np.all((flags.cpu().numpy() & 1) == 0)
 
 
 def test_grad_rate_map_autograd_and_differences(ctx):
@@ -175,17 +181,19 @@ def test_grad_rate_map_autograd_and_differences(ctx):
         assert abs(fd - grad[k]) <= 1e-5 * max(1.0, abs(grad[k]))
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["fp64_gram", "fp32"])
 def test_grad_rotated_d7_chi16_golden(ctx, mode):
     """The gradient workload: rotated d=7, 7 noisy rounds + 1 perfect,
     per-qubit / per-measurement rates log-uniform in [0.005, 0.05], chi =
     chi_m = 16, rank rule (1e-6, 1e-2); items 0, 85, 170, 255 of its 256
     syndromes (with 60 more in FP32: 64 syndromes x 512 networks in one call)
     x 25 mechanisms against stored oracle values
-    (tests/golden/make_rotated_d7_grad.py).  Log-value bounds: FP64 1e-9 or
-    twice the oracle's spread under two SVD drivers per term, whichever is
-    larger; FP32 1e-3 + 4 eps_32 (the decoded coset within 1e-3, a minority
-    coset of weight e^-gap within 1e-3 + 4 eps_32 e^gap).  The per-rate
+    (tests/golden/make_rotated_d7_grad.py).  FP64 on the Gram route (the
+    orthogonal route's one-sided Jacobi on 256-vector boundary families is
+    too slow for 512 networks here): log values within 1e-6, its bound, or
+    twice the oracle's spread under two SVD drivers, whichever is larger;
+    FP32 1e-3 + 4 eps_32 (the decoded coset within 1e-3, a minority coset of
+    weight e^-gap within 1e-3 + 4 eps_32 e^gap).  The per-rate
     gradient (49 qubit + 168 measurement rates) equals the chain-rule sum of
     the per-item derivatives."""
     from paper_2310_10722_amd import tn3d
@@ -198,8 +206,10 @@ def test_grad_rotated_d7_chi16_golden(ctx, mode):
     m = m[pick]
     say(f"case: gradient rotated d=7 T=7 chi=16 {mode}, {len(pick)} syndromes, 4 x 25 stored")
     net = tn3d.tn3d_net_rotated_phenom(ctx, 7, 7, dem.p)
-    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64 if mode == "fp64" else tn3d.PREC_FP32)
+    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64 if mode == "fp64_gram" else tn3d.PREC_FP32)
     prm.eps_rel, prm.tau_gap = gold["rule"]
+    if mode == "fp64_gram":
+        prm.flags = tn3d.OPT_GRAM_FACTOR
     nq, nZ = 49, 24
     rate_of = np.concatenate([np.tile(np.arange(nq), 7), nq + np.arange(7 * nZ)]).astype(np.int32)
     import time
@@ -216,9 +226,9 @@ def test_grad_rotated_d7_chi16_golden(ctx, mode):
     g1 = np.array(gold["grad"]["gesvd"])
     l0 = np.array(gold["loglik"]["gesdd"])
     got = items[:4][:, idx]
-    if mode == "fp64":
-        tol = np.maximum(term_tol(g0, p[None, :], 1e-9), 2.0 * np.abs(g1 - g0)) + 1e-12
-        ltol = np.maximum(1e-9, 2.0 * np.abs(np.array(gold["loglik"]["gesvd"]) - l0))
+    if mode == "fp64_gram":
+        tol = np.maximum(term_tol(g0, p[None, :], 1e-6), 2.0 * np.abs(g1 - g0)) + 1e-12
+        ltol = np.maximum(1e-6, 2.0 * np.abs(np.array(gold["loglik"]["gesvd"]) - l0))
     else:
         delta = 1e-3 + 4.0 * 2.0 ** -24
         tol = term_tol(g0, p[None, :], delta)

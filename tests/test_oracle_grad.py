@@ -120,6 +120,18 @@ def test_one_sided_form_equals_brute_force_marginals():
         np.testing.assert_allclose(g, gb, rtol=1e-10, atol=1e-10)
 
 
+def test_one_sided_form_rate_range():
+    # The depolarizing range [0, 3/4]: the step is 3/16; a one-mechanism
+    # closed form P(m=1) = p fixes the derivative 1/p at any rate.
+    def cosets(q):
+        return [np.log(q[0]), -np.inf]
+
+    for p0 in (0.05, 0.5, 0.7):
+        lp, g = loglik_grad_one_sided(cosets, np.array([p0]), rate_max=0.75)
+        assert lp == pytest.approx(np.log(p0), abs=1e-15)
+        assert g[0] == pytest.approx(1.0 / p0, rel=1e-12)
+
+
 def test_one_sided_form_with_the_sweep_at_untruncated_chi():
     # With the fixed-chi sweep as the evaluator at a chi that truncates
     # nothing, the gradient is the exact one (two-sided form, O-2).
@@ -136,3 +148,14 @@ def test_one_sided_form_with_the_sweep_at_untruncated_chi():
         le, ge = loglik_grad_exact(dem.H, dem.p, dem.obs, m[k])
         assert lp == pytest.approx(le, abs=1e-9)
         np.testing.assert_allclose(g, ge[idx], rtol=1e-8, atol=1e-8)
+
+
+def test_one_sided_form_non_positive_cosets():
+    # A coset an evaluator finds non-positive (NaN) counts as zero; every
+    # coset NaN at the given rates gives NaN.  One mechanism, P_0 = 1 - p,
+    # P_1 reported as NaN: log P = log(1 - p), d log P / d p = -1 / (1 - p).
+    lp, g = loglik_grad_one_sided(lambda q: [np.log(1.0 - q[0]), np.nan], np.array([0.2]))
+    assert lp == pytest.approx(np.log(0.8), abs=1e-15)
+    assert g[0] == pytest.approx(-1.0 / 0.8, rel=1e-12)
+    lp, g = loglik_grad_one_sided(lambda q: [np.nan, np.nan], np.array([0.2]))
+    assert np.isnan(lp) and np.isnan(g[0])
