@@ -70,10 +70,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(profile):
+def recorded_traffic(profile, sweeps_per_launch):
     """HBM bytes per launch from a committed counter summary (FETCH_SIZE x
-    its copy-calibrated scale + WRITE_SIZE), or None when the summary is
-    missing or was taken on other kernel sources."""
+    its copy-calibrated scale + WRITE_SIZE, per sweep the launch covers)
+    times the sweeps per launch, or None when the summary is missing or was
+    taken on other kernel sources."""
     try:
         with open(os.path.join(ROOT, "profiles", profile)) as fh:
             text = fh.read()
@@ -87,7 +88,7 @@ def recorded_traffic(profile):
     if rec.get("kernel source sha256") != kernel_source_hash():
         return None
     try:
-        return float(rec["traffic bytes per launch"])
+        return float(rec["traffic bytes per sweep and launch"]) * sweeps_per_launch
     except (KeyError, ValueError):
         return None
 
@@ -218,12 +219,15 @@ def bench_point_L8(a, tn3d, np, torch):
     say(f"{a.steps} timed steps: {dt:.2f} s")
     t = ctx.last_timing()
     (lay_ms, fin_ms, hot_ms, hot_launch, hot_bytes, eig_ms, eig_launch, eig_flops, za_ms, za_flops, za_launch,
-     sub_ms, sub_flops, sub_launch) = t
+     sub_ms, sub_flops, sub_launch, sub_sweeps) = t
     coset, lr, logp, flags = [x.cpu().numpy() for x in results]
     rf_eig = roof_entry("k_zip_bsub (boundary-MPS leading eigenpairs of families above 64 vectors: subspace "
                         "iteration with Rayleigh-Ritz on the FP64 matrix cores; BF16 pass and FP64 re-sweep)", "mfma",
                         sub_flops, sub_ms, sub_launch, FP64_PEAK_TFS, "TFLOP/s",
-                        recorded_traffic("pmc_k_zip_bsub_point_L8_chi32_bf16.md"))
+                        recorded_traffic("pmc_k_zip_bsub_point_L8_chi32_bf16.md",
+                                         sub_sweeps / sub_launch if sub_launch else 0.0))
+    if rf_eig:
+        rf_eig["sweeps_per_launch"] = sub_sweeps / sub_launch
     stream = roof_entry("k_gram2 + k_reabsorb2 + k_reabsorb (site-tensor streaming; BF16 pass and FP64 re-sweep)",
                         "hbm", hot_bytes, hot_ms, hot_launch, HBM_PEAK_GBS, "GB/s", None)
     out = {"metric": METRIC, "value": a.steps * B / dt, "unit": "syndromes/s", "n_gpus": 1, "steps": a.steps,
@@ -406,7 +410,7 @@ def bench_rotated_d7_grad(a, tn3d, np, torch):
     t = ctx.last_timing()
     ctx.set_timing(0)
     (lay_ms, fin_ms, hot_ms, hot_launch, hot_bytes, eig_ms, eig_launch, eig_flops, za_ms, za_flops, za_launch,
-     sub_ms, sub_flops, sub_launch) = t
+     sub_ms, sub_flops, sub_launch, _) = t
     grad, tot, ll, flags, items = res
     grad, ll, flags, items = grad.cpu().numpy(), ll.cpu().numpy(), flags.cpu().numpy(), items.cpu().numpy()
     rf_eig = roof_entry("k_zip_beig (boundary-MPS decompositions of families up to 64 vectors, one wavefront each)",

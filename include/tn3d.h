@@ -377,8 +377,9 @@ tn3d_status tn3d_autotune(tn3d_ctx ctx, int32_t batch, const tn3d_net* nets, con
  * algorithmic flops, out[10] = their number, out[11] = time of the
  * subspace-iteration launches (boundary-MPS families above 64 vectors on the
  * Gram route; out[5] then covers only the one-wavefront solver), out[12] =
- * their algorithmic flops, out[13] = their number.  Milliseconds for times;
- * n <= 14 values are written.
+ * their algorithmic flops, out[13] = their number, out[14] = the sweeps they
+ * covered (summed over the launches).  Milliseconds for times; n <= 15
+ * values are written.
  * Returns TN3D_E_INVALID if timing is not enabled. */
 tn3d_status tn3d_ctx_set_timing(tn3d_ctx ctx, int32_t enable);
 tn3d_status tn3d_last_timing(tn3d_ctx ctx, double* out, int32_t n);

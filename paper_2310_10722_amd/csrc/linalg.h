@@ -75,13 +75,15 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 // (row-major, leading dimension n; destroyed).  Writes F (r x n, row-major,
 // leading dimension n) with F^T F = Z up to the dropped trailing part, in the
 // original column order, and returns the rank r: elimination stops when the
-// largest remaining diagonal is <= tol * max(diag Z).  n <= 64.  perm is
-// scratch of n ints, red scratch of 2 doubles.
+// largest remaining diagonal is <= tol * max(diag Z).  Any n (the diagonal
+// is scanned by the first wavefront, lane l taking entries l, l + 64, ...).
+// perm is scratch of n ints, red scratch of 2 doubles.
 __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < n; i += nt) perm[i] = i;
-  if (tid < 64) {  // n <= 64: the first wavefront scans the diagonal
-    double m = tid < n ? Z[tid * n + tid] : 0.0;
+  if (tid < 64) {
+    double m = 0.0;
+    for (int i = tid; i < n; i += 64) m = fmax(m, Z[i * n + i]);
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if (tid == 0) red[0] = fmax(m, 0.0);
   }
@@ -91,8 +93,16 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
   int r = 0;
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {  // pivot: the largest remaining diagonal, lowest index on ties
-      double best = (tid >= k && tid < n) ? Z[tid * n + tid] : -1e300;
-      int j = tid;
+      double best = -1e300;
+      int j = n + tid;  // no candidate in this lane: loses every tie to a real index
+      for (int i = tid; i < n; i += 64)
+        if (i >= k) {
+          const double v = Z[i * n + i];
+          if (v > best) {  // ascending i: the lowest index of a lane's ties stays
+            best = v;
+            j = i;
+          }
+        }
       wave_argmax(best, j);
       if (tid == 0) {
         red[1] = double(j);

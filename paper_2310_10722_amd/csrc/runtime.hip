@@ -36,6 +36,7 @@ static std::map<int, char*> g_scratch_ptr;  // device -> address of scratch ther
 struct GraphKey {
   uint64_t net;
   int prec, chi, chi_mps;
+  uint32_t flags;  // params.flags: the factorisation route sets the workspace layout
   double eps, tau;
   int ni;
   int64_t chunk;
@@ -45,9 +46,9 @@ struct GraphKey {
   std::vector<int32_t> sched;  // chi-schedule (empty: constant chi)
   int tune;                    // launch-shape choice (LaunchTuning, packed)
   bool operator<(const GraphKey& o) const {
-    return std::tie(net, prec, chi, chi_mps, eps, tau, ni, chunk, timing, ws, ws_bytes, sched, tune) <
-           std::tie(o.net, o.prec, o.chi, o.chi_mps, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws, o.ws_bytes,
-                    o.sched, o.tune);
+    return std::tie(net, prec, chi, chi_mps, flags, eps, tau, ni, chunk, timing, ws, ws_bytes, sched, tune) <
+           std::tie(o.net, o.prec, o.chi, o.chi_mps, o.flags, o.eps, o.tau, o.ni, o.chunk, o.timing, o.ws,
+                    o.ws_bytes, o.sched, o.tune);
   }
 };
 
@@ -82,7 +83,7 @@ struct tn3d_ctx_s {
   size_t ws_bytes = 0;
   int timing = 0;                  // 1: kernel times, 2: also bond statistics
   int wclk_khz = 100000;           // device wall-clock rate
-  double timing_out[14] = {};  // launch counts (3, 6, 10, 13) kept on the host
+  double timing_out[15] = {};  // launch counts (3, 6, 10, 13) and sweeps (14) kept on the host
   double* tacc = nullptr;          // device sums of the times, bytes and flops since timing was set
   double stats_out[6] = {0, 0, 0, 0, 0, 0};
   int nb_last = 0;
@@ -460,7 +461,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     if (items[i] != items[0] + int32_t(i)) contiguous = false;
 
   const int timing = c->timing;
-  double hot_launches = 0, eig_launches = 0, zip_launches = 0, bsub_launches = 0;
+  double hot_launches = 0, eig_launches = 0, zip_launches = 0, bsub_launches = 0, bsub_sweeps = 0;
   for (int64_t i0 = 0; i0 < int64_t(items.size()); i0 += chunk_items) {
     const int ni = int(std::min<int64_t>(chunk_items, int64_t(items.size()) - i0));
     int32_t* d_items = reinterpret_cast<int32_t*>(ws + o_items);
@@ -641,7 +642,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       // inputs into the workspace, replay (capturing first if needed), results out
       gather_inputs();
       HIPCHK(c, hipGetLastError());
-      const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
+      const GraphKey key{n->serial, prec, pr.chi, pr.chi_mps, pr.flags, pr.eps_rel, pr.tau_gap, ni, chunk_items, timing,
                          c->ws, c->ws_bytes,
                          std::vector<int32_t>(pr.chi_layers, pr.chi_layers + std::max(0, pr.n_chi_layers)),
                          pack_tuning(TU)};
@@ -713,7 +714,11 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       zq.gram_path = gram_path ? 1 : 0;
       zip_launches += double(P.Ly) * P.Lx;
       for (int y = 0; y < P.Ly; ++y)
-        for (int x = 0; x < P.Lx; ++x) bsub_launches += zip_step_large(zq, x, y, L.legcap) == 1 ? 1 : 0;
+        for (int x = 0; x < P.Lx; ++x)
+          if (zip_step_large(zq, x, y, L.legcap) == 1) {
+            bsub_launches += 1;
+            bsub_sweeps += A.n_sweeps;
+          }
     }
     if (timing >= 2) {
       std::vector<int32_t> bd(size_t(A.n_sweeps) * P.n_bonds);
@@ -743,6 +748,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     c->timing_out[6] += eig_launches;
     c->timing_out[10] += zip_launches;
     c->timing_out[13] += bsub_launches;
+    c->timing_out[14] += bsub_sweeps;
   }
   return TN3D_OK;
 }
@@ -1402,7 +1408,7 @@ tn3d_status tn3d_ctx_set_timing(tn3d_ctx c, int32_t enable) {
   HIPCHK(c, hipSetDevice(c->device));
   c->timing = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
   // the sums restart here (ordered after the work already on the stream)
-  for (int k = 0; k < 14; ++k) c->timing_out[k] = 0;
+  for (int k = 0; k < 15; ++k) c->timing_out[k] = 0;
   for (int k = 0; k < 6; ++k) c->stats_out[k] = 0;
   HIPCHK(c, hipMemsetAsync(c->tacc, 0, 12 * sizeof(double), c->stream));
   return TN3D_OK;
@@ -1427,7 +1433,7 @@ tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   double acc[12];
   HIPCHK(c, hipMemcpyAsync(acc, c->tacc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double d[14];
+  double d[15];
   for (int i = 0; i < 10; ++i) d[i] = acc[i];
   d[3] = c->timing_out[3];
   d[6] = c->timing_out[6];
@@ -1435,7 +1441,8 @@ tn3d_status tn3d_last_timing(tn3d_ctx c, double* out, int32_t n) {
   d[11] = acc[10];
   d[12] = acc[11];
   d[13] = c->timing_out[13];
-  for (int i = 0; i < n && i < 14; ++i) out[i] = d[i];
+  d[14] = c->timing_out[14];
+  for (int i = 0; i < n && i < 15; ++i) out[i] = d[i];
   return TN3D_OK;
 }
 

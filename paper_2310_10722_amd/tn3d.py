@@ -197,8 +197,8 @@ class Context:
         return int(self.lib.tn3d_ctx_graphs_cached(self.h))
 
     def last_timing(self):
-        out = (ctypes.c_double * 14)()
-        _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 14))
+        out = (ctypes.c_double * 15)()
+        _check(self.lib, self.h, self.lib.tn3d_last_timing(self.h, out, 15))
         return list(out)
 
     def last_stats(self):

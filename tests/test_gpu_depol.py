@@ -259,6 +259,32 @@ def test_depol_L4_chi24(ctx, mode):
     check(got, ref, *({"fp32_reduced": (1e-3, "fp32"), "fp64_gram_reduced": (1e-6, 1e-4)}[mode]))
 
 
+@pytest.mark.parametrize("mode", ["fp32", "fp64_gram"])
+def test_depol_L6_chi24_golden(ctx, mode):
+    """The depolarizing workload's L = 6 draw at chi = chi_m = 24 and the
+    reduced-precision rule (1e-6, 1e-2): truncations of order 72 in most
+    gates of the upper layers (the pivoted Cholesky of their Grams must pivot
+    over all 72 columns).  Items 0 and 3 against stored oracle values
+    (tests/golden/make_depol_L6_chi24.py): FP64 Gram route 1e-6 on the most
+    likely coset and 1e-4 on every coset, FP32 1e-3 on the most likely coset
+    and 1e-3 + 4 eps_32 e^gap on the others."""
+    from paper_2310_10722_amd import tn3d
+    say(f"case: depolarizing L=6 p=0.15 chi=24 {mode}, items 0 and 3 of the workload's L=6 draw")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "depol_L6_chi24.json")))
+    dem = synth.surface3d_depolarizing(6, gold["p"])
+    m, _ = synth.sample_pauli(dem, gold["n"], gold["seed"])
+    m = m[gold["items"]]
+    assert np.array_equal(m, np.array(gold["syndromes"], dtype=np.uint8))
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 6, dem.params["p_qubit"])
+    prm = tn3d.tn3d_params_default(24, 24, tn3d.PREC_FP32 if mode == "fp32" else tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = gold["rule"]
+    if mode == "fp64_gram":
+        prm.flags = tn3d.OPT_GRAM_FACTOR
+    got, flags = gpu_logp(ctx, net, m, prm)
+    assert np.all(flags & 8 == 0)
+    check(got, np.array(gold["logp"]), *({"fp32": (1e-3, "fp32"), "fp64_gram": (1e-6, 1e-4)}[mode]))
+
+
 def test_depol_chi24_fp64_orthogonal_refused(ctx):
     """The FP64 orthogonal route factors gate sides of at most 64 columns:
     physical dim 4 times chi = 24 asks for the Gram route."""

@@ -366,6 +366,30 @@ def test_unsupported_width_is_refused(ctx):
         gpu_logp(ctx, net, m, prm)
 
 
+def test_graph_cache_separates_factorisation_routes(ctx):
+    """The FP64 Gram route and the FP64 orthogonal route use different
+    workspace layouts: calls that alternate between them on one context (same
+    network, batch, chi and rank rule) each replay their own captured
+    sequence and equal the eager launches bit for bit."""
+    from paper_2310_10722_amd import tn3d
+    say("case: graph cache, FP64 Gram route and orthogonal route alternating, rotated d=5 chi=16")
+    dem, m, _, _ = synth.config_workload(2, n=12)
+    net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
+    eager = tn3d.Context(0)
+    eager.set_graphs(False)
+    net_e = tn3d.tn3d_net_rotated_phenom(eager, 5, 5, dem.p)
+    prm = {}
+    for route in ("gram", "orth"):
+        prm[route] = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
+        prm[route].eps_rel, prm[route].tau_gap = 1e-6, 1e-4
+        prm[route].flags = tn3d.OPT_GRAM_FACTOR if route == "gram" else 0
+    ref = {r: gpu_logp(eager, net_e, m, prm[r]) for r in prm}
+    for route in ("gram", "orth", "gram", "orth"):
+        got, got_f = gpu_logp(ctx, net, m, prm[route])
+        assert np.array_equal(got, ref[route][0]) and np.array_equal(got_f, ref[route][1]), route
+    assert np.max(np.abs(ref["gram"][0][:, :2] - ref["orth"][0][:, :2])) <= 1e-6
+
+
 def test_graph_replay_matches_eager(ctx):
     """Captured launch sequences: the first call of a shape captures, later
     calls replay.  Every replay, with other device work and synchronisations
