@@ -237,6 +237,46 @@ tn3d_status tn3d_net_from_dem(tn3d_ctx ctx, int32_t n_det, int32_t n_mech, int64
                               const int32_t* mech_idx, const double* p_mech, int32_t n_obs, const uint8_t* obs,
                               const int32_t* det_coord, tn3d_net* out);
 
+/* Generic layered network (paper Sec. 4: layers of one topology absorbed
+ * into a 2D network; two-site operators split into operator-Schmidt terms by
+ * a truncated SVD, the paper's general gate splitting).  An lx-by-ly grid
+ * (lx, ly >= 2) of sites; per coset c < n_cosets (1..4) an initial tensor per
+ * site s = y lx + x with dims init_dims[c][s][5] = (p, w, e, n, s) (physical,
+ * then the bonds to the west, east, north and south neighbours; 1 on the
+ * grid boundary; every coset with the same dims; bonds of equal dimension
+ * at both ends, at most 64, and at most max(chi, 2) when contracted), its
+ * values T[p][w][e][n][s] (row-major) at values[init_off[c][s]].  Then
+ * n_layers layers of ops (ops[] in nondecreasing `layer` order; within a
+ * layer the one-site ops before the gates act first, then the gates, then
+ * the one-site ops after them, each group in array order):
+ *   TN3D_OP_PRE / TN3D_OP_POST on site (x, y): a d_out x d_in matrix
+ *     (row-major [p'][p], d_in the site's current physical dim, both <= 16);
+ *   TN3D_OP_GATE_H / _V on (x, y)-(x+1, y) or (x, y)-(x, y+1): a two-site
+ *     operator G[a'][b'][a][b] with d_in = dim at (x, y), d_out = dim at the
+ *     other site (unchanged by the gate), split into the terms of singular
+ *     value above split_tol times the largest (split_tol in [0, 1)); at
+ *     most one gate per bond and layer.
+ * det >= 0 makes an op depend on that syndrome bit (values at off1 when it
+ * is set, off0 otherwise); n_det bits per item.  Finally the vector of the
+ * site's final physical dim at values[final_off[s]] closes every site, and
+ * log p_{m,c} is the log of the contracted value of coset c (non-positive
+ * values: NaN with NUMERIC).  All inputs are host pointers, copied; the
+ * network has no rates (tn3d_grad_loglik refuses it).
+ * Errors: TN3D_E_INVALID with the reason (shapes, ranges, dims that do not
+ * match, non-finite values). */
+typedef struct {
+  int32_t layer, kind, x, y, d_in, d_out, det, reserved;
+  int64_t off0, off1;
+} tn3d_layer_op;
+#define TN3D_OP_PRE 0
+#define TN3D_OP_GATE_H 1
+#define TN3D_OP_GATE_V 2
+#define TN3D_OP_POST 3
+tn3d_status tn3d_net_from_layers(tn3d_ctx ctx, int32_t lx, int32_t ly, int32_t n_layers, int32_t n_det,
+                                 int32_t n_cosets, const int32_t* init_dims, const int64_t* init_off, int32_t n_ops,
+                                 const tn3d_layer_op* ops, const int64_t* final_off, const double* values,
+                                 int64_t n_values, double split_tol, tn3d_net* out);
+
 int32_t tn3d_net_num_detectors(tn3d_net net);
 int32_t tn3d_net_num_mechanisms(tn3d_net net);
 int32_t tn3d_net_num_cosets(tn3d_net net);

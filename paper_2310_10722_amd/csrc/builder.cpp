@@ -1137,5 +1137,203 @@ std::string build_from_dem(int32_t n_det, int32_t n_mech, int64_t nnz, const int
   return "";
 }
 
+
+namespace {
+
+// Operator-Schmidt terms of a dense two-site operator G[a'][b'][a][b] (dims
+// dA, dB) by a singular value decomposition of its matrix
+// M[(a', a)][(b', b)]: one-sided Jacobi (Hestenes) on the columns of M, V
+// accumulating the rotations, then OA_k = sqrt(s_k) u_k, OB_k = sqrt(s_k) v_k
+// for the singular values s_k > tol s_1 (the paper's general gate splitting,
+// Sec. 4).  An all-zero operator gives one zero term.
+std::vector<Term> svd_split(const double* G, int dA, int dB, double tol) {
+  const int m = dA * dA, n = dB * dB;
+  std::vector<double> M(size_t(m) * n), V(size_t(n) * n, 0.0);
+  for (int a2 = 0; a2 < dA; ++a2)
+    for (int b2 = 0; b2 < dB; ++b2)
+      for (int a = 0; a < dA; ++a)
+        for (int b = 0; b < dB; ++b)
+          M[size_t(a2 * dA + a) * n + (b2 * dB + b)] = G[((size_t(a2) * dB + b2) * dA + a) * dB + b];
+  for (int j = 0; j < n; ++j) V[size_t(j) * n + j] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int i = 0; i < n - 1; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        double alpha = 0, beta = 0, gamma = 0;
+        for (int r = 0; r < m; ++r) {
+          const double x = M[size_t(r) * n + i], y = M[size_t(r) * n + j];
+          alpha += x * x;
+          beta += y * y;
+          gamma += x * y;
+        }
+        if (gamma == 0.0 || !(std::fabs(gamma) > 1e-15 * std::sqrt(alpha * beta))) continue;
+        rotated = true;
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int r = 0; r < m; ++r) {
+          const double x = M[size_t(r) * n + i], y = M[size_t(r) * n + j];
+          M[size_t(r) * n + i] = c * x - sn * y;
+          M[size_t(r) * n + j] = sn * x + c * y;
+        }
+        for (int r = 0; r < n; ++r) {
+          const double x = V[size_t(r) * n + i], y = V[size_t(r) * n + j];
+          V[size_t(r) * n + i] = c * x - sn * y;
+          V[size_t(r) * n + j] = sn * x + c * y;
+        }
+      }
+    if (!rotated) break;
+  }
+  std::vector<std::pair<double, int>> sv;
+  for (int j = 0; j < n; ++j) {
+    double s2 = 0;
+    for (int r = 0; r < m; ++r) s2 += M[size_t(r) * n + j] * M[size_t(r) * n + j];
+    sv.push_back({std::sqrt(s2), j});
+  }
+  std::stable_sort(sv.begin(), sv.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first;
+  });
+  std::vector<Term> terms;
+  const double s1 = sv.empty() ? 0.0 : sv[0].first;
+  for (const auto& e : sv) {
+    const double sk = e.first;
+    const int j = e.second;
+    if (!terms.empty() && !(sk > tol * s1)) break;
+    Term t{Mat(size_t(dA) * dA, 0.0), Mat(size_t(dB) * dB, 0.0)};
+    const double r = std::sqrt(sk);
+    // column j of M is s_k u_k: u_k sqrt(s_k) = column / sqrt(s_k)
+    for (int a2 = 0; a2 < dA; ++a2)
+      for (int a = 0; a < dA; ++a) t.A[size_t(a2) * dA + a] = sk > 0.0 ? M[size_t(a2 * dA + a) * n + j] / r : 0.0;
+    for (int b2 = 0; b2 < dB; ++b2)
+      for (int b = 0; b < dB; ++b) t.B[size_t(b2) * dB + b] = V[size_t(b2 * dB + b) * n + j] * r;
+    terms.push_back(std::move(t));
+  }
+  return terms;
+}
+
+}  // namespace
+
+std::string build_from_layers(int32_t lx, int32_t ly, int32_t n_layers, int32_t n_det, int32_t n_cosets,
+                              const int32_t* init_dims, const int64_t* init_off, int32_t n_ops, const LayerOp* ops,
+                              const int64_t* final_off, const double* values, int64_t n_values, double split_tol,
+                              Program& P) {
+  if (!init_dims || !init_off || !final_off || !values || (n_ops > 0 && !ops)) return "null pointer";
+  if (lx < 2 || ly < 2 || int64_t(lx) * ly > 4096) return "grid must be at least 2 x 2 and at most 4096 sites";
+  if (n_layers < 1 || n_layers > 4096 || n_cosets < 1 || n_cosets > 4 || n_det < 0 || n_ops < 0 || n_values < 0)
+    return "bad counts (n_layers in 1..4096, n_cosets in 1..4, n_det >= 0)";
+  if (!(split_tol >= 0.0 && split_tol < 1.0)) return "split_tol must lie in [0, 1)";
+  for (int64_t i = 0; i < n_values; ++i)
+    if (!std::isfinite(values[i])) return "values must be finite";
+  const int ns = lx * ly;
+  auto in_range = [&](int64_t off, int64_t len) { return off >= 0 && len >= 0 && off <= n_values - len; };
+  P = Program{};
+  P.name = "layers";
+  P.n_det = n_det;
+  P.n_mech = 0;
+  P.n_cosets = n_cosets;
+  Assembler A(P, lx, ly);
+  // initial states: every coset with the same physical and bond dimensions
+  P.init_dims.assign(size_t(n_cosets) * ns * 5, 1);
+  P.init_off.assign(size_t(n_cosets) * ns, 0);
+  P.bond_dim0.assign(P.n_bonds, 0);
+  for (int c = 0; c < n_cosets; ++c)
+    for (int s = 0; s < ns; ++s) {
+      const int32_t* dm = init_dims + (size_t(c) * ns + s) * 5;
+      for (int i = 0; i < 5; ++i)
+        if (dm[i] < 1 || dm[i] != init_dims[size_t(s) * 5 + i])
+          return "initial dims must be positive and equal across cosets";
+      if (dm[0] > 16) return "physical dimension above 16";
+      for (int leg = 0; leg < 4; ++leg) {
+        const int b = P.leg_bond[s * 4 + leg];
+        if (b < 0 && dm[1 + leg] != 1) return "a boundary leg of an initial tensor must have dimension 1";
+        if (b >= 0) {
+          if (dm[1 + leg] > 64) return "initial bond dimension above 64";
+          if (P.bond_dim0[b] == 0) P.bond_dim0[b] = dm[1 + leg];
+          if (P.bond_dim0[b] != dm[1 + leg]) return "the two ends of an initial bond differ in dimension";
+        }
+      }
+      const int64_t n = int64_t(dm[0]) * dm[1] * dm[2] * dm[3] * dm[4];
+      const int64_t off = init_off[size_t(c) * ns + s];
+      if (!in_range(off, n)) return "initial tensor outside values";
+      // given as [p][w][e][n][s]; stored as [w][e][n][s][p]
+      Mat t(static_cast<size_t>(n));
+      const int64_t nv = n / dm[0];
+      for (int p = 0; p < dm[0]; ++p)
+        for (int64_t v = 0; v < nv; ++v) t[size_t(v * dm[0] + p)] = values[off + p * nv + v];
+      for (int i = 0; i < 5; ++i) P.init_dims[(size_t(c) * ns + s) * 5 + i] = dm[i];
+      P.init_off[size_t(c) * ns + s] = A.put(t);
+    }
+  for (int b = 0; b < P.n_bonds; ++b)
+    if (P.bond_dim0[b] == 0) P.bond_dim0[b] = 1;
+  for (int s = 0; s < ns; ++s) {
+    A.d[s] = init_dims[size_t(s) * 5];
+    P.dmax[s] = std::max(P.dmax[s], A.d[s]);
+  }
+  // layers: per layer the one-site ops before the gates, the gates, then the
+  // one-site ops after them, each group in array order
+  int32_t k0 = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    int32_t k1 = k0;
+    while (k1 < n_ops && ops[k1].layer == l) ++k1;
+    A.begin_layer();
+    std::vector<char> bond_used(P.n_bonds, 0);
+    for (int pass = 0; pass < 3; ++pass)
+      for (int32_t k = k0; k < k1; ++k) {
+        const LayerOp& o = ops[k];
+        if (o.x < 0 || o.x >= lx || o.y < 0 || o.y >= ly) return "op site outside the grid";
+        if (o.det < -1 || o.det >= n_det) return "op detector index out of range";
+        if (o.kind != OP_PRE && o.kind != OP_POST && o.kind != OP_GATE_H && o.kind != OP_GATE_V)
+          return "unknown op kind";
+        const int want = o.kind == OP_PRE ? 0 : o.kind == OP_POST ? 2 : 1;
+        if (want != pass) continue;
+        const int s = o.y * lx + o.x;
+        if (pass != 1) {
+          if (o.d_out < 1 || o.d_out > 16 || o.d_in < 1 || o.d_in > 16) return "one-site op dims out of range";
+          const int64_t n = int64_t(o.d_in) * o.d_out;
+          if (!in_range(o.off0, n) || (o.det >= 0 && !in_range(o.off1, n))) return "one-site op outside values";
+          Mat M0(values + o.off0, values + o.off0 + n), M1;
+          if (o.det >= 0) M1.assign(values + o.off1, values + o.off1 + n);
+          // the assembler composes it after the site's pending op and checks
+          // its input dimension against the site's
+          std::string e =
+              pass == 0 ? A.add_pre(s, M0, o.d_out, o.det, M1) : A.add_post(s, M0, o.d_out, o.det, M1);
+          if (!e.empty()) return e;
+        } else {
+          const bool h = o.kind == OP_GATE_H;
+          if ((h && o.x + 1 >= lx) || (!h && o.y + 1 >= ly)) return "gate reaches outside the grid";
+          const int b = h ? A.hbond(o.x, o.y) : A.vbond(o.x, o.y);
+          if (bond_used[b]) return "two gates on one bond in a layer";
+          bond_used[b] = 1;
+          const int sb = h ? s + 1 : s + lx;
+          if (o.d_in != A.staged_dim(s) || o.d_out != A.staged_dim(sb)) return "gate dims differ from the sites'";
+          const int64_t n = int64_t(o.d_in) * o.d_in * o.d_out * o.d_out;
+          if (!in_range(o.off0, n) || (o.det >= 0 && !in_range(o.off1, n))) return "gate outside values";
+          std::vector<Term> t0 = svd_split(values + o.off0, o.d_in, o.d_out, split_tol), t1;
+          if (o.det >= 0) {
+            t1 = svd_split(values + o.off1, o.d_in, o.d_out, split_tol);
+            // equal term counts for both sets: pad with zero terms
+            const size_t K = std::max(t0.size(), t1.size());
+            for (std::vector<Term>* ts : {&t0, &t1})
+              while (ts->size() < K)
+                ts->push_back(Term{Mat(size_t(o.d_in) * o.d_in, 0.0), Mat(size_t(o.d_out) * o.d_out, 0.0)});
+          }
+          A.add_gate(h ? 0 : 1, o.x, o.y, std::move(t0), o.det, std::move(t1));
+        }
+      }
+    std::string e = A.end_layer();
+    if (!e.empty()) return e;
+    k0 = k1;
+  }
+  if (k0 != n_ops) return "op layer indices must be nondecreasing and below n_layers";
+  std::vector<Mat> f(ns);
+  for (int s = 0; s < ns; ++s) {
+    const int64_t off = final_off[s];
+    if (!in_range(off, A.d[s])) return "final vector outside values";
+    f[s].assign(values + off, values + off + A.d[s]);
+  }
+  A.finish(f);
+  return "";
+}
+
 }  // namespace tn3d
 

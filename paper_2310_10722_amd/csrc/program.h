@@ -97,4 +97,15 @@ std::string build_from_dem(int32_t n_det, int32_t n_mech, int64_t nnz, const int
                            const int32_t* mech_idx, const double* p_mech, int32_t n_obs, const uint8_t* obs,
                            const int32_t* det_coord, Program& out);
 
+// A generic layered network (the flat description of tn3d_net_from_layers).
+struct LayerOp {
+  int32_t layer, kind, x, y, d_in, d_out, det, pad;
+  int64_t off0, off1;
+};
+enum : int32_t { OP_PRE = 0, OP_GATE_H = 1, OP_GATE_V = 2, OP_POST = 3 };
+std::string build_from_layers(int32_t lx, int32_t ly, int32_t n_layers, int32_t n_det, int32_t n_cosets,
+                              const int32_t* init_dims, const int64_t* init_off, int32_t n_ops, const LayerOp* ops,
+                              const int64_t* final_off, const double* values, int64_t n_values, double split_tol,
+                              Program& out);
+
 }  // namespace tn3d

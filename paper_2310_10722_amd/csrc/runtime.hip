@@ -358,6 +358,8 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   // the kernels' fixed-size LDS arrays bound these (sweep.hip)
   if (L.ncap > 96) return fail(c, TN3D_E_UNSUPPORTED, "physical dim x chi above 96 on a gated site");
   if (L.kdcap > 72) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 72");
+  for (int32_t b : P.bond_dim0)
+    if (b > L.legcap) return fail(c, TN3D_E_UNSUPPORTED, "an initial bond dimension above max(chi, 2)");
   if ((L.ncap > 64 || L.kdcap > 64) && prec == TN3D_PREC_FP64 && !(pr.flags & TN3D_OPT_GRAM_FACTOR))
     return fail(c, TN3D_E_UNSUPPORTED,
                 "physical dim x chi or gate rank x chi above 64 needs the Gram route in FP64 (TN3D_OPT_GRAM_FACTOR)");
@@ -974,6 +976,19 @@ tn3d_status tn3d_net_from_dem(tn3d_ctx c, int32_t n_det, int32_t n_mech, int64_t
     (*out)->rates.assign(p_mech, p_mech + n_mech);
   }
   return s;
+}
+
+tn3d_status tn3d_net_from_layers(tn3d_ctx c, int32_t lx, int32_t ly, int32_t n_layers, int32_t n_det,
+                                 int32_t n_cosets, const int32_t* init_dims, const int64_t* init_off, int32_t n_ops,
+                                 const tn3d_layer_op* ops, const int64_t* final_off, const double* values,
+                                 int64_t n_values, double split_tol, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  static_assert(sizeof(tn3d_layer_op) == sizeof(LayerOp), "tn3d_layer_op and LayerOp must match");
+  Program P;
+  std::string e = build_from_layers(lx, ly, n_layers, n_det, n_cosets, init_dims, init_off, n_ops,
+                                    reinterpret_cast<const LayerOp*>(ops), final_off, values, n_values, split_tol, P);
+  return make_net(c, e, std::move(P), out);
 }
 
 int32_t tn3d_net_num_detectors(tn3d_net n) { return n ? n->P.n_det : -1; }

@@ -39,7 +39,7 @@ SYMBOLS = [
     "tn3d_net_num_mechanisms", "tn3d_net_num_cosets", "tn3d_net_shape", "tn3d_net_destroy",
     "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
     "tn3d_last_timing", "tn3d_last_stats", "tn3d_autotune",
-    "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached", "tn3d_grad_loglik",
+    "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached", "tn3d_grad_loglik", "tn3d_net_from_layers",
 ]
 
 
@@ -117,6 +117,9 @@ def load_library(path: str | None = None):
     lib.tn3d_grad_loglik.argtypes = [c_p, c_p, i32, c_p, c_p, ctypes.POINTER(Params), i32, c_p, c_p, c_p, c_p, c_p,
                                      c_p]
     lib.tn3d_grad_loglik.restype = i32
+    lib.tn3d_net_from_layers.argtypes = [c_p, i32, i32, i32, i32, i32, c_p, c_p, i32, c_p, c_p, c_p,
+                                         ctypes.c_int64, ctypes.c_double, ctypes.POINTER(c_p)]
+    lib.tn3d_net_from_layers.restype = i32
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
               "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_from_dem", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
@@ -301,6 +304,41 @@ def tn3d_net_from_dem(ctx: Context, H, p_mech, obs, det_coord) -> Net:
 
 
 SECTOR_POINT, SECTOR_LOOP = 0, 1
+OP_PRE, OP_GATE_H, OP_GATE_V, OP_POST = 0, 1, 2, 3
+
+
+class LayerOp(ctypes.Structure):
+    _fields_ = [("layer", ctypes.c_int32), ("kind", ctypes.c_int32), ("x", ctypes.c_int32), ("y", ctypes.c_int32),
+                ("d_in", ctypes.c_int32), ("d_out", ctypes.c_int32), ("det", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("off0", ctypes.c_int64), ("off1", ctypes.c_int64)]
+
+
+def tn3d_net_from_layers(ctx: Context, lx: int, ly: int, n_layers: int, n_det: int, init_dims, init_off, ops,
+                         final_off, values, split_tol: float = 1e-14) -> Net:
+    """A generic layered network.  init_dims int [n_cosets, lx*ly, 5],
+    init_off int [n_cosets, lx*ly], ops: sequence of (layer, kind, x, y, d_in,
+    d_out, det, off0, off1), final_off int [lx*ly], values float64 (the
+    tensors and matrices the offsets point into)."""
+    dims = np.ascontiguousarray(np.asarray(init_dims, dtype=np.int32))
+    if dims.ndim != 3 or dims.shape[1:] != (lx * ly, 5):
+        raise ValueError("init_dims must have shape [n_cosets, lx * ly, 5]")
+    ioff = np.ascontiguousarray(np.asarray(init_off, dtype=np.int64))
+    if ioff.shape != dims.shape[:2]:
+        raise ValueError("init_off must have shape [n_cosets, lx * ly]")
+    foff = np.ascontiguousarray(np.asarray(final_off, dtype=np.int64).reshape(-1))
+    if foff.size != lx * ly:
+        raise ValueError("final_off needs lx * ly entries")
+    vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(-1))
+    arr = (LayerOp * max(len(ops), 1))()
+    for i, o in enumerate(ops):
+        layer, kind, x, y, d_in, d_out, det, off0, off1 = o
+        arr[i] = LayerOp(layer, kind, x, y, d_in, d_out, det, 0, off0, off1)
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_from_layers(
+        ctx.h, lx, ly, n_layers, n_det, dims.shape[0], dims.ctypes.data, ioff.ctypes.data, len(ops),
+        ctypes.cast(arr, ctypes.c_void_p),
+        foff.ctypes.data, vals.ctypes.data, vals.size, float(split_tol), ctypes.byref(h)))
+    return Net(ctx, h)
 
 
 def tn3d_net_surface3d_wht(ctx: Context, L: int, sector: int, p_mech) -> Net:

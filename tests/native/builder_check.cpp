@@ -141,6 +141,90 @@ int main() {
     e = build_from_dem(nd, nm, 2, bad_idx.data(), bad_m.data(), p.data(), 1, obs.data(), coord.data(), P);
     expect(!e.empty(), "DEM: detector index out of range refused");
   }
+  {
+    // generic layered networks: a 3 x 2 grid, product states of two cosets,
+    // one layer with a syndrome-dependent op before the gates, dense gates of
+    // known operator-Schmidt rank on every bond (rank 1, 2 and 4), an op after
+    // them; then invalid descriptions
+    const int lx = 3, ly = 2, ns = lx * ly;
+    std::vector<double> vals;
+    auto put = [&](const std::vector<double>& v) {
+      int64_t off = int64_t(vals.size());
+      vals.insert(vals.end(), v.begin(), v.end());
+      return off;
+    };
+    std::vector<int32_t> dims(size_t(2) * ns * 5, 1);
+    std::vector<int64_t> ioff(size_t(2) * ns);
+    for (int c = 0; c < 2; ++c)
+      for (int s = 0; s < ns; ++s) {
+        dims[(size_t(c) * ns + s) * 5] = 2;
+        ioff[size_t(c) * ns + s] = put({0.3 + 0.1 * s, 0.7 - 0.05 * c});
+      }
+    std::vector<LayerOp> ops;
+    ops.push_back({0, OP_PRE, 0, 0, 2, 3, 0, 0, put({1, 0, 0, 1, 1, 1}), put({0, 1, 1, 0, 1, 1})});
+    // gates: sums of `rank` products of functions of distinct frequencies
+    // (operator-Schmidt rank 1, 2 and 4)
+    auto gate = [&](int da, int db, int rank) {
+      std::vector<double> g(size_t(da) * db * da * db, 0.0);
+      for (int a2 = 0; a2 < da; ++a2)
+        for (int b2 = 0; b2 < db; ++b2)
+          for (int a = 0; a < da; ++a)
+            for (int b = 0; b < db; ++b) {
+              double v = 0.0;
+              for (int k = 0; k < rank; ++k)
+                v += std::cos((k + 1) * (0.7 * (a2 * da + a) + 0.3)) * std::sin((k + 1) * (0.45 * (b2 * db + b) + 0.2) + k);
+              g[((size_t(a2) * db + b2) * da + a) * db + b] = v;
+            }
+      return g;
+    };
+    ops.push_back({0, OP_GATE_H, 0, 0, 3, 2, -1, 0, put(gate(3, 2, 1)), 0});
+    ops.push_back({0, OP_GATE_H, 1, 1, 2, 2, 1, 0, put(gate(2, 2, 2)), put(gate(2, 2, 4))});
+    ops.push_back({0, OP_GATE_V, 2, 0, 2, 2, -1, 0, put(gate(2, 2, 4)), 0});
+    ops.push_back({0, OP_POST, 0, 0, 3, 2, -1, 0, put({1, 1, 0, 0, 1, 1}), 0});
+    std::vector<int64_t> foff(ns);
+    for (int s = 0; s < ns; ++s) foff[s] = put({1.0, 0.5});
+    Program P;
+    std::string e = build_from_layers(lx, ly, 1, 2, 2, dims.data(), ioff.data(), int32_t(ops.size()), ops.data(),
+                                      foff.data(), vals.data(), int64_t(vals.size()), 1e-12, P);
+    expect(e.empty(), "layers: valid description built (" + e + ")");
+    if (e.empty()) {
+      check_program(P, "layers");
+      int k1 = -1, k2 = -1, k4 = -1;
+      for (const auto& g : P.gates) {
+        if (g.dA == 3) k1 = g.K;
+        else if (g.det >= 0) k2 = g.K;
+        else k4 = g.K;
+      }
+      expect(k1 == 1, "layers: a rank-1 gate splits into one term");
+      expect(k2 == 4, "layers: a syndrome-dependent gate takes the larger term count of its two sets");
+      expect(k4 == 4, "layers: a rank-4 gate splits into four terms");
+    }
+    auto bad = [&](std::vector<LayerOp> o, int nl, const char* what) {
+      Program Q;
+      std::string e2 = build_from_layers(lx, ly, nl, 2, 2, dims.data(), ioff.data(), int32_t(o.size()), o.data(),
+                                         foff.data(), vals.data(), int64_t(vals.size()), 1e-12, Q);
+      expect(!e2.empty(), std::string("layers: refused ") + what);
+    };
+    auto o = ops;
+    o[1].x = 2;
+    bad(o, 1, "a gate reaching outside the grid");
+    o = ops;
+    o[1].off0 = int64_t(vals.size()) - 2;
+    bad(o, 1, "a gate outside values");
+    o = ops;
+    o[0].det = 7;
+    bad(o, 1, "a detector index out of range");
+    o = ops;
+    o.push_back(ops[3]);
+    bad(o, 1, "two gates on one bond");
+    o = ops;
+    o[1].d_in = 2;
+    bad(o, 1, "gate dims that differ from the sites'");
+    bad(ops, 0, "zero layers");
+    o = ops;
+    o[2].layer = 1;
+    bad(o, 1, "an op beyond the last layer");
+  }
   if (fails) {
     std::fprintf(stderr, "%d checks failed\n", fails);
     return 1;
