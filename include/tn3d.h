@@ -247,8 +247,10 @@ tn3d_status tn3d_net_from_dem(tn3d_ctx ctx, int32_t n_det, int32_t n_mech, int64
  * at both ends, at most 64, and at most max(chi, 2) when contracted), its
  * values T[p][w][e][n][s] (row-major) at values[init_off[c][s]].  Then
  * n_layers layers of ops (ops[] in nondecreasing `layer` order; within a
- * layer the one-site ops before the gates act first, then the gates, then
- * the one-site ops after them, each group in array order):
+ * layer the one-site ops before the gates act first, in array order, then
+ * the gates in four classes, (x, y)-(x+1, y) with x even, then x odd, then
+ * (x, y)-(x, y+1) with y even, then y odd (the gates of a class act on
+ * disjoint bonds), then the one-site ops after the gates, in array order):
  *   TN3D_OP_PRE / TN3D_OP_POST on site (x, y): a d_out x d_in matrix
  *     (row-major [p'][p], d_in the site's current physical dim, both <= 16);
  *   TN3D_OP_GATE_H / _V on (x, y)-(x+1, y) or (x, y)-(x, y+1): a two-site

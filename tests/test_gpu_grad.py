@@ -52,9 +52,9 @@ def changed_rate(p, rate_max=1.0):
     return np.where(p <= 0.5 * rate_max, p + 0.25 * rate_max, p - 0.25 * rate_max)
 
 
-def term_tol(g, p, delta):
+def term_tol(g, p, delta, rate_max=1.0):
     """Bound on |term_gpu - term_oracle| for log-value errors <= delta."""
-    c = changed_rate(p)
+    c = changed_rate(p, rate_max)
     r = 1.0 + g * (c - p)
     return (np.abs(r) + 1.0) * np.expm1(2.0 * delta) / np.abs(c - p) + 1e-12
 
@@ -242,3 +242,37 @@ def test_grad_rotated_d7_chi16_golden(ctx, mode):
     want = reduce_to_rates(items.sum(axis=0), rate_of, nq + 7 * nZ)
     assert np.allclose(grad, want, rtol=1e-12, atol=1e-9)
     assert np.all(np.isfinite(grad))
+
+
+def test_grad_depolarizing_equal_chi(ctx):
+    """The depolarizing family (per-qubit rates in [0, 3/4], so the changed
+    rate steps 3/16; four cosets): L = 3, rates drawn per qubit in
+    [0.05, 0.3], chi = chi_m = 8, FP64 and the reduced rank rule, two
+    syndromes, against the oracle's one-sided form over its fixed-chi sweep
+    at the same chi and rule on 8 sampled qubits (log values within 1e-9)."""
+    from oracle.grad import loglik_grad_one_sided
+    from oracle.network import depol3d_network
+    from oracle.sweep import sweep_logprob
+    from paper_2310_10722_amd import tn3d
+    say("case: gradient depolarizing L=3 chi=8 fp64, 2 syndromes, 8 qubits")
+    base = synth.surface3d_depolarizing(3, 0.15)
+    pq = np.random.default_rng(46).uniform(0.05, 0.3, base.params["p_qubit"].size)
+    dem = synth.surface3d_depolarizing(3, pq)
+    m, _ = synth.sample_pauli(dem, 2, 47)
+    net = tn3d.tn3d_net_surface3d_depolarizing(ctx, 3, pq)
+    prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    grad, tot, ll, flags, items = tn3d.tn3d_grad_loglik(ctx, net, syn_of(m), prm, per_item=True)
+    items, ll = items.cpu().numpy(), ll.cpu().numpy()
+    idx = list(np.random.default_rng(48).choice(pq.size, 8, replace=False))
+    for k in range(2):
+        def cosets(q):
+            return [sweep_logprob(depol3d_network(3, q, m[k], c), 8, 8, prm.eps_rel, prm.tau_gap)[0]
+                    for c in range(4)]
+        lp, g = loglik_grad_one_sided(cosets, pq, idx, rate_max=0.75)
+        tol = term_tol(g, pq[idx], 1e-9, rate_max=0.75)
+        err = np.abs(items[k, idx] - g)
+        say(f"  syndrome {k}: max |d term| = {err.max():.3g} (relative to its bound {(err / tol).max():.3g}),"
+            f" |d log P| = {abs(ll[k] - lp):.3g}")
+        assert np.all(err <= tol)
+        assert abs(ll[k] - lp) <= 1e-9
