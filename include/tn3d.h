@@ -279,6 +279,18 @@ tn3d_status tn3d_net_from_layers(tn3d_ctx ctx, int32_t lx, int32_t ly, int32_t n
                                  const tn3d_layer_op* ops, const int64_t* final_off, const double* values,
                                  int64_t n_values, double split_tol, tn3d_net* out);
 
+/* Gauge rounds (paper Sec. 6: better truncation environments by repeated
+ * simple updates with trivial gates, towards the Vidal gauge): a new network
+ * equal to `base` (same builder, rates or layers) with `rounds` (0..16)
+ * rounds of identity gates on every bond before each layer after the first.
+ * A round runs the four bond classes in the layer order, each gate truncated
+ * by the rank rule at the chi cap of the layer before it (no bond grows), and
+ * rescales like a layer; the contracted value is unchanged where nothing is
+ * truncated.  tn3d_net_shape reports the layers of the network, without the
+ * rounds; chi-schedules count those layers too.  Errors: TN3D_E_INVALID,
+ * TN3D_E_UNSUPPORTED (a network without a recorded builder). */
+tn3d_status tn3d_net_with_gauge_rounds(tn3d_ctx ctx, tn3d_net base, int32_t rounds, tn3d_net* out);
+
 int32_t tn3d_net_num_detectors(tn3d_net net);
 int32_t tn3d_net_num_mechanisms(tn3d_net net);
 int32_t tn3d_net_num_cosets(tn3d_net net);

@@ -36,7 +36,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .network import E_, N_, S_, W_, LayeredNet
+from .network import E_, N_, S_, W_, Layer, LayeredNet
 
 FLAG_TRUNC_CLUSTER = 1 << 1
 FLAG_NUMERIC = 1 << 0
@@ -66,8 +66,12 @@ def _svd(A, driver):
 
 class Sweep:
     def __init__(self, net: LayeredNet, chi, chi_m, eps_rel=1e-9, tau_gap=1e-6,
-                 svd_driver="gesdd", chi_layers=None):
+                 svd_driver="gesdd", chi_layers=None, gauge_rounds=0):
         self.net = net
+        # rounds of identity gates on every bond before each layer after the
+        # first (simple update with trivial gates: the bond environments move
+        # towards the Vidal gauge before the layer's truncations)
+        self.gauge_rounds = gauge_rounds
         self.Lx, self.Ly = net.Lx, net.Ly
         self.chi, self.chi_m = chi, chi_m
         # chi-schedule: the gates of layer l keep at most
@@ -248,8 +252,29 @@ class Sweep:
             return np.nan
         return logscale + np.log(z)
 
+    def gauge_round(self):
+        """Identity gates on every bond, the four classes in the layer order,
+        each truncated at the current cap (that of the layer before), then the
+        per-site rescale of a layer."""
+        Lx, Ly = self.Lx, self.Ly
+        gates = []
+        for y in range(Ly):
+            for x in range(Lx):
+                s = y * Lx + x
+                dA = self.G[s].shape[0]
+                if x + 1 < Lx:
+                    dB = self.G[s + 1].shape[0]
+                    gates.append(("H", x, y, np.einsum("ac,bd->abcd", np.eye(dA), np.eye(dB))))
+                if y + 1 < Ly:
+                    dB = self.G[s + Lx].shape[0]
+                    gates.append(("V", x, y, np.einsum("ac,bd->abcd", np.eye(dA), np.eye(dB))))
+        self.layer(Layer(gates=gates))
+
     def run(self):
         for li, lay in enumerate(self.net.layers):
+            if li > 0:
+                for _ in range(self.gauge_rounds):
+                    self.gauge_round()
             if self.chi_layers:
                 self.chi_cur = min(self.chi, self.chi_layers[min(li, len(self.chi_layers) - 1)])
             self.layer(lay)
@@ -258,12 +283,13 @@ class Sweep:
 
 
 def sweep_logprob(net: LayeredNet, chi, chi_m=None, eps_rel=1e-9, tau_gap=1e-6,
-                  svd_driver="gesdd", chi_layers=None):
+                  svd_driver="gesdd", chi_layers=None, gauge_rounds=0):
     """log of the approximate contraction value of one network; returns
     (logp, flags, n_cluster_splits).  The rank rule defaults to the FP64 rule
     (eps_rel 1e-9, tau_gap 1e-6); a strict rule (1e-12, 1e-9) is passed
     explicitly where the exact limit is compared."""
-    sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver, chi_layers)
+    sw = Sweep(net, chi, chi if chi_m is None else chi_m, eps_rel, tau_gap, svd_driver, chi_layers,
+               gauge_rounds)
     try:
         lp = sw.run()
     except FloatingPointError:

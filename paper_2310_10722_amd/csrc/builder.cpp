@@ -15,6 +15,11 @@
 #include "program.h"
 
 namespace tn3d {
+
+static thread_local int g_gauge_rounds = 0;
+GaugeRounds::GaugeRounds(int rounds) : saved(g_gauge_rounds) { g_gauge_rounds = rounds; }
+GaugeRounds::~GaugeRounds() { g_gauge_rounds = saved; }
+
 namespace {
 
 using Mat = std::vector<double>;  // row-major dout x din
@@ -231,6 +236,23 @@ class Assembler {
   };
 
   void begin_layer() {
+    // gauge rounds before every layer but the first: identity gates on all
+    // bonds at the current physical dims (their own layers, marked gauge)
+    if (!P.layers.empty())
+      for (int r = 0; r < g_gauge_rounds; ++r) {
+        reset_layer();
+        for (int y = 0; y < Ly; ++y)
+          for (int x = 0; x < Lx; ++x) {
+            const int s = y * Lx + x;
+            if (x + 1 < Lx) add_gate(0, x, y, {Term{eye(d[s]), eye(d[s + 1])}});
+            if (y + 1 < Ly) add_gate(1, x, y, {Term{eye(d[s]), eye(d[s + Lx])}});
+          }
+        end_layer();
+        P.layers.back().gauge = 1;
+      }
+    reset_layer();
+  }
+  void reset_layer() {
     for (auto& p : pre) p = Pending{};
     for (auto& p : post) p = Pending{};
     gates.clear();

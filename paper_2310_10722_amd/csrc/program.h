@@ -48,6 +48,7 @@ struct LayerRange {
   int32_t pre0, pre1;      // [pre0, pre1) in the one-site op array
   int32_t gate0[4], gate1[4];
   int32_t post0, post1;
+  int32_t gauge;           // 1: a gauge round (identity gates on every bond), not a layer of the network
 };
 
 struct Program {
@@ -86,6 +87,16 @@ struct Program {
   int32_t wht = 0;
   // every rate of the builder lies in [0, rate_max] (3/4 for depolarizing noise)
   double rate_max = 1.0;
+};
+
+// Gauge rounds: while a GaugeRounds object lives on this thread, the builders
+// put `rounds` rounds of identity gates on every bond before each layer after
+// the first (simple update with trivial gates, which moves the bond
+// environments towards the Vidal gauge before the layer's truncations).
+struct GaugeRounds {
+  explicit GaugeRounds(int rounds);
+  ~GaugeRounds();
+  int saved;
 };
 
 // Builders; return an empty string on success, else an error message.

@@ -114,8 +114,10 @@ struct tn3d_net_s {
   uint64_t* d_ext = nullptr;  // derived-bit rows (Program::ext_rows), or null
   int max_gates_class = 0;
   uint64_t tune_serial = 0;  // launch shapes come from the autotuner's entry of this network
-  // the builder call that made P, for networks at other rates (gradients)
-  std::function<std::string(const double*, Program&)> rebuild;
+  // the builder call that made P (gauge rounds included), for networks at
+  // other rates (gradients); build_plain without the gauge rounds
+  std::function<std::string(const double*, Program&)> rebuild, build_plain;
+  int gauge_rounds = 0;
   std::vector<double> rates;  // the builder's rate array (P.n_mech entries)
   // tn3d_grad_loglik: per mechanism i, this network with rate i at var_c[i],
   // as pool copy var_slot[i] of d_pool_all (copy 0 is this network's pool)
@@ -235,7 +237,8 @@ tn3d_status build_net(tn3d_ctx c, std::function<std::string(const double*, Progr
   std::string e = f(p, P);
   tn3d_status s = make_net(c, e, std::move(P), out);
   if (s == TN3D_OK) {
-    (*out)->rebuild = std::move(f);
+    (*out)->rebuild = f;
+    (*out)->build_plain = std::move(f);
     (*out)->rates.assign(p, p + (*out)->P.n_mech);
   }
   return s;
@@ -533,9 +536,12 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
       launch_stamp(stamp + 0, s);
     }
     launch_init(prec, A, n->d_init_dims, n->d_init_off, n->d_bond_dim0, s);
+    size_t real_layer = 0;  // the chi-schedule counts the network's layers, not gauge rounds
+    int32_t cut = pr.chi;
     for (size_t li = 0; li < P.layers.size(); ++li) {
       const LayerRange& R = P.layers[li];
-      A.chi_cut = layer_chi(pr, li);
+      if (!R.gauge) cut = layer_chi(pr, real_layer++);
+      A.chi_cut = cut;  // gauge rounds keep the cap of the layer before them
       launch_onesite(prec, A, n->d_ones + R.pre0, R.pre1 - R.pre0, s);
       for (int k = 0; k < 4; ++k) {
         const int ng = R.gate1[k] - R.gate0[k];
@@ -973,6 +979,7 @@ tn3d_status tn3d_net_from_dem(tn3d_ctx c, int32_t n_det, int32_t n_mech, int64_t
   tn3d_status s = make_net(c, e, std::move(P), out);
   if (s == TN3D_OK) {
     (*out)->rebuild = f;
+    (*out)->build_plain = f;
     (*out)->rates.assign(p_mech, p_mech + n_mech);
   }
   return s;
@@ -988,7 +995,43 @@ tn3d_status tn3d_net_from_layers(tn3d_ctx c, int32_t lx, int32_t ly, int32_t n_l
   Program P;
   std::string e = build_from_layers(lx, ly, n_layers, n_det, n_cosets, init_dims, init_off, n_ops,
                                     reinterpret_cast<const LayerOp*>(ops), final_off, values, n_values, split_tol, P);
-  return make_net(c, e, std::move(P), out);
+  tn3d_status s = make_net(c, e, std::move(P), out);
+  if (s == TN3D_OK) {
+    // the builder has checked the arrays: copies for rebuilds with gauge rounds
+    const int64_t nc = n_cosets, ns = int64_t(lx) * ly;
+    std::vector<int32_t> dv(init_dims, init_dims + nc * ns * 5);
+    std::vector<int64_t> iv(init_off, init_off + nc * ns), fv(final_off, final_off + ns);
+    std::vector<LayerOp> ov(reinterpret_cast<const LayerOp*>(ops), reinterpret_cast<const LayerOp*>(ops) + n_ops);
+    std::vector<double> vv(values, values + n_values);
+    (*out)->build_plain = [=](const double*, Program& Q) {
+      return build_from_layers(lx, ly, n_layers, n_det, n_cosets, dv.data(), iv.data(), n_ops, ov.data(), fv.data(),
+                               vv.data(), int64_t(vv.size()), split_tol, Q);
+    };
+  }
+  return s;
+}
+
+tn3d_status tn3d_net_with_gauge_rounds(tn3d_ctx c, tn3d_net base, int32_t rounds, tn3d_net* out) {
+  if (!c || !out) return TN3D_E_INVALID;
+  *out = nullptr;
+  if (!base || base->ctx != c) return fail(c, TN3D_E_INVALID, "network handle null or of another context");
+  if (rounds < 0 || rounds > 16) return fail(c, TN3D_E_INVALID, "rounds must lie in [0, 16]");
+  if (!base->build_plain) return fail(c, TN3D_E_UNSUPPORTED, "network without a recorded builder");
+  auto plain = base->build_plain;
+  auto f = [plain, rounds](const double* q, Program& Q) {
+    GaugeRounds g(rounds);
+    return plain(q, Q);
+  };
+  Program P;
+  std::string e = f(base->rates.data(), P);
+  tn3d_status s = make_net(c, e, std::move(P), out);
+  if (s == TN3D_OK) {
+    (*out)->build_plain = plain;
+    (*out)->gauge_rounds = rounds;
+    (*out)->rates = base->rates;
+    if (base->rebuild) (*out)->rebuild = f;
+  }
+  return s;
 }
 
 int32_t tn3d_net_num_detectors(tn3d_net n) { return n ? n->P.n_det : -1; }
@@ -999,7 +1042,8 @@ void tn3d_net_shape(tn3d_net n, int32_t* lx, int32_t* ly, int32_t* nl) {
   if (!n) return;
   if (lx) *lx = n->P.Lx;
   if (ly) *ly = n->P.Ly;
-  if (nl) *nl = int32_t(n->P.layers.size());
+  if (nl) *nl = int32_t(std::count_if(n->P.layers.begin(), n->P.layers.end(),
+                                      [](const LayerRange& r) { return r.gauge == 0; }));
 }
 
 static void drop_variants(tn3d_net net);

@@ -40,6 +40,7 @@ SYMBOLS = [
     "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc", "tn3d_decode", "tn3d_ctx_set_timing",
     "tn3d_last_timing", "tn3d_last_stats", "tn3d_autotune",
     "tn3d_ctx_set_graphs", "tn3d_ctx_graphs_cached", "tn3d_grad_loglik", "tn3d_net_from_layers",
+    "tn3d_net_with_gauge_rounds",
 ]
 
 
@@ -120,6 +121,8 @@ def load_library(path: str | None = None):
     lib.tn3d_net_from_layers.argtypes = [c_p, i32, i32, i32, i32, i32, c_p, c_p, i32, c_p, c_p, c_p,
                                          ctypes.c_int64, ctypes.c_double, ctypes.POINTER(c_p)]
     lib.tn3d_net_from_layers.restype = i32
+    lib.tn3d_net_with_gauge_rounds.argtypes = [c_p, c_p, i32, ctypes.POINTER(c_p)]
+    lib.tn3d_net_with_gauge_rounds.restype = i32
     lib.tn3d_last_stats.restype = i32
     for f in ("tn3d_ctx_create", "tn3d_net_surface3d_point", "tn3d_net_rotated_phenom",
               "tn3d_net_surface3d_depolarizing", "tn3d_net_surface3d_loop", "tn3d_net_surface3d_wht", "tn3d_net_from_dem", "tn3d_contract_cosets", "tn3d_contract_cosets_noalloc",
@@ -305,6 +308,14 @@ def tn3d_net_from_dem(ctx: Context, H, p_mech, obs, det_coord) -> Net:
 
 SECTOR_POINT, SECTOR_LOOP = 0, 1
 OP_PRE, OP_GATE_H, OP_GATE_V, OP_POST = 0, 1, 2, 3
+
+
+def tn3d_net_with_gauge_rounds(ctx: Context, base: Net, rounds: int) -> Net:
+    """`base` with `rounds` rounds of identity gates on every bond before each
+    layer after the first."""
+    h = ctypes.c_void_p()
+    _check(ctx.lib, ctx.h, ctx.lib.tn3d_net_with_gauge_rounds(ctx.h, base.h, int(rounds), ctypes.byref(h)))
+    return Net(ctx, h)
 
 
 class LayerOp(ctypes.Structure):

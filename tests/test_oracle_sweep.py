@@ -111,3 +111,45 @@ def test_chi_schedule_pins():
             # a binding cap in the first layer changes the value
             cut = sweep_logprob(net, 16, 64, 1e-12, 1e-9, chi_layers=[2, 8])[0]
             assert abs(cut - ex) > 1e-8
+
+
+def test_gauge_rounds_keep_the_exact_value():
+    # where chi truncates nothing, identity gates change no value
+    import synth
+    from oracle.exact import frontier_logprobs
+    from oracle.network import rotated_network
+    dem = synth.rotated_phenom(3, 2, 0.05, 0.05)
+    dem = dem.with_p(np.random.default_rng(9).uniform(0.02, 0.3, dem.n_mech))
+    m, _ = synth.sample_syndromes(dem, 3, 10)
+    for k in range(3):
+        ex = frontier_logprobs(dem.H, dem.p, dem.obs, m[k])
+        for c in range(2):
+            net = rotated_network(3, 2, dem.params["checks"], dem.p, m[k], c)
+            lp = sweep_logprob(net, 16, 64, 1e-12, 1e-9, gauge_rounds=2)[0]
+            assert abs(lp - ex[c]) <= 1e-9
+
+
+def test_gauge_rounds_reach_the_schmidt_values_on_a_chain():
+    # a 4-site chain (a tree): simple update with trivial gates converges to
+    # the canonical form, whose bond weights are the Schmidt values of the
+    # state across each bond (from a dense SVD), the largest scaled to 1
+    from oracle.network import Layer, LayeredNet
+    from oracle.sweep import Sweep
+    rng = np.random.default_rng(12)
+    init = [rng.uniform(0.2, 1, 2).reshape(2, 1, 1, 1, 1) for _ in range(4)]
+    gates = [("H", x, 0, rng.uniform(0, 1, (2, 2, 2, 2))) for x in range(3)]
+    net = LayeredNet(Lx=4, Ly=1, init=init, layers=[Layer(gates=gates)], final=[np.ones(2)] * 4)
+    sw = Sweep(net, 64, 64, 1e-14, 1e-12)
+    sw.layer(net.layers[0])
+    for _ in range(8):
+        sw.gauge_round()
+    # the dense state: product state, then the gates in class order
+    psi = np.einsum("a,b,c,d->abcd", *[t.reshape(2) for t in init])
+    for (k, x, y, G) in sorted(gates, key=lambda g: g[1] % 2):
+        psi = np.moveaxis(np.tensordot(G, psi, axes=([2, 3], [x, x + 1])), [0, 1], [x, x + 1])
+    for x in range(3):
+        S = np.linalg.svd(psi.reshape(2 ** (x + 1), -1), compute_uv=False)
+        S = S[S > 1e-12 * S[0]] / S[0]
+        lam = np.sort(sw.lamH[(x, 0)])[::-1]
+        lam = lam[: S.size] / lam[0]
+        np.testing.assert_allclose(lam, S, rtol=1e-8, atol=1e-10)
