@@ -35,7 +35,8 @@ The JSON line also reports
 
 Other workloads: --config 6 (the same L = 8 code and error draws in the loop
 sector, bit flips seen by the faces, below its threshold at p = 0.2),
---config 2 (rotated d=5, phenomenological, chi = 16, FP64), --config 4
+--config 2 (rotated d=5, phenomenological, chi = 16 or --chi, FP64, optionally
+with --gauge-rounds rounds of identity gates before each layer), --config 4
 (depolarizing, ragged L in {4, 5, 6}), --config 5 (the gradient of the
 syndrome log-likelihood with respect to 217 rates, rotated d=7, chi = 16).
 """
@@ -110,7 +111,8 @@ def cpu_model():
 
 
 def _oracle_one(args):
-    fam, prm_fam, p, m, c, chi, chi_m, eps, tau = args
+    fam, prm_fam, p, m, c, chi, chi_m, eps, tau = args[:9]
+    rounds = args[9] if len(args) > 9 else 0
     from oracle.network import point3d_network, rotated_network
     from oracle.sweep import sweep_logprob
     if fam == "rotated":
@@ -123,15 +125,15 @@ def _oracle_one(args):
         net = depol3d_network(prm_fam["L"], p, m, c)
     else:
         net = point3d_network(prm_fam["L"], p, m, c)
-    return sweep_logprob(net, chi, chi_m, eps, tau)[0]
+    return sweep_logprob(net, chi, chi_m, eps, tau, gauge_rounds=rounds)[0]
 
 
-def cpu_oracle(fam, prm_fam, p, ms, prm, workers):
+def cpu_oracle(fam, prm_fam, p, ms, prm, workers, gauge_rounds=0):
     """The oracle on every (syndrome, coset) of ms, one sweep per task, on a
     pool of `workers` single-threaded processes; returns (logp [n, 2], wall s)."""
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
-    jobs = [(fam, prm_fam, p, ms[i], c, prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap)
+    jobs = [(fam, prm_fam, p, ms[i], c, prm.chi, prm.chi_mps, prm.eps_rel, prm.tau_gap, gauge_rounds)
             for i in range(len(ms)) for c in range(2)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(workers) as pool:
@@ -332,8 +334,12 @@ def bench_rotated_d5(a, tn3d, np, torch):
     B = m.shape[0]
     ctx = tn3d.Context(0)
     net = tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p)
-    prm = tn3d.tn3d_params_default(16, 16, tn3d.PREC_FP64)
+    if a.gauge_rounds > 0:
+        net = tn3d.tn3d_net_with_gauge_rounds(ctx, net, a.gauge_rounds)
+    prm = tn3d.tn3d_params_default(a.chi if a.chi_given else 16, a.chi if a.chi_given else 16, tn3d.PREC_FP64)
     prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    if a.gram_route:
+        prm.flags = tn3d.OPT_GRAM_FACTOR
     syn = torch.from_numpy(m).to("cuda:0")
     tune = None if a.no_autotune else autotune_entry(tn3d, ctx, net, syn, prm, "the whole batch")
     for _ in range(a.warmup):
@@ -349,11 +355,13 @@ def bench_rotated_d5(a, tn3d, np, torch):
            "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Bernoulli error samples of the code's DEM)",
            "config": {"workload": "rotated d=5 surface code, phenomenological p=q=0.03, 5 noisy + 1 perfect rounds, "
-                                  "5x6 grid x 4 layers, chi=16, chi_mps=16, 1024 syndromes x 2 cosets",
-                      "global_batch": B}, "roofline": None, "autotune": tune}
+                                  f"5x6 grid x 4 layers, chi={prm.chi}, chi_mps={prm.chi_mps}, 1024 syndromes x 2 "
+                                  f"cosets, gauge rounds {a.gauge_rounds}, FP64 "
+                                  f"{'Gram' if a.gram_route else 'orthogonal'} route", "global_batch": B},
+           "roofline": None, "autotune": tune}
     if not a.no_cpu:
         n = min(a.cpu_sample, B)
-        ref, cdt = cpu_oracle("rotated", dict(dem.params), dem.p, m[:n], prm, CPU_WORKERS)
+        ref, cdt = cpu_oracle("rotated", dict(dem.params), dem.p, m[:n], prm, CPU_WORKERS, a.gauge_rounds)
         out["cpu_baseline"] = {"value": n / cdt, "unit": "syndromes/s", "cores": CPU_WORKERS, "kind": "oracle",
                                "cpu_model": cpu_model(), "sample": f"first {n} syndromes, both cosets"}
         out["accuracy"] = accuracy(np, logp[:n, :2], ref, coset[:n])
@@ -575,7 +583,11 @@ def main():
                          "2: rotated d=5; 4: depolarizing, ragged L in {4, 5, 6}; 5: the rate gradient, rotated d=7")
     ap.add_argument("--precision", default=None, choices=("bf16", "fp32", "fp64"),
                     help="--config 3 and 6 (default bf16), --config 4 and 5 (default fp32)")
-    ap.add_argument("--chi", type=int, default=24, help="chi = chi_mps for --config 4")
+    ap.add_argument("--chi", type=int, default=None, help="chi = chi_mps for --config 4 (default 24) and 2 (16)")
+    ap.add_argument("--gram-route", action="store_true",
+                    help="--config 2: FP64 through Grams (TN3D_OPT_GRAM_FACTOR) instead of orthogonal factorisations")
+    ap.add_argument("--gauge-rounds", type=int, default=0,
+                    help="--config 2: rounds of identity gates on every bond before each layer")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
@@ -586,6 +598,9 @@ def main():
                     help="only copy a MIB-sized device buffer once (the calibration run for the HBM byte "
                          "counters of a profiler) and exit")
     a = ap.parse_args()
+    a.chi_given = a.chi is not None
+    if a.chi is None:
+        a.chi = 24
     big = a.config in (3, 5, 6)
     if a.steps is None:
         a.steps = 3 if big else 5
