@@ -107,3 +107,29 @@ def test_gauge_rounds_invalid(ctx):
     for r in (-1, 17):
         with pytest.raises(tn3d.Tn3dError, match="INVALID"):
             tn3d.tn3d_net_with_gauge_rounds(ctx, base, r)
+
+
+def test_gauge_rounds_with_chi_schedule(ctx):
+    """A chi-schedule counts the network's layers, not the gauge rounds; a
+    round keeps the cap of the layer before it: rotated d = 5, schedule
+    (4, 6, 8, 8, 6), one round, FP64, against the oracle with the same
+    schedule and rounds (1e-9 or twice the driver spread)."""
+    from paper_2310_10722_amd import tn3d
+    say("case: gauge rounds 1 with chi-schedule (4, 6, 8, 8, 6), rotated d=5 fp64, 6 syndromes")
+    dem, m, _, _ = synth.config_workload(2, n=6)
+    net = tn3d.tn3d_net_with_gauge_rounds(ctx, tn3d.tn3d_net_rotated_phenom(ctx, 5, 5, dem.p), 1)
+    sched = [4, 6, 8, 8, 6]
+    prm = tn3d.tn3d_params_default(8, 8, tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    prm.set_chi_schedule(sched)
+    got, _ = gpu_logp(tn3d, ctx, net, m, prm)
+
+    def ref(drv):
+        return np.array([[sweep_logprob(rotated_network(5, 5, dem.params["checks"], dem.p, m[k], c), 8, 8,
+                                        prm.eps_rel, prm.tau_gap, svd_driver=drv, chi_layers=sched,
+                                        gauge_rounds=1)[0] for c in range(2)] for k in range(6)])
+    r0 = ref("gesdd")
+    spread = np.abs(ref("gesvd") - r0)
+    err = np.abs(got - r0)
+    say("  max |d log p| =", err.max(), " driver spread", spread.max())
+    assert np.all(err <= np.maximum(1e-9, 2.0 * spread))

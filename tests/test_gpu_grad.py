@@ -276,3 +276,49 @@ def test_grad_depolarizing_equal_chi(ctx):
             f" |d log P| = {abs(ll[k] - lp):.3g}")
         assert np.all(err <= tol)
         assert abs(ll[k] - lp) <= 1e-9
+
+
+@pytest.mark.parametrize("family", ["loop_L4", "wht_point_L3"])
+def test_grad_truncating_families_equal_chi(ctx, family):
+    """The loop sector (L = 4, chi = chi_m = 8, truncating) and the
+    Walsh-Hadamard form of the point sector (L = 3, chi = chi_m = 4): FP64 and
+    the reduced rule, two syndromes, 6 sampled mechanisms, against the
+    oracle's one-sided form over its sweep of the same networks at the same
+    chi (log values within 1e-9; the Walsh-Hadamard form from the signed
+    sweeps of Z_0, Z_1 combined as P_L = (Z_0 + (-1)^L Z_1) / 2)."""
+    from oracle.grad import loglik_grad_one_sided
+    from oracle.network import loop3d_network, point3d_network_wht
+    from oracle.sweep import sweep_logprob, sweep_signed
+    from paper_2310_10722_amd import tn3d
+    say(f"case: gradient {family}, truncating chi, fp64, 2 syndromes, 6 mechanisms")
+    prm = tn3d.tn3d_params_default(8 if family == "loop_L4" else 4, 8 if family == "loop_L4" else 4,
+                                   tn3d.PREC_FP64)
+    prm.eps_rel, prm.tau_gap = 1e-6, 1e-4
+    if family == "loop_L4":
+        base = synth.surface3d_loop(4, 0.1)
+        dem = base.with_p(np.random.default_rng(51).uniform(0.03, 0.2, base.n_mech))
+        net = tn3d.tn3d_net_surface3d_loop(ctx, 4, dem.p)
+    else:
+        base = synth.surface3d_point(3, 0.1)
+        dem = base.with_p(np.random.default_rng(52).uniform(0.03, 0.2, base.n_mech))
+        net = tn3d.tn3d_net_surface3d_wht(ctx, 3, tn3d.SECTOR_POINT, dem.p)
+    m, _ = synth.sample_syndromes(dem, 2, 53)
+    grad, tot, ll, flags, items = tn3d.tn3d_grad_loglik(ctx, net, syn_of(m), prm, per_item=True)
+    items, ll = items.cpu().numpy(), ll.cpu().numpy()
+    idx = list(np.random.default_rng(54).choice(dem.n_mech, 6, replace=False))
+    for k in range(2):
+        def cosets(q):
+            if family == "loop_L4":
+                return [sweep_logprob(loop3d_network(4, q, m[k], c), prm.chi, prm.chi_mps, prm.eps_rel,
+                                      prm.tau_gap)[0] for c in range(2)]
+            z = [sweep_signed(point3d_network_wht(3, q, m[k], b), prm.chi, prm.chi_mps, prm.eps_rel,
+                              prm.tau_gap) for b in range(2)]
+            v = [z[0][1] * np.exp(z[0][0]), z[1][1] * np.exp(z[1][0])]
+            return [np.log((v[0] + (-1) ** L * v[1]) / 2.0) if (v[0] + (-1) ** L * v[1]) > 0 else np.nan
+                    for L in range(2)]
+        lp, g = loglik_grad_one_sided(cosets, dem.p, idx)
+        tol = term_tol(g, dem.p[idx], 1e-9)
+        err = np.abs(items[k, idx] - g)
+        say(f"  syndrome {k}: max |d term| = {err.max():.3g} (relative to its bound {(err / tol).max():.3g})")
+        assert np.all(err <= tol)
+        assert abs(ll[k] - lp) <= 1e-9
