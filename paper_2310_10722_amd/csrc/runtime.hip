@@ -250,6 +250,9 @@ struct Layout {
   int64_t sbig = 0;  // doubles per (sweep, gate) of the order-above-64 truncation scratch
   std::vector<int64_t> site_off, fin_off;
   int64_t sweep_stride = 0, fin_stride = 0;
+  // the final tensors (FP64, without the physical leg) fit in the site slots
+  // of the parity the last layer left free, and are written there
+  bool fin_alias = false;
   int64_t mcap = 0, kcap = 0, bigcap = 0, jcap = 0;
   int eig_ys = 1;
   size_t per_sweep_bytes = 0;
@@ -288,13 +291,16 @@ Layout make_layout(const Program& P, int chi, int chi_m, int prec, int max_g) {
   // the subspace iteration of large families: four blocks of 64 vectors
   L.jcap = std::max<int64_t>(L.jcap, int64_t(4) * 64 * cm * L.legcap);
   const size_t esz = prec == TN3D_PREC_FP64 ? 8 : 4;
+  L.fin_alias = true;
+  for (int s = 0; s < ns; ++s)
+    if (size_t(P.dmax[s]) * esz < 8) L.fin_alias = false;
   size_t b = 0;
   b += 2 * L.sweep_stride * esz;
   b += P.n_bonds * (4 + 8 + 8 * size_t(L.legcap)) + P.Lx * P.Ly * 8 + 4;
   b += size_t(max_g) * 2 * (2 * L.ncap * L.ncap + 2) * 8 + size_t(max_g) * 4;
   L.sbig = L.kdcap > 64 ? int64_t(L.kdcap) * L.kdcap : 0;
   b += size_t(max_g) * L.sbig * 8;
-  b += L.fin_stride * 8;
+  if (!L.fin_alias) b += L.fin_stride * 8;
   b += size_t(2) * P.Lx * L.mcap * 8 + size_t(2) * P.Lx * 3 * 4 + L.kcap * 8 + 3 * 4 + 3 * L.bigcap * 8 + L.jcap * 8 + 8 + 4 + 12 * 4 + 1024 * 8;
   L.per_sweep_bytes = b + 64 * 20;
   return L;
@@ -391,6 +397,15 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   int64_t chunk_items = int64_t((budget - fixed) / (L.per_sweep_bytes * nc));
   chunk_items = std::max<int64_t>(1, std::min<int64_t>(chunk_items, int64_t(items.size())));
   chunk_items = std::min<int64_t>(chunk_items, 65535 / nc);  // grid y dimension
+  {
+    // as many chunks as the cap needs, of equal size: a ragged last chunk
+    // runs the latency-bound kernels at low occupancy, and a chunk a little
+    // above a multiple of the CU count puts a second wave of the
+    // one-workgroup-per-CU kernels behind the first
+    const int64_t n_it = int64_t(items.size());
+    const int64_t n_chunks = (n_it + chunk_items - 1) / chunk_items;
+    chunk_items = (n_it + n_chunks - 1) / n_chunks;
+  }
   const int64_t nsw_max = chunk_items * nc;
   // carve the workspace
   Carver cv;
@@ -409,7 +424,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   size_t o_w = cv.take<double>(nsw_max * max_g * 2 * (2 + L.ncap * L.ncap));
   size_t o_gn = cv.take<int32_t>(nsw_max * max_g);
   size_t o_sbig = cv.take<double>(std::max<int64_t>(1, nsw_max * max_g * L.sbig));
-  size_t o_fin = cv.take<double>(nsw_max * L.fin_stride);
+  size_t o_fin = cv.take<double>(L.fin_alias ? 1 : nsw_max * L.fin_stride);
   size_t o_mps0 = cv.take<double>(nsw_max * P.Lx * L.mcap);
   size_t o_mps1 = cv.take<double>(nsw_max * P.Lx * L.mcap);
   size_t o_mdim = cv.take<int32_t>(nsw_max * 2 * P.Lx * 3);
@@ -460,6 +475,17 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   }
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(ws + o_soff, L.site_off.data(), L.site_off.size() * 8, hipMemcpyHostToDevice, s));
+  if (L.fin_alias) {
+    // site s's final tensor goes to its slot of the parity the last layer
+    // left free (a slot holds dmax[s] >= 8 / esz times the final tensor's
+    // elements): offsets in doubles from buf0, 8-byte aligned since slots
+    // and sweeps start at multiples of 64 elements
+    const int ns = P.Lx * P.Ly;
+    const int32_t* pf = P.par_after.data() + (P.layers.size() - 1) * size_t(ns);
+    for (int si = 0; si < ns; ++si)
+      L.fin_off[si] = (int64_t(pf[si] ? 0 : o_buf1 - o_buf0) + L.site_off[si] * int64_t(esz)) / 8;
+    L.fin_stride = L.sweep_stride * int64_t(esz) / 8;
+  }
   HIPCHK(c, hipMemcpyAsync(ws + o_foff, L.fin_off.data(), L.fin_off.size() * 8, hipMemcpyHostToDevice, s));
   bool contiguous = true;
   for (size_t i = 1; i < items.size(); ++i)
@@ -571,7 +597,7 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
     HIPCHK(c, hipGetLastError());
     if (timing) launch_stamp(stamp + 1, s);
     const int32_t* par_final = n->d_par_after + (P.layers.size() - 1) * A.n_sites;
-    double* fin = reinterpret_cast<double*>(ws + o_fin);
+    double* fin = reinterpret_cast<double*>(ws + (L.fin_alias ? o_buf0 : o_fin));
     launch_finalize(prec, A, n->d_d_final, n->d_f_off, par_final, fin, L.fin_stride,
                     reinterpret_cast<int64_t*>(ws + o_foff), s);
     Z.n_sweeps = A.n_sweeps;
