@@ -1032,6 +1032,11 @@ __global__ __launch_bounds__(64) void k_reabsorb(SweepArgs A, const DevGate* gat
   win_close(A.win, w0);
 }
 
+// A workgroup of one wavefront: this wave's LDS accesses so far complete
+// before any that follow, and the compiler moves no memory access across.
+// Global stores still in flight are not waited for (__syncthreads would).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // The reabsorption T' = T W on the matrix cores, for rows of up to NMAX
 // (32 or 64) entries: one wavefront per (gate side, sweep), chunks of 32
 // rows.  A chunk of T is fetched in memory order (as k_gram2: consecutive
@@ -1049,6 +1054,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                   int ncap, int nlo) {
   constexpr int NL = GR * NMAX / 64;  // elements a lane moves per chunk
   constexpr int KB = BF ? NMAX / 32 : 1, KS = BF ? 1 : NMAX / 4;
+  static_assert(NMAX == 64 && GR == 32, "the chunk's lane assignment assumes 32 rows of 64 columns");
   const int gi = blockIdx.x >> 1, side = blockIdx.x & 1, sweep = blockIdx.y, lane = threadIdx.x;
   const DevGate g = gates[gi];
   const int site = side ? g.sb : g.sa, leg = side ? g.lb : g.la;
@@ -1122,15 +1128,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       rb_in[lane] = bi;
       rb_out[lane] = bo;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int j = 0; j < NL; ++j) {
-      const int e = lane + 64 * j;
-      const int rl = rowfast ? e % GR : e / NMAX, mc = rowfast ? e / GR : e % NMAX;
-      const int io = ioff[mc];
-      if (io >= 0) Tb[rl * TS + ican[mc]] = r0 + rl < v.rows ? in[rb_in[rl] + io] : T(0);
+    wave_lds_sync();
+    // the chunk into registers with every load in flight at once (each from
+    // an offset inside the tensor: element 0 stands in for the columns and
+    // rows past its end), then into LDS.  Rows run along memory (Cp > 1):
+    // lane l takes row l % 32 and columns l / 32 + 2 j; otherwise lane l
+    // takes column l of rows j.
+    T rv[NL];
+    if (rowfast) {
+      const int rl = lane & 31, m0 = lane >> 5;
+      const bool rok = r0 + rl < v.rows;
+      const int rbase = rb_in[rl];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const int io = ioff[m0 + 2 * j];
+        rv[j] = in[rok && io >= 0 ? rbase + io : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < NL; ++j)
+        if (ioff[m0 + 2 * j] >= 0) Tb[rl * TS + ican[m0 + 2 * j]] = rok ? rv[j] : T(0);
+    } else {
+      const int io = ioff[lane], ic = ican[lane];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) rv[j] = in[io >= 0 && r0 + j < v.rows ? rb_in[j] + io : 0];
+      if (io >= 0)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) Tb[j * TS + ic] = r0 + j < v.rows ? rv[j] : T(0);
     }
-    __syncthreads();
+    wave_lds_sync();
     // A operands of both 16-row blocks into registers, then the products into Tb
     if (BF == 0) {
       double a[2][KS];
@@ -1138,7 +1163,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) a[mb][ks] = double(Tb[(16 * mb + li) * TS + 4 * ks + lq]);
-      __syncthreads();
+      wave_lds_sync();
       const int nbn = (nout + 15) >> 4;
       dbl4 c[2][4];
 #pragma unroll
@@ -1173,7 +1198,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           for (int u = 0; u < 8; ++u) vv[u] = float(Tb[(16 * mb + li) * TS + 32 * kb + 8 * lq + u]);
           split3(vv, ah[mb][kb], am[mb][kb], al[mb][kb]);
         }
-      __syncthreads();
+      wave_lds_sync();
       const int nbn = (nout + 15) >> 4;
       flt4 c[2][4];
 #pragma unroll
@@ -1207,16 +1232,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
             for (int r = 0; r < 4; ++r) Tb[(16 * mb + 4 * lq + r) * TS + 16 * nb + li] = T(c[mb][nb][r]);
     }
-    __syncthreads();
-    // write back in memory order (output rows of nout entries)
-#pragma unroll 8
-    for (int j = 0; j < NL; ++j) {
-      const int e = lane + 64 * j;
-      const int rl = rowfast ? e % GR : e / NMAX, mc = rowfast ? e / GR : e % NMAX;
-      const int oo = ooff[mc];
-      if (oo >= 0 && r0 + rl < v.rows) out[rb_out[rl] + oo] = Tb[rl * TS + ocan[mc]];
+    wave_lds_sync();
+    // write back in memory order (output rows of nout entries), the same
+    // lane assignment: the LDS reads first, then the stores, which the next
+    // chunk does not wait for
+    if (rowfast) {
+      const int rl = lane & 31, m0 = lane >> 5;
+      const bool rok = r0 + rl < v.rows;
+      const int rbase = rb_out[rl];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const int oc = ocan[m0 + 2 * j];
+        rv[j] = Tb[rl * TS + (ooff[m0 + 2 * j] >= 0 ? oc : 0)];
+      }
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const int oo = ooff[m0 + 2 * j];
+        if (rok && oo >= 0) out[rbase + oo] = rv[j];
+      }
+    } else {
+      const int oo = ooff[lane], oc = oo >= 0 ? ocan[lane] : 0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) rv[j] = Tb[j * TS + oc];
+      if (oo >= 0)
+#pragma unroll
+        for (int j = 0; j < NL; ++j)
+          if (r0 + j < v.rows) out[rb_out[j] + oo] = rv[j];
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   win_close(A.win, w0);
 }
