@@ -369,6 +369,9 @@ tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items,
   if (L.kdcap > 72) return fail(c, TN3D_E_UNSUPPORTED, "gate rank x chi above 72");
   for (int32_t b : P.bond_dim0)
     if (b > L.legcap) return fail(c, TN3D_E_UNSUPPORTED, "an initial bond dimension above max(chi, 2)");
+  // the one-site and final-vector kernels hold a row of a site tensor in 16 registers
+  for (int32_t dm : P.dmax)
+    if (dm > 16) return fail(c, TN3D_E_UNSUPPORTED, "a physical dimension above 16");
   if ((L.ncap > 64 || L.kdcap > 64) && prec == TN3D_PREC_FP64 && !(pr.flags & TN3D_OPT_GRAM_FACTOR))
     return fail(c, TN3D_E_UNSUPPORTED,
                 "physical dim x chi or gate rank x chi above 64 needs the Gram route in FP64 (TN3D_OPT_GRAM_FACTOR)");

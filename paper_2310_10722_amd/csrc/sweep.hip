@@ -125,13 +125,29 @@ __global__ __launch_bounds__(ET) void k_onesite(SweepArgs A, const DevOneSite* o
   const T* in = tens<T>(A, op.src, sweep, op.site);
   T* out = tens<T>(A, op.src ^ 1, sweep, op.site);
   const int din = op.din, dout = op.dout;
-  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-    double v[16];  // din <= 16 (checked when the network is built)
-    for (int p = 0; p < din; ++p) v[p] = double(in[r * din + p]);
-    for (int q = 0; q < dout; ++q) {
-      double s = 0.0;
-      for (int p = 0; p < din; ++p) s += M[q * din + p] * v[p];
-      out[r * dout + q] = T(s);
+  // RU rows per lane and step, all their loads issued before any is used
+  // (rows past the end read row 0 and are not written)
+  constexpr int RU = 4;
+  for (int r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
+    T v[RU][16];  // din <= 16 (checked when the network is built)
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = r0 + u * ET < rows ? r0 + u * ET : 0;
+#pragma unroll
+      for (int p = 0; p < 16; ++p)
+        if (p < din) v[u][p] = in[r * din + p];
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = r0 + u * ET;
+      if (r < rows)
+        for (int q = 0; q < dout; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int p = 0; p < 16; ++p)
+            if (p < din) s += M[q * din + p] * double(v[u][p]);
+          out[r * dout + q] = T(s);
+        }
     }
   }
 }
@@ -1275,13 +1291,31 @@ __global__ __launch_bounds__(ET) void k_rescale(SweepArgs A, const int32_t* d_af
   site_dims(A, sweep, site, D);
   const int64_t n = int64_t(d_after[site]) * D[0] * D[1] * D[2] * D[3];
   T* t = tens<T>(A, par_after[site], sweep, site);
+  // EU elements per lane and step, their loads issued together
+  constexpr int EU = 8;
   double m = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += ET) m = fmax(m, fabs(double(t[e])));
+  int64_t e = threadIdx.x;
+  for (; e + (EU - 1) * ET < n; e += EU * ET) {
+    T v[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) v[u] = t[e + u * ET];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) m = fmax(m, fabs(double(v[u])));
+  }
+  for (; e < n; e += ET) m = fmax(m, fabs(double(t[e])));
   m = block_max_abs_reduce(m, red);
   const bool bad = !(m > 0.0) || !isfinite(m);
   const double c = bad ? 1.0 : m;
   const double inv = 1.0 / c;
-  for (int64_t e = threadIdx.x; e < n; e += ET) t[e] = T(double(t[e]) * inv);
+  e = threadIdx.x;
+  for (; e + (EU - 1) * ET < n; e += EU * ET) {
+    T v[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) v[u] = t[e + u * ET];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) t[e + u * ET] = T(double(v[u]) * inv);
+  }
+  for (; e < n; e += ET) t[e] = T(double(t[e]) * inv);
   if (threadIdx.x == 0) {
     A.logs[int64_t(sweep) * A.n_sites + site] += log(c);
     if (bad) atomicOr(&A.flags[sweep], 1u);
@@ -1303,10 +1337,26 @@ __global__ __launch_bounds__(ET) void k_finalize(SweepArgs A, const int32_t* d_f
   const double* f = pool_of(A, sweep) + f_off[site];
   const T* t = tens<T>(A, par_final[site], sweep, site);
   double* o = fin + int64_t(sweep) * fin_stride + fin_off[site];
-  for (int64_t r = threadIdx.x; r < rows; r += ET) {
-    double s = 0.0;
-    for (int p = 0; p < d; ++p) s += f[p] * double(t[r * d + p]);
-    o[r] = s;
+  // RU rows per lane and step, all their loads issued before any is used
+  // (rows past the end read row 0 and are not written)
+  constexpr int RU = 4;
+  for (int64_t r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
+    T v[RU][16];  // d <= 16 (checked when the network is built)
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t r = r0 + u * ET < rows ? r0 + u * ET : 0;
+#pragma unroll
+      for (int p = 0; p < 16; ++p)
+        if (p < d) v[u][p] = t[r * d + p];
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < 16; ++p)
+        if (p < d) s += f[p] * double(v[u][p]);
+      if (r0 + u * ET < rows) o[r0 + u * ET] = s;
+    }
   }
 }
 
