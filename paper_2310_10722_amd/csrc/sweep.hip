@@ -1780,9 +1780,9 @@ static_assert(CHEB % 3 == 1, "the filter's buffer rotation ends in Y for CHEB = 
 
 // Cyclic Jacobi on the symmetric n x n A (n <= 64, LDS, row stride 65) by a
 // 512-thread workgroup: the round-robin order gives 32 disjoint rotations per
-// round, applied as A <- A J, V <- V J, then A <- J^T A (Golub and Van Loan,
-// Sec. 8.5, the symmetric Schur rotation).  V starts as the identity.
-// Returns the number of sweeps.
+// round, applied as A <- J^T A J in one pass over 2 x 2 blocks and V <- V J
+// (Golub and Van Loan, Sec. 8.5, the symmetric Schur rotation).  V starts as
+// the identity.  Returns the number of sweeps.
 __device__ int block_jacobi_sym64(double* A, double* V, int n, double* cs, int* any) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += ZNT) {
@@ -1825,29 +1825,43 @@ __device__ int block_jacobi_sym64(double* A, double* V, int n, double* cs, int* 
         reinterpret_cast<int*>(cs)[8 * tid + 5] = q;
       }
       __syncthreads();
-      // columns: A <- A J and V <- V J
+      // A <- J^T A J by 2 x 2 blocks: the round's pairs partition the indices,
+      // so each element lies in one (row pair, column pair) block; per block
+      // the column rotation, then the row rotation.  V <- V J alongside.
+      for (int e = tid; e < 32 * 32; e += ZNT) {
+        const int k1 = e >> 5, k2 = e & 31;
+        const double c1 = cs[4 * k1], s1 = cs[4 * k1 + 1], c2 = cs[4 * k2], s2 = cs[4 * k2 + 1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = reinterpret_cast<const int*>(cs)[8 * k1 + 4], q1 = reinterpret_cast<const int*>(cs)[8 * k1 + 5];
+        const int p2 = reinterpret_cast<const int*>(cs)[8 * k2 + 4], q2 = reinterpret_cast<const int*>(cs)[8 * k2 + 5];
+        double xpp = A[p1 * 65 + p2], xpq = A[p1 * 65 + q2], xqp = A[q1 * 65 + p2], xqq = A[q1 * 65 + q2];
+        if (s2 != 0.0) {
+          const double app = xpp, apq = xpq, aqp = xqp, aqq = xqq;
+          xpp = c2 * app - s2 * apq;
+          xpq = s2 * app + c2 * apq;
+          xqp = c2 * aqp - s2 * aqq;
+          xqq = s2 * aqp + c2 * aqq;
+        }
+        if (s1 != 0.0) {
+          A[p1 * 65 + p2] = c1 * xpp - s1 * xqp;
+          A[q1 * 65 + p2] = s1 * xpp + c1 * xqp;
+          A[p1 * 65 + q2] = c1 * xpq - s1 * xqq;
+          A[q1 * 65 + q2] = s1 * xpq + c1 * xqq;
+        } else {
+          A[p1 * 65 + p2] = xpp;
+          A[q1 * 65 + p2] = xqp;
+          A[p1 * 65 + q2] = xpq;
+          A[q1 * 65 + q2] = xqq;
+        }
+      }
       for (int e = tid; e < 32 * 64; e += ZNT) {
         const int k = e >> 6, r = e & 63;
         const double c = cs[4 * k], sn = cs[4 * k + 1];
         if (sn == 0.0) continue;
         const int p = reinterpret_cast<const int*>(cs)[8 * k + 4], q = reinterpret_cast<const int*>(cs)[8 * k + 5];
-        const double ap = A[r * 65 + p], aq = A[r * 65 + q];
-        A[r * 65 + p] = c * ap - sn * aq;
-        A[r * 65 + q] = sn * ap + c * aq;
         const double vp = V[r * 65 + p], vq = V[r * 65 + q];
         V[r * 65 + p] = c * vp - sn * vq;
         V[r * 65 + q] = sn * vp + c * vq;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < 32 * 64; e += ZNT) {
-        const int k = e >> 6, r = e & 63;
-        const double c = cs[4 * k], sn = cs[4 * k + 1];
-        if (sn == 0.0) continue;
-        const int p = reinterpret_cast<const int*>(cs)[8 * k + 4], q = reinterpret_cast<const int*>(cs)[8 * k + 5];
-        const double ap = A[p * 65 + r], aq = A[q * 65 + r];
-        A[p * 65 + r] = c * ap - sn * aq;
-        A[q * 65 + r] = sn * ap + c * aq;
       }
       __syncthreads();
     }
@@ -1980,11 +1994,15 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   double* P = U + int64_t(nv) * SB;
   double* Sout = Z.zS + int64_t(s) * 1024;
   const int K = nv < Z.chi_m + 1 ? nv : Z.chi_m + 1;
-  // start: the columns of G at its SB largest diagonal entries (ties by index)
+  // start: the columns of G at its SB largest diagonal entries (ties by
+  // index); the diagonal is staged in the GEMM area, free until the first
+  // product (nv <= 1024 < GEMM_LDS)
+  for (int i = tid; i < nv; i += ZNT) gl[i] = G[int64_t(i) * nv + i];
+  __syncthreads();
   for (int i = tid; i < nv; i += ZNT) {
-    const double gi = G[int64_t(i) * nv + i];
+    const double gi = gl[i];
     int rank = 0;
-    for (int j = 0; j < nv; ++j) rank += sorts_before(G[int64_t(j) * nv + j], j, gi, i) ? 1 : 0;
+    for (int j = 0; j < nv; ++j) rank += sorts_before(gl[j], j, gi, i) ? 1 : 0;
     if (rank < SB) jsel[rank] = i;
   }
   __syncthreads();
