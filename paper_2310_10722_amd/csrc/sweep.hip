@@ -1883,6 +1883,23 @@ __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
   return double(h) * (2.0 / 4294967296.0) - 1.0;
 }
 
+// Elementwise pass over [0, n) by a ZNT-thread workgroup: a thread takes EU
+// elements per step and evaluates all of them (ld(e), whose loads read at
+// index e; indices past n read element 0) before storing any (st(e, v)), so
+// a step's loads are in flight together instead of each waiting behind the
+// previous element's store.
+template <int EU = 8, class LD, class ST>
+__device__ __forceinline__ void block_stream(int n, LD ld, ST st) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += EU * ZNT) {
+    double v[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) v[u] = ld(e0 + u * ZNT < n ? e0 + u * ZNT : 0);
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+      if (e0 + u * ZNT < n) st(e0 + u * ZNT, v[u]);
+  }
+}
+
 // X (nv x SB, row-major) <- an orthonormal basis of the span of Z (same
 // shape, destroyed) by Cholesky QR twice with column equilibration; a column
 // whose pivot shows it dependent on the previous ones is replaced by a hashed
@@ -1962,10 +1979,13 @@ __device__ void block_cholqr2(double* Z, double* X, int nv, double* R, double* R
         [&](int k, int n) { return Ri[k * 65 + n]; }, [&](int m, int n, double v) { X[m * SB + n] = v; }, gl);
     if (pass == 0) {
       // dead columns get a hashed vector; the second pass orthonormalises
-      for (int e = tid; e < nv * SB; e += ZNT) {
-        const int j = e % SB;
-        Z[e] = dsc[j] < 0.0 ? hash_unit(seed + unsigned(j), unsigned(e / SB)) : X[e];
-      }
+      block_stream(
+          nv * SB,
+          [&](int e) {
+            const int j = e % SB;
+            return dsc[j] < 0.0 ? hash_unit(seed + unsigned(j), unsigned(e / SB)) : X[e];
+          },
+          [&](int e, double v) { Z[e] = v; });
       __syncthreads();
     }
     __syncthreads();
@@ -2006,10 +2026,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
     if (rank < SB) jsel[rank] = i;
   }
   __syncthreads();
-  for (int e = tid; e < nv * SB; e += ZNT) {
-    const int r = e / SB, j = e % SB;
-    Y[e] = G[int64_t(r) * nv + jsel[j]];
-  }
+  block_stream(
+      nv * SB, [&](int e) { return G[int64_t(e / SB) * nv + jsel[e % SB]]; }, [&](int e, double v) { Y[e] = v; });
   __syncthreads();
   block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x1234u);
   const double tol = Z.sub_tol;
@@ -2056,11 +2074,22 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
     {
       const int j = tid & 63;
       double acc = 0.0;
-      if (j < K)
-        for (int r = tid >> 6; r < nv; r += ZNT / 64) {
+      if (j < K) {
+        // eight rows' loads in flight per step, accumulated in row order
+        constexpr int RS = ZNT / 64;
+        int r = tid >> 6;
+        for (; r + 7 * RS < nv; r += 8 * RS) {
+          double dv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) dv[u] = P[(r + u * RS) * SB + j] - th[j] * U[(r + u * RS) * SB + j];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = fma(dv[u], dv[u], acc);
+        }
+        for (; r < nv; r += RS) {
           const double d = P[r * SB + j] - th[j] * U[r * SB + j];
           acc = fma(d, d, acc);
         }
+      }
       atomicAdd(&rn[j], acc);
     }
     __syncthreads();
@@ -2087,7 +2116,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
       const double hw = 0.5 * c_lo, cen = 0.5 * c_lo;
       const double sig1 = hw / (t1 - cen);
       double sig = sig1;
-      for (int e = tid; e < nv * SB; e += ZNT) Y[e] = (P[e] - cen * U[e]) * (sig1 / hw);
+      block_stream(
+          nv * SB, [&](int e) { return (P[e] - cen * U[e]) * (sig1 / hw); }, [&](int e, double v) { Y[e] = v; });
       __syncthreads();
       double *pa = U, *pb = Y, *pt = X;  // steps j-1, j and the product buffer
       for (int deg = 2; deg <= CHEB; ++deg) {
@@ -2097,7 +2127,9 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
             [&](int k, int n) { return pb[k * SB + n]; }, [&](int m, int n, double v) { pt[m * SB + n] = v; }, gl);
         __syncthreads();
         const double ca = 2.0 * sn / hw, cb = sig * sn;
-        for (int e = tid; e < nv * SB; e += ZNT) pt[e] = ca * (pt[e] - cen * pb[e]) - cb * pa[e];
+        block_stream(
+            nv * SB, [&](int e) { return ca * (pt[e] - cen * pb[e]) - cb * pa[e]; },
+            [&](int e, double v) { pt[e] = v; });
         __syncthreads();
         double* q = pa;
         pa = pb;
@@ -2112,10 +2144,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
       // no interval to damp (a flat or rank-deficient block): a power step,
       // P diag(1 / theta), orthonormalised
       const double fl = 1e-15 * t1;
-      for (int e = tid; e < nv * SB; e += ZNT) {
-        const int j = e % SB;
-        Y[e] = P[e] / fmax(th[j], fl);
-      }
+      block_stream(
+          nv * SB, [&](int e) { return P[e] / fmax(th[e % SB], fl); }, [&](int e, double v) { Y[e] = v; });
       __syncthreads();
       block_cholqr2(Y, X, nv, H, Vv, gl, red, &flag[0], 0x51ED27u + unsigned(it) * 977u);
     }
@@ -2128,7 +2158,8 @@ __global__ __launch_bounds__(ZNT) void k_zip_bsub(ZipArgs Z, int x, int y) {
   const bool bad = Dn < 1;
   if (bad) Dn = 1;
   double* Fv = Z.L4 + int64_t(s) * Z.bigcap;
-  for (int e = tid; e < nv * Dn; e += ZNT) Fv[e] = U[(e / Dn) * SB + e % Dn];
+  block_stream(
+      nv * Dn, [&](int e) { return U[(e / Dn) * SB + e % Dn]; }, [&](int e, double v) { Fv[e] = v; });
   if (Z.flop_b && tid == 0) {
     // algorithmic flops: 2 nv^2 SB per block product by G (one per Ritz step
     // and CHEB - 1 more per filter); per Ritz step the projection and
