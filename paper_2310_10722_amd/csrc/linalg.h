@@ -167,12 +167,14 @@ __device__ int block_pchol(double* Z, double* F, int n, double tol, int* perm, d
 // of sweeps before the last; max_sweeps means no convergence.  A sweep whose
 // rotations all had |a_i . a_j| <= sqrt(tol) |a_i| |a_j| ends the iteration:
 // one-sided Jacobi converges quadratically, so what it leaves is of order
-// tol.  red: 2 doubles scratch, flag: 2 ints.
+// tol.  red: 2 doubles scratch, flag: 2 ints.  ldj: J's leading dimension
+// (0: nv).
 __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double* J, double tol,
-                            double floor_rel, int max_sweeps, int* flag, double* red) {
+                            double floor_rel, int max_sweeps, int* flag, double* red, int ldj = 0) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  if (ldj == 0) ldj = nv;
   for (int r = tid >> 4; r < nv; r += nt >> 4)
-    for (int c = tid & 15; c < nv; c += 16) J[r * nv + c] = r == c ? 1.0 : 0.0;
+    for (int c = tid & 15; c < nv; c += 16) J[r * ldj + c] = r == c ? 1.0 : 0.0;
   const int ne = nv + (nv & 1);
   const int npairs = ne / 2;
   int team = 64;
@@ -240,9 +242,9 @@ __device__ int block_jacobi(double* A, long vs, long es, int nv, int len, double
             A[j * vs + e * es] = sn * x + cs * y;
           }
           for (int e = lane; e < nv; e += team) {
-            double x = J[e * nv + i], y = J[e * nv + j];
-            J[e * nv + i] = cs * x - sn * y;
-            J[e * nv + j] = sn * x + cs * y;
+            double x = J[e * ldj + i], y = J[e * ldj + j];
+            J[e * ldj + i] = cs * x - sn * y;
+            J[e * ldj + j] = sn * x + cs * y;
           }
           if (lane == 0) {
             flag[0] = 1;

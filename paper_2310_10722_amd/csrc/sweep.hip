@@ -526,7 +526,12 @@ __device__ void build_gated_grams(const SweepArgs& A, const DevGate& g, const do
 // through the gate), threads first, first + stride, ... of the caller.
 __device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, int Dn, bool bad, int n, int rA, int rB,
                         const double* CM, const double* VM, const double* ZA, const double* ZB, const int* ord,
-                        const double* Ss, double s1, double* WA, double* WB, int first, int stride) {
+                        const double* Ss, double s1, double* WA, double* WB, int first, int stride, int ldc = 0,
+                        int ldj = 0) {
+  // ZA holds C' (rA x rB, leading dimension ldc), ZB the rotations V'
+  // (rB x rB, leading dimension ldj); 0 means rB
+  if (ldc == 0) ldc = rB;
+  if (ldj == 0) ldj = rB;
   const int K = g.K, dA = g.dA, dB = g.dB, nA = dA * D, nB = dB * D;
   const bool alt = gate_alt(A, g, sweep);
   const double* OA = pool_of(A, sweep) + (alt ? g.oA1 : g.oA);
@@ -546,8 +551,8 @@ __device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, 
       for (int k = 0; k < 4; ++k) {
         double pa = 0.0, pb = 0.0;
         if (k < K) {
-          for (int j = 0; j < rB; ++j) pa = fma(VM[j * n + k * D + b], ZB[j * rB + om], pa);
-          for (int i = 0; i < rA; ++i) pb = fma(CM[i * n + k * D + b], ZA[i * rB + om], pb);
+          for (int j = 0; j < rB; ++j) pa = fma(VM[j * n + k * D + b], ZB[j * ldj + om], pa);
+          for (int i = 0; i < rA; ++i) pb = fma(CM[i * n + k * D + b], ZA[i * ldc + om], pb);
         }
         phA[k] = pa;
         phB[k] = pb;
@@ -577,7 +582,7 @@ __device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, 
       double w = 0.0;
       for (int k = 0; k < K; ++k) {
         double phi = 0.0;
-        for (int j = 0; j < rB; ++j) phi = fma(VM[j * n + k * D + b], ZB[j * rB + ord[m]], phi);
+        for (int j = 0; j < rB; ++j) phi = fma(VM[j * n + k * D + b], ZB[j * ldj + ord[m]], phi);
         w = fma(OA[(k * dA + p2) * dA + p], phi, w);
       }
       WA[2 + e] = w * (sqrt(Ss[m] / s1) / Ss[m]);
@@ -588,7 +593,7 @@ __device__ void write_w(const SweepArgs& A, const DevGate& g, int sweep, int D, 
       double w = 0.0;
       for (int k = 0; k < K; ++k) {
         double phi = 0.0;
-        for (int i = 0; i < rA; ++i) phi = fma(CM[i * n + k * D + b], ZA[i * rB + ord[m]], phi);
+        for (int i = 0; i < rA; ++i) phi = fma(CM[i * n + k * D + b], ZA[i * ldc + ord[m]], phi);
         w = fma(OB[(k * dB + p2) * dB + p], phi, w);
       }
       WB[2 + e] = w * (sqrt(Ss[m] / s1) / (Ss[m] * Ss[m]));
@@ -614,12 +619,16 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
   const double logb_in = A.logb[bidx];  // loaded early, used at the end
   // four n x n matrices; above order 64 (the Gram route only) the second one
   // lives in the per-gate global scratch, so the rest fits the LDS
+  // Up to order 64 each matrix takes n (n + 1) doubles, so that C and the
+  // rotations can sit at an odd leading dimension: the Jacobi teams then read
+  // a column's consecutive entries from different LDS banks.
   double* ZA = sm;
   const bool zb_global = n > 64;
-  double* ZB = zb_global ? A.solve_big + int64_t(sweep * n_g + gi) * A.sbig_ld : ZA + n * n;
-  double* CM = zb_global ? ZA + n * n : ZB + n * n;
-  double* VM = CM + n * n;
-  double* S = VM + n * n;
+  const int slot = zb_global ? n * n : n * (n + 1);
+  double* ZB = zb_global ? A.solve_big + int64_t(sweep * n_g + gi) * A.sbig_ld : ZA + slot;
+  double* CM = zb_global ? ZA + slot : ZB + slot;
+  double* VM = CM + slot;
+  double* S = VM + slot;
   double* Ss = S + n;
   double* red = Ss + n;
   int* ord = reinterpret_cast<int*>(red + 4);
@@ -652,23 +661,25 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     rA = block_pchol(ZA, CM, n, A.pchol_tol, perm, red);  // F_A: CM, rA x n
     rB = block_pchol(ZB, VM, n, A.pchol_tol, perm, red);  // F_B: VM, rB x n
   }
-  // C = F_A F_B^T (rA x rB) into ZA
+  // C = F_A F_B^T (rA x rB) into ZA, leading dimension ldc; the rotations V'
+  // (rB x rB) go to ZB at leading dimension ldj
+  const int ldc = zb_global ? rB : (rB | 1), ldj = ldc;
   for (int i = tid >> 4; i < rA; i += NT >> 4)
     for (int j = tid & 15; j < rB; j += 16) {
       double s = 0.0;
       for (int c = 0; c < n; ++c) s += CM[i * n + c] * VM[j * n + c];
-      ZA[i * rB + j] = s;
+      ZA[i * ldc + j] = s;
     }
   __syncthreads();
   int Dn = 0, split = 0;
   double s1 = 0.0;
   if (rA > 0 && rB > 0) {
-    const int nsw = block_jacobi(ZA, 1, rB, rB, rA, ZB, A.jtol, A.jfloor, 40, flag, red);  // columns of C; V' in ZB
+    const int nsw = block_jacobi(ZA, 1, ldc, rB, rA, ZB, A.jtol, A.jfloor, 40, flag, red, ldj);  // columns of C; V' in ZB
     if (tid == 0) {
       atomicMax(&A.sweeps_max[0], nsw);
       if (nsw >= 40) atomicOr(&A.flags[sweep], 8u);
     }
-    block_norms_sorted(ZA, 1, rB, rB, rA, S, ord);
+    block_norms_sorted(ZA, 1, ldc, rB, rA, S, ord);
     for (int m = tid; m < rB; m += NT) Ss[m] = S[ord[m]];
     __syncthreads();
     Dn = rank_rule(Ss, rB, A.chi_cut, A.eps, A.tau, &split);
@@ -693,7 +704,7 @@ __global__ __launch_bounds__(NT) void k_solve(SweepArgs A, const DevGate* gates,
     if (f) atomicOr(&A.flags[sweep], f);
   }
   for (int m = tid; m < Dn; m += NT) A.lam[bidx * A.lam_ld + m] = bad ? 1.0 : Ss[m] / s1;
-  write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT);
+  write_w(A, g, sweep, D, Dn, bad, n, rA, rB, CM, VM, ZA, ZB, ord, Ss, s1, WA, WB, tid, NT, ldc, ldj);
 }
 
 // ---------------------------------------------------------------------------
@@ -2612,7 +2623,7 @@ static inline size_t bsub_lds_bytes() { return size_t(GEMM_LDS + 2 * SB * 65) * 
 
 hipError_t set_kernel_lds_limits() {
   const int kmax = 64;  // gate rank x chi, checked by the host
-  const int solve = 4 * kmax * kmax * 8 + 2 * kmax * 8 + 32 + (2 * kmax + 4) * 4;
+  const int solve = 4 * kmax * (kmax + 1) * 8 + 2 * kmax * 8 + 32 + (2 * kmax + 4) * 4;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_solve<SNT>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, solve);
   if (e == hipSuccess)
@@ -2694,11 +2705,14 @@ void launch_gram(int prec, const SweepArgs& A, const DevGate* gates, int n_g, in
 // Dynamic LDS of a k_solve launch whose orders reach kd: four n x n matrices
 // up to order 64, three above (see k_solve), the most any order <= kd needs.
 static size_t solve_lds(int kd) {
-  auto need = [](int n, int mats) {
-    return size_t(mats) * n * n * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
+  // matrices of n (n + 1) doubles up to order 64 (odd leading dimensions),
+  // of n x n above, where the second one lives in global scratch
+  auto need = [](int n, int mats, int ld) {
+    return size_t(mats) * n * ld * 8 + size_t(2) * n * 8 + 32 + size_t(2 * n + 4) * 4;
   };
-  size_t b = need(std::min(kd, 64), 4);
-  if (kd > 64) b = std::max(b, need(kd, 3));
+  const int k64 = std::min(kd, 64);
+  size_t b = need(k64, 4, k64 + 1);
+  if (kd > 64) b = std::max(b, need(kd, 3, kd));
   return b;
 }
 
