@@ -125,29 +125,42 @@ __global__ __launch_bounds__(ET) void k_onesite(SweepArgs A, const DevOneSite* o
   const T* in = tens<T>(A, op.src, sweep, op.site);
   T* out = tens<T>(A, op.src ^ 1, sweep, op.site);
   const int din = op.din, dout = op.dout;
-  // RU rows per lane and step, all their loads issued before any is used
-  // (rows past the end read row 0 and are not written)
-  constexpr int RU = 4;
-  for (int r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
-    T v[RU][16];  // din <= 16 (checked when the network is built)
+  if (din <= 4) {
+    // RU rows per lane and step, all their loads issued before any is used
+    // (rows past the end read row 0 and are not written); four inputs per row
+    // keep the registers, and with them the occupancy, low
+    constexpr int RU = 4;
+    for (int r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
+      T v[RU][4];
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int r = r0 + u * ET < rows ? r0 + u * ET : 0;
+      for (int u = 0; u < RU; ++u) {
+        const int r = r0 + u * ET < rows ? r0 + u * ET : 0;
 #pragma unroll
-      for (int p = 0; p < 16; ++p)
-        if (p < din) v[u][p] = in[r * din + p];
+        for (int p = 0; p < 4; ++p)
+          if (p < din) v[u][p] = in[r * din + p];
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int r = r0 + u * ET;
+        if (r < rows)
+          for (int q = 0; q < dout; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+              if (p < din) s += M[q * din + p] * double(v[u][p]);
+            out[r * dout + q] = T(s);
+          }
+      }
     }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int r = r0 + u * ET;
-      if (r < rows)
-        for (int q = 0; q < dout; ++q) {
-          double s = 0.0;
-#pragma unroll
-          for (int p = 0; p < 16; ++p)
-            if (p < din) s += M[q * din + p] * double(v[u][p]);
-          out[r * dout + q] = T(s);
-        }
+  } else {
+    for (int r = threadIdx.x; r < rows; r += ET) {
+      double v[16];  // din <= 16 (checked when the network is built)
+      for (int p = 0; p < din; ++p) v[p] = double(in[r * din + p]);
+      for (int q = 0; q < dout; ++q) {
+        double s = 0.0;
+        for (int p = 0; p < din; ++p) s += M[q * din + p] * v[p];
+        out[r * dout + q] = T(s);
+      }
     }
   }
 }
@@ -1348,25 +1361,33 @@ __global__ __launch_bounds__(ET) void k_finalize(SweepArgs A, const int32_t* d_f
   const double* f = pool_of(A, sweep) + f_off[site];
   const T* t = tens<T>(A, par_final[site], sweep, site);
   double* o = fin + int64_t(sweep) * fin_stride + fin_off[site];
-  // RU rows per lane and step, all their loads issued before any is used
-  // (rows past the end read row 0 and are not written)
-  constexpr int RU = 4;
-  for (int64_t r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
-    T v[RU][16];  // d <= 16 (checked when the network is built)
+  if (d <= 4) {
+    // RU rows per lane and step, all their loads issued before any is used
+    // (rows past the end read row 0 and are not written)
+    constexpr int RU = 4;
+    for (int64_t r0 = threadIdx.x; r0 < rows; r0 += RU * ET) {
+      T v[RU][4];
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int64_t r = r0 + u * ET < rows ? r0 + u * ET : 0;
+      for (int u = 0; u < RU; ++u) {
+        const int64_t r = r0 + u * ET < rows ? r0 + u * ET : 0;
 #pragma unroll
-      for (int p = 0; p < 16; ++p)
-        if (p < d) v[u][p] = t[r * d + p];
+        for (int p = 0; p < 4; ++p)
+          if (p < d) v[u][p] = t[r * d + p];
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          if (p < d) s += f[p] * double(v[u][p]);
+        if (r0 + u * ET < rows) o[r0 + u * ET] = s;
+      }
     }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
+  } else {
+    for (int64_t r = threadIdx.x; r < rows; r += ET) {
       double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < 16; ++p)
-        if (p < d) s += f[p] * double(v[u][p]);
-      if (r0 + u * ET < rows) o[r0 + u * ET] = s;
+      for (int p = 0; p < d; ++p) s += f[p] * double(t[r * d + p]);
+      o[r] = s;
     }
   }
 }
