@@ -227,8 +227,11 @@ __device__ __forceinline__ void win_close(unsigned long long* win, unsigned long
 // launch handles the Grams with ncols in (nlo, 16 NB].
 constexpr int GR = 32;  // rows per chunk
 
+// Up to 64 columns the kernel is held to two wavefronts per SIMD (at its
+// natural 272 registers one would fit); the 96-column variant would spill.
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_gram2(SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NB <= 4 ? 2 : 1))) void k_gram2(
+    SweepArgs A, const DevGate* gates, int n_g, double* gout, int ncap,
                                               int nlo) {
   constexpr int NC = 16 * NB;
   constexpr int NL = GR * NC / 64;  // elements each lane fetches per chunk
