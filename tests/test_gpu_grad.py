@@ -158,7 +158,8 @@ def test_grad_rate_map_autograd_and_differences(ctx):
 
     out = tn3d.log_likelihood(ctx, build, rates, syn, prm, rate_of)
     out.backward()
-    assert abs(float(out) - float(tot.cpu()[0])) <= 1e-12 * abs(float(out))
+    val = float(out.detach())
+    assert abs(val - float(tot.cpu()[0])) <= 1e-12 * abs(val)
     np.testing.assert_allclose(rates.grad.numpy(), grad, rtol=1e-12, atol=1e-12)
 
     def f(r):
