@@ -355,6 +355,7 @@ struct PoolSel {
 tn3d_status run_group(tn3d_ctx c, tn3d_net n, const std::vector<int32_t>& items, const uint8_t* synd,
                       const int64_t* synd_off, const tn3d_params& pr, double* logp, uint32_t* flags_out,
                       int prec, bool noalloc, const PoolSel* pools = nullptr) {
+  if (items.empty()) return TN3D_OK;  // (the chunk arithmetic below divides by the item count)
   const Program& P = n->P;
   const int nc = P.n_cosets;
   const int max_g = std::max(1, n->max_gates_class);
